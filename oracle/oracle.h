@@ -1,0 +1,72 @@
+/*
+ * oracle.h -- plain, slow CPU oracle for the per-frame path of virtual-memory
+ * 3D Gaussian Splatting (Haberl et al., "Virtual Memory for 3D Gaussian
+ * Splatting", arXiv 2506.19415).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product links, loads or calls
+ * this code; only the test-suite, the smoke check and the benchmark's CPU
+ * baseline do.  It shares no source with the HIP path.
+ *
+ * Every step is written as the plain definition (loops, qsort), in the order
+ * the paper gives: create-time paging (Sec. 3), page determination with a
+ * page-ID buffer, links and LOD (Sec. 4.1), the two-stage page table with
+ * LRU replacement (Sec. 4.1.1), and splatting of the resident Gaussians with
+ * the 3DGS math of Kerbl et al. (Sec. 4.2).  Decisions that turn floating
+ * point into integers (tile rectangles, depth keys, visibility, alpha
+ * thresholds) are taken in float32, the precision of the paper's renderer.
+ *
+ * Gaussian record (59 floats): mean[3] scale[3] quat(w,x,y,z)[4] opacity
+ * sh[16][3].
+ */
+#ifndef VM3DGS_ORACLE_H
+#define VM3DGS_ORACLE_H
+#include <stdint.h>
+
+#define OR_REC 59
+
+typedef struct {
+    int64_t n;
+    const float* means;   /* [n][3] */
+    const float* scales;  /* [n][3] */
+    const float* quats;   /* [n][4] */
+    const float* opacity; /* [n]    */
+    const float* sh;      /* [n][16][3] */
+} or_scene_in;
+
+typedef struct {
+    float view[16];   /* world -> camera, row-major, OpenCV axes */
+    float cam_pos[3];
+    float fx, fy, cx, cy, znear;
+} or_camera;
+
+typedef struct or_scene or_scene;
+typedef struct or_vm or_vm;
+
+/* ---- math definitions shared (by definition, not by code) with the GPU ---- */
+float or_vm_exp(float x);
+double or_sh_basis(int k, double x, double y, double z);
+
+/* ---- create time (Sec. 3) ---- */
+or_scene* or_scene_build(const or_scene_in* in, int page_size, int lod_levels,
+                         double cell_m, double link_sigma, int attr_format);
+void or_scene_free(or_scene* s);
+int64_t or_scene_get(const or_scene* s, const char* name, void* dst, int64_t cap);
+
+/* ---- per frame (Sec. 4) ---- */
+or_vm* or_vm_create(const or_scene* s, int pool_pages, int copy_budget, int use_links,
+                    int img_w, int img_h, int idbuf_w, int idbuf_h, float lod_radius_px);
+void or_vm_free(or_vm* vm);
+/* tile_mask: NULL = render every tile, else [n_views * TX * TY] bytes, 1 = render */
+int or_vm_frame(or_vm* vm, const or_camera* cams, int n_views, const uint8_t* tile_mask);
+int64_t or_vm_get(const or_vm* vm, const char* name, void* dst, int64_t cap);
+
+/* Full-scene splat of every level-0 Gaussian (no paging): the reference the
+ * VM image is compared with.  Results are read with or_vm_get on a VM made
+ * for the same image size. */
+int or_render_full(or_vm* vm, const or_camera* cams, int n_views, const uint8_t* tile_mask);
+
+/* fp16 / bf16 round trips (round to nearest even) */
+float or_round_f16(float x);
+float or_round_bf16(float x);
+
+#endif

@@ -1,0 +1,170 @@
+"""Pins of the oracle's splatting (Sec. 4.2, 3DGS math) on the CPU.
+
+- a lone isotropic Gaussian on the optical axis renders the analytic
+  projected 2D Gaussian (EWA with the 0.3 px^2 dilation);
+- the EWA Jacobian agrees with a finite-difference Jacobian of the pinhole
+  projection for off-axis anisotropic Gaussians;
+- degree-0 SH gives rgb = max(0, C0 * DC + 0.5);
+- transmittance is non-increasing, ends in [1e-4, 1], bounds the colour;
+- per-tile lists are the brute-force lists of covering Gaussians sorted by
+  (depth, index).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_19415_amd import synth
+
+C0 = 0.5 / math.sqrt(math.pi)
+
+
+def identity_cam(W, H, fov=60.0):
+    fx, fy, cx, cy = synth.intrinsics(W, H, fov)
+    return synth.Camera(np.eye(4, dtype=np.float32), np.zeros(3, np.float32), fx, fy, cx, cy, 0.2)
+
+
+def one_gaussian_scene(mean, scale, quat=(1, 0, 0, 0), opacity=0.8, sh=None):
+    n = 1
+    if sh is None:
+        sh = np.zeros((1, 16, 3), np.float32)
+        sh[0, 0] = [0.6, 0.2, -0.4]
+    return synth.Scene(np.array([mean], np.float32), np.array([scale], np.float32),
+                       np.array([quat], np.float32), np.array([opacity], np.float32),
+                       np.asarray(sh, np.float32).reshape(n, 16, 3))
+
+
+def render(scene, cam, W, H, page_size=1):
+    osc = oracle.OracleScene(scene, page_size, 1, 0.5, 2.0)
+    vm = oracle.OracleVM(osc, 1, (W, H), (max(W // 4, 1), max(H // 4, 1)))
+    vm.render_full([cam])
+    return vm
+
+
+def test_lone_gaussian_closed_form():
+    W, H = 96, 80
+    cam = identity_cam(W, H)
+    sigma, z, o = 0.05, 3.0, 0.8
+    sc = one_gaussian_scene([0.0, 0.0, z], [sigma] * 3, opacity=o)
+    vm = render(sc, cam, W, H)
+    img = vm.image()[0]
+    rgb = np.maximum(C0 * np.array([0.6, 0.2, -0.4]) + 0.5, 0.0)
+    var = (cam.fx * sigma / z) ** 2 + 0.3
+    u, v = cam.cx - 0.5, cam.cy - 0.5
+    r = math.ceil(3.0 * math.sqrt(var))
+    tx0, tx1 = max(0, math.floor((u - r) / 16)), min((W + 15) // 16, math.floor((u + r + 15) / 16))
+    ty0, ty1 = max(0, math.floor((v - r) / 16)), min((H + 15) // 16, math.floor((v + r + 15) / 16))
+    jj, ii = np.mgrid[0:H, 0:W]
+    alpha = np.minimum(0.99, o * np.exp(-0.5 * ((ii - u) ** 2 + (jj - v) ** 2) / var))
+    inside = (ii // 16 >= tx0) & (ii // 16 < tx1) & (jj // 16 >= ty0) & (jj // 16 < ty1)
+    keep = alpha >= 1.0 / 255.0
+    exp_img = np.where((inside & keep)[..., None], alpha[..., None] * rgb, 0.0)
+    near_thr = np.abs(alpha - 1.0 / 255.0) < 1e-5
+    diff = np.abs(img - exp_img).max(-1)
+    assert diff[~near_thr].max() < 2e-6
+    assert img[int(v), int(u)].max() > 0.1
+
+
+@pytest.mark.parametrize("mean,scale,quat", [
+    ([0.7, -0.4, 4.0], [0.08, 0.02, 0.05], [0.9, 0.1, -0.3, 0.2]),
+    ([-1.1, 0.6, 6.5], [0.2, 0.1, 0.01], [0.3, 0.8, 0.1, -0.5]),
+    ([0.2, 0.9, 2.5], [0.03, 0.03, 0.09], [0.5, -0.5, 0.5, 0.5]),
+])
+def test_ewa_conic_vs_finite_difference(mean, scale, quat):
+    W, H = 128, 96
+    cam = identity_cam(W, H)
+    q = np.array(quat, np.float64)
+    q /= np.linalg.norm(q)
+    sc = one_gaussian_scene(mean, scale, q)
+    vm = render(sc, cam, W, H)
+    f = vm.get("pp_float").reshape(-1, 10)[0]
+    mu = np.array(mean, np.float64)
+
+    def proj(p):
+        return np.array([cam.fx * p[0] / p[2] + cam.cx - 0.5, cam.fy * p[1] / p[2] + cam.cy - 0.5])
+
+    h = 1e-6
+    J = np.stack([(proj(mu + h * e) - proj(mu - h * e)) / (2 * h) for e in np.eye(3)], 1)
+    w, x, y, z = q
+    R = np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                  [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                  [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+    M = R @ np.diag(scale)
+    S2 = J @ (M @ M.T) @ J.T + 0.3 * np.eye(2)
+    conic = np.linalg.inv(S2)
+    got = np.array([[f[3], f[4]], [f[4], f[5]]])
+    assert np.allclose(got, conic, rtol=2e-4, atol=1e-7), (got, conic)
+    assert np.allclose(f[:2], proj(mu), atol=1e-4)
+    assert abs(f[2] - mean[2]) < 1e-6
+
+
+def test_sh_colour_matches_basis():
+    """Each basis function alone: rgb = max(0, Y_k(d) * c + 0.5)."""
+    W, H = 64, 64
+    cam = identity_cam(W, H)
+    mean = np.array([0.4, -0.3, 3.0])
+    d = mean / np.linalg.norm(mean)
+    for k in range(16):
+        sh = np.zeros((16, 3), np.float32)
+        sh[k] = [0.9, -0.7, 0.3]
+        vm = render(one_gaussian_scene(mean, [0.05] * 3, sh=sh[None]), cam, W, H)
+        rgb = vm.get("pp_float").reshape(-1, 10)[0, 7:10]
+        ref = np.maximum(oracle.sh_basis(k, *d) * sh[k].astype(np.float64) + 0.5, 0.0)
+        assert np.allclose(rgb, ref, atol=2e-6), (k, rgb, ref)
+
+
+def test_near_plane_and_padding_culled():
+    W, H = 64, 48
+    cam = identity_cam(W, H)
+    # behind the near plane
+    vm = render(one_gaussian_scene([0, 0, 0.19], [0.05] * 3), cam, W, H)
+    assert vm.get("pp_int").reshape(-1, 6)[0, 0] == 1
+    assert vm.image().max() == 0.0
+    # a page of 4 with one real Gaussian: three padding entries, all culled
+    vm = render(one_gaussian_scene([0, 0, 3.0], [0.05] * 3), cam, W, H, page_size=4)
+    pi = vm.get("pp_int").reshape(-1, 6)
+    assert list(pi[:, 0]) == [0, 1, 1, 1]
+
+
+@pytest.fixture(scope="module")
+def cluster_frame():
+    sc = synth.scene_clusters(0)
+    osc = oracle.OracleScene(sc, 256, 1, 0.5, 2.0)
+    cams = synth.orbit()
+    vm = oracle.OracleVM(osc, 64, (320, 240), (80, 60))
+    vm.frame([cams[1]])
+    return vm
+
+
+def test_transmittance_invariants(cluster_frame):
+    vm = cluster_frame
+    T = vm.get("final_T")
+    img = vm.get("image").reshape(-1, 3)
+    assert T.min() >= 1e-4 and T.max() <= 1.0
+    pf = vm.get("pp_float").reshape(-1, 10)
+    pi = vm.get("pp_int").reshape(-1, 6)
+    max_rgb = pf[pi[:, 0] == 0, 7:10].max()
+    assert np.all(img.max(1) <= max_rgb * (1.0 - T) + 1e-5)
+    # pixels with no blended Gaussian are black with T = 1
+    nb = vm.get("contrib")
+    assert np.all(T[nb == 0] == 1.0) and np.all(img[nb == 0] == 0.0)
+
+
+def test_tile_lists_brute_force(cluster_frame):
+    vm = cluster_frame
+    TX, TY = vm.TX, vm.TY
+    pf = vm.get("pp_float").reshape(-1, 10)
+    pi = vm.get("pp_int").reshape(-1, 6)
+    keys = vm.get("keys")
+    vals = vm.get("vals")
+    ranges = vm.get("ranges").reshape(-1, 2)
+    assert np.all(np.diff(keys.astype(np.float64)) >= 0) and np.all(keys[1:] >= keys[:-1])
+    depth_bits = pf[:, 2].view(np.uint32)
+    for t in range(TX * TY):
+        tx, ty = t % TX, t // TX
+        cover = np.nonzero((pi[:, 0] == 0) & (pi[:, 1] <= tx) & (tx < pi[:, 3]) & (pi[:, 2] <= ty) & (ty < pi[:, 4]))[0]
+        order = cover[np.lexsort((cover, depth_bits[cover]))]
+        s, e = ranges[t]
+        assert np.array_equal(vals[s:e], order)
+        assert np.all((keys[s:e] >> np.uint64(32)) == t)
