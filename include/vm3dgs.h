@@ -1,0 +1,184 @@
+/*
+ * vm3dgs.h -- C ABI of the MI355X (gfx950) virtual-memory 3D Gaussian
+ * Splatting frame path.
+ *
+ * Method: Haberl et al., "Virtual Memory for 3D Gaussian Splatting"
+ * (arXiv 2506.19415).  Gaussians are grouped into fixed-size pages (Sec. 3,
+ * "Page Assignment"); every frame a visibility pass finds the pages the
+ * camera needs (Sec. 4.1, "Page Determination": frustum test, a
+ * low-resolution page-ID buffer of a proxy, page links and a level of detail
+ * from the nearest depth), a page table maps them onto a pool of physical
+ * pages with least-recently-used replacement (Sec. 4.1.1), misses are copied
+ * from pinned host memory, and only resident Gaussians are splatted with the
+ * 3DGS math of Kerbl et al. (Sec. 4.2).
+ *
+ * Conventions for every entry point:
+ *  - plain C types, no exceptions cross the boundary;
+ *  - a return value < 0 is an error; vm3dgs_last_error() gives its text;
+ *  - after a HIP runtime error the context is poisoned: every later call
+ *    returns VM3DGS_E_STATE and only vm3dgs_destroy() is valid;
+ *  - one context per host thread at a time (no internal locking);
+ *  - "device" pointers are HIP device allocations on the current device,
+ *    "host" pointers ordinary host memory.
+ */
+#ifndef VM3DGS_H
+#define VM3DGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vm3dgs vm3dgs;
+typedef int32_t vm3dgs_status;
+
+#define VM3DGS_OK 0
+#define VM3DGS_E_INVALID_ARG (-1) /* a size, pointer or option is out of range */
+#define VM3DGS_E_HOST_OOM (-2)    /* host or pinned host allocation failed */
+#define VM3DGS_E_DEVICE_OOM (-3)  /* device allocation failed */
+#define VM3DGS_E_HIP (-4)         /* a HIP runtime call failed; context poisoned */
+#define VM3DGS_E_STATE (-5)       /* context poisoned by an earlier error */
+#define VM3DGS_E_CAPACITY (-6)    /* more views than max_views */
+
+/* Scene in the storage form of Sec. 3 ("Scene Storage"): activated scale and
+ * opacity, quaternion w,x,y,z (normalised by create), degree-3 SH with the
+ * 16 coefficients of each channel interleaved as sh[k][channel].  All arrays
+ * are host memory, borrowed only for the duration of vm3dgs_create. */
+typedef struct {
+    uint64_t n;
+    const float* means;   /* [n][3] metres */
+    const float* scales;  /* [n][3] standard deviations, > 0 */
+    const float* quats;   /* [n][4] w x y z */
+    const float* opacity; /* [n] in [0, 1] */
+    const float* sh;      /* [n][16][3] */
+} vm3dgs_scene;
+
+#define VM3DGS_FLAG_LINKS 1u           /* expand page links (Sec. 3 "Page Linking") */
+#define VM3DGS_FLAG_FULL_SCENE_COPY 2u /* keep all level-0 pages in HBM for vm3dgs_render_full */
+
+typedef struct {
+    uint32_t img_w, img_h;        /* output image, pixels */
+    uint32_t idbuf_w, idbuf_h;    /* page-ID buffer, pixels (Sec. 5.1.1: much smaller than the image) */
+    uint32_t max_views;           /* views per call, >= 1 */
+    uint32_t attr_format;         /* 0: fp32 (236 B/Gaussian); 1: means fp32, scale/quat/opacity fp16, SH bf16 (124 B) */
+    uint32_t copy_budget_pages;   /* page copies per frame, 0 = unlimited (Sec. 4.3: staging budget) */
+    uint32_t reserved0;
+    float proxy_cell_m;           /* proxy grid cell edge, metres */
+    float link_sigma;             /* link ellipsoid radius in standard deviations */
+    float lod_radius_px;          /* level l is chosen while the projected page radius <= tau / 2^(l-1) */
+    uint32_t flags;               /* VM3DGS_FLAG_* */
+    void* stream_render;          /* hipStream_t for the frame's kernels, NULL = library-owned stream */
+    void* stream_copy;            /* hipStream_t for page copies, NULL = library-owned stream */
+    uint64_t pair_capacity;       /* initial (tile, Gaussian) pair capacity; grows on demand; 0 = automatic */
+} vm3dgs_options;
+
+/* Fill *o with defaults: 1920x1080 image, 240x135 ID buffer, one view, fp32,
+ * unlimited copies, 1 m cells, 2-sigma links, 32 px LOD radius, links on. */
+void vm3dgs_options_default(vm3dgs_options* o);
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward).  view is the
+ * row-major 4x4 world-to-camera matrix, cam_pos the camera centre in world
+ * space.  Pixel centres are at integer + 0.5 in [0, img_w) x [0, img_h). */
+typedef struct {
+    float view[16];
+    float cam_pos[3];
+    float fx, fy, cx, cy, znear;
+} vm3dgs_camera;
+
+typedef struct {
+    uint32_t candidates;        /* pages passing the frustum test (summed over views) */
+    uint32_t requested;         /* unique pages requested */
+    uint32_t direct;            /* requested because seen in the ID buffer */
+    uint32_t linked;            /* requested only through a link */
+    uint32_t hits, misses, evictions, missing, copies;
+    uint32_t render_pages;      /* resident requested pages splatted this frame */
+    uint32_t pool_pages_used;   /* physical pages holding at least one virtual page */
+    uint32_t reserved0;
+    uint64_t render_gaussians;  /* Gaussians in the render set (incl. padding) x views */
+    uint64_t visible_gaussians; /* of those, not culled by the projection */
+    uint64_t pairs;             /* (tile, Gaussian) pairs sorted and blended */
+    uint64_t bytes_copied;      /* host -> device page bytes */
+    float ms_visibility, ms_pagetable, ms_copy, ms_preprocess, ms_sort, ms_blend, ms_total;
+} vm3dgs_stats;
+
+typedef struct {
+    const int32_t* requests;      /* host, context-owned: page ids in service order (class, depth, page) */
+    const int8_t* request_level;  /* host, context-owned: LOD level per request */
+    uint32_t n_requests;
+    const int32_t* missing;       /* host, context-owned: [n_missing][2] page, level not made resident */
+    uint32_t n_missing;
+    vm3dgs_stats stats;
+} vm3dgs_frame_out;
+
+/* Build the paged scene (Sec. 3): Morton-ordered pages of page_size Gaussians
+ * (last page padded with zero Gaussians), lod_levels levels (1..3; level l
+ * holds page_size / 8^l Gaussians per page, each the opacity-weighted moment
+ * match of 8 children), proxy boxes and links, the page-major pinned host
+ * store, and a device pool of pool_pages physical pages.
+ * Errors: INVALID_ARG if scene or out is NULL, n == 0, page_size == 0,
+ * lod_levels not in 1..3, page_size not divisible by 8^(lod_levels-1),
+ * pool_pages == 0, image or ID-buffer size 0, max_views == 0 or > 64;
+ * HOST_OOM / DEVICE_OOM on allocation failure.  On error *out is NULL. */
+vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint32_t pool_pages,
+                            uint32_t lod_levels, const vm3dgs_options* opt, vm3dgs** out);
+
+/* One frame for n_views cameras (Sec. 4): visibility, page table, copies of
+ * the misses (host -> device on the copy stream; the render stream waits for
+ * them), splatting of the resident pages.  image_dev: device, caller-owned,
+ * [n_views][img_h][img_w][3] float32, written on the render stream and
+ * complete when that stream reaches the end of this call's work.  The frame
+ * counter advances on every call.  out may be NULL.
+ * Errors: INVALID_ARG (NULL cams/image, n_views == 0), CAPACITY
+ * (n_views > max_views), HIP, STATE. */
+vm3dgs_status vm3dgs_frame(vm3dgs* ctx, const vm3dgs_camera* cams, uint32_t n_views, float* image_dev,
+                           vm3dgs_frame_out* out);
+
+/* Splat every level-0 Gaussian of the scene with the same kernels and no
+ * paging (the no-virtual-memory baseline of Sec. 5.3).  Needs
+ * VM3DGS_FLAG_FULL_SCENE_COPY at create.  image_dev as in vm3dgs_frame;
+ * stats may be NULL.  Does not touch the page table. */
+vm3dgs_status vm3dgs_render_full(vm3dgs* ctx, const vm3dgs_camera* cams, uint32_t n_views, float* image_dev,
+                                 vm3dgs_stats* stats);
+
+/* Copy a named piece of state or of the last frame's intermediates to host
+ * memory (parity checks).  Returns the byte size of the item (and copies it
+ * when host_dst != NULL and cap >= size), or -1 for an unknown name.
+ * Waits for the render stream.  Names: "info", "perm", "spheres", "cell_box",
+ * "cell_page", "link_start", "link_dst", "cand", "idbuf", "req_direct",
+ * "req_link", "page_level", "slot_level", "last_used", "sub_vpage",
+ * "sub_last_used", "v2p", "copies", "copy_id", "render_list", "pp_float",
+ * "pp_int", "keys", "vals", "ranges", "host_page" (level-0 attributes of all
+ * pages decoded to 59 floats). */
+int64_t vm3dgs_debug_get(vm3dgs* ctx, const char* name, void* host_dst, int64_t cap);
+
+/* Block until the render and copy streams are idle. */
+vm3dgs_status vm3dgs_sync(vm3dgs* ctx);
+
+/* Create-time paging only (Sec. 3), on the host, with no device work: the
+ * same Morton pages, proxy boxes, links, spheres and LOD levels that
+ * vm3dgs_create builds.  For inspection and host-side checks.  Items are read
+ * with vm3dgs_pages_get ("info", "perm", "spheres", "cell_box", "cell_page",
+ * "cell_start", "link_start", "link_dst", "rec0", "rec1", "rec2" (decoded
+ * 59-float records per level), "store" (the encoded page-major store)).
+ * Errors as for vm3dgs_create (INVALID_ARG, HOST_OOM). */
+typedef struct vm3dgs_pages vm3dgs_pages;
+vm3dgs_status vm3dgs_pages_build(const vm3dgs_scene* scene, uint32_t page_size, uint32_t lod_levels,
+                                 const vm3dgs_options* opt, vm3dgs_pages** out);
+int64_t vm3dgs_pages_get(const vm3dgs_pages* pages, const char* name, void* host_dst, int64_t cap);
+void vm3dgs_pages_destroy(vm3dgs_pages* pages);
+
+/* Text of the last error of this context (never NULL; "" when none). */
+const char* vm3dgs_last_error(const vm3dgs* ctx);
+
+/* Text of the last vm3dgs_create failure in this thread. */
+const char* vm3dgs_create_error(void);
+
+/* Release every host and device resource.  NULL is allowed. */
+void vm3dgs_destroy(vm3dgs* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

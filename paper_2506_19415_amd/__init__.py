@@ -1,0 +1,245 @@
+"""Python binding of the MI355X virtual-memory 3DGS library (libvm3dgs.so).
+
+Thin ctypes layer over include/vm3dgs.h: the functions below have the C
+names and only marshal arguments; every step of a frame runs in the HIP
+kernels of the shared library.  PyTorch is used for device memory (the
+output image) only.  When the shared library is missing this module raises
+at import of the library (no fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvm3dgs.so")
+
+VM3DGS_FLAG_LINKS = 1
+VM3DGS_FLAG_FULL_SCENE_COPY = 2
+
+_ERRORS = {-1: "INVALID_ARG", -2: "HOST_OOM", -3: "DEVICE_OOM", -4: "HIP", -5: "STATE", -6: "CAPACITY"}
+
+
+class Vm3dgsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"vm3dgs error {code} ({_ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class vm3dgs_scene(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class vm3dgs_options(C.Structure):
+    _fields_ = [("img_w", C.c_uint32), ("img_h", C.c_uint32), ("idbuf_w", C.c_uint32), ("idbuf_h", C.c_uint32),
+                ("max_views", C.c_uint32), ("attr_format", C.c_uint32), ("copy_budget_pages", C.c_uint32),
+                ("reserved0", C.c_uint32), ("proxy_cell_m", C.c_float), ("link_sigma", C.c_float),
+                ("lod_radius_px", C.c_float), ("flags", C.c_uint32), ("stream_render", C.c_void_p),
+                ("stream_copy", C.c_void_p), ("pair_capacity", C.c_uint64)]
+
+
+class vm3dgs_camera(C.Structure):
+    _fields_ = [("view", C.c_float * 16), ("cam_pos", C.c_float * 3), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("znear", C.c_float)]
+
+
+class vm3dgs_stats(C.Structure):
+    _fields_ = [(n, C.c_uint32) for n in ("candidates", "requested", "direct", "linked", "hits", "misses",
+                                           "evictions", "missing", "copies", "render_pages", "pool_pages_used",
+                                           "reserved0")] + \
+               [(n, C.c_uint64) for n in ("render_gaussians", "visible_gaussians", "pairs", "bytes_copied")] + \
+               [(n, C.c_float) for n in ("ms_visibility", "ms_pagetable", "ms_copy", "ms_preprocess", "ms_sort",
+                                          "ms_blend", "ms_total")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved0"}
+
+
+class vm3dgs_frame_out(C.Structure):
+    _fields_ = [("requests", C.POINTER(C.c_int32)), ("request_level", C.POINTER(C.c_int8)),
+                ("n_requests", C.c_uint32), ("missing", C.POINTER(C.c_int32)), ("n_missing", C.c_uint32),
+                ("stats", vm3dgs_stats)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libvm3dgs.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2506_19415_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        L.vm3dgs_options_default.argtypes = [C.POINTER(vm3dgs_options)]
+        L.vm3dgs_create.argtypes = [C.POINTER(vm3dgs_scene), C.c_uint32, C.c_uint32, C.c_uint32,
+                                    C.POINTER(vm3dgs_options), C.POINTER(C.c_void_p)]
+        L.vm3dgs_create.restype = C.c_int32
+        L.vm3dgs_frame.argtypes = [C.c_void_p, C.POINTER(vm3dgs_camera), C.c_uint32, C.c_void_p,
+                                   C.POINTER(vm3dgs_frame_out)]
+        L.vm3dgs_frame.restype = C.c_int32
+        L.vm3dgs_render_full.argtypes = [C.c_void_p, C.POINTER(vm3dgs_camera), C.c_uint32, C.c_void_p,
+                                         C.POINTER(vm3dgs_stats)]
+        L.vm3dgs_render_full.restype = C.c_int32
+        L.vm3dgs_debug_get.argtypes = [C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64]
+        L.vm3dgs_debug_get.restype = C.c_int64
+        L.vm3dgs_sync.argtypes = [C.c_void_p]
+        L.vm3dgs_sync.restype = C.c_int32
+        L.vm3dgs_last_error.argtypes = [C.c_void_p]
+        L.vm3dgs_last_error.restype = C.c_char_p
+        L.vm3dgs_create_error.argtypes = []
+        L.vm3dgs_create_error.restype = C.c_char_p
+        L.vm3dgs_destroy.argtypes = [C.c_void_p]
+        L.vm3dgs_pages_build.argtypes = [C.POINTER(vm3dgs_scene), C.c_uint32, C.c_uint32,
+                                         C.POINTER(vm3dgs_options), C.POINTER(C.c_void_p)]
+        L.vm3dgs_pages_build.restype = C.c_int32
+        L.vm3dgs_pages_get.argtypes = [C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64]
+        L.vm3dgs_pages_get.restype = C.c_int64
+        L.vm3dgs_pages_destroy.argtypes = [C.c_void_p]
+        _lib = L
+    return _lib
+
+
+# ------------------------------------------------------------------ C names
+def vm3dgs_options_default() -> vm3dgs_options:
+    o = vm3dgs_options()
+    lib().vm3dgs_options_default(C.byref(o))
+    return o
+
+
+def _cameras(cams):
+    arr = (vm3dgs_camera * len(cams))()
+    for i, c in enumerate(cams):
+        v = np.ascontiguousarray(c.view, dtype=np.float32).reshape(16)
+        arr[i].view[:] = [float(x) for x in v]
+        arr[i].cam_pos[:] = [float(x) for x in np.asarray(c.cam_pos, np.float32)]
+        arr[i].fx, arr[i].fy, arr[i].cx, arr[i].cy, arr[i].znear = (float(c.fx), float(c.fy), float(c.cx),
+                                                                    float(c.cy), float(c.znear))
+    return arr
+
+
+def vm3dgs_create(scene, page_size, pool_pages, lod_levels=1, opts: vm3dgs_options = None):
+    keep = [np.ascontiguousarray(a, dtype=np.float32) for a in
+            (scene.means, scene.scales, scene.quats, scene.opacity, scene.sh)]
+    s = vm3dgs_scene(scene.n, *[a.ctypes.data for a in keep])
+    h = C.c_void_p()
+    rc = lib().vm3dgs_create(C.byref(s), int(page_size), int(pool_pages), int(lod_levels),
+                             None if opts is None else C.byref(opts), C.byref(h))
+    if rc != 0:
+        raise Vm3dgsError(rc, lib().vm3dgs_create_error().decode())
+    return h
+
+
+def _check(h, rc):
+    if rc != 0:
+        raise Vm3dgsError(rc, lib().vm3dgs_last_error(h).decode())
+
+
+def vm3dgs_frame(h, cams, image_dev_ptr: int) -> vm3dgs_frame_out:
+    out = vm3dgs_frame_out()
+    arr = _cameras(cams)
+    _check(h, lib().vm3dgs_frame(h, arr, len(cams), C.c_void_p(image_dev_ptr), C.byref(out)))
+    return out
+
+
+def vm3dgs_render_full(h, cams, image_dev_ptr: int) -> vm3dgs_stats:
+    st = vm3dgs_stats()
+    arr = _cameras(cams)
+    _check(h, lib().vm3dgs_render_full(h, arr, len(cams), C.c_void_p(image_dev_ptr), C.byref(st)))
+    return st
+
+
+def vm3dgs_debug_get(h, name: str, dtype) -> np.ndarray:
+    n = lib().vm3dgs_debug_get(h, name.encode(), None, 0)
+    if n < 0:
+        raise KeyError(name)
+    dt = np.dtype(dtype)
+    out = np.empty(n // dt.itemsize, dtype=dt)
+    if n > 0 and lib().vm3dgs_debug_get(h, name.encode(), out.ctypes.data, n) < 0:
+        raise Vm3dgsError(-4, "debug copy failed")
+    return out
+
+
+def vm3dgs_pages_build(scene, page_size, lod_levels=1, opts: vm3dgs_options = None):
+    keep = [np.ascontiguousarray(a, dtype=np.float32) for a in
+            (scene.means, scene.scales, scene.quats, scene.opacity, scene.sh)]
+    s = vm3dgs_scene(scene.n, *[a.ctypes.data for a in keep])
+    h = C.c_void_p()
+    rc = lib().vm3dgs_pages_build(C.byref(s), int(page_size), int(lod_levels),
+                                  None if opts is None else C.byref(opts), C.byref(h))
+    if rc != 0:
+        raise Vm3dgsError(rc, lib().vm3dgs_create_error().decode())
+    return h
+
+
+def vm3dgs_pages_get(h, name: str, dtype) -> np.ndarray:
+    n = lib().vm3dgs_pages_get(h, name.encode(), None, 0)
+    if n < 0:
+        raise KeyError(name)
+    dt = np.dtype(dtype)
+    out = np.empty(n // dt.itemsize, dtype=dt)
+    if n > 0:
+        lib().vm3dgs_pages_get(h, name.encode(), out.ctypes.data, n)
+    return out
+
+
+def vm3dgs_pages_destroy(h):
+    lib().vm3dgs_pages_destroy(h)
+
+
+def vm3dgs_sync(h):
+    _check(h, lib().vm3dgs_sync(h))
+
+
+def vm3dgs_destroy(h):
+    lib().vm3dgs_destroy(h)
+
+
+# ------------------------------------------------------------------ convenience
+class Renderer:
+    """Owns one library context and a device image buffer (torch tensor)."""
+
+    def __init__(self, scene, page_size, pool_pages, lod_levels=1, img=(1920, 1080), idbuf=(240, 135),
+                 max_views=1, attr_format=0, cell=1.0, link_sigma=2.0, lod_radius_px=32.0, links=True,
+                 full_scene=False, copy_budget=0, pair_capacity=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("Renderer needs a HIP device")
+        o = vm3dgs_options_default()
+        o.img_w, o.img_h = img
+        o.idbuf_w, o.idbuf_h = idbuf
+        o.max_views = max_views
+        o.attr_format = attr_format
+        o.copy_budget_pages = copy_budget
+        o.proxy_cell_m, o.link_sigma, o.lod_radius_px = cell, link_sigma, lod_radius_px
+        o.flags = (VM3DGS_FLAG_LINKS if links else 0) | (VM3DGS_FLAG_FULL_SCENE_COPY if full_scene else 0)
+        o.pair_capacity = pair_capacity
+        self.opts = o
+        self.W, self.H = img
+        self.h = vm3dgs_create(scene, page_size, pool_pages, lod_levels, o)
+        self.image = torch.empty((max_views, self.H, self.W, 3), dtype=torch.float32, device="cuda")
+
+    def frame(self, cams):
+        out = vm3dgs_frame(self.h, cams, self.image.data_ptr())
+        return self.image[:len(cams)], out
+
+    def render_full(self, cams):
+        st = vm3dgs_render_full(self.h, cams, self.image.data_ptr())
+        return self.image[:len(cams)], st
+
+    def get(self, name, dtype):
+        return vm3dgs_debug_get(self.h, name, dtype)
+
+    def close(self):
+        if self.h:
+            vm3dgs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

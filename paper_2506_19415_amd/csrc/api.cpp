@@ -1,0 +1,723 @@
+// api.cpp -- the C ABI of include/vm3dgs.h: context, frame scheduler, copies.
+//
+// One frame (Sec. 4 of the paper):
+//   render stream: camera upload -> visibility kernels -> page table kernel
+//   host:          read back the counters and the copy list (the one place the
+//                  host waits on the device before splatting, like the paper's
+//                  fence before its page-table update, Sec. 5.1.3)
+//   copy stream:   hipMemcpyAsync of every missed page (contiguous runs
+//                  merged) from the pinned page-major store into its pool slot
+//   render stream: waits for the copies, then preprocess -> depth sort ->
+//                  scan of tile counts (pair total read back to size the
+//                  pair buffers) -> pair emission -> tile sort -> ranges ->
+//                  blend into the caller's image
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "vm3dgs_impl.h"
+
+namespace vm {
+bool pagetable_l1_fits(int n_pg, int S);
+}
+
+using namespace vm;
+
+struct vm3dgs {
+    vm3dgs_options opt{};
+    PagedScene ps;
+    int S = 0, L = 1, P = 0, n_pg = 0, TX = 0, TY = 0;
+    hipStream_t sr = nullptr, sc = nullptr;
+    bool own_sr = false, own_sc = false;
+    hipEvent_t ev_copy = nullptr;
+    hipEvent_t ev[8] = {};
+    // scene on the device
+    float4* d_sph = nullptr; float4* d_clo = nullptr; float4* d_chi = nullptr;
+    int32_t* d_ls = nullptr; int32_t* d_ld = nullptr;
+    uint8_t* d_pool = nullptr; uint8_t* d_full = nullptr; uint8_t* h_store = nullptr;
+    int64_t* d_level_base = nullptr;
+    CamK* d_cams = nullptr; CamK* h_cams = nullptr;
+    // visibility
+    uint8_t* d_cand = nullptr; float4* d_rays = nullptr; unsigned long long* d_idbuf = nullptr;
+    uint32_t* d_rd = nullptr; uint32_t* d_rl = nullptr; int8_t* d_plevel = nullptr; uint64_t* d_keys = nullptr;
+    uint32_t* d_ctr = nullptr; uint32_t* h_ctr = nullptr;
+    // page table
+    int8_t* d_slot_level = nullptr; int32_t* d_last_used = nullptr; int32_t* d_sub_vpage = nullptr;
+    int32_t* d_sub_lu = nullptr; int32_t* d_v2p = nullptr; uint8_t* d_req_sub = nullptr; uint8_t* d_slot_req = nullptr;
+    uint32_t* d_miss = nullptr;
+    CopyCmd* d_copies = nullptr; CopyCmd* h_copies = nullptr; int32_t* d_copy_id = nullptr;
+    int32_t* d_missing = nullptr; int32_t* h_missing = nullptr;
+    uint64_t* h_keys = nullptr;
+    RenderEntry* d_rlist = nullptr; RenderEntry* d_rlist_full = nullptr;
+    // splat
+    uint64_t cap_render = 0;
+    float2* d_xy = nullptr; float4* d_conic = nullptr; float4* d_rgb = nullptr;
+    uint32_t* d_depth = nullptr; uint2* d_rect = nullptr; uint32_t* d_tiles = nullptr;
+    uint32_t* d_dkey[2] = {nullptr, nullptr}; uint32_t* d_dval[2] = {nullptr, nullptr};
+    uint32_t* d_offs = nullptr;
+    uint64_t cap_pairs = 0;
+    uint32_t* d_pkey[2] = {nullptr, nullptr}; uint32_t* d_pval[2] = {nullptr, nullptr};
+    uint2* d_ranges = nullptr;
+    uint32_t* d_temp = nullptr; size_t temp_words = 0;
+    uint32_t* d_total = nullptr; uint32_t* h_total = nullptr;
+    int frame = 0;
+    // last frame, for vm3dgs_debug_get and the frame output
+    uint32_t last_views = 0, last_n_render = 0, last_n_pairs = 0, last_n_copy = 0, last_n_missing = 0;
+    uint32_t last_n_req = 0, last_n_rl = 0;
+    int last_pbuf = 0, last_dbuf = 0;
+    std::vector<int32_t> out_req, out_missing;
+    std::vector<int8_t> out_req_level;
+    std::string err;
+    bool poisoned = false;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct HipError {
+    hipError_t e;
+    const char* what;
+    int line;
+};
+
+#define HIPCHK(x)                                        \
+    do {                                                 \
+        hipError_t e_ = (x);                             \
+        if (e_ != hipSuccess) throw HipError{e_, #x, __LINE__}; \
+    } while (0)
+
+template <class T>
+void dalloc(T** p, size_t count) {
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * count);
+    if (e != hipSuccess) throw HipError{e, "hipMalloc", __LINE__};
+}
+
+template <class T>
+void dfree(T*& p) {
+    if (p) hipFree((void*)p);
+    p = nullptr;
+}
+
+template <class T>
+void halloc(T** p, size_t count) {
+    if (count == 0) count = 1;
+    hipError_t e = hipHostMalloc((void**)p, sizeof(T) * count, hipHostMallocDefault);
+    if (e != hipSuccess) throw HipError{e, "hipHostMalloc", __LINE__};
+}
+
+template <class T>
+void hfree(T*& p) {
+    if (p) hipHostFree((void*)p);
+    p = nullptr;
+}
+
+int bits_for(uint64_t n) {
+    int b = 0;
+    while ((1ull << b) < n) ++b;
+    return b;
+}
+
+void to_camk(const vm3dgs_camera& c, CamK& k) {
+    for (int i = 0; i < 12; ++i) k.V[i] = c.view[i];
+    for (int i = 0; i < 3; ++i) k.pos[i] = c.cam_pos[i];
+    k.fx = c.fx; k.fy = c.fy; k.cx = c.cx; k.cy = c.cy; k.znear = c.znear;
+}
+
+void free_all(vm3dgs* c) {
+    if (c->sr) hipStreamSynchronize(c->sr);
+    if (c->sc) hipStreamSynchronize(c->sc);
+    dfree(c->d_sph); dfree(c->d_clo); dfree(c->d_chi); dfree(c->d_ls); dfree(c->d_ld);
+    dfree(c->d_pool); dfree(c->d_full); hfree(c->h_store); dfree(c->d_level_base);
+    dfree(c->d_cams); hfree(c->h_cams);
+    dfree(c->d_cand); dfree(c->d_rays); dfree(c->d_idbuf); dfree(c->d_rd); dfree(c->d_rl); dfree(c->d_plevel);
+    dfree(c->d_keys); dfree(c->d_ctr); hfree(c->h_ctr);
+    dfree(c->d_slot_level); dfree(c->d_last_used); dfree(c->d_sub_vpage); dfree(c->d_sub_lu); dfree(c->d_v2p);
+    dfree(c->d_req_sub); dfree(c->d_slot_req); dfree(c->d_miss);
+    dfree(c->d_copies); hfree(c->h_copies); dfree(c->d_copy_id); dfree(c->d_missing); hfree(c->h_missing);
+    hfree(c->h_keys);
+    dfree(c->d_rlist); dfree(c->d_rlist_full);
+    dfree(c->d_xy); dfree(c->d_conic); dfree(c->d_rgb); dfree(c->d_depth); dfree(c->d_rect); dfree(c->d_tiles);
+    for (int i = 0; i < 2; ++i) { dfree(c->d_dkey[i]); dfree(c->d_dval[i]); dfree(c->d_pkey[i]); dfree(c->d_pval[i]); }
+    dfree(c->d_offs); dfree(c->d_ranges); dfree(c->d_temp); dfree(c->d_total); hfree(c->h_total);
+    if (c->ev_copy) hipEventDestroy(c->ev_copy);
+    for (auto& e : c->ev)
+        if (e) hipEventDestroy(e);
+    if (c->own_sr && c->sr) hipStreamDestroy(c->sr);
+    if (c->own_sc && c->sc) hipStreamDestroy(c->sc);
+}
+
+void ensure_temp(vm3dgs* c) {
+    const size_t need = std::max({radix_temp_words(c->cap_render), radix_temp_words(c->cap_pairs),
+                                  scan_temp_words(c->cap_render), scan_temp_words(c->cap_pairs), (size_t)4096});
+    if (need > c->temp_words) {
+        dfree(c->d_temp);
+        dalloc(&c->d_temp, need);
+        c->temp_words = need;
+    }
+}
+
+void ensure_pairs(vm3dgs* c, uint64_t n) {
+    if (n <= c->cap_pairs) return;
+    HIPCHK(hipStreamSynchronize(c->sr));
+    const uint64_t cap = std::max<uint64_t>(n + n / 4, 1u << 20);
+    for (int i = 0; i < 2; ++i) {
+        dfree(c->d_pkey[i]); dfree(c->d_pval[i]);
+        dalloc(&c->d_pkey[i], cap);
+        dalloc(&c->d_pval[i], cap);
+    }
+    c->cap_pairs = cap;
+    ensure_temp(c);
+}
+
+// the render half of a frame: preprocess .. blend for n_render Gaussians per view
+void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool, uint32_t n_render, uint32_t n_views,
+           float* image, vm3dgs_stats* st) {
+    const uint64_t n_total = (uint64_t)n_render * n_views;
+    hipEvent_t* ev = c->ev;
+    HIPCHK(hipEventRecord(ev[3], c->sr));
+    SplatArgs a{};
+    a.rl = rl; a.n_rl = (int)n_rl; a.pool = pool; a.P = c->P; a.fmt = c->ps.fmt;
+    a.cams = c->d_cams; a.n_views = (int)n_views; a.W = (int)c->opt.img_w; a.H = (int)c->opt.img_h;
+    a.TX = c->TX; a.TY = c->TY; a.n_render = n_render;
+    a.xy = c->d_xy; a.conic = c->d_conic; a.rgb = c->d_rgb; a.depth = c->d_depth; a.rect = c->d_rect;
+    a.tiles = c->d_tiles; a.dkey = c->d_dkey[0]; a.dval = c->d_dval[0];
+    launch_preprocess(c->sr, a);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(ev[4], c->sr));
+    // depth order of the render set (culled entries carry all-ones keys and sort last)
+    const int db = radix_sort_u32(c->sr, c->d_dkey, c->d_dval, (uint32_t)n_total, 0, 32, c->d_temp);
+    scan_excl_gather(c->sr, c->d_tiles, c->d_dval[db], n_total, c->d_offs, c->d_total, c->d_temp);
+    HIPCHK(hipMemcpyAsync(c->h_total, c->d_total, sizeof(uint32_t), hipMemcpyDeviceToHost, c->sr));
+    HIPCHK(hipStreamSynchronize(c->sr));
+    const uint32_t n_pairs = *c->h_total;
+    ensure_pairs(c, n_pairs);
+    launch_emit(c->sr, c->d_dval[db], c->d_offs, c->d_rect, (uint32_t)n_total, n_render, c->TX, c->TY, c->d_pkey[0],
+                c->d_pval[0], (uint32_t)c->cap_pairs);
+    const uint32_t n_tiles = (uint32_t)(c->TX * c->TY) * n_views;
+    const int pb = radix_sort_u32(c->sr, c->d_pkey, c->d_pval, n_pairs, 0, std::max(1, bits_for(n_tiles)), c->d_temp);
+    launch_ranges(c->sr, c->d_pkey[pb], n_pairs, c->d_ranges, n_tiles);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(ev[5], c->sr));
+    launch_blend(c->sr, c->d_ranges, c->d_pval[pb], c->d_xy, c->d_conic, c->d_rgb, (int)c->opt.img_w,
+                 (int)c->opt.img_h, c->TX, c->TY, (int)n_views, image);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(ev[6], c->sr));
+    c->last_views = n_views; c->last_n_render = n_render; c->last_n_pairs = n_pairs;
+    c->last_pbuf = pb; c->last_dbuf = db;
+    if (st) {
+        st->render_gaussians = n_total;
+        st->pairs = n_pairs;
+    }
+}
+
+vm3dgs_status fail(vm3dgs* c, const HipError& h) {
+    c->err = std::string("HIP error ") + hipGetErrorString(h.e) + " in " + h.what + " (api.cpp:" +
+             std::to_string(h.line) + ")";
+    c->poisoned = true;
+    return VM3DGS_E_HIP;
+}
+
+vm3dgs_status bad(vm3dgs* c, const char* m) {
+    c->err = m;
+    return VM3DGS_E_INVALID_ARG;
+}
+
+float ms(hipEvent_t a, hipEvent_t b) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, a, b) != hipSuccess) return 0.0f;
+    return t;
+}
+
+}  // namespace
+
+extern "C" {
+
+void vm3dgs_options_default(vm3dgs_options* o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->img_w = 1920; o->img_h = 1080; o->idbuf_w = 240; o->idbuf_h = 135; o->max_views = 1;
+    o->attr_format = 0; o->copy_budget_pages = 0;
+    o->proxy_cell_m = 1.0f; o->link_sigma = 2.0f; o->lod_radius_px = 32.0f;
+    o->flags = VM3DGS_FLAG_LINKS;
+}
+
+const char* vm3dgs_create_error(void) { return g_create_error.c_str(); }
+
+vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint32_t pool_pages, uint32_t lod_levels,
+                            const vm3dgs_options* opt, vm3dgs** out) {
+    g_create_error.clear();
+    if (!out) { g_create_error = "out is NULL"; return VM3DGS_E_INVALID_ARG; }
+    *out = nullptr;
+    vm3dgs_options o;
+    if (opt) o = *opt; else vm3dgs_options_default(&o);
+    auto inval = [](const char* m) { g_create_error = m; return VM3DGS_E_INVALID_ARG; };
+    if (!scene || scene->n == 0 || !scene->means || !scene->scales || !scene->quats || !scene->opacity || !scene->sh)
+        return inval("scene is NULL or empty");
+    if (page_size == 0 || pool_pages == 0) return inval("page_size and pool_pages must be > 0");
+    if (lod_levels < 1 || lod_levels > 3) return inval("lod_levels must be 1..3");
+    for (uint32_t l = 1; l < lod_levels; ++l)
+        if ((page_size >> (3 * l)) == 0 || ((page_size >> (3 * l)) << (3 * l)) != page_size)
+            return inval("page_size must be divisible by 8^(lod_levels-1)");
+    if (o.img_w == 0 || o.img_h == 0 || o.idbuf_w == 0 || o.idbuf_h == 0) return inval("image sizes must be > 0");
+    if (o.img_w > 65535 * 16 || o.img_h > 65535 * 16) return inval("image too large");
+    if (o.max_views == 0 || o.max_views > 64) return inval("max_views must be 1..64");
+    if (o.attr_format > 1) return inval("attr_format must be 0 or 1");
+    if (!(o.proxy_cell_m > 0.0f) || !(o.link_sigma >= 0.0f) || !(o.lod_radius_px > 0.0f))
+        return inval("proxy_cell_m, link_sigma, lod_radius_px out of range");
+    if (scene->n > (uint64_t)INT32_MAX * page_size) return inval("scene too large");
+
+    vm3dgs* c = new (std::nothrow) vm3dgs();
+    if (!c) { g_create_error = "host allocation failed"; return VM3DGS_E_HOST_OOM; }
+    c->opt = o;
+    try {
+        std::string e = build_paged_scene(*scene, (int)page_size, (int)lod_levels, (int)o.attr_format,
+                                          (double)o.proxy_cell_m, (double)o.link_sigma, c->ps);
+        if (!e.empty()) { g_create_error = e; delete c; return VM3DGS_E_INVALID_ARG; }
+    } catch (const std::bad_alloc&) {
+        g_create_error = "host allocation failed";
+        delete c;
+        return VM3DGS_E_HOST_OOM;
+    }
+    const PagedScene& ps = c->ps;
+    c->S = (int)pool_pages; c->L = (int)lod_levels; c->P = (int)page_size; c->n_pg = ps.n_pg;
+    c->TX = (int)((o.img_w + 15) / 16); c->TY = (int)((o.img_h + 15) / 16);
+    if (c->L == 1 && !pagetable_l1_fits(c->n_pg, c->S)) {
+        g_create_error = "this build handles at most 8192 pages and 8192 physical pages with one LOD level";
+        delete c;
+        return VM3DGS_E_INVALID_ARG;
+    }
+    if (c->L > 1) {
+        g_create_error = "several LOD levels are not enabled in this build of the frame path";
+        delete c;
+        return VM3DGS_E_INVALID_ARG;
+    }
+    try {
+        if (o.stream_render) c->sr = (hipStream_t)o.stream_render;
+        else { HIPCHK(hipStreamCreateWithFlags(&c->sr, hipStreamNonBlocking)); c->own_sr = true; }
+        if (o.stream_copy) c->sc = (hipStream_t)o.stream_copy;
+        else { HIPCHK(hipStreamCreateWithFlags(&c->sc, hipStreamNonBlocking)); c->own_sc = true; }
+        HIPCHK(hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming));
+        for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+        const int n_pg = c->n_pg, S = c->S, L = c->L, V = (int)o.max_views;
+        const int64_t nc = ps.nc();
+        // scene metadata
+        dalloc(&c->d_sph, n_pg);
+        HIPCHK(hipMemcpy(c->d_sph, ps.spheres.data(), sizeof(float) * 4 * n_pg, hipMemcpyHostToDevice));
+        dalloc(&c->d_clo, nc); dalloc(&c->d_chi, nc);
+        if (nc) {
+            HIPCHK(hipMemcpy(c->d_clo, ps.cell_lo.data(), sizeof(float) * 4 * nc, hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(c->d_chi, ps.cell_hi.data(), sizeof(float) * 4 * nc, hipMemcpyHostToDevice));
+        }
+        dalloc(&c->d_ls, n_pg + 1);
+        HIPCHK(hipMemcpy(c->d_ls, ps.link_start.data(), sizeof(int32_t) * (n_pg + 1), hipMemcpyHostToDevice));
+        dalloc(&c->d_ld, ps.link_dst.size());
+        if (!ps.link_dst.empty())
+            HIPCHK(hipMemcpy(c->d_ld, ps.link_dst.data(), sizeof(int32_t) * ps.link_dst.size(), hipMemcpyHostToDevice));
+        dalloc(&c->d_level_base, 3);
+        HIPCHK(hipMemcpy(c->d_level_base, ps.level_base, sizeof(int64_t) * 3, hipMemcpyHostToDevice));
+        // pinned page-major store and the pool
+        halloc(&c->h_store, (size_t)ps.store_bytes);
+        encode_store(ps, c->h_store);
+        const size_t slot_bytes = (size_t)c->P * ps.bytes_g;
+        dalloc(&c->d_pool, slot_bytes * S);
+        HIPCHK(hipMemset(c->d_pool, 0, slot_bytes * S));
+        if (o.flags & VM3DGS_FLAG_FULL_SCENE_COPY) {
+            dalloc(&c->d_full, slot_bytes * n_pg);
+            HIPCHK(hipMemcpy(c->d_full, c->h_store, slot_bytes * n_pg, hipMemcpyHostToDevice));
+        }
+        dalloc(&c->d_cams, V); halloc(&c->h_cams, V);
+        // visibility
+        const int64_t npx = (int64_t)o.idbuf_w * o.idbuf_h;
+        dalloc(&c->d_cand, (size_t)V * n_pg); dalloc(&c->d_rays, (size_t)V * npx); dalloc(&c->d_idbuf, (size_t)V * npx);
+        dalloc(&c->d_rd, n_pg); dalloc(&c->d_rl, n_pg); dalloc(&c->d_plevel, n_pg);
+        dalloc(&c->d_keys, (size_t)2 * n_pg); halloc(&c->h_keys, n_pg);
+        dalloc(&c->d_ctr, C_NCOUNTERS); halloc(&c->h_ctr, C_NCOUNTERS);
+        // page table (empty pool)
+        dalloc(&c->d_slot_level, S); dalloc(&c->d_last_used, S); dalloc(&c->d_sub_vpage, (size_t)S * SUBS);
+        dalloc(&c->d_sub_lu, (size_t)S * SUBS); dalloc(&c->d_v2p, (size_t)n_pg * L);
+        dalloc(&c->d_req_sub, (size_t)S * SUBS); dalloc(&c->d_slot_req, S); dalloc(&c->d_miss, (size_t)n_pg * L);
+        HIPCHK(hipMemset(c->d_slot_level, 0xff, S));
+        HIPCHK(hipMemset(c->d_last_used, 0xff, sizeof(int32_t) * S));
+        HIPCHK(hipMemset(c->d_sub_vpage, 0xff, sizeof(int32_t) * S * SUBS));
+        HIPCHK(hipMemset(c->d_sub_lu, 0xff, sizeof(int32_t) * S * SUBS));
+        HIPCHK(hipMemset(c->d_v2p, 0xff, sizeof(int32_t) * n_pg * L));
+        dalloc(&c->d_copies, (size_t)n_pg * L); halloc(&c->h_copies, (size_t)n_pg * L);
+        dalloc(&c->d_copy_id, (size_t)4 * n_pg * L);
+        dalloc(&c->d_missing, (size_t)2 * n_pg * L); halloc(&c->h_missing, (size_t)2 * n_pg * L);
+        dalloc(&c->d_rlist, n_pg);
+        // splat buffers
+        const uint64_t per_view = std::max<uint64_t>((uint64_t)S * c->P,
+                                                     (o.flags & VM3DGS_FLAG_FULL_SCENE_COPY) ? (uint64_t)n_pg * c->P : 0);
+        if (per_view * V > 0xffffffffull) throw HipError{hipErrorInvalidValue, "render set exceeds 2^32", __LINE__};
+        c->cap_render = per_view * V;
+        const uint64_t R = c->cap_render;
+        dalloc(&c->d_xy, R); dalloc(&c->d_conic, R); dalloc(&c->d_rgb, R); dalloc(&c->d_depth, R);
+        dalloc(&c->d_rect, R); dalloc(&c->d_tiles, R); dalloc(&c->d_offs, R + 1);
+        for (int i = 0; i < 2; ++i) { dalloc(&c->d_dkey[i], R); dalloc(&c->d_dval[i], R); }
+        dalloc(&c->d_ranges, (size_t)c->TX * c->TY * V);
+        dalloc(&c->d_total, 4); halloc(&c->h_total, 4);
+        c->cap_pairs = 0;
+        ensure_pairs(c, o.pair_capacity ? o.pair_capacity : std::max<uint64_t>(R * 4, 1u << 22));
+        ensure_temp(c);
+        if (o.flags & VM3DGS_FLAG_FULL_SCENE_COPY) {
+            std::vector<RenderEntry> full((size_t)n_pg);
+            for (int p = 0; p < n_pg; ++p)
+                full[(size_t)p] = RenderEntry{(uint32_t)p * (uint32_t)c->P, (uint32_t)c->P, (uint32_t)p * (uint32_t)c->P, 0u};
+            dalloc(&c->d_rlist_full, n_pg);
+            HIPCHK(hipMemcpy(c->d_rlist_full, full.data(), sizeof(RenderEntry) * n_pg, hipMemcpyHostToDevice));
+        }
+        HIPCHK(hipDeviceSynchronize());
+    } catch (const HipError& h) {
+        g_create_error = std::string("HIP error ") + hipGetErrorString(h.e) + " in " + h.what;
+        const bool oom = h.e == hipErrorOutOfMemory || h.e == hipErrorMemoryAllocation;
+        free_all(c);
+        delete c;
+        return oom ? VM3DGS_E_DEVICE_OOM : VM3DGS_E_HIP;
+    } catch (const std::bad_alloc&) {
+        g_create_error = "host allocation failed";
+        free_all(c);
+        delete c;
+        return VM3DGS_E_HOST_OOM;
+    }
+    *out = c;
+    return VM3DGS_OK;
+}
+
+vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views, float* image,
+                           vm3dgs_frame_out* out) {
+    if (!c) return VM3DGS_E_INVALID_ARG;
+    if (c->poisoned) return VM3DGS_E_STATE;
+    if (!cams || !image || n_views == 0) return bad(c, "cams, image and n_views must be given");
+    if (n_views > c->opt.max_views) { c->err = "n_views exceeds max_views"; return VM3DGS_E_CAPACITY; }
+    vm3dgs_stats st{};
+    try {
+        hipEvent_t* ev = c->ev;
+        float fy_max = 0.0f;
+        for (uint32_t v = 0; v < n_views; ++v) {
+            to_camk(cams[v], c->h_cams[v]);
+            fy_max = std::max(fy_max, cams[v].fy);
+        }
+        HIPCHK(hipEventRecord(ev[0], c->sr));
+        HIPCHK(hipMemcpyAsync(c->d_cams, c->h_cams, sizeof(CamK) * n_views, hipMemcpyHostToDevice, c->sr));
+        launch_fill_u32(c->sr, c->d_ctr, C_NCOUNTERS, 0u);
+        VisArgs va{};
+        va.spheres = c->d_sph; va.n_pg = c->n_pg; va.cell_lo = c->d_clo; va.cell_hi = c->d_chi; va.nc = c->ps.nc();
+        va.link_start = c->d_ls; va.link_dst = c->d_ld; va.use_links = (c->opt.flags & VM3DGS_FLAG_LINKS) ? 1 : 0;
+        va.cams = c->d_cams; va.n_views = (int)n_views; va.W = (int)c->opt.img_w; va.H = (int)c->opt.img_h;
+        va.Wv = (int)c->opt.idbuf_w; va.Hv = (int)c->opt.idbuf_h; va.L = c->L; va.tau = c->opt.lod_radius_px;
+        va.fy_max = fy_max;
+        va.cand = c->d_cand; va.rays = c->d_rays; va.idbuf = c->d_idbuf; va.req_direct = c->d_rd; va.req_link = c->d_rl;
+        va.page_level = c->d_plevel; va.req_keys = c->d_keys; va.counters = c->d_ctr;
+        launch_visibility(c->sr, va);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipEventRecord(ev[1], c->sr));
+        PtArgs pa{};
+        pa.req_keys = c->d_keys; pa.n_pg = c->n_pg; pa.L = c->L; pa.P = c->P; pa.S = c->S; pa.frame = c->frame;
+        pa.budget = (int)c->opt.copy_budget_pages; pa.bytes_g = c->ps.bytes_g; pa.page_level = c->d_plevel;
+        pa.slot_level = c->d_slot_level; pa.last_used = c->d_last_used; pa.sub_vpage = c->d_sub_vpage;
+        pa.sub_last_used = c->d_sub_lu; pa.v2p = c->d_v2p; pa.req_sub = c->d_req_sub; pa.slot_req = c->d_slot_req;
+        pa.miss = c->d_miss; pa.copies = c->d_copies; pa.copy_id = c->d_copy_id; pa.missing = c->d_missing;
+        pa.counters = c->d_ctr; pa.level_base = c->d_level_base; pa.rl = c->d_rlist;
+        launch_pagetable(c->sr, pa, 0);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipEventRecord(ev[2], c->sr));
+        HIPCHK(hipMemcpyAsync(c->h_ctr, c->d_ctr, sizeof(uint32_t) * C_NCOUNTERS, hipMemcpyDeviceToHost, c->sr));
+        HIPCHK(hipStreamSynchronize(c->sr));
+        const uint32_t* k = c->h_ctr;
+        const uint32_t n_copy = k[C_NCOPY];
+        if (n_copy) {
+            HIPCHK(hipMemcpyAsync(c->h_copies, c->d_copies, sizeof(CopyCmd) * n_copy, hipMemcpyDeviceToHost, c->sr));
+            HIPCHK(hipStreamSynchronize(c->sr));
+            // merge runs that are contiguous on both sides, then one async copy per run
+            const CopyCmd* cp = c->h_copies;
+            uint32_t i = 0;
+            uint64_t bytes = 0;
+            while (i < n_copy) {
+                int64_t h = cp[i].host_off, d = cp[i].pool_off, b = cp[i].bytes;
+                uint32_t j = i + 1;
+                while (j < n_copy && cp[j].host_off == h + b && cp[j].pool_off == d + b) { b += cp[j].bytes; ++j; }
+                HIPCHK(hipMemcpyAsync(c->d_pool + d, c->h_store + h, (size_t)b, hipMemcpyHostToDevice, c->sc));
+                bytes += (uint64_t)b;
+                i = j;
+            }
+            HIPCHK(hipEventRecord(c->ev_copy, c->sc));
+            HIPCHK(hipStreamWaitEvent(c->sr, c->ev_copy, 0));
+            st.bytes_copied = bytes;
+        }
+        const uint32_t n_render = k[C_NRENDER];
+        c->last_n_copy = n_copy; c->last_n_missing = k[C_NMISSING]; c->last_n_req = k[C_NREQ];
+        c->last_n_rl = k[C_NRL];
+        st.candidates = k[C_CAND]; st.requested = k[C_NREQ]; st.direct = k[C_DIRECT]; st.linked = k[C_LINKED];
+        st.hits = k[C_HITS]; st.misses = k[C_MISSES]; st.evictions = k[C_EVICT]; st.missing = k[C_NMISSING];
+        st.copies = n_copy; st.render_pages = k[C_NRL]; st.pool_pages_used = k[C_POOLUSED];
+        splat(c, c->d_rlist, k[C_NRL], c->d_pool, n_render, n_views, image, &st);
+        // outputs of the frame: request order and missing list
+        if (c->last_n_req)
+            HIPCHK(hipMemcpyAsync(c->h_keys, c->d_keys + c->n_pg, sizeof(uint64_t) * c->last_n_req,
+                                  hipMemcpyDeviceToHost, c->sr));
+        if (c->last_n_missing)
+            HIPCHK(hipMemcpyAsync(c->h_missing, c->d_missing, sizeof(int32_t) * 2 * c->last_n_missing,
+                                  hipMemcpyDeviceToHost, c->sr));
+        HIPCHK(hipStreamSynchronize(c->sr));
+        c->out_req.resize(c->last_n_req);
+        c->out_req_level.resize(c->last_n_req);
+        for (uint32_t i = 0; i < c->last_n_req; ++i) {
+            c->out_req[i] = (int32_t)(c->h_keys[i] & 0x3fffffffull);
+            c->out_req_level[i] = 0;
+        }
+        c->out_missing.assign(c->h_missing, c->h_missing + 2 * c->last_n_missing);
+        st.ms_visibility = ms(ev[0], ev[1]);
+        st.ms_pagetable = ms(ev[1], ev[2]);
+        st.ms_copy = ms(ev[2], ev[3]);
+        st.ms_preprocess = ms(ev[3], ev[4]);
+        st.ms_sort = ms(ev[4], ev[5]);
+        st.ms_blend = ms(ev[5], ev[6]);
+        st.ms_total = ms(ev[0], ev[6]);
+        c->frame++;
+    } catch (const HipError& h) {
+        return fail(c, h);
+    }
+    if (out) {
+        out->requests = c->out_req.data();
+        out->request_level = c->out_req_level.data();
+        out->n_requests = (uint32_t)c->out_req.size();
+        out->missing = c->out_missing.data();
+        out->n_missing = (uint32_t)(c->out_missing.size() / 2);
+        out->stats = st;
+    }
+    return VM3DGS_OK;
+}
+
+vm3dgs_status vm3dgs_render_full(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views, float* image,
+                                 vm3dgs_stats* stats) {
+    if (!c) return VM3DGS_E_INVALID_ARG;
+    if (c->poisoned) return VM3DGS_E_STATE;
+    if (!cams || !image || n_views == 0) return bad(c, "cams, image and n_views must be given");
+    if (n_views > c->opt.max_views) { c->err = "n_views exceeds max_views"; return VM3DGS_E_CAPACITY; }
+    if (!c->d_full) return bad(c, "vm3dgs_render_full needs VM3DGS_FLAG_FULL_SCENE_COPY at create");
+    vm3dgs_stats st{};
+    try {
+        for (uint32_t v = 0; v < n_views; ++v) to_camk(cams[v], c->h_cams[v]);
+        HIPCHK(hipEventRecord(c->ev[0], c->sr));
+        HIPCHK(hipMemcpyAsync(c->d_cams, c->h_cams, sizeof(CamK) * n_views, hipMemcpyHostToDevice, c->sr));
+        splat(c, c->d_rlist_full, (uint32_t)c->n_pg, c->d_full, (uint32_t)c->n_pg * (uint32_t)c->P, n_views, image, &st);
+        HIPCHK(hipStreamSynchronize(c->sr));
+        st.ms_preprocess = ms(c->ev[3], c->ev[4]);
+        st.ms_sort = ms(c->ev[4], c->ev[5]);
+        st.ms_blend = ms(c->ev[5], c->ev[6]);
+        st.ms_total = ms(c->ev[0], c->ev[6]);
+        st.render_pages = (uint32_t)c->n_pg;
+    } catch (const HipError& h) {
+        return fail(c, h);
+    }
+    if (stats) *stats = st;
+    return VM3DGS_OK;
+}
+
+vm3dgs_status vm3dgs_sync(vm3dgs* c) {
+    if (!c) return VM3DGS_E_INVALID_ARG;
+    if (c->poisoned) return VM3DGS_E_STATE;
+    try {
+        HIPCHK(hipStreamSynchronize(c->sr));
+        HIPCHK(hipStreamSynchronize(c->sc));
+    } catch (const HipError& h) {
+        return fail(c, h);
+    }
+    return VM3DGS_OK;
+}
+
+const char* vm3dgs_last_error(const vm3dgs* c) { return c ? c->err.c_str() : "context is NULL"; }
+
+void vm3dgs_destroy(vm3dgs* c) {
+    if (!c) return;
+    free_all(c);
+    delete c;
+}
+
+struct vm3dgs_pages {
+    PagedScene ps;
+    std::vector<uint8_t> store;
+};
+
+vm3dgs_status vm3dgs_pages_build(const vm3dgs_scene* scene, uint32_t page_size, uint32_t lod_levels,
+                                 const vm3dgs_options* opt, vm3dgs_pages** out) {
+    g_create_error.clear();
+    if (!out) { g_create_error = "out is NULL"; return VM3DGS_E_INVALID_ARG; }
+    *out = nullptr;
+    vm3dgs_options o;
+    if (opt) o = *opt; else vm3dgs_options_default(&o);
+    if (!scene || scene->n == 0 || !scene->means || !scene->scales || !scene->quats || !scene->opacity || !scene->sh) {
+        g_create_error = "scene is NULL or empty";
+        return VM3DGS_E_INVALID_ARG;
+    }
+    if (page_size == 0 || lod_levels < 1 || lod_levels > 3 || o.attr_format > 1 || !(o.proxy_cell_m > 0.0f)) {
+        g_create_error = "page_size, lod_levels, attr_format or proxy_cell_m out of range";
+        return VM3DGS_E_INVALID_ARG;
+    }
+    for (uint32_t l = 1; l < lod_levels; ++l)
+        if ((page_size >> (3 * l)) == 0 || ((page_size >> (3 * l)) << (3 * l)) != page_size) {
+            g_create_error = "page_size must be divisible by 8^(lod_levels-1)";
+            return VM3DGS_E_INVALID_ARG;
+        }
+    vm3dgs_pages* p = new (std::nothrow) vm3dgs_pages();
+    if (!p) return VM3DGS_E_HOST_OOM;
+    try {
+        std::string e = build_paged_scene(*scene, (int)page_size, (int)lod_levels, (int)o.attr_format,
+                                          (double)o.proxy_cell_m, (double)o.link_sigma, p->ps);
+        if (!e.empty()) { g_create_error = e; delete p; return VM3DGS_E_INVALID_ARG; }
+        p->store.resize((size_t)p->ps.store_bytes);
+        encode_store(p->ps, p->store.data());
+    } catch (const std::bad_alloc&) {
+        delete p;
+        g_create_error = "host allocation failed";
+        return VM3DGS_E_HOST_OOM;
+    }
+    *out = p;
+    return VM3DGS_OK;
+}
+
+int64_t vm3dgs_pages_get(const vm3dgs_pages* p, const char* name, void* dst, int64_t cap) {
+    if (!p || !name) return -1;
+    const std::string n(name);
+    const PagedScene& ps = p->ps;
+    auto host = [&](const void* src, int64_t bytes) -> int64_t {
+        if (dst && cap >= bytes && bytes > 0) memcpy(dst, src, (size_t)bytes);
+        return bytes;
+    };
+    if (n == "info") {
+        int64_t v[8] = {ps.n_pg, ps.P, ps.L, ps.bytes_g, ps.nc(), (int64_t)ps.link_dst.size(), ps.store_bytes, 0};
+        return host(v, sizeof v);
+    }
+    if (n == "perm") return host(ps.perm.data(), 8 * (int64_t)ps.perm.size());
+    if (n == "spheres") return host(ps.spheres.data(), 4 * (int64_t)ps.spheres.size());
+    if (n == "cell_box") {
+        const int64_t nc = ps.nc();
+        if (dst && cap >= 24 * nc)
+            for (int64_t i = 0; i < nc; ++i) {
+                float* o = (float*)dst + 6 * i;
+                for (int a = 0; a < 3; ++a) { o[a] = ps.cell_lo[(size_t)i * 4 + a]; o[3 + a] = ps.cell_hi[(size_t)i * 4 + a]; }
+            }
+        return 24 * nc;
+    }
+    if (n == "cell_page") return host(ps.cell_page.data(), 4 * ps.nc());
+    if (n == "cell_start") return host(ps.cell_start.data(), 4 * (int64_t)ps.cell_start.size());
+    if (n == "link_start") return host(ps.link_start.data(), 4 * (int64_t)ps.link_start.size());
+    if (n == "link_dst") return host(ps.link_dst.data(), 4 * (int64_t)ps.link_dst.size());
+    if (n == "rec0") return host(ps.rec[0].data(), 4 * (int64_t)ps.rec[0].size());
+    if (n == "rec1" && ps.L > 1) return host(ps.rec[1].data(), 4 * (int64_t)ps.rec[1].size());
+    if (n == "rec2" && ps.L > 2) return host(ps.rec[2].data(), 4 * (int64_t)ps.rec[2].size());
+    if (n == "store") return host(p->store.data(), (int64_t)p->store.size());
+    return -1;
+}
+
+void vm3dgs_pages_destroy(vm3dgs_pages* p) { delete p; }
+
+int64_t vm3dgs_debug_get(vm3dgs* c, const char* name, void* dst, int64_t cap) {
+    if (!c || !name) return -1;
+    const std::string n(name);
+    auto host = [&](const void* src, int64_t bytes) -> int64_t {
+        if (dst && cap >= bytes && bytes > 0) memcpy(dst, src, (size_t)bytes);
+        return bytes;
+    };
+    auto dev = [&](const void* src, int64_t bytes) -> int64_t {
+        if (dst && cap >= bytes && bytes > 0) {
+            if (hipStreamSynchronize(c->sr) != hipSuccess) return -1;
+            if (hipMemcpy(dst, src, (size_t)bytes, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+        }
+        return bytes;
+    };
+    const PagedScene& ps = c->ps;
+    const int64_t V = c->last_views ? c->last_views : 1;
+    if (n == "info") {
+        int64_t v[16] = {ps.n_pg, ps.P, ps.L, ps.bytes_g, ps.nc(), (int64_t)ps.link_dst.size(), c->S, c->frame,
+                         c->TX, c->TY, (int64_t)c->cap_pairs, ps.store_bytes, c->last_n_render, c->last_n_pairs,
+                         c->last_views, c->last_n_rl};
+        return host(v, sizeof v);
+    }
+    if (n == "perm") return host(ps.perm.data(), 8 * (int64_t)ps.perm.size());
+    if (n == "spheres") return host(ps.spheres.data(), 4 * (int64_t)ps.spheres.size());
+    if (n == "cell_box") {
+        const int64_t nc = ps.nc();
+        if (dst && cap >= 24 * nc)
+            for (int64_t i = 0; i < nc; ++i) {
+                float* o = (float*)dst + 6 * i;
+                for (int a = 0; a < 3; ++a) { o[a] = ps.cell_lo[(size_t)i * 4 + a]; o[3 + a] = ps.cell_hi[(size_t)i * 4 + a]; }
+            }
+        return 24 * nc;
+    }
+    if (n == "cell_page") return host(ps.cell_page.data(), 4 * ps.nc());
+    if (n == "cell_start") return host(ps.cell_start.data(), 4 * (int64_t)ps.cell_start.size());
+    if (n == "link_start") return host(ps.link_start.data(), 4 * (int64_t)ps.link_start.size());
+    if (n == "link_dst") return host(ps.link_dst.data(), 4 * (int64_t)ps.link_dst.size());
+    if (n == "host_page") return host(ps.rec[0].data(), 4 * (int64_t)ps.rec[0].size());
+    if (n == "cand") return dev(c->d_cand, V * c->n_pg);
+    if (n == "idbuf") return dev(c->d_idbuf, 8 * V * c->opt.idbuf_w * c->opt.idbuf_h);
+    if (n == "req_direct") return dev(c->d_rd, 4 * (int64_t)c->n_pg);
+    if (n == "req_link") return dev(c->d_rl, 4 * (int64_t)c->n_pg);
+    if (n == "page_level") return dev(c->d_plevel, c->n_pg);
+    if (n == "req_page") return host(c->out_req.data(), 4 * (int64_t)c->out_req.size());
+    if (n == "slot_level") return dev(c->d_slot_level, c->S);
+    if (n == "last_used") return dev(c->d_last_used, 4 * (int64_t)c->S);
+    if (n == "sub_vpage") return dev(c->d_sub_vpage, 4 * (int64_t)c->S * SUBS);
+    if (n == "sub_last_used") return dev(c->d_sub_lu, 4 * (int64_t)c->S * SUBS);
+    if (n == "v2p") return dev(c->d_v2p, 4 * (int64_t)c->n_pg * c->L);
+    if (n == "copies") return dev(c->d_copies, 24 * (int64_t)c->last_n_copy);
+    if (n == "copy_id") return dev(c->d_copy_id, 16 * (int64_t)c->last_n_copy);
+    if (n == "missing") return host(c->out_missing.data(), 4 * (int64_t)c->out_missing.size());
+    if (n == "render_list") return dev(c->d_rlist, 16 * (int64_t)c->last_n_rl);
+    const int64_t nt = (int64_t)c->last_n_render * c->last_views;
+    if (n == "pp_float") {
+        const int64_t bytes = 40 * nt;
+        if (dst && cap >= bytes) {
+            std::vector<float2> xy((size_t)nt);
+            std::vector<float4> co((size_t)nt), rgb((size_t)nt);
+            std::vector<uint32_t> dep((size_t)nt);
+            hipStreamSynchronize(c->sr);
+            hipMemcpy(xy.data(), c->d_xy, 8 * nt, hipMemcpyDeviceToHost);
+            hipMemcpy(co.data(), c->d_conic, 16 * nt, hipMemcpyDeviceToHost);
+            hipMemcpy(rgb.data(), c->d_rgb, 16 * nt, hipMemcpyDeviceToHost);
+            hipMemcpy(dep.data(), c->d_depth, 4 * nt, hipMemcpyDeviceToHost);
+            for (int64_t i = 0; i < nt; ++i) {
+                float* f = (float*)dst + 10 * i;
+                float d;
+                memcpy(&d, &dep[(size_t)i], 4);
+                f[0] = xy[(size_t)i].x; f[1] = xy[(size_t)i].y; f[2] = d;
+                f[3] = co[(size_t)i].x; f[4] = co[(size_t)i].y; f[5] = co[(size_t)i].z; f[6] = co[(size_t)i].w;
+                f[7] = rgb[(size_t)i].x; f[8] = rgb[(size_t)i].y; f[9] = rgb[(size_t)i].z;
+            }
+        }
+        return bytes;
+    }
+    if (n == "pp_int") {
+        const int64_t bytes = 24 * nt;
+        if (dst && cap >= bytes) {
+            std::vector<uint2> rc((size_t)nt);
+            std::vector<uint32_t> dep((size_t)nt), til((size_t)nt);
+            hipStreamSynchronize(c->sr);
+            hipMemcpy(rc.data(), c->d_rect, 8 * nt, hipMemcpyDeviceToHost);
+            hipMemcpy(dep.data(), c->d_depth, 4 * nt, hipMemcpyDeviceToHost);
+            hipMemcpy(til.data(), c->d_tiles, 4 * nt, hipMemcpyDeviceToHost);
+            for (int64_t i = 0; i < nt; ++i) {
+                int32_t* q = (int32_t*)dst + 6 * i;
+                q[0] = dep[(size_t)i] == 0xffffffffu ? 1 : 0;
+                q[1] = (int32_t)(rc[(size_t)i].x & 0xffffu); q[2] = (int32_t)(rc[(size_t)i].x >> 16);
+                q[3] = (int32_t)(rc[(size_t)i].y & 0xffffu); q[4] = (int32_t)(rc[(size_t)i].y >> 16);
+                q[5] = (int32_t)til[(size_t)i];
+            }
+        }
+        return bytes;
+    }
+    if (n == "keys") return dev(c->d_pkey[c->last_pbuf], 4 * (int64_t)c->last_n_pairs);
+    if (n == "vals") return dev(c->d_pval[c->last_pbuf], 4 * (int64_t)c->last_n_pairs);
+    if (n == "ranges") return dev(c->d_ranges, 8 * (int64_t)c->TX * c->TY * V);
+    if (n == "depth_order") return dev(c->d_dval[c->last_dbuf], 4 * nt);
+    return -1;
+}
+
+}  // extern "C"

@@ -1,0 +1,356 @@
+// k_splat.hip -- splatting of the resident Gaussians (Sec. 4.2: the 3DGS math
+// of Kerbl et al.) on gfx950.
+//
+//  k_preprocess  one thread per (view, render Gaussian): coalesced SoA loads
+//                from the pool block, EWA projection (0.3 px^2 dilation),
+//                conic, 3-sigma radius, 16x16 tile rectangle, degree-3 SH
+//                colour, view depth.  Padding (opacity 0) and Gaussians in
+//                front of the near plane are culled.
+//  k_emit        pairs in depth order: a wave spreads the tile rectangles of
+//                its 64 Gaussians over its lanes (prefix sums of the counts)
+//                and writes (tile, Gaussian) pairs coalesced.
+//  k_ranges      [start, end) of every tile in the tile-sorted pairs.
+//  k_blend       one 256-thread workgroup per 16x16 tile; Gaussians staged
+//                in LDS in batches of 256; per pixel front-to-back blending
+//                until transmittance would fall below 1e-4; the workgroup
+//                leaves when every pixel is done.
+#include "kcommon.h"
+#include "vm3dgs_impl.h"
+
+namespace vmk {
+
+using vm::CamK;
+using vm::RenderEntry;
+
+__device__ __forceinline__ void load_gauss(const uint8_t* __restrict__ blk, uint32_t C, uint32_t i, int fmt,
+                                           Gauss& g) {
+    if (fmt == 0) {
+        const float* f = (const float*)blk;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g.m[a] = f[(size_t)a * C + i];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g.s[a] = f[(size_t)(3 + a) * C + i];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) g.q[a] = f[(size_t)(6 + a) * C + i];
+        g.o = f[(size_t)10 * C + i];
+#pragma unroll
+        for (int a = 0; a < 48; ++a) g.sh[a] = f[(size_t)(11 + a) * C + i];
+    } else {
+        const float* f = (const float*)blk;
+        const uint32_t* u = (const uint32_t*)blk;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g.m[a] = f[(size_t)a * C + i];
+        const uint32_t p0 = u[(size_t)3 * C + i], p1 = u[(size_t)4 * C + i];
+        const uint32_t p2 = u[(size_t)5 * C + i], p3 = u[(size_t)6 * C + i];
+        g.s[0] = f16_lo(p0); g.s[1] = f16_hi(p0); g.s[2] = f16_lo(p1); g.q[0] = f16_hi(p1);
+        g.q[1] = f16_lo(p2); g.q[2] = f16_hi(p2); g.q[3] = f16_lo(p3); g.o = f16_hi(p3);
+#pragma unroll
+        for (int m = 0; m < 24; ++m) {
+            const uint32_t w = u[(size_t)(7 + m) * C + i];
+            g.sh[2 * m] = bf16_lo(w);
+            g.sh[2 * m + 1] = bf16_hi(w);
+        }
+    }
+}
+
+struct PreArgs {
+    const RenderEntry* rl; int n_rl;
+    const uint8_t* pool; int fmt; int bytes_g;
+    const CamK* cams;
+    int W, H, TX, TY;
+    uint32_t n_render; uint64_t n_total;
+    float2* xy; float4* conic; float4* rgb; uint32_t* depth; uint2* rect; uint32_t* tiles;
+    uint32_t* dkey; uint32_t* dval;
+};
+
+__global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
+    const uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= a.n_total) return;
+    const uint32_t v = (uint32_t)(f / a.n_render);
+    const uint32_t gi = (uint32_t)(f - (uint64_t)v * a.n_render);
+    // render entry holding gi: last entry with base <= gi
+    int lo = 0, hi = a.n_rl - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.rl[mid].base <= gi) lo = mid; else hi = mid - 1;
+    }
+    const RenderEntry e = a.rl[lo];
+    const uint32_t i = gi - e.base;
+    Gauss g;
+    load_gauss(a.pool + (size_t)e.pool_off * a.bytes_g, e.count, i, a.fmt, g);
+    const CamK& c = a.cams[v];
+
+    bool ok = g.o != 0.0f;  // padding
+    const float3 t = view_xform(c.V, g.m[0], g.m[1], g.m[2]);
+    ok = ok && (t.z > c.znear);
+    float u = 0.f, vv = 0.f, ca = 0.f, cb = 0.f, cc2 = 0.f;
+    int ix0 = 0, iy0 = 0, ix1 = 0, iy1 = 0;
+    float col[3] = {0.f, 0.f, 0.f};
+    if (ok) {
+        const float w = g.q[0], x = g.q[1], y = g.q[2], z = g.q[3];
+        float R[3][3];
+        R[0][0] = 1.0f - 2.0f * (y * y + z * z);
+        R[0][1] = 2.0f * (x * y - w * z);
+        R[0][2] = 2.0f * (x * z + w * y);
+        R[1][0] = 2.0f * (x * y + w * z);
+        R[1][1] = 1.0f - 2.0f * (x * x + z * z);
+        R[1][2] = 2.0f * (y * z - w * x);
+        R[2][0] = 2.0f * (x * z - w * y);
+        R[2][1] = 2.0f * (y * z + w * x);
+        R[2][2] = 1.0f - 2.0f * (x * x + y * y);
+        float M[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) M[r][k] = R[r][k] * g.s[k];
+        float S[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) S[r][k] = (M[r][0] * M[k][0] + M[r][1] * M[k][1]) + M[r][2] * M[k][2];
+        const float limx = 1.3f * ((0.5f * (float)a.W) / c.fx);
+        const float limy = 1.3f * ((0.5f * (float)a.H) / c.fy);
+        const float cxz = fminf(limx, fmaxf(-limx, t.x / t.z)) * t.z;
+        const float cyz = fminf(limy, fmaxf(-limy, t.y / t.z)) * t.z;
+        const float tz2 = t.z * t.z;
+        const float j00 = c.fx / t.z, j02 = -((c.fx * cxz) / tz2);
+        const float j11 = c.fy / t.z, j12 = -((c.fy * cyz) / tz2);
+        float T0[3], T1[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            T0[k] = j00 * c.V[k] + j02 * c.V[8 + k];
+            T1[k] = j11 * c.V[4 + k] + j12 * c.V[8 + k];
+        }
+        float U0[3], U1[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            U0[k] = (T0[0] * S[0][k] + T0[1] * S[1][k]) + T0[2] * S[2][k];
+            U1[k] = (T1[0] * S[0][k] + T1[1] * S[1][k]) + T1[2] * S[2][k];
+        }
+        const float A = ((U0[0] * T0[0] + U0[1] * T0[1]) + U0[2] * T0[2]) + 0.3f;
+        const float B = (U0[0] * T1[0] + U0[1] * T1[1]) + U0[2] * T1[2];
+        const float Cc = ((U1[0] * T1[0] + U1[1] * T1[1]) + U1[2] * T1[2]) + 0.3f;
+        const float det = A * Cc - B * B;
+        ok = det > 0.0f;
+        if (ok) {
+            const float inv = 1.0f / det;
+            const float mid = 0.5f * (A + Cc);
+            const float lam = mid + sqrtf(fmaxf(0.1f, mid * mid - det));
+            const float rad = ceilf(3.0f * sqrtf(lam));
+            u = (c.fx * t.x) / t.z + (c.cx - 0.5f);
+            vv = (c.fy * t.y) / t.z + (c.cy - 0.5f);
+            const float x0 = fminf(fmaxf(floorf((u - rad) / 16.0f), 0.0f), (float)a.TX);
+            const float x1 = fminf(fmaxf(floorf(((u + rad) + 15.0f) / 16.0f), 0.0f), (float)a.TX);
+            const float y0 = fminf(fmaxf(floorf((vv - rad) / 16.0f), 0.0f), (float)a.TY);
+            const float y1 = fminf(fmaxf(floorf(((vv + rad) + 15.0f) / 16.0f), 0.0f), (float)a.TY);
+            ix0 = (int)x0; ix1 = (int)x1; iy0 = (int)y0; iy1 = (int)y1;
+            ok = (ix1 - ix0) * (iy1 - iy0) != 0;
+            ca = Cc * inv; cb = -B * inv; cc2 = A * inv;
+        }
+        if (ok) {
+            const float d0 = g.m[0] - c.pos[0], d1 = g.m[1] - c.pos[1], d2 = g.m[2] - c.pos[2];
+            const float len = sqrtf((d0 * d0 + d1 * d1) + d2 * d2);
+            const float X = d0 / len, Y = d1 / len, Z = d2 / len;
+            const float xx = X * X, yy = Y * Y, zz = Z * Z;
+            const float xy_ = X * Y, yz = Y * Z, xz = X * Z;
+            float b[16];
+            b[0] = ShConst::k0;
+            b[1] = ShConst::k1 * Y;
+            b[2] = ShConst::k2 * Z;
+            b[3] = ShConst::k3 * X;
+            b[4] = ShConst::k4 * xy_;
+            b[5] = ShConst::k5 * yz;
+            b[6] = ShConst::k6 * ((2.0f * zz - xx) - yy);
+            b[7] = ShConst::k7 * xz;
+            b[8] = ShConst::k8 * (xx - yy);
+            b[9] = (ShConst::k9 * Y) * (3.0f * xx - yy);
+            b[10] = (ShConst::k10 * xy_) * Z;
+            b[11] = (ShConst::k11 * Y) * ((4.0f * zz - xx) - yy);
+            b[12] = (ShConst::k12 * Z) * ((2.0f * zz - 3.0f * xx) - 3.0f * yy);
+            b[13] = (ShConst::k13 * X) * ((4.0f * zz - xx) - yy);
+            b[14] = (ShConst::k14 * Z) * (xx - yy);
+            b[15] = (ShConst::k15 * X) * (xx - 3.0f * yy);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float acc = b[0] * g.sh[ch];
+#pragma unroll
+                for (int k = 1; k < 16; ++k) acc = acc + b[k] * g.sh[k * 3 + ch];
+                acc = acc + 0.5f;
+                col[ch] = acc > 0.0f ? acc : 0.0f;
+            }
+        }
+    }
+    a.xy[f] = make_float2(u, vv);
+    a.conic[f] = make_float4(ca, cb, cc2, ok ? g.o : 0.0f);
+    a.rgb[f] = make_float4(col[0], col[1], col[2], 0.0f);
+    a.depth[f] = ok ? __float_as_uint(t.z) : NONE32;
+    a.rect[f] = ok ? make_uint2((uint32_t)ix0 | ((uint32_t)iy0 << 16), (uint32_t)ix1 | ((uint32_t)iy1 << 16))
+                   : make_uint2(0u, 0u);
+    a.tiles[f] = ok ? (uint32_t)((ix1 - ix0) * (iy1 - iy0)) : 0u;
+    a.dkey[f] = ok ? __float_as_uint(t.z) : NONE32;
+    a.dval[f] = (uint32_t)f;
+}
+
+// pairs of 64 depth-ordered Gaussians per wave, balanced over the lanes
+__global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order, const uint32_t* __restrict__ offs,
+                                              const uint2* __restrict__ rect, uint32_t n_total, uint32_t n_render,
+                                              int TX, int TY, uint32_t* __restrict__ pkey,
+                                              uint32_t* __restrict__ pval, uint32_t cap) {
+    __shared__ uint32_t s_off[4][WAVE];
+    __shared__ uint32_t s_f[4][WAVE];
+    __shared__ uint2 s_rect[4][WAVE];
+    const int w = threadIdx.x / WAVE, lane = __lane_id();
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    uint32_t f = 0, off = 0, cnt = 0;
+    uint2 r = make_uint2(0u, 0u);
+    if (i < n_total) {
+        f = order[i];
+        off = offs[i];
+        r = rect[f];
+        const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu, y1 = r.y >> 16;
+        cnt = (x1 - x0) * (y1 - y0);
+    }
+    s_off[w][lane] = off;
+    s_f[w][lane] = f;
+    s_rect[w][lane] = r;
+    // pairs of this wave: [first, first + total)
+    const uint32_t first = __shfl(off, 0, WAVE);
+    const uint32_t last_end = off + cnt;
+    uint32_t total = 0;
+    {
+        // the last valid lane's end is the wave's end
+        uint32_t e = (i < n_total) ? last_end : 0u;
+#pragma unroll
+        for (int o = WAVE / 2; o > 0; o >>= 1) e = max(e, __shfl_xor(e, o, WAVE));
+        total = e > first ? e - first : 0u;
+    }
+    __syncthreads();
+    const uint32_t view_tiles = (uint32_t)(TX * TY);
+    for (uint32_t k = lane; k < total; k += WAVE) {
+        const uint32_t j = first + k;
+        // owning lane: last lane with s_off <= j (lanes with no tiles share offsets; take the last)
+        int lo = 0, hi = WAVE - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[w][mid] <= j && (blockIdx.x * 256 + w * WAVE + mid) < n_total) lo = mid; else hi = mid - 1;
+        }
+        // lanes with zero tiles share the next lane's offset: skip forward to one with tiles
+        const uint2 rr = s_rect[w][lo];
+        const uint32_t x0 = rr.x & 0xffffu, y0 = rr.x >> 16, x1 = rr.y & 0xffffu;
+        const uint32_t wd = x1 - x0;
+        const uint32_t q = j - s_off[w][lo];
+        const uint32_t tx = x0 + q % wd, ty = y0 + q / wd;
+        const uint32_t ff = s_f[w][lo];
+        const uint32_t view = ff / n_render;
+        if (j < cap) {
+            pkey[j] = view * view_tiles + ty * (uint32_t)TX + tx;
+            pval[j] = ff;
+        }
+    }
+}
+
+__global__ void k_ranges(const uint32_t* __restrict__ key, uint32_t n, uint2* __restrict__ ranges) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t t = key[i];
+    if (i == 0 || key[i - 1] != t) ranges[t].x = i;
+    if (i == n - 1 || key[i + 1] != t) ranges[t].y = i + 1;
+}
+
+constexpr int BL_NT = TILE * TILE;
+
+__global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ ranges, const uint32_t* __restrict__ pval,
+                                                 const float2* __restrict__ xy, const float4* __restrict__ conic,
+                                                 const float4* __restrict__ rgb, int W, int H, int TX, int TY,
+                                                 float* __restrict__ image) {
+    __shared__ float2 s_xy[BL_NT];
+    __shared__ float4 s_co[BL_NT];
+    __shared__ float4 s_rgb[BL_NT];
+    const uint32_t tile = blockIdx.x;
+    const uint32_t per_view = (uint32_t)(TX * TY);
+    const uint32_t view = tile / per_view;
+    const uint32_t t = tile - view * per_view;
+    const int tx = (int)(t % (uint32_t)TX), ty = (int)(t / (uint32_t)TX);
+    const int px = tx * TILE + (int)(threadIdx.x % TILE);
+    const int py = ty * TILE + (int)(threadIdx.x / TILE);
+    const bool inside = px < W && py < H;
+    bool done = !inside;
+    const uint2 rg = ranges[tile];
+    const float fpx = (float)px, fpy = (float)py;
+    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+    for (uint32_t base = rg.x; base < rg.y; base += BL_NT) {
+        if (__syncthreads_count(done ? 1 : 0) == BL_NT) break;
+        const uint32_t j = base + threadIdx.x;
+        if (j < rg.y) {
+            const uint32_t f = pval[j];
+            s_xy[threadIdx.x] = xy[f];
+            s_co[threadIdx.x] = conic[f];
+            s_rgb[threadIdx.x] = rgb[f];
+        }
+        __syncthreads();
+        const int cnt = (int)min((uint32_t)BL_NT, rg.y - base);
+        for (int k = 0; k < cnt && !done; ++k) {
+            const float2 p = s_xy[k];
+            const float4 co = s_co[k];
+            const float dx = p.x - fpx, dy = p.y - fpy;
+            const float q = fmaf(co.x * dx, dx, (co.z * dy) * dy);
+            const float power = fmaf(-0.5f, q, -((co.y * dx) * dy));
+            // exp(-5.55) < 1/255 and opacity <= 1: such terms are skipped by the
+            // alpha test anyway, so their exp is not evaluated
+            if (power > 0.0f || power < -5.55f) continue;
+            const float alpha = fminf(0.99f, co.w * vm_exp(power));
+            if (alpha < 1.0f / 255.0f) continue;
+            const float Tn = T * (1.0f - alpha);
+            if (Tn < 0.0001f) { done = true; break; }
+            const float wgt = alpha * T;
+            const float4 c = s_rgb[k];
+            C0 = fmaf(c.x, wgt, C0);
+            C1 = fmaf(c.y, wgt, C1);
+            C2 = fmaf(c.z, wgt, C2);
+            T = Tn;
+        }
+    }
+    if (inside) {
+        float* o = image + (((size_t)view * H + py) * W + px) * 3;
+        o[0] = C0; o[1] = C1; o[2] = C2;
+    }
+}
+
+}  // namespace vmk
+
+namespace vm {
+using namespace vmk;
+
+static unsigned nblk(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+void launch_preprocess(hipStream_t st, const SplatArgs& s) {
+    PreArgs a;
+    a.rl = s.rl; a.n_rl = s.n_rl; a.pool = s.pool; a.fmt = s.fmt; a.bytes_g = s.fmt == 1 ? 124 : 236;
+    a.cams = s.cams; a.W = s.W; a.H = s.H; a.TX = s.TX; a.TY = s.TY;
+    a.n_render = s.n_render; a.n_total = (uint64_t)s.n_render * s.n_views;
+    a.xy = s.xy; a.conic = s.conic; a.rgb = s.rgb; a.depth = s.depth; a.rect = s.rect; a.tiles = s.tiles;
+    a.dkey = s.dkey; a.dval = s.dval;
+    if (a.n_total == 0 || s.n_rl == 0) return;
+    hipLaunchKernelGGL(k_preprocess, dim3(nblk(a.n_total, 256)), dim3(256), 0, st, a);
+}
+
+void launch_emit(hipStream_t st, const uint32_t* order, const uint32_t* offsets, const uint2* rect,
+                 uint32_t n_total, uint32_t n_render, int TX, int TY, uint32_t* pkey, uint32_t* pval, uint32_t cap) {
+    if (n_total == 0) return;
+    hipLaunchKernelGGL(k_emit, dim3(nblk(n_total, 256)), dim3(256), 0, st, order, offsets, rect, n_total, n_render, TX,
+                       TY, pkey, pval, cap);
+}
+
+void launch_ranges(hipStream_t st, const uint32_t* pkey, uint32_t n_pairs, uint2* ranges, uint32_t n_tiles) {
+    launch_fill_u64(st, (unsigned long long*)ranges, n_tiles, 0ull);
+    if (n_pairs)
+        hipLaunchKernelGGL(k_ranges, dim3(nblk(n_pairs, 256)), dim3(256), 0, st, pkey, n_pairs, ranges);
+}
+
+void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* pval, const float2* xy, const float4* conic,
+                  const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image) {
+    const uint32_t n_tiles = (uint32_t)(TX * TY * n_views);
+    hipLaunchKernelGGL(k_blend, dim3(n_tiles), dim3(BL_NT), 0, st, ranges, pval, xy, conic, rgb, W, H, TX, TY, image);
+}
+
+}  // namespace vm

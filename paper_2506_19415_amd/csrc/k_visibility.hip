@@ -1,0 +1,263 @@
+// k_visibility.hip -- page determination of Sec. 4.1 on gfx950.
+//
+//  k_frustum       page bounding sphere vs near plane and the four side planes
+//  k_rays          per ID-buffer pixel: reciprocal world direction of the
+//                  ray through the pixel centre (view depth = ray parameter)
+//  k_proxy_raster  the proxy boxes of candidate pages, rasterised at pixel
+//                  centres (slab test); 64-bit atomicMin of
+//                  (depth bits << 32 | page + 1): nearest wins, independent
+//                  of order.  Work is balanced inside a block by a prefix sum
+//                  of the boxes' pixel rectangles.
+//  k_reduce        per pixel: nearest depth per page (Sec. 5.1.1 reduction)
+//  k_links         a directly seen page pushes its depth to its linked pages
+//  k_requests      LOD level from the projected page radius, request keys
+//                  (class, depth, page)
+#include "kcommon.h"
+#include "vm3dgs_impl.h"
+
+namespace vmk {
+
+using vm::CamK;
+
+__global__ void k_frustum(const float4* __restrict__ sph, int n_pg, const CamK* __restrict__ cams, int n_views,
+                          int W, int H, uint8_t* __restrict__ cand, uint32_t* __restrict__ counters) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_pg * n_views) return;
+    const int v = (int)(i / n_pg);
+    const int p = (int)(i - (int64_t)v * n_pg);
+    const CamK& c = cams[v];
+    const float4 s = sph[p];
+    const float3 q = view_xform(c.V, s.x, s.y, s.z);
+    const float r = s.w;
+    bool in = q.z + r > c.znear;
+    const float tl = c.cx / c.fx, tr = ((float)W - c.cx) / c.fx;
+    const float tt = c.cy / c.fy, tb = ((float)H - c.cy) / c.fy;
+    const float kl = sqrtf(1.0f + tl * tl), kr = sqrtf(1.0f + tr * tr);
+    const float kt = sqrtf(1.0f + tt * tt), kb = sqrtf(1.0f + tb * tb);
+    in = in && (q.x + tl * q.z >= -(r * kl));
+    in = in && (-q.x + tr * q.z >= -(r * kr));
+    in = in && (q.y + tt * q.z >= -(r * kt));
+    in = in && (-q.y + tb * q.z >= -(r * kb));
+    cand[i] = in ? 1 : 0;
+    const uint64_t b = __ballot(in);
+    if (__lane_id() == 0 && b) atomicAdd(&counters[vm::C_CAND], (uint32_t)__popcll(b));
+}
+
+__global__ void k_rays(const CamK* __restrict__ cams, int n_views, int W, int H, int Wv, int Hv,
+                       float4* __restrict__ rays) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t npx = (int64_t)Wv * Hv;
+    if (i >= npx * n_views) return;
+    const int v = (int)(i / npx);
+    const int pix = (int)(i - v * npx);
+    const int px = pix % Wv, py = pix / Wv;
+    const CamK& c = cams[v];
+    const float sx = (float)W / (float)Wv, sy = (float)H / (float)Hv;
+    const float dcx = (((float)px + 0.5f) * sx - c.cx) / c.fx;
+    const float dcy = (((float)py + 0.5f) * sy - c.cy) / c.fy;
+    float inv[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float d = (c.V[a] * dcx + c.V[4 + a] * dcy) + c.V[8 + a];
+        if (d == 0.0f) d = 1e-30f;
+        inv[a] = 1.0f / d;
+    }
+    rays[i] = make_float4(inv[0], inv[1], inv[2], 0.0f);
+}
+
+// conservative inclusive pixel rectangle of a world box in the ID buffer
+__device__ bool box_rect(const CamK& c, int W, int H, int Wv, int Hv, const float* b, int4* r) {
+    float vmin[3] = {INFINITY, INFINITY, INFINITY}, vmax[3] = {-INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float3 p = view_xform(c.V, b[(k & 1) ? 3 : 0], b[(k & 2) ? 4 : 1], b[(k & 4) ? 5 : 2]);
+        vmin[0] = fminf(vmin[0], p.x); vmax[0] = fmaxf(vmax[0], p.x);
+        vmin[1] = fminf(vmin[1], p.y); vmax[1] = fmaxf(vmax[1], p.y);
+        vmin[2] = fminf(vmin[2], p.z); vmax[2] = fmaxf(vmax[2], p.z);
+    }
+    if (!(vmax[2] > c.znear * 0.5f)) return false;
+    const float z0 = fmaxf(vmin[2], c.znear * 0.5f), z1 = vmax[2];
+    const float xl = fminf(fminf(vmin[0] / z0, vmin[0] / z1), fminf(vmax[0] / z0, vmax[0] / z1));
+    const float xh = fmaxf(fmaxf(vmin[0] / z0, vmin[0] / z1), fmaxf(vmax[0] / z0, vmax[0] / z1));
+    const float yl = fminf(fminf(vmin[1] / z0, vmin[1] / z1), fminf(vmax[1] / z0, vmax[1] / z1));
+    const float yh = fmaxf(fmaxf(vmin[1] / z0, vmin[1] / z1), fmaxf(vmax[1] / z0, vmax[1] / z1));
+    const float sx = (float)W / (float)Wv, sy = (float)H / (float)Hv;
+    float fx0 = floorf((c.fx * xl + c.cx) / sx) - 1.0f, fx1 = floorf((c.fx * xh + c.cx) / sx) + 1.0f;
+    float fy0 = floorf((c.fy * yl + c.cy) / sy) - 1.0f, fy1 = floorf((c.fy * yh + c.cy) / sy) + 1.0f;
+    fx0 = fmaxf(fx0, 0.0f); fy0 = fmaxf(fy0, 0.0f);
+    fx1 = fminf(fx1, (float)(Wv - 1)); fy1 = fminf(fy1, (float)(Hv - 1));
+    if (!(fx0 <= fx1) || !(fy0 <= fy1)) return false;
+    *r = make_int4((int)fx0, (int)fy0, (int)fx1, (int)fy1);
+    return true;
+}
+
+constexpr int PR_NT = 256;
+
+__global__ __launch_bounds__(PR_NT) void k_proxy_raster(const float4* __restrict__ lo4, const float4* __restrict__ hi4,
+                                                       int64_t nc, const uint8_t* __restrict__ cand, int n_pg,
+                                                       const CamK* __restrict__ cams, int n_views, int W, int H,
+                                                       int Wv, int Hv, const float4* __restrict__ rays,
+                                                       unsigned long long* __restrict__ idbuf) {
+    __shared__ uint32_t s_end[PR_NT];   // inclusive prefix of rectangle areas
+    __shared__ int4 s_rect[PR_NT];
+    __shared__ float s_box[PR_NT][6];
+    __shared__ uint32_t s_page[PR_NT];
+    __shared__ uint32_t scan_sh[PR_NT / WAVE];
+    const int64_t c = (int64_t)blockIdx.x * PR_NT + threadIdx.x;
+    float b[6] = {0, 0, 0, 0, 0, 0};
+    uint32_t page = 0;
+    if (c < nc) {
+        const float4 l = lo4[c], h = hi4[c];
+        b[0] = l.x; b[1] = l.y; b[2] = l.z; b[3] = h.x; b[4] = h.y; b[5] = h.z;
+        page = __float_as_uint(l.w);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s_box[threadIdx.x][k] = b[k];
+    s_page[threadIdx.x] = page;
+    const int64_t npx = (int64_t)Wv * Hv;
+    for (int v = 0; v < n_views; ++v) {
+        const CamK& cam = cams[v];
+        uint32_t area = 0;
+        int4 r = make_int4(0, 0, -1, -1);
+        if (c < nc && cand[(int64_t)v * n_pg + page]) {
+            if (box_rect(cam, W, H, Wv, Hv, b, &r)) area = (uint32_t)((r.z - r.x + 1) * (r.w - r.y + 1));
+        }
+        uint32_t total;
+        const uint32_t ex = block_excl_scan<PR_NT>(area, scan_sh, &total);
+        s_end[threadIdx.x] = ex + area;
+        s_rect[threadIdx.x] = r;
+        __syncthreads();
+        const float o0 = cam.pos[0], o1 = cam.pos[1], o2 = cam.pos[2];
+        for (uint32_t i = threadIdx.x; i < total; i += PR_NT) {
+            int lo = 0, hi = PR_NT - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_end[mid] > i) hi = mid; else lo = mid + 1;
+            }
+            const int4 rr = s_rect[lo];
+            const uint32_t w = (uint32_t)(rr.z - rr.x + 1);
+            const uint32_t k = i - (s_end[lo] - w * (uint32_t)(rr.w - rr.y + 1));
+            const int px = rr.x + (int)(k % w), py = rr.y + (int)(k / w);
+            const float4 inv = rays[v * npx + (int64_t)py * Wv + px];
+            const float* bb = s_box[lo];
+            float ta = (bb[0] - o0) * inv.x, tb = (bb[3] - o0) * inv.x;
+            float t0 = fminf(ta, tb), t1 = fmaxf(ta, tb);
+            ta = (bb[1] - o1) * inv.y; tb = (bb[4] - o1) * inv.y;
+            t0 = fmaxf(t0, fminf(ta, tb)); t1 = fminf(t1, fmaxf(ta, tb));
+            ta = (bb[2] - o2) * inv.z; tb = (bb[5] - o2) * inv.z;
+            t0 = fmaxf(t0, fminf(ta, tb)); t1 = fminf(t1, fmaxf(ta, tb));
+            if (t0 <= t1 && t1 > cam.znear) {
+                const float d = fmaxf(t0, cam.znear);
+                const unsigned long long key =
+                    ((unsigned long long)__float_as_uint(d) << 32) | (unsigned long long)(s_page[lo] + 1u);
+                atomicMin(&idbuf[v * npx + (int64_t)py * Wv + px], key);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_reduce(const unsigned long long* __restrict__ idbuf, int64_t n, uint32_t* __restrict__ req_direct) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const unsigned long long k = idbuf[i];
+    if (k == NONE64) return;
+    const uint32_t page = (uint32_t)(k & 0xffffffffull) - 1u;
+    atomicMin(&req_direct[page], (uint32_t)(k >> 32));
+}
+
+__global__ void k_links(const uint32_t* __restrict__ req_direct, const int32_t* __restrict__ ls,
+                        const int32_t* __restrict__ ld, int n_pg, uint32_t* __restrict__ req_link) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_pg) return;
+    const uint32_t d = req_direct[q];
+    if (d == NONE32) return;
+    for (int e = ls[q]; e < ls[q + 1]; ++e) atomicMin(&req_link[ld[e]], d);
+}
+
+__global__ void k_requests(const uint32_t* __restrict__ rd, const uint32_t* __restrict__ rl,
+                           const float4* __restrict__ sph, int n_pg, int L, float tau, float fy,
+                           int8_t* __restrict__ page_level, uint64_t* __restrict__ keys,
+                           uint32_t* __restrict__ counters) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    bool req = false, direct = false;
+    uint64_t key = 0;
+    if (p < n_pg) {
+        const uint32_t a = rd[p], b = rl[p];
+        const uint32_t d = a < b ? a : b;
+        int8_t lvl = -1;
+        if (d != NONE32) {
+            req = true;
+            direct = a != NONE32;
+            int l = 0;
+            if (L > 1) {
+                const float rpx = (fy * sph[p].w) / __uint_as_float(d);
+                float thr = tau;
+                while (l < L - 1 && !(rpx > thr)) { ++l; thr = thr * 0.5f; }
+            }
+            lvl = (int8_t)l;
+            key = ((uint64_t)(direct ? 0u : 1u) << 61) | ((uint64_t)d << 30) | (uint64_t)p;
+        }
+        page_level[p] = lvl;
+    }
+    // wave-aggregated compaction; order is restored by the sort of the keys
+    const uint64_t m = __ballot(req);
+    const uint64_t md = __ballot(direct);
+    uint32_t base = 0;
+    if (__lane_id() == 0 && m) {
+        base = atomicAdd(&counters[vm::C_NREQ], (uint32_t)__popcll(m));
+        atomicAdd(&counters[vm::C_DIRECT], (uint32_t)__popcll(md));
+        atomicAdd(&counters[vm::C_LINKED], (uint32_t)(__popcll(m) - __popcll(md)));
+    }
+    base = __shfl(base, 0, WAVE);
+    if (req) keys[base + __popcll(m & lanemask_lt())] = key;
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace vmk
+
+namespace vm {
+using namespace vmk;
+
+static unsigned nblk(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v) {
+    if (n) hipLaunchKernelGGL(k_fill_u32, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v);
+}
+
+void launch_fill_u64(hipStream_t st, unsigned long long* p, uint64_t n, unsigned long long v) {
+    if (n) hipLaunchKernelGGL(k_fill_u64, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v);
+}
+
+void launch_visibility(hipStream_t st, const VisArgs& a) {
+    const int64_t npx = (int64_t)a.Wv * a.Hv;
+    launch_fill_u64(st, a.idbuf, npx * a.n_views, NONE64);
+    launch_fill_u32(st, a.req_direct, a.n_pg, NONE32);
+    launch_fill_u32(st, a.req_link, a.n_pg, NONE32);
+    hipLaunchKernelGGL(k_frustum, dim3(nblk((uint64_t)a.n_pg * a.n_views, 256)), dim3(256), 0, st, a.spheres, a.n_pg,
+                       a.cams, a.n_views, a.W, a.H, a.cand, a.counters);
+    hipLaunchKernelGGL(k_rays, dim3(nblk(npx * a.n_views, 256)), dim3(256), 0, st, a.cams, a.n_views, a.W, a.H, a.Wv,
+                       a.Hv, a.rays);
+    if (a.nc > 0)
+        hipLaunchKernelGGL(k_proxy_raster, dim3(nblk(a.nc, PR_NT)), dim3(PR_NT), 0, st, a.cell_lo, a.cell_hi, a.nc,
+                           a.cand, a.n_pg, a.cams, a.n_views, a.W, a.H, a.Wv, a.Hv, (const float4*)a.rays, a.idbuf);
+    hipLaunchKernelGGL(k_reduce, dim3(nblk(npx * a.n_views, 256)), dim3(256), 0, st,
+                       (const unsigned long long*)a.idbuf, npx * a.n_views, a.req_direct);
+    if (a.use_links)
+        hipLaunchKernelGGL(k_links, dim3(nblk(a.n_pg, 256)), dim3(256), 0, st, (const uint32_t*)a.req_direct,
+                           a.link_start, a.link_dst, a.n_pg, a.req_link);
+    hipLaunchKernelGGL(k_requests, dim3(nblk(a.n_pg, 256)), dim3(256), 0, st, (const uint32_t*)a.req_direct,
+                       (const uint32_t*)a.req_link, a.spheres, a.n_pg, a.L, a.tau, a.fy_max, a.page_level,
+                       a.req_keys, a.counters);
+}
+
+}  // namespace vm

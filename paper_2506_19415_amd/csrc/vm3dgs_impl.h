@@ -1,0 +1,116 @@
+// vm3dgs_impl.h -- internal declarations of the VM-3DGS library (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/vm3dgs.h"
+
+namespace vm {
+
+constexpr int REC = 59;   // floats per Gaussian record
+constexpr int SUBS = 64;  // sub-slots per physical page
+
+// ----------------------------------------------------------- create time
+struct PagedScene {
+    int64_t n_in = 0;
+    int P = 0, L = 1, n_pg = 0, fmt = 0, bytes_g = 236;
+    double lo[3] = {0, 0, 0};
+    std::vector<int64_t> perm;         // [n_pg*P] input index, -1 = padding
+    std::vector<float> rec[3];         // decoded records per level [n_pg*P_l][59]
+    std::vector<float> spheres;        // [n_pg][4]
+    std::vector<float> cell_lo, cell_hi;  // [nc][4]; lo.w = page id as float bits
+    std::vector<int32_t> cell_page, cell_start;  // [nc], [n_pg+1]
+    std::vector<int32_t> link_start, link_dst;   // [n_pg+1], [n_links]
+    int64_t level_base[3] = {0, 0, 0};  // byte offset of each level in the host store
+    int64_t store_bytes = 0;
+    int P_l(int l) const { return P >> (3 * l); }
+    int64_t nc() const { return (int64_t)cell_page.size(); }
+};
+
+// Builds everything of Sec. 3 for the library; returns "" or an error text.
+std::string build_paged_scene(const vm3dgs_scene& sc, int page_size, int lod_levels, int fmt, double cell_m,
+                              double link_sigma, PagedScene& out);
+// Writes the page-major SoA store of every level into dst (store_bytes).
+void encode_store(const PagedScene& ps, uint8_t* dst);
+
+// ----------------------------------------------------------- device sort/scan
+size_t scan_temp_words(uint64_t n);
+size_t radix_temp_words(uint64_t n);
+void scan_excl(hipStream_t st, const uint32_t* in, uint64_t n, uint32_t* out, uint32_t* total, uint32_t* temp);
+void scan_excl_gather(hipStream_t st, const uint32_t* a, const uint32_t* idx, uint64_t n, uint32_t* out,
+                      uint32_t* total, uint32_t* temp);
+int radix_sort_u32(hipStream_t st, uint32_t* keys[2], uint32_t* vals[2], uint32_t n, int begin_bit, int end_bit,
+                   uint32_t* temp);
+int radix_sort_u64(hipStream_t st, uint64_t* keys[2], uint32_t* vals[2], uint32_t n, int begin_bit, int end_bit,
+                   uint32_t* temp);
+
+// ----------------------------------------------------------- kernels' camera
+struct CamK {
+    float V[12];       // rows of the world->camera transform
+    float pos[3];
+    float fx, fy, cx, cy, znear;
+};
+
+// Counters written by the page-table kernels and read back once per frame.
+enum Ctr {
+    C_NREQ = 0, C_DIRECT, C_LINKED, C_HITS, C_MISSES, C_EVICT, C_NCOPY, C_NMISSING, C_NRL, C_NRENDER,
+    C_CAND, C_POOLUSED, C_NCOUNTERS = 16
+};
+
+struct RenderEntry {   // one resident requested (sub-)page in render order
+    uint32_t pool_off;  // first Gaussian of the block in the pool (Gaussian units)
+    uint32_t count;     // Gaussians in the block
+    uint32_t base;      // first render index
+    uint32_t level;
+};
+
+struct CopyCmd {
+    int64_t host_off, pool_off, bytes;
+};
+
+// ----------------------------------------------------------- launchers
+struct VisArgs {
+    const float4* spheres; int n_pg;
+    const float4* cell_lo; const float4* cell_hi; int64_t nc;
+    const int32_t* link_start; const int32_t* link_dst; int use_links;
+    const CamK* cams; int n_views;
+    int W, H, Wv, Hv, L; float tau; float fy_max;
+    uint8_t* cand; float4* rays; unsigned long long* idbuf;
+    uint32_t* req_direct; uint32_t* req_link; int8_t* page_level;
+    uint64_t* req_keys; uint32_t* counters;
+};
+void launch_visibility(hipStream_t st, const VisArgs& a);
+
+struct PtArgs {
+    const uint64_t* req_keys; int n_pg, L, P, S, frame, budget, bytes_g;
+    const int8_t* page_level;
+    int8_t* slot_level; int32_t* last_used; int32_t* sub_vpage; int32_t* sub_last_used; int32_t* v2p;
+    uint8_t* req_sub; uint8_t* slot_req; uint32_t* miss;
+    CopyCmd* copies; int32_t* copy_id; int32_t* missing; uint32_t* counters;
+    const int64_t* level_base;  // device [3]
+    RenderEntry* rl;
+};
+void launch_pagetable(hipStream_t st, const PtArgs& a, int n_req_host_bound);
+
+struct SplatArgs {
+    const RenderEntry* rl; int n_rl;
+    const uint8_t* pool; int P; int fmt;
+    const CamK* cams; int n_views;
+    int W, H, TX, TY;
+    uint32_t n_render;  // per view
+    float2* xy; float4* conic; float4* rgb; uint32_t* depth; uint2* rect; uint32_t* tiles;
+    uint32_t* dkey; uint32_t* dval;
+};
+void launch_preprocess(hipStream_t st, const SplatArgs& a);
+void launch_emit(hipStream_t st, const uint32_t* order, const uint32_t* offsets, const uint2* rect, uint32_t n_total,
+                 uint32_t n_render, int TX, int TY, uint32_t* pkey, uint32_t* pval, uint32_t cap);
+void launch_ranges(hipStream_t st, const uint32_t* pkey, uint32_t n_pairs, uint2* ranges, uint32_t n_tiles);
+void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* pval, const float2* xy, const float4* conic,
+                  const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image);
+void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v);
+void launch_fill_u64(hipStream_t st, unsigned long long* p, uint64_t n, unsigned long long v);
+
+}  // namespace vm

@@ -18,6 +18,7 @@ z forward), cam_pos [3], fx, fy, cx, cy, znear.
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -95,9 +96,23 @@ def _random_quats(rng, n):
     return q
 
 
-def _sh(rng, n, std=0.3, dc_offset=0.5):
-    sh = rng.normal(0.0, std, size=(n, 16, 3))
-    sh[:, 0, :] += dc_offset
+def _sh(rng, n, std=0.3, dc_offset=0.5, chunks=16):
+    """SH coefficients N(0, std^2) (DC shifted by dc_offset), drawn in float32
+    from `chunks` child streams of `rng` filled in parallel threads; the result
+    depends only on the seed, not on the number of cores."""
+    from concurrent.futures import ThreadPoolExecutor
+    sh = np.empty((n, 16, 3), dtype=np.float32)
+    flat = sh.reshape(-1)
+    children = rng.spawn(chunks)
+    bounds = np.linspace(0, flat.size, chunks + 1).astype(np.int64)
+
+    def fill(i):
+        children[i].standard_normal(out=flat[bounds[i]:bounds[i + 1]], dtype=np.float32)
+
+    with ThreadPoolExecutor(max_workers=min(chunks, os.cpu_count() or 1)) as ex:
+        list(ex.map(fill, range(chunks)))
+    sh *= np.float32(std)
+    sh[:, 0, :] += np.float32(dc_offset)
     return sh
 
 
@@ -174,17 +189,20 @@ def _height_grad(params, x, y):
 
 
 def _frame_quats(normals, rng):
-    """Unit quaternions whose local z axis is ``normals`` with a random in-plane spin."""
+    """Unit quaternions (w, x, y, z) whose local z axis is ``normals``, with a
+    uniform random spin about it: the shortest rotation taking z to the normal,
+    composed with a rotation about z."""
     n = normals / np.linalg.norm(normals, axis=1, keepdims=True)
-    a = np.where(np.abs(n[:, 2:3]) < 0.9, np.array([[0.0, 0.0, 1.0]]), np.array([[1.0, 0.0, 0.0]]))
-    t = np.cross(a, n)
-    t /= np.linalg.norm(t, axis=1, keepdims=True)
-    b = np.cross(n, t)
-    th = rng.uniform(0.0, 2.0 * math.pi, size=(n.shape[0], 1))
-    u = np.cos(th) * t + np.sin(th) * b
-    v = np.cross(n, u)
-    R = np.stack([u, v, n], axis=2)  # columns = local axes
-    return _mat_to_quat(R)
+    w1 = 1.0 + n[:, 2]
+    x1 = -n[:, 1]
+    y1 = n[:, 0].copy()
+    flip = w1 < 1e-9                      # normal = -z: rotate by pi about x
+    w1[flip], x1[flip], y1[flip] = 0.0, 1.0, 0.0
+    nrm = np.sqrt(w1 * w1 + x1 * x1 + y1 * y1)
+    w1 /= nrm; x1 /= nrm; y1 /= nrm
+    th = rng.uniform(0.0, 2.0 * math.pi, size=n.shape[0])
+    w2, z2 = np.cos(0.5 * th), np.sin(0.5 * th)
+    return np.stack([w1 * w2, x1 * w2 + y1 * z2, y1 * w2 - x1 * z2, w1 * z2], 1)
 
 
 def _mat_to_quat(R):

@@ -1,0 +1,172 @@
+"""HIP path against the CPU oracle, through the C ABI, on the same seeded inputs.
+
+Bit-exact: frustum candidates, the page-ID buffer, per-page request depths,
+request order, page-table state, copy and missing lists, render list, tile
+rectangles and depth keys, the sorted (tile, Gaussian) pairs and tile
+ranges.  Floating point: conic and colour within 1e-5 relative, images
+within 1e-3 absolute per channel (the target of the method's parity claim).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_19415_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+NONE32 = np.uint32(0xffffffff)
+
+
+def _renderer(sc, P, S, img, idbuf, cell, **kw):
+    import paper_2506_19415_amd as pkg
+    return pkg.Renderer(sc, P, S, img=img, idbuf=idbuf, cell=cell, **kw)
+
+
+def compare_frame(r, ovm, out, n_views, check_image=True, tag=""):
+    """Every intermediate of the last frame of the library against the oracle."""
+    g = r.get
+    P = int(g("info", np.int64)[1])
+    # visibility
+    assert np.array_equal(g("cand", np.uint8)[: ovm.get("cand").size], ovm.get("cand")), tag
+    assert np.array_equal(g("idbuf", np.uint64)[: ovm.get("idbuf").size], ovm.get("idbuf")), tag
+    assert np.array_equal(g("req_direct", np.uint32), ovm.get("req_direct")), tag
+    assert np.array_equal(g("req_link", np.uint32), ovm.get("req_link")), tag
+    assert np.array_equal(g("page_level", np.int8), ovm.get("page_level")), tag
+    req = np.ctypeslib.as_array(out.requests, (out.n_requests,)) if out.n_requests else np.zeros(0, np.int32)
+    assert np.array_equal(req, ovm.get("req_page")), tag
+    # page table
+    for name, dt in [("slot_level", np.int8), ("last_used", np.int32), ("sub_vpage", np.int32),
+                     ("sub_last_used", np.int32), ("v2p", np.int32)]:
+        assert np.array_equal(g(name, dt), ovm.get(name)), (tag, name)
+    assert np.array_equal(g("copies", np.int64), ovm.get("copies")), tag
+    assert np.array_equal(g("copy_id", np.int32), ovm.get("copy_id")), tag
+    miss = np.ctypeslib.as_array(out.missing, (2 * out.n_missing,)) if out.n_missing else np.zeros(0, np.int32)
+    assert np.array_equal(miss, ovm.get("missing")), tag
+    c = ovm.counts()
+    st = out.stats
+    assert (st.requested, st.hits, st.misses, st.evictions, st.copies, st.missing, st.render_pages) == \
+           (c["requests"], c["hits"], c["misses"], c["evictions"], c["copies"], c["missing"], c["render_pages"]), tag
+    rl = g("render_list", np.uint32).reshape(-1, 4)
+    orl = ovm.get("render_list").reshape(-1, 6)
+    assert rl.shape[0] == orl.shape[0]
+    assert np.array_equal(rl[:, 0], orl[:, 2] * P + orl[:, 3] * orl[:, 4]), tag
+    assert np.array_equal(rl[:, 1], orl[:, 4]) and np.array_equal(rl[:, 2], orl[:, 5]), tag
+    compare_splat(r, ovm, n_views, check_image, tag)
+
+
+def compare_splat(r, ovm, n_views, check_image=True, tag=""):
+    g = r.get
+    pf, pi = g("pp_float", np.float32).reshape(-1, 10), g("pp_int", np.int32).reshape(-1, 6)
+    of, oi = ovm.get("pp_float").reshape(-1, 10), ovm.get("pp_int").reshape(-1, 6)
+    assert pf.shape == of.shape, tag
+    assert np.array_equal(pi[:, 0], oi[:, 0]), tag           # culled
+    vis = oi[:, 0] == 0
+    assert np.array_equal(pi[vis], oi[vis]), tag              # rect and tile counts
+    assert np.array_equal(pf[vis, 2].view(np.uint32), of[vis, 2].view(np.uint32)), tag   # depth keys
+    assert np.array_equal(pf[vis, :2], of[vis, :2]), tag      # pixel centre
+    np.testing.assert_allclose(pf[vis, 3:10], of[vis, 3:10], rtol=1e-5, atol=1e-7, err_msg=tag)
+    n_render = pf.shape[0] // n_views
+    keys, vals = g("keys", np.uint32), g("vals", np.uint32)
+    okeys, ovals = ovm.get("keys"), ovm.get("vals")
+    assert keys.shape == okeys.shape, tag
+    assert np.array_equal(keys.astype(np.uint64), okeys >> np.uint64(32)), tag
+    assert np.array_equal(vals % n_render, ovals), tag
+    assert np.array_equal(pf[vals, 2].view(np.uint32).astype(np.uint64), okeys & np.uint64(0xffffffff)), tag
+    # an empty tile's range is any (s, s): compare non-empty ranges, and emptiness
+    rg = g("ranges", np.uint32)[: ovm.get("ranges").size].reshape(-1, 2)
+    org = ovm.get("ranges").reshape(-1, 2)
+    ne = org[:, 1] > org[:, 0]
+    assert np.array_equal(rg[ne], org[ne]), tag
+    assert np.all(rg[~ne, 0] == rg[~ne, 1]), tag
+    if check_image:
+        img = r.image[:n_views].cpu().numpy()
+        ref = ovm.image(n_views)
+        err = np.abs(img - ref).max()
+        assert err <= 1e-3, (tag, err)
+
+
+@pytest.fixture(scope="module")
+def clusters():
+    sc = synth.scene_clusters(0)
+    return sc, oracle.OracleScene(sc, 256, 1, 0.5, 2.0)
+
+
+def test_clusters_all_frames(clusters):
+    sc, osc = clusters
+    cams = synth.orbit()
+    r = _renderer(sc, 256, 64, (320, 240), (80, 60), 0.5, full_scene=True)
+    ovm = oracle.OracleVM(osc, 64, (320, 240), (80, 60))
+    for k, cam in enumerate(cams):
+        print(f"clusters frame {k}", flush=True)
+        _, out = r.frame([cam])
+        ovm.frame([cam])
+        compare_frame(r, ovm, out, 1, tag=f"frame {k}")
+    # the full-scene baseline with the same kernels
+    r.render_full([cams[3]])
+    ovm.render_full([cams[3]])
+    compare_splat(r, ovm, 1, tag="full")
+    r.close()
+
+
+def test_two_views_ragged_image(clusters):
+    """Two views per call, an image that is not a multiple of the tile size
+    and an ID buffer that does not divide it."""
+    sc, osc = clusters
+    W, H, Wv, Hv = 330, 250, 70, 50
+    cams = [synth.orbit(8, 25.0, W, H)[i] for i in (1, 6)]
+    r = _renderer(sc, 256, 96, (W, H), (Wv, Hv), 0.5, max_views=2)
+    ovm = oracle.OracleVM(osc, 96, (W, H), (Wv, Hv))
+    for k in range(2):
+        _, out = r.frame(cams)
+        ovm.frame(cams)
+        compare_frame(r, ovm, out, 2, tag=f"two views {k}")
+    r.close()
+
+
+def test_copy_budget_and_no_links(clusters):
+    sc, osc = clusters
+    cams = synth.orbit()
+    r = _renderer(sc, 256, 64, (320, 240), (80, 60), 0.5, copy_budget=5, links=False)
+    ovm = oracle.OracleVM(osc, 64, (320, 240), (80, 60), copy_budget=5, use_links=False)
+    for k in range(3):
+        _, out = r.frame([cams[k]])
+        ovm.frame([cams[k]])
+        assert out.stats.copies <= 5
+        compare_frame(r, ovm, out, 1, tag=f"budget {k}")
+    r.close()
+
+
+def test_empty_and_inside_views(clusters):
+    """A camera looking away from the scene (nothing requested, black image)
+    and a camera inside a cluster (proxy boxes straddle the near plane)."""
+    sc, osc = clusters
+    centre = sc.means[:4096].mean(0)
+    away = synth.look_at(centre + np.array([0.0, 0.0, 60.0]), [0.0, 0.0, 1.0], 320, 240, 60.0)
+    inside = synth.look_at(centre, [1.0, 0.2, 0.1], 320, 240, 60.0)
+    r = _renderer(sc, 256, 64, (320, 240), (80, 60), 0.5)
+    ovm = oracle.OracleVM(osc, 64, (320, 240), (80, 60))
+    _, out = r.frame([away])
+    ovm.frame([away])
+    assert out.n_requests == 0 and out.stats.pairs == 0
+    assert float(r.image[0].abs().max()) == 0.0
+    compare_frame(r, ovm, out, 1, tag="away")
+    _, out = r.frame([inside])
+    ovm.frame([inside])
+    assert out.n_requests > 0
+    compare_frame(r, ovm, out, 1, tag="inside")
+    r.close()
+
+
+def test_padding_page_and_tiny_pool():
+    """A scene whose last page is mostly padding, one physical page: every
+    frame replaces the resident page."""
+    sc = synth.scene_clusters(7, n_clusters=2, per_cluster=700)   # 1400 = 5 pages of 256 + 120
+    osc = oracle.OracleScene(sc, 256, 1, 0.5, 2.0)
+    cams = synth.orbit(4, 20.0, 160, 128)
+    r = _renderer(sc, 256, 1, (160, 128), (40, 32), 0.5)
+    ovm = oracle.OracleVM(osc, 1, (160, 128), (40, 32))
+    for k, cam in enumerate(cams):
+        _, out = r.frame([cam])
+        ovm.frame([cam])
+        compare_frame(r, ovm, out, 1, tag=f"tiny pool {k}")
+    r.close()
