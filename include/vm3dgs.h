@@ -57,6 +57,7 @@ typedef struct {
 
 #define VM3DGS_FLAG_LINKS 1u           /* expand page links (Sec. 3 "Page Linking") */
 #define VM3DGS_FLAG_FULL_SCENE_COPY 2u /* keep all level-0 pages in HBM for vm3dgs_render_full */
+#define VM3DGS_FLAG_BLEND_STATS 4u     /* count blend work (stats.blend_evals / blend_alphas); slower */
 
 typedef struct {
     uint32_t img_w, img_h;        /* output image, pixels */
@@ -64,7 +65,7 @@ typedef struct {
     uint32_t max_views;           /* views per call, >= 1 */
     uint32_t attr_format;         /* 0: fp32 (236 B/Gaussian); 1: means fp32, scale/quat/opacity fp16, SH bf16 (124 B) */
     uint32_t copy_budget_pages;   /* page copies per frame, 0 = unlimited (Sec. 4.3: staging budget) */
-    uint32_t reserved0;
+    float idbuf_guard_px;         /* the ID buffer and frustum extend this many image pixels past each edge */
     float proxy_cell_m;           /* proxy grid cell edge, metres */
     float link_sigma;             /* link ellipsoid radius in standard deviations */
     float lod_radius_px;          /* level l is chosen while the projected page radius <= tau / 2^(l-1) */
@@ -74,8 +75,9 @@ typedef struct {
     uint64_t pair_capacity;       /* initial (tile, Gaussian) pair capacity; grows on demand; 0 = automatic */
 } vm3dgs_options;
 
-/* Fill *o with defaults: 1920x1080 image, 240x135 ID buffer, one view, fp32,
- * unlimited copies, 1 m cells, 2-sigma links, 32 px LOD radius, links on. */
+/* Fill *o with defaults: 1920x1080 image, 240x135 ID buffer with a 32 px
+ * guard band, one view, fp32, unlimited copies, 1 m cells, 2-sigma links,
+ * 32 px LOD radius, links on. */
 void vm3dgs_options_default(vm3dgs_options* o);
 
 /* Pinhole camera, OpenCV axes (x right, y down, z forward).  view is the
@@ -100,6 +102,8 @@ typedef struct {
     uint64_t visible_gaussians; /* of those, not culled by the projection */
     uint64_t pairs;             /* (tile, Gaussian) pairs sorted and blended */
     uint64_t bytes_copied;      /* host -> device page bytes */
+    uint64_t blend_evals;       /* pixel-Gaussian evaluations (VM3DGS_FLAG_BLEND_STATS only) */
+    uint64_t blend_alphas;      /* of those, evaluations that computed alpha (same flag) */
     float ms_visibility, ms_pagetable, ms_copy, ms_preprocess, ms_sort, ms_blend, ms_total;
 } vm3dgs_stats;
 
@@ -152,6 +156,11 @@ vm3dgs_status vm3dgs_render_full(vm3dgs* ctx, const vm3dgs_camera* cams, uint32_
  * "pp_int", "keys", "vals", "ranges", "host_page" (level-0 attributes of all
  * pages decoded to 59 floats). */
 int64_t vm3dgs_debug_get(vm3dgs* ctx, const char* name, void* host_dst, int64_t cap);
+
+/* Replace the VM3DGS_FLAG_LINKS / VM3DGS_FLAG_BLEND_STATS bits of the options
+ * for later frames (VM3DGS_FLAG_FULL_SCENE_COPY is fixed at create).
+ * Errors: INVALID_ARG for a NULL context. */
+vm3dgs_status vm3dgs_set_flags(vm3dgs* ctx, uint32_t flags);
 
 /* Block until the render and copy streams are idle. */
 vm3dgs_status vm3dgs_sync(vm3dgs* ctx);

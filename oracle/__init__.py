@@ -48,7 +48,7 @@ def lib():
         L.or_scene_get.argtypes = [C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64]
         L.or_vm_create.restype = C.c_void_p
         L.or_vm_create.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
-                                   C.c_int, C.c_int, C.c_float]
+                                   C.c_int, C.c_int, C.c_float, C.c_float]
         L.or_vm_free.argtypes = [C.c_void_p]
         L.or_vm_frame.argtypes = [C.c_void_p, C.POINTER(_Cam), C.c_int, C.c_void_p]
         L.or_vm_visibility.argtypes = [C.c_void_p, C.POINTER(_Cam), C.c_int, C.c_int]
@@ -181,13 +181,13 @@ class OracleVM:
     """Per-frame oracle state: page table over ``pool_pages`` physical pages."""
 
     def __init__(self, oscene: OracleScene, pool_pages, img, idbuf, copy_budget=0, use_links=True,
-                 lod_radius_px=32.0):
+                 lod_radius_px=32.0, guard_px=32.0):
         self.scene = oscene
         self.W, self.H = img
         self.Wv, self.Hv = idbuf
         self.TX, self.TY = (self.W + 15) // 16, (self.H + 15) // 16
         self.ptr = lib().or_vm_create(oscene.ptr, int(pool_pages), int(copy_budget), int(bool(use_links)),
-                                      self.W, self.H, self.Wv, self.Hv, float(lod_radius_px))
+                                      self.W, self.H, self.Wv, self.Hv, float(lod_radius_px), float(guard_px))
         if not self.ptr:
             raise ValueError("oracle: invalid VM parameters")
 

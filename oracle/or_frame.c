@@ -60,6 +60,7 @@ struct or_vm {
     const or_scene* s;
     int S, budget, use_links, W, H, Wv, Hv, TX, TY;
     float tau;
+    float guard;           /* ID buffer and frustum extend this many pixels past each image edge */
     int P, L, n_pg, bytes_g;
     int frame;
     int force_all;         /* test switch: every page is directly requested */
@@ -100,15 +101,16 @@ static inline void view_xform(const float* V, float x, float y, float z, float* 
     o[2] = ((V[8] * x + V[9] * y) + V[10] * z) + V[11];
 }
 
-/* ---- 1a. frustum: sphere against near plane and the four side planes ---- */
-static int sphere_in_frustum(const or_camera* c, int W, int H, const float* sp)
+/* ---- 1a. frustum: sphere against near plane and the four side planes, which
+ * pass through the edges of the image widened by the guard band G ---- */
+static int sphere_in_frustum(const or_camera* c, int W, int H, float G, const float* sp)
 {
     float p[3];
     view_xform(c->view, sp[0], sp[1], sp[2], p);
     float r = sp[3];
     if (!(p[2] + r > c->znear)) return 0;
-    float tl = c->cx / c->fx, tr = ((float)W - c->cx) / c->fx;
-    float tt = c->cy / c->fy, tb = ((float)H - c->cy) / c->fy;
+    float tl = (c->cx + G) / c->fx, tr = (((float)W + G) - c->cx) / c->fx;
+    float tt = (c->cy + G) / c->fy, tb = (((float)H + G) - c->cy) / c->fy;
     float kl = sqrtf(1.0f + tl * tl), kr = sqrtf(1.0f + tr * tr);
     float kt = sqrtf(1.0f + tt * tt), kb = sqrtf(1.0f + tb * tb);
     if (!(p[0] + tl * p[2] >= -(r * kl))) return 0;
@@ -118,13 +120,15 @@ static int sphere_in_frustum(const or_camera* c, int W, int H, const float* sp)
     return 1;
 }
 
-/* ---- 1b. page-ID buffer: the ray through each buffer pixel centre against
- * each proxy box (slab test); the nearest entry depth wins ---- */
-static void pixel_ray(const or_camera* c, int W, int H, int Wv, int Hv, int px, int py, float inv[3])
+/* ---- 1b. page-ID buffer: it spans image coordinates [-G, W+G) x [-G, H+G);
+ * the ray through each buffer pixel centre against each proxy box (slab
+ * test); the nearest entry depth wins ---- */
+static void pixel_ray(const or_camera* c, int W, int H, float G, int Wv, int Hv, int px, int py, float inv[3])
 {
-    float sx = (float)W / (float)Wv, sy = (float)H / (float)Hv;
-    float dcx = (((float)px + 0.5f) * sx - c->cx) / c->fx;
-    float dcy = (((float)py + 0.5f) * sy - c->cy) / c->fy;
+    float sx = ((float)W + 2.0f * G) / (float)Wv, sy = ((float)H + 2.0f * G) / (float)Hv;
+    float xc = ((float)px + 0.5f) * sx - G, yc = ((float)py + 0.5f) * sy - G;
+    float dcx = (xc - c->cx) / c->fx;
+    float dcy = (yc - c->cy) / c->fy;
     const float* V = c->view;
     for (int a = 0; a < 3; a++) {
         float d = (V[a] * dcx + V[4 + a] * dcy) + V[8 + a];
@@ -151,7 +155,7 @@ static int ray_box(const float* o, const float* inv, const float* box, float zne
 }
 
 /* conservative pixel rectangle of a box (inclusive, may be empty) */
-static int box_rect(const or_camera* c, int W, int H, int Wv, int Hv, const float* box, int* r)
+static int box_rect(const or_camera* c, int W, int H, float G, int Wv, int Hv, const float* box, int* r)
 {
     float vmin[3] = {INFINITY, INFINITY, INFINITY}, vmax[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int k = 0; k < 8; k++) {
@@ -165,9 +169,9 @@ static int box_rect(const or_camera* c, int W, int H, int Wv, int Hv, const floa
     float ys[4] = {vmin[1] / z0, vmin[1] / z1, vmax[1] / z0, vmax[1] / z1};
     float xl = fminf(fminf(xs[0], xs[1]), fminf(xs[2], xs[3])), xh = fmaxf(fmaxf(xs[0], xs[1]), fmaxf(xs[2], xs[3]));
     float yl = fminf(fminf(ys[0], ys[1]), fminf(ys[2], ys[3])), yh = fmaxf(fmaxf(ys[0], ys[1]), fmaxf(ys[2], ys[3]));
-    float sx = (float)W / (float)Wv, sy = (float)H / (float)Hv;
-    float fx0 = floorf((c->fx * xl + c->cx) / sx) - 1.0f, fx1 = floorf((c->fx * xh + c->cx) / sx) + 1.0f;
-    float fy0 = floorf((c->fy * yl + c->cy) / sy) - 1.0f, fy1 = floorf((c->fy * yh + c->cy) / sy) + 1.0f;
+    float sx = ((float)W + 2.0f * G) / (float)Wv, sy = ((float)H + 2.0f * G) / (float)Hv;
+    float fx0 = floorf(((c->fx * xl + c->cx) + G) / sx) - 1.0f, fx1 = floorf(((c->fx * xh + c->cx) + G) / sx) + 1.0f;
+    float fy0 = floorf(((c->fy * yl + c->cy) + G) / sy) - 1.0f, fy1 = floorf(((c->fy * yh + c->cy) + G) / sy) + 1.0f;
     fx0 = fmaxf(fx0, 0.0f); fy0 = fmaxf(fy0, 0.0f);
     fx1 = fminf(fx1, (float)(Wv - 1)); fy1 = fminf(fy1, (float)(Hv - 1));
     if (!(fx0 <= fx1) || !(fy0 <= fy1)) return 0;
@@ -182,7 +186,7 @@ static void idbuf_render(const or_vm* vm, const or_camera* c, const uint8_t* can
     for (int i = 0; i < Wv * Hv; i++) ib[i] = NONE64;
     float* inv = malloc(sizeof(float) * 3 * (size_t)Wv * Hv);
     for (int py = 0; py < Hv; py++)
-        for (int px = 0; px < Wv; px++) pixel_ray(c, vm->W, vm->H, Wv, Hv, px, py, inv + 3 * (py * Wv + px));
+        for (int px = 0; px < Wv; px++) pixel_ray(c, vm->W, vm->H, vm->guard, Wv, Hv, px, py, inv + 3 * (py * Wv + px));
     const float* boxes = or_scene_cellbox(vm->s);
     const int32_t* cstart = or_scene_cellstart(vm->s);
     for (int p = 0; p < vm->n_pg; p++) {
@@ -190,7 +194,7 @@ static void idbuf_render(const or_vm* vm, const or_camera* c, const uint8_t* can
         for (int32_t ci = cstart[p]; ci < cstart[p + 1]; ci++) {
             const float* box = boxes + 6 * ci;
             int r[4] = {0, 0, Wv - 1, Hv - 1};
-            if (!brute_force && !box_rect(c, vm->W, vm->H, Wv, Hv, box, r)) continue;
+            if (!brute_force && !box_rect(c, vm->W, vm->H, vm->guard, Wv, Hv, box, r)) continue;
             for (int py = r[1]; py <= r[3]; py++)
                 for (int px = r[0]; px <= r[2]; px++) {
                     float d;
@@ -530,12 +534,12 @@ static void splat(or_vm* vm, const or_camera* cams, int n_views, const uint8_t* 
 
 /* ------------------------------------------------------------------------ */
 or_vm* or_vm_create(const or_scene* s, int pool_pages, int copy_budget, int use_links,
-                    int W, int H, int Wv, int Hv, float tau)
+                    int W, int H, int Wv, int Hv, float tau, float guard)
 {
     if (!s || pool_pages <= 0 || W <= 0 || H <= 0 || Wv <= 0 || Hv <= 0) return NULL;
     or_vm* vm = calloc(1, sizeof(or_vm));
     vm->s = s; vm->S = pool_pages; vm->budget = copy_budget; vm->use_links = use_links;
-    vm->W = W; vm->H = H; vm->Wv = Wv; vm->Hv = Hv; vm->tau = tau;
+    vm->W = W; vm->H = H; vm->Wv = Wv; vm->Hv = Hv; vm->tau = tau; vm->guard = guard;
     vm->TX = (W + 15) / 16; vm->TY = (H + 15) / 16;
     vm->P = or_scene_P(s); vm->L = or_scene_L(s); vm->n_pg = or_scene_npg(s);
     vm->bytes_g = or_scene_format(s) == 1 ? 124 : 236;
@@ -597,7 +601,7 @@ int or_vm_visibility(or_vm* vm, const or_camera* cams, int n_views, int brute_fo
     const float* sp = or_scene_spheres(vm->s);
     for (int v = 0; v < n_views; v++) {
         for (int p = 0; p < n_pg; p++)
-            vm->cand[(size_t)v * n_pg + p] = (uint8_t)sphere_in_frustum(&cams[v], vm->W, vm->H, sp + 4 * p);
+            vm->cand[(size_t)v * n_pg + p] = (uint8_t)sphere_in_frustum(&cams[v], vm->W, vm->H, vm->guard, sp + 4 * p);
         idbuf_render(vm, &cams[v], vm->cand + (size_t)v * n_pg, vm->idbuf + (size_t)v * Wv * Hv, brute_force);
     }
     /* reduction: nearest depth per page, then links */

@@ -53,8 +53,10 @@ void or_scene_free(or_scene* s);
 int64_t or_scene_get(const or_scene* s, const char* name, void* dst, int64_t cap);
 
 /* ---- per frame (Sec. 4) ---- */
+/* guard_px: the page-ID buffer and the frustum extend this many pixels past
+ * each edge of the image */
 or_vm* or_vm_create(const or_scene* s, int pool_pages, int copy_budget, int use_links,
-                    int img_w, int img_h, int idbuf_w, int idbuf_h, float lod_radius_px);
+                    int img_w, int img_h, int idbuf_w, int idbuf_h, float lod_radius_px, float guard_px);
 void or_vm_free(or_vm* vm);
 /* tile_mask: NULL = render every tile, else [n_views * TX * TY] bytes, 1 = render */
 int or_vm_frame(or_vm* vm, const or_camera* cams, int n_views, const uint8_t* tile_mask);

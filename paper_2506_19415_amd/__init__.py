@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libvm3dgs.so")
 
 VM3DGS_FLAG_LINKS = 1
 VM3DGS_FLAG_FULL_SCENE_COPY = 2
+VM3DGS_FLAG_BLEND_STATS = 4
 
 _ERRORS = {-1: "INVALID_ARG", -2: "HOST_OOM", -3: "DEVICE_OOM", -4: "HIP", -5: "STATE", -6: "CAPACITY"}
 
@@ -36,7 +37,7 @@ class vm3dgs_scene(C.Structure):
 class vm3dgs_options(C.Structure):
     _fields_ = [("img_w", C.c_uint32), ("img_h", C.c_uint32), ("idbuf_w", C.c_uint32), ("idbuf_h", C.c_uint32),
                 ("max_views", C.c_uint32), ("attr_format", C.c_uint32), ("copy_budget_pages", C.c_uint32),
-                ("reserved0", C.c_uint32), ("proxy_cell_m", C.c_float), ("link_sigma", C.c_float),
+                ("idbuf_guard_px", C.c_float), ("proxy_cell_m", C.c_float), ("link_sigma", C.c_float),
                 ("lod_radius_px", C.c_float), ("flags", C.c_uint32), ("stream_render", C.c_void_p),
                 ("stream_copy", C.c_void_p), ("pair_capacity", C.c_uint64)]
 
@@ -50,7 +51,8 @@ class vm3dgs_stats(C.Structure):
     _fields_ = [(n, C.c_uint32) for n in ("candidates", "requested", "direct", "linked", "hits", "misses",
                                            "evictions", "missing", "copies", "render_pages", "pool_pages_used",
                                            "reserved0")] + \
-               [(n, C.c_uint64) for n in ("render_gaussians", "visible_gaussians", "pairs", "bytes_copied")] + \
+               [(n, C.c_uint64) for n in ("render_gaussians", "visible_gaussians", "pairs", "bytes_copied",
+                                           "blend_evals", "blend_alphas")] + \
                [(n, C.c_float) for n in ("ms_visibility", "ms_pagetable", "ms_copy", "ms_preprocess", "ms_sort",
                                           "ms_blend", "ms_total")]
 
@@ -86,6 +88,8 @@ def lib():
         L.vm3dgs_render_full.restype = C.c_int32
         L.vm3dgs_debug_get.argtypes = [C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64]
         L.vm3dgs_debug_get.restype = C.c_int64
+        L.vm3dgs_set_flags.argtypes = [C.c_void_p, C.c_uint32]
+        L.vm3dgs_set_flags.restype = C.c_int32
         L.vm3dgs_sync.argtypes = [C.c_void_p]
         L.vm3dgs_sync.restype = C.c_int32
         L.vm3dgs_last_error.argtypes = [C.c_void_p]
@@ -190,6 +194,10 @@ def vm3dgs_pages_destroy(h):
     lib().vm3dgs_pages_destroy(h)
 
 
+def vm3dgs_set_flags(h, flags: int):
+    _check(h, lib().vm3dgs_set_flags(h, int(flags)))
+
+
 def vm3dgs_sync(h):
     _check(h, lib().vm3dgs_sync(h))
 
@@ -204,7 +212,7 @@ class Renderer:
 
     def __init__(self, scene, page_size, pool_pages, lod_levels=1, img=(1920, 1080), idbuf=(240, 135),
                  max_views=1, attr_format=0, cell=1.0, link_sigma=2.0, lod_radius_px=32.0, links=True,
-                 full_scene=False, copy_budget=0, pair_capacity=0):
+                 full_scene=False, copy_budget=0, pair_capacity=0, guard_px=32.0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Renderer needs a HIP device")
@@ -214,6 +222,7 @@ class Renderer:
         o.max_views = max_views
         o.attr_format = attr_format
         o.copy_budget_pages = copy_budget
+        o.idbuf_guard_px = guard_px
         o.proxy_cell_m, o.link_sigma, o.lod_radius_px = cell, link_sigma, lod_radius_px
         o.flags = (VM3DGS_FLAG_LINKS if links else 0) | (VM3DGS_FLAG_FULL_SCENE_COPY if full_scene else 0)
         o.pair_capacity = pair_capacity
@@ -229,6 +238,10 @@ class Renderer:
     def render_full(self, cams):
         st = vm3dgs_render_full(self.h, cams, self.image.data_ptr())
         return self.image[:len(cams)], st
+
+    def set_flags(self, flags):
+        vm3dgs_set_flags(self.h, flags)
+        self.opts.flags = (self.opts.flags & VM3DGS_FLAG_FULL_SCENE_COPY) | (flags & ~VM3DGS_FLAG_FULL_SCENE_COPY)
 
     def get(self, name, dtype):
         return vm3dgs_debug_get(self.h, name, dtype)

@@ -43,6 +43,7 @@ struct vm3dgs {
     CamK* d_cams = nullptr; CamK* h_cams = nullptr;
     // visibility
     uint8_t* d_cand = nullptr; float4* d_rays = nullptr; unsigned long long* d_idbuf = nullptr;
+    int4* d_crect = nullptr; uint32_t* d_carea = nullptr; uint32_t* d_coffs = nullptr; uint32_t* d_vtemp = nullptr;
     uint32_t* d_rd = nullptr; uint32_t* d_rl = nullptr; int8_t* d_plevel = nullptr; uint64_t* d_keys = nullptr;
     uint32_t* d_ctr = nullptr; uint32_t* h_ctr = nullptr;
     // page table
@@ -63,7 +64,12 @@ struct vm3dgs {
     uint32_t* d_pkey[2] = {nullptr, nullptr}; uint32_t* d_pval[2] = {nullptr, nullptr};
     uint2* d_ranges = nullptr;
     uint32_t* d_temp = nullptr; size_t temp_words = 0;
+    // zero block: counters | look-back error flag | tickets | histograms (cleared per frame)
+    uint32_t* d_zero = nullptr;
+    uint64_t* d_status = nullptr; size_t status_words = 0;
+    SortWork sw;
     uint32_t* d_total = nullptr; uint32_t* h_total = nullptr;
+    uint2* d_bstats = nullptr; uint2* h_bstats = nullptr;
     int frame = 0;
     // last frame, for vm3dgs_debug_get and the frame output
     uint32_t last_views = 0, last_n_render = 0, last_n_pairs = 0, last_n_copy = 0, last_n_missing = 0;
@@ -135,8 +141,9 @@ void free_all(vm3dgs* c) {
     dfree(c->d_sph); dfree(c->d_clo); dfree(c->d_chi); dfree(c->d_ls); dfree(c->d_ld);
     dfree(c->d_pool); dfree(c->d_full); hfree(c->h_store); dfree(c->d_level_base);
     dfree(c->d_cams); hfree(c->h_cams);
-    dfree(c->d_cand); dfree(c->d_rays); dfree(c->d_idbuf); dfree(c->d_rd); dfree(c->d_rl); dfree(c->d_plevel);
-    dfree(c->d_keys); dfree(c->d_ctr); hfree(c->h_ctr);
+    dfree(c->d_cand); dfree(c->d_rays); dfree(c->d_idbuf);
+    dfree(c->d_crect); dfree(c->d_carea); dfree(c->d_coffs); dfree(c->d_vtemp); dfree(c->d_rd); dfree(c->d_rl); dfree(c->d_plevel);
+    dfree(c->d_keys); c->d_ctr = nullptr; hfree(c->h_ctr);
     dfree(c->d_slot_level); dfree(c->d_last_used); dfree(c->d_sub_vpage); dfree(c->d_sub_lu); dfree(c->d_v2p);
     dfree(c->d_req_sub); dfree(c->d_slot_req); dfree(c->d_miss);
     dfree(c->d_copies); hfree(c->h_copies); dfree(c->d_copy_id); dfree(c->d_missing); hfree(c->h_missing);
@@ -145,11 +152,32 @@ void free_all(vm3dgs* c) {
     dfree(c->d_xy); dfree(c->d_conic); dfree(c->d_rgb); dfree(c->d_depth); dfree(c->d_rect); dfree(c->d_tiles);
     for (int i = 0; i < 2; ++i) { dfree(c->d_dkey[i]); dfree(c->d_dval[i]); dfree(c->d_pkey[i]); dfree(c->d_pval[i]); }
     dfree(c->d_offs); dfree(c->d_ranges); dfree(c->d_temp); dfree(c->d_total); hfree(c->h_total);
+    dfree(c->d_zero); dfree(c->d_status); dfree(c->d_bstats); hfree(c->h_bstats);
     if (c->ev_copy) hipEventDestroy(c->ev_copy);
     for (auto& e : c->ev)
         if (e) hipEventDestroy(e);
     if (c->own_sr && c->sr) hipStreamDestroy(c->sr);
     if (c->own_sc && c->sc) hipStreamDestroy(c->sc);
+}
+
+constexpr int ZB_CTR = 0, ZB_ERR = C_NCOUNTERS, ZB_TICKETS = ZB_ERR + 16,
+              ZB_HIST = ZB_TICKETS + SortWork::kMaxTickets, ZB_WORDS = ZB_HIST + 256 * SortWork::kMaxHist;
+
+void ensure_status(vm3dgs* c) {
+    const size_t need = lb_status_words(std::max(c->cap_pairs, c->cap_render));
+    if (need > c->status_words) {
+        dfree(c->d_status);
+        dalloc(&c->d_status, need);
+        HIPCHK(hipMemset(c->d_status, 0, sizeof(uint64_t) * need));
+        c->status_words = need;
+        c->sw.status = c->d_status;
+    }
+}
+
+// start of a frame's device work: clear counters, tickets and histograms
+void begin_work(vm3dgs* c) {
+    launch_fill_u32(c->sr, c->d_zero, ZB_WORDS, 0u);
+    c->sw.reset();
 }
 
 void ensure_temp(vm3dgs* c) {
@@ -173,6 +201,7 @@ void ensure_pairs(vm3dgs* c, uint64_t n) {
     }
     c->cap_pairs = cap;
     ensure_temp(c);
+    ensure_status(c);
 }
 
 // the render half of a frame: preprocess .. blend for n_render Gaussians per view
@@ -191,23 +220,34 @@ void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool,
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[4], c->sr));
     // depth order of the render set (culled entries carry all-ones keys and sort last)
-    const int db = radix_sort_u32(c->sr, c->d_dkey, c->d_dval, (uint32_t)n_total, 0, 32, c->d_temp);
-    scan_excl_gather(c->sr, c->d_tiles, c->d_dval[db], n_total, c->d_offs, c->d_total, c->d_temp);
+    const int db = onesweep_u32(c->sr, c->sw, c->d_dkey, c->d_dval, (uint32_t)n_total, 0, 32);
+    scan_lb_gather(c->sr, c->sw, c->d_tiles, c->d_dval[db], n_total, c->d_offs, c->d_total);
     HIPCHK(hipMemcpyAsync(c->h_total, c->d_total, sizeof(uint32_t), hipMemcpyDeviceToHost, c->sr));
+    HIPCHK(hipMemcpyAsync(c->h_total + 1, c->d_zero + ZB_ERR, sizeof(uint32_t), hipMemcpyDeviceToHost, c->sr));
     HIPCHK(hipStreamSynchronize(c->sr));
+    if (c->h_total[1]) throw HipError{hipErrorUnknown, "single-pass scan look-back did not complete", __LINE__};
     const uint32_t n_pairs = *c->h_total;
     ensure_pairs(c, n_pairs);
     launch_emit(c->sr, c->d_dval[db], c->d_offs, c->d_rect, (uint32_t)n_total, n_render, c->TX, c->TY, c->d_pkey[0],
                 c->d_pval[0], (uint32_t)c->cap_pairs);
     const uint32_t n_tiles = (uint32_t)(c->TX * c->TY) * n_views;
-    const int pb = radix_sort_u32(c->sr, c->d_pkey, c->d_pval, n_pairs, 0, std::max(1, bits_for(n_tiles)), c->d_temp);
+    const int pb = onesweep_u32(c->sr, c->sw, c->d_pkey, c->d_pval, n_pairs, 0, std::max(1, bits_for(n_tiles)));
     launch_ranges(c->sr, c->d_pkey[pb], n_pairs, c->d_ranges, n_tiles);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[5], c->sr));
+    const bool bstats = (c->opt.flags & VM3DGS_FLAG_BLEND_STATS) != 0;
     launch_blend(c->sr, c->d_ranges, c->d_pval[pb], c->d_xy, c->d_conic, c->d_rgb, (int)c->opt.img_w,
-                 (int)c->opt.img_h, c->TX, c->TY, (int)n_views, image);
+                 (int)c->opt.img_h, c->TX, c->TY, (int)n_views, image, bstats ? c->d_bstats : nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[6], c->sr));
+    if (bstats && st) {
+        HIPCHK(hipMemcpyAsync(c->h_bstats, c->d_bstats, sizeof(uint2) * n_tiles, hipMemcpyDeviceToHost, c->sr));
+        HIPCHK(hipStreamSynchronize(c->sr));
+        uint64_t e = 0, al = 0;
+        for (uint32_t i = 0; i < n_tiles; ++i) { e += c->h_bstats[i].x; al += c->h_bstats[i].y; }
+        st->blend_evals = e;
+        st->blend_alphas = al;
+    }
     c->last_views = n_views; c->last_n_render = n_render; c->last_n_pairs = n_pairs;
     c->last_pbuf = pb; c->last_dbuf = db;
     if (st) {
@@ -243,7 +283,7 @@ void vm3dgs_options_default(vm3dgs_options* o) {
     memset(o, 0, sizeof(*o));
     o->img_w = 1920; o->img_h = 1080; o->idbuf_w = 240; o->idbuf_h = 135; o->max_views = 1;
     o->attr_format = 0; o->copy_budget_pages = 0;
-    o->proxy_cell_m = 1.0f; o->link_sigma = 2.0f; o->lod_radius_px = 32.0f;
+    o->proxy_cell_m = 1.0f; o->link_sigma = 2.0f; o->lod_radius_px = 32.0f; o->idbuf_guard_px = 32.0f;
     o->flags = VM3DGS_FLAG_LINKS;
 }
 
@@ -268,7 +308,8 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
     if (o.img_w > 65535 * 16 || o.img_h > 65535 * 16) return inval("image too large");
     if (o.max_views == 0 || o.max_views > 64) return inval("max_views must be 1..64");
     if (o.attr_format > 1) return inval("attr_format must be 0 or 1");
-    if (!(o.proxy_cell_m > 0.0f) || !(o.link_sigma >= 0.0f) || !(o.lod_radius_px > 0.0f))
+    if (!(o.proxy_cell_m > 0.0f) || !(o.link_sigma >= 0.0f) || !(o.lod_radius_px > 0.0f) ||
+        !(o.idbuf_guard_px >= 0.0f && o.idbuf_guard_px <= 4096.0f))
         return inval("proxy_cell_m, link_sigma, lod_radius_px out of range");
     if (scene->n > (uint64_t)INT32_MAX * page_size) return inval("scene too large");
 
@@ -335,9 +376,17 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         // visibility
         const int64_t npx = (int64_t)o.idbuf_w * o.idbuf_h;
         dalloc(&c->d_cand, (size_t)V * n_pg); dalloc(&c->d_rays, (size_t)V * npx); dalloc(&c->d_idbuf, (size_t)V * npx);
+        dalloc(&c->d_crect, (size_t)V * nc); dalloc(&c->d_carea, (size_t)V * nc); dalloc(&c->d_coffs, (size_t)V * nc + 1);
+        dalloc(&c->d_vtemp, scan_temp_words((uint64_t)V * nc));
         dalloc(&c->d_rd, n_pg); dalloc(&c->d_rl, n_pg); dalloc(&c->d_plevel, n_pg);
         dalloc(&c->d_keys, (size_t)2 * n_pg); halloc(&c->h_keys, n_pg);
-        dalloc(&c->d_ctr, C_NCOUNTERS); halloc(&c->h_ctr, C_NCOUNTERS);
+        dalloc(&c->d_zero, ZB_WORDS);
+        HIPCHK(hipMemset(c->d_zero, 0, sizeof(uint32_t) * ZB_WORDS));
+        c->d_ctr = c->d_zero + ZB_CTR;
+        c->sw.err = c->d_zero + ZB_ERR;
+        c->sw.tickets = c->d_zero + ZB_TICKETS;
+        c->sw.hist = c->d_zero + ZB_HIST;
+        halloc(&c->h_ctr, C_NCOUNTERS);
         // page table (empty pool)
         dalloc(&c->d_slot_level, S); dalloc(&c->d_last_used, S); dalloc(&c->d_sub_vpage, (size_t)S * SUBS);
         dalloc(&c->d_sub_lu, (size_t)S * SUBS); dalloc(&c->d_v2p, (size_t)n_pg * L);
@@ -361,10 +410,12 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         dalloc(&c->d_rect, R); dalloc(&c->d_tiles, R); dalloc(&c->d_offs, R + 1);
         for (int i = 0; i < 2; ++i) { dalloc(&c->d_dkey[i], R); dalloc(&c->d_dval[i], R); }
         dalloc(&c->d_ranges, (size_t)c->TX * c->TY * V);
-        dalloc(&c->d_total, 4); halloc(&c->h_total, 4);
+        dalloc(&c->d_bstats, (size_t)c->TX * c->TY * V); halloc(&c->h_bstats, (size_t)c->TX * c->TY * V);
+        dalloc(&c->d_total, 4); halloc(&c->h_total, 4);  // [0] pairs, [1] look-back error
         c->cap_pairs = 0;
         ensure_pairs(c, o.pair_capacity ? o.pair_capacity : std::max<uint64_t>(R * 4, 1u << 22));
         ensure_temp(c);
+        ensure_status(c);
         if (o.flags & VM3DGS_FLAG_FULL_SCENE_COPY) {
             std::vector<RenderEntry> full((size_t)n_pg);
             for (int p = 0; p < n_pg; ++p)
@@ -405,15 +456,18 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         }
         HIPCHK(hipEventRecord(ev[0], c->sr));
         HIPCHK(hipMemcpyAsync(c->d_cams, c->h_cams, sizeof(CamK) * n_views, hipMemcpyHostToDevice, c->sr));
-        launch_fill_u32(c->sr, c->d_ctr, C_NCOUNTERS, 0u);
+        begin_work(c);
         VisArgs va{};
         va.spheres = c->d_sph; va.n_pg = c->n_pg; va.cell_lo = c->d_clo; va.cell_hi = c->d_chi; va.nc = c->ps.nc();
         va.link_start = c->d_ls; va.link_dst = c->d_ld; va.use_links = (c->opt.flags & VM3DGS_FLAG_LINKS) ? 1 : 0;
         va.cams = c->d_cams; va.n_views = (int)n_views; va.W = (int)c->opt.img_w; va.H = (int)c->opt.img_h;
         va.Wv = (int)c->opt.idbuf_w; va.Hv = (int)c->opt.idbuf_h; va.L = c->L; va.tau = c->opt.lod_radius_px;
         va.fy_max = fy_max;
+        va.guard = c->opt.idbuf_guard_px;
         va.cand = c->d_cand; va.rays = c->d_rays; va.idbuf = c->d_idbuf; va.req_direct = c->d_rd; va.req_link = c->d_rl;
         va.page_level = c->d_plevel; va.req_keys = c->d_keys; va.counters = c->d_ctr;
+        va.cell_rects = c->d_crect; va.cell_area = c->d_carea; va.cell_offs = c->d_coffs; va.scan_temp = c->d_vtemp;
+        va.sw = &c->sw;
         launch_visibility(c->sr, va);
         HIPCHK(hipGetLastError());
         HIPCHK(hipEventRecord(ev[1], c->sr));
@@ -506,6 +560,7 @@ vm3dgs_status vm3dgs_render_full(vm3dgs* c, const vm3dgs_camera* cams, uint32_t 
         for (uint32_t v = 0; v < n_views; ++v) to_camk(cams[v], c->h_cams[v]);
         HIPCHK(hipEventRecord(c->ev[0], c->sr));
         HIPCHK(hipMemcpyAsync(c->d_cams, c->h_cams, sizeof(CamK) * n_views, hipMemcpyHostToDevice, c->sr));
+        begin_work(c);
         splat(c, c->d_rlist_full, (uint32_t)c->n_pg, c->d_full, (uint32_t)c->n_pg * (uint32_t)c->P, n_views, image, &st);
         HIPCHK(hipStreamSynchronize(c->sr));
         st.ms_preprocess = ms(c->ev[3], c->ev[4]);
@@ -517,6 +572,13 @@ vm3dgs_status vm3dgs_render_full(vm3dgs* c, const vm3dgs_camera* cams, uint32_t 
         return fail(c, h);
     }
     if (stats) *stats = st;
+    return VM3DGS_OK;
+}
+
+vm3dgs_status vm3dgs_set_flags(vm3dgs* c, uint32_t flags) {
+    if (!c) return VM3DGS_E_INVALID_ARG;
+    const uint32_t fixed = VM3DGS_FLAG_FULL_SCENE_COPY;
+    c->opt.flags = (c->opt.flags & fixed) | (flags & ~fixed);
     return VM3DGS_OK;
 }
 

@@ -10,10 +10,11 @@
 //                its 64 Gaussians over its lanes (prefix sums of the counts)
 //                and writes (tile, Gaussian) pairs coalesced.
 //  k_ranges      [start, end) of every tile in the tile-sorted pairs.
-//  k_blend       one 256-thread workgroup per 16x16 tile; Gaussians staged
-//                in LDS in batches of 256; per pixel front-to-back blending
-//                until transmittance would fall below 1e-4; the workgroup
-//                leaves when every pixel is done.
+//  k_blend       one 256-thread workgroup per 16x16 tile, one pixel per
+//                thread; Gaussians staged in LDS in batches of 256; per pixel
+//                front-to-back
+//                blending until transmittance would fall below 1e-4; the wave
+//                leaves when all its pixels are done.
 #include "kcommon.h"
 #include "vm3dgs_impl.h"
 
@@ -257,15 +258,22 @@ __global__ void k_ranges(const uint32_t* __restrict__ key, uint32_t n, uint2* __
     if (i == n - 1 || key[i + 1] != t) ranges[t].y = i + 1;
 }
 
+// One 256-thread workgroup per 16x16 tile, one pixel per thread.  Gaussians
+// are staged in LDS in batches of 256; a wave stops when its 64 pixels are
+// done, the workgroup when all 256 are.  STATS counts, per tile, the
+// pixel-Gaussian evaluations and those that reached the alpha computation
+// (the algorithmic work of the kernel).
 constexpr int BL_NT = TILE * TILE;
 
+template <bool STATS>
 __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ ranges, const uint32_t* __restrict__ pval,
                                                  const float2* __restrict__ xy, const float4* __restrict__ conic,
                                                  const float4* __restrict__ rgb, int W, int H, int TX, int TY,
-                                                 float* __restrict__ image) {
+                                                 float* __restrict__ image, uint2* __restrict__ stats) {
     __shared__ float2 s_xy[BL_NT];
     __shared__ float4 s_co[BL_NT];
     __shared__ float4 s_rgb[BL_NT];
+    __shared__ uint32_t s_st[2][BL_NT / WAVE];
     const uint32_t tile = blockIdx.x;
     const uint32_t per_view = (uint32_t)(TX * TY);
     const uint32_t view = tile / per_view;
@@ -278,6 +286,7 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
     const uint2 rg = ranges[tile];
     const float fpx = (float)px, fpy = (float)py;
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+    uint32_t n_eval = 0, n_alpha = 0;
     for (uint32_t base = rg.x; base < rg.y; base += BL_NT) {
         if (__syncthreads_count(done ? 1 : 0) == BL_NT) break;
         const uint32_t j = base + threadIdx.x;
@@ -295,9 +304,11 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
             const float dx = p.x - fpx, dy = p.y - fpy;
             const float q = fmaf(co.x * dx, dx, (co.z * dy) * dy);
             const float power = fmaf(-0.5f, q, -((co.y * dx) * dy));
-            // exp(-5.55) < 1/255 and opacity <= 1: such terms are skipped by the
-            // alpha test anyway, so their exp is not evaluated
+            if (STATS) ++n_eval;
+            // exp(-5.55) < 1/255 and opacity <= 1: such terms fail the alpha
+            // test, so their exp is not evaluated
             if (power > 0.0f || power < -5.55f) continue;
+            if (STATS) ++n_alpha;
             const float alpha = fminf(0.99f, co.w * vm_exp(power));
             if (alpha < 1.0f / 255.0f) continue;
             const float Tn = T * (1.0f - alpha);
@@ -313,6 +324,16 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
     if (inside) {
         float* o = image + (((size_t)view * H + py) * W + px) * 3;
         o[0] = C0; o[1] = C1; o[2] = C2;
+    }
+    if (STATS) {
+        const uint32_t e = wave_sum(n_eval), a = wave_sum(n_alpha);
+        if (__lane_id() == 0) { s_st[0][threadIdx.x / WAVE] = e; s_st[1][threadIdx.x / WAVE] = a; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t se = 0, sa = 0;
+            for (int i = 0; i < BL_NT / WAVE; ++i) { se += s_st[0][i]; sa += s_st[1][i]; }
+            stats[tile] = make_uint2(se, sa);
+        }
     }
 }
 
@@ -348,9 +369,14 @@ void launch_ranges(hipStream_t st, const uint32_t* pkey, uint32_t n_pairs, uint2
 }
 
 void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* pval, const float2* xy, const float4* conic,
-                  const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image) {
+                  const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image, uint2* stats) {
     const uint32_t n_tiles = (uint32_t)(TX * TY * n_views);
-    hipLaunchKernelGGL(k_blend, dim3(n_tiles), dim3(BL_NT), 0, st, ranges, pval, xy, conic, rgb, W, H, TX, TY, image);
+    if (stats)
+        hipLaunchKernelGGL(k_blend<true>, dim3(n_tiles), dim3(BL_NT), 0, st, ranges, pval, xy, conic, rgb, W, H, TX,
+                           TY, image, stats);
+    else
+        hipLaunchKernelGGL(k_blend<false>, dim3(n_tiles), dim3(BL_NT), 0, st, ranges, pval, xy, conic, rgb, W, H, TX,
+                           TY, image, stats);
 }
 
 }  // namespace vm

@@ -2,13 +2,18 @@
 //
 //  k_frustum       page bounding sphere vs near plane and the four side planes
 //  k_rays          per ID-buffer pixel: reciprocal world direction of the
-//                  ray through the pixel centre (view depth = ray parameter)
-//  k_proxy_raster  the proxy boxes of candidate pages, rasterised at pixel
-//                  centres (slab test); 64-bit atomicMin of
-//                  (depth bits << 32 | page + 1): nearest wins, independent
-//                  of order.  Work is balanced inside a block by a prefix sum
-//                  of the boxes' pixel rectangles.
-//  k_reduce        per pixel: nearest depth per page (Sec. 5.1.1 reduction)
+//                  ray through the pixel centre (view depth = ray parameter);
+//                  the buffer spans the image widened by a guard band of G
+//                  pixels per edge, the frustum planes likewise
+//  k_cell_rects    per (view, proxy box of a candidate page): its conservative
+//                  pixel rectangle in the ID buffer and area
+//  k_raster_items  one thread per (box, pixel) item, balanced over the whole
+//                  grid by a prefix sum of the areas: the ray through the
+//                  pixel centre against the box (slab test); 64-bit atomicMin
+//                  of (depth bits << 32 | page + 1): nearest wins whatever
+//                  the order
+//  k_reduce        per pixel: nearest depth per page (Sec. 5.1.1 reduction),
+//                  one atomic per page per wave
 //  k_links         a directly seen page pushes its depth to its linked pages
 //  k_requests      LOD level from the projected page radius, request keys
 //                  (class, depth, page)
@@ -20,7 +25,7 @@ namespace vmk {
 using vm::CamK;
 
 __global__ void k_frustum(const float4* __restrict__ sph, int n_pg, const CamK* __restrict__ cams, int n_views,
-                          int W, int H, uint8_t* __restrict__ cand, uint32_t* __restrict__ counters) {
+                          int W, int H, float G, uint8_t* __restrict__ cand, uint32_t* __restrict__ counters) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)n_pg * n_views) return;
     const int v = (int)(i / n_pg);
@@ -30,8 +35,8 @@ __global__ void k_frustum(const float4* __restrict__ sph, int n_pg, const CamK* 
     const float3 q = view_xform(c.V, s.x, s.y, s.z);
     const float r = s.w;
     bool in = q.z + r > c.znear;
-    const float tl = c.cx / c.fx, tr = ((float)W - c.cx) / c.fx;
-    const float tt = c.cy / c.fy, tb = ((float)H - c.cy) / c.fy;
+    const float tl = (c.cx + G) / c.fx, tr = (((float)W + G) - c.cx) / c.fx;
+    const float tt = (c.cy + G) / c.fy, tb = (((float)H + G) - c.cy) / c.fy;
     const float kl = sqrtf(1.0f + tl * tl), kr = sqrtf(1.0f + tr * tr);
     const float kt = sqrtf(1.0f + tt * tt), kb = sqrtf(1.0f + tb * tb);
     in = in && (q.x + tl * q.z >= -(r * kl));
@@ -43,7 +48,7 @@ __global__ void k_frustum(const float4* __restrict__ sph, int n_pg, const CamK* 
     if (__lane_id() == 0 && b) atomicAdd(&counters[vm::C_CAND], (uint32_t)__popcll(b));
 }
 
-__global__ void k_rays(const CamK* __restrict__ cams, int n_views, int W, int H, int Wv, int Hv,
+__global__ void k_rays(const CamK* __restrict__ cams, int n_views, int W, int H, float G, int Wv, int Hv,
                        float4* __restrict__ rays) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t npx = (int64_t)Wv * Hv;
@@ -52,9 +57,10 @@ __global__ void k_rays(const CamK* __restrict__ cams, int n_views, int W, int H,
     const int pix = (int)(i - v * npx);
     const int px = pix % Wv, py = pix / Wv;
     const CamK& c = cams[v];
-    const float sx = (float)W / (float)Wv, sy = (float)H / (float)Hv;
-    const float dcx = (((float)px + 0.5f) * sx - c.cx) / c.fx;
-    const float dcy = (((float)py + 0.5f) * sy - c.cy) / c.fy;
+    const float sx = ((float)W + 2.0f * G) / (float)Wv, sy = ((float)H + 2.0f * G) / (float)Hv;
+    const float xc = ((float)px + 0.5f) * sx - G, yc = ((float)py + 0.5f) * sy - G;
+    const float dcx = (xc - c.cx) / c.fx;
+    const float dcy = (yc - c.cy) / c.fy;
     float inv[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -66,7 +72,7 @@ __global__ void k_rays(const CamK* __restrict__ cams, int n_views, int W, int H,
 }
 
 // conservative inclusive pixel rectangle of a world box in the ID buffer
-__device__ bool box_rect(const CamK& c, int W, int H, int Wv, int Hv, const float* b, int4* r) {
+__device__ bool box_rect(const CamK& c, int W, int H, float G, int Wv, int Hv, const float* b, int4* r) {
     float vmin[3] = {INFINITY, INFINITY, INFINITY}, vmax[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -81,9 +87,9 @@ __device__ bool box_rect(const CamK& c, int W, int H, int Wv, int Hv, const floa
     const float xh = fmaxf(fmaxf(vmin[0] / z0, vmin[0] / z1), fmaxf(vmax[0] / z0, vmax[0] / z1));
     const float yl = fminf(fminf(vmin[1] / z0, vmin[1] / z1), fminf(vmax[1] / z0, vmax[1] / z1));
     const float yh = fmaxf(fmaxf(vmin[1] / z0, vmin[1] / z1), fmaxf(vmax[1] / z0, vmax[1] / z1));
-    const float sx = (float)W / (float)Wv, sy = (float)H / (float)Hv;
-    float fx0 = floorf((c.fx * xl + c.cx) / sx) - 1.0f, fx1 = floorf((c.fx * xh + c.cx) / sx) + 1.0f;
-    float fy0 = floorf((c.fy * yl + c.cy) / sy) - 1.0f, fy1 = floorf((c.fy * yh + c.cy) / sy) + 1.0f;
+    const float sx = ((float)W + 2.0f * G) / (float)Wv, sy = ((float)H + 2.0f * G) / (float)Hv;
+    float fx0 = floorf(((c.fx * xl + c.cx) + G) / sx) - 1.0f, fx1 = floorf(((c.fx * xh + c.cx) + G) / sx) + 1.0f;
+    float fy0 = floorf(((c.fy * yl + c.cy) + G) / sy) - 1.0f, fy1 = floorf(((c.fy * yh + c.cy) + G) / sy) + 1.0f;
     fx0 = fmaxf(fx0, 0.0f); fy0 = fmaxf(fy0, 0.0f);
     fx1 = fminf(fx1, (float)(Wv - 1)); fy1 = fminf(fy1, (float)(Hv - 1));
     if (!(fx0 <= fx1) || !(fy0 <= fy1)) return false;
@@ -93,63 +99,84 @@ __device__ bool box_rect(const CamK& c, int W, int H, int Wv, int Hv, const floa
 
 constexpr int PR_NT = 256;
 
-__global__ __launch_bounds__(PR_NT) void k_proxy_raster(const float4* __restrict__ lo4, const float4* __restrict__ hi4,
-                                                       int64_t nc, const uint8_t* __restrict__ cand, int n_pg,
-                                                       const CamK* __restrict__ cams, int n_views, int W, int H,
-                                                       int Wv, int Hv, const float4* __restrict__ rays,
-                                                       unsigned long long* __restrict__ idbuf) {
-    __shared__ uint32_t s_end[PR_NT];   // inclusive prefix of rectangle areas
-    __shared__ int4 s_rect[PR_NT];
-    __shared__ float s_box[PR_NT][6];
-    __shared__ uint32_t s_page[PR_NT];
-    __shared__ uint32_t scan_sh[PR_NT / WAVE];
-    const int64_t c = (int64_t)blockIdx.x * PR_NT + threadIdx.x;
-    float b[6] = {0, 0, 0, 0, 0, 0};
-    uint32_t page = 0;
-    if (c < nc) {
-        const float4 l = lo4[c], h = hi4[c];
-        b[0] = l.x; b[1] = l.y; b[2] = l.z; b[3] = h.x; b[4] = h.y; b[5] = h.z;
-        page = __float_as_uint(l.w);
+// per (view, cell): the pixel rectangle of a candidate page's box and its area
+__global__ void k_cell_rects(const float4* __restrict__ lo4, const float4* __restrict__ hi4, int64_t nc,
+                             const uint8_t* __restrict__ cand, int n_pg, const CamK* __restrict__ cams, int n_views,
+                             int W, int H, float G, int Wv, int Hv, int4* __restrict__ rects,
+                             uint32_t* __restrict__ area) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nc * n_views) return;
+    const int v = (int)(i / nc);
+    const int64_t c = i - (int64_t)v * nc;
+    const float4 l = lo4[c], h = hi4[c];
+    const uint32_t page = __float_as_uint(l.w);
+    int4 r = make_int4(0, 0, -1, -1);
+    uint32_t a = 0;
+    if (cand[(int64_t)v * n_pg + page]) {
+        const float b[6] = {l.x, l.y, l.z, h.x, h.y, h.z};
+        if (box_rect(cams[v], W, H, G, Wv, Hv, b, &r)) a = (uint32_t)((r.z - r.x + 1) * (r.w - r.y + 1));
     }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) s_box[threadIdx.x][k] = b[k];
-    s_page[threadIdx.x] = page;
+    rects[i] = r;
+    area[i] = a;
+}
+
+// one (cell, pixel) item per thread and step: the ray through the pixel centre
+// against the cell's box.  Thread 0 brackets the slots holding the block's
+// items; each thread then finds its slot by binary search inside the bracket.
+__global__ __launch_bounds__(PR_NT) void k_raster_items(const float4* __restrict__ lo4, const float4* __restrict__ hi4,
+                                                       int64_t nc, const CamK* __restrict__ cams, int Wv, int Hv,
+                                                       const int4* __restrict__ rects, const uint32_t* __restrict__ offs,
+                                                       const uint32_t* __restrict__ total_p, int64_t n_slots,
+                                                       const float4* __restrict__ rays,
+                                                       unsigned long long* __restrict__ idbuf) {
+    __shared__ int64_t s_lo, s_hi;
+    const uint32_t total = *total_p;      // = offs[n_slots]
     const int64_t npx = (int64_t)Wv * Hv;
-    for (int v = 0; v < n_views; ++v) {
-        const CamK& cam = cams[v];
-        uint32_t area = 0;
-        int4 r = make_int4(0, 0, -1, -1);
-        if (c < nc && cand[(int64_t)v * n_pg + page]) {
-            if (box_rect(cam, W, H, Wv, Hv, b, &r)) area = (uint32_t)((r.z - r.x + 1) * (r.w - r.y + 1));
-        }
-        uint32_t total;
-        const uint32_t ex = block_excl_scan<PR_NT>(area, scan_sh, &total);
-        s_end[threadIdx.x] = ex + area;
-        s_rect[threadIdx.x] = r;
-        __syncthreads();
-        const float o0 = cam.pos[0], o1 = cam.pos[1], o2 = cam.pos[2];
-        for (uint32_t i = threadIdx.x; i < total; i += PR_NT) {
-            int lo = 0, hi = PR_NT - 1;
+    for (uint64_t b0 = (uint64_t)blockIdx.x * PR_NT; b0 < total; b0 += (uint64_t)gridDim.x * PR_NT) {
+        if (threadIdx.x == 0) {
+            // slot of item x: the first s with offs[s + 1] > x (it has area > 0)
+            int64_t lo = 0, hi = n_slots - 1;
             while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (s_end[mid] > i) hi = mid; else lo = mid + 1;
+                const int64_t mid = (lo + hi) >> 1;
+                if (offs[mid + 1] > b0) hi = mid; else lo = mid + 1;
             }
-            const int4 rr = s_rect[lo];
+            s_lo = lo;
+            const uint64_t last = min((uint64_t)total - 1, b0 + PR_NT - 1);
+            int64_t l2 = lo, h2 = n_slots - 1;
+            while (l2 < h2) {
+                const int64_t mid = (l2 + h2) >> 1;
+                if (offs[mid + 1] > last) h2 = mid; else l2 = mid + 1;
+            }
+            s_hi = l2;
+        }
+        __syncthreads();
+        const uint64_t item = b0 + threadIdx.x;
+        if (item < total) {
+            int64_t a = s_lo, bnd = s_hi;
+            while (a < bnd) {
+                const int64_t mid = (a + bnd) >> 1;
+                if (offs[mid + 1] > item) bnd = mid; else a = mid + 1;
+            }
+            const int64_t slot = a;
+            const int v = (int)(slot / nc);
+            const int64_t c = slot - (int64_t)v * nc;
+            const int4 rr = rects[slot];
             const uint32_t w = (uint32_t)(rr.z - rr.x + 1);
-            const uint32_t k = i - (s_end[lo] - w * (uint32_t)(rr.w - rr.y + 1));
+            const uint32_t k = (uint32_t)(item - offs[slot]);
             const int px = rr.x + (int)(k % w), py = rr.y + (int)(k / w);
+            const CamK& cam = cams[v];
             const float4 inv = rays[v * npx + (int64_t)py * Wv + px];
-            const float* bb = s_box[lo];
-            float ta = (bb[0] - o0) * inv.x, tb = (bb[3] - o0) * inv.x;
+            const float4 l4 = lo4[c], h4 = hi4[c];
+            float ta = (l4.x - cam.pos[0]) * inv.x, tb = (h4.x - cam.pos[0]) * inv.x;
             float t0 = fminf(ta, tb), t1 = fmaxf(ta, tb);
-            ta = (bb[1] - o1) * inv.y; tb = (bb[4] - o1) * inv.y;
+            ta = (l4.y - cam.pos[1]) * inv.y; tb = (h4.y - cam.pos[1]) * inv.y;
             t0 = fmaxf(t0, fminf(ta, tb)); t1 = fminf(t1, fmaxf(ta, tb));
-            ta = (bb[2] - o2) * inv.z; tb = (bb[5] - o2) * inv.z;
+            ta = (l4.z - cam.pos[2]) * inv.z; tb = (h4.z - cam.pos[2]) * inv.z;
             t0 = fmaxf(t0, fminf(ta, tb)); t1 = fminf(t1, fmaxf(ta, tb));
             if (t0 <= t1 && t1 > cam.znear) {
                 const float d = fmaxf(t0, cam.znear);
                 const unsigned long long key =
-                    ((unsigned long long)__float_as_uint(d) << 32) | (unsigned long long)(s_page[lo] + 1u);
+                    ((unsigned long long)__float_as_uint(d) << 32) | (unsigned long long)(__float_as_uint(l4.w) + 1u);
                 atomicMin(&idbuf[v * npx + (int64_t)py * Wv + px], key);
             }
         }
@@ -159,11 +186,22 @@ __global__ __launch_bounds__(PR_NT) void k_proxy_raster(const float4* __restrict
 
 __global__ void k_reduce(const unsigned long long* __restrict__ idbuf, int64_t n, uint32_t* __restrict__ req_direct) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const unsigned long long k = idbuf[i];
-    if (k == NONE64) return;
+    const unsigned long long k = i < n ? idbuf[i] : NONE64;
+    const bool valid = k != NONE64;
     const uint32_t page = (uint32_t)(k & 0xffffffffull) - 1u;
-    atomicMin(&req_direct[page], (uint32_t)(k >> 32));
+    const uint32_t d = (uint32_t)(k >> 32);
+    // neighbouring pixels mostly show the same page: one atomic per page per wave
+    uint64_t active = __ballot(valid);
+    while (active) {
+        const int leader = __ffsll((unsigned long long)active) - 1;
+        const uint32_t lp = __shfl(page, leader, WAVE);
+        const bool mine = valid && page == lp;
+        uint32_t m = mine ? d : NONE32;
+#pragma unroll
+        for (int o = WAVE / 2; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor(m, o, WAVE));
+        if ((int)__lane_id() == leader) atomicMin(&req_direct[lp], m);
+        active &= ~__ballot(mine);
+    }
 }
 
 __global__ void k_links(const uint32_t* __restrict__ req_direct, const int32_t* __restrict__ ls,
@@ -244,12 +282,18 @@ void launch_visibility(hipStream_t st, const VisArgs& a) {
     launch_fill_u32(st, a.req_direct, a.n_pg, NONE32);
     launch_fill_u32(st, a.req_link, a.n_pg, NONE32);
     hipLaunchKernelGGL(k_frustum, dim3(nblk((uint64_t)a.n_pg * a.n_views, 256)), dim3(256), 0, st, a.spheres, a.n_pg,
-                       a.cams, a.n_views, a.W, a.H, a.cand, a.counters);
-    hipLaunchKernelGGL(k_rays, dim3(nblk(npx * a.n_views, 256)), dim3(256), 0, st, a.cams, a.n_views, a.W, a.H, a.Wv,
-                       a.Hv, a.rays);
-    if (a.nc > 0)
-        hipLaunchKernelGGL(k_proxy_raster, dim3(nblk(a.nc, PR_NT)), dim3(PR_NT), 0, st, a.cell_lo, a.cell_hi, a.nc,
-                           a.cand, a.n_pg, a.cams, a.n_views, a.W, a.H, a.Wv, a.Hv, (const float4*)a.rays, a.idbuf);
+                       a.cams, a.n_views, a.W, a.H, a.guard, a.cand, a.counters);
+    hipLaunchKernelGGL(k_rays, dim3(nblk(npx * a.n_views, 256)), dim3(256), 0, st, a.cams, a.n_views, a.W, a.H,
+                       a.guard, a.Wv, a.Hv, a.rays);
+    if (a.nc > 0) {
+        const int64_t slots = a.nc * a.n_views;
+        hipLaunchKernelGGL(k_cell_rects, dim3(nblk(slots, 256)), dim3(256), 0, st, a.cell_lo, a.cell_hi, a.nc, a.cand,
+                           a.n_pg, a.cams, a.n_views, a.W, a.H, a.guard, a.Wv, a.Hv, a.cell_rects, a.cell_area);
+        scan_lb(st, *a.sw, a.cell_area, (uint64_t)slots, a.cell_offs, a.cell_offs + slots);
+        hipLaunchKernelGGL(k_raster_items, dim3(2048), dim3(PR_NT), 0, st, a.cell_lo, a.cell_hi, a.nc, a.cams, a.Wv,
+                           a.Hv, (const int4*)a.cell_rects, (const uint32_t*)a.cell_offs,
+                           (const uint32_t*)(a.cell_offs + slots), slots, (const float4*)a.rays, a.idbuf);
+    }
     hipLaunchKernelGGL(k_reduce, dim3(nblk(npx * a.n_views, 256)), dim3(256), 0, st,
                        (const unsigned long long*)a.idbuf, npx * a.n_views, a.req_direct);
     if (a.use_links)

@@ -47,6 +47,37 @@ int radix_sort_u32(hipStream_t st, uint32_t* keys[2], uint32_t* vals[2], uint32_
 int radix_sort_u64(hipStream_t st, uint64_t* keys[2], uint32_t* vals[2], uint32_t n, int begin_bit, int end_bit,
                    uint32_t* temp);
 
+// Workspace of the single-pass sorts and scans of one frame.  reset() is
+// called when the frame's zero-fill of `zero_base` (counters, histograms,
+// tickets) has been enqueued; every launch then takes the next histogram
+// block, ticket and epoch.
+struct SortWork {
+    uint64_t* status = nullptr;   // look-back status words (no clearing needed)
+    uint32_t* hist = nullptr;     // [kMaxHist][256], zeroed per frame
+    uint32_t* tickets = nullptr;  // [kMaxTickets], zeroed per frame
+    uint32_t* err = nullptr;      // look-back spin overrun flag
+    static constexpr int kMaxHist = 32;
+    static constexpr int kMaxTickets = 64;
+    int hist_used = 0, tickets_used = 0;
+    uint32_t epoch = 0;
+    void reset() { hist_used = 0; tickets_used = 0; }
+    uint32_t* next_hist(int n) {
+        uint32_t* p = hist + 256 * (size_t)hist_used;
+        hist_used += n;
+        return p;
+    }
+    uint32_t* next_ticket() { return tickets + tickets_used++; }
+    uint32_t next_epoch() { epoch = (epoch + 1) & 0x3fffffffu; if (epoch == 0) epoch = 1; return epoch; }
+};
+size_t lb_status_words(uint64_t n_keys);
+int onesweep_u32(hipStream_t st, SortWork& w, uint32_t* keys[2], uint32_t* vals[2], uint32_t n, int begin_bit,
+                 int end_bit);
+int onesweep_u64(hipStream_t st, SortWork& w, uint64_t* keys[2], uint32_t* vals[2], uint32_t n, int begin_bit,
+                 int end_bit);
+void scan_lb(hipStream_t st, SortWork& w, const uint32_t* in, uint64_t n, uint32_t* out, uint32_t* total);
+void scan_lb_gather(hipStream_t st, SortWork& w, const uint32_t* a, const uint32_t* idx, uint64_t n, uint32_t* out,
+                    uint32_t* total);
+
 // ----------------------------------------------------------- kernels' camera
 struct CamK {
     float V[12];       // rows of the world->camera transform
@@ -77,10 +108,13 @@ struct VisArgs {
     const float4* cell_lo; const float4* cell_hi; int64_t nc;
     const int32_t* link_start; const int32_t* link_dst; int use_links;
     const CamK* cams; int n_views;
-    int W, H, Wv, Hv, L; float tau; float fy_max;
+    int W, H, Wv, Hv, L; float tau; float fy_max; float guard;
     uint8_t* cand; float4* rays; unsigned long long* idbuf;
     uint32_t* req_direct; uint32_t* req_link; int8_t* page_level;
     uint64_t* req_keys; uint32_t* counters;
+    int4* cell_rects; uint32_t* cell_area; uint32_t* cell_offs;  // [views*nc], [views*nc], [views*nc + 1]
+    uint32_t* scan_temp;
+    SortWork* sw;
 };
 void launch_visibility(hipStream_t st, const VisArgs& a);
 
@@ -109,7 +143,7 @@ void launch_emit(hipStream_t st, const uint32_t* order, const uint32_t* offsets,
                  uint32_t n_render, int TX, int TY, uint32_t* pkey, uint32_t* pval, uint32_t cap);
 void launch_ranges(hipStream_t st, const uint32_t* pkey, uint32_t n_pairs, uint2* ranges, uint32_t n_tiles);
 void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* pval, const float2* xy, const float4* conic,
-                  const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image);
+                  const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image, uint2* stats);
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v);
 void launch_fill_u64(hipStream_t st, unsigned long long* p, uint64_t n, unsigned long long v);
 

@@ -27,12 +27,31 @@ def test_every_declared_symbol_is_exported():
     assert not missing, missing
 
 
-def test_struct_sizes_match_header_layout():
-    # the binding's structures must have the C layout (8-byte aligned pointers)
-    assert C.sizeof(pkg.vm3dgs_options) == 72
-    assert C.sizeof(pkg.vm3dgs_camera) == 96
-    assert C.sizeof(pkg.vm3dgs_stats) == 112
-    assert C.sizeof(pkg.vm3dgs_scene) == 48
+def test_struct_layout_matches_c_compiler(tmp_path):
+    """The binding's structures have the sizes and field offsets the C compiler
+    gives the header's structures."""
+    import subprocess
+    fields = {"vm3dgs_options": ["img_w", "flags", "stream_render", "stream_copy", "pair_capacity"],
+              "vm3dgs_camera": ["view", "cam_pos", "fx", "znear"],
+              "vm3dgs_stats": ["candidates", "render_gaussians", "blend_alphas", "ms_visibility", "ms_total"],
+              "vm3dgs_scene": ["n", "sh"],
+              "vm3dgs_frame_out": ["requests", "n_requests", "missing", "n_missing", "stats"]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "vm3dgs.h"', "int main(void) {"]
+    for s, fs in fields.items():
+        lines.append(f'printf("{s} %zu\\n", sizeof({s}));')
+        for f in fs:
+            lines.append(f'printf("{s}.{f} %zu\\n", offsetof({s}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split("\n") if l)
+    for s, fs in fields.items():
+        cls = getattr(pkg, s)
+        assert C.sizeof(cls) == int(out[s]), s
+        for f in fs:
+            assert getattr(cls, f).offset == int(out[f"{s}.{f}"]), (s, f)
 
 
 def test_options_default():

@@ -166,12 +166,13 @@ def test_idbuf_closed_form_coverage():
     sc = _scene_from_points(pts, None, 9)
     osc = oracle.OracleScene(sc, 9, 1, 4.0, 2.0)  # one 4 m cell holds the whole plate
     assert osc.get("n_cells")[0] == 1
-    vm = oracle.OracleVM(osc, 1, (W, H), (Wv, Hv))
+    G = 16.0                               # guard band: the buffer spans [-G, W+G) x [-G, H+G)
+    vm = oracle.OracleVM(osc, 1, (W, H), (Wv, Hv), guard_px=G)
     vm.visibility([cam])
     ib = vm.get("idbuf").reshape(Hv, Wv)
-    sx = W / Wv
-    px = (np.arange(Wv) + 0.5) * sx
-    py = (np.arange(Hv) + 0.5) * sx
+    sx, sy = (W + 2 * G) / Wv, (H + 2 * G) / Hv
+    px = (np.arange(Wv) + 0.5) * sx - G
+    py = (np.arange(Hv) + 0.5) * sy - G
     xs = (px - cam.cx) / cam.fx * 5.0
     ys = (py - cam.cy) / cam.fy * 5.0
     cover = (np.abs(ys)[:, None] <= 1.0) & (np.abs(xs)[None, :] <= 1.0)
@@ -228,12 +229,30 @@ def test_frustum_planes():
     sc = synth.Scene(pts, np.full((n, 3), 0.1, np.float32), np.tile(np.array([[1, 0, 0, 0]], np.float32), (n, 1)),
                      np.full(n, 0.9, np.float32), np.zeros((n, 16, 3), np.float32))
     osc = oracle.OracleScene(sc, 1, 1, 1.0, 0.0)
-    vm = oracle.OracleVM(osc, 4, (W, H), (40, 30), use_links=False)
+    vm = oracle.OracleVM(osc, 4, (W, H), (40, 30), use_links=False, guard_px=0.0)
     vm.visibility([cam])
     cand = vm.get("cand")
     perm = osc.get("perm")
     for page in range(n):
         assert bool(cand[page]) == expect[perm[page]], (page, pts[perm[page]])
+
+
+def test_guard_band_frustum():
+    """With a guard band of G pixels the side planes pass through the image
+    edges widened by G: a sphere 2.5 G-pixels outside is dropped with no
+    band, kept with G = 3 x that distance."""
+    W, H = 160, 120
+    cam = _cam_identity(W, H)
+    z = 10.0
+    x = ((W + 40.0) - cam.cx) / cam.fx * z       # 40 px right of the image edge
+    pts = np.array([[x, 0.0, z]], np.float32)
+    sc = synth.Scene(pts, np.full((1, 3), 0.01, np.float32), np.array([[1, 0, 0, 0]], np.float32),
+                     np.full(1, 0.9, np.float32), np.zeros((1, 16, 3), np.float32))
+    osc = oracle.OracleScene(sc, 1, 1, 1.0, 0.0)
+    for G, expect in [(0.0, 0), (16.0, 0), (64.0, 1)]:
+        vm = oracle.OracleVM(osc, 1, (W, H), (40, 30), use_links=False, guard_px=G)
+        vm.visibility([cam])
+        assert vm.get("cand")[0] == expect, G
 
 
 def test_idbuf_rect_equals_brute_force(clusters):
