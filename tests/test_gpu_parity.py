@@ -170,3 +170,85 @@ def test_padding_page_and_tiny_pool():
         ovm.frame([cam])
         compare_frame(r, ovm, out, 1, tag=f"tiny pool {k}")
     r.close()
+
+
+def test_half_form_clusters():
+    """Pages stored with SH in bf16 and scale / rotation / opacity in fp16:
+    the kernels decode them exactly, so the frame matches the oracle run on
+    the same rounded attributes."""
+    sc = synth.scene_clusters(0)
+    osc = oracle.OracleScene(sc, 256, 1, 0.5, 2.0, attr_format=1)
+    cams = synth.orbit()
+    r = _renderer(sc, 256, 64, (320, 240), (80, 60), 0.5, attr_format=1)
+    ovm = oracle.OracleVM(osc, 64, (320, 240), (80, 60))
+    for k in (0, 3, 5):
+        _, out = r.frame([cams[k]])
+        ovm.frame([cams[k]])
+        assert out.stats.bytes_copied % 124 == 0
+        compare_frame(r, ovm, out, 1, tag=f"half {k}")
+    r.close()
+
+
+def test_eight_views_shared_pool(clusters):
+    """Eight cameras per call share one pool: requests are the union, per
+    page the nearest depth over the views; tiles carry the view index."""
+    sc, osc = clusters
+    cams = synth.orbit(8, 25.0, 160, 120)
+    r = _renderer(sc, 256, 128, (160, 120), (40, 30), 0.5, max_views=8)
+    ovm = oracle.OracleVM(osc, 128, (160, 120), (40, 30))
+    _, out = r.frame(cams)
+    ovm.frame(cams)
+    compare_frame(r, ovm, out, 8, tag="eight views")
+    r.close()
+
+
+@pytest.mark.slow
+def test_terrain6m_full_size_sampled():
+    """The bench workload at full size in the bench's launch configuration:
+    visibility, page table and preprocess compared in full for three frames,
+    the pair lists, ranges and pixels of 48 sampled tiles (ragged last tile
+    row included) for the third."""
+    import paper_2506_19415_amd as pkg
+    sc = synth.scene_terrain(0)
+    cams = synth.path_terrain(sc)
+    print("terrain6m generated", flush=True)
+    r = pkg.Renderer(sc, 1024, 1465, img=(1920, 1080), idbuf=(240, 135), cell=1.0, full_scene=True)
+    osc = oracle.OracleScene(sc, 1024, 1, 1.0, 2.0)
+    ovm = oracle.OracleVM(osc, 1465, (1920, 1080), (240, 135))
+    TX, TY = 120, 68
+    rng = np.random.default_rng(0)
+    tiles = np.concatenate([rng.choice(TX * (TY - 1), 40, replace=False), TX * (TY - 1) + rng.choice(TX, 8, replace=False)])
+    mask = np.zeros(TX * TY, np.uint8)
+    mask[tiles] = 1
+    for k in range(3):
+        _, out = r.frame([cams[k]])
+        ovm.frame([cams[k]], tile_mask=mask if k == 2 else np.zeros_like(mask))
+        print(f"terrain6m frame {k}: {out.n_requests} requests, {out.stats.pairs} pairs", flush=True)
+        g = r.get
+        for name, dt in [("cand", np.uint8), ("idbuf", np.uint64), ("req_direct", np.uint32), ("req_link", np.uint32),
+                         ("slot_level", np.int8), ("last_used", np.int32), ("sub_vpage", np.int32), ("v2p", np.int32),
+                         ("copies", np.int64)]:
+            assert np.array_equal(g(name, dt), ovm.get(name)), (k, name)
+        req = np.ctypeslib.as_array(out.requests, (out.n_requests,))
+        assert np.array_equal(req, ovm.get("req_page")), k
+        pf, pi = g("pp_float", np.float32).reshape(-1, 10), g("pp_int", np.int32).reshape(-1, 6)
+        of, oi = ovm.get("pp_float").reshape(-1, 10), ovm.get("pp_int").reshape(-1, 6)
+        assert np.array_equal(pi[:, 0], oi[:, 0]), k
+        vis = oi[:, 0] == 0
+        assert np.array_equal(pi[vis], oi[vis]), k
+        assert np.array_equal(pf[vis, :3].view(np.uint32), of[vis, :3].view(np.uint32)), k
+    keys, vals = g("keys", np.uint32), g("vals", np.uint32)
+    ranges = g("ranges", np.uint32).reshape(-1, 2)
+    okeys, ovals = ovm.get("keys"), ovm.get("vals")
+    orng = ovm.get("ranges").reshape(-1, 2)
+    img = r.image[0].cpu().numpy()
+    ref = ovm.image(1)[0]
+    for t in tiles:
+        s, e = ranges[t]
+        os_, oe = orng[t]
+        assert np.array_equal(vals[s:e], ovals[os_:oe]), t
+        assert np.all(keys[s:e] == t)
+        ty, tx = divmod(int(t), TX)
+        blk = (slice(ty * 16, min(ty * 16 + 16, 1080)), slice(tx * 16, tx * 16 + 16))
+        assert np.abs(img[blk] - ref[blk]).max() <= 1e-3, t
+    r.close()
