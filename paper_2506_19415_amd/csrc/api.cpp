@@ -53,6 +53,11 @@ struct vm3dgs {
     CopyCmd* d_copies = nullptr; CopyCmd* h_copies = nullptr; int32_t* d_copy_id = nullptr;
     int32_t* d_missing = nullptr; int32_t* h_missing = nullptr;
     uint64_t* h_keys = nullptr;
+    // several LOD levels: candidate lists and request order of the multi-kernel page table
+    uint64_t* d_lkeys_alt = nullptr; uint64_t* d_wkeys[2] = {nullptr, nullptr};
+    uint64_t* d_ck[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+    uint32_t* d_lflag = nullptr; uint32_t* d_lpos = nullptr; int32_t* d_fresh = nullptr;
+    int8_t* d_lvl_out = nullptr; int8_t* h_lvl = nullptr;
     RenderEntry* d_rlist = nullptr; RenderEntry* d_rlist_full = nullptr;
     // splat
     uint64_t cap_render = 0;
@@ -148,6 +153,9 @@ void free_all(vm3dgs* c) {
     dfree(c->d_req_sub); dfree(c->d_slot_req); dfree(c->d_miss);
     dfree(c->d_copies); hfree(c->h_copies); dfree(c->d_copy_id); dfree(c->d_missing); hfree(c->h_missing);
     hfree(c->h_keys);
+    dfree(c->d_lkeys_alt); dfree(c->d_wkeys[0]); dfree(c->d_wkeys[1]);
+    for (auto& q : c->d_ck) { dfree(q[0]); dfree(q[1]); }
+    dfree(c->d_lflag); dfree(c->d_lpos); dfree(c->d_fresh); dfree(c->d_lvl_out); hfree(c->h_lvl);
     dfree(c->d_rlist); dfree(c->d_rlist_full);
     dfree(c->d_xy); dfree(c->d_conic); dfree(c->d_rgb); dfree(c->d_depth); dfree(c->d_rect); dfree(c->d_tiles);
     for (int i = 0; i < 2; ++i) { dfree(c->d_dkey[i]); dfree(c->d_dval[i]); dfree(c->d_pkey[i]); dfree(c->d_pval[i]); }
@@ -164,7 +172,8 @@ constexpr int ZB_CTR = 0, ZB_ERR = C_NCOUNTERS, ZB_TICKETS = ZB_ERR + 16,
               ZB_HIST = ZB_TICKETS + SortWork::kMaxTickets, ZB_WORDS = ZB_HIST + 256 * SortWork::kMaxHist;
 
 void ensure_status(vm3dgs* c) {
-    const size_t need = lb_status_words(std::max(c->cap_pairs, c->cap_render));
+    const size_t need = lb_status_words(std::max({c->cap_pairs, c->cap_render, (uint64_t)c->S * SUBS,
+                                                  (uint64_t)c->n_pg}));
     if (need > c->status_words) {
         dfree(c->d_status);
         dalloc(&c->d_status, need);
@@ -333,11 +342,6 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         delete c;
         return VM3DGS_E_INVALID_ARG;
     }
-    if (c->L > 1) {
-        g_create_error = "several LOD levels are not enabled in this build of the frame path";
-        delete c;
-        return VM3DGS_E_INVALID_ARG;
-    }
     try {
         if (o.stream_render) c->sr = (hipStream_t)o.stream_render;
         else { HIPCHK(hipStreamCreateWithFlags(&c->sr, hipStreamNonBlocking)); c->own_sr = true; }
@@ -390,7 +394,7 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         // page table (empty pool)
         dalloc(&c->d_slot_level, S); dalloc(&c->d_last_used, S); dalloc(&c->d_sub_vpage, (size_t)S * SUBS);
         dalloc(&c->d_sub_lu, (size_t)S * SUBS); dalloc(&c->d_v2p, (size_t)n_pg * L);
-        dalloc(&c->d_req_sub, (size_t)S * SUBS); dalloc(&c->d_slot_req, S); dalloc(&c->d_miss, (size_t)n_pg * L);
+        dalloc(&c->d_req_sub, (size_t)S * SUBS); dalloc(&c->d_slot_req, (size_t)(S + 3) / 4 * 4); dalloc(&c->d_miss, (size_t)n_pg * L);
         HIPCHK(hipMemset(c->d_slot_level, 0xff, S));
         HIPCHK(hipMemset(c->d_last_used, 0xff, sizeof(int32_t) * S));
         HIPCHK(hipMemset(c->d_sub_vpage, 0xff, sizeof(int32_t) * S * SUBS));
@@ -400,6 +404,13 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         dalloc(&c->d_copy_id, (size_t)4 * n_pg * L);
         dalloc(&c->d_missing, (size_t)2 * n_pg * L); halloc(&c->h_missing, (size_t)2 * n_pg * L);
         dalloc(&c->d_rlist, n_pg);
+        if (L > 1) {
+            dalloc(&c->d_lkeys_alt, n_pg); dalloc(&c->d_lflag, n_pg); dalloc(&c->d_lpos, (size_t)n_pg + 1);
+            dalloc(&c->d_wkeys[0], S); dalloc(&c->d_wkeys[1], S);
+            for (int l = 1; l < L; ++l) { dalloc(&c->d_ck[l][0], (size_t)S * SUBS); dalloc(&c->d_ck[l][1], (size_t)S * SUBS); }
+            dalloc(&c->d_fresh, (size_t)3 * S);
+            dalloc(&c->d_lvl_out, n_pg); halloc(&c->h_lvl, n_pg);
+        }
         // splat buffers
         const uint64_t per_view = std::max<uint64_t>((uint64_t)S * c->P,
                                                      (o.flags & VM3DGS_FLAG_FULL_SCENE_COPY) ? (uint64_t)n_pg * c->P : 0);
@@ -478,7 +489,16 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         pa.sub_last_used = c->d_sub_lu; pa.v2p = c->d_v2p; pa.req_sub = c->d_req_sub; pa.slot_req = c->d_slot_req;
         pa.miss = c->d_miss; pa.copies = c->d_copies; pa.copy_id = c->d_copy_id; pa.missing = c->d_missing;
         pa.counters = c->d_ctr; pa.level_base = c->d_level_base; pa.rl = c->d_rlist;
-        launch_pagetable(c->sr, pa, 0);
+        if (c->L == 1) {
+            launch_pagetable(c->sr, pa, 0);
+        } else {
+            LodWork lw{};
+            lw.keys_alt = c->d_lkeys_alt; lw.keys_out = c->d_keys + c->n_pg; lw.level_out = c->d_lvl_out;
+            lw.flag = c->d_lflag; lw.pos = c->d_lpos; lw.wkeys[0] = c->d_wkeys[0]; lw.wkeys[1] = c->d_wkeys[1];
+            for (int l = 0; l < 3; ++l) { lw.ck[l][0] = c->d_ck[l][0]; lw.ck[l][1] = c->d_ck[l][1]; }
+            lw.fresh = c->d_fresh;
+            launch_pagetable_lod(c->sr, pa, c->sw, lw);
+        }
         HIPCHK(hipGetLastError());
         HIPCHK(hipEventRecord(ev[2], c->sr));
         HIPCHK(hipMemcpyAsync(c->h_ctr, c->d_ctr, sizeof(uint32_t) * C_NCOUNTERS, hipMemcpyDeviceToHost, c->sr));
@@ -515,6 +535,8 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         if (c->last_n_req)
             HIPCHK(hipMemcpyAsync(c->h_keys, c->d_keys + c->n_pg, sizeof(uint64_t) * c->last_n_req,
                                   hipMemcpyDeviceToHost, c->sr));
+        if (c->last_n_req && c->L > 1)
+            HIPCHK(hipMemcpyAsync(c->h_lvl, c->d_lvl_out, c->last_n_req, hipMemcpyDeviceToHost, c->sr));
         if (c->last_n_missing)
             HIPCHK(hipMemcpyAsync(c->h_missing, c->d_missing, sizeof(int32_t) * 2 * c->last_n_missing,
                                   hipMemcpyDeviceToHost, c->sr));
@@ -523,7 +545,7 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         c->out_req_level.resize(c->last_n_req);
         for (uint32_t i = 0; i < c->last_n_req; ++i) {
             c->out_req[i] = (int32_t)(c->h_keys[i] & 0x3fffffffull);
-            c->out_req_level[i] = 0;
+            c->out_req_level[i] = c->L > 1 ? c->h_lvl[i] : (int8_t)0;
         }
         c->out_missing.assign(c->h_missing, c->h_missing + 2 * c->last_n_missing);
         st.ms_visibility = ms(ev[0], ev[1]);
@@ -536,6 +558,10 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         c->frame++;
     } catch (const HipError& h) {
         return fail(c, h);
+    } catch (const std::length_error& e) {
+        c->err = e.what();
+        c->poisoned = true;
+        return VM3DGS_E_CAPACITY;
     }
     if (out) {
         out->requests = c->out_req.data();
@@ -570,6 +596,10 @@ vm3dgs_status vm3dgs_render_full(vm3dgs* c, const vm3dgs_camera* cams, uint32_t 
         st.render_pages = (uint32_t)c->n_pg;
     } catch (const HipError& h) {
         return fail(c, h);
+    } catch (const std::length_error& e) {
+        c->err = e.what();
+        c->poisoned = true;
+        return VM3DGS_E_CAPACITY;
     }
     if (stats) *stats = st;
     return VM3DGS_OK;
@@ -590,6 +620,10 @@ vm3dgs_status vm3dgs_sync(vm3dgs* c) {
         HIPCHK(hipStreamSynchronize(c->sc));
     } catch (const HipError& h) {
         return fail(c, h);
+    } catch (const std::length_error& e) {
+        c->err = e.what();
+        c->poisoned = true;
+        return VM3DGS_E_CAPACITY;
     }
     return VM3DGS_OK;
 }

@@ -13,6 +13,9 @@
 // levels: the placement of a miss depends on the ones before it (sub-slots
 // of a physical page fill up), so one wave walks the misses in order over
 // candidate lists sorted beforehand.
+#include <algorithm>
+#include <stdexcept>
+
 #include "kcommon.h"
 #include "vm3dgs_impl.h"
 
@@ -189,6 +192,239 @@ __global__ __launch_bounds__(PT_NT) void k_pagetable_l1(const uint64_t* __restri
     }
 }
 
+// ------------------------------------------------------------------ LOD path
+// Several levels: a level-l physical page holds 8^l sub-pages.  Candidate
+// lists are built and sorted in parallel; one thread then places the misses
+// in request order (each placement can change what the next one finds).
+
+// stage 1 over the sorted requests: hits, miss flags (request order kept)
+// unused key slots past the compacted requests sort last
+__global__ void k_ptl_pad_keys(uint64_t* __restrict__ keys, int n_pg, const uint32_t* __restrict__ counters) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_pg && (uint32_t)i >= counters[vm::C_NREQ]) keys[i] = ~0ull;
+}
+
+__global__ void k_ptl_hits(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ counters,
+                           const int8_t* __restrict__ page_level, int n_pg, int L, const int32_t* __restrict__ v2p,
+                           uint8_t* __restrict__ req_sub, uint8_t* __restrict__ slot_req,
+                           int32_t* __restrict__ last_used, int32_t* __restrict__ sub_last_used, int frame,
+                           uint32_t* __restrict__ miss_flag, uint64_t* __restrict__ keys_out,
+                           int8_t* __restrict__ level_out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pg) return;
+    const uint32_t n = counters[vm::C_NREQ];
+    uint32_t flag = 0;
+    if ((uint32_t)i < n) {
+        const uint64_t key = keys[i];
+        const int32_t pg = (int32_t)(key & 0x3fffffffull);
+        const int l = page_level[pg];
+        keys_out[i] = key;
+        level_out[i] = (int8_t)l;
+        const int32_t e = v2p[pg * L + l];
+        if (e >= 0) {
+            req_sub[e] = 1;
+            slot_req[e / vmk::SUBS] = 1;
+            last_used[e / vmk::SUBS] = frame;
+            sub_last_used[e] = frame;
+        } else {
+            flag = 1;
+        }
+    }
+    miss_flag[i] = flag;
+}
+
+__global__ void k_ptl_miss_list(const uint64_t* __restrict__ keys, const int8_t* __restrict__ page_level, int n_pg,
+                                const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos,
+                                uint32_t* __restrict__ miss) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pg || !flag[i]) return;
+    const uint32_t pg = (uint32_t)(keys[i] & 0x3fffffffull);
+    miss[pos[i]] = pg | ((uint32_t)page_level[pg] << 30);
+}
+
+// candidate keys: whole free pages (last use + 1, slot) and, per level l >= 1,
+// the non-required sub-slots of level-l pages (0 for empty else last use + 1,
+// slot * 64 + sub); ineligible entries are all-ones and sort last
+__global__ void k_ptl_cand_keys(int S, int L, int idx_bits, const int8_t* __restrict__ slot_level,
+                                const int32_t* __restrict__ last_used, const int32_t* __restrict__ sub_vpage,
+                                const int32_t* __restrict__ sub_last_used, const uint8_t* __restrict__ req_sub,
+                                const uint8_t* __restrict__ slot_req, uint64_t* __restrict__ wkeys,
+                                uint64_t* __restrict__ ck1, uint64_t* __restrict__ ck2, uint32_t* __restrict__ counters) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)S * vmk::SUBS) return;
+    const int s = (int)(i / vmk::SUBS), j = (int)(i % vmk::SUBS);
+    if (j == 0)
+        wkeys[s] = slot_req[s] ? ~0ull : (((uint64_t)(uint32_t)(last_used[s] + 1) << idx_bits) | (uint64_t)s);
+    const int l = slot_level[s];
+    bool ok1 = false, ok2 = false;
+    uint64_t key = ~0ull;
+    if (l >= 1 && j < (1 << (3 * l)) && !req_sub[i]) {
+        const uint32_t k1 = sub_vpage[i] < 0 ? 0u : (uint32_t)(sub_last_used[i] + 1);
+        key = ((uint64_t)k1 << idx_bits) | (uint64_t)i;
+        ok1 = l == 1;
+        ok2 = l == 2;
+    }
+    if (L > 1) ck1[i] = ok1 ? key : ~0ull;
+    if (L > 2) ck2[i] = ok2 ? key : ~0ull;
+    const uint64_t b1 = __ballot(ok1), b2 = __ballot(ok2);
+    if (__lane_id() == 0) {
+        if (b1) atomicAdd(&counters[vm::C_NCAND1], (uint32_t)__popcll(b1));
+        if (b2) atomicAdd(&counters[vm::C_NCAND2], (uint32_t)__popcll(b2));
+    }
+}
+
+struct PtWalk {
+    const uint32_t* miss; const uint64_t* wkeys; const uint64_t* ck[3];
+    int S, L, P, frame, budget, bytes_g;
+    uint64_t idx_mask;
+    const int64_t* level_base;
+    int8_t* slot_level; int32_t* last_used; int32_t* sub_vpage; int32_t* sub_last_used; int32_t* v2p;
+    uint8_t* req_sub; uint8_t* slot_req; int32_t* fresh;   // fresh: [3][S]
+    CopyCmd* copies; int32_t* copy_id; int32_t* missing; uint32_t* counters;
+};
+
+// one thread: the misses in request order over the sorted candidate lists
+__global__ void k_ptl_walk(PtWalk a) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint32_t n_miss = a.counters[vm::C_MISSES];
+    const uint32_t n_s = (uint32_t)a.S;
+    uint32_t ncl[3] = {0u, a.counters[vm::C_NCAND1], a.counters[vm::C_NCAND2]};
+    uint32_t pw = 0, pc[3] = {0, 0, 0}, fn[3] = {0, 0, 0}, fh[3] = {0, 0, 0};
+    uint32_t n_copy = 0, n_missing = 0, evict = 0;
+    for (uint32_t i = 0; i < n_miss; ++i) {
+        const uint32_t m = a.miss[i];
+        const int32_t p = (int32_t)(m & 0x3fffffffu);
+        const int l = (int)(m >> 30);
+        if (a.budget > 0 && n_copy >= (uint32_t)a.budget) {
+            a.missing[2 * n_missing] = p; a.missing[2 * n_missing + 1] = l; ++n_missing;
+            continue;
+        }
+        int ts = -1, tj = -1;
+        const int cap = 1 << (3 * l);
+        if (l > 0) {
+            while (pc[l] < ncl[l]) {
+                const uint32_t idx = (uint32_t)(a.ck[l][pc[l]++] & a.idx_mask);
+                const int s = (int)(idx / vmk::SUBS), j = (int)(idx % vmk::SUBS);
+                if (a.slot_level[s] == l && !a.req_sub[idx]) { ts = s; tj = j; break; }
+            }
+            while (ts < 0 && fh[l] < fn[l]) {
+                const int s = a.fresh[l * a.S + fh[l]];
+                int jj = -1;
+                if (a.slot_level[s] == l)
+                    for (int t = 0; t < cap; ++t)
+                        if (!a.req_sub[s * vmk::SUBS + t] && a.sub_vpage[s * vmk::SUBS + t] < 0) { jj = t; break; }
+                if (jj >= 0) { ts = s; tj = jj; } else ++fh[l];
+            }
+        }
+        if (ts < 0) {
+            while (pw < n_s) {
+                const uint64_t wk = a.wkeys[pw++];
+                if (wk == ~0ull) { pw = n_s; break; }
+                const int s = (int)(wk & a.idx_mask);
+                if (a.slot_req[s]) continue;
+                const int oldl = a.slot_level[s];
+                if (oldl >= 0)
+                    for (int j = 0; j < (1 << (3 * oldl)); ++j) {
+                        const int32_t op = a.sub_vpage[s * vmk::SUBS + j];
+                        if (op >= 0) { a.v2p[op * a.L + oldl] = -1; ++evict; }
+                    }
+                for (int j = 0; j < vmk::SUBS; ++j) {
+                    a.sub_vpage[s * vmk::SUBS + j] = -1;
+                    a.sub_last_used[s * vmk::SUBS + j] = -1;
+                }
+                a.slot_level[s] = (int8_t)l;
+                ts = s; tj = 0;
+                if (l > 0) a.fresh[l * a.S + fn[l]++] = s;
+                break;
+            }
+        }
+        if (ts < 0) {
+            a.missing[2 * n_missing] = p; a.missing[2 * n_missing + 1] = l; ++n_missing;
+            continue;
+        }
+        const int e = ts * vmk::SUBS + tj;
+        const int32_t old = a.sub_vpage[e];
+        if (old >= 0) { a.v2p[old * a.L + l] = -1; ++evict; }
+        a.sub_vpage[e] = p;
+        a.sub_last_used[e] = a.frame;
+        a.last_used[ts] = a.frame;
+        a.v2p[p * a.L + l] = e;
+        a.req_sub[e] = 1;
+        a.slot_req[ts] = 1;
+        const int64_t Pl = a.P >> (3 * l);
+        CopyCmd c;
+        c.host_off = a.level_base[l] + (int64_t)p * Pl * a.bytes_g;
+        c.pool_off = ((int64_t)ts * a.P + (int64_t)tj * Pl) * a.bytes_g;
+        c.bytes = Pl * a.bytes_g;
+        a.copies[n_copy] = c;
+        a.copy_id[4 * n_copy] = p; a.copy_id[4 * n_copy + 1] = l;
+        a.copy_id[4 * n_copy + 2] = ts; a.copy_id[4 * n_copy + 3] = tj;
+        ++n_copy;
+    }
+    a.counters[vm::C_EVICT] = evict;
+    a.counters[vm::C_NCOPY] = n_copy;
+    a.counters[vm::C_NMISSING] = n_missing;
+}
+
+// render list with per-level counts, and the number of occupied physical pages
+__global__ __launch_bounds__(PT_NT) void k_ptl_render_list(const int8_t* __restrict__ page_level,
+                                                           const int32_t* __restrict__ v2p, int n_pg, int L, int P,
+                                                           int S, const int8_t* __restrict__ slot_level,
+                                                           const int32_t* __restrict__ sub_vpage,
+                                                           RenderEntry* __restrict__ rl, uint32_t* __restrict__ counters) {
+    __shared__ uint32_t scan_sh[PT_NT / WAVE];
+    __shared__ uint32_t s_used;
+    if (threadIdx.x == 0) s_used = 0;
+    uint32_t n_rl = 0, base = 0;
+    for (int b = 0; b < n_pg; b += PT_NT) {
+        const int p = b + threadIdx.x;
+        bool r = false;
+        int32_t e = -1;
+        int l = 0;
+        if (p < n_pg && page_level[p] >= 0) {
+            l = page_level[p];
+            e = v2p[p * L + l];
+            r = e >= 0;
+        }
+        const uint32_t cnt = r ? (uint32_t)(P >> (3 * l)) : 0u;
+        uint32_t tot, totc;
+        const uint32_t ex = block_excl_scan<PT_NT>(r ? 1u : 0u, scan_sh, &tot);
+        const uint32_t exc = block_excl_scan<PT_NT>(cnt, scan_sh, &totc);
+        if (r) {
+            RenderEntry q;
+            q.pool_off = (uint32_t)((e / vmk::SUBS) * P + (e % vmk::SUBS) * (P >> (3 * l)));
+            q.count = cnt;
+            q.base = base + exc;
+            q.level = (uint32_t)l;
+            rl[n_rl + ex] = q;
+        }
+        n_rl += tot;
+        base += totc;
+    }
+    uint32_t used = 0;
+    for (int s = threadIdx.x; s < S; s += PT_NT) {
+        const int l = slot_level[s];
+        if (l < 0) continue;
+        bool any = false;
+        for (int j = 0; j < (1 << (3 * l)); ++j) any = any || sub_vpage[s * vmk::SUBS + j] >= 0;
+        used += any ? 1u : 0u;
+    }
+    used = wave_sum(used);
+    __syncthreads();
+    if (__lane_id() == 0) atomicAdd(&s_used, used);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        counters[vm::C_NRL] = n_rl;
+        counters[vm::C_NRENDER] = base;
+        counters[vm::C_POOLUSED] = s_used;
+        counters[vm::C_HITS] = counters[vm::C_NREQ] - counters[vm::C_MISSES];
+    }
+}
+
+__global__ void k_ptl_count_misses(const uint32_t* __restrict__ total, uint32_t* __restrict__ counters) {
+    counters[vm::C_MISSES] = *total;
+}
+
 }  // namespace vmk
 
 namespace vm {
@@ -205,6 +441,70 @@ void launch_pagetable(hipStream_t st, const PtArgs& a, int) {
     k.sub_last_used = a.sub_last_used; k.v2p = a.v2p; k.slot_req = a.slot_req; k.miss = a.miss;
     k.copies = a.copies; k.copy_id = a.copy_id; k.missing = a.missing; k.counters = a.counters; k.rl = a.rl;
     hipLaunchKernelGGL(k_pagetable_l1, dim3(1), dim3(PT_NT), 0, st, a.req_keys, k);
+}
+
+}  // namespace vm
+
+namespace vm {
+
+static int bits_for_u(uint64_t n) {
+    int b = 0;
+    while ((1ull << b) < n) ++b;
+    return b;
+}
+
+void launch_pagetable_lod(hipStream_t st, const PtArgs& a, SortWork& sw, const LodWork& w) {
+    const int n_pg = a.n_pg, S = a.S, L = a.L;
+    const unsigned nb_pg = (unsigned)((n_pg + 255) / 256);
+    // requests in service order: all n_pg key slots (unused ones are all-ones)
+    uint64_t* rk[2] = {const_cast<uint64_t*>(a.req_keys), w.keys_alt};
+    uint32_t* nov[2] = {nullptr, nullptr};
+    hipLaunchKernelGGL(k_ptl_pad_keys, dim3(nb_pg), dim3(256), 0, st, rk[0], n_pg, (const uint32_t*)a.counters);
+    const int kb = onesweep_u64(st, sw, rk, nov, (uint32_t)n_pg, 0, 64);
+    const uint64_t* keys = rk[kb];
+    launch_fill_u32(st, (uint32_t*)a.req_sub, ((uint64_t)S * SUBS + 3) / 4, 0u);
+    launch_fill_u32(st, (uint32_t*)a.slot_req, ((uint64_t)S + 3) / 4, 0u);
+    hipLaunchKernelGGL(k_ptl_hits, dim3(nb_pg), dim3(256), 0, st, keys, (const uint32_t*)a.counters, a.page_level,
+                       n_pg, L, (const int32_t*)a.v2p, a.req_sub, a.slot_req, a.last_used, a.sub_last_used, a.frame,
+                       w.flag, w.keys_out, w.level_out);
+    scan_lb(st, sw, w.flag, (uint64_t)n_pg, w.pos, w.pos + n_pg);
+    hipLaunchKernelGGL(k_ptl_count_misses, dim3(1), dim3(1), 0, st, (const uint32_t*)(w.pos + n_pg), a.counters);
+    hipLaunchKernelGGL(k_ptl_miss_list, dim3(nb_pg), dim3(256), 0, st, keys, a.page_level, n_pg,
+                       (const uint32_t*)w.flag, (const uint32_t*)w.pos, a.miss);
+    const int idx_bits = bits_for_u((uint64_t)S * SUBS);
+    // one bit above the largest eligible key, so that the all-ones keys of
+    // ineligible entries sort strictly after every eligible one
+    const int end_bit = idx_bits + bits_for_u((uint64_t)a.frame + 2) + 1;
+    hipLaunchKernelGGL(k_ptl_cand_keys, dim3((unsigned)(((uint64_t)S * SUBS + 255) / 256)), dim3(256), 0, st, S, L,
+                       idx_bits, (const int8_t*)a.slot_level, (const int32_t*)a.last_used,
+                       (const int32_t*)a.sub_vpage, (const int32_t*)a.sub_last_used, (const uint8_t*)a.req_sub,
+                       (const uint8_t*)a.slot_req, w.wkeys[0], w.ck[1][0], w.ck[2][0], a.counters);
+    uint64_t* wk[2] = {w.wkeys[0], w.wkeys[1]};
+    const int wb = onesweep_u64(st, sw, wk, nov, (uint32_t)S, 0, std::max(8, end_bit));
+    PtWalk pw;
+    pw.wkeys = wk[wb];
+    pw.ck[0] = nullptr;
+    if (end_bit > 64) throw std::length_error("LOD page table: frame counter and pool size exceed the 64-bit keys");
+    for (int l = 1; l < 3; ++l) {
+        pw.ck[l] = nullptr;
+        if (l < L) {
+            uint64_t* ck[2] = {w.ck[l][0], w.ck[l][1]};
+            const int cb = onesweep_u64(st, sw, ck, nov, (uint32_t)S * SUBS, 0, std::max(8, end_bit));
+            pw.ck[l] = ck[cb];
+        }
+    }
+    pw.miss = a.miss;
+    pw.S = S; pw.L = L; pw.P = a.P; pw.frame = a.frame; pw.budget = a.budget; pw.bytes_g = a.bytes_g;
+    pw.idx_mask = (1ull << idx_bits) - 1;
+    pw.level_base = a.level_base;
+    pw.slot_level = a.slot_level; pw.last_used = a.last_used; pw.sub_vpage = a.sub_vpage;
+    pw.sub_last_used = a.sub_last_used; pw.v2p = a.v2p; pw.req_sub = a.req_sub; pw.slot_req = a.slot_req;
+    pw.fresh = w.fresh; pw.copies = a.copies; pw.copy_id = a.copy_id; pw.missing = a.missing;
+    pw.counters = a.counters;
+    hipLaunchKernelGGL(k_ptl_walk, dim3(1), dim3(64), 0, st, pw);
+    hipLaunchKernelGGL(k_ptl_render_list, dim3(1), dim3(PT_NT), 0, st, (const int8_t*)a.page_level,
+                       (const int32_t*)a.v2p, n_pg, L, a.P, S, (const int8_t*)a.slot_level,
+                       (const int32_t*)a.sub_vpage, a.rl, a.counters);
 }
 
 }  // namespace vm

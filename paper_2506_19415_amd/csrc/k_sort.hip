@@ -299,12 +299,13 @@ __global__ __launch_bounds__(RS_NT) void k_os_hist(const K* __restrict__ keys, u
 
 // one stable 8-bit pass: local ranking (ballot digit matching per wave), look-back
 // over earlier tiles per digit, LDS staging in digit order, coalesced writes
-template <typename K>
+// HV: values travel with the keys (without them no value pointer is touched)
+template <typename K, bool HV>
 __global__ __launch_bounds__(RS_NT) void k_os_pass(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                   K* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t n,
                                                   int shift, const uint32_t* __restrict__ ghist_pass,
-                                                  uint64_t* status, uint32_t* ticket, uint32_t epoch, uint32_t* err,
-                                                  int has_vals) {
+                                                  uint64_t* status, uint32_t* ticket, uint32_t epoch, uint32_t* err) {
+    constexpr bool has_vals = HV;
     __shared__ uint32_t wc[RS_WAVES][256];
     __shared__ uint32_t dbase[256];
     __shared__ uint32_t gbase[256];
@@ -463,10 +464,14 @@ static int onesweep_impl(hipStream_t st, SortWork& w, K* keys[2], uint32_t* vals
                            np, gh);
         for (int p = 0; p < np; ++p) {
             const int shift = begin_bit + 8 * (p0 + p);
-            hipLaunchKernelGGL(k_os_pass<K>, dim3(nb), dim3(RS_NT), 0, st, (const K*)keys[cur],
-                               (const uint32_t*)vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, shift,
-                               (const uint32_t*)(gh + 256 * p), w.status, w.next_ticket(), w.next_epoch(), w.err,
-                               has_vals);
+            if (has_vals)
+                hipLaunchKernelGGL((k_os_pass<K, true>), dim3(nb), dim3(RS_NT), 0, st, (const K*)keys[cur],
+                                   (const uint32_t*)vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, shift,
+                                   (const uint32_t*)(gh + 256 * p), w.status, w.next_ticket(), w.next_epoch(), w.err);
+            else
+                hipLaunchKernelGGL((k_os_pass<K, false>), dim3(nb), dim3(RS_NT), 0, st, (const K*)keys[cur],
+                                   (const uint32_t*)nullptr, keys[cur ^ 1], (uint32_t*)nullptr, n, shift,
+                                   (const uint32_t*)(gh + 256 * p), w.status, w.next_ticket(), w.next_epoch(), w.err);
             cur ^= 1;
         }
     }

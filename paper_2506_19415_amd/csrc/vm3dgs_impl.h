@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -56,17 +57,21 @@ struct SortWork {
     uint32_t* hist = nullptr;     // [kMaxHist][256], zeroed per frame
     uint32_t* tickets = nullptr;  // [kMaxTickets], zeroed per frame
     uint32_t* err = nullptr;      // look-back spin overrun flag
-    static constexpr int kMaxHist = 32;
-    static constexpr int kMaxTickets = 64;
+    static constexpr int kMaxHist = 64;
+    static constexpr int kMaxTickets = 128;
     int hist_used = 0, tickets_used = 0;
     uint32_t epoch = 0;
     void reset() { hist_used = 0; tickets_used = 0; }
     uint32_t* next_hist(int n) {
+        if (hist_used + n > kMaxHist) throw std::length_error("sort histograms of one frame exhausted");
         uint32_t* p = hist + 256 * (size_t)hist_used;
         hist_used += n;
         return p;
     }
-    uint32_t* next_ticket() { return tickets + tickets_used++; }
+    uint32_t* next_ticket() {
+        if (tickets_used >= kMaxTickets) throw std::length_error("sort tickets of one frame exhausted");
+        return tickets + tickets_used++;
+    }
     uint32_t next_epoch() { epoch = (epoch + 1) & 0x3fffffffu; if (epoch == 0) epoch = 1; return epoch; }
 };
 size_t lb_status_words(uint64_t n_keys);
@@ -88,7 +93,7 @@ struct CamK {
 // Counters written by the page-table kernels and read back once per frame.
 enum Ctr {
     C_NREQ = 0, C_DIRECT, C_LINKED, C_HITS, C_MISSES, C_EVICT, C_NCOPY, C_NMISSING, C_NRL, C_NRENDER,
-    C_CAND, C_POOLUSED, C_NCOUNTERS = 16
+    C_CAND, C_POOLUSED, C_NCAND1, C_NCAND2, C_NCOUNTERS = 16
 };
 
 struct RenderEntry {   // one resident requested (sub-)page in render order
@@ -128,6 +133,19 @@ struct PtArgs {
     RenderEntry* rl;
 };
 void launch_pagetable(hipStream_t st, const PtArgs& a, int n_req_host_bound);
+
+// scratch of the LOD page table
+struct LodWork {
+    uint64_t* keys_alt;     // [n_pg] sort ping-pong for the requests
+    uint64_t* keys_out;     // [n_pg] requests in service order (read back)
+    int8_t* level_out;      // [n_pg] their levels (read back)
+    uint32_t* flag;         // [n_pg]
+    uint32_t* pos;          // [n_pg + 1]
+    uint64_t* wkeys[2];     // [S] x 2
+    uint64_t* ck[3][2];     // per level 1, 2: [S*64] x 2
+    int32_t* fresh;         // [3][S]
+};
+void launch_pagetable_lod(hipStream_t st, const PtArgs& a, SortWork& sw, const LodWork& w);
 
 struct SplatArgs {
     const RenderEntry* rl; int n_rl;

@@ -34,6 +34,8 @@ def compare_frame(r, ovm, out, n_views, check_image=True, tag=""):
     assert np.array_equal(g("page_level", np.int8), ovm.get("page_level")), tag
     req = np.ctypeslib.as_array(out.requests, (out.n_requests,)) if out.n_requests else np.zeros(0, np.int32)
     assert np.array_equal(req, ovm.get("req_page")), tag
+    lvl = np.ctypeslib.as_array(out.request_level, (out.n_requests,)) if out.n_requests else np.zeros(0, np.int8)
+    assert np.array_equal(lvl, ovm.get("req_level")), tag
     # page table
     for name, dt in [("slot_level", np.int8), ("last_used", np.int32), ("sub_vpage", np.int32),
                      ("sub_last_used", np.int32), ("v2p", np.int32)]:
@@ -251,4 +253,36 @@ def test_terrain6m_full_size_sampled():
         ty, tx = divmod(int(t), TX)
         blk = (slice(ty * 16, min(ty * 16 + 16, 1080)), slice(tx * 16, tx * 16 + 16))
         assert np.abs(img[blk] - ref[blk]).max() <= 1e-3, t
+    r.close()
+
+
+# ---------------------------------------------------------------- LOD levels
+@pytest.fixture(scope="module")
+def city():
+    sc = synth.scene_city(0, n=200_000, size=300.0, block=60.0, street=12.0)
+    return sc, synth.path_city(sc, n_frames=30, width=480, height=270)
+
+
+@pytest.mark.parametrize("L,tau,S,budget,fmt", [(3, 128.0, 64, 0, 0), (3, 256.0, 48, 20, 1), (2, 128.0, 80, 0, 0)])
+def test_lod_city(city, L, tau, S, budget, fmt):
+    """Three (or two) LOD levels on a street-to-aerial city path: sub-slot
+    reuse, pages converted between levels, evictions of whole physical pages,
+    missing pages under pool pressure and a copy budget; every intermediate
+    and the image against the oracle."""
+    sc, cams = city
+    osc = oracle.OracleScene(sc, 512, L, 2.0, 2.0, attr_format=fmt)
+    r = _renderer(sc, 512, S, (480, 270), (120, 68), 2.0, lod_levels=L, lod_radius_px=tau,
+                  copy_budget=budget, attr_format=fmt)
+    ovm = oracle.OracleVM(osc, S, (480, 270), (120, 68), copy_budget=budget, lod_radius_px=tau)
+    seen = np.zeros(L, np.int64)
+    evictions = 0
+    for k in range(0, 30, 2):
+        print(f"lod L={L} tau={tau} S={S} frame {k}", flush=True)
+        _, out = r.frame([cams[k]])
+        ovm.frame([cams[k]])
+        compare_frame(r, ovm, out, 1, tag=f"lod frame {k}")
+        seen += np.bincount(ovm.get("req_level"), minlength=L)[:L]
+        evictions += out.stats.evictions
+    assert np.all(seen > 0), seen          # every level was requested
+    assert evictions > 0
     r.close()
