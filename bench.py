@@ -16,9 +16,11 @@ and the PSNR of each timed VM frame against it is reported.
 One JSON line on stdout; progress on stderr.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import statistics
 import sys
 import time
@@ -41,6 +43,32 @@ FLOP_EVAL, FLOP_ALPHA = 11, 23
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+# HBM traffic of k_blend from the committed counter summary, valid only while
+# the kernel's source is the one the counters were taken on
+BLEND_SOURCES = ["paper_2506_19415_amd/csrc/k_splat.hip", "paper_2506_19415_amd/csrc/kcommon.h"]
+BLEND_PMC = "profiles/k_blend_terrain6m_pmc.md"
+
+
+def blend_source_hash():
+    h = hashlib.sha256()
+    for f in BLEND_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def blend_traffic():
+    path = os.path.join(ROOT, BLEND_PMC)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_hash = re.search(r"source_sha256:\s*([0-9a-f]{64})", txt)
+    m_bytes = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_hash or not m_bytes or m_hash.group(1) != blend_source_hash():
+        return None
+    return float(m_bytes.group(1))
 
 
 def psnr(a, b):
@@ -79,7 +107,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-full", action="store_true", help="skip the full-scene timing (profiling runs)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the timed frames, one plain device-to-device copy of this many MiB "
+                         "(the reference kernel that scales the HBM counters)")
+    ap.add_argument("--print-source-hash", action="store_true", help="print the k_blend source hash and exit")
     args = ap.parse_args()
+    if args.print_source_hash:
+        print(blend_source_hash())
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this path is built and measured on a single MI355X "
               f"(requested --gpus {args.gpus})", file=sys.stderr)
@@ -183,7 +218,7 @@ def main():
     flops = statistics.mean([FLOP_EVAL * e + FLOP_ALPHA * a for e, a in zip(evals, alphas)])
     achieved = flops / (blend_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / ALU_PEAK_TFLOPS, "traffic": None, "kernel": "k_blend",
+                "frac": achieved / ALU_PEAK_TFLOPS, "traffic": blend_traffic(), "kernel": "k_blend",
                 "per_unit": f"{FLOP_EVAL} flop per pixel-Gaussian evaluation + {FLOP_ALPHA} per alpha evaluation",
                 "evals_per_launch": statistics.mean(evals), "alphas_per_launch": statistics.mean(alphas),
                 "launch_ms": blend_ms}
@@ -221,6 +256,15 @@ def main():
                                 "per_unit": "300 B per render Gaussian (236 B attributes read, 64 B written)"},
         "roofline": roofline,
     }
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 2.0, out=dst)   # an elementwise kernel: reads and writes the size once
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mib} MiB read and written by one elementwise kernel")
+        del src, dst
     r.close()
     del vm_imgs
     if not args.no_cpu_baseline:

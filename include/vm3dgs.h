@@ -58,6 +58,12 @@ typedef struct {
 #define VM3DGS_FLAG_LINKS 1u           /* expand page links (Sec. 3 "Page Linking") */
 #define VM3DGS_FLAG_FULL_SCENE_COPY 2u /* keep all level-0 pages in HBM for vm3dgs_render_full */
 #define VM3DGS_FLAG_BLEND_STATS 4u     /* count blend work (stats.blend_evals / blend_alphas); slower */
+/* Tile rectangles from the 3-sigma radius alone.  By default each rectangle
+ * is cut to the support box of the Gaussian: the pixels where the blend's
+ * power can reach -5.55 (with float rounding bounded), outside which every
+ * term fails the 1/255 alpha test; the image is the same either way, with
+ * fewer (tile, Gaussian) pairs. */
+#define VM3DGS_FLAG_SIGMA3_TILES 8u
 
 typedef struct {
     uint32_t img_w, img_h;        /* output image, pixels */
@@ -157,7 +163,7 @@ vm3dgs_status vm3dgs_render_full(vm3dgs* ctx, const vm3dgs_camera* cams, uint32_
  * pages decoded to 59 floats). */
 int64_t vm3dgs_debug_get(vm3dgs* ctx, const char* name, void* host_dst, int64_t cap);
 
-/* Replace the VM3DGS_FLAG_LINKS / VM3DGS_FLAG_BLEND_STATS bits of the options
+/* Replace the VM3DGS_FLAG_LINKS / BLEND_STATS / SIGMA3_TILES bits of the options
  * for later frames (VM3DGS_FLAG_FULL_SCENE_COPY is fixed at create).
  * Errors: INVALID_ARG for a NULL context. */
 vm3dgs_status vm3dgs_set_flags(vm3dgs* ctx, uint32_t flags);
@@ -186,6 +192,52 @@ const char* vm3dgs_create_error(void);
 
 /* Release every host and device resource.  NULL is allowed. */
 void vm3dgs_destroy(vm3dgs* ctx);
+
+/* ---- Learned page prefetch: the network ----------------------------------
+ * The paper leaves prefetching to future work (Sec. 6).  This network
+ * proposes lowest-priority page requests; the visibility pass stays the
+ * judge of what is rendered.  A multilayer perceptron: dims[0] inputs,
+ * ReLU hidden layers, dims[n_layers] logits (one per page cluster), trained
+ * with the mean binary cross-entropy of sigmoid(logit) and Adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8) on fp32 master weights.  Every matrix product runs
+ * on the matrix cores with bf16 operands (weights, inputs, hidden
+ * activations, output gradients; round to nearest even) and fp32
+ * accumulation.
+ *
+ * Parameter layout (floats, host or device as stated): per layer l,
+ * W_l [dims[l]][dims[l+1]] row-major (input index major), then b_l
+ * [dims[l+1]]; vm3dgs_mlp_n_params gives the total.
+ * The network owns its device memory; calls are ordered on its stream
+ * (stream = NULL: its own); pointers named _dev are device memory the caller
+ * owns, and results written there are ready on that stream. */
+typedef struct vm3dgs_mlp vm3dgs_mlp;
+
+/* dims[n_layers + 1], 1 <= n_layers <= 8, widths 1..65536; max_batch rows
+ * per call (1..65536).  INVALID_ARG for bad sizes, DEVICE_OOM, HIP. */
+vm3dgs_status vm3dgs_mlp_create(const uint32_t* dims, uint32_t n_layers, uint32_t max_batch, void* stream,
+                                vm3dgs_mlp** out);
+const char* vm3dgs_mlp_create_error(void);
+const char* vm3dgs_mlp_last_error(const vm3dgs_mlp* net);
+uint64_t vm3dgs_mlp_n_params(const vm3dgs_mlp* net);
+/* Weights from host memory (n = vm3dgs_mlp_n_params); resets Adam. */
+vm3dgs_status vm3dgs_mlp_set_params(vm3dgs_mlp* net, const float* params_host, uint64_t n);
+/* Master weights and Adam moments to host memory (any pointer may be NULL);
+ * step = Adam steps taken since the last set_params. */
+vm3dgs_status vm3dgs_mlp_get_state(vm3dgs_mlp* net, float* params_host, float* adam_m_host, float* adam_v_host,
+                                   uint64_t n, uint32_t* step);
+/* x_dev [batch][dims[0]] fp32 -> logits_dev [batch][dims[n_layers]] fp32.
+ * CAPACITY when batch > max_batch. */
+vm3dgs_status vm3dgs_mlp_forward(vm3dgs_mlp* net, const float* x_dev, uint32_t batch, float* logits_dev);
+/* Gradient of the loss for labels y_dev [batch][dims[n_layers]] (0/1 fp32)
+ * into grad_dev (parameter layout, fp32); loss_host may be NULL. */
+vm3dgs_status vm3dgs_mlp_gradient(vm3dgs_mlp* net, const float* x_dev, const float* y_dev, uint32_t batch,
+                                  float* grad_dev, float* loss_host);
+/* Forward, backward and one Adam step with learning rate lr; loss_host (the
+ * loss before the step) may be NULL (then nothing waits for the device). */
+vm3dgs_status vm3dgs_mlp_train_step(vm3dgs_mlp* net, const float* x_dev, const float* y_dev, uint32_t batch,
+                                    float lr, float* loss_host);
+vm3dgs_status vm3dgs_mlp_sync(vm3dgs_mlp* net);
+void vm3dgs_mlp_destroy(vm3dgs_mlp* net);
 
 #ifdef __cplusplus
 }

@@ -60,6 +60,7 @@ def lib():
             getattr(L, nm).argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
         L.or_vm_pagetable.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.or_vm_set_force_all.argtypes = [C.c_void_p, C.c_int]
+        L.or_vm_set_sigma3_tiles.argtypes = [C.c_void_p, C.c_int]
         if hasattr(L, "or_mlp_forward"):
             _bind_mlp(L)
         _LIB = L
@@ -68,8 +69,10 @@ def lib():
 
 def _bind_mlp(L):
     d = C.c_void_p
-    L.or_mlp_forward.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), d, d, d, d]
-    L.or_mlp_backward.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), d, d, d, d, d, d, d]
+    L.or_mlp_n_params.restype = C.c_int64
+    L.or_mlp_n_params.argtypes = [C.c_int, d]
+    L.or_mlp_forward.argtypes = [C.c_int, C.c_int, d, d, d, C.c_int, d]
+    L.or_mlp_backward.argtypes = [C.c_int, C.c_int, d, d, d, d, C.c_int, d, d]
     L.or_mlp_backward.restype = C.c_double
     L.or_adam.argtypes = [C.c_int64, d, d, d, d, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int]
 
@@ -213,6 +216,10 @@ class OracleVM:
     def set_force_all(self, on=True):
         lib().or_vm_set_force_all(self.ptr, int(bool(on)))
 
+    def set_sigma3_tiles(self, on=True):
+        """Tile rectangles from the 3-sigma radius alone (support box off)."""
+        lib().or_vm_set_sigma3_tiles(self.ptr, int(bool(on)))
+
     def get(self, name):
         n = lib().or_vm_get(self.ptr, name.encode(), None, 0)
         if n < 0:
@@ -235,3 +242,43 @@ class OracleVM:
         if getattr(self, "ptr", None):
             lib().or_vm_free(self.ptr)
             self.ptr = None
+
+
+# ---------------------------------------------------------------- prefetch network
+def mlp_n_params(dims):
+    dm = np.ascontiguousarray(dims, dtype=np.int32)
+    return int(lib().or_mlp_n_params(len(dims) - 1, dm.ctypes.data))
+
+
+def mlp_forward(params, dims, x, bf16=True):
+    """Logits [B][d_L] in double."""
+    dm = np.ascontiguousarray(dims, dtype=np.int32)
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    xx = np.ascontiguousarray(x, dtype=np.float32)
+    B = xx.shape[0]
+    z = np.zeros((B, dims[-1]), np.float64)
+    lib().or_mlp_forward(B, len(dims) - 1, dm.ctypes.data, p.ctypes.data, xx.ctypes.data, int(bool(bf16)),
+                         z.ctypes.data)
+    return z
+
+
+def mlp_backward(params, dims, x, y, bf16=True):
+    """(loss, grad in the parameter layout, logits)."""
+    dm = np.ascontiguousarray(dims, dtype=np.int32)
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    xx = np.ascontiguousarray(x, dtype=np.float32)
+    yy = np.ascontiguousarray(y, dtype=np.float32)
+    B = xx.shape[0]
+    g = np.zeros(p.size, np.float64)
+    z = np.zeros((B, dims[-1]), np.float64)
+    loss = lib().or_mlp_backward(B, len(dims) - 1, dm.ctypes.data, p.ctypes.data, xx.ctypes.data, yy.ctypes.data,
+                                 int(bool(bf16)), g.ctypes.data, z.ctypes.data)
+    return loss, g, z
+
+
+def adam(w, m, v, g, lr, b1, b2, eps, t):
+    """One Adam step on float32 arrays w, m, v (in place)."""
+    for a in (w, m, v):
+        assert a.dtype == np.float32 and a.flags.c_contiguous
+    gg = np.ascontiguousarray(g, dtype=np.float64)
+    lib().or_adam(w.size, w.ctypes.data, m.ctypes.data, v.ctypes.data, gg.ctypes.data, lr, b1, b2, eps, int(t))

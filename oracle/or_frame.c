@@ -52,6 +52,7 @@ typedef struct {
     float rgb[3];
     int rect[4];   /* x0 y0 x1 y1, tiles, exclusive upper */
     int tiles;
+    float hy;      /* half height of the support box in pixels (infinite: none) */
 } pp_t;
 
 typedef struct { int32_t page, level, slot, sub, count; int64_t base; } rl_t;
@@ -64,6 +65,7 @@ struct or_vm {
     int P, L, n_pg, bytes_g;
     int frame;
     int force_all;         /* test switch: every page is directly requested */
+    int sigma3_tiles;      /* 1: tile rectangles from the 3-sigma radius alone (no support box) */
     /* page table */
     int8_t* slot_level;
     int32_t* last_used;
@@ -350,10 +352,12 @@ static void page_table(or_vm* vm)
 }
 
 /* ---- 6. splatting -------------------------------------------------------- */
-static void preprocess_one(const float* g, const or_camera* c, int W, int H, int TX, int TY, pp_t* o)
+static void preprocess_one(const float* g, const or_camera* c, int W, int H, int TX, int TY, int sigma3_tiles,
+                           pp_t* o)
 {
     memset(o, 0, sizeof *o);
     o->culled = 1;
+    o->hy = INFINITY;
     float op = g[10];
     if (op == 0.0f) return;                       /* padding */
     float t[3];
@@ -411,8 +415,34 @@ static void preprocess_one(const float* g, const or_camera* c, int W, int H, int
     float x1 = fminf(fmaxf(floorf(((u + rad) + 15.0f) / 16.0f), 0.0f), (float)TX);
     float y0 = fminf(fmaxf(floorf((v - rad) / 16.0f), 0.0f), (float)TY);
     float y1 = fminf(fmaxf(floorf(((v + rad) + 15.0f) / 16.0f), 0.0f), (float)TY);
+    /* Support box.  Blending accepts a term only where power >= -5.55, that
+     * is where the quadratic form Q = d^T Sigma'^-1 d is at most 11.1; over a
+     * column at horizontal offset dx the smallest Q is dx^2 / Sigma'_xx, so
+     * the accepted region lies within |dx| <= sqrt(11.1 Sigma'_xx) (and the
+     * same for rows).  The float evaluation of the power errs by less than
+     * 5e-7 kap Q with kap = (a + c)^2 / det >= cond(Sigma') + 2, so the
+     * threshold is divided by (1 - 5e-7 kap), and one pixel is added; a
+     * footprint with 5e-7 kap >= 1/2 keeps the 3-sigma rectangle.  Tiles
+     * outside the box hold no accepted pixel of this Gaussian, so the image
+     * is that of the 3-sigma rectangles. */
+    float hy = INFINITY;
+    if (!sigma3_tiles) {
+        float kap = ((a + cc) * (a + cc)) / det;
+        float e = 5e-7f * kap;
+        if (e < 0.5f) {
+            float f = 1.0f / (1.0f - e);
+            float hx = sqrtf((11.11f * f) * a) + 1.0f;
+            hy = sqrtf((11.11f * f) * cc) + 1.0f;
+            float bx0 = fminf(fmaxf(floorf((u - hx) / 16.0f), 0.0f), (float)TX);
+            float bx1 = fminf(fmaxf(floorf((u + hx) / 16.0f) + 1.0f, 0.0f), (float)TX);
+            float by0 = fminf(fmaxf(floorf((v - hy) / 16.0f), 0.0f), (float)TY);
+            float by1 = fminf(fmaxf(floorf((v + hy) / 16.0f) + 1.0f, 0.0f), (float)TY);
+            x0 = fmaxf(x0, bx0); x1 = fminf(x1, bx1);
+            y0 = fmaxf(y0, by0); y1 = fminf(y1, by1);
+        }
+    }
     int ix0 = (int)x0, ix1 = (int)x1, iy0 = (int)y0, iy1 = (int)y1;
-    if ((ix1 - ix0) * (iy1 - iy0) == 0) return;
+    if (ix1 <= ix0 || iy1 <= iy0) return;
     /* colour from SH in the viewing direction */
     float d0 = g[0] - c->cam_pos[0], d1 = g[1] - c->cam_pos[1], d2 = g[2] - c->cam_pos[2];
     float len = sqrtf((d0 * d0 + d1 * d1) + d2 * d2);
@@ -423,6 +453,7 @@ static void preprocess_one(const float* g, const or_camera* c, int W, int H, int
     o->opacity = op;
     o->rect[0] = ix0; o->rect[1] = iy0; o->rect[2] = ix1; o->rect[3] = iy1;
     o->tiles = (ix1 - ix0) * (iy1 - iy0);
+    o->hy = hy;
     (void)W; (void)H;
 }
 
@@ -447,7 +478,7 @@ static void splat(or_vm* vm, const or_camera* cams, int n_views, const uint8_t* 
     vm->pp = malloc(sizeof(pp_t) * (size_t)(n_views * n_render > 0 ? n_views * n_render : 1));
     for (int v = 0; v < n_views; v++)
         for (int64_t r = 0; r < n_render; r++)
-            preprocess_one(gauss[r], &cams[v], W, H, TX, TY, &vm->pp[v * n_render + r]);
+            preprocess_one(gauss[r], &cams[v], W, H, TX, TY, vm->sigma3_tiles, &vm->pp[v * n_render + r]);
     /* bucket per tile */
     int64_t* cnt = calloc((size_t)nt + 1, sizeof(int64_t));
     for (int v = 0; v < n_views; v++)
@@ -698,6 +729,8 @@ int or_vm_pagetable(or_vm* vm, int n, const int32_t* pages, const int8_t* levels
 
 void or_vm_set_force_all(or_vm* vm, int on) { vm->force_all = on; }
 
+void or_vm_set_sigma3_tiles(or_vm* vm, int on) { vm->sigma3_tiles = on; }
+
 int or_vm_frame(or_vm* vm, const or_camera* cams, int n_views, const uint8_t* tile_mask)
 {
     or_vm_visibility(vm, cams, n_views, 0);
@@ -767,12 +800,13 @@ int64_t or_vm_get(const or_vm* vm, const char* name, void* dst, int64_t cap)
             }
         return bytes;
     }
-    if (!strcmp(name, "pp_float")) {         /* [n][10] u v depth conic3 opacity rgb3 */
-        int64_t bytes = 40 * npp;
+    if (!strcmp(name, "pp_float")) {         /* [n][11] u v depth conic3 opacity rgb3 hy */
+        int64_t bytes = 44 * npp;
         if (dst && cap >= bytes)
             for (int64_t i = 0; i < npp; i++) {
                 const pp_t* o = &vm->pp[i];
-                float* f = (float*)dst + 10 * i;
+                float* f = (float*)dst + 11 * i;
+                f[10] = o->hy;
                 f[0] = o->u; f[1] = o->v; f[2] = o->depth;
                 f[3] = o->conic[0]; f[4] = o->conic[1]; f[5] = o->conic[2];
                 f[6] = o->opacity; f[7] = o->rgb[0]; f[8] = o->rgb[1]; f[9] = o->rgb[2];

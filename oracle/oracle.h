@@ -67,6 +67,27 @@ int64_t or_vm_get(const or_vm* vm, const char* name, void* dst, int64_t cap);
  * for the same image size. */
 int or_render_full(or_vm* vm, const or_camera* cams, int n_views, const uint8_t* tile_mask);
 
+/* Visibility, requests and page table only; brute_force rasterises every
+ * proxy box over every ID-buffer pixel. */
+int or_vm_visibility(or_vm* vm, const or_camera* cams, int n_views, int brute_force);
+/* The page table driven by an explicit request list in service order. */
+int or_vm_pagetable(or_vm* vm, int n, const int32_t* pages, const int8_t* levels);
+/* Test switches: every page directly requested; tile rectangles from the
+ * 3-sigma radius alone (the support box off). */
+void or_vm_set_force_all(or_vm* vm, int on);
+void or_vm_set_sigma3_tiles(or_vm* vm, int on);
+
+/* ---- learned page prefetch (network oracle, or_mlp.c) ---- */
+/* dims[n_layers + 1]; params: per layer W [d_l][d_{l+1}] then b [d_{l+1}];
+ * bf16 != 0 rounds the operands of every product to bf16 as the GPU holds
+ * them.  z: logits [B][d_L]; grad: parameter layout. */
+int64_t or_mlp_n_params(int n_layers, const int* dims);
+int or_mlp_forward(int B, int n_layers, const int* dims, const float* params, const float* x, int bf16, double* z);
+double or_mlp_backward(int B, int n_layers, const int* dims, const float* params, const float* x, const float* y,
+                       int bf16, double* grad, double* z);
+void or_adam(int64_t n, float* w, float* m, float* v, const double* g, double lr, double b1, double b2, double eps,
+             int t);
+
 /* fp16 / bf16 round trips (round to nearest even) */
 float or_round_f16(float x);
 float or_round_bf16(float x);

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libvm3dgs.so")
 VM3DGS_FLAG_LINKS = 1
 VM3DGS_FLAG_FULL_SCENE_COPY = 2
 VM3DGS_FLAG_BLEND_STATS = 4
+VM3DGS_FLAG_SIGMA3_TILES = 8
 
 _ERRORS = {-1: "INVALID_ARG", -2: "HOST_OOM", -3: "DEVICE_OOM", -4: "HIP", -5: "STATE", -6: "CAPACITY"}
 
@@ -103,6 +104,23 @@ def lib():
         L.vm3dgs_pages_get.argtypes = [C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64]
         L.vm3dgs_pages_get.restype = C.c_int64
         L.vm3dgs_pages_destroy.argtypes = [C.c_void_p]
+        vp, u32 = C.c_void_p, C.c_uint32
+        for name, args in [("vm3dgs_mlp_create", [vp, u32, u32, vp, C.POINTER(vp)]),
+                           ("vm3dgs_mlp_set_params", [vp, vp, C.c_uint64]),
+                           ("vm3dgs_mlp_get_state", [vp, vp, vp, vp, C.c_uint64, vp]),
+                           ("vm3dgs_mlp_forward", [vp, vp, u32, vp]),
+                           ("vm3dgs_mlp_gradient", [vp, vp, vp, u32, vp, vp]),
+                           ("vm3dgs_mlp_train_step", [vp, vp, vp, u32, C.c_float, vp]),
+                           ("vm3dgs_mlp_sync", [vp])]:
+            getattr(L, name).argtypes = args
+            getattr(L, name).restype = C.c_int32
+        L.vm3dgs_mlp_create_error.argtypes = []
+        L.vm3dgs_mlp_create_error.restype = C.c_char_p
+        L.vm3dgs_mlp_last_error.argtypes = [vp]
+        L.vm3dgs_mlp_last_error.restype = C.c_char_p
+        L.vm3dgs_mlp_n_params.argtypes = [vp]
+        L.vm3dgs_mlp_n_params.restype = C.c_uint64
+        L.vm3dgs_mlp_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -249,6 +267,78 @@ class Renderer:
     def close(self):
         if self.h:
             vm3dgs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ prefetch network
+class Mlp:
+    """The page-prefetch network of the library (vm3dgs_mlp_*): device
+    memory of inputs, labels and outputs comes from torch tensors."""
+
+    def __init__(self, dims, max_batch, stream=None):
+        import torch
+        if stream is None:   # torch's current stream: inputs written by torch are ordered before the network
+            stream = torch.cuda.current_stream().cuda_stream
+        self.dims = [int(d) for d in dims]
+        arr = (C.c_uint32 * len(self.dims))(*self.dims)
+        h = C.c_void_p()
+        rc = lib().vm3dgs_mlp_create(arr, len(self.dims) - 1, int(max_batch), stream, C.byref(h))
+        if rc != 0:
+            raise Vm3dgsError(rc, lib().vm3dgs_mlp_create_error().decode())
+        self.h = h
+        self.n_params = int(lib().vm3dgs_mlp_n_params(h))
+
+    def _check(self, rc):
+        if rc != 0:
+            raise Vm3dgsError(rc, lib().vm3dgs_mlp_last_error(self.h).decode())
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(lib().vm3dgs_mlp_set_params(self.h, p.ctypes.data, p.size))
+
+    def get_state(self):
+        n = self.n_params
+        p, m, v = np.zeros(n, np.float32), np.zeros(n, np.float32), np.zeros(n, np.float32)
+        step = C.c_uint32()
+        self._check(lib().vm3dgs_mlp_get_state(self.h, p.ctypes.data, m.ctypes.data, v.ctypes.data, n,
+                                               C.byref(step)))
+        return p, m, v, step.value
+
+    def forward(self, x):
+        import torch
+        x = x.contiguous()
+        z = torch.empty((x.shape[0], self.dims[-1]), dtype=torch.float32, device=x.device)
+        self._check(lib().vm3dgs_mlp_forward(self.h, x.data_ptr(), x.shape[0], z.data_ptr()))
+        self.sync()
+        return z
+
+    def gradient(self, x, y):
+        import torch
+        x, y = x.contiguous(), y.contiguous()
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        loss = C.c_float()
+        self._check(lib().vm3dgs_mlp_gradient(self.h, x.data_ptr(), y.data_ptr(), x.shape[0], g.data_ptr(),
+                                              C.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, x, y, lr, want_loss=True):
+        loss = C.c_float()
+        self._check(lib().vm3dgs_mlp_train_step(self.h, x.data_ptr(), y.data_ptr(), x.shape[0], float(lr),
+                                                C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def sync(self):
+        self._check(lib().vm3dgs_mlp_sync(self.h))
+
+    def close(self):
+        if self.h:
+            lib().vm3dgs_mlp_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -67,7 +67,7 @@ struct vm3dgs {
     uint32_t* d_offs = nullptr;
     uint64_t cap_pairs = 0;
     uint32_t* d_pkey[2] = {nullptr, nullptr}; uint32_t* d_pval[2] = {nullptr, nullptr};
-    uint2* d_ranges = nullptr;
+    uint2* d_ranges = nullptr; uint32_t* d_tile_order = nullptr;
     uint32_t* d_temp = nullptr; size_t temp_words = 0;
     // zero block: counters | look-back error flag | tickets | histograms (cleared per frame)
     uint32_t* d_zero = nullptr;
@@ -159,7 +159,7 @@ void free_all(vm3dgs* c) {
     dfree(c->d_rlist); dfree(c->d_rlist_full);
     dfree(c->d_xy); dfree(c->d_conic); dfree(c->d_rgb); dfree(c->d_depth); dfree(c->d_rect); dfree(c->d_tiles);
     for (int i = 0; i < 2; ++i) { dfree(c->d_dkey[i]); dfree(c->d_dval[i]); dfree(c->d_pkey[i]); dfree(c->d_pval[i]); }
-    dfree(c->d_offs); dfree(c->d_ranges); dfree(c->d_temp); dfree(c->d_total); hfree(c->h_total);
+    dfree(c->d_offs); dfree(c->d_ranges); dfree(c->d_tile_order); dfree(c->d_temp); dfree(c->d_total); hfree(c->h_total);
     dfree(c->d_zero); dfree(c->d_status); dfree(c->d_bstats); hfree(c->h_bstats);
     if (c->ev_copy) hipEventDestroy(c->ev_copy);
     for (auto& e : c->ev)
@@ -223,6 +223,7 @@ void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool,
     a.rl = rl; a.n_rl = (int)n_rl; a.pool = pool; a.P = c->P; a.fmt = c->ps.fmt;
     a.cams = c->d_cams; a.n_views = (int)n_views; a.W = (int)c->opt.img_w; a.H = (int)c->opt.img_h;
     a.TX = c->TX; a.TY = c->TY; a.n_render = n_render;
+    a.sigma3_tiles = (c->opt.flags & VM3DGS_FLAG_SIGMA3_TILES) ? 1 : 0;
     a.xy = c->d_xy; a.conic = c->d_conic; a.rgb = c->d_rgb; a.depth = c->d_depth; a.rect = c->d_rect;
     a.tiles = c->d_tiles; a.dkey = c->d_dkey[0]; a.dval = c->d_dval[0];
     launch_preprocess(c->sr, a);
@@ -242,10 +243,11 @@ void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool,
     const uint32_t n_tiles = (uint32_t)(c->TX * c->TY) * n_views;
     const int pb = onesweep_u32(c->sr, c->sw, c->d_pkey, c->d_pval, n_pairs, 0, std::max(1, bits_for(n_tiles)));
     launch_ranges(c->sr, c->d_pkey[pb], n_pairs, c->d_ranges, n_tiles);
+    launch_tile_order(c->sr, c->d_ranges, n_tiles, c->d_tile_order);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[5], c->sr));
     const bool bstats = (c->opt.flags & VM3DGS_FLAG_BLEND_STATS) != 0;
-    launch_blend(c->sr, c->d_ranges, c->d_pval[pb], c->d_xy, c->d_conic, c->d_rgb, (int)c->opt.img_w,
+    launch_blend(c->sr, c->d_ranges, c->d_tile_order, c->d_pval[pb], c->d_xy, c->d_conic, c->d_rgb, (int)c->opt.img_w,
                  (int)c->opt.img_h, c->TX, c->TY, (int)n_views, image, bstats ? c->d_bstats : nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[6], c->sr));
@@ -421,6 +423,7 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         dalloc(&c->d_rect, R); dalloc(&c->d_tiles, R); dalloc(&c->d_offs, R + 1);
         for (int i = 0; i < 2; ++i) { dalloc(&c->d_dkey[i], R); dalloc(&c->d_dval[i], R); }
         dalloc(&c->d_ranges, (size_t)c->TX * c->TY * V);
+        dalloc(&c->d_tile_order, (size_t)c->TX * c->TY * V);
         dalloc(&c->d_bstats, (size_t)c->TX * c->TY * V); halloc(&c->h_bstats, (size_t)c->TX * c->TY * V);
         dalloc(&c->d_total, 4); halloc(&c->h_total, 4);  // [0] pairs, [1] look-back error
         c->cap_pairs = 0;
@@ -769,7 +772,7 @@ int64_t vm3dgs_debug_get(vm3dgs* c, const char* name, void* dst, int64_t cap) {
     if (n == "render_list") return dev(c->d_rlist, 16 * (int64_t)c->last_n_rl);
     const int64_t nt = (int64_t)c->last_n_render * c->last_views;
     if (n == "pp_float") {
-        const int64_t bytes = 40 * nt;
+        const int64_t bytes = 44 * nt;
         if (dst && cap >= bytes) {
             std::vector<float2> xy((size_t)nt);
             std::vector<float4> co((size_t)nt), rgb((size_t)nt);
@@ -780,7 +783,8 @@ int64_t vm3dgs_debug_get(vm3dgs* c, const char* name, void* dst, int64_t cap) {
             hipMemcpy(rgb.data(), c->d_rgb, 16 * nt, hipMemcpyDeviceToHost);
             hipMemcpy(dep.data(), c->d_depth, 4 * nt, hipMemcpyDeviceToHost);
             for (int64_t i = 0; i < nt; ++i) {
-                float* f = (float*)dst + 10 * i;
+                float* f = (float*)dst + 11 * i;
+                f[10] = rgb[(size_t)i].w;
                 float d;
                 memcpy(&d, &dep[(size_t)i], 4);
                 f[0] = xy[(size_t)i].x; f[1] = xy[(size_t)i].y; f[2] = d;

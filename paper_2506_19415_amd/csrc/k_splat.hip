@@ -10,6 +10,9 @@
 //                its 64 Gaussians over its lanes (prefix sums of the counts)
 //                and writes (tile, Gaussian) pairs coalesced.
 //  k_ranges      [start, end) of every tile in the tile-sorted pairs.
+//  k_tile_order  blend order of the tiles: by decreasing power-of-two class
+//                of their pair counts, so that the longest tiles start first
+//                and the short ones fill in behind them.
 //  k_blend       one 256-thread workgroup per 16x16 tile, one pixel per
 //                thread; Gaussians staged in LDS in batches of 256; per pixel
 //                front-to-back
@@ -60,6 +63,7 @@ struct PreArgs {
     const CamK* cams;
     int W, H, TX, TY;
     uint32_t n_render; uint64_t n_total;
+    int sigma3_tiles;
     float2* xy; float4* conic; float4* rgb; uint32_t* depth; uint2* rect; uint32_t* tiles;
     uint32_t* dkey; uint32_t* dval;
 };
@@ -86,6 +90,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
     ok = ok && (t.z > c.znear);
     float u = 0.f, vv = 0.f, ca = 0.f, cb = 0.f, cc2 = 0.f;
     int ix0 = 0, iy0 = 0, ix1 = 0, iy1 = 0;
+    float hy = __builtin_inff();
     float col[3] = {0.f, 0.f, 0.f};
     if (ok) {
         const float w = g.q[0], x = g.q[1], y = g.q[2], z = g.q[3];
@@ -140,12 +145,31 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
             const float rad = ceilf(3.0f * sqrtf(lam));
             u = (c.fx * t.x) / t.z + (c.cx - 0.5f);
             vv = (c.fy * t.y) / t.z + (c.cy - 0.5f);
-            const float x0 = fminf(fmaxf(floorf((u - rad) / 16.0f), 0.0f), (float)a.TX);
-            const float x1 = fminf(fmaxf(floorf(((u + rad) + 15.0f) / 16.0f), 0.0f), (float)a.TX);
-            const float y0 = fminf(fmaxf(floorf((vv - rad) / 16.0f), 0.0f), (float)a.TY);
-            const float y1 = fminf(fmaxf(floorf(((vv + rad) + 15.0f) / 16.0f), 0.0f), (float)a.TY);
+            float x0 = fminf(fmaxf(floorf((u - rad) / 16.0f), 0.0f), (float)a.TX);
+            float x1 = fminf(fmaxf(floorf(((u + rad) + 15.0f) / 16.0f), 0.0f), (float)a.TX);
+            float y0 = fminf(fmaxf(floorf((vv - rad) / 16.0f), 0.0f), (float)a.TY);
+            float y1 = fminf(fmaxf(floorf(((vv + rad) + 15.0f) / 16.0f), 0.0f), (float)a.TY);
+            // support box: outside it the blend's power is below -5.55 even
+            // with the rounding of its float evaluation (bounded through
+            // kap = (A + Cc)^2 / det); ill-conditioned footprints keep the
+            // 3-sigma rectangle
+            if (!a.sigma3_tiles) {
+                const float kap = ((A + Cc) * (A + Cc)) / det;
+                const float e = 5e-7f * kap;
+                if (e < 0.5f) {
+                    const float fm = 1.0f / (1.0f - e);
+                    const float hx = sqrtf((11.11f * fm) * A) + 1.0f;
+                    hy = sqrtf((11.11f * fm) * Cc) + 1.0f;
+                    const float bx0 = fminf(fmaxf(floorf((u - hx) / 16.0f), 0.0f), (float)a.TX);
+                    const float bx1 = fminf(fmaxf(floorf((u + hx) / 16.0f) + 1.0f, 0.0f), (float)a.TX);
+                    const float by0 = fminf(fmaxf(floorf((vv - hy) / 16.0f), 0.0f), (float)a.TY);
+                    const float by1 = fminf(fmaxf(floorf((vv + hy) / 16.0f) + 1.0f, 0.0f), (float)a.TY);
+                    x0 = fmaxf(x0, bx0); x1 = fminf(x1, bx1);
+                    y0 = fmaxf(y0, by0); y1 = fminf(y1, by1);
+                }
+            }
             ix0 = (int)x0; ix1 = (int)x1; iy0 = (int)y0; iy1 = (int)y1;
-            ok = (ix1 - ix0) * (iy1 - iy0) != 0;
+            ok = ix1 > ix0 && iy1 > iy0;
             ca = Cc * inv; cb = -B * inv; cc2 = A * inv;
         }
         if (ok) {
@@ -183,7 +207,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
     }
     a.xy[f] = make_float2(u, vv);
     a.conic[f] = make_float4(ca, cb, cc2, ok ? g.o : 0.0f);
-    a.rgb[f] = make_float4(col[0], col[1], col[2], 0.0f);
+    a.rgb[f] = make_float4(col[0], col[1], col[2], ok ? hy : __builtin_inff());
     a.depth[f] = ok ? __float_as_uint(t.z) : NONE32;
     a.rect[f] = ok ? make_uint2((uint32_t)ix0 | ((uint32_t)iy0 << 16), (uint32_t)ix1 | ((uint32_t)iy1 << 16))
                    : make_uint2(0u, 0u);
@@ -250,6 +274,33 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
     }
 }
 
+constexpr int TO_NT = 1024;
+
+__global__ __launch_bounds__(TO_NT) void k_tile_order(const uint2* __restrict__ ranges, uint32_t n_tiles,
+                                                      uint32_t* __restrict__ order) {
+    __shared__ uint32_t cnt[33];
+    if (threadIdx.x < 33) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < n_tiles; t += TO_NT) {
+        const uint2 r = ranges[t];
+        atomicAdd(&cnt[32 - __clz(r.y - r.x)], 1u);   // class 0: empty, c: count in [2^(c-1), 2^c)
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int c = 32; c >= 0; --c) {
+            const uint32_t k = cnt[c];
+            cnt[c] = acc;
+            acc += k;
+        }
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < n_tiles; t += TO_NT) {
+        const uint2 r = ranges[t];
+        order[atomicAdd(&cnt[32 - __clz(r.y - r.x)], 1u)] = t;
+    }
+}
+
 __global__ void k_ranges(const uint32_t* __restrict__ key, uint32_t n, uint2* __restrict__ ranges) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -266,7 +317,8 @@ __global__ void k_ranges(const uint32_t* __restrict__ key, uint32_t n, uint2* __
 constexpr int BL_NT = TILE * TILE;
 
 template <bool STATS>
-__global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ ranges, const uint32_t* __restrict__ pval,
+__global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ ranges, const uint32_t* __restrict__ order,
+                                                 const uint32_t* __restrict__ pval,
                                                  const float2* __restrict__ xy, const float4* __restrict__ conic,
                                                  const float4* __restrict__ rgb, int W, int H, int TX, int TY,
                                                  float* __restrict__ image, uint2* __restrict__ stats) {
@@ -274,7 +326,7 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
     __shared__ float4 s_co[BL_NT];
     __shared__ float4 s_rgb[BL_NT];
     __shared__ uint32_t s_st[2][BL_NT / WAVE];
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = order[blockIdx.x];
     const uint32_t per_view = (uint32_t)(TX * TY);
     const uint32_t view = tile / per_view;
     const uint32_t t = tile - view * per_view;
@@ -285,6 +337,9 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
     bool done = !inside;
     const uint2 rg = ranges[tile];
     const float fpx = (float)px, fpy = (float)py;
+    // centre row of this wave's 16 x 4 strip: a Gaussian whose support box
+    // misses the strip's rows is rejected by every pixel of the strip
+    const float strip_c = (float)(ty * TILE + (int)(threadIdx.x / WAVE) * (WAVE / TILE)) + 1.5f;
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     uint32_t n_eval = 0, n_alpha = 0;
     for (uint32_t base = rg.x; base < rg.y; base += BL_NT) {
@@ -300,6 +355,8 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
         const int cnt = (int)min((uint32_t)BL_NT, rg.y - base);
         for (int k = 0; k < cnt && !done; ++k) {
             const float2 p = s_xy[k];
+            const float hy = s_rgb[k].w;
+            if (!(fabsf(p.y - strip_c) <= hy + 1.5f)) continue;
             const float4 co = s_co[k];
             const float dx = p.x - fpx, dy = p.y - fpy;
             const float q = fmaf(co.x * dx, dx, (co.z * dy) * dy);
@@ -349,6 +406,7 @@ void launch_preprocess(hipStream_t st, const SplatArgs& s) {
     a.rl = s.rl; a.n_rl = s.n_rl; a.pool = s.pool; a.fmt = s.fmt; a.bytes_g = s.fmt == 1 ? 124 : 236;
     a.cams = s.cams; a.W = s.W; a.H = s.H; a.TX = s.TX; a.TY = s.TY;
     a.n_render = s.n_render; a.n_total = (uint64_t)s.n_render * s.n_views;
+    a.sigma3_tiles = s.sigma3_tiles;
     a.xy = s.xy; a.conic = s.conic; a.rgb = s.rgb; a.depth = s.depth; a.rect = s.rect; a.tiles = s.tiles;
     a.dkey = s.dkey; a.dval = s.dval;
     if (a.n_total == 0 || s.n_rl == 0) return;
@@ -368,15 +426,20 @@ void launch_ranges(hipStream_t st, const uint32_t* pkey, uint32_t n_pairs, uint2
         hipLaunchKernelGGL(k_ranges, dim3(nblk(n_pairs, 256)), dim3(256), 0, st, pkey, n_pairs, ranges);
 }
 
-void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* pval, const float2* xy, const float4* conic,
-                  const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image, uint2* stats) {
+void launch_tile_order(hipStream_t st, const uint2* ranges, uint32_t n_tiles, uint32_t* order) {
+    if (n_tiles) hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(TO_NT), 0, st, ranges, n_tiles, order);
+}
+
+void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* order, const uint32_t* pval, const float2* xy,
+                  const float4* conic, const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image,
+                  uint2* stats) {
     const uint32_t n_tiles = (uint32_t)(TX * TY * n_views);
     if (stats)
-        hipLaunchKernelGGL(k_blend<true>, dim3(n_tiles), dim3(BL_NT), 0, st, ranges, pval, xy, conic, rgb, W, H, TX,
-                           TY, image, stats);
+        hipLaunchKernelGGL(k_blend<true>, dim3(n_tiles), dim3(BL_NT), 0, st, ranges, order, pval, xy, conic, rgb, W, H,
+                           TX, TY, image, stats);
     else
-        hipLaunchKernelGGL(k_blend<false>, dim3(n_tiles), dim3(BL_NT), 0, st, ranges, pval, xy, conic, rgb, W, H, TX,
-                           TY, image, stats);
+        hipLaunchKernelGGL(k_blend<false>, dim3(n_tiles), dim3(BL_NT), 0, st, ranges, order, pval, xy, conic, rgb, W,
+                           H, TX, TY, image, stats);
 }
 
 }  // namespace vm

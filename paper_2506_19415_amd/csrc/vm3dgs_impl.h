@@ -153,6 +153,7 @@ struct SplatArgs {
     const CamK* cams; int n_views;
     int W, H, TX, TY;
     uint32_t n_render;  // per view
+    int sigma3_tiles;   // 1: 3-sigma tile rectangles only (no support box)
     float2* xy; float4* conic; float4* rgb; uint32_t* depth; uint2* rect; uint32_t* tiles;
     uint32_t* dkey; uint32_t* dval;
 };
@@ -160,9 +161,38 @@ void launch_preprocess(hipStream_t st, const SplatArgs& a);
 void launch_emit(hipStream_t st, const uint32_t* order, const uint32_t* offsets, const uint2* rect, uint32_t n_total,
                  uint32_t n_render, int TX, int TY, uint32_t* pkey, uint32_t* pval, uint32_t cap);
 void launch_ranges(hipStream_t st, const uint32_t* pkey, uint32_t n_pairs, uint2* ranges, uint32_t n_tiles);
-void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* pval, const float2* xy, const float4* conic,
-                  const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image, uint2* stats);
+void launch_tile_order(hipStream_t st, const uint2* ranges, uint32_t n_tiles, uint32_t* order);
+void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* order, const uint32_t* pval, const float2* xy,
+                  const float4* conic, const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image,
+                  uint2* stats);
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v);
 void launch_fill_u64(hipStream_t st, unsigned long long* p, uint64_t n, unsigned long long v);
+
+
+// ---------------------------------------------------------------- prefetch network
+// Device state of the network (k_mlp.hip).  Layer l maps dims[l] -> dims[l+1];
+// act[l] is its bf16 input [b_pad][kpad[l]] (kpad = dims rounded up to 32,
+// the padding columns and the rows past the batch are zero), dz[l] the bf16
+// gradient of its output [b_pad][dims[l+1]], wb[l] its bf16 weights
+// [kpad[l]][dims[l+1]] (padding rows zero).  master/adam_m/adam_v/grad use
+// the parameter layout: per layer W [dims[l]][dims[l+1]] then b.
+struct MlpDev {
+    int n_layers = 0;
+    int dims[9] = {};
+    int kpad[9] = {};
+    int64_t off[9] = {};
+    int b_pad = 0;
+    float* master = nullptr; float* adam_m = nullptr; float* adam_v = nullptr; float* grad = nullptr;
+    uint16_t* wb[8] = {};
+    uint16_t* act[8] = {};
+    uint16_t* dz[8] = {};
+    float* logits = nullptr;
+    float* loss_part = nullptr;
+};
+void mlp_input_dev(hipStream_t st, const MlpDev& d, const float* x, int B);
+void mlp_forward_dev(hipStream_t st, const MlpDev& d, int B);
+void mlp_backward_dev(hipStream_t st, const MlpDev& d, const float* y, int B);
+void mlp_adam_dev(hipStream_t st, const MlpDev& d, float lr, float b1, float b2, float eps, int t);
+void mlp_sync_bf16_dev(hipStream_t st, const MlpDev& d);
 
 }  // namespace vm

@@ -1,0 +1,103 @@
+"""The prefetch network's kernels (bf16 matrix-core products, fp32
+accumulation) against the oracle (double sums on the same bf16-rounded
+operands): logits within 1e-2 and gradients within 2e-2 of the largest
+magnitude of each layer, one Adam step, and a loss that falls."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+FULL = [540, 256, 256, 256, 4096]
+
+
+def _params(dims, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for l in range(len(dims) - 1):
+        out.append((rng.standard_normal(dims[l] * dims[l + 1]) * np.sqrt(2.0 / dims[l])).astype(np.float32))
+        out.append((rng.standard_normal(dims[l + 1]) * 0.1).astype(np.float32))
+    return np.concatenate(out)
+
+
+def _data(dims, B, seed, pos=0.1):
+    rng = np.random.default_rng(seed + 100)
+    x = rng.standard_normal((B, dims[0])).astype(np.float32)
+    y = (rng.random((B, dims[-1])) < pos).astype(np.float32)
+    return x, y
+
+
+def _layers(dims):
+    o = 0
+    for l in range(len(dims) - 1):
+        n = dims[l] * dims[l + 1] + dims[l + 1]
+        yield l, slice(o, o + n)
+        o += n
+
+
+@pytest.mark.parametrize("dims,B", [([40, 64, 32], 5), ([70, 96, 96, 130], 67), (FULL, 8), (FULL, 100)])
+def test_forward_and_gradient(dims, B):
+    import torch
+    import paper_2506_19415_amd as pkg
+    print(f"mlp dims {dims} batch {B}", flush=True)
+    p = _params(dims, 1)
+    x, y = _data(dims, B, 1)
+    net = pkg.Mlp(dims, max_batch=max(B, 16))
+    net.set_params(p)
+    xd, yd = torch.tensor(x, device="cuda"), torch.tensor(y, device="cuda")
+    z = net.forward(xd).cpu().numpy()
+    loss_o, g_o, z_o = oracle.mlp_backward(p, dims, x, y, bf16=True)
+    assert np.abs(z - z_o).max() <= 1e-2 * np.abs(z_o).max()
+    g, loss = net.gradient(xd, yd)
+    net.sync()
+    g = g.cpu().numpy()
+    assert loss == pytest.approx(loss_o, rel=1e-4)
+    for l, sl in _layers(dims):
+        ref = g_o[sl]
+        assert np.abs(g[sl] - ref).max() <= 2e-2 * np.abs(ref).max(), l
+    net.close()
+
+
+def test_adam_step_matches_oracle():
+    import torch
+    import paper_2506_19415_amd as pkg
+    dims, B, lr = [64, 128, 64, 256], 40, 1e-3
+    p = _params(dims, 2)
+    x, y = _data(dims, B, 2)
+    net = pkg.Mlp(dims, max_batch=B)
+    net.set_params(p)
+    net.train_step(torch.tensor(x, device="cuda"), torch.tensor(y, device="cuda"), lr)
+    w, m, v, step = net.get_state()
+    assert step == 1
+    _, g_o, _ = oracle.mlp_backward(p, dims, x, y, bf16=True)
+    wo, mo, vo = p.copy(), np.zeros_like(p), np.zeros_like(p)
+    oracle.adam(wo, mo, vo, g_o, lr, 0.9, 0.999, 1e-8, 1)
+    for l, sl in _layers(dims):
+        big = np.abs(g_o[sl]) > 0.05 * np.abs(g_o[sl]).max()   # where the sign of the step is certain
+        assert np.allclose(w[sl][big], wo[sl][big], rtol=0, atol=lr * 0.05), l
+        assert np.allclose(m[sl], mo[sl], rtol=0, atol=0.02 * np.abs(mo[sl]).max()), l
+        assert np.all(np.abs(w[sl] - p[sl]) <= lr * 1.0001 + 1e-7), l    # |step| <= lr at step 1
+    net.close()
+
+
+def test_training_lowers_the_loss():
+    """A learnable target: labels from a fixed random linear map of the
+    inputs; 300 Adam steps on the GPU cut the loss well below its start."""
+    import torch
+    import paper_2506_19415_amd as pkg
+    dims, B = [96, 128, 128, 64], 256
+    rng = np.random.default_rng(5)
+    T = rng.standard_normal((dims[0], dims[-1])).astype(np.float32)
+    net = pkg.Mlp(dims, max_batch=B)
+    net.set_params(_params(dims, 5))
+    first = last = None
+    for it in range(300):
+        x = rng.standard_normal((B, dims[0])).astype(np.float32)
+        y = ((x @ T) > 0.5 * np.sqrt(dims[0])).astype(np.float32)
+        loss = net.train_step(torch.tensor(x, device="cuda"), torch.tensor(y, device="cuda"), 2e-3)
+        if it == 0:
+            first = loss
+        last = loss
+    assert last < 0.5 * first, (first, last)
+    net.close()

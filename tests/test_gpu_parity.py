@@ -58,8 +58,8 @@ def compare_frame(r, ovm, out, n_views, check_image=True, tag=""):
 
 def compare_splat(r, ovm, n_views, check_image=True, tag=""):
     g = r.get
-    pf, pi = g("pp_float", np.float32).reshape(-1, 10), g("pp_int", np.int32).reshape(-1, 6)
-    of, oi = ovm.get("pp_float").reshape(-1, 10), ovm.get("pp_int").reshape(-1, 6)
+    pf, pi = g("pp_float", np.float32).reshape(-1, 11), g("pp_int", np.int32).reshape(-1, 6)
+    of, oi = ovm.get("pp_float").reshape(-1, 11), ovm.get("pp_int").reshape(-1, 6)
     assert pf.shape == of.shape, tag
     assert np.array_equal(pi[:, 0], oi[:, 0]), tag           # culled
     vis = oi[:, 0] == 0
@@ -67,6 +67,7 @@ def compare_splat(r, ovm, n_views, check_image=True, tag=""):
     assert np.array_equal(pf[vis, 2].view(np.uint32), of[vis, 2].view(np.uint32)), tag   # depth keys
     assert np.array_equal(pf[vis, :2], of[vis, :2]), tag      # pixel centre
     np.testing.assert_allclose(pf[vis, 3:10], of[vis, 3:10], rtol=1e-5, atol=1e-7, err_msg=tag)
+    assert np.array_equal(pf[vis, 10], of[vis, 10]), tag     # support-box half height
     n_render = pf.shape[0] // n_views
     keys, vals = g("keys", np.uint32), g("vals", np.uint32)
     okeys, ovals = ovm.get("keys"), ovm.get("vals")
@@ -233,8 +234,8 @@ def test_terrain6m_full_size_sampled():
             assert np.array_equal(g(name, dt), ovm.get(name)), (k, name)
         req = np.ctypeslib.as_array(out.requests, (out.n_requests,))
         assert np.array_equal(req, ovm.get("req_page")), k
-        pf, pi = g("pp_float", np.float32).reshape(-1, 10), g("pp_int", np.int32).reshape(-1, 6)
-        of, oi = ovm.get("pp_float").reshape(-1, 10), ovm.get("pp_int").reshape(-1, 6)
+        pf, pi = g("pp_float", np.float32).reshape(-1, 11), g("pp_int", np.int32).reshape(-1, 6)
+        of, oi = ovm.get("pp_float").reshape(-1, 11), ovm.get("pp_int").reshape(-1, 6)
         assert np.array_equal(pi[:, 0], oi[:, 0]), k
         vis = oi[:, 0] == 0
         assert np.array_equal(pi[vis], oi[vis]), k

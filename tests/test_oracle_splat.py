@@ -78,7 +78,7 @@ def test_ewa_conic_vs_finite_difference(mean, scale, quat):
     q /= np.linalg.norm(q)
     sc = one_gaussian_scene(mean, scale, q)
     vm = render(sc, cam, W, H)
-    f = vm.get("pp_float").reshape(-1, 10)[0]
+    f = vm.get("pp_float").reshape(-1, 11)[0]
     mu = np.array(mean, np.float64)
 
     def proj(p):
@@ -109,7 +109,7 @@ def test_sh_colour_matches_basis():
         sh = np.zeros((16, 3), np.float32)
         sh[k] = [0.9, -0.7, 0.3]
         vm = render(one_gaussian_scene(mean, [0.05] * 3, sh=sh[None]), cam, W, H)
-        rgb = vm.get("pp_float").reshape(-1, 10)[0, 7:10]
+        rgb = vm.get("pp_float").reshape(-1, 11)[0, 7:10]
         ref = np.maximum(oracle.sh_basis(k, *d) * sh[k].astype(np.float64) + 0.5, 0.0)
         assert np.allclose(rgb, ref, atol=2e-6), (k, rgb, ref)
 
@@ -142,7 +142,7 @@ def test_transmittance_invariants(cluster_frame):
     T = vm.get("final_T")
     img = vm.get("image").reshape(-1, 3)
     assert T.min() >= 1e-4 and T.max() <= 1.0
-    pf = vm.get("pp_float").reshape(-1, 10)
+    pf = vm.get("pp_float").reshape(-1, 11)
     pi = vm.get("pp_int").reshape(-1, 6)
     max_rgb = pf[pi[:, 0] == 0, 7:10].max()
     assert np.all(img.max(1) <= max_rgb * (1.0 - T) + 1e-5)
@@ -154,7 +154,7 @@ def test_transmittance_invariants(cluster_frame):
 def test_tile_lists_brute_force(cluster_frame):
     vm = cluster_frame
     TX, TY = vm.TX, vm.TY
-    pf = vm.get("pp_float").reshape(-1, 10)
+    pf = vm.get("pp_float").reshape(-1, 11)
     pi = vm.get("pp_int").reshape(-1, 6)
     keys = vm.get("keys")
     vals = vm.get("vals")
@@ -168,3 +168,86 @@ def test_tile_lists_brute_force(cluster_frame):
         s, e = ranges[t]
         assert np.array_equal(vals[s:e], order)
         assert np.all((keys[s:e] >> np.uint64(32)) == t)
+
+
+def needle_scene(seed=3, n=3000):
+    """Anisotropic Gaussians (axis ratios up to 500), random orientations and
+    opacities, in front of the identity camera: footprints from sub-pixel
+    dots to long thin needles at every angle."""
+    rng = np.random.default_rng(seed)
+    means = np.stack([rng.uniform(-2.0, 2.0, n), rng.uniform(-1.5, 1.5, n), rng.uniform(2.5, 9.0, n)], 1)
+    scales = np.exp(rng.uniform(np.log(0.002), np.log(0.6), (n, 3)))
+    q = rng.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    sh = rng.normal(0.0, 0.6, (n, 16, 3))
+    return synth.Scene(means.astype(np.float32), scales.astype(np.float32), q.astype(np.float32),
+                       rng.uniform(0.02, 1.0, n).astype(np.float32), sh.astype(np.float32))
+
+
+def _render_both(osc, cams, W, H):
+    out = []
+    for sigma3 in (True, False):
+        vm = oracle.OracleVM(osc, 4096, (W, H), (W // 4, H // 4))
+        vm.set_sigma3_tiles(sigma3)
+        res = []
+        for cam in cams:
+            vm.render_full([cam])
+            res.append((vm.image()[0].copy(), vm.get("final_T").copy(), vm.get("contrib").copy(),
+                        vm.get("keys").size, vm.get("pp_float").reshape(-1, 11), vm.get("pp_int").reshape(-1, 6)))
+        out.append(res)
+    return out
+
+
+@pytest.mark.parametrize("which", ["needles", "clusters"])
+def test_support_box_keeps_the_image(which):
+    """Cutting the tile rectangles to the support box drops only pairs whose
+    every pixel fails the alpha test: image, transmittance and per-pixel
+    contributor counts are bit-identical to the 3-sigma rectangles, with
+    fewer pairs."""
+    if which == "needles":
+        W, H = 192, 144
+        osc = oracle.OracleScene(needle_scene(), 1, 1, 0.5, 2.0)
+        cams = [identity_cam(W, H)]
+    else:
+        W, H = 320, 240
+        osc = oracle.OracleScene(synth.scene_clusters(0), 256, 1, 0.5, 2.0)
+        cams = synth.orbit()[::3]
+    sig3, box = _render_both(osc, cams, W, H)
+    for (i3, t3, c3, n3, _, _), (ib, tb, cb, nb, _, _) in zip(sig3, box):
+        assert np.array_equal(i3, ib) and np.array_equal(t3, tb) and np.array_equal(c3, cb)
+        assert nb < n3
+
+
+def test_support_box_contains_the_accepted_region():
+    """Brute force in float64: every pixel of the 3-sigma rectangle where the
+    quadratic form of the conic is at most 11.1 (power >= -5.55) lies in a
+    tile of the cut rectangle and within hy rows of the centre; the cut
+    rectangle never leaves the 3-sigma one."""
+    W, H = 192, 144
+    osc = oracle.OracleScene(needle_scene(), 1, 1, 0.5, 2.0)
+    (s3,), (bx,) = _render_both(osc, [identity_cam(W, H)], W, H)
+    pf, pi, pi3 = bx[4], bx[5], s3[5]
+    vis = np.nonzero(pi[:, 0] == 0)[0]
+    assert np.array_equal(pi[:, 0] == 0, (pi3[:, 0] == 0) & (pi[:, 0] == 0))
+    jj, ii = np.mgrid[0:H, 0:W].astype(np.float64)
+    n_tight = 0
+    for g in vis:
+        u, v = float(pf[g, 0]), float(pf[g, 1])
+        a, b, c = (float(x) for x in pf[g, 3:6])
+        dx, dy = u - ii, v - jj
+        q = a * dx * dx + 2.0 * b * dx * dy + c * dy * dy
+        t3 = (ii // 16 >= pi3[g, 1]) & (ii // 16 < pi3[g, 3]) & (jj // 16 >= pi3[g, 2]) & (jj // 16 < pi3[g, 4])
+        acc = (q <= 11.1) & t3
+        x0, y0, x1, y1 = pi[g, 1:5]
+        assert pi3[g, 1] <= x0 and pi3[g, 2] <= y0 and x1 <= pi3[g, 3] and y1 <= pi3[g, 4]
+        tx, ty = ii[acc] // 16, jj[acc] // 16
+        assert np.all((tx >= x0) & (tx < x1) & (ty >= y0) & (ty < y1)), g
+        hy = float(pf[g, 10])
+        assert np.all(np.abs(jj[acc] - v) <= hy), g
+        if np.isfinite(hy):
+            n_tight += 1
+            # the half height is the closed form sqrt(11.11 f Sigma'_yy) + 1
+            det = a * c - b * b
+            syy = a / det
+            assert hy >= math.sqrt(11.1 * syy) and hy <= math.sqrt(11.2 * syy) * 1.05 + 1.0 + 1e-3, g
+    assert n_tight > 0.9 * vis.size
