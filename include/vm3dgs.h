@@ -103,7 +103,7 @@ typedef struct {
     uint32_t hits, misses, evictions, missing, copies;
     uint32_t render_pages;      /* resident requested pages splatted this frame */
     uint32_t pool_pages_used;   /* physical pages holding at least one virtual page */
-    uint32_t reserved0;
+    uint32_t prefetched;        /* pages copied by the prefetch stage (not awaited by this frame) */
     uint64_t render_gaussians;  /* Gaussians in the render set (incl. padding) x views */
     uint64_t visible_gaussians; /* of those, not culled by the projection */
     uint64_t pairs;             /* (tile, Gaussian) pairs sorted and blended */
@@ -238,6 +238,40 @@ vm3dgs_status vm3dgs_mlp_train_step(vm3dgs_mlp* net, const float* x_dev, const f
                                     float lr, float* loss_host);
 vm3dgs_status vm3dgs_mlp_sync(vm3dgs_mlp* net);
 void vm3dgs_mlp_destroy(vm3dgs_mlp* net);
+
+/* ---- Learned page prefetch: the stage in the frame -----------------------
+ * Features of view v (28 + hist_bins floats): its last four camera poses,
+ * oldest first (position minus center, over extent; the camera-to-world
+ * rotation as a unit quaternion w x y z with w >= 0; the oldest pose repeats
+ * until four frames were seen), then the resident fraction (any level) of
+ * each of hist_bins equal page-id ranges, after the frame's demand stages.
+ * Clusters are n_clusters equal page-id ranges.  A page is proposed when the
+ * logit of its cluster exceeds logit_threshold for some view, the frame did
+ * not request it and it is not resident at the level its nearest distance
+ * (sphere centre distance minus radius, at least znear) gives.  Proposals are
+ * served nearest first after the demand misses, only into physical pages used
+ * in neither this frame nor the previous one (least recently used first), at
+ * most budget_pages per frame; their copies follow the demand copies on the
+ * copy stream, this frame does not wait for them or render them, and the
+ * next frame waits for them before it reads the pool. */
+typedef struct {
+    uint32_t n_clusters;        /* network outputs */
+    uint32_t hist_bins;         /* network inputs = 28 + hist_bins */
+    uint32_t budget_pages;      /* prefetch copies per frame */
+    float logit_threshold;
+    float center[3];
+    float extent;               /* > 0 */
+} vm3dgs_prefetch_opts;
+
+/* Attach the stage.  net may be NULL: then only the pose history is kept
+ * and vm3dgs_prefetch_features works (gathering training data).  The network
+ * must have dims[0] = 28 + hist_bins, n_clusters outputs and max_batch >=
+ * max_views, and must not be trained while frames use it.  Poses are
+ * recorded from the next frame on.  INVALID_ARG on a mismatch. */
+vm3dgs_status vm3dgs_set_prefetch(vm3dgs* ctx, vm3dgs_mlp* net, const vm3dgs_prefetch_opts* opts);
+/* Feature rows [n_views][28 + hist_bins] of the current state (the poses of
+ * the frames so far and the residency now) into host memory. */
+vm3dgs_status vm3dgs_prefetch_features(vm3dgs* ctx, uint32_t n_views, float* x_host);
 
 #ifdef __cplusplus
 }

@@ -43,6 +43,7 @@ void or_sh_color_f32(const float* sh, float x, float y, float z, float out[3]);
 #define NONE32 0xffffffffu
 #define NONE64 0xffffffffffffffffull
 #define SUBS 64
+#define OR_MAX_VIEWS 16
 
 typedef struct {
     int culled;
@@ -66,6 +67,17 @@ struct or_vm {
     int frame;
     int force_all;         /* test switch: every page is directly requested */
     int sigma3_tiles;      /* 1: tile rectangles from the 3-sigma radius alone (no support box) */
+    /* learned prefetch (Sec. 6 future work): configuration, pose history,
+     * the logits a frame is given and what the last frame did with them */
+    int pf_on, pf_K, pf_H, pf_budget;
+    float pf_thr, pf_center[3], pf_extent;
+    int pf_n_hist;                 /* poses pushed so far (saturates at 4) */
+    float pf_pose[OR_MAX_VIEWS][4][7];
+    const float* pf_logits;        /* [n_views][K] for the frame being run, or NULL */
+    const or_camera* pf_cams;      /* cameras of the frame being run */
+    int n_copy_demand, n_prefetch, n_pf_req;
+    uint64_t* pf_keys;             /* [n_pg] sorted prefetch request keys of the last frame */
+    float* pf_x;                   /* [n_views][28 + H] features the last frame computed */
     /* page table */
     int8_t* slot_level;
     int32_t* last_used;
@@ -247,6 +259,8 @@ static void assign(or_vm* vm, int32_t p, int lvl, int s, int j, uint8_t* req_sub
     vm->n_copy++;
 }
 
+static void prefetch_stage(or_vm* vm, uint8_t* req_sub, uint8_t* slot_req);
+
 static void page_table(or_vm* vm)
 {
     int S = vm->S, L = vm->L;
@@ -347,8 +361,165 @@ static void page_table(or_vm* vm)
         assign(vm, p, l, ts, tj, req_sub, slot_req);
     }
     (void)fresh;
+    vm->n_copy_demand = vm->n_copy;
+    vm->n_prefetch = 0;
+    vm->n_pf_req = 0;
+    if (vm->pf_on && vm->pf_logits) prefetch_stage(vm, req_sub, slot_req);
     for (int l = 0; l < 3; l++) { free(cl[l]); free(fresh_list[l]); }
     free(wl); free(miss); free(req_sub); free(slot_req);
+}
+
+/* ---- 5. learned prefetch -------------------------------------------------
+ * Features of a view: its last four camera poses (position relative to the
+ * scene centre over the extent, and the camera-to-world rotation as a unit
+ * quaternion with w >= 0; the oldest pose repeats until four were seen) and
+ * the resident fraction of each of H equal ranges of page ids.  Clusters are
+ * K equal ranges of page ids (Morton order, so spatially compact).  A page is
+ * proposed when some view's logit of its cluster exceeds the threshold, it is
+ * not requested by the visibility pass, and it is not resident at the level
+ * its distance gives.  Proposals are served after the demand misses, nearest
+ * first, into physical pages used in neither this frame nor the previous one
+ * (least recently used first), up to the prefetch budget; nothing proposed
+ * is rendered in this frame. */
+static void pose_of(const or_camera* c, const or_vm* vm, float* o)
+{
+    const float* V = c->view;
+    double M[3][3];                       /* camera to world: transpose of the view rotation */
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) M[i][j] = V[4 * j + i];
+    double w, x, y, z, tr = M[0][0] + M[1][1] + M[2][2];
+    if (tr > 0.0) {
+        double S = sqrt(tr + 1.0) * 2.0;
+        w = 0.25 * S; x = (M[2][1] - M[1][2]) / S; y = (M[0][2] - M[2][0]) / S; z = (M[1][0] - M[0][1]) / S;
+    } else if (M[0][0] > M[1][1] && M[0][0] > M[2][2]) {
+        double S = sqrt(1.0 + M[0][0] - M[1][1] - M[2][2]) * 2.0;
+        w = (M[2][1] - M[1][2]) / S; x = 0.25 * S; y = (M[0][1] + M[1][0]) / S; z = (M[0][2] + M[2][0]) / S;
+    } else if (M[1][1] > M[2][2]) {
+        double S = sqrt(1.0 + M[1][1] - M[0][0] - M[2][2]) * 2.0;
+        w = (M[0][2] - M[2][0]) / S; x = (M[0][1] + M[1][0]) / S; y = 0.25 * S; z = (M[1][2] + M[2][1]) / S;
+    } else {
+        double S = sqrt(1.0 + M[2][2] - M[0][0] - M[1][1]) * 2.0;
+        w = (M[1][0] - M[0][1]) / S; x = (M[0][2] + M[2][0]) / S; y = (M[1][2] + M[2][1]) / S; z = 0.25 * S;
+    }
+    double n = sqrt(w * w + x * x + y * y + z * z);
+    if (w < 0.0) n = -n;
+    for (int a = 0; a < 3; a++) o[a] = (float)(((double)c->cam_pos[a] - vm->pf_center[a]) / vm->pf_extent);
+    o[3] = (float)(w / n); o[4] = (float)(x / n); o[5] = (float)(y / n); o[6] = (float)(z / n);
+}
+
+static void push_poses(or_vm* vm, const or_camera* cams, int n_views)
+{
+    for (int v = 0; v < n_views && v < OR_MAX_VIEWS; v++) {
+        float cur[7];
+        pose_of(&cams[v], vm, cur);
+        if (vm->pf_n_hist == 0)
+            for (int k = 0; k < 4; k++) memcpy(vm->pf_pose[v][k], cur, sizeof cur);
+        else {
+            for (int k = 0; k < 3; k++) memcpy(vm->pf_pose[v][k], vm->pf_pose[v][k + 1], sizeof cur);
+            memcpy(vm->pf_pose[v][3], cur, sizeof cur);
+        }
+    }
+    if (vm->pf_n_hist < 4) vm->pf_n_hist++;
+}
+
+/* feature row of view v from the current state: 28 pose floats, H fractions */
+static void features(const or_vm* vm, int v, float* x)
+{
+    for (int k = 0; k < 4; k++) memcpy(x + 7 * k, vm->pf_pose[v][k], 7 * sizeof(float));
+    int H = vm->pf_H, n_pg = vm->n_pg;
+    for (int b = 0; b < H; b++) {
+        int64_t lo = ((int64_t)b * n_pg + H - 1) / H, hi = ((int64_t)(b + 1) * n_pg + H - 1) / H;
+        int cnt = 0;
+        for (int64_t p = lo; p < hi; p++) {
+            int res = 0;
+            for (int l = 0; l < vm->L; l++) res |= vm->v2p[p * vm->L + l] >= 0;
+            cnt += res;
+        }
+        x[28 + b] = hi > lo ? (float)cnt / (float)(hi - lo) : 0.0f;
+    }
+}
+
+static int cmp_u64(const void* a, const void* b)
+{
+    uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return (x > y) - (x < y);
+}
+
+static void prefetch_stage(or_vm* vm, uint8_t* req_sub, uint8_t* slot_req)
+{
+    int n_pg = vm->n_pg, L = vm->L, K = vm->pf_K, nv = vm->n_views, S = vm->S;
+    const or_camera* cams = vm->pf_cams;
+    const float* sp = or_scene_spheres(vm->s);
+    for (int v = 0; v < nv; v++) features(vm, v, vm->pf_x + (size_t)v * (28 + vm->pf_H));
+    float fy = cams[0].fy;
+    for (int v = 1; v < nv; v++) fy = fmaxf(fy, cams[v].fy);
+    int n = 0;
+    for (int p = 0; p < n_pg; p++) {
+        int c = (int)((int64_t)p * K / n_pg);
+        int sel = 0;
+        for (int v = 0; v < nv; v++) sel |= vm->pf_logits[(size_t)v * K + c] > vm->pf_thr;
+        if (!sel || vm->page_level[p] >= 0) continue;
+        const float* q = sp + 4 * p;
+        float dmin = INFINITY;
+        for (int v = 0; v < nv; v++) {
+            float dx = q[0] - cams[v].cam_pos[0], dy = q[1] - cams[v].cam_pos[1], dz = q[2] - cams[v].cam_pos[2];
+            float d = fmaxf(sqrtf((dx * dx + dy * dy) + dz * dz) - q[3], cams[v].znear);
+            dmin = fminf(dmin, d);
+        }
+        int lvl = 0;
+        if (L > 1) {
+            float rpx = (fy * q[3]) / dmin;
+            float thr = vm->tau;
+            while (lvl < L - 1 && !(rpx > thr)) { lvl++; thr = thr * 0.5f; }
+        }
+        if (vm->v2p[p * L + lvl] >= 0) continue;
+        vm->pf_keys[n++] = (2ull << 61) | ((uint64_t)fbits(dmin) << 30) | ((uint64_t)lvl << 28) | (uint64_t)p;
+    }
+    qsort(vm->pf_keys, (size_t)n, sizeof(uint64_t), cmp_u64);
+    vm->n_pf_req = n;
+    /* physical pages used in neither this frame nor the previous one */
+    ck* el = malloc(sizeof(ck) * (size_t)(S > 0 ? S : 1));
+    int ne = 0;
+    for (int s = 0; s < S; s++)
+        if (!slot_req[s] && vm->last_used[s] < vm->frame - 1) {
+            el[ne].k1 = vm->last_used[s]; el[ne].k2 = s; el[ne].k3 = 0; el[ne].a = s; el[ne].b = 0; ne++;
+        }
+    qsort(el, (size_t)ne, sizeof(ck), cmp_ck);
+    int32_t* fresh = malloc(sizeof(int32_t) * 3 * (size_t)(S + 1));
+    int fn[3] = {0, 0, 0}, fh[3] = {0, 0, 0}, pe = 0;
+    for (int i = 0; i < n && vm->n_prefetch < vm->pf_budget; i++) {
+        int32_t p = (int32_t)(vm->pf_keys[i] & 0x0fffffffu);
+        int l = (int)((vm->pf_keys[i] >> 28) & 3u);
+        int ts = -1, tj = -1;
+        while (l > 0 && ts < 0 && fh[l] < fn[l]) {
+            int s = fresh[l * (S + 1) + fh[l]];
+            for (int t = 0; t < cap_of(l) && ts < 0; t++)
+                if (vm->slot_level[s] == l && !req_sub[s * SUBS + t] && vm->sub_vpage[s * SUBS + t] < 0) { ts = s; tj = t; }
+            if (ts < 0) fh[l]++;
+        }
+        if (ts < 0) {
+            while (pe < ne) {
+                int s = el[pe++].a;
+                if (slot_req[s]) continue;
+                int oldl = vm->slot_level[s];
+                if (oldl >= 0)
+                    for (int j = 0; j < cap_of(oldl); j++) {
+                        int32_t op = vm->sub_vpage[s * SUBS + j];
+                        if (op >= 0) { vm->v2p[op * L + oldl] = -1; vm->evictions++; }
+                    }
+                for (int j = 0; j < SUBS; j++) { vm->sub_vpage[s * SUBS + j] = -1; vm->sub_last_used[s * SUBS + j] = -1; }
+                vm->slot_level[s] = (int8_t)l;
+                ts = s; tj = 0;
+                if (l > 0) fresh[l * (S + 1) + fn[l]++] = s;
+                break;
+            }
+        }
+        if (ts < 0) break;                 /* no physical page left for prefetching */
+        assign(vm, p, l, ts, tj, req_sub, slot_req);
+        vm->n_prefetch++;
+    }
+    free(fresh);
+    free(el);
 }
 
 /* ---- 6. splatting -------------------------------------------------------- */
@@ -608,6 +779,7 @@ void or_vm_free(or_vm* vm)
     free(vm->copy); free(vm->copy_id); free(vm->missing); free(vm->rl);
     free(vm->pp); free(vm->keys); free(vm->vals); free(vm->ranges); free(vm->image); free(vm->final_T);
     free(vm->contrib);
+    free(vm->pf_keys); free(vm->pf_x);
     free(vm);
 }
 
@@ -626,6 +798,8 @@ int or_vm_visibility(or_vm* vm, const or_camera* cams, int n_views, int brute_fo
 {
     int n_pg = vm->n_pg, Wv = vm->Wv, Hv = vm->Hv;
     vm->n_views = n_views;
+    vm->pf_cams = cams;
+    if (vm->pf_on) push_poses(vm, cams, n_views);
     free(vm->cand); free(vm->idbuf);
     vm->cand = calloc((size_t)n_views * n_pg, 1);
     vm->idbuf = malloc(sizeof(uint64_t) * (size_t)n_views * Wv * Hv);
@@ -729,6 +903,32 @@ int or_vm_pagetable(or_vm* vm, int n, const int32_t* pages, const int8_t* levels
 
 void or_vm_set_force_all(or_vm* vm, int on) { vm->force_all = on; }
 
+int or_vm_set_prefetch(or_vm* vm, int n_clusters, int hist_bins, float logit_threshold, int budget_pages,
+                       const float* center, float extent)
+{
+    if (n_clusters < 1 || hist_bins < 1 || !(extent > 0.0f)) return -1;
+    vm->pf_on = 1;
+    vm->pf_K = n_clusters; vm->pf_H = hist_bins; vm->pf_thr = logit_threshold; vm->pf_budget = budget_pages;
+    for (int a = 0; a < 3; a++) vm->pf_center[a] = center[a];
+    vm->pf_extent = extent;
+    vm->pf_n_hist = 0;
+    free(vm->pf_keys); free(vm->pf_x);
+    vm->pf_keys = malloc(sizeof(uint64_t) * (size_t)(vm->n_pg > 0 ? vm->n_pg : 1));
+    vm->pf_x = calloc((size_t)OR_MAX_VIEWS * (28 + hist_bins), sizeof(float));
+    return 0;
+}
+
+void or_vm_features(const or_vm* vm, int view, float* x) { features(vm, view, x); }
+
+int or_vm_frame_prefetch(or_vm* vm, const or_camera* cams, int n_views, const float* logits,
+                         const uint8_t* tile_mask)
+{
+    vm->pf_logits = logits;
+    int r = or_vm_frame(vm, cams, n_views, tile_mask);
+    vm->pf_logits = NULL;
+    return r;
+}
+
 void or_vm_set_sigma3_tiles(or_vm* vm, int on) { vm->sigma3_tiles = on; }
 
 int or_vm_frame(or_vm* vm, const or_camera* cams, int n_views, const uint8_t* tile_mask)
@@ -786,6 +986,12 @@ int64_t or_vm_get(const or_vm* vm, const char* name, void* dst, int64_t cap)
     if (!strcmp(name, "copies")) return put(dst, cap, vm->copy, 24 * (int64_t)vm->n_copy);
     if (!strcmp(name, "copy_id")) return put(dst, cap, vm->copy_id, 16 * (int64_t)vm->n_copy);
     if (!strcmp(name, "missing")) return put(dst, cap, vm->missing, 8 * (int64_t)vm->n_missing);
+    if (!strcmp(name, "pf_keys")) return put(dst, cap, vm->pf_keys, 8 * (int64_t)vm->n_pf_req);
+    if (!strcmp(name, "pf_x")) return put(dst, cap, vm->pf_x, 4 * (int64_t)vm->n_views * (28 + vm->pf_H));
+    if (!strcmp(name, "pf_counts")) {
+        int64_t c[3] = {vm->n_pf_req, vm->n_prefetch, vm->n_copy_demand};
+        return put(dst, cap, c, sizeof c);
+    }
     if (!strcmp(name, "counts")) {
         int64_t c[8] = {vm->n_req, vm->hits, vm->misses, vm->evictions, vm->n_copy, vm->n_missing, vm->n_rl, vm->n_render};
         return put(dst, cap, c, sizeof c);

@@ -77,6 +77,19 @@ int or_vm_pagetable(or_vm* vm, int n, const int32_t* pages, const int8_t* levels
 void or_vm_set_force_all(or_vm* vm, int on);
 void or_vm_set_sigma3_tiles(or_vm* vm, int on);
 
+/* Learned prefetch: n_clusters equal page-id ranges, hist_bins equal ranges
+ * for the residency features, proposals where a logit exceeds
+ * logit_threshold, at most budget_pages prefetch copies per frame; poses are
+ * taken relative to center over extent.  Poses are recorded from the next
+ * frame on.  or_vm_features: the feature row of a view from the current
+ * state (28 pose floats, then hist_bins fractions).  or_vm_frame_prefetch:
+ * a frame whose prefetch stage uses the given logits [n_views][n_clusters]. */
+int or_vm_set_prefetch(or_vm* vm, int n_clusters, int hist_bins, float logit_threshold, int budget_pages,
+                       const float* center, float extent);
+void or_vm_features(const or_vm* vm, int view, float* x);
+int or_vm_frame_prefetch(or_vm* vm, const or_camera* cams, int n_views, const float* logits,
+                         const uint8_t* tile_mask);
+
 /* ---- learned page prefetch (network oracle, or_mlp.c) ---- */
 /* dims[n_layers + 1]; params: per layer W [d_l][d_{l+1}] then b [d_{l+1}];
  * bf16 != 0 rounds the operands of every product to bf16 as the GPU holds

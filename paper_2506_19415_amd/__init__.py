@@ -48,17 +48,22 @@ class vm3dgs_camera(C.Structure):
                 ("cx", C.c_float), ("cy", C.c_float), ("znear", C.c_float)]
 
 
+class vm3dgs_prefetch_opts(C.Structure):
+    _fields_ = [("n_clusters", C.c_uint32), ("hist_bins", C.c_uint32), ("budget_pages", C.c_uint32),
+                ("logit_threshold", C.c_float), ("center", C.c_float * 3), ("extent", C.c_float)]
+
+
 class vm3dgs_stats(C.Structure):
     _fields_ = [(n, C.c_uint32) for n in ("candidates", "requested", "direct", "linked", "hits", "misses",
                                            "evictions", "missing", "copies", "render_pages", "pool_pages_used",
-                                           "reserved0")] + \
+                                           "prefetched")] + \
                [(n, C.c_uint64) for n in ("render_gaussians", "visible_gaussians", "pairs", "bytes_copied",
                                            "blend_evals", "blend_alphas")] + \
                [(n, C.c_float) for n in ("ms_visibility", "ms_pagetable", "ms_copy", "ms_preprocess", "ms_sort",
                                           "ms_blend", "ms_total")]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved0"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class vm3dgs_frame_out(C.Structure):
@@ -121,6 +126,10 @@ def lib():
         L.vm3dgs_mlp_n_params.argtypes = [vp]
         L.vm3dgs_mlp_n_params.restype = C.c_uint64
         L.vm3dgs_mlp_destroy.argtypes = [vp]
+        L.vm3dgs_set_prefetch.argtypes = [vp, vp, C.POINTER(vm3dgs_prefetch_opts)]
+        L.vm3dgs_set_prefetch.restype = C.c_int32
+        L.vm3dgs_prefetch_features.argtypes = [vp, u32, vp]
+        L.vm3dgs_prefetch_features.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -256,6 +265,27 @@ class Renderer:
     def render_full(self, cams):
         st = vm3dgs_render_full(self.h, cams, self.image.data_ptr())
         return self.image[:len(cams)], st
+
+    def set_prefetch(self, net, n_clusters, hist_bins, logit_threshold, budget_pages, center, extent):
+        """Attach the learned prefetch stage (net: an Mlp, or None to keep
+        only the pose history for vm3dgs_prefetch_features)."""
+        o = vm3dgs_prefetch_opts()
+        o.n_clusters, o.hist_bins, o.budget_pages = int(n_clusters), int(hist_bins), int(budget_pages)
+        o.logit_threshold = float(logit_threshold)
+        o.center[:] = [float(v) for v in center]
+        o.extent = float(extent)
+        rc = lib().vm3dgs_set_prefetch(self.h, net.h if net is not None else None, C.byref(o))
+        if rc != 0:
+            raise Vm3dgsError(rc, lib().vm3dgs_last_error(self.h).decode())
+        self.pf_net = net
+        self.pf_width = 28 + int(hist_bins)
+
+    def prefetch_features(self, n_views=1):
+        x = np.zeros((n_views, self.pf_width), np.float32)
+        rc = lib().vm3dgs_prefetch_features(self.h, int(n_views), x.ctypes.data)
+        if rc != 0:
+            raise Vm3dgsError(rc, lib().vm3dgs_last_error(self.h).decode())
+        return x
 
     def set_flags(self, flags):
         vm3dgs_set_flags(self.h, flags)

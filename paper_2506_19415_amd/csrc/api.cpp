@@ -76,6 +76,17 @@ struct vm3dgs {
     uint32_t* d_total = nullptr; uint32_t* h_total = nullptr;
     uint2* d_bstats = nullptr; uint2* h_bstats = nullptr;
     int frame = 0;
+    // learned prefetch: configuration, pose history (host), features, proposals
+    bool pf_on = false, pf_pending = false;
+    vm3dgs_prefetch_opts pf{};
+    vm3dgs_mlp* pf_net = nullptr;
+    int pf_n_hist = 0;
+    std::vector<float> pf_pose;                 // [max_views][4][7]
+    float* d_pf_x = nullptr; float* h_pf_x = nullptr;   // [max_views][28 + H]
+    uint64_t* d_pf_keys[2] = {nullptr, nullptr}; uint64_t* d_pf_idle[2] = {nullptr, nullptr};
+    const uint64_t* pf_sorted = nullptr;
+    hipEvent_t ev_pf = nullptr;
+    uint32_t last_n_pfreq = 0, last_n_pf = 0;
     // last frame, for vm3dgs_debug_get and the frame output
     uint32_t last_views = 0, last_n_render = 0, last_n_pairs = 0, last_n_copy = 0, last_n_missing = 0;
     uint32_t last_n_req = 0, last_n_rl = 0;
@@ -162,6 +173,9 @@ void free_all(vm3dgs* c) {
     dfree(c->d_offs); dfree(c->d_ranges); dfree(c->d_tile_order); dfree(c->d_temp); dfree(c->d_total); hfree(c->h_total);
     dfree(c->d_zero); dfree(c->d_status); dfree(c->d_bstats); hfree(c->h_bstats);
     if (c->ev_copy) hipEventDestroy(c->ev_copy);
+    if (c->ev_pf) hipEventDestroy(c->ev_pf);
+    dfree(c->d_pf_x); hfree(c->h_pf_x);
+    for (int i = 0; i < 2; ++i) { dfree(c->d_pf_keys[i]); dfree(c->d_pf_idle[i]); }
     for (auto& e : c->ev)
         if (e) hipEventDestroy(e);
     if (c->own_sr && c->sr) hipStreamDestroy(c->sr);
@@ -265,6 +279,58 @@ void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool,
         st->render_gaussians = n_total;
         st->pairs = n_pairs;
     }
+}
+
+// camera pose for the prefetch features: position relative to the centre
+// over the extent, camera-to-world rotation as a unit quaternion, w >= 0
+void pose_of(const vm3dgs_camera& cam, const vm3dgs_prefetch_opts& o, float* out) {
+    double M[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) M[i][j] = cam.view[4 * j + i];
+    double w, x, y, z;
+    const double tr = M[0][0] + M[1][1] + M[2][2];
+    if (tr > 0.0) {
+        const double S = std::sqrt(tr + 1.0) * 2.0;
+        w = 0.25 * S; x = (M[2][1] - M[1][2]) / S; y = (M[0][2] - M[2][0]) / S; z = (M[1][0] - M[0][1]) / S;
+    } else if (M[0][0] > M[1][1] && M[0][0] > M[2][2]) {
+        const double S = std::sqrt(1.0 + M[0][0] - M[1][1] - M[2][2]) * 2.0;
+        w = (M[2][1] - M[1][2]) / S; x = 0.25 * S; y = (M[0][1] + M[1][0]) / S; z = (M[0][2] + M[2][0]) / S;
+    } else if (M[1][1] > M[2][2]) {
+        const double S = std::sqrt(1.0 + M[1][1] - M[0][0] - M[2][2]) * 2.0;
+        w = (M[0][2] - M[2][0]) / S; x = (M[0][1] + M[1][0]) / S; y = 0.25 * S; z = (M[1][2] + M[2][1]) / S;
+    } else {
+        const double S = std::sqrt(1.0 + M[2][2] - M[0][0] - M[1][1]) * 2.0;
+        w = (M[1][0] - M[0][1]) / S; x = (M[0][2] + M[2][0]) / S; y = (M[1][2] + M[2][1]) / S; z = 0.25 * S;
+    }
+    double n = std::sqrt(w * w + x * x + y * y + z * z);
+    if (w < 0.0) n = -n;
+    for (int a = 0; a < 3; ++a) out[a] = (float)(((double)cam.cam_pos[a] - o.center[a]) / o.extent);
+    out[3] = (float)(w / n); out[4] = (float)(x / n); out[5] = (float)(y / n); out[6] = (float)(z / n);
+}
+
+void push_poses(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views) {
+    for (uint32_t v = 0; v < n_views; ++v) {
+        float cur[7];
+        pose_of(cams[v], c->pf, cur);
+        float* h = &c->pf_pose[(size_t)v * 28];
+        if (c->pf_n_hist == 0)
+            for (int k = 0; k < 4; ++k) memcpy(h + 7 * k, cur, sizeof cur);
+        else {
+            memmove(h, h + 7, sizeof(float) * 21);
+            memcpy(h + 21, cur, sizeof cur);
+        }
+    }
+    if (c->pf_n_hist < 4) c->pf_n_hist++;
+}
+
+// feature rows of n_views views into d_pf_x: pose history from the host, the
+// residency fractions by a kernel (on the render stream)
+void pf_features(vm3dgs* c, uint32_t n_views) {
+    const int ld = 28 + (int)c->pf.hist_bins;
+    for (uint32_t v = 0; v < n_views; ++v) memcpy(c->h_pf_x + (size_t)v * ld, &c->pf_pose[(size_t)v * 28], 28 * 4);
+    HIPCHK(hipMemcpy2DAsync(c->d_pf_x, sizeof(float) * ld, c->h_pf_x, sizeof(float) * ld, 28 * sizeof(float),
+                            n_views, hipMemcpyHostToDevice, c->sr));
+    launch_pf_features(c->sr, c->d_v2p, c->n_pg, c->L, (int)c->pf.hist_bins, (int)n_views, c->d_pf_x);
 }
 
 vm3dgs_status fail(vm3dgs* c, const HipError& h) {
@@ -470,6 +536,7 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         }
         HIPCHK(hipEventRecord(ev[0], c->sr));
         HIPCHK(hipMemcpyAsync(c->d_cams, c->h_cams, sizeof(CamK) * n_views, hipMemcpyHostToDevice, c->sr));
+        if (c->pf_on) push_poses(c, cams, n_views);
         begin_work(c);
         VisArgs va{};
         va.spheres = c->d_sph; va.n_pg = c->n_pg; va.cell_lo = c->d_clo; va.cell_hi = c->d_chi; va.nc = c->ps.nc();
@@ -502,18 +569,67 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
             lw.fresh = c->d_fresh;
             launch_pagetable_lod(c->sr, pa, c->sw, lw);
         }
+        if (c->pf_on && c->pf_net) {
+            // features of the state after the demand stages, the network, proposals, third stage
+            pf_features(c, n_views);
+            const MlpDev& nd = *mlp_dev_of(c->pf_net);
+            mlp_input_dev(c->sr, nd, c->d_pf_x, (int)n_views);
+            mlp_forward_dev(c->sr, nd, (int)n_views);
+            PfArgs fa{};
+            fa.logits = nd.logits; fa.K = (int)c->pf.n_clusters; fa.thr = c->pf.logit_threshold;
+            fa.page_level = c->d_plevel; fa.v2p = c->d_v2p; fa.sph = c->d_sph; fa.n_pg = c->n_pg; fa.L = c->L;
+            fa.tau = c->opt.lod_radius_px; fa.fy = fy_max; fa.cams = c->d_cams; fa.n_views = (int)n_views;
+            fa.keys[0] = c->d_pf_keys[0]; fa.keys[1] = c->d_pf_keys[1];
+            fa.idle[0] = c->d_pf_idle[0]; fa.idle[1] = c->d_pf_idle[1];
+            fa.S = c->S; fa.P = c->P; fa.frame = c->frame; fa.budget = (int)c->pf.budget_pages;
+            fa.bytes_g = c->ps.bytes_g; fa.level_base = c->d_level_base;
+            fa.slot_level = c->d_slot_level; fa.last_used = c->d_last_used; fa.sub_vpage = c->d_sub_vpage;
+            fa.sub_last_used = c->d_sub_lu; fa.fresh = c->d_fresh;
+            fa.copies = c->d_copies; fa.copy_id = c->d_copy_id; fa.counters = c->d_ctr;
+            fa.sorted_out = &c->pf_sorted;
+            launch_prefetch(c->sr, fa, c->sw);
+        }
         HIPCHK(hipGetLastError());
         HIPCHK(hipEventRecord(ev[2], c->sr));
         HIPCHK(hipMemcpyAsync(c->h_ctr, c->d_ctr, sizeof(uint32_t) * C_NCOUNTERS, hipMemcpyDeviceToHost, c->sr));
         HIPCHK(hipStreamSynchronize(c->sr));
         const uint32_t* k = c->h_ctr;
         const uint32_t n_copy = k[C_NCOPY];
+        const uint32_t n_pf = (c->pf_on && c->pf_net) ? k[C_NPF] : 0u;
+        const uint32_t n_dem = n_copy - n_pf;
         if (n_copy) {
             HIPCHK(hipMemcpyAsync(c->h_copies, c->d_copies, sizeof(CopyCmd) * n_copy, hipMemcpyDeviceToHost, c->sr));
             HIPCHK(hipStreamSynchronize(c->sr));
             // merge runs that are contiguous on both sides, then one async copy per run
             const CopyCmd* cp = c->h_copies;
-            uint32_t i = 0;
+            uint64_t bytes = 0;
+            auto issue = [&](uint32_t i, uint32_t end) {
+                while (i < end) {
+                    int64_t h = cp[i].host_off, d = cp[i].pool_off, b = cp[i].bytes;
+                    uint32_t j = i + 1;
+                    while (j < end && cp[j].host_off == h + b && cp[j].pool_off == d + b) { b += cp[j].bytes; ++j; }
+                    HIPCHK(hipMemcpyAsync(c->d_pool + d, c->h_store + h, (size_t)b, hipMemcpyHostToDevice, c->sc));
+                    bytes += (uint64_t)b;
+                    i = j;
+                }
+            };
+            // demand copies: this frame's render waits for them
+            issue(0, n_dem);
+            if (n_dem) {
+                HIPCHK(hipEventRecord(c->ev_copy, c->sc));
+                HIPCHK(hipStreamWaitEvent(c->sr, c->ev_copy, 0));
+            }
+            st.bytes_copied = bytes;
+        }
+        // prefetch copies of earlier frames complete before this frame reads the pool;
+        // this frame's prefetch copies follow its demand copies and are not awaited here
+        if (c->pf_pending) {
+            HIPCHK(hipStreamWaitEvent(c->sr, c->ev_pf, 0));
+            c->pf_pending = false;
+        }
+        if (n_pf) {
+            const CopyCmd* cp = c->h_copies;
+            uint32_t i = n_dem;
             uint64_t bytes = 0;
             while (i < n_copy) {
                 int64_t h = cp[i].host_off, d = cp[i].pool_off, b = cp[i].bytes;
@@ -523,16 +639,19 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
                 bytes += (uint64_t)b;
                 i = j;
             }
-            HIPCHK(hipEventRecord(c->ev_copy, c->sc));
-            HIPCHK(hipStreamWaitEvent(c->sr, c->ev_copy, 0));
-            st.bytes_copied = bytes;
+            HIPCHK(hipEventRecord(c->ev_pf, c->sc));
+            c->pf_pending = true;
+            st.bytes_copied += bytes;
         }
+        c->last_n_pfreq = (c->pf_on && c->pf_net) ? k[C_NPFREQ] : 0u;
+        c->last_n_pf = n_pf;
+        st.prefetched = n_pf;
         const uint32_t n_render = k[C_NRENDER];
         c->last_n_copy = n_copy; c->last_n_missing = k[C_NMISSING]; c->last_n_req = k[C_NREQ];
         c->last_n_rl = k[C_NRL];
         st.candidates = k[C_CAND]; st.requested = k[C_NREQ]; st.direct = k[C_DIRECT]; st.linked = k[C_LINKED];
         st.hits = k[C_HITS]; st.misses = k[C_MISSES]; st.evictions = k[C_EVICT]; st.missing = k[C_NMISSING];
-        st.copies = n_copy; st.render_pages = k[C_NRL]; st.pool_pages_used = k[C_POOLUSED];
+        st.copies = n_dem; st.render_pages = k[C_NRL]; st.pool_pages_used = k[C_POOLUSED];
         splat(c, c->d_rlist, k[C_NRL], c->d_pool, n_render, n_views, image, &st);
         // outputs of the frame: request order and missing list
         if (c->last_n_req)
@@ -605,6 +724,57 @@ vm3dgs_status vm3dgs_render_full(vm3dgs* c, const vm3dgs_camera* cams, uint32_t 
         return VM3DGS_E_CAPACITY;
     }
     if (stats) *stats = st;
+    return VM3DGS_OK;
+}
+
+vm3dgs_status vm3dgs_set_prefetch(vm3dgs* c, vm3dgs_mlp* net, const vm3dgs_prefetch_opts* o) {
+    if (!c) return VM3DGS_E_INVALID_ARG;
+    if (c->poisoned) return VM3DGS_E_STATE;
+    if (!o || o->n_clusters == 0 || o->hist_bins == 0 || !(o->extent > 0.0f)) return bad(c, "prefetch options out of range");
+    if (c->n_pg >= (1 << 28)) return bad(c, "prefetch keys hold page ids below 2^28");
+    if (net) {
+        const MlpDev& d = *mlp_dev_of(net);
+        if (d.dims[0] != 28 + (int)o->hist_bins || d.dims[d.n_layers] != (int)o->n_clusters ||
+            mlp_max_batch_of(net) < (int)c->opt.max_views)
+            return bad(c, "network widths or batch do not match the prefetch options");
+    }
+    try {
+        HIPCHK(hipStreamSynchronize(c->sr));
+        HIPCHK(hipStreamSynchronize(c->sc));
+        const size_t V = c->opt.max_views, ld = 28 + (size_t)o->hist_bins;
+        dfree(c->d_pf_x); hfree(c->h_pf_x);
+        dalloc(&c->d_pf_x, V * ld); halloc(&c->h_pf_x, V * ld);
+        for (int i = 0; i < 2; ++i) {
+            if (!c->d_pf_keys[i]) dalloc(&c->d_pf_keys[i], (size_t)c->n_pg);
+            if (!c->d_pf_idle[i]) dalloc(&c->d_pf_idle[i], (size_t)c->S);
+        }
+        if (!c->d_fresh) dalloc(&c->d_fresh, (size_t)3 * c->S);
+        if (!c->ev_pf) HIPCHK(hipEventCreateWithFlags(&c->ev_pf, hipEventDisableTiming));
+    } catch (const HipError& h) {
+        return fail(c, h);
+    }
+    c->pf = *o;
+    c->pf_net = net;
+    c->pf_on = true;
+    c->pf_n_hist = 0;
+    c->pf_pose.assign((size_t)c->opt.max_views * 28, 0.0f);
+    c->pf_sorted = nullptr;
+    c->last_n_pfreq = c->last_n_pf = 0;
+    return VM3DGS_OK;
+}
+
+vm3dgs_status vm3dgs_prefetch_features(vm3dgs* c, uint32_t n_views, float* x) {
+    if (!c) return VM3DGS_E_INVALID_ARG;
+    if (c->poisoned) return VM3DGS_E_STATE;
+    if (!c->pf_on || !x || n_views == 0 || n_views > c->opt.max_views) return bad(c, "no prefetch stage or bad views");
+    try {
+        pf_features(c, n_views);
+        HIPCHK(hipMemcpyAsync(x, c->d_pf_x, sizeof(float) * n_views * (28 + c->pf.hist_bins), hipMemcpyDeviceToHost,
+                              c->sr));
+        HIPCHK(hipStreamSynchronize(c->sr));
+    } catch (const HipError& h) {
+        return fail(c, h);
+    }
     return VM3DGS_OK;
 }
 
@@ -766,6 +936,10 @@ int64_t vm3dgs_debug_get(vm3dgs* c, const char* name, void* dst, int64_t cap) {
     if (n == "sub_vpage") return dev(c->d_sub_vpage, 4 * (int64_t)c->S * SUBS);
     if (n == "sub_last_used") return dev(c->d_sub_lu, 4 * (int64_t)c->S * SUBS);
     if (n == "v2p") return dev(c->d_v2p, 4 * (int64_t)c->n_pg * c->L);
+    if (n == "pf_keys") return c->pf_sorted ? dev(c->pf_sorted, 8 * (int64_t)c->last_n_pfreq) : 0;
+    if (n == "pf_x") return c->d_pf_x ? dev(c->d_pf_x, 4 * (int64_t)c->last_views * (28 + c->pf.hist_bins)) : 0;
+    if (n == "pf_logits")
+        return c->pf_net ? dev(mlp_dev_of(c->pf_net)->logits, 4 * (int64_t)c->last_views * c->pf.n_clusters) : 0;
     if (n == "copies") return dev(c->d_copies, 24 * (int64_t)c->last_n_copy);
     if (n == "copy_id") return dev(c->d_copy_id, 16 * (int64_t)c->last_n_copy);
     if (n == "missing") return host(c->out_missing.data(), 4 * (int64_t)c->out_missing.size());

@@ -68,6 +68,14 @@ std::string g_mlp_create_error;
 extern "C" {
 
 const char* vm3dgs_mlp_create_error(void) { return g_mlp_create_error.c_str(); }
+}  // extern "C"
+
+namespace vm {
+const MlpDev* mlp_dev_of(const vm3dgs_mlp* net) { return &net->d; }
+int mlp_max_batch_of(const vm3dgs_mlp* net) { return net->max_batch; }
+}  // namespace vm
+
+extern "C" {
 
 vm3dgs_status vm3dgs_mlp_create(const uint32_t* dims, uint32_t n_layers, uint32_t max_batch, void* stream,
                                 vm3dgs_mlp** out) {

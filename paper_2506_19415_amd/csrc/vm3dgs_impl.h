@@ -93,7 +93,7 @@ struct CamK {
 // Counters written by the page-table kernels and read back once per frame.
 enum Ctr {
     C_NREQ = 0, C_DIRECT, C_LINKED, C_HITS, C_MISSES, C_EVICT, C_NCOPY, C_NMISSING, C_NRL, C_NRENDER,
-    C_CAND, C_POOLUSED, C_NCAND1, C_NCAND2, C_NCOUNTERS = 16
+    C_CAND, C_POOLUSED, C_NCAND1, C_NCAND2, C_NPFREQ, C_NPF, C_NCOUNTERS = 16
 };
 
 struct RenderEntry {   // one resident requested (sub-)page in render order
@@ -194,5 +194,23 @@ void mlp_forward_dev(hipStream_t st, const MlpDev& d, int B);
 void mlp_backward_dev(hipStream_t st, const MlpDev& d, const float* y, int B);
 void mlp_adam_dev(hipStream_t st, const MlpDev& d, float lr, float b1, float b2, float eps, int t);
 void mlp_sync_bf16_dev(hipStream_t st, const MlpDev& d);
+
+
+// learned prefetch (k_prefetch.hip)
+struct PfArgs {
+    const float* logits; int K; float thr;
+    const int8_t* page_level; int32_t* v2p; const float4* sph; int n_pg, L; float tau, fy;
+    const CamK* cams; int n_views;
+    uint64_t* keys[2]; uint64_t* idle[2];
+    int S, P, frame, budget, bytes_g;
+    const int64_t* level_base;
+    int8_t* slot_level; int32_t* last_used; int32_t* sub_vpage; int32_t* sub_last_used; int32_t* fresh;
+    CopyCmd* copies; int32_t* copy_id; uint32_t* counters;
+    const uint64_t** sorted_out;   // receives the buffer holding the sorted proposals
+};
+void launch_pf_features(hipStream_t st, const int32_t* v2p, int n_pg, int L, int H, int n_views, float* x);
+void launch_prefetch(hipStream_t st, const PfArgs& a, SortWork& sw);
+const MlpDev* mlp_dev_of(const vm3dgs_mlp* net);
+int mlp_max_batch_of(const vm3dgs_mlp* net);
 
 }  // namespace vm

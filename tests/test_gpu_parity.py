@@ -46,7 +46,7 @@ def compare_frame(r, ovm, out, n_views, check_image=True, tag=""):
     assert np.array_equal(miss, ovm.get("missing")), tag
     c = ovm.counts()
     st = out.stats
-    assert (st.requested, st.hits, st.misses, st.evictions, st.copies, st.missing, st.render_pages) == \
+    assert (st.requested, st.hits, st.misses, st.evictions, st.copies + st.prefetched, st.missing, st.render_pages) == \
            (c["requests"], c["hits"], c["misses"], c["evictions"], c["copies"], c["missing"], c["render_pages"]), tag
     rl = g("render_list", np.uint32).reshape(-1, 4)
     orl = ovm.get("render_list").reshape(-1, 6)

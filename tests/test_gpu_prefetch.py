@@ -1,0 +1,67 @@
+"""The learned prefetch stage on the GPU against the oracle, through the C ABI.
+
+The network's logits come from the library's own bf16 kernels; the oracle is
+given those same logits, so proposals and the third page-table stage are
+compared bit for bit (keys, copies, page-table state), the features within
+float rounding, and the logits against the oracle network within 1e-2."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_19415_amd import synth
+from test_gpu_parity import compare_frame
+
+pytestmark = pytest.mark.gpu
+
+KC, HB = 64, 32
+
+
+@pytest.fixture(scope="module")
+def city():
+    sc = synth.scene_city(0, n=100_000, size=300.0, block=60.0, street=12.0)
+    cams = synth.path_city(sc, n_frames=40, width=320, height=180)
+    means = np.asarray(sc.means, np.float64)
+    lo, hi = means.min(0), means.max(0)
+    return sc, cams, ((lo + hi) / 2).astype(np.float32), float((hi - lo).max() / 2)
+
+
+def _net_params(dims, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for l in range(len(dims) - 1):
+        out.append((rng.standard_normal(dims[l] * dims[l + 1]) * np.sqrt(2.0 / dims[l])).astype(np.float32))
+        out.append((rng.standard_normal(dims[l + 1]) * 0.3).astype(np.float32))
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("L,P,S,tau,budget", [(1, 256, 250, 32.0, 8), (3, 512, 90, 128.0, 6)])
+def test_prefetch_stage_parity(city, L, P, S, tau, budget):
+    import paper_2506_19415_amd as pkg
+    sc, cams, center, extent = city
+    dims = [28 + HB, 64, 64, KC]
+    params = _net_params(dims, 7)
+    net = pkg.Mlp(dims, max_batch=4)
+    net.set_params(params)
+    r = pkg.Renderer(sc, P, S, lod_levels=L, img=(320, 180), idbuf=(80, 45), cell=2.0, lod_radius_px=tau)
+    r.set_prefetch(net, KC, HB, 0.0, budget, center, extent)
+    osc = oracle.OracleScene(sc, P, L, 2.0, 2.0)
+    ovm = oracle.OracleVM(osc, S, (320, 180), (80, 45), lod_radius_px=tau)
+    ovm.set_prefetch(KC, HB, 0.0, budget, center, extent)
+    n_pf = 0
+    for k in range(0, 40, 2):
+        print(f"prefetch L={L} frame {k}", flush=True)
+        _, out = r.frame([cams[k]])
+        logits = r.get("pf_logits", np.float32).reshape(1, KC)
+        x = r.get("pf_x", np.float32).reshape(1, 28 + HB)
+        ovm.frame_prefetch([cams[k]], logits)
+        assert np.allclose(x, ovm.get("pf_x").reshape(1, -1), rtol=0, atol=2e-6), k
+        z = oracle.mlp_forward(params, dims, ovm.get("pf_x").reshape(1, -1), bf16=True)
+        assert np.abs(logits - z).max() <= 1e-2 * max(np.abs(z).max(), 1.0), k
+        n_req, n_p, n_dem = (int(v) for v in ovm.get("pf_counts"))
+        assert out.stats.prefetched == n_p and out.stats.copies == n_dem, k
+        assert np.array_equal(r.get("pf_keys", np.uint64), ovm.get("pf_keys")), k
+        compare_frame(r, ovm, out, 1, tag=f"prefetch L={L} frame {k}")
+        n_pf += n_p
+    assert n_pf > 0
+    r.close()
+    net.close()
