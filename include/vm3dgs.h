@@ -163,6 +163,11 @@ vm3dgs_status vm3dgs_render_full(vm3dgs* ctx, const vm3dgs_camera* cams, uint32_
  * pages decoded to 59 floats). */
 int64_t vm3dgs_debug_get(vm3dgs* ctx, const char* name, void* host_dst, int64_t cap);
 
+/* Empty the pool and the page table and restart the frame counter (and the
+ * prefetch pose history), as after create; the scene stays.  Waits for both
+ * streams. */
+vm3dgs_status vm3dgs_reset(vm3dgs* ctx);
+
 /* Replace the VM3DGS_FLAG_LINKS / BLEND_STATS / SIGMA3_TILES bits of the options
  * for later frames (VM3DGS_FLAG_FULL_SCENE_COPY is fixed at create).
  * Errors: INVALID_ARG for a NULL context. */

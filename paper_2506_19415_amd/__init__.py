@@ -126,6 +126,8 @@ def lib():
         L.vm3dgs_mlp_n_params.argtypes = [vp]
         L.vm3dgs_mlp_n_params.restype = C.c_uint64
         L.vm3dgs_mlp_destroy.argtypes = [vp]
+        L.vm3dgs_reset.argtypes = [vp]
+        L.vm3dgs_reset.restype = C.c_int32
         L.vm3dgs_set_prefetch.argtypes = [vp, vp, C.POINTER(vm3dgs_prefetch_opts)]
         L.vm3dgs_set_prefetch.restype = C.c_int32
         L.vm3dgs_prefetch_features.argtypes = [vp, u32, vp]
@@ -279,6 +281,11 @@ class Renderer:
             raise Vm3dgsError(rc, lib().vm3dgs_last_error(self.h).decode())
         self.pf_net = net
         self.pf_width = 28 + int(hist_bins)
+
+    def reset(self):
+        rc = lib().vm3dgs_reset(self.h)
+        if rc != 0:
+            raise Vm3dgsError(rc, lib().vm3dgs_last_error(self.h).decode())
 
     def prefetch_features(self, n_views=1):
         x = np.zeros((n_views, self.pf_width), np.float32)

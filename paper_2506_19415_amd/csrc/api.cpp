@@ -727,6 +727,29 @@ vm3dgs_status vm3dgs_render_full(vm3dgs* c, const vm3dgs_camera* cams, uint32_t 
     return VM3DGS_OK;
 }
 
+vm3dgs_status vm3dgs_reset(vm3dgs* c) {
+    if (!c) return VM3DGS_E_INVALID_ARG;
+    if (c->poisoned) return VM3DGS_E_STATE;
+    try {
+        HIPCHK(hipStreamSynchronize(c->sr));
+        HIPCHK(hipStreamSynchronize(c->sc));
+        const size_t S = c->S, n_pg = c->n_pg, L = c->L;
+        HIPCHK(hipMemset(c->d_slot_level, 0xff, S));
+        HIPCHK(hipMemset(c->d_last_used, 0xff, sizeof(int32_t) * S));
+        HIPCHK(hipMemset(c->d_sub_vpage, 0xff, sizeof(int32_t) * S * SUBS));
+        HIPCHK(hipMemset(c->d_sub_lu, 0xff, sizeof(int32_t) * S * SUBS));
+        HIPCHK(hipMemset(c->d_v2p, 0xff, sizeof(int32_t) * n_pg * L));
+    } catch (const HipError& h) {
+        return fail(c, h);
+    }
+    c->frame = 0;
+    c->pf_n_hist = 0;
+    c->pf_pending = false;
+    c->last_n_copy = c->last_n_missing = c->last_n_req = c->last_n_rl = 0;
+    c->last_n_pfreq = c->last_n_pf = 0;
+    return VM3DGS_OK;
+}
+
 vm3dgs_status vm3dgs_set_prefetch(vm3dgs* c, vm3dgs_mlp* net, const vm3dgs_prefetch_opts* o) {
     if (!c) return VM3DGS_E_INVALID_ARG;
     if (c->poisoned) return VM3DGS_E_STATE;

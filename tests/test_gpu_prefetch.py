@@ -65,3 +65,33 @@ def test_prefetch_stage_parity(city, L, P, S, tau, budget):
     assert n_pf > 0
     r.close()
     net.close()
+
+
+def test_trained_network_cuts_demand_misses(city):
+    """Trained on the GPU (the library's kernels) on plain-pass page sets of
+    seeded city paths, the network's prefetches turn later demand misses into
+    hits on held-out paths: fewer misses per frame than the method alone.
+    The gain is a measurement of this workload, not a property the paper
+    fixes (parity unpinned)."""
+    import paper_2506_19415_amd as pkg
+    from paper_2506_19415_amd import prefetch as pf
+    sc, _, center, extent = city
+    dims = [28 + HB, 128, 128, KC]
+    train_paths = [synth.path_city(sc, n_frames=48, width=320, height=180, seed=1000 + i) for i in range(24)]
+    test_paths = [synth.path_city(sc, n_frames=48, width=320, height=180, seed=2000 + i) for i in range(4)]
+    r = pkg.Renderer(sc, 256, 250, img=(320, 180), idbuf=(80, 45), cell=2.0)
+    X, Y = pf.collect(r, train_paths, KC, HB, center, extent)
+    print(f"training rows {X.shape[0]}, positive rate {Y.mean():.3f}", flush=True)
+    net = pkg.Mlp(dims, max_batch=256)
+    net.set_params(_net_params(dims, 11) * 0.5)
+    losses = pf.train(net, X, Y, steps=1500, batch=128, lr=2e-3, log_every=500)
+    print("losses", losses, flush=True)
+    assert losses[-1][1] < losses[0][1]
+    base = pf.evaluate(r, None, test_paths, KC, HB, 0.0, 16, center, extent)
+    with_net = pf.evaluate(r, net, test_paths, KC, HB, 0.0, 16, center, extent)
+    print("without", base, flush=True)
+    print("with", with_net, flush=True)
+    assert with_net["proposed"] > 0 and with_net["recall"] > 0.0
+    assert with_net["misses_per_frame"] < 0.95 * base["misses_per_frame"], (base, with_net)
+    r.close()
+    net.close()
