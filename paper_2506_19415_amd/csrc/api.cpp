@@ -34,6 +34,7 @@ struct vm3dgs {
     hipStream_t sr = nullptr, sc = nullptr;
     bool own_sr = false, own_sc = false;
     hipEvent_t ev_copy = nullptr;
+    hipEvent_t ev_sync = nullptr;   // host waits inside a frame spin on this event
     hipEvent_t ev[8] = {};
     // scene on the device
     float4* d_sph = nullptr; float4* d_clo = nullptr; float4* d_chi = nullptr;
@@ -173,6 +174,7 @@ void free_all(vm3dgs* c) {
     dfree(c->d_offs); dfree(c->d_ranges); dfree(c->d_tile_order); dfree(c->d_temp); dfree(c->d_total); hfree(c->h_total);
     dfree(c->d_zero); dfree(c->d_status); dfree(c->d_bstats); hfree(c->h_bstats);
     if (c->ev_copy) hipEventDestroy(c->ev_copy);
+    if (c->ev_sync) hipEventDestroy(c->ev_sync);
     if (c->ev_pf) hipEventDestroy(c->ev_pf);
     dfree(c->d_pf_x); hfree(c->h_pf_x);
     for (int i = 0; i < 2; ++i) { dfree(c->d_pf_keys[i]); dfree(c->d_pf_idle[i]); }
@@ -181,6 +183,8 @@ void free_all(vm3dgs* c) {
     if (c->own_sr && c->sr) hipStreamDestroy(c->sr);
     if (c->own_sc && c->sc) hipStreamDestroy(c->sc);
 }
+
+constexpr uint32_t kCopyHead = 128;   // copy commands read back with the counters
 
 constexpr int ZB_CTR = 0, ZB_ERR = C_NCOUNTERS, ZB_TICKETS = ZB_ERR + 16,
               ZB_HIST = ZB_TICKETS + SortWork::kMaxTickets, ZB_WORDS = ZB_HIST + 256 * SortWork::kMaxHist;
@@ -195,6 +199,17 @@ void ensure_status(vm3dgs* c) {
         c->status_words = need;
         c->sw.status = c->d_status;
     }
+}
+
+// Wait, inside a frame, for the render stream to reach this point: a spin on
+// an event (the frame's readbacks are a few bytes and the host has nothing
+// else to do; a sleeping wait adds its wake-up time to every frame).
+void spin_wait(vm3dgs* c) {
+    HIPCHK(hipEventRecord(c->ev_sync, c->sr));
+    hipError_t e;
+    while ((e = hipEventQuery(c->ev_sync)) == hipErrorNotReady) {
+    }
+    if (e != hipSuccess) throw HipError{e, "hipEventQuery", __LINE__};
 }
 
 // start of a frame's device work: clear counters, tickets and histograms
@@ -222,6 +237,7 @@ void ensure_pairs(vm3dgs* c, uint64_t n) {
         dalloc(&c->d_pkey[i], cap);
         dalloc(&c->d_pval[i], cap);
     }
+
     c->cap_pairs = cap;
     ensure_temp(c);
     ensure_status(c);
@@ -248,7 +264,7 @@ void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool,
     scan_lb_gather(c->sr, c->sw, c->d_tiles, c->d_dval[db], n_total, c->d_offs, c->d_total);
     HIPCHK(hipMemcpyAsync(c->h_total, c->d_total, sizeof(uint32_t), hipMemcpyDeviceToHost, c->sr));
     HIPCHK(hipMemcpyAsync(c->h_total + 1, c->d_zero + ZB_ERR, sizeof(uint32_t), hipMemcpyDeviceToHost, c->sr));
-    HIPCHK(hipStreamSynchronize(c->sr));
+    spin_wait(c);
     if (c->h_total[1]) throw HipError{hipErrorUnknown, "single-pass scan look-back did not complete", __LINE__};
     const uint32_t n_pairs = *c->h_total;
     ensure_pairs(c, n_pairs);
@@ -261,8 +277,8 @@ void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool,
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[5], c->sr));
     const bool bstats = (c->opt.flags & VM3DGS_FLAG_BLEND_STATS) != 0;
-    launch_blend(c->sr, c->d_ranges, c->d_tile_order, c->d_pval[pb], c->d_xy, c->d_conic, c->d_rgb, (int)c->opt.img_w,
-                 (int)c->opt.img_h, c->TX, c->TY, (int)n_views, image, bstats ? c->d_bstats : nullptr);
+    launch_blend(c->sr, c->d_ranges, c->d_tile_order, c->d_pval[pb], c->d_xy, c->d_conic, c->d_rgb,
+                 (int)c->opt.img_w, (int)c->opt.img_h, c->TX, c->TY, (int)n_views, image, bstats ? c->d_bstats : nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[6], c->sr));
     if (bstats && st) {
@@ -416,6 +432,7 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         if (o.stream_copy) c->sc = (hipStream_t)o.stream_copy;
         else { HIPCHK(hipStreamCreateWithFlags(&c->sc, hipStreamNonBlocking)); c->own_sc = true; }
         HIPCHK(hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming));
         for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
         const int n_pg = c->n_pg, S = c->S, L = c->L, V = (int)o.max_views;
         const int64_t nc = ps.nc();
@@ -591,15 +608,22 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         }
         HIPCHK(hipGetLastError());
         HIPCHK(hipEventRecord(ev[2], c->sr));
+        // counters and the head of the copy list in one wait; a longer list
+        // (cold frames) takes a second
+        const uint32_t head = std::min<uint32_t>(kCopyHead, (uint32_t)c->n_pg * c->L);
         HIPCHK(hipMemcpyAsync(c->h_ctr, c->d_ctr, sizeof(uint32_t) * C_NCOUNTERS, hipMemcpyDeviceToHost, c->sr));
-        HIPCHK(hipStreamSynchronize(c->sr));
+        HIPCHK(hipMemcpyAsync(c->h_copies, c->d_copies, sizeof(CopyCmd) * head, hipMemcpyDeviceToHost, c->sr));
+        spin_wait(c);
         const uint32_t* k = c->h_ctr;
         const uint32_t n_copy = k[C_NCOPY];
         const uint32_t n_pf = (c->pf_on && c->pf_net) ? k[C_NPF] : 0u;
         const uint32_t n_dem = n_copy - n_pf;
         if (n_copy) {
-            HIPCHK(hipMemcpyAsync(c->h_copies, c->d_copies, sizeof(CopyCmd) * n_copy, hipMemcpyDeviceToHost, c->sr));
-            HIPCHK(hipStreamSynchronize(c->sr));
+            if (n_copy > head) {
+                HIPCHK(hipMemcpyAsync(c->h_copies + head, c->d_copies + head, sizeof(CopyCmd) * (n_copy - head),
+                                      hipMemcpyDeviceToHost, c->sr));
+                spin_wait(c);
+            }
             // merge runs that are contiguous on both sides, then one async copy per run
             const CopyCmd* cp = c->h_copies;
             uint64_t bytes = 0;

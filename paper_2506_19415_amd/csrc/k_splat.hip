@@ -14,10 +14,10 @@
 //                of their pair counts, so that the longest tiles start first
 //                and the short ones fill in behind them.
 //  k_blend       one 256-thread workgroup per 16x16 tile, one pixel per
-//                thread; Gaussians staged in LDS in batches of 256; per pixel
-//                front-to-back
-//                blending until transmittance would fall below 1e-4; the wave
-//                leaves when all its pixels are done.
+//                thread, one 16 x 4 strip per wave; Gaussians staged in LDS in
+//                batches of 256; per pixel front-to-back blending until
+//                transmittance would fall below 1e-4; the wave leaves a batch
+//                when all its pixels are done.
 #include "kcommon.h"
 #include "vm3dgs_impl.h"
 
@@ -309,22 +309,29 @@ __global__ void k_ranges(const uint32_t* __restrict__ key, uint32_t n, uint2* __
     if (i == n - 1 || key[i + 1] != t) ranges[t].y = i + 1;
 }
 
-// One 256-thread workgroup per 16x16 tile, one pixel per thread.  Gaussians
-// are staged in LDS in batches of 256; a wave stops when its 64 pixels are
-// done, the workgroup when all 256 are.  STATS counts, per tile, the
-// pixel-Gaussian evaluations and those that reached the alpha computation
-// (the algorithmic work of the kernel).
+// One 256-thread workgroup per 16x16 tile, one pixel per thread, one 16 x 4
+// strip per wave.  Gaussians are staged in LDS in batches of 256 (centre,
+// support half height, opacity; conic; colour).  A staged Gaussian is the
+// same for all 64 lanes, so its row test against the strip is taken on
+// scalar registers (a uniform branch); the lanes then evaluate it with the
+// pixel's "live" flag as a predicate, and the wave leaves the batch when no
+// lane is live.  STATS counts, per tile, the pixel-Gaussian evaluations and
+// those that reached the alpha computation (the algorithmic work).
 constexpr int BL_NT = TILE * TILE;
+
+__device__ __forceinline__ float uniform_f(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
 
 template <bool STATS>
 __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ ranges, const uint32_t* __restrict__ order,
-                                                 const uint32_t* __restrict__ pval,
-                                                 const float2* __restrict__ xy, const float4* __restrict__ conic,
-                                                 const float4* __restrict__ rgb, int W, int H, int TX, int TY,
-                                                 float* __restrict__ image, uint2* __restrict__ stats) {
-    __shared__ float2 s_xy[BL_NT];
-    __shared__ float4 s_co[BL_NT];
-    __shared__ float4 s_rgb[BL_NT];
+                                                 const uint32_t* __restrict__ pval, const float2* __restrict__ xy,
+                                                 const float4* __restrict__ conic, const float4* __restrict__ rgb,
+                                                 int W, int H, int TX, int TY, float* __restrict__ image,
+                                                 uint2* __restrict__ stats) {
+    __shared__ float4 s_a[BL_NT];    // u, v, support half height, opacity
+    __shared__ float4 s_b[BL_NT];    // conic ca, cb, cc
+    __shared__ float4 s_c[BL_NT];    // colour
     __shared__ uint32_t s_st[2][BL_NT / WAVE];
     const uint32_t tile = order[blockIdx.x];
     const uint32_t per_view = (uint32_t)(TX * TY);
@@ -334,48 +341,57 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
     const int px = tx * TILE + (int)(threadIdx.x % TILE);
     const int py = ty * TILE + (int)(threadIdx.x / TILE);
     const bool inside = px < W && py < H;
-    bool done = !inside;
     const uint2 rg = ranges[tile];
     const float fpx = (float)px, fpy = (float)py;
-    // centre row of this wave's 16 x 4 strip: a Gaussian whose support box
-    // misses the strip's rows is rejected by every pixel of the strip
-    const float strip_c = (float)(ty * TILE + (int)(threadIdx.x / WAVE) * (WAVE / TILE)) + 1.5f;
+    // centre row of this wave's strip, in a scalar register
+    const float strip_c = uniform_f((float)(ty * TILE + (int)(threadIdx.x / WAVE) * (WAVE / TILE)) + 1.5f);
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     uint32_t n_eval = 0, n_alpha = 0;
+    bool live = inside;   // this pixel still blends
     for (uint32_t base = rg.x; base < rg.y; base += BL_NT) {
-        if (__syncthreads_count(done ? 1 : 0) == BL_NT) break;
+        if (__syncthreads_count(live ? 1 : 0) == 0) break;
         const uint32_t j = base + threadIdx.x;
         if (j < rg.y) {
             const uint32_t f = pval[j];
-            s_xy[threadIdx.x] = xy[f];
-            s_co[threadIdx.x] = conic[f];
-            s_rgb[threadIdx.x] = rgb[f];
+            const float2 p = xy[f];
+            const float4 co = conic[f];
+            const float4 cl = rgb[f];
+            s_a[threadIdx.x] = make_float4(p.x, p.y, cl.w, co.w);
+            s_b[threadIdx.x] = co;
+            s_c[threadIdx.x] = cl;
         }
         __syncthreads();
         const int cnt = (int)min((uint32_t)BL_NT, rg.y - base);
-        for (int k = 0; k < cnt && !done; ++k) {
-            const float2 p = s_xy[k];
-            const float hy = s_rgb[k].w;
-            if (!(fabsf(p.y - strip_c) <= hy + 1.5f)) continue;
-            const float4 co = s_co[k];
-            const float dx = p.x - fpx, dy = p.y - fpy;
+        if (__ballot(live) == 0) continue;
+        for (int k = 0; k < cnt; ++k) {
+            const float4 a = s_a[k];
+            const float ay = uniform_f(a.y), ah = uniform_f(a.z);
+            // support rows miss the strip: every pixel of it rejects the Gaussian
+            if (!(fabsf(ay - strip_c) <= ah + 1.5f)) continue;
+            const float4 co = s_b[k];
+            const float dx = a.x - fpx, dy = a.y - fpy;
             const float q = fmaf(co.x * dx, dx, (co.z * dy) * dy);
             const float power = fmaf(-0.5f, q, -((co.y * dx) * dy));
-            if (STATS) ++n_eval;
-            // exp(-5.55) < 1/255 and opacity <= 1: such terms fail the alpha
-            // test, so their exp is not evaluated
-            if (power > 0.0f || power < -5.55f) continue;
-            if (STATS) ++n_alpha;
-            const float alpha = fminf(0.99f, co.w * vm_exp(power));
-            if (alpha < 1.0f / 255.0f) continue;
+            if (STATS) n_eval += live ? 1u : 0u;
+            // exp(-5.55) < 1/255 and opacity <= 1: outside [-5.55, 0] a term
+            // fails the alpha test, so the rest runs only when some lane is in
+            const bool in = live && !(power > 0.0f || power < -5.55f);
+            if (__ballot(in) == 0) continue;
+            if (STATS) n_alpha += in ? 1u : 0u;
+            // every lane computes; the pixel's state changes only where "in"
+            const float alpha = fminf(0.99f, a.w * vm_exp_core(fminf(fmaxf(power, -6.0f), 0.0f)));
+            const bool take = in && alpha >= 1.0f / 255.0f;
             const float Tn = T * (1.0f - alpha);
-            if (Tn < 0.0001f) { done = true; break; }
+            const bool stop = take && Tn < 0.0001f;
+            const bool add = take && !stop;
             const float wgt = alpha * T;
-            const float4 c = s_rgb[k];
-            C0 = fmaf(c.x, wgt, C0);
-            C1 = fmaf(c.y, wgt, C1);
-            C2 = fmaf(c.z, wgt, C2);
-            T = Tn;
+            const float4 c = s_c[k];
+            C0 = add ? fmaf(c.x, wgt, C0) : C0;
+            C1 = add ? fmaf(c.y, wgt, C1) : C1;
+            C2 = add ? fmaf(c.z, wgt, C2) : C2;
+            T = add ? Tn : T;
+            live = live && !stop;
+            if (__ballot(live) == 0) break;             // every pixel of the wave is done
         }
     }
     if (inside) {
@@ -383,8 +399,8 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
         o[0] = C0; o[1] = C1; o[2] = C2;
     }
     if (STATS) {
-        const uint32_t e = wave_sum(n_eval), a = wave_sum(n_alpha);
-        if (__lane_id() == 0) { s_st[0][threadIdx.x / WAVE] = e; s_st[1][threadIdx.x / WAVE] = a; }
+        const uint32_t e = wave_sum(n_eval), al = wave_sum(n_alpha);
+        if (__lane_id() == 0) { s_st[0][threadIdx.x / WAVE] = e; s_st[1][threadIdx.x / WAVE] = al; }
         __syncthreads();
         if (threadIdx.x == 0) {
             uint32_t se = 0, sa = 0;

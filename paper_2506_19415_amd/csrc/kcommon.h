@@ -80,6 +80,26 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, ui
 // r = x - n ln2 (ln2 = 22713/32768 + tail, so n*head is exact), degree-7
 // Taylor polynomial in Horner form with fused multiply-adds, times 2^n.
 // Zero below -87 (where e^x is still a normal float).
+// vm_exp without its underflow branch: equal to vm_exp for x in [-87, 0]
+__device__ __forceinline__ float vm_exp_core(float x) {
+    const float kLog2e = (float)(1.0 / 0.69314718055994530942);
+    const float kLn2Hi = (float)(22713.0 / 32768.0);
+    const float kLn2Lo = (float)(0.69314718055994530942 - 22713.0 / 32768.0);
+    const float n = rintf(x * kLog2e);
+    float r = fmaf(-n, kLn2Hi, x);
+    r = fmaf(-n, kLn2Lo, r);
+    float p = (float)(1.0 / 5040.0);
+    p = fmaf(p, r, (float)(1.0 / 720.0));
+    p = fmaf(p, r, (float)(1.0 / 120.0));
+    p = fmaf(p, r, (float)(1.0 / 24.0));
+    p = fmaf(p, r, (float)(1.0 / 6.0));
+    p = fmaf(p, r, 0.5f);
+    p = fmaf(p, r, 1.0f);
+    p = fmaf(p, r, 1.0f);
+    const int e = (int)n + 127;
+    return p * __int_as_float(e << 23);
+}
+
 __device__ __forceinline__ float vm_exp(float x) {
     if (!(x >= -87.0f)) return 0.0f;
     const float kLog2e = (float)(1.0 / 0.69314718055994530942);
