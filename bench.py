@@ -100,6 +100,164 @@ def cpu_baseline(sc, cams, budget_s=30.0):
                       f"(oracle create-time build {build_s:.1f} s not included)"}
 
 
+
+CITY = {
+    # three LOD levels (1024/128/16), the pool of 4M Gaussians, 1080p, the 600-frame street-ascent-aerial path
+    "city50m_lod": dict(fmt=0, views=1, img=(1920, 1080), idbuf=(240, 135)),
+    # the same with half-precision pages (SH bf16; scale, rotation, opacity fp16; means fp32)
+    "city50m_half": dict(fmt=1, views=1, img=(1920, 1080), idbuf=(240, 135)),
+    # half pages, eight views per call at 1280x720 on their own paths, sharing one pool, with the learned prefetch
+    "city50m_prefetch8": dict(fmt=1, views=8, img=(1280, 720), idbuf=(160, 90)),
+}
+
+
+def run_city(args, pkg, synth):
+    """The city workloads: VM frames per second over the path, the full-scene
+    fp32 splat of all level-0 Gaussians on the same cameras (FPS and the PSNR
+    of every VM image against it), stage times; for the prefetch workload the
+    demand misses, stalls and proposal quality with and without the network,
+    which is trained here on plain-pass frames of other paths."""
+    import numpy as np
+    import torch
+    cfg = CITY[args.workload]
+    W, H = cfg["img"]
+    V = cfg["views"]
+    t0 = time.time()
+    sc = synth.scene_city(0, n=args.city_n)
+    log(f"city scene {sc.n} Gaussians in {time.time() - t0:.1f} s")
+    if V == 1:
+        paths = [synth.path_city(sc, n_frames=600, width=W, height=H)]
+    else:
+        paths = [synth.path_city(sc, n_frames=600, width=W, height=H, seed=2000 + v) for v in range(V)]
+    frames = [[p[i] for p in paths] for i in range(600)]
+    t0 = time.time()
+    r = pkg.Renderer(sc, 1024, 3907, lod_levels=3, img=(W, H), idbuf=cfg["idbuf"], max_views=V,
+                     attr_format=cfg["fmt"], cell=2.0, lod_radius_px=32.0)
+    log(f"VM context (L=3, pool 3907, format {cfg['fmt']}) {time.time() - t0:.1f} s")
+    # LOD thresholds follow memory use (Sec. 4.1): the 4M-Gaussian pool cannot hold
+    # every page at the 32 px radius near street level
+    r.set_flags(pkg.VM3DGS_FLAG_LINKS | pkg.VM3DGS_FLAG_ADAPTIVE_LOD)
+    K, Wm = args.steps, args.warmup
+    net = None
+    pf_report = None
+    if args.workload == "city50m_prefetch8":
+        from paper_2506_19415_amd import prefetch as pf
+        center, extent = pf.scene_frame(sc)
+        KC, HB = 4096, 512
+        dims = [28 + HB, 256, 256, 256, KC]
+        n_paths = max(1, args.train_frames // 200)
+        train_paths = [synth.path_city(sc, n_frames=200, width=W, height=H, seed=1000 + i) for i in range(n_paths)]
+        r1 = pkg.Renderer(sc, 1024, 3907, lod_levels=3, img=(W, H), idbuf=cfg["idbuf"], max_views=1,
+                          attr_format=cfg["fmt"], cell=2.0, lod_radius_px=32.0)
+        t0 = time.time()
+        X, Y = pf.collect(r1, train_paths, KC, HB, center, extent)
+        r1.close()
+        log(f"training data: {X.shape[0]} frames in {time.time() - t0:.1f} s, positive rate {Y.mean():.4f}")
+        rng = np.random.default_rng(3)
+        params = []
+        for l in range(len(dims) - 1):
+            params.append((rng.standard_normal(dims[l] * dims[l + 1]) * np.sqrt(2.0 / dims[l]) * 0.5).astype(np.float32))
+            params.append(np.zeros(dims[l + 1], np.float32))
+        net = pkg.Mlp(dims, max_batch=max(256, V))
+        net.set_params(np.concatenate(params))
+        t0 = time.time()
+        losses = pf.train(net, X, Y, steps=3000, batch=256, lr=1e-3, log_every=1000)
+        log(f"training: 3000 Adam steps in {time.time() - t0:.1f} s, loss {losses}")
+        thr = pf.calibrate_threshold(net, X, Y, factor=2.0)
+        log(f"logit threshold {thr:.3f}")
+        pf_report = {"training_frames": int(X.shape[0]), "loss": losses, "dims": dims, "logit_threshold": thr}
+        r.set_prefetch(net, KC, HB, thr, 64, center, extent)
+
+    def run_frames(n0, n):
+        stats, walls = [], []
+        for i in range(n0, n0 + n):
+            t = time.perf_counter()
+            img, out = r.frame(frames[i % 600])
+            walls.append((time.perf_counter() - t) * 1e3)
+            stats.append(out.stats.as_dict())
+        return stats, walls
+
+    run_frames(0, Wm)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    stats, walls = run_frames(Wm, K)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    log(f"VM: {K} frames in {elapsed:.3f} s")
+    res_pf = None
+    if net is not None:
+        # the same frames without the network, from the same start
+        r.reset()
+        r.set_prefetch(None, 4096, 512, 0.0, 0, pf.scene_frame(sc)[0], pf.scene_frame(sc)[1])
+        run_frames(0, Wm)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        stats0, _ = run_frames(Wm, K)
+        torch.cuda.synchronize()
+        el0 = time.perf_counter() - t1
+        res_pf = {"fps_with": K / elapsed, "fps_without": K / el0,
+                  "demand_misses_per_frame_with": statistics.mean(s["misses"] for s in stats),
+                  "demand_misses_per_frame_without": statistics.mean(s["misses"] for s in stats0),
+                  "copy_stage_ms_with": statistics.mean(s["ms_copy"] for s in stats),
+                  "copy_stage_ms_without": statistics.mean(s["ms_copy"] for s in stats0),
+                  "prefetched_per_frame": statistics.mean(s["prefetched"] for s in stats)}
+        pf_report.update(res_pf)
+    # full-scene fp32 baseline on the same cameras, and PSNR of VM frames against it
+    r.close()
+    full_fps = psnrs = None
+    if not args.no_full:
+        rf = pkg.Renderer(sc, 1024, 1, lod_levels=1, img=(W, H), idbuf=cfg["idbuf"], max_views=V, attr_format=0,
+                          cell=2.0, full_scene=True)
+        for i in range(2):
+            rf.render_full(frames[(Wm + i) % 600])
+        torch.cuda.synchronize()
+        tf = time.perf_counter()
+        nf = min(K, 60)
+        for i in range(nf):
+            rf.render_full(frames[(Wm + i) % 600])
+        torch.cuda.synchronize()
+        full_fps = nf / (time.perf_counter() - tf)
+        # PSNR on every 10th timed frame: re-run the VM path to that frame
+        rv = pkg.Renderer(sc, 1024, 3907, lod_levels=3, img=(W, H), idbuf=cfg["idbuf"], max_views=V,
+                          attr_format=cfg["fmt"], cell=2.0, lod_radius_px=32.0)
+        rv.set_flags(pkg.VM3DGS_FLAG_LINKS | pkg.VM3DGS_FLAG_ADAPTIVE_LOD)
+        if net is not None:
+            rv.set_prefetch(net, 4096, 512, pf_report["logit_threshold"], 64, *pf.scene_frame(sc))
+        psnrs = []
+        for i in range(Wm + K):
+            img, _ = rv.frame(frames[i % 600])
+            if i >= Wm and (i - Wm) % 10 == 0:
+                vm_img = img.clone()
+                ref, _ = rf.render_full(frames[i % 600])
+                for v in range(V):
+                    psnrs.append(psnr(vm_img[v], ref[v]))
+        rv.close()
+        rf.close()
+        log(f"full: {full_fps:.1f} FPS; PSNR min {min(psnrs):.2f} median {statistics.median(psnrs):.2f}")
+
+    def med(key):
+        return statistics.median([s[key] for s in stats])
+
+    return {
+        "metric": METRIC, "value": K / elapsed, "unit": "frames/s", "n_gpus": 1, "steps": K, "warmup": Wm,
+        "ms_per_step": elapsed * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": f"synthetic (seeded city, {sc.n} Gaussians)",
+        "config": {"workload": f"{args.workload}: {sc.n} Gaussians, 1024/page, 3 LOD levels, pool 3907 pages, "
+                               f"{V} view(s) at {W}x{H}, 600-frame street-ascent-aerial path",
+                   "attr_format": "half" if cfg["fmt"] else "fp32", "views": V},
+        "fps_median_frame": 1000.0 / statistics.median(walls),
+        "full_scene_fps": full_fps, "speedup_vs_full": (K / elapsed) / full_fps if full_fps else None,
+        "psnr_min": min(psnrs) if psnrs else None, "psnr_median": statistics.median(psnrs) if psnrs else None,
+        "stage_ms_median": {k: med(k) for k in ["ms_visibility", "ms_pagetable", "ms_copy", "ms_preprocess",
+                                                 "ms_sort", "ms_blend", "ms_total"]},
+        "render_gaussians_median": med("render_gaussians"), "pairs_median": med("pairs"),
+        "lod_radius_px_median": med("lod_radius_px"), "lod_radius_px_max": max(s["lod_radius_px"] for s in stats),
+        "misses_per_frame": statistics.mean(s["misses"] for s in stats),
+        "missing_per_frame": statistics.mean(s["missing"] for s in stats),
+        "bytes_copied_per_frame": statistics.mean(s["bytes_copied"] for s in stats),
+        "prefetch": pf_report,
+    }
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +269,14 @@ def main():
                     help="after the timed frames, one plain device-to-device copy of this many MiB "
                          "(the reference kernel that scales the HBM counters)")
     ap.add_argument("--print-source-hash", action="store_true", help="print the k_blend source hash and exit")
+    ap.add_argument("--workload", default="terrain6m", choices=["terrain6m", "city50m_lod", "city50m_half",
+                                                                "city50m_prefetch8"],
+                    help="terrain6m (the default, the metric's workload) or the 50M-Gaussian city with three "
+                         "LOD levels: fp32, half-precision pages, or half pages with eight views and the "
+                         "learned prefetch")
+    ap.add_argument("--city-n", type=int, default=50_000_000, help="Gaussians of the city workloads")
+    ap.add_argument("--train-frames", type=int, default=2000,
+                    help="city50m_prefetch8: plain-pass frames of training data for the network")
     args = ap.parse_args()
     if args.print_source_hash:
         print(blend_source_hash())
@@ -131,6 +297,9 @@ def main():
     from paper_2506_19415_amd import synth
 
     torch.cuda.set_device(0)
+    if args.workload != "terrain6m":
+        print(json.dumps(run_city(args, pkg, synth)), flush=True)
+        return
     t0 = time.time()
     sc = synth.scene_terrain(0)
     cams = synth.path_terrain(sc)

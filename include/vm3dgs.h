@@ -64,6 +64,13 @@ typedef struct {
  * term fails the 1/255 alpha test; the image is the same either way, with
  * fewer (tile, Gaussian) pairs. */
 #define VM3DGS_FLAG_SIGMA3_TILES 8u
+/* With several LOD levels, move the level-0 radius with memory use (Sec. 4.1):
+ * up (coarser) when the frame's required physical pages exceed 95 % of the
+ * pool or requests go missing, down towards lod_radius_px below 80 % while
+ * coarse levels are in use; the step grows by 1.5 while the direction holds
+ * and halves when it reverses (1/64 .. 1/2, starting at 1/8).  The radius a
+ * frame used is in stats.lod_radius_px; the next frame uses the new one. */
+#define VM3DGS_FLAG_ADAPTIVE_LOD 16u
 
 typedef struct {
     uint32_t img_w, img_h;        /* output image, pixels */
@@ -111,6 +118,7 @@ typedef struct {
     uint64_t blend_evals;       /* pixel-Gaussian evaluations (VM3DGS_FLAG_BLEND_STATS only) */
     uint64_t blend_alphas;      /* of those, evaluations that computed alpha (same flag) */
     float ms_visibility, ms_pagetable, ms_copy, ms_preprocess, ms_sort, ms_blend, ms_total;
+    float lod_radius_px;        /* level-0 radius this frame used (moves with VM3DGS_FLAG_ADAPTIVE_LOD) */
 } vm3dgs_stats;
 
 typedef struct {

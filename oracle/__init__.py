@@ -61,6 +61,8 @@ def lib():
         L.or_vm_pagetable.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.or_vm_set_force_all.argtypes = [C.c_void_p, C.c_int]
         L.or_vm_set_sigma3_tiles.argtypes = [C.c_void_p, C.c_int]
+        L.or_vm_set_adaptive_lod.argtypes = [C.c_void_p, C.c_int]
+        L.or_vm_render_fp64.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Cam), C.c_int, C.c_void_p]
         L.or_vm_set_prefetch.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_float, C.c_int, C.c_void_p, C.c_float]
         L.or_vm_features.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
         L.or_vm_frame_prefetch.argtypes = [C.c_void_p, C.POINTER(_Cam), C.c_int, C.c_void_p, C.c_void_p]
@@ -145,7 +147,7 @@ _SCENE_DT = {"perm": np.int64, "attr0": np.float32, "attr1": np.float32, "attr2"
              "cell_start": np.int32, "link_start": np.int32, "link_dst": np.int32,
              "n_pages": np.int64, "n_cells": np.int64, "n_links": np.int64, "lo": np.float64}
 
-_VM_DT = {"pf_keys": np.uint64, "pf_x": np.float32, "pf_counts": np.int64, "frame": np.int64, "cand": np.uint8, "idbuf": np.uint64, "req_direct": np.uint32,
+_VM_DT = {"lod": np.float32, "pf_keys": np.uint64, "pf_x": np.float32, "pf_counts": np.int64, "frame": np.int64, "cand": np.uint8, "idbuf": np.uint64, "req_direct": np.uint32,
           "req_link": np.uint32, "page_level": np.int8, "req_page": np.int32, "req_level": np.int8,
           "req_class": np.uint8, "slot_level": np.int8, "last_used": np.int32, "sub_vpage": np.int32,
           "sub_last_used": np.int32, "v2p": np.int32, "copies": np.int64, "copy_id": np.int32,
@@ -236,6 +238,17 @@ class OracleVM:
         assert z.shape == (len(cams), self.pf_dims[0])
         m = None if tile_mask is None else np.ascontiguousarray(tile_mask, dtype=np.uint8)
         lib().or_vm_frame_prefetch(self.ptr, arr, len(cams), z.ctypes.data, None if m is None else m.ctypes.data)
+
+    def render_fp64(self, src_scene, cams):
+        """FP64 splat of the last frame's render set with the attributes of
+        src_scene (an OracleScene of the same pages)."""
+        arr = cams_array(cams)
+        img = np.zeros((len(cams), self.H, self.W, 3), np.float64)
+        lib().or_vm_render_fp64(self.ptr, src_scene.ptr, arr, len(cams), img.ctypes.data)
+        return img
+
+    def set_adaptive_lod(self, on=True):
+        lib().or_vm_set_adaptive_lod(self.ptr, int(bool(on)))
 
     def set_sigma3_tiles(self, on=True):
         """Tile rectangles from the 3-sigma radius alone (support box off)."""

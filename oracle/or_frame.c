@@ -67,6 +67,11 @@ struct or_vm {
     int frame;
     int force_all;         /* test switch: every page is directly requested */
     int sigma3_tiles;      /* 1: tile rectangles from the 3-sigma radius alone (no support box) */
+    int last_full;         /* the last splat was or_render_full (every level-0 Gaussian) */
+    /* LOD thresholds that follow memory use (Sec. 4.1) */
+    int adaptive;
+    float tau0, lod_step, tau_used;
+    int lod_dir, req_slots, n_coarse;
     /* learned prefetch (Sec. 6 future work): configuration, pose history,
      * the logits a frame is given and what the last frame did with them */
     int pf_on, pf_K, pf_H, pf_budget;
@@ -362,6 +367,8 @@ static void page_table(or_vm* vm)
     }
     (void)fresh;
     vm->n_copy_demand = vm->n_copy;
+    vm->req_slots = 0;
+    for (int s = 0; s < S; s++) vm->req_slots += slot_req[s];
     vm->n_prefetch = 0;
     vm->n_pf_req = 0;
     if (vm->pf_on && vm->pf_logits) prefetch_stage(vm, req_sub, slot_req);
@@ -742,6 +749,7 @@ or_vm* or_vm_create(const or_scene* s, int pool_pages, int copy_budget, int use_
     or_vm* vm = calloc(1, sizeof(or_vm));
     vm->s = s; vm->S = pool_pages; vm->budget = copy_budget; vm->use_links = use_links;
     vm->W = W; vm->H = H; vm->Wv = Wv; vm->Hv = Hv; vm->tau = tau; vm->guard = guard;
+    vm->tau0 = tau; vm->lod_step = 0.125f; vm->tau_used = tau;
     vm->TX = (W + 15) / 16; vm->TY = (H + 15) / 16;
     vm->P = or_scene_P(s); vm->L = or_scene_L(s); vm->n_pg = or_scene_npg(s);
     vm->bytes_g = or_scene_format(s) == 1 ? 124 : 236;
@@ -791,6 +799,23 @@ static int cmp_rq(const void* a, const void* b)
 {
     const rq* x = a; const rq* y = b;
     return (x->key > y->key) - (x->key < y->key);
+}
+
+/* LOD thresholds from memory use: above 95 % of the pool required (or any
+ * request missing) the level-0 radius moves up, below 80 % with coarse levels
+ * requested it moves back down, not below its configured value; the relative
+ * step grows by 1.5 while the direction holds and halves on a reversal
+ * (1/64 .. 1/2).  The next frame uses the new radius. */
+static void lod_control(or_vm* vm)
+{
+    int d = 0;
+    if (vm->n_missing > 0 || (int64_t)vm->req_slots * 20 > (int64_t)vm->S * 19) d = 1;
+    else if ((int64_t)vm->req_slots * 5 < (int64_t)vm->S * 4 && vm->n_coarse > 0 && vm->tau > vm->tau0) d = -1;
+    if (d == 0) return;
+    if (vm->lod_dir == d) vm->lod_step = fminf(vm->lod_step * 1.5f, 0.5f);
+    else if (vm->lod_dir == -d) vm->lod_step = fmaxf(vm->lod_step * 0.5f, 0.015625f);
+    vm->lod_dir = d;
+    vm->tau = d > 0 ? vm->tau * (1.0f + vm->lod_step) : fmaxf(vm->tau / (1.0f + vm->lod_step), vm->tau0);
 }
 
 /* visibility, requests and page table; brute_force selects the every-pixel raster */
@@ -859,8 +884,12 @@ int or_vm_visibility(or_vm* vm, const or_camera* cams, int n_views, int brute_fo
         vm->req_depth[i] = (uint32_t)((r[i].key >> 30) & 0x7fffffffu);
     }
     free(r);
+    vm->n_coarse = 0;
+    for (int p = 0; p < n_pg; p++) vm->n_coarse += vm->page_level[p] > 0;
+    vm->tau_used = vm->tau;
     page_table(vm);
     build_render_list(vm);
+    if (vm->adaptive && vm->L > 1) lod_control(vm);
     vm->frame++;
     return 0;
 }
@@ -931,8 +960,11 @@ int or_vm_frame_prefetch(or_vm* vm, const or_camera* cams, int n_views, const fl
 
 void or_vm_set_sigma3_tiles(or_vm* vm, int on) { vm->sigma3_tiles = on; }
 
+void or_vm_set_adaptive_lod(or_vm* vm, int on) { vm->adaptive = on; }
+
 int or_vm_frame(or_vm* vm, const or_camera* cams, int n_views, const uint8_t* tile_mask)
 {
+    vm->last_full = 0;
     or_vm_visibility(vm, cams, n_views, 0);
     const float** g = malloc(sizeof(float*) * (size_t)(vm->n_render > 0 ? vm->n_render : 1));
     for (int i = 0; i < vm->n_rl; i++) {
@@ -954,8 +986,129 @@ int or_render_full(or_vm* vm, const or_camera* cams, int n_views, const uint8_t*
     for (int64_t k = 0; k < n; k++) g[k] = a + k * OR_REC;
     vm->n_views = n_views;
     vm->n_render = n;
+    vm->last_full = 1;
     splat(vm, cams, n_views, tile_mask, g, n);
     free(g);
+    return 0;
+}
+
+/* ---- FP64 reference render of the current render set ----------------------
+ * The last frame's render list, with the attributes of `src` (a scene of the
+ * same pages: the half-precision scene gives the decoded half attributes, an
+ * fp32 scene the original ones), splatted in double with libm exp: the same
+ * steps as the float path (EWA with 0.3 dilation, 3-sigma tile rectangles,
+ * SH colour, per-tile (depth, index) order, alpha = min(0.99, o e^power),
+ * skip below 1/255, stop before T < 1e-4), no rounding to float anywhere.
+ * image: [n_views][H][W][3] doubles. */
+typedef struct { double u, v, depth, ca, cb, cc, o, rgb[3]; int x0, y0, x1, y1, ok; } ppd_t;
+
+static void preprocess_d(const float* g, const or_camera* c, int W, int H, int TX, int TY, ppd_t* o)
+{
+    memset(o, 0, sizeof *o);
+    double op = g[10];
+    if (op == 0.0) return;
+    const float* V = c->view;
+    double t[3];
+    for (int r = 0; r < 3; r++) t[r] = (double)V[4 * r] * g[0] + (double)V[4 * r + 1] * g[1] + (double)V[4 * r + 2] * g[2] + V[4 * r + 3];
+    if (!(t[2] > c->znear)) return;
+    double w = g[6], x = g[7], y = g[8], z = g[9];
+    double R[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
+                      {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
+                      {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
+    double M[3][3], Sg[3][3];
+    for (int i = 0; i < 3; i++) for (int j = 0; j < 3; j++) M[i][j] = R[i][j] * g[3 + j];
+    for (int i = 0; i < 3; i++) for (int k = 0; k < 3; k++) Sg[i][k] = M[i][0] * M[k][0] + M[i][1] * M[k][1] + M[i][2] * M[k][2];
+    double limx = 1.3 * (0.5 * W / c->fx), limy = 1.3 * (0.5 * H / c->fy);
+    double cxz = fmin(limx, fmax(-limx, t[0] / t[2])) * t[2], cyz = fmin(limy, fmax(-limy, t[1] / t[2])) * t[2];
+    double j00 = c->fx / t[2], j02 = -(c->fx * cxz) / (t[2] * t[2]);
+    double j11 = c->fy / t[2], j12 = -(c->fy * cyz) / (t[2] * t[2]);
+    double T0[3], T1[3], U0[3], U1[3];
+    for (int j = 0; j < 3; j++) { T0[j] = j00 * V[j] + j02 * V[8 + j]; T1[j] = j11 * V[4 + j] + j12 * V[8 + j]; }
+    for (int j = 0; j < 3; j++) {
+        U0[j] = T0[0] * Sg[0][j] + T0[1] * Sg[1][j] + T0[2] * Sg[2][j];
+        U1[j] = T1[0] * Sg[0][j] + T1[1] * Sg[1][j] + T1[2] * Sg[2][j];
+    }
+    double a = U0[0] * T0[0] + U0[1] * T0[1] + U0[2] * T0[2] + 0.3;
+    double b = U0[0] * T1[0] + U0[1] * T1[1] + U0[2] * T1[2];
+    double cc = U1[0] * T1[0] + U1[1] * T1[1] + U1[2] * T1[2] + 0.3;
+    double det = a * cc - b * b;
+    if (!(det > 0.0)) return;
+    double mid = 0.5 * (a + cc), lam = mid + sqrt(fmax(0.1, mid * mid - det));
+    double rad = ceil(3.0 * sqrt(lam));
+    double u = c->fx * t[0] / t[2] + (c->cx - 0.5), v = c->fy * t[1] / t[2] + (c->cy - 0.5);
+    int x0 = (int)fmin(fmax(floor((u - rad) / 16.0), 0.0), TX), x1 = (int)fmin(fmax(floor((u + rad + 15.0) / 16.0), 0.0), TX);
+    int y0 = (int)fmin(fmax(floor((v - rad) / 16.0), 0.0), TY), y1 = (int)fmin(fmax(floor((v + rad + 15.0) / 16.0), 0.0), TY);
+    if (x1 <= x0 || y1 <= y0) return;
+    double d0 = g[0] - c->cam_pos[0], d1 = g[1] - c->cam_pos[1], d2 = g[2] - c->cam_pos[2];
+    double len = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    for (int ch = 0; ch < 3; ch++) {
+        double acc = 0.0;
+        for (int k = 0; k < 16; k++) acc += or_sh_basis(k, d0 / len, d1 / len, d2 / len) * g[11 + 3 * k + ch];
+        acc += 0.5;
+        o->rgb[ch] = acc > 0.0 ? acc : 0.0;
+    }
+    o->u = u; o->v = v; o->depth = t[2];
+    o->ca = cc / det; o->cb = -b / det; o->cc = a / det; o->o = op;
+    o->x0 = x0; o->y0 = y0; o->x1 = x1; o->y1 = y1; o->ok = 1;
+}
+
+typedef struct { double depth; int64_t idx; } dd_t;
+
+static int cmp_dd(const void* x, const void* y)
+{
+    const dd_t* a = x; const dd_t* b = y;
+    if (a->depth != b->depth) return a->depth < b->depth ? -1 : 1;
+    return (a->idx > b->idx) - (a->idx < b->idx);
+}
+
+int or_vm_render_fp64(const or_vm* vm, const or_scene* src, const or_camera* cams, int n_views, double* image)
+{
+    int W = vm->W, H = vm->H, TX = vm->TX, TY = vm->TY;
+    int64_t n = vm->n_render;
+    const float** g = malloc(sizeof(float*) * (size_t)(n > 0 ? n : 1));
+    if (vm->last_full) {
+        const float* a = or_scene_attr(src, 0);
+        for (int64_t k = 0; k < n; k++) g[k] = a + k * OR_REC;
+    } else {
+        for (int i = 0; i < vm->n_rl; i++) {
+            const float* a = or_scene_attr(src, vm->rl[i].level);
+            int64_t Pl = vm->rl[i].count;
+            for (int64_t k = 0; k < Pl; k++) g[vm->rl[i].base + k] = a + ((int64_t)vm->rl[i].page * Pl + k) * OR_REC;
+        }
+    }
+    ppd_t* pp = malloc(sizeof(ppd_t) * (size_t)(n > 0 ? n : 1));
+    dd_t* list = malloc(sizeof(dd_t) * (size_t)(n > 0 ? n : 1));
+    for (int v = 0; v < n_views; v++) {
+        for (int64_t r = 0; r < n; r++) preprocess_d(g[r], &cams[v], W, H, TX, TY, &pp[r]);
+        for (int ty = 0; ty < TY; ty++)
+            for (int tx = 0; tx < TX; tx++) {
+                int64_t m = 0;
+                for (int64_t r = 0; r < n; r++)
+                    if (pp[r].ok && pp[r].x0 <= tx && tx < pp[r].x1 && pp[r].y0 <= ty && ty < pp[r].y1) {
+                        list[m].depth = pp[r].depth; list[m].idx = r; m++;
+                    }
+                qsort(list, (size_t)m, sizeof(dd_t), cmp_dd);
+                for (int py = ty * 16; py < ty * 16 + 16 && py < H; py++)
+                    for (int px = tx * 16; px < tx * 16 + 16 && px < W; px++) {
+                        double T = 1.0, C[3] = {0.0, 0.0, 0.0};
+                        for (int64_t q = 0; q < m; q++) {
+                            const ppd_t* o = &pp[list[q].idx];
+                            double dx = o->u - px, dy = o->v - py;
+                            double power = -0.5 * (o->ca * dx * dx + o->cc * dy * dy) - o->cb * dx * dy;
+                            if (power > 0.0) continue;
+                            double alpha = fmin(0.99, o->o * exp(power));
+                            if (alpha < 1.0 / 255.0) continue;
+                            double Tn = T * (1.0 - alpha);
+                            if (Tn < 1e-4) break;
+                            for (int ch = 0; ch < 3; ch++) C[ch] += o->rgb[ch] * alpha * T;
+                            T = Tn;
+                        }
+                        double* out = image + (((size_t)v * H + py) * W + px) * 3;
+                        for (int ch = 0; ch < 3; ch++) out[ch] = C[ch];
+                    }
+            }
+    }
+    free(list); free(pp); free(g);
     return 0;
 }
 
@@ -986,6 +1139,10 @@ int64_t or_vm_get(const or_vm* vm, const char* name, void* dst, int64_t cap)
     if (!strcmp(name, "copies")) return put(dst, cap, vm->copy, 24 * (int64_t)vm->n_copy);
     if (!strcmp(name, "copy_id")) return put(dst, cap, vm->copy_id, 16 * (int64_t)vm->n_copy);
     if (!strcmp(name, "missing")) return put(dst, cap, vm->missing, 8 * (int64_t)vm->n_missing);
+    if (!strcmp(name, "lod")) {
+        float f[2] = {vm->tau_used, vm->tau};
+        return put(dst, cap, f, sizeof f);
+    }
     if (!strcmp(name, "pf_keys")) return put(dst, cap, vm->pf_keys, 8 * (int64_t)vm->n_pf_req);
     if (!strcmp(name, "pf_x")) return put(dst, cap, vm->pf_x, 4 * (int64_t)vm->n_views * (28 + vm->pf_H));
     if (!strcmp(name, "pf_counts")) {

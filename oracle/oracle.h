@@ -76,6 +76,8 @@ int or_vm_pagetable(or_vm* vm, int n, const int32_t* pages, const int8_t* levels
  * 3-sigma radius alone (the support box off). */
 void or_vm_set_force_all(or_vm* vm, int on);
 void or_vm_set_sigma3_tiles(or_vm* vm, int on);
+/* LOD thresholds that follow memory use (several levels only). */
+void or_vm_set_adaptive_lod(or_vm* vm, int on);
 
 /* Learned prefetch: n_clusters equal page-id ranges, hist_bins equal ranges
  * for the residency features, proposals where a logit exceeds
@@ -100,6 +102,11 @@ double or_mlp_backward(int B, int n_layers, const int* dims, const float* params
                        int bf16, double* grad, double* z);
 void or_adam(int64_t n, float* w, float* m, float* v, const double* g, double lr, double b1, double b2, double eps,
              int t);
+
+/* FP64 reference splat of the last frame's render set with the attributes
+ * of src (a scene of the same pages, e.g. the fp32 form of a half scene);
+ * image: [n_views][H][W][3] doubles. */
+int or_vm_render_fp64(const or_vm* vm, const or_scene* src, const or_camera* cams, int n_views, double* image);
 
 /* fp16 / bf16 round trips (round to nearest even) */
 float or_round_f16(float x);

@@ -20,6 +20,7 @@ VM3DGS_FLAG_LINKS = 1
 VM3DGS_FLAG_FULL_SCENE_COPY = 2
 VM3DGS_FLAG_BLEND_STATS = 4
 VM3DGS_FLAG_SIGMA3_TILES = 8
+VM3DGS_FLAG_ADAPTIVE_LOD = 16
 
 _ERRORS = {-1: "INVALID_ARG", -2: "HOST_OOM", -3: "DEVICE_OOM", -4: "HIP", -5: "STATE", -6: "CAPACITY"}
 
@@ -60,7 +61,7 @@ class vm3dgs_stats(C.Structure):
                [(n, C.c_uint64) for n in ("render_gaussians", "visible_gaussians", "pairs", "bytes_copied",
                                            "blend_evals", "blend_alphas")] + \
                [(n, C.c_float) for n in ("ms_visibility", "ms_pagetable", "ms_copy", "ms_preprocess", "ms_sort",
-                                          "ms_blend", "ms_total")]
+                                          "ms_blend", "ms_total", "lod_radius_px")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -40,6 +40,9 @@ struct vm3dgs {
     float4* d_sph = nullptr; float4* d_clo = nullptr; float4* d_chi = nullptr;
     int32_t* d_ls = nullptr; int32_t* d_ld = nullptr;
     uint8_t* d_pool = nullptr; uint8_t* d_full = nullptr; uint8_t* h_store = nullptr;
+    const uint8_t* h_store_dev = nullptr;   // the pinned store as the GPU addresses it
+    uint32_t* d_cp_err = nullptr;           // sticky flag: a copy command out of bounds
+    unsigned long long* d_pf_bytes = nullptr;   // bytes of prefetch copies (copy stream)
     int64_t* d_level_base = nullptr;
     CamK* d_cams = nullptr; CamK* h_cams = nullptr;
     // visibility
@@ -77,6 +80,10 @@ struct vm3dgs {
     uint32_t* d_total = nullptr; uint32_t* h_total = nullptr;
     uint2* d_bstats = nullptr; uint2* h_bstats = nullptr;
     int frame = 0;
+    bool multi = false;   // multi-kernel page table (several levels or a large table)
+    // LOD threshold control from memory use (VM3DGS_FLAG_ADAPTIVE_LOD)
+    float lod_tau = 0.0f, lod_step = 0.125f;
+    int lod_dir = 0;
     // learned prefetch: configuration, pose history (host), features, proposals
     bool pf_on = false, pf_pending = false;
     vm3dgs_prefetch_opts pf{};
@@ -157,6 +164,7 @@ void free_all(vm3dgs* c) {
     if (c->sc) hipStreamSynchronize(c->sc);
     dfree(c->d_sph); dfree(c->d_clo); dfree(c->d_chi); dfree(c->d_ls); dfree(c->d_ld);
     dfree(c->d_pool); dfree(c->d_full); hfree(c->h_store); dfree(c->d_level_base);
+    dfree(c->d_cp_err); dfree(c->d_pf_bytes);
     dfree(c->d_cams); hfree(c->h_cams);
     dfree(c->d_cand); dfree(c->d_rays); dfree(c->d_idbuf);
     dfree(c->d_crect); dfree(c->d_carea); dfree(c->d_coffs); dfree(c->d_vtemp); dfree(c->d_rd); dfree(c->d_rl); dfree(c->d_plevel);
@@ -184,9 +192,7 @@ void free_all(vm3dgs* c) {
     if (c->own_sc && c->sc) hipStreamDestroy(c->sc);
 }
 
-constexpr uint32_t kCopyHead = 128;   // copy commands read back with the counters
-
-constexpr int ZB_CTR = 0, ZB_ERR = C_NCOUNTERS, ZB_TICKETS = ZB_ERR + 16,
+constexpr int ZB_CTR = 0, ZB_ERR = C_NCOUNTERS, ZB_BYTES = ZB_ERR + 2, ZB_TICKETS = ZB_ERR + 16,
               ZB_HIST = ZB_TICKETS + SortWork::kMaxTickets, ZB_WORDS = ZB_HIST + 256 * SortWork::kMaxHist;
 
 void ensure_status(vm3dgs* c) {
@@ -349,6 +355,26 @@ void pf_features(vm3dgs* c, uint32_t n_views) {
     launch_pf_features(c->sr, c->d_v2p, c->n_pg, c->L, (int)c->pf.hist_bins, (int)n_views, c->d_pf_x);
 }
 
+// The LOD thresholds follow memory use (Sec. 4.1): when the frame's required
+// physical pages exceed 95 % of the pool, or requests went missing, the level-0
+// radius tau moves up (coarser, thresholds move away from the camera); below
+// 80 % with coarse levels in use it moves back down, never below the
+// configured radius.  The relative step grows by 1.5 while the direction
+// holds and halves when it reverses (within 1/64 .. 1/2).  The new tau is
+// used from the next frame on.
+void lod_control(vm3dgs* c, uint32_t n_missing, uint32_t req_slots, uint32_t n_coarse) {
+    const float tau0 = c->opt.lod_radius_px;
+    const uint64_t S = (uint64_t)c->S;
+    int d = 0;
+    if (n_missing > 0 || (uint64_t)req_slots * 20 > S * 19) d = 1;
+    else if ((uint64_t)req_slots * 5 < S * 4 && n_coarse > 0 && c->lod_tau > tau0) d = -1;
+    if (d == 0) return;
+    if (c->lod_dir == d) c->lod_step = std::min(c->lod_step * 1.5f, 0.5f);
+    else if (c->lod_dir == -d) c->lod_step = std::max(c->lod_step * 0.5f, 0.015625f);
+    c->lod_dir = d;
+    c->lod_tau = d > 0 ? c->lod_tau * (1.0f + c->lod_step) : std::max(c->lod_tau / (1.0f + c->lod_step), tau0);
+}
+
 vm3dgs_status fail(vm3dgs* c, const HipError& h) {
     c->err = std::string("HIP error ") + hipGetErrorString(h.e) + " in " + h.what + " (api.cpp:" +
              std::to_string(h.line) + ")";
@@ -421,11 +447,10 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
     const PagedScene& ps = c->ps;
     c->S = (int)pool_pages; c->L = (int)lod_levels; c->P = (int)page_size; c->n_pg = ps.n_pg;
     c->TX = (int)((o.img_w + 15) / 16); c->TY = (int)((o.img_h + 15) / 16);
-    if (c->L == 1 && !pagetable_l1_fits(c->n_pg, c->S)) {
-        g_create_error = "this build handles at most 8192 pages and 8192 physical pages with one LOD level";
-        delete c;
-        return VM3DGS_E_INVALID_ARG;
-    }
+    // one level and a table that fits one workgroup's LDS: the single-kernel page
+    // table; otherwise the multi-kernel one (sorted candidate lists, ordered walk)
+    c->multi = c->L > 1 || !pagetable_l1_fits(c->n_pg, c->S);
+    c->lod_tau = o.lod_radius_px;
     try {
         if (o.stream_render) c->sr = (hipStream_t)o.stream_render;
         else { HIPCHK(hipStreamCreateWithFlags(&c->sr, hipStreamNonBlocking)); c->own_sr = true; }
@@ -454,6 +479,15 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         // pinned page-major store and the pool
         halloc(&c->h_store, (size_t)ps.store_bytes);
         encode_store(ps, c->h_store);
+        {
+            void* dp = nullptr;
+            HIPCHK(hipHostGetDevicePointer(&dp, c->h_store, 0));
+            c->h_store_dev = (const uint8_t*)dp;
+        }
+        dalloc(&c->d_cp_err, 4);
+        HIPCHK(hipMemset(c->d_cp_err, 0, 16));
+        dalloc(&c->d_pf_bytes, 1);
+        HIPCHK(hipMemset(c->d_pf_bytes, 0, 8));
         const size_t slot_bytes = (size_t)c->P * ps.bytes_g;
         dalloc(&c->d_pool, slot_bytes * S);
         HIPCHK(hipMemset(c->d_pool, 0, slot_bytes * S));
@@ -489,7 +523,7 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         dalloc(&c->d_copy_id, (size_t)4 * n_pg * L);
         dalloc(&c->d_missing, (size_t)2 * n_pg * L); halloc(&c->h_missing, (size_t)2 * n_pg * L);
         dalloc(&c->d_rlist, n_pg);
-        if (L > 1) {
+        if (c->multi) {
             dalloc(&c->d_lkeys_alt, n_pg); dalloc(&c->d_lflag, n_pg); dalloc(&c->d_lpos, (size_t)n_pg + 1);
             dalloc(&c->d_wkeys[0], S); dalloc(&c->d_wkeys[1], S);
             for (int l = 1; l < L; ++l) { dalloc(&c->d_ck[l][0], (size_t)S * SUBS); dalloc(&c->d_ck[l][1], (size_t)S * SUBS); }
@@ -508,7 +542,7 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         dalloc(&c->d_ranges, (size_t)c->TX * c->TY * V);
         dalloc(&c->d_tile_order, (size_t)c->TX * c->TY * V);
         dalloc(&c->d_bstats, (size_t)c->TX * c->TY * V); halloc(&c->h_bstats, (size_t)c->TX * c->TY * V);
-        dalloc(&c->d_total, 4); halloc(&c->h_total, 4);  // [0] pairs, [1] look-back error
+        dalloc(&c->d_total, 4); halloc(&c->h_total, 8);  // [0] pairs, [1] look-back error, [2..3] bytes, [4] copy error
         c->cap_pairs = 0;
         ensure_pairs(c, o.pair_capacity ? o.pair_capacity : std::max<uint64_t>(R * 4, 1u << 22));
         ensure_temp(c);
@@ -559,7 +593,7 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         va.spheres = c->d_sph; va.n_pg = c->n_pg; va.cell_lo = c->d_clo; va.cell_hi = c->d_chi; va.nc = c->ps.nc();
         va.link_start = c->d_ls; va.link_dst = c->d_ld; va.use_links = (c->opt.flags & VM3DGS_FLAG_LINKS) ? 1 : 0;
         va.cams = c->d_cams; va.n_views = (int)n_views; va.W = (int)c->opt.img_w; va.H = (int)c->opt.img_h;
-        va.Wv = (int)c->opt.idbuf_w; va.Hv = (int)c->opt.idbuf_h; va.L = c->L; va.tau = c->opt.lod_radius_px;
+        va.Wv = (int)c->opt.idbuf_w; va.Hv = (int)c->opt.idbuf_h; va.L = c->L; va.tau = c->lod_tau;
         va.fy_max = fy_max;
         va.guard = c->opt.idbuf_guard_px;
         va.cand = c->d_cand; va.rays = c->d_rays; va.idbuf = c->d_idbuf; va.req_direct = c->d_rd; va.req_link = c->d_rl;
@@ -576,7 +610,7 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         pa.sub_last_used = c->d_sub_lu; pa.v2p = c->d_v2p; pa.req_sub = c->d_req_sub; pa.slot_req = c->d_slot_req;
         pa.miss = c->d_miss; pa.copies = c->d_copies; pa.copy_id = c->d_copy_id; pa.missing = c->d_missing;
         pa.counters = c->d_ctr; pa.level_base = c->d_level_base; pa.rl = c->d_rlist;
-        if (c->L == 1) {
+        if (!c->multi) {
             launch_pagetable(c->sr, pa, 0);
         } else {
             LodWork lw{};
@@ -595,7 +629,7 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
             PfArgs fa{};
             fa.logits = nd.logits; fa.K = (int)c->pf.n_clusters; fa.thr = c->pf.logit_threshold;
             fa.page_level = c->d_plevel; fa.v2p = c->d_v2p; fa.sph = c->d_sph; fa.n_pg = c->n_pg; fa.L = c->L;
-            fa.tau = c->opt.lod_radius_px; fa.fy = fy_max; fa.cams = c->d_cams; fa.n_views = (int)n_views;
+            fa.tau = c->lod_tau; fa.fy = fy_max; fa.cams = c->d_cams; fa.n_views = (int)n_views;
             fa.keys[0] = c->d_pf_keys[0]; fa.keys[1] = c->d_pf_keys[1];
             fa.idle[0] = c->d_pf_idle[0]; fa.idle[1] = c->d_pf_idle[1];
             fa.S = c->S; fa.P = c->P; fa.frame = c->frame; fa.budget = (int)c->pf.budget_pages;
@@ -608,65 +642,38 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         }
         HIPCHK(hipGetLastError());
         HIPCHK(hipEventRecord(ev[2], c->sr));
-        // counters and the head of the copy list in one wait; a longer list
-        // (cold frames) takes a second
-        const uint32_t head = std::min<uint32_t>(kCopyHead, (uint32_t)c->n_pg * c->L);
+        // the counters: how many copies, render entries and Gaussians this frame has
         HIPCHK(hipMemcpyAsync(c->h_ctr, c->d_ctr, sizeof(uint32_t) * C_NCOUNTERS, hipMemcpyDeviceToHost, c->sr));
-        HIPCHK(hipMemcpyAsync(c->h_copies, c->d_copies, sizeof(CopyCmd) * head, hipMemcpyDeviceToHost, c->sr));
         spin_wait(c);
         const uint32_t* k = c->h_ctr;
         const uint32_t n_copy = k[C_NCOPY];
         const uint32_t n_pf = (c->pf_on && c->pf_net) ? k[C_NPF] : 0u;
         const uint32_t n_dem = n_copy - n_pf;
-        if (n_copy) {
-            if (n_copy > head) {
-                HIPCHK(hipMemcpyAsync(c->h_copies + head, c->d_copies + head, sizeof(CopyCmd) * (n_copy - head),
-                                      hipMemcpyDeviceToHost, c->sr));
-                spin_wait(c);
-            }
-            // merge runs that are contiguous on both sides, then one async copy per run
-            const CopyCmd* cp = c->h_copies;
-            uint64_t bytes = 0;
-            auto issue = [&](uint32_t i, uint32_t end) {
-                while (i < end) {
-                    int64_t h = cp[i].host_off, d = cp[i].pool_off, b = cp[i].bytes;
-                    uint32_t j = i + 1;
-                    while (j < end && cp[j].host_off == h + b && cp[j].pool_off == d + b) { b += cp[j].bytes; ++j; }
-                    HIPCHK(hipMemcpyAsync(c->d_pool + d, c->h_store + h, (size_t)b, hipMemcpyHostToDevice, c->sc));
-                    bytes += (uint64_t)b;
-                    i = j;
-                }
-            };
-            // demand copies: this frame's render waits for them
-            issue(0, n_dem);
-            if (n_dem) {
-                HIPCHK(hipEventRecord(c->ev_copy, c->sc));
-                HIPCHK(hipStreamWaitEvent(c->sr, c->ev_copy, 0));
-            }
-            st.bytes_copied = bytes;
-        }
-        // prefetch copies of earlier frames complete before this frame reads the pool;
-        // this frame's prefetch copies follow its demand copies and are not awaited here
+        const uint64_t max_cmd = (uint64_t)c->P * c->ps.bytes_g;
+        const uint64_t pool_bytes = max_cmd * (uint64_t)c->S;
+        // prefetch copies of earlier frames (copy stream) finish before this frame
+        // writes or reads the pool
         if (c->pf_pending) {
             HIPCHK(hipStreamWaitEvent(c->sr, c->ev_pf, 0));
             c->pf_pending = false;
         }
+        // demand copies: read by the GPU from the pinned store, in order before the splat
+        launch_copy_pages(c->sr, c->d_copies, 0, n_dem, max_cmd, c->h_store_dev, (uint64_t)c->ps.store_bytes,
+                          c->d_pool, pool_bytes, (unsigned long long*)(c->d_zero + ZB_BYTES), c->d_cp_err);
+        HIPCHK(hipGetLastError());
+        // prefetch copies: on the copy stream, after the page table; not awaited by this frame
         if (n_pf) {
-            const CopyCmd* cp = c->h_copies;
-            uint32_t i = n_dem;
-            uint64_t bytes = 0;
-            while (i < n_copy) {
-                int64_t h = cp[i].host_off, d = cp[i].pool_off, b = cp[i].bytes;
-                uint32_t j = i + 1;
-                while (j < n_copy && cp[j].host_off == h + b && cp[j].pool_off == d + b) { b += cp[j].bytes; ++j; }
-                HIPCHK(hipMemcpyAsync(c->d_pool + d, c->h_store + h, (size_t)b, hipMemcpyHostToDevice, c->sc));
-                bytes += (uint64_t)b;
-                i = j;
-            }
+            HIPCHK(hipEventRecord(c->ev_copy, c->sr));
+            HIPCHK(hipStreamWaitEvent(c->sc, c->ev_copy, 0));
+            launch_copy_pages(c->sc, c->d_copies, n_dem, n_pf, max_cmd, c->h_store_dev,
+                              (uint64_t)c->ps.store_bytes, c->d_pool, pool_bytes, c->d_pf_bytes, c->d_cp_err);
+            HIPCHK(hipGetLastError());
             HIPCHK(hipEventRecord(c->ev_pf, c->sc));
             c->pf_pending = true;
-            st.bytes_copied += bytes;
         }
+        st.lod_radius_px = c->lod_tau;
+        if ((c->opt.flags & VM3DGS_FLAG_ADAPTIVE_LOD) && c->L > 1)
+            lod_control(c, k[C_NMISSING], k[C_REQSLOTS], k[C_NCOARSE]);
         c->last_n_pfreq = (c->pf_on && c->pf_net) ? k[C_NPFREQ] : 0u;
         c->last_n_pf = n_pf;
         st.prefetched = n_pf;
@@ -686,7 +693,16 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         if (c->last_n_missing)
             HIPCHK(hipMemcpyAsync(c->h_missing, c->d_missing, sizeof(int32_t) * 2 * c->last_n_missing,
                                   hipMemcpyDeviceToHost, c->sr));
+        HIPCHK(hipMemcpyAsync(c->h_total + 2, c->d_zero + ZB_BYTES, 8, hipMemcpyDeviceToHost, c->sr));
+        HIPCHK(hipMemcpyAsync(c->h_total + 4, c->d_cp_err, 4, hipMemcpyDeviceToHost, c->sr));
         HIPCHK(hipStreamSynchronize(c->sr));
+        if (c->h_total[4]) throw HipError{hipErrorInvalidValue, "a page copy command left the store or the pool",
+                                          __LINE__};
+        {
+            uint64_t b;
+            memcpy(&b, c->h_total + 2, 8);
+            st.bytes_copied = b;
+        }
         c->out_req.resize(c->last_n_req);
         c->out_req_level.resize(c->last_n_req);
         for (uint32_t i = 0; i < c->last_n_req; ++i) {
@@ -767,6 +783,7 @@ vm3dgs_status vm3dgs_reset(vm3dgs* c) {
         return fail(c, h);
     }
     c->frame = 0;
+    c->lod_tau = c->opt.lod_radius_px; c->lod_step = 0.125f; c->lod_dir = 0;
     c->pf_n_hist = 0;
     c->pf_pending = false;
     c->last_n_copy = c->last_n_missing = c->last_n_req = c->last_n_rl = 0;

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(PT_NT) void k_pagetable_l1(const uint64_t* __restri
     const int t = threadIdx.x;
     const int n = (int)a.counters[vm::C_NREQ];
     if (n > PT_MAXK || a.S > PT_MAXK) {   // host checks these bounds; never reached
-        if (t == 0) a.counters[vm::C_NCOUNTERS - 1] = 1;
+        if (t == 0) a.counters[vm::C_PTERR] = 1;
         return;
     }
     if (t < 4) s_cnt[t] = 0;
@@ -187,6 +187,7 @@ __global__ __launch_bounds__(PT_NT) void k_pagetable_l1(const uint64_t* __restri
         a.counters[vm::C_NCOPY] = n_take;
         a.counters[vm::C_NMISSING] = n_miss - n_take;
         a.counters[vm::C_NRL] = n_rl;
+        a.counters[vm::C_REQSLOTS] = n_rl;   // one level: one physical page per render entry
         a.counters[vm::C_NRENDER] = n_rl * (uint32_t)a.P;
         a.counters[vm::C_POOLUSED] = s_cnt[1];
     }
@@ -371,10 +372,11 @@ __global__ __launch_bounds__(PT_NT) void k_ptl_render_list(const int8_t* __restr
                                                            const int32_t* __restrict__ v2p, int n_pg, int L, int P,
                                                            int S, const int8_t* __restrict__ slot_level,
                                                            const int32_t* __restrict__ sub_vpage,
+                                                           const uint8_t* __restrict__ slot_req,
                                                            RenderEntry* __restrict__ rl, uint32_t* __restrict__ counters) {
     __shared__ uint32_t scan_sh[PT_NT / WAVE];
-    __shared__ uint32_t s_used;
-    if (threadIdx.x == 0) s_used = 0;
+    __shared__ uint32_t s_used, s_reqd;
+    if (threadIdx.x == 0) { s_used = 0; s_reqd = 0; }
     uint32_t n_rl = 0, base = 0;
     for (int b = 0; b < n_pg; b += PT_NT) {
         const int p = b + threadIdx.x;
@@ -401,8 +403,9 @@ __global__ __launch_bounds__(PT_NT) void k_ptl_render_list(const int8_t* __restr
         n_rl += tot;
         base += totc;
     }
-    uint32_t used = 0;
+    uint32_t used = 0, reqd = 0;
     for (int s = threadIdx.x; s < S; s += PT_NT) {
+        reqd += slot_req[s] ? 1u : 0u;
         const int l = slot_level[s];
         if (l < 0) continue;
         bool any = false;
@@ -410,11 +413,13 @@ __global__ __launch_bounds__(PT_NT) void k_ptl_render_list(const int8_t* __restr
         used += any ? 1u : 0u;
     }
     used = wave_sum(used);
+    reqd = wave_sum(reqd);
     __syncthreads();
-    if (__lane_id() == 0) atomicAdd(&s_used, used);
+    if (__lane_id() == 0) { atomicAdd(&s_used, used); atomicAdd(&s_reqd, reqd); }
     __syncthreads();
     if (threadIdx.x == 0) {
         counters[vm::C_NRL] = n_rl;
+        counters[vm::C_REQSLOTS] = s_reqd;
         counters[vm::C_NRENDER] = base;
         counters[vm::C_POOLUSED] = s_used;
         counters[vm::C_HITS] = counters[vm::C_NREQ] - counters[vm::C_MISSES];
@@ -423,6 +428,55 @@ __global__ __launch_bounds__(PT_NT) void k_ptl_render_list(const int8_t* __restr
 
 __global__ void k_ptl_count_misses(const uint32_t* __restrict__ total, uint32_t* __restrict__ counters) {
     counters[vm::C_MISSES] = *total;
+}
+
+
+// ------------------------------------------------------------------ page copies
+// Miss streaming by the GPU itself: each workgroup reads one 16 KB chunk of a
+// copy command from the pinned host store (over PCIe, with many loads in
+// flight) and writes it into the pool; the commands stay on the device.
+// Offsets and sizes are multiples of 4 bytes (Gaussian records are 236 or 124
+// bytes); 16-byte accesses where the command allows.  A command that would
+// leave the store or the pool is skipped and flagged.
+constexpr int CP_NT = 256;
+constexpr uint32_t CP_CHUNK = 16384;
+
+__global__ __launch_bounds__(CP_NT) void k_copy_pages(const vm::CopyCmd* __restrict__ cmds, uint32_t first,
+                                                      uint32_t chunks_per_cmd, const uint8_t* __restrict__ host,
+                                                      uint64_t host_bytes, uint8_t* __restrict__ pool,
+                                                      uint64_t pool_bytes, unsigned long long* __restrict__ bytes_done,
+                                                      uint32_t* __restrict__ err) {
+    const uint32_t c = first + blockIdx.x / chunks_per_cmd;
+    const uint32_t ch = blockIdx.x % chunks_per_cmd;
+    const vm::CopyCmd cmd = cmds[c];
+    const uint64_t h0 = (uint64_t)cmd.host_off, p0 = (uint64_t)cmd.pool_off, nb = (uint64_t)cmd.bytes;
+    if (cmd.host_off < 0 || cmd.pool_off < 0 || cmd.bytes < 0 || h0 + nb > host_bytes || p0 + nb > pool_bytes) {
+        if (threadIdx.x == 0 && ch == 0) atomicOr(err, 1u);
+        return;
+    }
+    const uint64_t lo = (uint64_t)ch * CP_CHUNK;
+    if (lo >= nb) return;
+    const uint64_t hi = lo + CP_CHUNK < nb ? lo + CP_CHUNK : nb;
+    if (threadIdx.x == 0) atomicAdd(bytes_done, (unsigned long long)(hi - lo));
+    if (((h0 | p0 | lo | hi) & 15) == 0) {
+        const uint4* src = (const uint4*)(host + h0 + lo);
+        uint4* dst = (uint4*)(pool + p0 + lo);
+        const uint32_t n = (uint32_t)((hi - lo) / 16);
+        for (uint32_t i = threadIdx.x; i < n; i += CP_NT * 4) {
+            uint4 v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (i + k * CP_NT < n) v[k] = src[i + k * CP_NT];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (i + k * CP_NT < n) dst[i + k * CP_NT] = v[k];
+        }
+    } else {
+        const uint32_t* src = (const uint32_t*)(host + h0 + lo);
+        uint32_t* dst = (uint32_t*)(pool + p0 + lo);
+        const uint32_t n = (uint32_t)((hi - lo) / 4);
+        for (uint32_t i = threadIdx.x; i < n; i += CP_NT) dst[i] = src[i];
+    }
 }
 
 }  // namespace vmk
@@ -504,7 +558,20 @@ void launch_pagetable_lod(hipStream_t st, const PtArgs& a, SortWork& sw, const L
     hipLaunchKernelGGL(k_ptl_walk, dim3(1), dim3(64), 0, st, pw);
     hipLaunchKernelGGL(k_ptl_render_list, dim3(1), dim3(PT_NT), 0, st, (const int8_t*)a.page_level,
                        (const int32_t*)a.v2p, n_pg, L, a.P, S, (const int8_t*)a.slot_level,
-                       (const int32_t*)a.sub_vpage, a.rl, a.counters);
+                       (const int32_t*)a.sub_vpage, (const uint8_t*)a.slot_req, a.rl, a.counters);
+}
+
+}  // namespace vm
+
+namespace vm {
+
+void launch_copy_pages(hipStream_t st, const CopyCmd* cmds, uint32_t first, uint32_t count, uint64_t max_cmd_bytes,
+                       const uint8_t* host, uint64_t host_bytes, uint8_t* pool, uint64_t pool_bytes,
+                       unsigned long long* bytes_done, uint32_t* err) {
+    if (count == 0) return;
+    const uint32_t per = (uint32_t)((max_cmd_bytes + vmk::CP_CHUNK - 1) / vmk::CP_CHUNK);
+    hipLaunchKernelGGL(vmk::k_copy_pages, dim3(count * per), dim3(vmk::CP_NT), 0, st, cmds, first, per, host,
+                       host_bytes, pool, pool_bytes, bytes_done, err);
 }
 
 }  // namespace vm

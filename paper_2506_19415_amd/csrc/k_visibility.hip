@@ -241,11 +241,13 @@ __global__ void k_requests(const uint32_t* __restrict__ rd, const uint32_t* __re
     // wave-aggregated compaction; order is restored by the sort of the keys
     const uint64_t m = __ballot(req);
     const uint64_t md = __ballot(direct);
+    const uint64_t mc = __ballot(req && p < n_pg && page_level[p] > 0);
     uint32_t base = 0;
     if (__lane_id() == 0 && m) {
         base = atomicAdd(&counters[vm::C_NREQ], (uint32_t)__popcll(m));
         atomicAdd(&counters[vm::C_DIRECT], (uint32_t)__popcll(md));
         atomicAdd(&counters[vm::C_LINKED], (uint32_t)(__popcll(m) - __popcll(md)));
+        if (mc) atomicAdd(&counters[vm::C_NCOARSE], (uint32_t)__popcll(mc));
     }
     base = __shfl(base, 0, WAVE);
     if (req) keys[base + __popcll(m & lanemask_lt())] = key;

@@ -93,7 +93,11 @@ struct CamK {
 // Counters written by the page-table kernels and read back once per frame.
 enum Ctr {
     C_NREQ = 0, C_DIRECT, C_LINKED, C_HITS, C_MISSES, C_EVICT, C_NCOPY, C_NMISSING, C_NRL, C_NRENDER,
-    C_CAND, C_POOLUSED, C_NCAND1, C_NCAND2, C_NPFREQ, C_NPF, C_NCOUNTERS = 16
+    C_CAND, C_POOLUSED, C_NCAND1, C_NCAND2, C_NPFREQ, C_NPF,
+    C_REQSLOTS,   // physical pages required after the demand stages
+    C_NCOARSE,    // requests at a level above 0
+    C_PTERR,      // page-table bound check (never set when the host checks hold)
+    C_NCOUNTERS = 24
 };
 
 struct RenderEntry {   // one resident requested (sub-)page in render order
@@ -212,5 +216,11 @@ void launch_pf_features(hipStream_t st, const int32_t* v2p, int n_pg, int L, int
 void launch_prefetch(hipStream_t st, const PfArgs& a, SortWork& sw);
 const MlpDev* mlp_dev_of(const vm3dgs_mlp* net);
 int mlp_max_batch_of(const vm3dgs_mlp* net);
+
+// copies of the misses by the GPU from the pinned host store (one command per
+// 16 KB chunk and workgroup); bytes_done accumulates the bytes copied
+void launch_copy_pages(hipStream_t st, const CopyCmd* cmds, uint32_t first, uint32_t count, uint64_t max_cmd_bytes,
+                       const uint8_t* host, uint64_t host_bytes, uint8_t* pool, uint64_t pool_bytes,
+                       unsigned long long* bytes_done, uint32_t* err);
 
 }  // namespace vm

@@ -76,6 +76,19 @@ def train(net, X, Y, steps, batch=256, lr=1e-3, seed=0, log_every=0):
     return losses
 
 
+def calibrate_threshold(net, X, Y, factor=2.0, batch=256):
+    """The logit threshold at which the network proposes about `factor` times
+    as many clusters as the labels hold on the rows X (positives are rare,
+    so the plain 0.5 probability proposes almost nothing)."""
+    import torch
+    zs = []
+    for i in range(0, X.shape[0], batch):
+        zs.append(net.forward(torch.tensor(X[i:i + batch], device="cuda")).cpu().numpy())
+    z = np.concatenate(zs).ravel()
+    q = min(max(1.0 - factor * float(Y.mean()), 0.0), 1.0)
+    return float(np.quantile(z, q))
+
+
 def evaluate(r, net, paths, n_clusters, hist_bins, threshold, budget, center, extent, skip=2):
     """Demand misses, stall and proposal quality along the paths, with the
     network (net) or without it (net=None).  Frames before `skip` on each

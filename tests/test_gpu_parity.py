@@ -287,3 +287,43 @@ def test_lod_city(city, L, tau, S, budget, fmt):
     assert np.all(seen > 0), seen          # every level was requested
     assert evictions > 0
     r.close()
+
+
+def test_large_one_level_table(clusters):
+    """One level with more pages than the single-workgroup page table holds
+    (16,384 pages of 2): the multi-kernel page table, bit-exact as well."""
+    sc, _ = clusters
+    osc = oracle.OracleScene(sc, 2, 1, 0.5, 2.0)
+    cams = synth.orbit()
+    r = _renderer(sc, 2, 6000, (320, 240), (80, 60), 0.5)
+    ovm = oracle.OracleVM(osc, 6000, (320, 240), (80, 60))
+    for k in range(4):
+        print(f"large table frame {k}", flush=True)
+        _, out = r.frame([cams[k]])
+        ovm.frame([cams[k]])
+        compare_frame(r, ovm, out, 1, tag=f"large table {k}")
+    r.close()
+
+
+def test_adaptive_lod_thresholds(city):
+    """Thresholds that follow memory use: the radius each frame used, and
+    every intermediate, equal the oracle's along a path that first overloads
+    the pool and then relieves it."""
+    import paper_2506_19415_amd as pkg
+    sc = synth.scene_city(0, n=400_000, size=300.0, block=60.0, street=12.0)
+    cams = synth.path_city(sc, n_frames=60, width=320, height=180)
+    osc = oracle.OracleScene(sc, 512, 3, 2.0, 2.0)
+    r = _renderer(sc, 512, 60, (320, 180), (80, 45), 2.0, lod_levels=3, lod_radius_px=64.0)
+    r.set_flags(pkg.VM3DGS_FLAG_LINKS | pkg.VM3DGS_FLAG_ADAPTIVE_LOD)
+    ovm = oracle.OracleVM(osc, 60, (320, 180), (80, 45), lod_radius_px=64.0)
+    ovm.set_adaptive_lod(True)
+    taus = []
+    for k in range(0, 60, 2):
+        print(f"adaptive lod frame {k}", flush=True)
+        _, out = r.frame([cams[k]])
+        ovm.frame([cams[k]])
+        assert out.stats.lod_radius_px == float(ovm.get("lod")[0]), k
+        taus.append(out.stats.lod_radius_px)
+        compare_frame(r, ovm, out, 1, tag=f"adaptive lod {k}")
+    assert max(taus) > 128.0
+    r.close()

@@ -251,3 +251,38 @@ def test_support_box_contains_the_accepted_region():
             syy = a / det
             assert hy >= math.sqrt(11.1 * syy) and hy <= math.sqrt(11.2 * syy) * 1.05 + 1.0 + 1e-3, g
     assert n_tight > 0.9 * vis.size
+
+
+def test_fp64_render_of_the_render_set(cluster_frame):
+    """The double-precision reference splat of the last frame's render set
+    agrees with the float oracle image to float rounding, except at the few
+    pixels where a threshold decision (alpha against 1/255, T against 1e-4)
+    falls the other way in double."""
+    vm = cluster_frame
+    cams = synth.orbit()
+    img = vm.render_fp64(vm.scene, [cams[1]])[0]
+    ref = vm.image()[0].astype(np.float64)
+    d = np.abs(img - ref)
+    assert np.quantile(d, 0.999) < 2e-5 and (d > 1e-4).mean() < 1e-3 and d.max() < 0.05, (d.max(), d.mean())
+
+
+def test_fp64_render_lone_gaussian_closed_form():
+    W, H = 96, 80
+    cam = identity_cam(W, H)
+    sigma, z, o = 0.05, 3.0, 0.8
+    vm = render(one_gaussian_scene([0.0, 0.0, z], [sigma] * 3, opacity=o), cam, W, H)
+    img = vm.render_fp64(vm.scene, [cam])[0]
+    f32 = lambda a: np.float64(np.float32(a))        # the scene and camera hold float32 values
+    sh = np.array([f32(0.6), f32(0.2), f32(-0.4)])
+    rgb = np.maximum(oracle.sh_basis(0, 0.0, 0.0, 1.0) * sh + 0.5, 0.0)
+    sigma, z, o = f32(sigma), f32(z), f32(o)
+    var = (f32(cam.fx) * sigma / z) ** 2 + 0.3
+    u, v = cam.cx - 0.5, cam.cy - 0.5
+    jj, ii = np.mgrid[0:H, 0:W]
+    alpha = np.minimum(0.99, o * np.exp(-0.5 * ((ii - u) ** 2 + (jj - v) ** 2) / var))
+    r = math.ceil(3.0 * math.sqrt(var))
+    tx0, tx1 = max(0, math.floor((u - r) / 16)), min((W + 15) // 16, math.floor((u + r + 15) / 16))
+    ty0, ty1 = max(0, math.floor((v - r) / 16)), min((H + 15) // 16, math.floor((v + r + 15) / 16))
+    inside = (ii // 16 >= tx0) & (ii // 16 < tx1) & (jj // 16 >= ty0) & (jj // 16 < ty1)
+    exp_img = np.where((inside & (alpha >= 1.0 / 255.0))[..., None], alpha[..., None] * rgb, 0.0)
+    assert np.abs(img - exp_img).max() < 1e-13
