@@ -47,7 +47,7 @@ struct vm3dgs {
     CamK* d_cams = nullptr; CamK* h_cams = nullptr;
     // visibility
     uint8_t* d_cand = nullptr; float4* d_rays = nullptr; unsigned long long* d_idbuf = nullptr;
-    int4* d_crect = nullptr; uint32_t* d_carea = nullptr; uint32_t* d_coffs = nullptr; uint32_t* d_vtemp = nullptr;
+    int4* d_crect = nullptr; uint32_t* d_carea = nullptr; uint32_t* d_coffs = nullptr;
     uint32_t* d_rd = nullptr; uint32_t* d_rl = nullptr; int8_t* d_plevel = nullptr; uint64_t* d_keys = nullptr;
     uint32_t* d_ctr = nullptr; uint32_t* h_ctr = nullptr;
     // page table
@@ -72,7 +72,6 @@ struct vm3dgs {
     uint64_t cap_pairs = 0;
     uint32_t* d_pkey[2] = {nullptr, nullptr}; uint32_t* d_pval[2] = {nullptr, nullptr};
     uint2* d_ranges = nullptr; uint32_t* d_tile_order = nullptr;
-    uint32_t* d_temp = nullptr; size_t temp_words = 0;
     // zero block: counters | look-back error flag | tickets | histograms (cleared per frame)
     uint32_t* d_zero = nullptr;
     uint64_t* d_status = nullptr; size_t status_words = 0;
@@ -167,7 +166,7 @@ void free_all(vm3dgs* c) {
     dfree(c->d_cp_err); dfree(c->d_pf_bytes);
     dfree(c->d_cams); hfree(c->h_cams);
     dfree(c->d_cand); dfree(c->d_rays); dfree(c->d_idbuf);
-    dfree(c->d_crect); dfree(c->d_carea); dfree(c->d_coffs); dfree(c->d_vtemp); dfree(c->d_rd); dfree(c->d_rl); dfree(c->d_plevel);
+    dfree(c->d_crect); dfree(c->d_carea); dfree(c->d_coffs); dfree(c->d_rd); dfree(c->d_rl); dfree(c->d_plevel);
     dfree(c->d_keys); c->d_ctr = nullptr; hfree(c->h_ctr);
     dfree(c->d_slot_level); dfree(c->d_last_used); dfree(c->d_sub_vpage); dfree(c->d_sub_lu); dfree(c->d_v2p);
     dfree(c->d_req_sub); dfree(c->d_slot_req); dfree(c->d_miss);
@@ -179,7 +178,7 @@ void free_all(vm3dgs* c) {
     dfree(c->d_rlist); dfree(c->d_rlist_full);
     dfree(c->d_xy); dfree(c->d_conic); dfree(c->d_rgb); dfree(c->d_depth); dfree(c->d_rect); dfree(c->d_tiles);
     for (int i = 0; i < 2; ++i) { dfree(c->d_dkey[i]); dfree(c->d_dval[i]); dfree(c->d_pkey[i]); dfree(c->d_pval[i]); }
-    dfree(c->d_offs); dfree(c->d_ranges); dfree(c->d_tile_order); dfree(c->d_temp); dfree(c->d_total); hfree(c->h_total);
+    dfree(c->d_offs); dfree(c->d_ranges); dfree(c->d_tile_order); dfree(c->d_total); hfree(c->h_total);
     dfree(c->d_zero); dfree(c->d_status); dfree(c->d_bstats); hfree(c->h_bstats);
     if (c->ev_copy) hipEventDestroy(c->ev_copy);
     if (c->ev_sync) hipEventDestroy(c->ev_sync);
@@ -224,15 +223,6 @@ void begin_work(vm3dgs* c) {
     c->sw.reset();
 }
 
-void ensure_temp(vm3dgs* c) {
-    const size_t need = std::max({radix_temp_words(c->cap_render), radix_temp_words(c->cap_pairs),
-                                  scan_temp_words(c->cap_render), scan_temp_words(c->cap_pairs), (size_t)4096});
-    if (need > c->temp_words) {
-        dfree(c->d_temp);
-        dalloc(&c->d_temp, need);
-        c->temp_words = need;
-    }
-}
 
 void ensure_pairs(vm3dgs* c, uint64_t n) {
     if (n <= c->cap_pairs) return;
@@ -245,7 +235,6 @@ void ensure_pairs(vm3dgs* c, uint64_t n) {
     }
 
     c->cap_pairs = cap;
-    ensure_temp(c);
     ensure_status(c);
 }
 
@@ -500,7 +489,6 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         const int64_t npx = (int64_t)o.idbuf_w * o.idbuf_h;
         dalloc(&c->d_cand, (size_t)V * n_pg); dalloc(&c->d_rays, (size_t)V * npx); dalloc(&c->d_idbuf, (size_t)V * npx);
         dalloc(&c->d_crect, (size_t)V * nc); dalloc(&c->d_carea, (size_t)V * nc); dalloc(&c->d_coffs, (size_t)V * nc + 1);
-        dalloc(&c->d_vtemp, scan_temp_words((uint64_t)V * nc));
         dalloc(&c->d_rd, n_pg); dalloc(&c->d_rl, n_pg); dalloc(&c->d_plevel, n_pg);
         dalloc(&c->d_keys, (size_t)2 * n_pg); halloc(&c->h_keys, n_pg);
         dalloc(&c->d_zero, ZB_WORDS);
@@ -545,8 +533,7 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         dalloc(&c->d_total, 4); halloc(&c->h_total, 8);  // [0] pairs, [1] look-back error, [2..3] bytes, [4] copy error
         c->cap_pairs = 0;
         ensure_pairs(c, o.pair_capacity ? o.pair_capacity : std::max<uint64_t>(R * 4, 1u << 22));
-        ensure_temp(c);
-        ensure_status(c);
+            ensure_status(c);
         if (o.flags & VM3DGS_FLAG_FULL_SCENE_COPY) {
             std::vector<RenderEntry> full((size_t)n_pg);
             for (int p = 0; p < n_pg; ++p)
@@ -598,7 +585,7 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         va.guard = c->opt.idbuf_guard_px;
         va.cand = c->d_cand; va.rays = c->d_rays; va.idbuf = c->d_idbuf; va.req_direct = c->d_rd; va.req_link = c->d_rl;
         va.page_level = c->d_plevel; va.req_keys = c->d_keys; va.counters = c->d_ctr;
-        va.cell_rects = c->d_crect; va.cell_area = c->d_carea; va.cell_offs = c->d_coffs; va.scan_temp = c->d_vtemp;
+        va.cell_rects = c->d_crect; va.cell_area = c->d_carea; va.cell_offs = c->d_coffs;
         va.sw = &c->sw;
         launch_visibility(c->sr, va);
         HIPCHK(hipGetLastError());

@@ -38,16 +38,6 @@ std::string build_paged_scene(const vm3dgs_scene& sc, int page_size, int lod_lev
 void encode_store(const PagedScene& ps, uint8_t* dst);
 
 // ----------------------------------------------------------- device sort/scan
-size_t scan_temp_words(uint64_t n);
-size_t radix_temp_words(uint64_t n);
-void scan_excl(hipStream_t st, const uint32_t* in, uint64_t n, uint32_t* out, uint32_t* total, uint32_t* temp);
-void scan_excl_gather(hipStream_t st, const uint32_t* a, const uint32_t* idx, uint64_t n, uint32_t* out,
-                      uint32_t* total, uint32_t* temp);
-int radix_sort_u32(hipStream_t st, uint32_t* keys[2], uint32_t* vals[2], uint32_t n, int begin_bit, int end_bit,
-                   uint32_t* temp);
-int radix_sort_u64(hipStream_t st, uint64_t* keys[2], uint32_t* vals[2], uint32_t n, int begin_bit, int end_bit,
-                   uint32_t* temp);
-
 // Workspace of the single-pass sorts and scans of one frame.  reset() is
 // called when the frame's zero-fill of `zero_base` (counters, histograms,
 // tickets) has been enqueued; every launch then takes the next histogram
@@ -122,7 +112,6 @@ struct VisArgs {
     uint32_t* req_direct; uint32_t* req_link; int8_t* page_level;
     uint64_t* req_keys; uint32_t* counters;
     int4* cell_rects; uint32_t* cell_area; uint32_t* cell_offs;  // [views*nc], [views*nc], [views*nc + 1]
-    uint32_t* scan_temp;
     SortWork* sw;
 };
 void launch_visibility(hipStream_t st, const VisArgs& a);
