@@ -332,6 +332,7 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
     __shared__ float4 s_a[BL_NT];    // u, v, support half height, opacity
     __shared__ float4 s_b[BL_NT];    // conic ca, cb, cc
     __shared__ float4 s_c[BL_NT];    // colour
+    __shared__ uint16_t s_idx[BL_NT / WAVE][BL_NT];
     __shared__ uint32_t s_st[2][BL_NT / WAVE];
     const uint32_t tile = order[blockIdx.x];
     const uint32_t per_view = (uint32_t)(TX * TY);
@@ -363,11 +364,24 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
         __syncthreads();
         const int cnt = (int)min((uint32_t)BL_NT, rg.y - base);
         if (__ballot(live) == 0) continue;
-        for (int k = 0; k < cnt; ++k) {
+        // this wave's list: the batch entries whose support rows meet its strip
+        // (the others are rejected by every pixel of the strip), in batch order
+        int n_w = 0;
+#pragma unroll
+        for (int r = 0; r < BL_NT / WAVE; ++r) {
+            const int k = r * WAVE + (int)__lane_id();
+            bool keep = false;
+            if (k < cnt) {
+                const float4 a = s_a[k];
+                keep = fabsf(a.y - strip_c) <= a.z + 1.5f;
+            }
+            const uint64_t b = __ballot(keep);
+            if (keep) s_idx[threadIdx.x / WAVE][n_w + (int)__popcll(b & lanemask_lt())] = (uint16_t)k;
+            n_w += (int)__popcll(b);
+        }
+        for (int i = 0; i < n_w; ++i) {
+            const int k = __builtin_amdgcn_readfirstlane((int)s_idx[threadIdx.x / WAVE][i]);
             const float4 a = s_a[k];
-            const float ay = uniform_f(a.y), ah = uniform_f(a.z);
-            // support rows miss the strip: every pixel of it rejects the Gaussian
-            if (!(fabsf(ay - strip_c) <= ah + 1.5f)) continue;
             const float4 co = s_b[k];
             const float dx = a.x - fpx, dy = a.y - fpy;
             const float q = fmaf(co.x * dx, dx, (co.z * dy) * dy);
