@@ -71,6 +71,7 @@ struct vm3dgs {
     uint32_t* d_offs = nullptr;
     uint64_t cap_pairs = 0;
     uint32_t* d_pkey[2] = {nullptr, nullptr}; uint32_t* d_pval[2] = {nullptr, nullptr};
+    uint32_t* d_emit_start = nullptr;
     uint2* d_ranges = nullptr; uint32_t* d_tile_order = nullptr;
     // zero block: counters | look-back error flag | tickets | histograms (cleared per frame)
     uint32_t* d_zero = nullptr;
@@ -178,6 +179,7 @@ void free_all(vm3dgs* c) {
     dfree(c->d_rlist); dfree(c->d_rlist_full);
     dfree(c->d_xy); dfree(c->d_conic); dfree(c->d_rgb); dfree(c->d_depth); dfree(c->d_rect); dfree(c->d_tiles);
     for (int i = 0; i < 2; ++i) { dfree(c->d_dkey[i]); dfree(c->d_dval[i]); dfree(c->d_pkey[i]); dfree(c->d_pval[i]); }
+    dfree(c->d_emit_start);
     dfree(c->d_offs); dfree(c->d_ranges); dfree(c->d_tile_order); dfree(c->d_total); hfree(c->h_total);
     dfree(c->d_zero); dfree(c->d_status); dfree(c->d_bstats); hfree(c->h_bstats);
     if (c->ev_copy) hipEventDestroy(c->ev_copy);
@@ -233,6 +235,8 @@ void ensure_pairs(vm3dgs* c, uint64_t n) {
         dalloc(&c->d_pkey[i], cap);
         dalloc(&c->d_pval[i], cap);
     }
+    dfree(c->d_emit_start);
+    dalloc(&c->d_emit_start, cap / EMIT_SPAN + 2);
 
     c->cap_pairs = cap;
     ensure_status(c);
@@ -263,8 +267,9 @@ void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool,
     if (c->h_total[1]) throw HipError{hipErrorUnknown, "single-pass scan look-back did not complete", __LINE__};
     const uint32_t n_pairs = *c->h_total;
     ensure_pairs(c, n_pairs);
-    launch_emit(c->sr, c->d_dval[db], c->d_offs, c->d_rect, (uint32_t)n_total, n_render, c->TX, c->TY, c->d_pkey[0],
-                c->d_pval[0], (uint32_t)c->cap_pairs);
+    launch_emit(c->sr, c->d_dval[db], c->d_offs, c->d_tiles, c->d_rect, c->d_emit_start, (uint32_t)n_total, n_pairs,
+                n_render, c->TX, c->TY, c->d_pkey[0], c->d_pval[0],
+                (uint32_t)std::min<uint64_t>(c->cap_pairs, 0xffffffffu));
     const uint32_t n_tiles = (uint32_t)(c->TX * c->TY) * n_views;
     const int pb = onesweep_u32(c->sr, c->sw, c->d_pkey, c->d_pval, n_pairs, 0, std::max(1, bits_for(n_tiles)));
     launch_ranges(c->sr, c->d_pkey[pb], n_pairs, c->d_ranges, n_tiles);

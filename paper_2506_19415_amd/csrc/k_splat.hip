@@ -6,9 +6,9 @@
 //                conic, 3-sigma radius, 16x16 tile rectangle, degree-3 SH
 //                colour, view depth.  Padding (opacity 0) and Gaussians in
 //                front of the near plane are culled.
-//  k_emit        pairs in depth order: a wave spreads the tile rectangles of
-//                its 64 Gaussians over its lanes (prefix sums of the counts)
-//                and writes (tile, Gaussian) pairs coalesced.
+//  k_emit        pairs in depth order, balanced over pairs: each workgroup
+//                writes 1024 consecutive pairs, finding their Gaussians by
+//                binary search over the runs of pairs in LDS.
 //  k_ranges      [start, end) of every tile in the tile-sorted pairs.
 //  k_tile_order  blend order of the tiles: by decreasing power-of-two class
 //                of their pair counts, so that the longest tiles start first
@@ -216,60 +216,68 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
     a.dval[f] = (uint32_t)f;
 }
 
-// pairs of 64 depth-ordered Gaussians per wave, balanced over the lanes
+// Pair emission balanced over pairs: workgroup b writes pairs
+// [b EMIT_SPAN, (b + 1) EMIT_SPAN).  k_emit_starts records, for every block
+// boundary, the depth-ordered Gaussian whose run of pairs holds it; k_emit
+// loads the runs from there (each Gaussian with a run has at least one pair,
+// so at most EMIT_SPAN + 1 runs meet a block) and each thread finds the owner
+// of its pairs by binary search in LDS.  A pair's tile comes from the run's
+// first tile key and width (a float reciprocal corrected to the exact
+// quotient).
+using vm::EMIT_SPAN;
+
+__global__ void k_emit_starts(const uint32_t* __restrict__ offs, const uint32_t* __restrict__ order,
+                              const uint32_t* __restrict__ tiles, uint32_t n_total, uint32_t* __restrict__ start) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_total) return;
+    const uint32_t off = offs[i], cnt = tiles[order[i]];
+    if (cnt == 0) return;
+    for (uint32_t b = (off + EMIT_SPAN - 1) / EMIT_SPAN; b * EMIT_SPAN < off + cnt; ++b) start[b] = i;
+}
+
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order, const uint32_t* __restrict__ offs,
-                                              const uint2* __restrict__ rect, uint32_t n_total, uint32_t n_render,
-                                              int TX, int TY, uint32_t* __restrict__ pkey,
-                                              uint32_t* __restrict__ pval, uint32_t cap) {
-    __shared__ uint32_t s_off[4][WAVE];
-    __shared__ uint32_t s_f[4][WAVE];
-    __shared__ uint2 s_rect[4][WAVE];
-    const int w = threadIdx.x / WAVE, lane = __lane_id();
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    uint32_t f = 0, off = 0, cnt = 0;
-    uint2 r = make_uint2(0u, 0u);
-    if (i < n_total) {
-        f = order[i];
-        off = offs[i];
-        r = rect[f];
-        const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu, y1 = r.y >> 16;
-        cnt = (x1 - x0) * (y1 - y0);
-    }
-    s_off[w][lane] = off;
-    s_f[w][lane] = f;
-    s_rect[w][lane] = r;
-    // pairs of this wave: [first, first + total)
-    const uint32_t first = __shfl(off, 0, WAVE);
-    const uint32_t last_end = off + cnt;
-    uint32_t total = 0;
-    {
-        // the last valid lane's end is the wave's end
-        uint32_t e = (i < n_total) ? last_end : 0u;
-#pragma unroll
-        for (int o = WAVE / 2; o > 0; o >>= 1) e = max(e, __shfl_xor(e, o, WAVE));
-        total = e > first ? e - first : 0u;
+                                              const uint2* __restrict__ rect, const uint32_t* __restrict__ start,
+                                              uint32_t n_total, uint32_t n_pairs, uint32_t n_render, int TX, int TY,
+                                              uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval,
+                                              uint32_t cap) {
+    __shared__ uint32_t s_off[EMIT_SPAN + 1];
+    __shared__ uint32_t s_f[EMIT_SPAN + 1];
+    __shared__ uint32_t s_kb[EMIT_SPAN + 1];
+    __shared__ uint32_t s_wd[EMIT_SPAN + 1];
+    __shared__ float s_inv[EMIT_SPAN + 1];
+    const uint32_t p0 = blockIdx.x * EMIT_SPAN;
+    const uint32_t p1 = min(p0 + EMIT_SPAN, n_pairs);
+    const uint32_t g0 = start[blockIdx.x];
+    const uint32_t n_runs = min(EMIT_SPAN + 1, n_total - g0);
+    for (uint32_t t = threadIdx.x; t < n_runs; t += 256) {
+        const uint32_t g = g0 + t;
+        const uint32_t f = order[g];
+        const uint2 r = rect[f];
+        const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu;
+        const uint32_t wd = x1 > x0 ? x1 - x0 : 1u;
+        s_off[t] = offs[g];
+        s_f[t] = f;
+        s_kb[t] = (f / n_render) * (uint32_t)(TX * TY) + y0 * (uint32_t)TX + x0;
+        s_wd[t] = wd;
+        s_inv[t] = 1.0f / (float)wd;
     }
     __syncthreads();
-    const uint32_t view_tiles = (uint32_t)(TX * TY);
-    for (uint32_t k = lane; k < total; k += WAVE) {
-        const uint32_t j = first + k;
-        // owning lane: last lane with s_off <= j (lanes with no tiles share offsets; take the last)
-        int lo = 0, hi = WAVE - 1;
+    for (uint32_t j = p0 + threadIdx.x; j < p1; j += 256) {
+        // owner: the last run starting at or before j (zero-length runs share
+        // the next start and come before it)
+        int lo = 0, hi = (int)n_runs - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (s_off[w][mid] <= j && (blockIdx.x * 256 + w * WAVE + mid) < n_total) lo = mid; else hi = mid - 1;
+            if (s_off[mid] <= j) lo = mid; else hi = mid - 1;
         }
-        // lanes with zero tiles share the next lane's offset: skip forward to one with tiles
-        const uint2 rr = s_rect[w][lo];
-        const uint32_t x0 = rr.x & 0xffffu, y0 = rr.x >> 16, x1 = rr.y & 0xffffu;
-        const uint32_t wd = x1 - x0;
-        const uint32_t q = j - s_off[w][lo];
-        const uint32_t tx = x0 + q % wd, ty = y0 + q / wd;
-        const uint32_t ff = s_f[w][lo];
-        const uint32_t view = ff / n_render;
+        const uint32_t q = j - s_off[lo];
+        const uint32_t wd = s_wd[lo];
+        uint32_t qy = (uint32_t)((float)q * s_inv[lo]);
+        if (qy * wd > q) --qy;
+        else if ((qy + 1) * wd <= q) ++qy;
         if (j < cap) {
-            pkey[j] = view * view_tiles + ty * (uint32_t)TX + tx;
-            pval[j] = ff;
+            pkey[j] = s_kb[lo] + qy * (uint32_t)TX + (q - qy * wd);
+            pval[j] = s_f[lo];
         }
     }
 }
@@ -443,11 +451,13 @@ void launch_preprocess(hipStream_t st, const SplatArgs& s) {
     hipLaunchKernelGGL(k_preprocess, dim3(nblk(a.n_total, 256)), dim3(256), 0, st, a);
 }
 
-void launch_emit(hipStream_t st, const uint32_t* order, const uint32_t* offsets, const uint2* rect,
-                 uint32_t n_total, uint32_t n_render, int TX, int TY, uint32_t* pkey, uint32_t* pval, uint32_t cap) {
-    if (n_total == 0) return;
-    hipLaunchKernelGGL(k_emit, dim3(nblk(n_total, 256)), dim3(256), 0, st, order, offsets, rect, n_total, n_render, TX,
-                       TY, pkey, pval, cap);
+void launch_emit(hipStream_t st, const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles,
+                 const uint2* rect, uint32_t* starts, uint32_t n_total, uint32_t n_pairs, uint32_t n_render, int TX,
+                 int TY, uint32_t* pkey, uint32_t* pval, uint32_t cap) {
+    if (n_total == 0 || n_pairs == 0) return;
+    hipLaunchKernelGGL(k_emit_starts, dim3(nblk(n_total, 256)), dim3(256), 0, st, offsets, order, tiles, n_total, starts);
+    hipLaunchKernelGGL(k_emit, dim3(nblk(n_pairs, EMIT_SPAN)), dim3(256), 0, st, order, offsets, rect,
+                       (const uint32_t*)starts, n_total, n_pairs, n_render, TX, TY, pkey, pval, cap);
 }
 
 void launch_ranges(hipStream_t st, const uint32_t* pkey, uint32_t n_pairs, uint2* ranges, uint32_t n_tiles) {

@@ -13,6 +13,7 @@ namespace vm {
 
 constexpr int REC = 59;   // floats per Gaussian record
 constexpr int SUBS = 64;  // sub-slots per physical page
+constexpr uint32_t EMIT_SPAN = 1024;  // pairs per workgroup of the pair emission
 
 // ----------------------------------------------------------- create time
 struct PagedScene {
@@ -151,8 +152,9 @@ struct SplatArgs {
     uint32_t* dkey; uint32_t* dval;
 };
 void launch_preprocess(hipStream_t st, const SplatArgs& a);
-void launch_emit(hipStream_t st, const uint32_t* order, const uint32_t* offsets, const uint2* rect, uint32_t n_total,
-                 uint32_t n_render, int TX, int TY, uint32_t* pkey, uint32_t* pval, uint32_t cap);
+void launch_emit(hipStream_t st, const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles,
+                 const uint2* rect, uint32_t* starts, uint32_t n_total, uint32_t n_pairs, uint32_t n_render, int TX,
+                 int TY, uint32_t* pkey, uint32_t* pval, uint32_t cap);
 void launch_ranges(hipStream_t st, const uint32_t* pkey, uint32_t n_pairs, uint2* ranges, uint32_t n_tiles);
 void launch_tile_order(hipStream_t st, const uint2* ranges, uint32_t n_tiles, uint32_t* order);
 void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* order, const uint32_t* pval, const float2* xy,
