@@ -320,15 +320,21 @@ __global__ void k_ranges(const uint32_t* __restrict__ key, uint32_t n, uint2* __
 // One 256-thread workgroup per 16x16 tile, one pixel per thread, one 16 x 4
 // strip per wave.  Gaussians are staged in LDS in batches of 256 (centre,
 // support half height, opacity; conic; colour).  A staged Gaussian is the
-// same for all 64 lanes, so its row test against the strip is taken on
-// scalar registers (a uniform branch); the lanes then evaluate it with the
-// pixel's "live" flag as a predicate, and the wave leaves the batch when no
-// lane is live.  STATS counts, per tile, the pixel-Gaussian evaluations and
+// same for all 64 lanes: each wave lists the staged Gaussians whose support
+// rows meet its strip, holds 64 list entries at a time in registers (one per
+// lane) and broadcasts them one by one through scalar registers; the lanes
+// evaluate each with the pixel's "live" flag as a predicate, and the wave
+// leaves the batch when no lane is live.  STATS counts, per tile, the pixel-Gaussian evaluations and
 // those that reached the alpha computation (the algorithmic work).
 constexpr int BL_NT = TILE * TILE;
 
 __device__ __forceinline__ float uniform_f(float x) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+
+// lane i's value of x, in a scalar register (i uniform)
+__device__ __forceinline__ float lane_f(float x, int i) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), i));
 }
 
 template <bool STATS>
@@ -387,33 +393,51 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
             if (keep) s_idx[threadIdx.x / WAVE][n_w + (int)__popcll(b & lanemask_lt())] = (uint16_t)k;
             n_w += (int)__popcll(b);
         }
-        for (int i = 0; i < n_w; ++i) {
-            const int k = __builtin_amdgcn_readfirstlane((int)s_idx[threadIdx.x / WAVE][i]);
-            const float4 a = s_a[k];
-            const float4 co = s_b[k];
-            const float dx = a.x - fpx, dy = a.y - fpy;
-            const float q = fmaf(co.x * dx, dx, (co.z * dy) * dy);
-            const float power = fmaf(-0.5f, q, -((co.y * dx) * dy));
-            if (STATS) n_eval += live ? 1u : 0u;
-            // exp(-5.55) < 1/255 and opacity <= 1: outside [-5.55, 0] a term
-            // fails the alpha test, so the rest runs only when some lane is in
-            const bool in = live && !(power > 0.0f || power < -5.55f);
-            if (__ballot(in) == 0) continue;
-            if (STATS) n_alpha += in ? 1u : 0u;
-            // every lane computes; the pixel's state changes only where "in"
-            const float alpha = fminf(0.99f, a.w * vm_exp_core(fminf(fmaxf(power, -6.0f), 0.0f)));
-            const bool take = in && alpha >= 1.0f / 255.0f;
-            const float Tn = T * (1.0f - alpha);
-            const bool stop = take && Tn < 0.0001f;
-            const bool add = take && !stop;
-            const float wgt = alpha * T;
-            const float4 c = s_c[k];
-            C0 = add ? fmaf(c.x, wgt, C0) : C0;
-            C1 = add ? fmaf(c.y, wgt, C1) : C1;
-            C2 = add ? fmaf(c.z, wgt, C2) : C2;
-            T = add ? Tn : T;
-            live = live && !stop;
-            if (__ballot(live) == 0) break;             // every pixel of the wave is done
+        __builtin_amdgcn_wave_barrier();
+        // the list in chunks of 64: lane l holds entry c0 + l in registers and
+        // the wave takes them one by one through v_readlane into scalar
+        // registers, so the loop over Gaussians touches no LDS
+        bool wave_live = true;
+        for (int c0 = 0; c0 < n_w && wave_live; c0 += WAVE) {
+            float4 ga = make_float4(0.f, 0.f, 0.f, 0.f), gb = ga, gc = ga;
+            if (c0 + (int)__lane_id() < n_w) {
+                const int k = (int)s_idx[threadIdx.x / WAVE][c0 + (int)__lane_id()];
+                ga = s_a[k];
+                gb = s_b[k];
+                gc = s_c[k];
+            }
+            const int m = min(WAVE, n_w - c0);
+            for (int i = 0; i < m && wave_live; ++i) {
+                const float gu = lane_f(ga.x, i), gv = lane_f(ga.y, i);
+                const float ca = lane_f(gb.x, i), cb = lane_f(gb.y, i), cc = lane_f(gb.z, i);
+                const float dx = gu - fpx, dy = gv - fpy;
+                const float q = fmaf(ca * dx, dx, (cc * dy) * dy);
+                const float power = fmaf(-0.5f, q, -((cb * dx) * dy));
+                if (STATS) n_eval += live ? 1u : 0u;
+                // exp(-5.55) < 1/255 and opacity <= 1: outside [-5.55, 0] a term
+                // fails the alpha test, so the rest runs only when some lane is in
+                const bool in = live && !(power > 0.0f || power < -5.55f);
+                if (__ballot(in) != 0) {
+                    if (STATS) n_alpha += in ? 1u : 0u;
+                    // every lane computes; the pixel's state changes only where "in"
+                    const float op = lane_f(ga.w, i);
+                    const float alpha = fminf(0.99f, op * vm_exp_core(fminf(fmaxf(power, -6.0f), 0.0f)));
+                    const bool take = in && alpha >= 1.0f / 255.0f;
+                    const float Tn = T * (1.0f - alpha);
+                    const bool stop = take && Tn < 0.0001f;
+                    const bool add = take && !stop;
+                    const float wgt = alpha * T;
+                    const float n0 = fmaf(lane_f(gc.x, i), wgt, C0);
+                    const float n1 = fmaf(lane_f(gc.y, i), wgt, C1);
+                    const float n2 = fmaf(lane_f(gc.z, i), wgt, C2);
+                    C0 = add ? n0 : C0;
+                    C1 = add ? n1 : C1;
+                    C2 = add ? n2 : C2;
+                    T = add ? Tn : T;
+                    live = live && !stop;
+                    wave_live = __ballot(live) != 0;    // the wave leaves when every pixel is done
+                }
+            }
         }
     }
     if (inside) {
