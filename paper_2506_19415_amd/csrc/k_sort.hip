@@ -3,19 +3,17 @@
 // the (tile, Gaussian) pair order, request order and page-table candidates.
 //
 // Radix: one histogram kernel reads the keys once for up to four 8-bit
-// passes; each pass is one kernel: a block takes its tile by ticket, ranks its
-// keys per wave with ballot digit matching, finds each digit's global start by
-// a decoupled look-back over earlier tiles, stages the tile in LDS in digit
-// order and writes runs coalesced.  The tile (keys per block) is a template
-// parameter of the kernels.
+// passes (LDS counters per key); each pass is one kernel: a block takes its
+// tile by ticket, ranks its keys per wave with ballot digit matching, finds
+// each digit's global start by a decoupled look-back over earlier tiles,
+// stages the tile in LDS in digit order and writes runs coalesced.  Threads
+// per block and keys per thread are template parameters of the kernels.
 #include "kcommon.h"
 #include "vm3dgs_impl.h"
 
 namespace vmk {
 
-constexpr int RS_NT = 256;
-constexpr int RS_WAVES = RS_NT / WAVE;
-constexpr int RS_MIN_TILE = RS_NT * 16;       // keys per block of the smallest tile in use
+constexpr int RS_MIN_TILE = 4096;       // keys per block (tile)
 
 constexpr int SC_NT = 256;
 constexpr int SC_ITEMS = 16;
@@ -118,53 +116,63 @@ __global__ __launch_bounds__(SC_NT) void k_scan_lb(In in, uint64_t n, uint32_t* 
     if (total && (uint64_t)(tile + 1) * SC_TILE >= n && threadIdx.x == SC_NT - 1) *total = run;
 }
 
-// digit histograms of several 8-bit passes in one read of the keys
-template <typename K, int ITEMS>
-__global__ __launch_bounds__(RS_NT) void k_os_hist(const K* __restrict__ keys, uint32_t n, int shift0, int passes,
-                                                  uint32_t* __restrict__ ghist) {
-    __shared__ uint32_t h[4][256];
-    for (int i = threadIdx.x; i < 4 * 256; i += RS_NT) (&h[0][0])[i] = 0;
+// digit histograms of several 8-bit passes in one read of the keys: every
+// key adds one to its digit's counter in LDS (four copies, wave w using copy
+// w mod 4, summed at the end, so that the waves of a block spread over them)
+template <typename K, int NT, int ITEMS>
+__global__ __launch_bounds__(NT) void k_os_hist(const K* __restrict__ keys, uint32_t n, int shift0, int passes,
+                                                uint32_t* __restrict__ ghist) {
+    constexpr int NC = 4;
+    constexpr int TILE_K = NT * ITEMS;
+    __shared__ uint32_t h[NC][4][256];
+    for (int i = threadIdx.x; i < NC * 4 * 256; i += NT) (&h[0][0][0])[i] = 0;
     __syncthreads();
-    const uint64_t lt = lanemask_lt();
-    const int w = threadIdx.x / WAVE;
-    constexpr int TILE_K = RS_NT * ITEMS, SPAN = TILE_K / RS_WAVES;
-    const uint32_t base = blockIdx.x * TILE_K + w * SPAN;
-    for (int r = 0; r < SPAN / WAVE; ++r) {
-        const uint32_t idx = base + r * WAVE + __lane_id();
-        const bool valid = idx < n;
-        const K k = valid ? keys[idx] : (K)0;
-        for (int p = 0; p < passes; ++p) {
-            const uint32_t d = digit_of(k, shift0 + 8 * p);
-            const uint64_t peers = match_digit8(d, valid);
-            if (valid && (peers & lt) == 0) atomicAdd(&h[p][d], (uint32_t)__popcll(peers));
-        }
+    const int w = (threadIdx.x / WAVE) % NC;
+    const uint32_t base = blockIdx.x * TILE_K + threadIdx.x;
+    K kr[ITEMS];
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t idx = base + r * NT;
+        kr[r] = idx < n ? keys[idx] : (K)0;
+    }
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        if (base + r * NT < n)
+            for (int p = 0; p < passes; ++p) atomicAdd(&h[w][p][digit_of(kr[r], shift0 + 8 * p)], 1u);
     }
     __syncthreads();
-    for (int p = 0; p < passes; ++p) {
-        const uint32_t c = h[p][threadIdx.x];
-        if (c) atomicAdd(&ghist[p * 256 + threadIdx.x], c);
+    for (int i = threadIdx.x; i < passes * 256; i += NT) {
+        const int p = i >> 8, d = i & 255;
+        uint32_t c = 0;
+#pragma unroll
+        for (int v = 0; v < NC; ++v) c += h[v][p][d];
+        if (c) atomicAdd(&ghist[i], c);
     }
 }
 
 // one stable 8-bit pass: local ranking (ballot digit matching per wave), look-back
-// over earlier tiles per digit, LDS staging in digit order, coalesced writes
+// over earlier tiles per digit, LDS staging in digit order, coalesced writes.
+// NT threads, ITEMS keys each; each wave ranks ITEMS consecutive rows of 64
+// keys and the first 256 threads do the per-digit work.
 // HV: values travel with the keys (without them no value pointer is touched)
-template <typename K, bool HV, int ITEMS>
-__global__ __launch_bounds__(RS_NT) void k_os_pass(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                  K* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t n,
-                                                  int shift, const uint32_t* __restrict__ ghist_pass,
-                                                  uint64_t* status, uint32_t* ticket, uint32_t epoch, uint32_t* err) {
+template <typename K, bool HV, int NT, int ITEMS>
+__global__ __launch_bounds__(NT) void k_os_pass(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                K* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t n,
+                                                int shift, const uint32_t* __restrict__ ghist_pass,
+                                                uint64_t* status, uint32_t* ticket, uint32_t epoch, uint32_t* err) {
     constexpr bool has_vals = HV;
-    constexpr int TILE_K = RS_NT * ITEMS, SPAN = TILE_K / RS_WAVES;
-    __shared__ uint32_t wc[RS_WAVES][256];
+    constexpr int NW = NT / WAVE;
+    constexpr int TILE_K = NT * ITEMS, SPAN = TILE_K / NW;
+    static_assert(NT >= 256, "the digit phase needs 256 threads");
+    __shared__ uint32_t wc[NW][256];
     __shared__ uint32_t dbase[256];
     __shared__ uint32_t gbase[256];
-    __shared__ uint32_t scan_sh[RS_NT / WAVE];
+    __shared__ uint32_t scan_sh[NW];
     __shared__ K skey[TILE_K];
     __shared__ uint32_t sval[TILE_K];
     __shared__ uint32_t s_tile;
     if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
-    for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&wc[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < NW * 256; i += NT) (&wc[0][0])[i] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
     const int w = threadIdx.x / WAVE;
@@ -180,6 +188,10 @@ __global__ __launch_bounds__(RS_NT) void k_os_pass(const K* __restrict__ kin, co
         const bool valid = idx < n;
         key[r] = valid ? kin[idx] : (K)0;
         val[r] = (valid && has_vals) ? vin[idx] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const bool valid = base + r * WAVE + __lane_id() < n;
         const uint32_t d = digit_of(key[r], shift);
         const uint64_t peers = match_digit8(d, valid);
         const uint32_t old = valid ? wc[w][d] : 0u;
@@ -189,19 +201,22 @@ __global__ __launch_bounds__(RS_NT) void k_os_pass(const K* __restrict__ kin, co
     __syncthreads();
     {
         const int d = threadIdx.x;
-        uint32_t c[RS_WAVES], tot = 0;
+        const bool dig = d < 256;
+        uint32_t c[NW], tot = 0;
 #pragma unroll
-        for (int i = 0; i < RS_WAVES; ++i) { c[i] = wc[i][d]; tot += c[i]; }
+        for (int i = 0; i < NW; ++i) { c[i] = dig ? wc[i][d] : 0u; tot += c[i]; }
         uint32_t all;
-        const uint32_t start = block_excl_scan<RS_NT>(tot, scan_sh, &all);
-        dbase[d] = start;
-        uint32_t run = start;
+        const uint32_t start = block_excl_scan<NT>(tot, scan_sh, &all);
+        if (dig) {
+            dbase[d] = start;
+            uint32_t run = start;
 #pragma unroll
-        for (int i = 0; i < RS_WAVES; ++i) { wc[i][d] = run; run += c[i]; }
+            for (int i = 0; i < NW; ++i) { wc[i][d] = run; run += c[i]; }
+        }
         // global start of digit d: all keys with smaller digits, then earlier tiles
         uint32_t gall;
-        const uint32_t dstart = block_excl_scan<RS_NT>(ghist_pass[d], scan_sh, &gall);
-        gbase[d] = dstart + lb_lookback(status, 256, (uint32_t)d, tile, epoch, tot, err);
+        const uint32_t dstart = block_excl_scan<NT>(dig ? ghist_pass[d] : 0u, scan_sh, &gall);
+        if (dig) gbase[d] = dstart + lb_lookback(status, 256, (uint32_t)d, tile, epoch, tot, err);
     }
     __syncthreads();
 #pragma unroll
@@ -216,9 +231,9 @@ __global__ __launch_bounds__(RS_NT) void k_os_pass(const K* __restrict__ kin, co
     }
     __syncthreads();
     const uint32_t cnt = tile0 < n ? min((uint32_t)TILE_K, n - tile0) : 0u;
-#pragma unroll 4
+#pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t j = i * RS_NT + threadIdx.x;
+        const uint32_t j = i * NT + threadIdx.x;
         if (j < cnt) {
             const K k = skey[j];
             const uint32_t d = digit_of(k, shift);
@@ -241,26 +256,26 @@ static uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) /
 // ---------------------------------------------------------------- onesweep
 size_t lb_status_words(uint64_t n_keys) { return (size_t)256 * div_up(n_keys, RS_MIN_TILE) + 256; }
 
-template <typename K, int ITEMS>
+template <typename K, int NT, int ITEMS>
 static int onesweep_items(hipStream_t st, SortWork& w, K* keys[2], uint32_t* vals[2], uint32_t n, int begin_bit,
                           int end_bit) {
-    const uint32_t nb = div_up(n, RS_NT * ITEMS);
+    const uint32_t nb = div_up(n, NT * ITEMS);
     const int passes = (end_bit - begin_bit + 7) / 8;
     const int has_vals = vals[0] != nullptr;
     int cur = 0;
     for (int p0 = 0; p0 < passes; p0 += 4) {
         const int np = std::min(4, passes - p0);
         uint32_t* gh = w.next_hist(np);
-        hipLaunchKernelGGL((k_os_hist<K, ITEMS>), dim3(nb), dim3(RS_NT), 0, st, (const K*)keys[cur], n,
+        hipLaunchKernelGGL((k_os_hist<K, NT, ITEMS>), dim3(nb), dim3(NT), 0, st, (const K*)keys[cur], n,
                            begin_bit + 8 * p0, np, gh);
         for (int p = 0; p < np; ++p) {
             const int shift = begin_bit + 8 * (p0 + p);
             if (has_vals)
-                hipLaunchKernelGGL((k_os_pass<K, true, ITEMS>), dim3(nb), dim3(RS_NT), 0, st, (const K*)keys[cur],
+                hipLaunchKernelGGL((k_os_pass<K, true, NT, ITEMS>), dim3(nb), dim3(NT), 0, st, (const K*)keys[cur],
                                    (const uint32_t*)vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, shift,
                                    (const uint32_t*)(gh + 256 * p), w.status, w.next_ticket(), w.next_epoch(), w.err);
             else
-                hipLaunchKernelGGL((k_os_pass<K, false, ITEMS>), dim3(nb), dim3(RS_NT), 0, st, (const K*)keys[cur],
+                hipLaunchKernelGGL((k_os_pass<K, false, NT, ITEMS>), dim3(nb), dim3(NT), 0, st, (const K*)keys[cur],
                                    (const uint32_t*)nullptr, keys[cur ^ 1], (uint32_t*)nullptr, n, shift,
                                    (const uint32_t*)(gh + 256 * p), w.status, w.next_ticket(), w.next_epoch(), w.err);
             cur ^= 1;
@@ -269,13 +284,16 @@ static int onesweep_items(hipStream_t st, SortWork& w, K* keys[2], uint32_t* val
     return cur;
 }
 
-// 4096 keys per block: measured on the terrain frames, smaller tiles (1024,
-// 2048) make every pass slower (longer look-back chains, more blocks)
+// 4096 keys per block (tile), 512 threads of 8 keys: measured on 1M 32-bit
+// depth keys (four passes) and 3M 13-bit tile keys (two passes), 512 threads
+// sort the depth keys 7 % faster than 256 and 1 % faster than 1024; smaller
+// tiles make every pass slower (more blocks, longer look-back chains)
+constexpr int SORT_NT = 512;
 template <typename K>
 static int onesweep_impl(hipStream_t st, SortWork& w, K* keys[2], uint32_t* vals[2], uint32_t n, int begin_bit,
                          int end_bit) {
     if (n == 0) return 0;
-    return onesweep_items<K, 16>(st, w, keys, vals, n, begin_bit, end_bit);
+    return onesweep_items<K, SORT_NT, RS_MIN_TILE / SORT_NT>(st, w, keys, vals, n, begin_bit, end_bit);
 }
 
 int onesweep_u32(hipStream_t st, SortWork& w, uint32_t* keys[2], uint32_t* vals[2], uint32_t n, int begin_bit,
