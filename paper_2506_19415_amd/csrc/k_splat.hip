@@ -395,8 +395,10 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
         }
         __builtin_amdgcn_wave_barrier();
         // the list in chunks of 64: lane l holds entry c0 + l in registers and
-        // the wave takes them one by one through v_readlane into scalar
-        // registers, so the loop over Gaussians touches no LDS
+        // the wave takes them through v_readlane into scalar registers, so the
+        // loop over Gaussians touches no LDS; the exponents of four entries
+        // are evaluated together, then the four are blended in order (the
+        // pixel state of one decides whether the next one is taken)
         bool wave_live = true;
         for (int c0 = 0; c0 < n_w && wave_live; c0 += WAVE) {
             float4 ga = make_float4(0.f, 0.f, 0.f, 0.f), gb = ga, gc = ga;
@@ -407,36 +409,47 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
                 gc = s_c[k];
             }
             const int m = min(WAVE, n_w - c0);
-            for (int i = 0; i < m && wave_live; ++i) {
-                const float gu = lane_f(ga.x, i), gv = lane_f(ga.y, i);
-                const float ca = lane_f(gb.x, i), cb = lane_f(gb.y, i), cc = lane_f(gb.z, i);
-                const float dx = gu - fpx, dy = gv - fpy;
-                const float q = fmaf(ca * dx, dx, (cc * dy) * dy);
-                const float power = fmaf(-0.5f, q, -((cb * dx) * dy));
-                if (STATS) n_eval += live ? 1u : 0u;
-                // exp(-5.55) < 1/255 and opacity <= 1: outside [-5.55, 0] a term
-                // fails the alpha test, so the rest runs only when some lane is in
-                const bool in = live && !(power > 0.0f || power < -5.55f);
-                if (__ballot(in) != 0) {
-                    if (STATS) n_alpha += in ? 1u : 0u;
-                    // every lane computes; the pixel's state changes only where "in"
-                    const float op = lane_f(ga.w, i);
-                    const float alpha = fminf(0.99f, op * vm_exp_core(fminf(fmaxf(power, -6.0f), 0.0f)));
-                    const bool take = in && alpha >= 1.0f / 255.0f;
-                    const float Tn = T * (1.0f - alpha);
-                    const bool stop = take && Tn < 0.0001f;
-                    const bool add = take && !stop;
-                    const float wgt = alpha * T;
-                    const float n0 = fmaf(lane_f(gc.x, i), wgt, C0);
-                    const float n1 = fmaf(lane_f(gc.y, i), wgt, C1);
-                    const float n2 = fmaf(lane_f(gc.z, i), wgt, C2);
-                    C0 = add ? n0 : C0;
-                    C1 = add ? n1 : C1;
-                    C2 = add ? n2 : C2;
-                    T = add ? Tn : T;
-                    live = live && !stop;
-                    wave_live = __ballot(live) != 0;    // the wave leaves when every pixel is done
+            for (int i = 0; i < m && wave_live; i += 4) {
+                float pw[4];
+                bool inr[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool two = i + u < m;
+                    const int ii = two ? i + u : i;
+                    const float gu = lane_f(ga.x, ii), gv = lane_f(ga.y, ii);
+                    const float ca = lane_f(gb.x, ii), cb = lane_f(gb.y, ii), cc = lane_f(gb.z, ii);
+                    const float dx = gu - fpx, dy = gv - fpy;
+                    const float q = fmaf(ca * dx, dx, (cc * dy) * dy);
+                    pw[u] = fmaf(-0.5f, q, -((cb * dx) * dy));
+                    inr[u] = !(pw[u] > 0.0f || pw[u] < -5.55f) && two;
                 }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool two = i + u < m;
+                    const int ii = two ? i + u : i;
+                    const float power = pw[u];
+                    if (STATS) n_eval += (live && two) ? 1u : 0u;
+                    const bool in = live && inr[u];
+                    if (__ballot(in) != 0) {
+                        if (STATS) n_alpha += in ? 1u : 0u;
+                        const float op = lane_f(ga.w, ii);
+                        const float alpha = fminf(0.99f, op * vm_exp_core(fminf(fmaxf(power, -6.0f), 0.0f)));
+                        const bool take = in && alpha >= 1.0f / 255.0f;
+                        const float Tn = T * (1.0f - alpha);
+                        const bool stop = take && Tn < 0.0001f;
+                        const bool add = take && !stop;
+                        const float wgt = alpha * T;
+                        const float n0 = fmaf(lane_f(gc.x, ii), wgt, C0);
+                        const float n1 = fmaf(lane_f(gc.y, ii), wgt, C1);
+                        const float n2 = fmaf(lane_f(gc.z, ii), wgt, C2);
+                        C0 = add ? n0 : C0;
+                        C1 = add ? n1 : C1;
+                        C2 = add ? n2 : C2;
+                        T = add ? Tn : T;
+                        live = live && !stop;
+                    }
+                }
+                wave_live = __ballot(live) != 0;
             }
         }
     }
