@@ -168,7 +168,9 @@ vm3dgs_status vm3dgs_render_full(vm3dgs* ctx, const vm3dgs_camera* cams, uint32_
  * "req_link", "page_level", "slot_level", "last_used", "sub_vpage",
  * "sub_last_used", "v2p", "copies", "copy_id", "render_list", "pp_float",
  * "pp_int", "keys", "vals", "ranges", "host_page" (level-0 attributes of all
- * pages decoded to 59 floats). */
+ * pages decoded to 59 floats), "blend_stats" (per tile: pixel-Gaussian
+ * evaluations and alpha evaluations, two uint32, of the last frame run with
+ * VM3DGS_FLAG_BLEND_STATS). */
 int64_t vm3dgs_debug_get(vm3dgs* ctx, const char* name, void* host_dst, int64_t cap);
 
 /* Empty the pool and the page table and restart the frame counter (and the

@@ -1047,6 +1047,7 @@ int64_t vm3dgs_debug_get(vm3dgs* c, const char* name, void* dst, int64_t cap) {
     if (n == "vals") return dev(c->d_pval[c->last_pbuf], 4 * (int64_t)c->last_n_pairs);
     if (n == "ranges") return dev(c->d_ranges, 8 * (int64_t)c->TX * c->TY * V);
     if (n == "depth_order") return dev(c->d_dval[c->last_dbuf], 4 * nt);
+    if (n == "blend_stats") return host(c->h_bstats, 8 * (int64_t)c->TX * c->TY * V);
     return -1;
 }
 

@@ -14,10 +14,10 @@
 //                of their pair counts, so that the longest tiles start first
 //                and the short ones fill in behind them.
 //  k_blend       one 256-thread workgroup per 16x16 tile, one pixel per
-//                thread, one 16 x 4 strip per wave; Gaussians staged in LDS in
-//                batches of 256; per pixel front-to-back blending until
-//                transmittance would fall below 1e-4; the wave leaves a batch
-//                when all its pixels are done.
+//                thread, one 16 x 4 strip per wave; each wave walks the
+//                tile's pairs on its own (registers, no LDS, no barriers);
+//                per pixel front-to-back blending until transmittance would
+//                fall below 1e-4; the wave stops when all its pixels are done.
 #include "kcommon.h"
 #include "vm3dgs_impl.h"
 
@@ -318,14 +318,20 @@ __global__ void k_ranges(const uint32_t* __restrict__ key, uint32_t n, uint2* __
 }
 
 // One 256-thread workgroup per 16x16 tile, one pixel per thread, one 16 x 4
-// strip per wave.  Gaussians are staged in LDS in batches of 256 (centre,
-// support half height, opacity; conic; colour).  A staged Gaussian is the
-// same for all 64 lanes: each wave lists the staged Gaussians whose support
-// rows meet its strip, holds 64 list entries at a time in registers (one per
-// lane) and broadcasts them one by one through scalar registers; the lanes
-// evaluate each with the pixel's "live" flag as a predicate, and the wave
-// leaves the batch when no lane is live.  STATS counts, per tile, the pixel-Gaussian evaluations and
-// those that reached the alpha computation (the algorithmic work).
+// strip per wave.  The four waves of a tile work independently (no LDS, no
+// barriers), so a wave whose strip holds most of the tile's work (a horizon
+// band, say) is not held back at every batch by the others: each wave walks
+// the tile's depth-ordered pairs in chunks of 64, one pair per lane, with the
+// gathers of the next chunk in flight while it blends the current one.  The
+// lanes whose Gaussian's support rows meet the strip form a mask; the wave
+// takes the set bits in order, four at a time, and broadcasts each Gaussian
+// from its lane through scalar registers (v_readlane).  The exponents of four
+// Gaussians are evaluated together, then the four are blended in order (the
+// pixel state after one decides whether the next one is taken); the lanes
+// evaluate with the pixel's "live" flag as a predicate, and the wave stops
+// when no lane is live.  STATS counts, per tile, the pixel-Gaussian
+// evaluations and those that reached the alpha computation (the algorithmic
+// work).
 constexpr int BL_NT = TILE * TILE;
 
 __device__ __forceinline__ float uniform_f(float x) {
@@ -343,10 +349,6 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
                                                  const float4* __restrict__ conic, const float4* __restrict__ rgb,
                                                  int W, int H, int TX, int TY, float* __restrict__ image,
                                                  uint2* __restrict__ stats) {
-    __shared__ float4 s_a[BL_NT];    // u, v, support half height, opacity
-    __shared__ float4 s_b[BL_NT];    // conic ca, cb, cc
-    __shared__ float4 s_c[BL_NT];    // colour
-    __shared__ uint16_t s_idx[BL_NT / WAVE][BL_NT];
     __shared__ uint32_t s_st[2][BL_NT / WAVE];
     const uint32_t tile = order[blockIdx.x];
     const uint32_t per_view = (uint32_t)(TX * TY);
@@ -358,99 +360,86 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
     const bool inside = px < W && py < H;
     const uint2 rg = ranges[tile];
     const float fpx = (float)px, fpy = (float)py;
+    const int lane = (int)__lane_id();
     // centre row of this wave's strip, in a scalar register
     const float strip_c = uniform_f((float)(ty * TILE + (int)(threadIdx.x / WAVE) * (WAVE / TILE)) + 1.5f);
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     uint32_t n_eval = 0, n_alpha = 0;
     bool live = inside;   // this pixel still blends
-    for (uint32_t base = rg.x; base < rg.y; base += BL_NT) {
-        if (__syncthreads_count(live ? 1 : 0) == 0) break;
-        const uint32_t j = base + threadIdx.x;
-        if (j < rg.y) {
-            const uint32_t f = pval[j];
-            const float2 p = xy[f];
-            const float4 co = conic[f];
-            const float4 cl = rgb[f];
-            s_a[threadIdx.x] = make_float4(p.x, p.y, cl.w, co.w);
-            s_b[threadIdx.x] = co;
-            s_c[threadIdx.x] = cl;
+    bool wave_live = __ballot(live) != 0;
+    // chunk registers: this chunk's Gaussian (centre; conic and opacity;
+    // colour and support half height), the next chunk's, and the pair value
+    // of the one after
+    float2 n_p = make_float2(0.f, 0.f);
+    float4 n_co = make_float4(0.f, 0.f, 0.f, 0.f), n_cl = n_co;
+    if (rg.x + lane < rg.y) {
+        const uint32_t f = pval[rg.x + lane];
+        n_p = xy[f];
+        n_co = conic[f];
+        n_cl = rgb[f];
+    }
+    uint32_t n_f = rg.x + WAVE + lane < rg.y ? pval[rg.x + WAVE + lane] : 0u;
+    for (uint32_t base = rg.x; base < rg.y && wave_live; base += WAVE) {
+        const float2 gp = n_p;
+        const float4 gb = n_co, gc = n_cl;
+        const bool valid = base + lane < rg.y;
+        if (base + WAVE + lane < rg.y) {
+            n_p = xy[n_f];
+            n_co = conic[n_f];
+            n_cl = rgb[n_f];
         }
-        __syncthreads();
-        const int cnt = (int)min((uint32_t)BL_NT, rg.y - base);
-        if (__ballot(live) == 0) continue;
-        // this wave's list: the batch entries whose support rows meet its strip
-        // (the others are rejected by every pixel of the strip), in batch order
-        int n_w = 0;
+        n_f = base + 2 * WAVE + lane < rg.y ? pval[base + 2 * WAVE + lane] : 0u;
+        // the chunk's Gaussians whose support rows meet this strip (the
+        // others are rejected by every pixel of the strip)
+        uint64_t mask = __ballot(valid && fabsf(gp.y - strip_c) <= gc.w + 1.5f);
+        while (mask != 0 && wave_live) {
+            int ii[4];
+            bool ok[4];
 #pragma unroll
-        for (int r = 0; r < BL_NT / WAVE; ++r) {
-            const int k = r * WAVE + (int)__lane_id();
-            bool keep = false;
-            if (k < cnt) {
-                const float4 a = s_a[k];
-                keep = fabsf(a.y - strip_c) <= a.z + 1.5f;
+            for (int u = 0; u < 4; ++u) {
+                ok[u] = mask != 0;
+                ii[u] = ok[u] ? (int)__builtin_ctzll(mask) : 0;
+                mask = ok[u] ? (mask & (mask - 1)) : mask;
             }
-            const uint64_t b = __ballot(keep);
-            if (keep) s_idx[threadIdx.x / WAVE][n_w + (int)__popcll(b & lanemask_lt())] = (uint16_t)k;
-            n_w += (int)__popcll(b);
-        }
-        __builtin_amdgcn_wave_barrier();
-        // the list in chunks of 64: lane l holds entry c0 + l in registers and
-        // the wave takes them through v_readlane into scalar registers, so the
-        // loop over Gaussians touches no LDS; the exponents of four entries
-        // are evaluated together, then the four are blended in order (the
-        // pixel state of one decides whether the next one is taken)
-        bool wave_live = true;
-        for (int c0 = 0; c0 < n_w && wave_live; c0 += WAVE) {
-            float4 ga = make_float4(0.f, 0.f, 0.f, 0.f), gb = ga, gc = ga;
-            if (c0 + (int)__lane_id() < n_w) {
-                const int k = (int)s_idx[threadIdx.x / WAVE][c0 + (int)__lane_id()];
-                ga = s_a[k];
-                gb = s_b[k];
-                gc = s_c[k];
-            }
-            const int m = min(WAVE, n_w - c0);
-            for (int i = 0; i < m && wave_live; i += 4) {
-                float pw[4];
-                bool inr[4];
+            float pw[4];
+            bool inr[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const bool two = i + u < m;
-                    const int ii = two ? i + u : i;
-                    const float gu = lane_f(ga.x, ii), gv = lane_f(ga.y, ii);
-                    const float ca = lane_f(gb.x, ii), cb = lane_f(gb.y, ii), cc = lane_f(gb.z, ii);
-                    const float dx = gu - fpx, dy = gv - fpy;
-                    const float q = fmaf(ca * dx, dx, (cc * dy) * dy);
-                    pw[u] = fmaf(-0.5f, q, -((cb * dx) * dy));
-                    inr[u] = !(pw[u] > 0.0f || pw[u] < -5.55f) && two;
+            for (int u = 0; u < 4; ++u) {
+                const float gu = lane_f(gp.x, ii[u]), gv = lane_f(gp.y, ii[u]);
+                const float ca = lane_f(gb.x, ii[u]), cb = lane_f(gb.y, ii[u]), cc = lane_f(gb.z, ii[u]);
+                const float dx = gu - fpx, dy = gv - fpy;
+                const float q = fmaf(ca * dx, dx, (cc * dy) * dy);
+                pw[u] = fmaf(-0.5f, q, -((cb * dx) * dy));
+                inr[u] = !(pw[u] > 0.0f || pw[u] < -5.55f) && ok[u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float power = pw[u];
+                if (STATS) n_eval += (live && ok[u]) ? 1u : 0u;
+                // exp(-5.55) < 1/255 and opacity <= 1: outside [-5.55, 0] a term
+                // fails the alpha test, so the rest runs only when some lane is in
+                const bool in = live && inr[u];
+                if (__ballot(in) != 0) {
+                    if (STATS) n_alpha += in ? 1u : 0u;
+                    // every lane computes; the pixel's state changes only where "in"
+                    const float op = lane_f(gb.w, ii[u]);
+                    const float alpha = fminf(0.99f, op * vm_exp_core(fminf(fmaxf(power, -6.0f), 0.0f)));
+                    const bool take = in && alpha >= 1.0f / 255.0f;
+                    const float Tn = T * (1.0f - alpha);
+                    const bool stop = take && Tn < 0.0001f;
+                    const bool add = take && !stop;
+                    const float wgt = alpha * T;
+                    const float n0 = fmaf(lane_f(gc.x, ii[u]), wgt, C0);
+                    const float n1 = fmaf(lane_f(gc.y, ii[u]), wgt, C1);
+                    const float n2 = fmaf(lane_f(gc.z, ii[u]), wgt, C2);
+                    C0 = add ? n0 : C0;
+                    C1 = add ? n1 : C1;
+                    C2 = add ? n2 : C2;
+                    T = add ? Tn : T;
+                    live = live && !stop;
                 }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const bool two = i + u < m;
-                    const int ii = two ? i + u : i;
-                    const float power = pw[u];
-                    if (STATS) n_eval += (live && two) ? 1u : 0u;
-                    const bool in = live && inr[u];
-                    if (__ballot(in) != 0) {
-                        if (STATS) n_alpha += in ? 1u : 0u;
-                        const float op = lane_f(ga.w, ii);
-                        const float alpha = fminf(0.99f, op * vm_exp_core(fminf(fmaxf(power, -6.0f), 0.0f)));
-                        const bool take = in && alpha >= 1.0f / 255.0f;
-                        const float Tn = T * (1.0f - alpha);
-                        const bool stop = take && Tn < 0.0001f;
-                        const bool add = take && !stop;
-                        const float wgt = alpha * T;
-                        const float n0 = fmaf(lane_f(gc.x, ii), wgt, C0);
-                        const float n1 = fmaf(lane_f(gc.y, ii), wgt, C1);
-                        const float n2 = fmaf(lane_f(gc.z, ii), wgt, C2);
-                        C0 = add ? n0 : C0;
-                        C1 = add ? n1 : C1;
-                        C2 = add ? n2 : C2;
-                        T = add ? Tn : T;
-                        live = live && !stop;
-                    }
-                }
-                wave_live = __ballot(live) != 0;
             }
+            wave_live = __ballot(live) != 0;   // the wave stops when every pixel is done
         }
     }
     if (inside) {
@@ -459,7 +448,7 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
     }
     if (STATS) {
         const uint32_t e = wave_sum(n_eval), al = wave_sum(n_alpha);
-        if (__lane_id() == 0) { s_st[0][threadIdx.x / WAVE] = e; s_st[1][threadIdx.x / WAVE] = al; }
+        if (lane == 0) { s_st[0][threadIdx.x / WAVE] = e; s_st[1][threadIdx.x / WAVE] = al; }
         __syncthreads();
         if (threadIdx.x == 0) {
             uint32_t se = 0, sa = 0;
