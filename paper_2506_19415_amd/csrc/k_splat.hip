@@ -366,7 +366,8 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     uint32_t n_eval = 0, n_alpha = 0;
     bool live = inside;   // this pixel still blends
-    bool wave_live = __ballot(live) != 0;
+    uint64_t live_m = __builtin_amdgcn_ballot_w64(live);   // the wave's live pixels
+    bool wave_live = live_m != 0;
     // chunk registers: this chunk's Gaussian (centre; conic and opacity;
     // colour and support half height), the next chunk's, and the pair value
     // of the one after
@@ -391,7 +392,7 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
         n_f = base + 2 * WAVE + lane < rg.y ? pval[base + 2 * WAVE + lane] : 0u;
         // the chunk's Gaussians whose support rows meet this strip (the
         // others are rejected by every pixel of the strip)
-        uint64_t mask = __ballot(valid && fabsf(gp.y - strip_c) <= gc.w + 1.5f);
+        uint64_t mask = __builtin_amdgcn_ballot_w64(valid && fabsf(gp.y - strip_c) <= gc.w + 1.5f);
         while (mask != 0 && wave_live) {
             int ii[4];
             bool ok[4];
@@ -402,7 +403,6 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
                 mask = ok[u] ? (mask & (mask - 1)) : mask;
             }
             float pw[4];
-            bool inr[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const float gu = lane_f(gp.x, ii[u]), gv = lane_f(gp.y, ii[u]);
@@ -410,20 +410,22 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
                 const float dx = gu - fpx, dy = gv - fpy;
                 const float q = fmaf(ca * dx, dx, (cc * dy) * dy);
                 pw[u] = fmaf(-0.5f, q, -((cb * dx) * dy));
-                inr[u] = !(pw[u] > 0.0f || pw[u] < -5.55f) && ok[u];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const float power = pw[u];
                 if (STATS) n_eval += (live && ok[u]) ? 1u : 0u;
                 // exp(-5.55) < 1/255 and opacity <= 1: outside [-5.55, 0] a term
-                // fails the alpha test, so the rest runs only when some lane is in
-                const bool in = live && inr[u];
-                if (__ballot(in) != 0) {
+                // fails the alpha test, so the rest runs only when some lane is
+                // in (the mask from one ballot per compare, no lane booleans)
+                const uint64_t m = __builtin_amdgcn_ballot_w64(power <= 0.0f) &
+                                   __builtin_amdgcn_ballot_w64(power >= -5.55f) & live_m;
+                if (ok[u] && m != 0) {
+                    const bool in = live && power <= 0.0f && power >= -5.55f;
                     if (STATS) n_alpha += in ? 1u : 0u;
                     // every lane computes; the pixel's state changes only where "in"
                     const float op = lane_f(gb.w, ii[u]);
-                    const float alpha = fminf(0.99f, op * vm_exp_core(fminf(fmaxf(power, -6.0f), 0.0f)));
+                    const float alpha = fminf(0.99f, op * vm_exp_core(__builtin_amdgcn_fmed3f(power, -6.0f, 0.0f)));
                     const bool take = in && alpha >= 1.0f / 255.0f;
                     const float Tn = T * (1.0f - alpha);
                     const bool stop = take && Tn < 0.0001f;
@@ -437,9 +439,10 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
                     C2 = add ? n2 : C2;
                     T = add ? Tn : T;
                     live = live && !stop;
+                    live_m = __builtin_amdgcn_ballot_w64(live);
                 }
             }
-            wave_live = __ballot(live) != 0;   // the wave stops when every pixel is done
+            wave_live = live_m != 0;   // the wave stops when every pixel is done
         }
     }
     if (inside) {
