@@ -402,7 +402,11 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
                 ii[u] = ok[u] ? (int)__builtin_ctzll(mask) : 0;
                 mask = ok[u] ? (mask & (mask - 1)) : mask;
             }
+            // exponents and in-range masks of the four (exp(-5.55) < 1/255 and
+            // opacity <= 1: outside [-5.55, 0] a term fails the alpha test);
+            // one ballot per compare, no lane booleans
             float pw[4];
+            uint64_t mk[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const float gu = lane_f(gp.x, ii[u]), gv = lane_f(gp.y, ii[u]);
@@ -410,17 +414,19 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
                 const float dx = gu - fpx, dy = gv - fpy;
                 const float q = fmaf(ca * dx, dx, (cc * dy) * dy);
                 pw[u] = fmaf(-0.5f, q, -((cb * dx) * dy));
+                mk[u] = __builtin_amdgcn_ballot_w64(pw[u] <= 0.0f) & __builtin_amdgcn_ballot_w64(pw[u] >= -5.55f) &
+                        (ok[u] ? ~0ull : 0ull);
+            }
+            if (((mk[0] | mk[1] | mk[2] | mk[3]) & live_m) == 0) {
+                // no live pixel of the strip is in range of any of the four
+                if (STATS) n_eval += live ? (uint32_t)(ok[0] + ok[1] + ok[2] + ok[3]) : 0u;
+                continue;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const float power = pw[u];
                 if (STATS) n_eval += (live && ok[u]) ? 1u : 0u;
-                // exp(-5.55) < 1/255 and opacity <= 1: outside [-5.55, 0] a term
-                // fails the alpha test, so the rest runs only when some lane is
-                // in (the mask from one ballot per compare, no lane booleans)
-                const uint64_t m = __builtin_amdgcn_ballot_w64(power <= 0.0f) &
-                                   __builtin_amdgcn_ballot_w64(power >= -5.55f) & live_m;
-                if (ok[u] && m != 0) {
+                if ((mk[u] & live_m) != 0) {
                     const bool in = live && power <= 0.0f && power >= -5.55f;
                     if (STATS) n_alpha += in ? 1u : 0u;
                     // every lane computes; the pixel's state changes only where "in"
