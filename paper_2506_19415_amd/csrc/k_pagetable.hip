@@ -284,12 +284,19 @@ struct PtWalk {
     CopyCmd* copies; int32_t* copy_id; int32_t* missing; uint32_t* counters;
 };
 
-// one thread: the misses in request order over the sorted candidate lists
-__global__ void k_ptl_walk(PtWalk a) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One wave: the misses in request order over the sorted candidate lists.  The
+// walk's state is uniform (every lane computes it alike and stores the same
+// values); the scans of a candidate list read 64 entries at a time and take the
+// first usable one by ballot, and the sub-slots of a physical page are read and
+// cleared one per lane.
+__device__ __forceinline__ int lane_i(int x, int i) { return __builtin_amdgcn_readlane(x, i); }
+
+__global__ __launch_bounds__(WAVE) void k_ptl_walk(PtWalk a) {
+    if (blockIdx.x != 0) return;
+    const int lane = (int)__lane_id();
     const uint32_t n_miss = a.counters[vm::C_MISSES];
     const uint32_t n_s = (uint32_t)a.S;
-    uint32_t ncl[3] = {0u, a.counters[vm::C_NCAND1], a.counters[vm::C_NCAND2]};
+    const uint32_t ncl[3] = {0u, a.counters[vm::C_NCAND1], a.counters[vm::C_NCAND2]};
     uint32_t pw = 0, pc[3] = {0, 0, 0}, fn[3] = {0, 0, 0}, fh[3] = {0, 0, 0};
     uint32_t n_copy = 0, n_missing = 0, evict = 0;
     for (uint32_t i = 0; i < n_miss; ++i) {
@@ -303,40 +310,71 @@ __global__ void k_ptl_walk(PtWalk a) {
         int ts = -1, tj = -1;
         const int cap = 1 << (3 * l);
         if (l > 0) {
+            // (1) non-required sub-slots of level-l pages, in candidate order
             while (pc[l] < ncl[l]) {
-                const uint32_t idx = (uint32_t)(a.ck[l][pc[l]++] & a.idx_mask);
-                const int s = (int)(idx / vmk::SUBS), j = (int)(idx % vmk::SUBS);
-                if (a.slot_level[s] == l && !a.req_sub[idx]) { ts = s; tj = j; break; }
+                const uint32_t k = pc[l] + (uint32_t)lane;
+                int idx = 0;
+                bool ok = false;
+                if (k < ncl[l]) {
+                    idx = (int)(a.ck[l][k] & a.idx_mask);
+                    ok = a.slot_level[idx / vmk::SUBS] == l && !a.req_sub[idx];
+                }
+                const uint64_t b = __builtin_amdgcn_ballot_w64(ok);
+                if (b != 0) {
+                    const int f = (int)__builtin_ctzll(b);
+                    const int id = lane_i(idx, f);
+                    ts = id / vmk::SUBS; tj = id % vmk::SUBS;
+                    pc[l] += (uint32_t)f + 1u;
+                    break;
+                }
+                pc[l] = min(pc[l] + (uint32_t)WAVE, ncl[l]);
             }
+            // (2) remaining sub-slots of pages converted to level l in this frame
             while (ts < 0 && fh[l] < fn[l]) {
                 const int s = a.fresh[l * a.S + fh[l]];
-                int jj = -1;
-                if (a.slot_level[s] == l)
-                    for (int t = 0; t < cap; ++t)
-                        if (!a.req_sub[s * vmk::SUBS + t] && a.sub_vpage[s * vmk::SUBS + t] < 0) { jj = t; break; }
-                if (jj >= 0) { ts = s; tj = jj; } else ++fh[l];
+                bool ok = false;
+                if (a.slot_level[s] == l && lane < cap)
+                    ok = !a.req_sub[s * vmk::SUBS + lane] && a.sub_vpage[s * vmk::SUBS + lane] < 0;
+                const uint64_t b = __builtin_amdgcn_ballot_w64(ok);
+                if (b != 0) { ts = s; tj = (int)__builtin_ctzll(b); } else ++fh[l];
             }
         }
         if (ts < 0) {
+            // (3) the least recently used wholly free physical page
             while (pw < n_s) {
-                const uint64_t wk = a.wkeys[pw++];
-                if (wk == ~0ull) { pw = n_s; break; }
-                const int s = (int)(wk & a.idx_mask);
-                if (a.slot_req[s]) continue;
-                const int oldl = a.slot_level[s];
-                if (oldl >= 0)
-                    for (int j = 0; j < (1 << (3 * oldl)); ++j) {
-                        const int32_t op = a.sub_vpage[s * vmk::SUBS + j];
-                        if (op >= 0) { a.v2p[op * a.L + oldl] = -1; ++evict; }
-                    }
-                for (int j = 0; j < vmk::SUBS; ++j) {
-                    a.sub_vpage[s * vmk::SUBS + j] = -1;
-                    a.sub_last_used[s * vmk::SUBS + j] = -1;
+                const uint32_t k = pw + (uint32_t)lane;
+                const uint64_t wk = k < n_s ? a.wkeys[k] : ~0ull;
+                const bool real = wk != ~0ull;
+                const int s = real ? (int)(wk & a.idx_mask) : 0;
+                const bool ok = real && !a.slot_req[s];
+                const uint64_t b_end = __builtin_amdgcn_ballot_w64(!real);
+                const uint64_t b_ok = __builtin_amdgcn_ballot_w64(ok);
+                // usable entries before the first all-ones key (the end of the list)
+                const uint64_t before_end = b_end != 0 ? ((1ull << __builtin_ctzll(b_end)) - 1ull) : ~0ull;
+                const uint64_t b = b_ok & before_end;
+                if (b != 0) {
+                    const int f = (int)__builtin_ctzll(b);
+                    ts = lane_i(s, f); tj = 0;
+                    pw += (uint32_t)f + 1u;
+                    break;
                 }
-                a.slot_level[s] = (int8_t)l;
-                ts = s; tj = 0;
-                if (l > 0) a.fresh[l * a.S + fn[l]++] = s;
-                break;
+                if (b_end != 0) { pw = n_s; break; }
+                pw += (uint32_t)WAVE;
+            }
+            if (ts >= 0) {
+                const int oldl = a.slot_level[ts];
+                bool ev = false;
+                if (oldl >= 0 && lane < (1 << (3 * oldl))) {
+                    const int32_t op = a.sub_vpage[ts * vmk::SUBS + lane];
+                    if (op >= 0) { a.v2p[op * a.L + oldl] = -1; ev = true; }
+                }
+                evict += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(ev));
+                a.sub_vpage[ts * vmk::SUBS + lane] = -1;
+                a.sub_last_used[ts * vmk::SUBS + lane] = -1;
+                __threadfence_block();   // the cleared sub-slots before any lane reads them again
+                a.slot_level[ts] = (int8_t)l;
+                if (l > 0) a.fresh[l * a.S + fn[l]] = ts;
+                if (l > 0) ++fn[l];
             }
         }
         if (ts < 0) {
@@ -352,19 +390,24 @@ __global__ void k_ptl_walk(PtWalk a) {
         a.v2p[p * a.L + l] = e;
         a.req_sub[e] = 1;
         a.slot_req[ts] = 1;
-        const int64_t Pl = a.P >> (3 * l);
-        CopyCmd c;
-        c.host_off = a.level_base[l] + (int64_t)p * Pl * a.bytes_g;
-        c.pool_off = ((int64_t)ts * a.P + (int64_t)tj * Pl) * a.bytes_g;
-        c.bytes = Pl * a.bytes_g;
-        a.copies[n_copy] = c;
-        a.copy_id[4 * n_copy] = p; a.copy_id[4 * n_copy + 1] = l;
-        a.copy_id[4 * n_copy + 2] = ts; a.copy_id[4 * n_copy + 3] = tj;
+        if (lane == 0) {
+            const int64_t Pl = a.P >> (3 * l);
+            CopyCmd c;
+            c.host_off = a.level_base[l] + (int64_t)p * Pl * a.bytes_g;
+            c.pool_off = ((int64_t)ts * a.P + (int64_t)tj * Pl) * a.bytes_g;
+            c.bytes = Pl * a.bytes_g;
+            a.copies[n_copy] = c;
+            a.copy_id[4 * n_copy] = p; a.copy_id[4 * n_copy + 1] = l;
+            a.copy_id[4 * n_copy + 2] = ts; a.copy_id[4 * n_copy + 3] = tj;
+        }
         ++n_copy;
+        __threadfence_block();   // this placement before the next miss's scans
     }
-    a.counters[vm::C_EVICT] = evict;
-    a.counters[vm::C_NCOPY] = n_copy;
-    a.counters[vm::C_NMISSING] = n_missing;
+    if (lane == 0) {
+        a.counters[vm::C_EVICT] = evict;
+        a.counters[vm::C_NCOPY] = n_copy;
+        a.counters[vm::C_NMISSING] = n_missing;
+    }
 }
 
 // render list with per-level counts, and the number of occupied physical pages
@@ -555,7 +598,7 @@ void launch_pagetable_lod(hipStream_t st, const PtArgs& a, SortWork& sw, const L
     pw.sub_last_used = a.sub_last_used; pw.v2p = a.v2p; pw.req_sub = a.req_sub; pw.slot_req = a.slot_req;
     pw.fresh = w.fresh; pw.copies = a.copies; pw.copy_id = a.copy_id; pw.missing = a.missing;
     pw.counters = a.counters;
-    hipLaunchKernelGGL(k_ptl_walk, dim3(1), dim3(64), 0, st, pw);
+    hipLaunchKernelGGL(k_ptl_walk, dim3(1), dim3(WAVE), 0, st, pw);
     hipLaunchKernelGGL(k_ptl_render_list, dim3(1), dim3(PT_NT), 0, st, (const int8_t*)a.page_level,
                        (const int32_t*)a.v2p, n_pg, L, a.P, S, (const int8_t*)a.slot_level,
                        (const int32_t*)a.sub_vpage, (const uint8_t*)a.slot_req, a.rl, a.counters);
