@@ -26,6 +26,7 @@ using vm::RenderEntry;
 
 constexpr int PT_NT = 1024;
 constexpr int PT_MAXK = 8192;  // requests / slots sorted in LDS
+constexpr int RL_SEG = 65536;  // pages per segment of the LOD render list (one byte each in LDS)
 
 // ascending bitonic sort of n (power of two, <= PT_MAXK) keys in LDS
 __device__ void bitonic_lds(uint64_t* s, int n) {
@@ -418,36 +419,52 @@ __global__ __launch_bounds__(PT_NT) void k_ptl_render_list(const int8_t* __restr
                                                            const uint8_t* __restrict__ slot_req,
                                                            RenderEntry* __restrict__ rl, uint32_t* __restrict__ counters) {
     __shared__ uint32_t scan_sh[PT_NT / WAVE];
+    __shared__ int8_t s_lvl[RL_SEG];   // per page of the segment: level rendered, or -1
     __shared__ uint32_t s_used, s_reqd;
-    if (threadIdx.x == 0) { s_used = 0; s_reqd = 0; }
-    uint32_t n_rl = 0, base = 0;
-    for (int b = 0; b < n_pg; b += PT_NT) {
-        const int p = b + threadIdx.x;
-        bool r = false;
-        int32_t e = -1;
-        int l = 0;
-        if (p < n_pg && page_level[p] >= 0) {
-            l = page_level[p];
-            e = v2p[p * L + l];
-            r = e >= 0;
+    const int t = threadIdx.x;
+    if (t == 0) { s_used = 0; s_reqd = 0; }
+    uint32_t n_rl = 0, n_g = 0;
+    // segments of RL_SEG pages: a coalesced pass marks the rendered pages in
+    // LDS (the loads of a thread are independent, so they are in flight
+    // together); thread t then takes the consecutive pages [t K, (t + 1) K) of
+    // the segment, one scan over the threads places its entries in page order
+    for (int seg = 0; seg < n_pg; seg += RL_SEG) {
+        const int n = min(RL_SEG, n_pg - seg);
+        for (int i = t; i < n; i += PT_NT) {
+            const int l = page_level[seg + i];
+            s_lvl[i] = (int8_t)((l >= 0 && v2p[(int64_t)(seg + i) * L + l] >= 0) ? l : -1);
         }
-        const uint32_t cnt = r ? (uint32_t)(P >> (3 * l)) : 0u;
-        uint32_t tot, totc;
-        const uint32_t ex = block_excl_scan<PT_NT>(r ? 1u : 0u, scan_sh, &tot);
-        const uint32_t exc = block_excl_scan<PT_NT>(cnt, scan_sh, &totc);
-        if (r) {
+        __syncthreads();
+        const int K = (n + PT_NT - 1) / PT_NT;
+        const int i0 = min(n, t * K), i1 = min(n, i0 + K);
+        uint32_t n_mine = 0, g_mine = 0;
+        for (int i = i0; i < i1; ++i) {
+            const int l = s_lvl[i];
+            if (l >= 0) { ++n_mine; g_mine += (uint32_t)(P >> (3 * l)); }
+        }
+        uint32_t tot, totg;
+        const uint32_t ex = block_excl_scan<PT_NT>(n_mine, scan_sh, &tot);
+        const uint32_t exg = block_excl_scan<PT_NT>(g_mine, scan_sh, &totg);
+        uint32_t k = n_rl + ex, base = n_g + exg;
+        for (int i = i0; i < i1; ++i) {
+            const int l = s_lvl[i];
+            if (l < 0) continue;
+            const int32_t e = v2p[(int64_t)(seg + i) * L + l];
+            const uint32_t cnt = (uint32_t)(P >> (3 * l));
             RenderEntry q;
-            q.pool_off = (uint32_t)((e / vmk::SUBS) * P + (e % vmk::SUBS) * (P >> (3 * l)));
+            q.pool_off = (uint32_t)((e / vmk::SUBS) * P + (e % vmk::SUBS) * (int)cnt);
             q.count = cnt;
-            q.base = base + exc;
+            q.base = base;
             q.level = (uint32_t)l;
-            rl[n_rl + ex] = q;
+            rl[k++] = q;
+            base += cnt;
         }
         n_rl += tot;
-        base += totc;
+        n_g += totg;
+        __syncthreads();   // s_lvl is rewritten by the next segment
     }
     uint32_t used = 0, reqd = 0;
-    for (int s = threadIdx.x; s < S; s += PT_NT) {
+    for (int s = t; s < S; s += PT_NT) {
         reqd += slot_req[s] ? 1u : 0u;
         const int l = slot_level[s];
         if (l < 0) continue;
@@ -457,13 +474,12 @@ __global__ __launch_bounds__(PT_NT) void k_ptl_render_list(const int8_t* __restr
     }
     used = wave_sum(used);
     reqd = wave_sum(reqd);
-    __syncthreads();
     if (__lane_id() == 0) { atomicAdd(&s_used, used); atomicAdd(&s_reqd, reqd); }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         counters[vm::C_NRL] = n_rl;
         counters[vm::C_REQSLOTS] = s_reqd;
-        counters[vm::C_NRENDER] = base;
+        counters[vm::C_NRENDER] = n_g;
         counters[vm::C_POOLUSED] = s_used;
         counters[vm::C_HITS] = counters[vm::C_NREQ] - counters[vm::C_MISSES];
     }
