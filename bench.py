@@ -11,7 +11,10 @@ A step is one vm3dgs_frame (visibility, page table, copies of the misses,
 preprocess, sorts, blend) for the next camera of the path.  W warm-up steps
 (the cold first frame among them), then K timed steps.  The full-scene splat
 of every Gaussian (same kernels, no paging) is timed on the same cameras,
-and the PSNR of each timed VM frame against it is reported.
+and the PSNR of each timed VM frame against it is reported (the VM images
+come from a second pass over the same cameras, which also counts the blend's
+work; with no missing pages, which the JSON reports, they equal the timed
+frames' images).
 
 One JSON line on stdout; progress on stderr.
 """
@@ -320,7 +323,6 @@ def main():
             log(f"cold frame: copies {out.stats.copies} pages, {out.stats.bytes_copied / 1e6:.1f} MB, "
                 f"{out.stats.ms_total:.2f} ms")
     torch.cuda.synchronize()
-    vm_imgs = torch.empty((K, 1080, 1920, 3), dtype=torch.float32, device="cuda")
     stats, walls = [], []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -328,23 +330,29 @@ def main():
         t = time.perf_counter()
         img, out = r.frame([cams[(W + i) % n_cam]])
         walls.append((time.perf_counter() - t) * 1e3)
-        vm_imgs[i].copy_(img[0])
         stats.append(out.stats.as_dict())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     log(f"VM: {K} frames in {elapsed:.3f} s")
 
-    # the same cameras again with the blend's work counters on: with no missing
-    # pages the render set depends only on the camera, so the blend does the
-    # same work as in the timed frames
+    # the same cameras again with the blend's work counters on, keeping the
+    # images for the PSNR: with no missing pages the render set, and so the
+    # image and the blend's work, depend only on the camera
     r.set_flags(pkg.VM3DGS_FLAG_LINKS | pkg.VM3DGS_FLAG_BLEND_STATS)
+    vm_imgs = torch.empty((K, 1080, 1920, 3), dtype=torch.float32, device="cuda")
     evals, alphas = [], []
+    missing_second = 0
     for i in range(K):
-        _, out = r.frame([cams[(W + i) % n_cam]])
+        img, out = r.frame([cams[(W + i) % n_cam]])
+        vm_imgs[i].copy_(img[0])
         evals.append(out.stats.blend_evals)
         alphas.append(out.stats.blend_alphas)
+        missing_second += out.stats.missing
     r.set_flags(pkg.VM3DGS_FLAG_LINKS)
     missing_timed = sum(s["missing"] for s in stats)
+    if missing_timed or missing_second:
+        log(f"warning: missing pages (timed {missing_timed}, second pass {missing_second}): the second pass's "
+            "images and work counts may differ from the timed frames")
 
     full_fps = None
     full_walls = []
@@ -425,6 +433,7 @@ def main():
         "stage_gbs": stage_gbs,
         "blend_ms_mean": blend_ms,
         "missing_pages_timed": missing_timed,
+        "missing_pages_second_pass": missing_second,
         "preprocess_roofline": {"bound": "hbm", "achieved": pre_bytes / (pre_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                                 "unit": "GB/s", "frac": pre_bytes / (pre_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                 "per_unit": "300 B per render Gaussian (236 B attributes read, 64 B written)"},

@@ -580,7 +580,7 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         HIPCHK(hipEventRecord(ev[0], c->sr));
         HIPCHK(hipMemcpyAsync(c->d_cams, c->h_cams, sizeof(CamK) * n_views, hipMemcpyHostToDevice, c->sr));
         if (c->pf_on) push_poses(c, cams, n_views);
-        begin_work(c);
+        c->sw.reset();
         VisArgs va{};
         va.spheres = c->d_sph; va.n_pg = c->n_pg; va.cell_lo = c->d_clo; va.cell_hi = c->d_chi; va.nc = c->ps.nc();
         va.link_start = c->d_ls; va.link_dst = c->d_ld; va.use_links = (c->opt.flags & VM3DGS_FLAG_LINKS) ? 1 : 0;
@@ -592,6 +592,13 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         va.page_level = c->d_plevel; va.req_keys = c->d_keys; va.counters = c->d_ctr;
         va.cell_rects = c->d_crect; va.cell_area = c->d_carea; va.cell_offs = c->d_coffs;
         va.sw = &c->sw;
+        {
+            // counters, tickets, histograms, ID buffer and request arrays: one launch
+            FillSegs fs;
+            fs.seg[fs.n++] = FillSeg{c->d_zero, (uint64_t)ZB_WORDS, 0u, 0};
+            visibility_clears(va, fs);
+            launch_fill_multi(c->sr, fs);
+        }
         launch_visibility(c->sr, va);
         HIPCHK(hipGetLastError());
         HIPCHK(hipEventRecord(ev[1], c->sr));
@@ -687,7 +694,7 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
                                   hipMemcpyDeviceToHost, c->sr));
         HIPCHK(hipMemcpyAsync(c->h_total + 2, c->d_zero + ZB_BYTES, 8, hipMemcpyDeviceToHost, c->sr));
         HIPCHK(hipMemcpyAsync(c->h_total + 4, c->d_cp_err, 4, hipMemcpyDeviceToHost, c->sr));
-        HIPCHK(hipStreamSynchronize(c->sr));
+        spin_wait(c);
         if (c->h_total[4]) throw HipError{hipErrorInvalidValue, "a page copy command left the store or the pool",
                                           __LINE__};
         {

@@ -17,6 +17,9 @@
 //  k_links         a directly seen page pushes its depth to its linked pages
 //  k_requests      LOD level from the projected page radius, request keys
 //                  (class, depth, page)
+#include <algorithm>
+#include <stdexcept>
+
 #include "kcommon.h"
 #include "vm3dgs_impl.h"
 
@@ -263,6 +266,19 @@ __global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long
     if (i < n) p[i] = v;
 }
 
+// several fills in one launch (the clears at the start of a frame, where the
+// GPU would otherwise wait for the host to submit each small kernel)
+__global__ void k_fill_multi(vm::FillSegs f) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (int s = 0; s < f.n; ++s) {
+        const vm::FillSeg g = f.seg[s];
+        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += stride) {
+            if (g.wide) ((unsigned long long*)g.p)[i] = g.v;
+            else ((uint32_t*)g.p)[i] = (uint32_t)g.v;
+        }
+    }
+}
+
 }  // namespace vmk
 
 namespace vm {
@@ -278,11 +294,24 @@ void launch_fill_u64(hipStream_t st, unsigned long long* p, uint64_t n, unsigned
     if (n) hipLaunchKernelGGL(k_fill_u64, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v);
 }
 
+void launch_fill_multi(hipStream_t st, const FillSegs& f) {
+    uint64_t mx = 0;
+    for (int s = 0; s < f.n; ++s) mx = std::max(mx, f.seg[s].n);
+    if (mx) hipLaunchKernelGGL(k_fill_multi, dim3((unsigned)std::min<uint64_t>(nblk(mx, 256), 1024)), dim3(256), 0, st,
+                               f);
+}
+
+void visibility_clears(const VisArgs& a, FillSegs& f) {
+    const int64_t npx = (int64_t)a.Wv * a.Hv;
+    if (f.n + 3 > FillSegs::kMax) throw std::length_error("fill segments exhausted");
+    f.seg[f.n++] = FillSeg{a.idbuf, (uint64_t)(npx * a.n_views), NONE64, 1};
+    f.seg[f.n++] = FillSeg{a.req_direct, (uint64_t)a.n_pg, NONE32, 0};
+    f.seg[f.n++] = FillSeg{a.req_link, (uint64_t)a.n_pg, NONE32, 0};
+}
+
+// the ID buffer and the request arrays are cleared beforehand (visibility_clears)
 void launch_visibility(hipStream_t st, const VisArgs& a) {
     const int64_t npx = (int64_t)a.Wv * a.Hv;
-    launch_fill_u64(st, a.idbuf, npx * a.n_views, NONE64);
-    launch_fill_u32(st, a.req_direct, a.n_pg, NONE32);
-    launch_fill_u32(st, a.req_link, a.n_pg, NONE32);
     hipLaunchKernelGGL(k_frustum, dim3(nblk((uint64_t)a.n_pg * a.n_views, 256)), dim3(256), 0, st, a.spheres, a.n_pg,
                        a.cams, a.n_views, a.W, a.H, a.guard, a.cand, a.counters);
     hipLaunchKernelGGL(k_rays, dim3(nblk(npx * a.n_views, 256)), dim3(256), 0, st, a.cams, a.n_views, a.W, a.H,

@@ -160,6 +160,17 @@ void launch_tile_order(hipStream_t st, const uint2* ranges, uint32_t n_tiles, ui
 void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* order, const uint32_t* pval, const float2* xy,
                   const float4* conic, const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image,
                   uint2* stats);
+// fills done together in one launch (at most kMax)
+struct FillSeg {
+    void* p; uint64_t n; uint64_t v; int wide;   // wide: 8-byte words, else 4-byte
+};
+struct FillSegs {
+    static constexpr int kMax = 8;
+    FillSeg seg[kMax];
+    int n = 0;
+};
+void launch_fill_multi(hipStream_t st, const FillSegs& f);
+void visibility_clears(const VisArgs& a, FillSegs& f);
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v);
 void launch_fill_u64(hipStream_t st, unsigned long long* p, uint64_t n, unsigned long long v);
 
