@@ -117,6 +117,11 @@ typedef struct {
     uint64_t bytes_copied;      /* host -> device page bytes */
     uint64_t blend_evals;       /* pixel-Gaussian evaluations (VM3DGS_FLAG_BLEND_STATS only) */
     uint64_t blend_alphas;      /* of those, evaluations that computed alpha (same flag) */
+    /* stage times on the render stream (HIP events): ms_pagetable includes the
+     * readback of the page-table counters; ms_copy is the launch that runs the
+     * demand copies side by side with the preprocess of the Gaussians resident
+     * before the frame (0 without misses); ms_preprocess is the rest of the
+     * preprocess */
     float ms_visibility, ms_pagetable, ms_copy, ms_preprocess, ms_sort, ms_blend, ms_total;
     float lod_radius_px;        /* level-0 radius this frame used (moves with VM3DGS_FLAG_ADAPTIVE_LOD) */
 } vm3dgs_stats;
@@ -143,8 +148,9 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
                             uint32_t lod_levels, const vm3dgs_options* opt, vm3dgs** out);
 
 /* One frame for n_views cameras (Sec. 4): visibility, page table, copies of
- * the misses (host -> device on the copy stream; the render stream waits for
- * them), splatting of the resident pages.  image_dev: device, caller-owned,
+ * the misses (read by the GPU from the pinned store on the render stream,
+ * before any copied Gaussian is used; prefetch copies on the copy stream),
+ * splatting of the resident pages.  image_dev: device, caller-owned,
  * [n_views][img_h][img_w][3] float32, written on the render stream and
  * complete when that stream reaches the end of this call's work.  The frame
  * counter advances on every call.  out may be NULL.
