@@ -70,6 +70,11 @@ struct vm3dgs {
     uint32_t* d_dkey[2] = {nullptr, nullptr}; uint32_t* d_dval[2] = {nullptr, nullptr};
     uint32_t* d_offs = nullptr;
     uint64_t cap_pairs = 0;
+    // pairs the launches after the scan cover (their grids), per kind of
+    // frame: 1.5 times the last count; a frame with more is splatted again
+    uint32_t pair_grid[2] = {1u << 20, 1u << 20};   // VM frames, full-scene renders
+    int pair_kind = 0;                              // of the splat in flight
+    uint32_t pair_cover = 0;                        // its bound
     uint32_t* d_pkey[2] = {nullptr, nullptr}; uint32_t* d_pval[2] = {nullptr, nullptr};
     uint32_t* d_emit_start = nullptr;
     uint2* d_ranges = nullptr; uint32_t* d_tile_order = nullptr;
@@ -265,18 +270,18 @@ void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool,
     // depth order of the render set (culled entries carry all-ones keys and sort last)
     const int db = onesweep_u32(c->sr, c->sw, c->d_dkey, c->d_dval, (uint32_t)n_total, 0, 32);
     scan_lb_gather(c->sr, c->sw, c->d_tiles, c->d_dval[db], n_total, c->d_offs, c->d_total);
-    HIPCHK(hipMemcpyAsync(c->h_total, c->d_total, sizeof(uint32_t), hipMemcpyDeviceToHost, c->sr));
-    HIPCHK(hipMemcpyAsync(c->h_total + 1, c->d_zero + ZB_ERR, sizeof(uint32_t), hipMemcpyDeviceToHost, c->sr));
-    spin_wait(c);
-    if (c->h_total[1]) throw HipError{hipErrorUnknown, "single-pass scan look-back did not complete", __LINE__};
-    const uint32_t n_pairs = *c->h_total;
-    ensure_pairs(c, n_pairs);
-    launch_emit(c->sr, c->d_dval[db], c->d_offs, c->d_tiles, c->d_rect, c->d_emit_start, (uint32_t)n_total, n_pairs,
-                n_render, c->TX, c->TY, c->d_pkey[0], c->d_pval[0],
-                (uint32_t)std::min<uint64_t>(c->cap_pairs, 0xffffffffu));
+    // the pair count stays on the device: emission, tile sort and ranges read
+    // it there, with grids sized for a bound on it; the host checks the count
+    // against the bound once the frame is done (splat_pairs_ok)
+    const uint32_t cap = (uint32_t)std::min<uint64_t>({c->cap_pairs, (uint64_t)c->pair_grid[c->pair_kind],
+                                                       0xffffffffull});
+    c->pair_cover = cap;
+    launch_emit(c->sr, c->d_dval[db], c->d_offs, c->d_tiles, c->d_rect, c->d_emit_start, (uint32_t)n_total,
+                c->d_total, n_render, c->TX, c->TY, c->d_pkey[0], c->d_pval[0], cap);
     const uint32_t n_tiles = (uint32_t)(c->TX * c->TY) * n_views;
-    const int pb = onesweep_u32(c->sr, c->sw, c->d_pkey, c->d_pval, n_pairs, 0, std::max(1, bits_for(n_tiles)));
-    launch_ranges(c->sr, c->d_pkey[pb], n_pairs, c->d_ranges, n_tiles);
+    const int pb = onesweep_u32_dev(c->sr, c->sw, c->d_pkey, c->d_pval, cap, c->d_total, 0,
+                                    std::max(1, bits_for(n_tiles)));
+    launch_ranges(c->sr, c->d_pkey[pb], cap, c->d_total, c->d_ranges, n_tiles);
     launch_tile_order(c->sr, c->d_ranges, n_tiles, c->d_tile_order);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[5], c->sr));
@@ -293,12 +298,27 @@ void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool,
         st->blend_evals = e;
         st->blend_alphas = al;
     }
-    c->last_views = n_views; c->last_n_render = n_render; c->last_n_pairs = n_pairs;
+    HIPCHK(hipMemcpyAsync(c->h_total, c->d_total, sizeof(uint32_t), hipMemcpyDeviceToHost, c->sr));
+    HIPCHK(hipMemcpyAsync(c->h_total + 1, c->d_zero + ZB_ERR, sizeof(uint32_t), hipMemcpyDeviceToHost, c->sr));
+    c->last_views = n_views; c->last_n_render = n_render;
     c->last_pbuf = pb; c->last_dbuf = db;
-    if (st) {
-        st->render_gaussians = n_total;
-        st->pairs = n_pairs;
+    if (st) st->render_gaussians = n_total;
+}
+
+// after the render stream has passed splat: true when every pair fitted the
+// pair buffers; otherwise they are grown and the caller runs splat again
+bool splat_pairs_ok(vm3dgs* c, vm3dgs_stats* st) {
+    if (c->h_total[1]) throw HipError{hipErrorUnknown, "single-pass scan look-back did not complete", __LINE__};
+    const uint32_t n_pairs = c->h_total[0];
+    const uint64_t want = std::min<uint64_t>((uint64_t)n_pairs + n_pairs / 2 + 1024, 0xffffffffull);
+    c->pair_grid[c->pair_kind] = (uint32_t)want;
+    if (n_pairs > c->pair_cover) {
+        ensure_pairs(c, n_pairs);
+        return false;
     }
+    c->last_n_pairs = n_pairs;
+    if (st) st->pairs = n_pairs;
+    return true;
 }
 
 // camera pose for the prefetch features: position relative to the centre
@@ -689,6 +709,7 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         st.candidates = k[C_CAND]; st.requested = k[C_NREQ]; st.direct = k[C_DIRECT]; st.linked = k[C_LINKED];
         st.hits = k[C_HITS]; st.misses = k[C_MISSES]; st.evictions = k[C_EVICT]; st.missing = k[C_NMISSING];
         st.copies = n_dem; st.render_pages = k[C_NRL]; st.pool_pages_used = k[C_POOLUSED];
+        c->pair_kind = 0;
         splat(c, c->d_rlist, k[C_NRL], c->d_pool, n_render, n_views, image, &st, n_dem ? &dem : nullptr);
         // outputs of the frame: request order and missing list
         if (c->last_n_req)
@@ -704,6 +725,13 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         spin_wait(c);
         if (c->h_total[4]) throw HipError{hipErrorInvalidValue, "a page copy command left the store or the pool",
                                           __LINE__};
+        if (!splat_pairs_ok(c, &st)) {
+            // more pairs than the buffers held: the same render set again (its
+            // pages are resident now) with the grown buffers
+            splat(c, c->d_rlist, k[C_NRL], c->d_pool, n_render, n_views, image, &st, nullptr);
+            spin_wait(c);
+            if (!splat_pairs_ok(c, &st)) throw std::length_error("pair buffers could not hold the frame's pairs");
+        }
         {
             uint64_t b;
             memcpy(&b, c->h_total + 2, 8);
@@ -758,9 +786,16 @@ vm3dgs_status vm3dgs_render_full(vm3dgs* c, const vm3dgs_camera* cams, uint32_t 
         HIPCHK(hipEventRecord(c->ev[0], c->sr));
         HIPCHK(hipMemcpyAsync(c->d_cams, c->h_cams, sizeof(CamK) * n_views, hipMemcpyHostToDevice, c->sr));
         begin_work(c);
+        c->pair_kind = 1;
         splat(c, c->d_rlist_full, (uint32_t)c->n_pg, c->d_full, (uint32_t)c->n_pg * (uint32_t)c->P, n_views, image, &st,
               nullptr);
         HIPCHK(hipStreamSynchronize(c->sr));
+        if (!splat_pairs_ok(c, &st)) {
+            splat(c, c->d_rlist_full, (uint32_t)c->n_pg, c->d_full, (uint32_t)c->n_pg * (uint32_t)c->P, n_views,
+                  image, &st, nullptr);
+            HIPCHK(hipStreamSynchronize(c->sr));
+            if (!splat_pairs_ok(c, &st)) throw std::length_error("pair buffers could not hold the frame's pairs");
+        }
         st.ms_preprocess = ms(c->ev[3], c->ev[4]);
         st.ms_sort = ms(c->ev[4], c->ev[5]);
         st.ms_blend = ms(c->ev[5], c->ev[6]);

@@ -120,8 +120,10 @@ __global__ __launch_bounds__(SC_NT) void k_scan_lb(In in, uint64_t n, uint32_t* 
 // key adds one to its digit's counter in LDS (four copies, wave w using copy
 // w mod 4, summed at the end, so that the waves of a block spread over them)
 template <typename K, int NT, int ITEMS>
-__global__ __launch_bounds__(NT) void k_os_hist(const K* __restrict__ keys, uint32_t n, int shift0, int passes,
+__global__ __launch_bounds__(NT) void k_os_hist(const K* __restrict__ keys, uint32_t n_arg,
+                                                const uint32_t* __restrict__ n_dev, int shift0, int passes,
                                                 uint32_t* __restrict__ ghist) {
+    const uint32_t n = n_dev ? min(*n_dev, n_arg) : n_arg;
     constexpr int NC = 4;
     constexpr int TILE_K = NT * ITEMS;
     __shared__ uint32_t h[NC][4][256];
@@ -157,9 +159,11 @@ __global__ __launch_bounds__(NT) void k_os_hist(const K* __restrict__ keys, uint
 // HV: values travel with the keys (without them no value pointer is touched)
 template <typename K, bool HV, int NT, int ITEMS>
 __global__ __launch_bounds__(NT) void k_os_pass(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                K* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t n,
+                                                K* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t n_arg,
+                                                const uint32_t* __restrict__ n_dev,
                                                 int shift, const uint32_t* __restrict__ ghist_pass,
                                                 uint64_t* status, uint32_t* ticket, uint32_t epoch, uint32_t* err) {
+    const uint32_t n = n_dev ? min(*n_dev, n_arg) : n_arg;
     constexpr bool has_vals = HV;
     constexpr int NW = NT / WAVE;
     constexpr int TILE_K = NT * ITEMS, SPAN = TILE_K / NW;
@@ -175,9 +179,10 @@ __global__ __launch_bounds__(NT) void k_os_pass(const K* __restrict__ kin, const
     for (int i = threadIdx.x; i < NW * 256; i += NT) (&wc[0][0])[i] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
+    const uint32_t tile0 = tile * TILE_K;
+    if (tile0 >= n && tile > 0) return;   // beyond the keys (grid sized for a capacity bound)
     const int w = threadIdx.x / WAVE;
     const uint64_t lt = lanemask_lt();
-    const uint32_t tile0 = tile * TILE_K;
     const uint32_t base = tile0 + w * SPAN;
     K key[ITEMS];
     uint32_t val[ITEMS];
@@ -256,9 +261,11 @@ static uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) /
 // ---------------------------------------------------------------- onesweep
 size_t lb_status_words(uint64_t n_keys) { return (size_t)256 * div_up(n_keys, RS_MIN_TILE) + 256; }
 
+// n: the number of keys, or with n_dev a bound on it (the grid covers n keys,
+// the kernels sort min(*n_dev, n))
 template <typename K, int NT, int ITEMS>
-static int onesweep_items(hipStream_t st, SortWork& w, K* keys[2], uint32_t* vals[2], uint32_t n, int begin_bit,
-                          int end_bit) {
+static int onesweep_items(hipStream_t st, SortWork& w, K* keys[2], uint32_t* vals[2], uint32_t n,
+                          const uint32_t* n_dev, int begin_bit, int end_bit) {
     const uint32_t nb = div_up(n, NT * ITEMS);
     const int passes = (end_bit - begin_bit + 7) / 8;
     const int has_vals = vals[0] != nullptr;
@@ -266,17 +273,17 @@ static int onesweep_items(hipStream_t st, SortWork& w, K* keys[2], uint32_t* val
     for (int p0 = 0; p0 < passes; p0 += 4) {
         const int np = std::min(4, passes - p0);
         uint32_t* gh = w.next_hist(np);
-        hipLaunchKernelGGL((k_os_hist<K, NT, ITEMS>), dim3(nb), dim3(NT), 0, st, (const K*)keys[cur], n,
+        hipLaunchKernelGGL((k_os_hist<K, NT, ITEMS>), dim3(nb), dim3(NT), 0, st, (const K*)keys[cur], n, n_dev,
                            begin_bit + 8 * p0, np, gh);
         for (int p = 0; p < np; ++p) {
             const int shift = begin_bit + 8 * (p0 + p);
             if (has_vals)
                 hipLaunchKernelGGL((k_os_pass<K, true, NT, ITEMS>), dim3(nb), dim3(NT), 0, st, (const K*)keys[cur],
-                                   (const uint32_t*)vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, shift,
+                                   (const uint32_t*)vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, n_dev, shift,
                                    (const uint32_t*)(gh + 256 * p), w.status, w.next_ticket(), w.next_epoch(), w.err);
             else
                 hipLaunchKernelGGL((k_os_pass<K, false, NT, ITEMS>), dim3(nb), dim3(NT), 0, st, (const K*)keys[cur],
-                                   (const uint32_t*)nullptr, keys[cur ^ 1], (uint32_t*)nullptr, n, shift,
+                                   (const uint32_t*)nullptr, keys[cur ^ 1], (uint32_t*)nullptr, n, n_dev, shift,
                                    (const uint32_t*)(gh + 256 * p), w.status, w.next_ticket(), w.next_epoch(), w.err);
             cur ^= 1;
         }
@@ -290,20 +297,25 @@ static int onesweep_items(hipStream_t st, SortWork& w, K* keys[2], uint32_t* val
 // tiles make every pass slower (more blocks, longer look-back chains)
 constexpr int SORT_NT = 512;
 template <typename K>
-static int onesweep_impl(hipStream_t st, SortWork& w, K* keys[2], uint32_t* vals[2], uint32_t n, int begin_bit,
-                         int end_bit) {
+static int onesweep_impl(hipStream_t st, SortWork& w, K* keys[2], uint32_t* vals[2], uint32_t n,
+                         const uint32_t* n_dev, int begin_bit, int end_bit) {
     if (n == 0) return 0;
-    return onesweep_items<K, SORT_NT, RS_MIN_TILE / SORT_NT>(st, w, keys, vals, n, begin_bit, end_bit);
+    return onesweep_items<K, SORT_NT, RS_MIN_TILE / SORT_NT>(st, w, keys, vals, n, n_dev, begin_bit, end_bit);
 }
 
 int onesweep_u32(hipStream_t st, SortWork& w, uint32_t* keys[2], uint32_t* vals[2], uint32_t n, int begin_bit,
                  int end_bit) {
-    return onesweep_impl<uint32_t>(st, w, keys, vals, n, begin_bit, end_bit);
+    return onesweep_impl<uint32_t>(st, w, keys, vals, n, nullptr, begin_bit, end_bit);
+}
+
+int onesweep_u32_dev(hipStream_t st, SortWork& w, uint32_t* keys[2], uint32_t* vals[2], uint32_t n_bound,
+                     const uint32_t* n_dev, int begin_bit, int end_bit) {
+    return onesweep_impl<uint32_t>(st, w, keys, vals, n_bound, n_dev, begin_bit, end_bit);
 }
 
 int onesweep_u64(hipStream_t st, SortWork& w, uint64_t* keys[2], uint32_t* vals[2], uint32_t n, int begin_bit,
                  int end_bit) {
-    return onesweep_impl<uint64_t>(st, w, keys, vals, n, begin_bit, end_bit);
+    return onesweep_impl<uint64_t>(st, w, keys, vals, n, nullptr, begin_bit, end_bit);
 }
 
 void scan_lb(hipStream_t st, SortWork& w, const uint32_t* in, uint64_t n, uint32_t* out, uint32_t* total) {

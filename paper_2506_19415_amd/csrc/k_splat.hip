@@ -251,25 +251,31 @@ __global__ __launch_bounds__(256) void k_copy_preprocess(CopyArgs c, uint32_t n_
 using vm::EMIT_SPAN;
 
 __global__ void k_emit_starts(const uint32_t* __restrict__ offs, const uint32_t* __restrict__ order,
-                              const uint32_t* __restrict__ tiles, uint32_t n_total, uint32_t* __restrict__ start) {
+                              const uint32_t* __restrict__ tiles, uint32_t n_total, uint32_t n_start,
+                              uint32_t* __restrict__ start) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_total) return;
     const uint32_t off = offs[i], cnt = tiles[order[i]];
     if (cnt == 0) return;
-    for (uint32_t b = (off + EMIT_SPAN - 1) / EMIT_SPAN; b * EMIT_SPAN < off + cnt; ++b) start[b] = i;
+    // blocks past the pair capacity are not launched (n_start bounds the table)
+    for (uint32_t b = (off + EMIT_SPAN - 1) / EMIT_SPAN; b * EMIT_SPAN < off + cnt && b < n_start; ++b) start[b] = i;
 }
 
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order, const uint32_t* __restrict__ offs,
                                               const uint2* __restrict__ rect, const uint32_t* __restrict__ start,
-                                              uint32_t n_total, uint32_t n_pairs, uint32_t n_render, int TX, int TY,
-                                              uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval,
-                                              uint32_t cap) {
+                                              uint32_t n_total, const uint32_t* __restrict__ n_pairs_dev,
+                                              uint32_t n_render, int TX, int TY, uint32_t* __restrict__ pkey,
+                                              uint32_t* __restrict__ pval, uint32_t cap) {
     __shared__ uint32_t s_off[EMIT_SPAN + 1];
     __shared__ uint32_t s_f[EMIT_SPAN + 1];
     __shared__ uint32_t s_kb[EMIT_SPAN + 1];
     __shared__ uint32_t s_wd[EMIT_SPAN + 1];
     __shared__ float s_inv[EMIT_SPAN + 1];
+    // pairs beyond the capacity are not written (the frame is run again with
+    // larger buffers)
+    const uint32_t n_pairs = min(*n_pairs_dev, cap);
     const uint32_t p0 = blockIdx.x * EMIT_SPAN;
+    if (p0 >= n_pairs) return;
     const uint32_t p1 = min(p0 + EMIT_SPAN, n_pairs);
     const uint32_t g0 = start[blockIdx.x];
     const uint32_t n_runs = min(EMIT_SPAN + 1, n_total - g0);
@@ -299,10 +305,8 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
         uint32_t qy = (uint32_t)((float)q * s_inv[lo]);
         if (qy * wd > q) --qy;
         else if ((qy + 1) * wd <= q) ++qy;
-        if (j < cap) {
-            pkey[j] = s_kb[lo] + qy * (uint32_t)TX + (q - qy * wd);
-            pval[j] = s_f[lo];
-        }
+        pkey[j] = s_kb[lo] + qy * (uint32_t)TX + (q - qy * wd);
+        pval[j] = s_f[lo];
     }
 }
 
@@ -333,7 +337,9 @@ __global__ __launch_bounds__(TO_NT) void k_tile_order(const uint2* __restrict__ 
     }
 }
 
-__global__ void k_ranges(const uint32_t* __restrict__ key, uint32_t n, uint2* __restrict__ ranges) {
+__global__ void k_ranges(const uint32_t* __restrict__ key, uint32_t cap, const uint32_t* __restrict__ n_dev,
+                         uint2* __restrict__ ranges) {
+    const uint32_t n = min(*n_dev, cap);
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t t = key[i];
@@ -529,18 +535,20 @@ void launch_preprocess(hipStream_t st, const SplatArgs& s) {
 }
 
 void launch_emit(hipStream_t st, const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles,
-                 const uint2* rect, uint32_t* starts, uint32_t n_total, uint32_t n_pairs, uint32_t n_render, int TX,
-                 int TY, uint32_t* pkey, uint32_t* pval, uint32_t cap) {
-    if (n_total == 0 || n_pairs == 0) return;
-    hipLaunchKernelGGL(k_emit_starts, dim3(nblk(n_total, 256)), dim3(256), 0, st, offsets, order, tiles, n_total, starts);
-    hipLaunchKernelGGL(k_emit, dim3(nblk(n_pairs, EMIT_SPAN)), dim3(256), 0, st, order, offsets, rect,
-                       (const uint32_t*)starts, n_total, n_pairs, n_render, TX, TY, pkey, pval, cap);
+                 const uint2* rect, uint32_t* starts, uint32_t n_total, const uint32_t* n_pairs_dev, uint32_t n_render,
+                 int TX, int TY, uint32_t* pkey, uint32_t* pval, uint32_t cap) {
+    if (n_total == 0 || cap == 0) return;
+    const uint32_t n_blocks = nblk(cap, EMIT_SPAN);
+    hipLaunchKernelGGL(k_emit_starts, dim3(nblk(n_total, 256)), dim3(256), 0, st, offsets, order, tiles, n_total,
+                       n_blocks, starts);
+    hipLaunchKernelGGL(k_emit, dim3(n_blocks), dim3(256), 0, st, order, offsets, rect, (const uint32_t*)starts,
+                       n_total, n_pairs_dev, n_render, TX, TY, pkey, pval, cap);
 }
 
-void launch_ranges(hipStream_t st, const uint32_t* pkey, uint32_t n_pairs, uint2* ranges, uint32_t n_tiles) {
+void launch_ranges(hipStream_t st, const uint32_t* pkey, uint32_t cap, const uint32_t* n_pairs_dev, uint2* ranges,
+                   uint32_t n_tiles) {
     launch_fill_u64(st, (unsigned long long*)ranges, n_tiles, 0ull);
-    if (n_pairs)
-        hipLaunchKernelGGL(k_ranges, dim3(nblk(n_pairs, 256)), dim3(256), 0, st, pkey, n_pairs, ranges);
+    if (cap) hipLaunchKernelGGL(k_ranges, dim3(nblk(cap, 256)), dim3(256), 0, st, pkey, cap, n_pairs_dev, ranges);
 }
 
 void launch_tile_order(hipStream_t st, const uint2* ranges, uint32_t n_tiles, uint32_t* order) {

@@ -68,6 +68,9 @@ struct SortWork {
 size_t lb_status_words(uint64_t n_keys);
 int onesweep_u32(hipStream_t st, SortWork& w, uint32_t* keys[2], uint32_t* vals[2], uint32_t n, int begin_bit,
                  int end_bit);
+// the same with the key count on the device (at most n_bound, which sizes the grid)
+int onesweep_u32_dev(hipStream_t st, SortWork& w, uint32_t* keys[2], uint32_t* vals[2], uint32_t n_bound,
+                     const uint32_t* n_dev, int begin_bit, int end_bit);
 int onesweep_u64(hipStream_t st, SortWork& w, uint64_t* keys[2], uint32_t* vals[2], uint32_t n, int begin_bit,
                  int end_bit);
 void scan_lb(hipStream_t st, SortWork& w, const uint32_t* in, uint64_t n, uint32_t* out, uint32_t* total);
@@ -161,10 +164,12 @@ struct SplatArgs {
     uint32_t* dkey; uint32_t* dval;
 };
 void launch_preprocess(hipStream_t st, const SplatArgs& a);
+// pairs counted on the device (*n_pairs_dev); the grids cover the capacity cap
 void launch_emit(hipStream_t st, const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles,
-                 const uint2* rect, uint32_t* starts, uint32_t n_total, uint32_t n_pairs, uint32_t n_render, int TX,
-                 int TY, uint32_t* pkey, uint32_t* pval, uint32_t cap);
-void launch_ranges(hipStream_t st, const uint32_t* pkey, uint32_t n_pairs, uint2* ranges, uint32_t n_tiles);
+                 const uint2* rect, uint32_t* starts, uint32_t n_total, const uint32_t* n_pairs_dev, uint32_t n_render,
+                 int TX, int TY, uint32_t* pkey, uint32_t* pval, uint32_t cap);
+void launch_ranges(hipStream_t st, const uint32_t* pkey, uint32_t cap, const uint32_t* n_pairs_dev, uint2* ranges,
+                   uint32_t n_tiles);
 void launch_tile_order(hipStream_t st, const uint2* ranges, uint32_t n_tiles, uint32_t* order);
 void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* order, const uint32_t* pval, const float2* xy,
                   const float4* conic, const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image,
