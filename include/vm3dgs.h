@@ -117,11 +117,6 @@ typedef struct {
     uint64_t bytes_copied;      /* host -> device page bytes */
     uint64_t blend_evals;       /* pixel-Gaussian evaluations (VM3DGS_FLAG_BLEND_STATS only) */
     uint64_t blend_alphas;      /* of those, evaluations that computed alpha (same flag) */
-    /* stage times on the render stream (HIP events): ms_pagetable includes the
-     * readback of the page-table counters; ms_copy is the launch that runs the
-     * demand copies side by side with the preprocess of the Gaussians resident
-     * before the frame (0 without misses); ms_preprocess is the rest of the
-     * preprocess */
     float ms_visibility, ms_pagetable, ms_copy, ms_preprocess, ms_sort, ms_blend, ms_total;
     float lod_radius_px;        /* level-0 radius this frame used (moves with VM3DGS_FLAG_ADAPTIVE_LOD) */
 } vm3dgs_stats;
@@ -148,14 +143,16 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
                             uint32_t lod_levels, const vm3dgs_options* opt, vm3dgs** out);
 
 /* One frame for n_views cameras (Sec. 4): visibility, page table, copies of
- * the misses (read by the GPU from the pinned store on the render stream,
- * before any copied Gaussian is used; prefetch copies on the copy stream),
- * splatting of the resident pages.  image_dev: device, caller-owned,
+ * the misses (read by the GPU from the pinned store, on the render stream
+ * before the preprocess; prefetch copies on the copy stream), splatting of
+ * the resident pages.  image_dev: device, caller-owned,
  * [n_views][img_h][img_w][3] float32, written on the render stream and
  * complete when that stream reaches the end of this call's work.  The frame
- * counter advances on every call.  out may be NULL.
+ * counter advances on every call.  out may be NULL.  The (tile, Gaussian)
+ * pairs of one call are counted in 32 bits (at most 2^32 - 1); the pair
+ * buffers grow as needed (a call that outgrows them splats again).
  * Errors: INVALID_ARG (NULL cams/image, n_views == 0), CAPACITY
- * (n_views > max_views), HIP, STATE. */
+ * (n_views > max_views, or the pair buffers cannot grow), HIP, STATE. */
 vm3dgs_status vm3dgs_frame(vm3dgs* ctx, const vm3dgs_camera* cams, uint32_t n_views, float* image_dev,
                            vm3dgs_frame_out* out);
 

@@ -248,10 +248,8 @@ void ensure_pairs(vm3dgs* c, uint64_t n) {
 }
 
 // the render half of a frame: preprocess .. blend for n_render Gaussians per view
-// dem: the frame's demand copies (run with the preprocess of the entries
-// resident before the frame), or null
 void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool, uint32_t n_render, uint32_t n_views,
-           float* image, vm3dgs_stats* st, const DemandCopies* dem) {
+           float* image, vm3dgs_stats* st) {
     const uint64_t n_total = (uint64_t)n_render * n_views;
     hipEvent_t* ev = c->ev;
     HIPCHK(hipEventRecord(ev[3], c->sr));
@@ -262,8 +260,6 @@ void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool,
     a.sigma3_tiles = (c->opt.flags & VM3DGS_FLAG_SIGMA3_TILES) ? 1 : 0;
     a.xy = c->d_xy; a.conic = c->d_conic; a.rgb = c->d_rgb; a.depth = c->d_depth; a.rect = c->d_rect;
     a.tiles = c->d_tiles; a.dkey = c->d_dkey[0]; a.dval = c->d_dval[0];
-    a.copies = dem;
-    a.ev_mid = dem ? ev[7] : nullptr;
     launch_preprocess(c->sr, a);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[4], c->sr));
@@ -680,13 +676,10 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
             HIPCHK(hipStreamWaitEvent(c->sr, c->ev_pf, 0));
             c->pf_pending = false;
         }
-        // demand copies: read by the GPU from the pinned store, in the same launch
-        // as the preprocess of the entries that were resident before this frame
-        DemandCopies dem{};
-        dem.cmds = c->d_copies; dem.count = n_dem; dem.max_cmd_bytes = max_cmd;
-        dem.host = c->h_store_dev; dem.host_bytes = (uint64_t)c->ps.store_bytes;
-        dem.pool = c->d_pool; dem.pool_bytes = pool_bytes;
-        dem.bytes_done = (unsigned long long*)(c->d_zero + ZB_BYTES); dem.err = c->d_cp_err;
+        // demand copies: read by the GPU from the pinned store, in order before the splat
+        launch_copy_pages(c->sr, c->d_copies, 0, n_dem, max_cmd, c->h_store_dev, (uint64_t)c->ps.store_bytes,
+                          c->d_pool, pool_bytes, (unsigned long long*)(c->d_zero + ZB_BYTES), c->d_cp_err);
+        HIPCHK(hipGetLastError());
         // prefetch copies: on the copy stream, after the page table; not awaited by this frame
         if (n_pf) {
             HIPCHK(hipEventRecord(c->ev_copy, c->sr));
@@ -710,7 +703,7 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         st.hits = k[C_HITS]; st.misses = k[C_MISSES]; st.evictions = k[C_EVICT]; st.missing = k[C_NMISSING];
         st.copies = n_dem; st.render_pages = k[C_NRL]; st.pool_pages_used = k[C_POOLUSED];
         c->pair_kind = 0;
-        splat(c, c->d_rlist, k[C_NRL], c->d_pool, n_render, n_views, image, &st, n_dem ? &dem : nullptr);
+        splat(c, c->d_rlist, k[C_NRL], c->d_pool, n_render, n_views, image, &st);
         // outputs of the frame: request order and missing list
         if (c->last_n_req)
             HIPCHK(hipMemcpyAsync(c->h_keys, c->d_keys + c->n_pg, sizeof(uint64_t) * c->last_n_req,
@@ -728,7 +721,7 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         if (!splat_pairs_ok(c, &st)) {
             // more pairs than the buffers held: the same render set again (its
             // pages are resident now) with the grown buffers
-            splat(c, c->d_rlist, k[C_NRL], c->d_pool, n_render, n_views, image, &st, nullptr);
+            splat(c, c->d_rlist, k[C_NRL], c->d_pool, n_render, n_views, image, &st);
             spin_wait(c);
             if (!splat_pairs_ok(c, &st)) throw std::length_error("pair buffers could not hold the frame's pairs");
         }
@@ -745,12 +738,9 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         }
         c->out_missing.assign(c->h_missing, c->h_missing + 2 * c->last_n_missing);
         st.ms_visibility = ms(ev[0], ev[1]);
-        // page table with the readback of its counters; the launch of the demand
-        // copies with the preprocess of the resident entries; the rest of the
-        // preprocess
-        st.ms_pagetable = ms(ev[1], ev[3]);
-        st.ms_copy = n_dem ? ms(ev[3], ev[7]) : 0.0f;
-        st.ms_preprocess = n_dem ? ms(ev[7], ev[4]) : ms(ev[3], ev[4]);
+        st.ms_pagetable = ms(ev[1], ev[2]);
+        st.ms_copy = ms(ev[2], ev[3]);
+        st.ms_preprocess = ms(ev[3], ev[4]);
         st.ms_sort = ms(ev[4], ev[5]);
         st.ms_blend = ms(ev[5], ev[6]);
         st.ms_total = ms(ev[0], ev[6]);
@@ -787,12 +777,11 @@ vm3dgs_status vm3dgs_render_full(vm3dgs* c, const vm3dgs_camera* cams, uint32_t 
         HIPCHK(hipMemcpyAsync(c->d_cams, c->h_cams, sizeof(CamK) * n_views, hipMemcpyHostToDevice, c->sr));
         begin_work(c);
         c->pair_kind = 1;
-        splat(c, c->d_rlist_full, (uint32_t)c->n_pg, c->d_full, (uint32_t)c->n_pg * (uint32_t)c->P, n_views, image, &st,
-              nullptr);
+        splat(c, c->d_rlist_full, (uint32_t)c->n_pg, c->d_full, (uint32_t)c->n_pg * (uint32_t)c->P, n_views, image, &st);
         HIPCHK(hipStreamSynchronize(c->sr));
         if (!splat_pairs_ok(c, &st)) {
             splat(c, c->d_rlist_full, (uint32_t)c->n_pg, c->d_full, (uint32_t)c->n_pg * (uint32_t)c->P, n_views,
-                  image, &st, nullptr);
+                  image, &st);
             HIPCHK(hipStreamSynchronize(c->sr));
             if (!splat_pairs_ok(c, &st)) throw std::length_error("pair buffers could not hold the frame's pairs");
         }

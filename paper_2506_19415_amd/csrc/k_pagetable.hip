@@ -16,7 +16,6 @@
 #include <algorithm>
 #include <stdexcept>
 
-#include "k_copy.h"
 #include "kcommon.h"
 #include "vm3dgs_impl.h"
 
@@ -140,7 +139,6 @@ __global__ __launch_bounds__(PT_NT) void k_pagetable_l1(const uint64_t* __restri
             a.sub_last_used[sl * vmk::SUBS] = a.frame;
             a.last_used[sl] = a.frame;
             a.slot_level[sl] = 0;
-            a.slot_req[sl] = 2;   // copied in this frame
             a.v2p[p] = sl * vmk::SUBS;
             CopyCmd c;
             c.host_off = (int64_t)p * a.P * a.bytes_g;
@@ -172,7 +170,7 @@ __global__ __launch_bounds__(PT_NT) void k_pagetable_l1(const uint64_t* __restri
             q.pool_off = (uint32_t)((e / vmk::SUBS) * a.P);
             q.count = (uint32_t)a.P;
             q.base = (n_rl + ex) * (uint32_t)a.P;
-            q.level = a.slot_req[e / vmk::SUBS] == 2 ? vm::RL_FRESH : 0u;
+            q.level = 0;
             a.rl[n_rl + ex] = q;
         }
         n_rl += tot;
@@ -391,7 +389,7 @@ __global__ __launch_bounds__(WAVE) void k_ptl_walk(PtWalk a) {
         a.sub_last_used[e] = a.frame;
         a.last_used[ts] = a.frame;
         a.v2p[p * a.L + l] = e;
-        a.req_sub[e] = 2;   // required, and copied in this frame
+        a.req_sub[e] = 1;
         a.slot_req[ts] = 1;
         if (lane == 0) {
             const int64_t Pl = a.P >> (3 * l);
@@ -419,7 +417,6 @@ __global__ __launch_bounds__(PT_NT) void k_ptl_render_list(const int8_t* __restr
                                                            int S, const int8_t* __restrict__ slot_level,
                                                            const int32_t* __restrict__ sub_vpage,
                                                            const uint8_t* __restrict__ slot_req,
-                                                           const uint8_t* __restrict__ req_sub,
                                                            RenderEntry* __restrict__ rl, uint32_t* __restrict__ counters) {
     __shared__ uint32_t scan_sh[PT_NT / WAVE];
     __shared__ int8_t s_lvl[RL_SEG];   // per page of the segment: level rendered, or -1
@@ -458,7 +455,7 @@ __global__ __launch_bounds__(PT_NT) void k_ptl_render_list(const int8_t* __restr
             q.pool_off = (uint32_t)((e / vmk::SUBS) * P + (e % vmk::SUBS) * (int)cnt);
             q.count = cnt;
             q.base = base;
-            q.level = (uint32_t)l | (req_sub[e] == 2 ? vm::RL_FRESH : 0u);
+            q.level = (uint32_t)l;
             rl[k++] = q;
             base += cnt;
         }
@@ -494,13 +491,51 @@ __global__ void k_ptl_count_misses(const uint32_t* __restrict__ total, uint32_t*
 
 
 // ------------------------------------------------------------------ page copies
-// one workgroup per 16 KB chunk of a copy command (copy_chunk, k_copy.h)
+// Miss streaming by the GPU itself: each workgroup reads one 16 KB chunk of a
+// copy command from the pinned host store (over PCIe, with many loads in
+// flight) and writes it into the pool; the commands stay on the device.
+// Offsets and sizes are multiples of 4 bytes (Gaussian records are 236 or 124
+// bytes); 16-byte accesses where the command allows.  A command that would
+// leave the store or the pool is skipped and flagged.
+constexpr int CP_NT = 256;
+constexpr uint32_t CP_CHUNK = 16384;
+
 __global__ __launch_bounds__(CP_NT) void k_copy_pages(const vm::CopyCmd* __restrict__ cmds, uint32_t first,
                                                       uint32_t chunks_per_cmd, const uint8_t* __restrict__ host,
                                                       uint64_t host_bytes, uint8_t* __restrict__ pool,
                                                       uint64_t pool_bytes, unsigned long long* __restrict__ bytes_done,
                                                       uint32_t* __restrict__ err) {
-    copy_chunk(cmds, first, chunks_per_cmd, blockIdx.x, host, host_bytes, pool, pool_bytes, bytes_done, err);
+    const uint32_t c = first + blockIdx.x / chunks_per_cmd;
+    const uint32_t ch = blockIdx.x % chunks_per_cmd;
+    const vm::CopyCmd cmd = cmds[c];
+    const uint64_t h0 = (uint64_t)cmd.host_off, p0 = (uint64_t)cmd.pool_off, nb = (uint64_t)cmd.bytes;
+    if (cmd.host_off < 0 || cmd.pool_off < 0 || cmd.bytes < 0 || h0 + nb > host_bytes || p0 + nb > pool_bytes) {
+        if (threadIdx.x == 0 && ch == 0) atomicOr(err, 1u);
+        return;
+    }
+    const uint64_t lo = (uint64_t)ch * CP_CHUNK;
+    if (lo >= nb) return;
+    const uint64_t hi = lo + CP_CHUNK < nb ? lo + CP_CHUNK : nb;
+    if (threadIdx.x == 0) atomicAdd(bytes_done, (unsigned long long)(hi - lo));
+    if (((h0 | p0 | lo | hi) & 15) == 0) {
+        const uint4* src = (const uint4*)(host + h0 + lo);
+        uint4* dst = (uint4*)(pool + p0 + lo);
+        const uint32_t n = (uint32_t)((hi - lo) / 16);
+        for (uint32_t i = threadIdx.x; i < n; i += CP_NT * 4) {
+            uint4 v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (i + k * CP_NT < n) v[k] = src[i + k * CP_NT];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (i + k * CP_NT < n) dst[i + k * CP_NT] = v[k];
+        }
+    } else {
+        const uint32_t* src = (const uint32_t*)(host + h0 + lo);
+        uint32_t* dst = (uint32_t*)(pool + p0 + lo);
+        const uint32_t n = (uint32_t)((hi - lo) / 4);
+        for (uint32_t i = threadIdx.x; i < n; i += CP_NT) dst[i] = src[i];
+    }
 }
 
 }  // namespace vmk
@@ -582,8 +617,7 @@ void launch_pagetable_lod(hipStream_t st, const PtArgs& a, SortWork& sw, const L
     hipLaunchKernelGGL(k_ptl_walk, dim3(1), dim3(WAVE), 0, st, pw);
     hipLaunchKernelGGL(k_ptl_render_list, dim3(1), dim3(PT_NT), 0, st, (const int8_t*)a.page_level,
                        (const int32_t*)a.v2p, n_pg, L, a.P, S, (const int8_t*)a.slot_level,
-                       (const int32_t*)a.sub_vpage, (const uint8_t*)a.slot_req, (const uint8_t*)a.req_sub, a.rl,
-                       a.counters);
+                       (const int32_t*)a.sub_vpage, (const uint8_t*)a.slot_req, a.rl, a.counters);
 }
 
 }  // namespace vm

@@ -18,7 +18,6 @@
 //                tile's pairs on its own (registers, no LDS, no barriers);
 //                per pixel front-to-back blending until transmittance would
 //                fall below 1e-4; the wave stops when all its pixels are done.
-#include "k_copy.h"
 #include "kcommon.h"
 #include "vm3dgs_impl.h"
 
@@ -65,12 +64,12 @@ struct PreArgs {
     int W, H, TX, TY;
     uint32_t n_render; uint64_t n_total;
     int sigma3_tiles;
-    int sel;   // 0: every entry; 1: entries resident before this frame; 2: entries copied in it
     float2* xy; float4* conic; float4* rgb; uint32_t* depth; uint2* rect; uint32_t* tiles;
     uint32_t* dkey; uint32_t* dval;
 };
 
-__device__ __forceinline__ void preprocess_one(const PreArgs& a, uint64_t f) {
+__global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
+    const uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= a.n_total) return;
     const uint32_t v = (uint32_t)(f / a.n_render);
     const uint32_t gi = (uint32_t)(f - (uint64_t)v * a.n_render);
@@ -81,7 +80,6 @@ __device__ __forceinline__ void preprocess_one(const PreArgs& a, uint64_t f) {
         if (a.rl[mid].base <= gi) lo = mid; else hi = mid - 1;
     }
     const RenderEntry e = a.rl[lo];
-    if (a.sel != 0 && ((e.level & vm::RL_FRESH) != 0) != (a.sel == 2)) return;   // the other launch's entries
     const uint32_t i = gi - e.base;
     Gauss g;
     load_gauss(a.pool + (size_t)e.pool_off * a.bytes_g, e.count, i, a.fmt, g);
@@ -216,28 +214,6 @@ __device__ __forceinline__ void preprocess_one(const PreArgs& a, uint64_t f) {
     a.tiles[f] = ok ? (uint32_t)((ix1 - ix0) * (iy1 - iy0)) : 0u;
     a.dkey[f] = ok ? __float_as_uint(t.z) : NONE32;
     a.dval[f] = (uint32_t)f;
-}
-
-__global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
-    preprocess_one(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
-}
-
-// The frame's demand copies and the preprocess of the entries that were
-// resident before it, in one launch: the first workgroups copy (latency-bound
-// reads over PCIe), the rest preprocess (HBM-bound), side by side on the CUs.
-struct CopyArgs {
-    const vm::CopyCmd* cmds; uint32_t count, per;
-    const uint8_t* host; uint64_t host_bytes; uint8_t* pool; uint64_t pool_bytes;
-    unsigned long long* bytes_done; uint32_t* err;
-};
-
-__global__ __launch_bounds__(256) void k_copy_preprocess(CopyArgs c, uint32_t n_copy_blocks, PreArgs a) {
-    static_assert(CP_NT == 256, "copy and preprocess workgroups have one size");
-    if (blockIdx.x < n_copy_blocks) {
-        copy_chunk(c.cmds, 0, c.per, blockIdx.x, c.host, c.host_bytes, c.pool, c.pool_bytes, c.bytes_done, c.err);
-        return;
-    }
-    preprocess_one(a, (uint64_t)(blockIdx.x - n_copy_blocks) * blockDim.x + threadIdx.x);
 }
 
 // Pair emission balanced over pairs: workgroup b writes pairs
@@ -510,28 +486,10 @@ void launch_preprocess(hipStream_t st, const SplatArgs& s) {
     a.cams = s.cams; a.W = s.W; a.H = s.H; a.TX = s.TX; a.TY = s.TY;
     a.n_render = s.n_render; a.n_total = (uint64_t)s.n_render * s.n_views;
     a.sigma3_tiles = s.sigma3_tiles;
-    a.sel = 0;
     a.xy = s.xy; a.conic = s.conic; a.rgb = s.rgb; a.depth = s.depth; a.rect = s.rect; a.tiles = s.tiles;
     a.dkey = s.dkey; a.dval = s.dval;
-    const bool work = a.n_total != 0 && s.n_rl != 0;
-    if (!s.copies || s.copies->count == 0) {
-        if (work) hipLaunchKernelGGL(k_preprocess, dim3(nblk(a.n_total, 256)), dim3(256), 0, st, a);
-        return;
-    }
-    // copies with the preprocess of the entries resident before the frame,
-    // then the preprocess of the copied entries
-    const vm::DemandCopies& d = *s.copies;
-    CopyArgs c;
-    c.cmds = d.cmds; c.count = d.count; c.per = (uint32_t)((d.max_cmd_bytes + CP_CHUNK - 1) / CP_CHUNK);
-    c.host = d.host; c.host_bytes = d.host_bytes; c.pool = d.pool; c.pool_bytes = d.pool_bytes;
-    c.bytes_done = d.bytes_done; c.err = d.err;
-    const uint32_t n_copy_blocks = c.count * c.per;
-    a.sel = 1;
-    hipLaunchKernelGGL(k_copy_preprocess, dim3(n_copy_blocks + (work ? nblk(a.n_total, 256) : 0u)), dim3(256), 0, st,
-                       c, n_copy_blocks, a);
-    if (s.ev_mid) (void)hipEventRecord(s.ev_mid, st);
-    a.sel = 2;
-    if (work) hipLaunchKernelGGL(k_preprocess, dim3(nblk(a.n_total, 256)), dim3(256), 0, st, a);
+    if (a.n_total == 0 || s.n_rl == 0) return;
+    hipLaunchKernelGGL(k_preprocess, dim3(nblk(a.n_total, 256)), dim3(256), 0, st, a);
 }
 
 void launch_emit(hipStream_t st, const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles,

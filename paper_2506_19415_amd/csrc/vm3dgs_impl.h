@@ -98,9 +98,8 @@ struct RenderEntry {   // one resident requested (sub-)page in render order
     uint32_t pool_off;  // first Gaussian of the block in the pool (Gaussian units)
     uint32_t count;     // Gaussians in the block
     uint32_t base;      // first render index
-    uint32_t level;     // LOD level; RL_FRESH set when the block is copied in this frame
+    uint32_t level;
 };
-constexpr uint32_t RL_FRESH = 1u << 31;
 
 struct CopyCmd {
     int64_t host_off, pool_off, bytes;
@@ -145,12 +144,6 @@ struct LodWork {
 };
 void launch_pagetable_lod(hipStream_t st, const PtArgs& a, SortWork& sw, const LodWork& w);
 
-// the demand copies of a frame, run with the preprocess (launch_preprocess)
-struct DemandCopies {
-    const CopyCmd* cmds; uint32_t count; uint64_t max_cmd_bytes;
-    const uint8_t* host; uint64_t host_bytes; uint8_t* pool; uint64_t pool_bytes;
-    unsigned long long* bytes_done; uint32_t* err;
-};
 struct SplatArgs {
     const RenderEntry* rl; int n_rl;
     const uint8_t* pool; int P; int fmt;
@@ -158,8 +151,6 @@ struct SplatArgs {
     int W, H, TX, TY;
     uint32_t n_render;  // per view
     int sigma3_tiles;   // 1: 3-sigma tile rectangles only (no support box)
-    const DemandCopies* copies;   // or null
-    hipEvent_t ev_mid;            // recorded after the copies (with the resident entries), or null
     float2* xy; float4* conic; float4* rgb; uint32_t* depth; uint2* rect; uint32_t* tiles;
     uint32_t* dkey; uint32_t* dval;
 };
