@@ -227,7 +227,9 @@ void vm3dgs_destroy(vm3dgs* ctx);
  * [dims[l+1]]; vm3dgs_mlp_n_params gives the total.
  * The network owns its device memory; calls are ordered on its stream
  * (stream = NULL: its own); pointers named _dev are device memory the caller
- * owns, and results written there are ready on that stream. */
+ * owns, and results written there are ready on that stream.  Inputs written
+ * on another stream must be complete before a call, and must stay valid
+ * until the network's stream has passed it (vm3dgs_mlp_sync). */
 typedef struct vm3dgs_mlp vm3dgs_mlp;
 
 /* dims[n_layers + 1], 1 <= n_layers <= 8, widths 1..65536; max_batch rows

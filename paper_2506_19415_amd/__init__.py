@@ -321,7 +321,12 @@ class Mlp:
 
     def __init__(self, dims, max_batch, stream=None):
         import torch
-        if stream is None:   # torch's current stream: inputs written by torch are ordered before the network
+        if stream is None:
+            # torch's current stream when it is a stream of its own; its default
+            # stream has the handle 0, which the library reads as "a stream of
+            # the network's own", so the calls below also order the two streams
+            # on the host: torch's work before a call, the network's work before
+            # the call returns (inputs may be torch temporaries)
             stream = torch.cuda.current_stream().cuda_stream
         self.dims = [int(d) for d in dims]
         arr = (C.c_uint32 * len(self.dims))(*self.dims)
@@ -352,6 +357,7 @@ class Mlp:
         import torch
         x = x.contiguous()
         z = torch.empty((x.shape[0], self.dims[-1]), dtype=torch.float32, device=x.device)
+        torch.cuda.current_stream().synchronize()
         self._check(lib().vm3dgs_mlp_forward(self.h, x.data_ptr(), x.shape[0], z.data_ptr()))
         self.sync()
         return z
@@ -361,14 +367,19 @@ class Mlp:
         x, y = x.contiguous(), y.contiguous()
         g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
         loss = C.c_float()
+        torch.cuda.current_stream().synchronize()
         self._check(lib().vm3dgs_mlp_gradient(self.h, x.data_ptr(), y.data_ptr(), x.shape[0], g.data_ptr(),
                                               C.byref(loss)))
+        self.sync()
         return g, loss.value
 
     def train_step(self, x, y, lr, want_loss=True):
+        import torch
         loss = C.c_float()
+        torch.cuda.current_stream().synchronize()
         self._check(lib().vm3dgs_mlp_train_step(self.h, x.data_ptr(), y.data_ptr(), x.shape[0], float(lr),
                                                 C.byref(loss) if want_loss else None))
+        self.sync()
         return loss.value if want_loss else None
 
     def sync(self):
