@@ -101,3 +101,27 @@ def test_training_lowers_the_loss():
         last = loss
     assert last < 0.5 * first, (first, last)
     net.close()
+
+
+def test_training_is_reproducible():
+    """Two trainings from the same weights on the same minibatches (drawn on
+    the device by torch indexing, as the training driver does) end with the
+    same weights bit for bit: the network never reads a batch before torch
+    has written it."""
+    import torch
+    import paper_2506_19415_amd as pkg
+    from paper_2506_19415_amd import prefetch as pf
+    dims = [92, 128, 128, 512]
+    p0 = _params(dims, 7)
+    rng = np.random.default_rng(8)
+    X = rng.random((1500, dims[0])).astype(np.float32)
+    Y = (rng.random((1500, dims[-1])) < 0.05).astype(np.float32)
+    out = []
+    for _ in range(2):
+        net = pkg.Mlp(dims, max_batch=256)
+        net.set_params(p0)
+        pf.train(net, X, Y, steps=200, batch=256, lr=1e-3)
+        out.append(net.get_state()[0])
+        net.close()
+    torch.cuda.synchronize()
+    assert np.array_equal(out[0], out[1])
