@@ -261,11 +261,24 @@ class Renderer:
         self.h = vm3dgs_create(scene, page_size, pool_pages, lod_levels, o)
         self.image = torch.empty((max_views, self.H, self.W, 3), dtype=torch.float32, device="cuda")
 
+    # The library renders on streams of its own and returns once the image is
+    # complete; before it overwrites the image, torch's pending work (which
+    # may still read the previous image) is waited for (a query first: an idle
+    # stream costs no wait).
+    @staticmethod
+    def _torch_idle():
+        import torch
+        s = torch.cuda.current_stream()
+        if not s.query():
+            s.synchronize()
+
     def frame(self, cams):
+        self._torch_idle()
         out = vm3dgs_frame(self.h, cams, self.image.data_ptr())
         return self.image[:len(cams)], out
 
     def render_full(self, cams):
+        self._torch_idle()
         st = vm3dgs_render_full(self.h, cams, self.image.data_ptr())
         return self.image[:len(cams)], st
 
