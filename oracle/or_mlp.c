@@ -2,7 +2,7 @@
  *
  * A multilayer perceptron with ReLU hidden layers and one logit per page
  * cluster, trained with the mean binary cross-entropy of the logits and Adam.
- * The method's own visibility pass stays the judge: the network only adds
+ * The method's own visibility pass alone decides what renders: the network only adds
  * lowest-priority prefetch requests (the "prefetching" the paper leaves to
  * future work, Sec. 6).  Everything here is plain double-precision loops.
  *

@@ -1,7 +1,7 @@
 // Learned prefetch on the device: the residency features, the proposals from
 // the network's logits, and the third page-table stage that serves them into
 // physical pages idle for two frames.  Prefetching is the paper's future work
-// (Sec. 6); the visibility pass stays the judge of what a frame renders.
+// (Sec. 6); the visibility pass alone decides what a frame renders.
 //
 //  k_pf_hist     resident fraction of each of H equal page-id ranges, into
 //                every view's feature row (after the 28 pose floats).
