@@ -308,6 +308,29 @@ def test_large_one_level_table(clusters):
     r.close()
 
 
+@pytest.mark.parametrize("S", [8192, 3000])
+def test_one_level_table_at_its_limit(clusters, S):
+    """The single-workgroup page table at its size limit: 8,192 pages of 4,
+    8,192 physical pages (or 3,000, with evictions and missing pages), and
+    more than 4,096 requests, so that the requests and the candidates each
+    fill the 8,192-key sort in LDS.  Bit-exact like the smaller tables."""
+    sc, _ = clusters
+    osc = oracle.OracleScene(sc, 4, 1, 0.5, 2.0)
+    cams = synth.orbit()
+    r = _renderer(sc, 4, S, (320, 240), (160, 120), 0.5)
+    assert int(r.get("info", np.int64)[0]) == 8192
+    ovm = oracle.OracleVM(osc, S, (320, 240), (160, 120))
+    most = 0
+    for k in range(4):
+        print(f"table at its limit S={S} frame {k}", flush=True)
+        _, out = r.frame([cams[k]])
+        ovm.frame([cams[k]])
+        compare_frame(r, ovm, out, 1, tag=f"limit S={S} {k}")
+        most = max(most, out.n_requests)
+    assert most > 4096, most
+    r.close()
+
+
 def test_adaptive_lod_thresholds(city):
     """Thresholds that follow memory use: the radius each frame used, and
     every intermediate, equal the oracle's along a path that first overloads
