@@ -145,6 +145,25 @@ def scene_clusters(seed: int = 0, n_clusters: int = 8, per_cluster: int = 4096,
     return _pack(means, scales, quats, opacity, sh, bounds=b)
 
 
+def scene_ties(seed: int = 0, copies: int = 4, per_cluster: int = 1024) -> Scene:
+    """The cluster scene with every mean shared by ``copies`` consecutive
+    Gaussians, whose other attributes are drawn for each: exact depth ties in
+    every view (8 * per_cluster * copies Gaussians).
+
+    Draw order: the cluster scene's (seed), then log-scales, quaternions,
+    opacity and SH of all copies (seed + 1).
+    """
+    base = scene_clusters(seed, per_cluster=per_cluster)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    means = np.repeat(base.means, copies, axis=0)
+    n = means.shape[0]
+    scales = np.exp(rng.normal(-3.0, 0.5, size=(n, 3)))
+    quats = _random_quats(rng, n)
+    opacity = _sigmoid(rng.normal(0.0, 1.0, size=n))
+    sh = _sh(rng, n)
+    return _pack(means, scales, quats, opacity, sh, bounds=base.bounds)
+
+
 def orbit(n_frames: int = 8, radius: float = 25.0, width: int = 320, height: int = 240,
           fov_x_deg: float = 60.0, height_z: float = 0.0):
     """Circle of ``radius`` in the z = 0 plane looking at the origin, angle 2 pi k / n."""

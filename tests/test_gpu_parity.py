@@ -111,6 +111,28 @@ def test_clusters_all_frames(clusters):
     r.close()
 
 
+def test_depth_ties():
+    """Four Gaussians at every mean: exact depth ties in every tile, broken by
+    Gaussian index on both sides (pairs bit-exact), on VM frames and on the
+    full-scene render."""
+    sc = synth.scene_ties(0)
+    osc = oracle.OracleScene(sc, 256, 1, 0.5, 2.0)
+    cams = synth.orbit()
+    r = _renderer(sc, 256, 64, (320, 240), (80, 60), 0.5, full_scene=True)
+    ovm = oracle.OracleVM(osc, 64, (320, 240), (80, 60))
+    for k in range(4):
+        print(f"depth ties frame {k}", flush=True)
+        _, out = r.frame([cams[k]])
+        ovm.frame([cams[k]])
+        compare_frame(r, ovm, out, 1, tag=f"ties {k}")
+    r.render_full([cams[5]])
+    ovm.render_full([cams[5]])
+    compare_splat(r, ovm, 1, tag="ties full")
+    keys = ovm.get("keys")
+    assert np.count_nonzero(keys[1:] == keys[:-1]) > 1000   # tied (tile, depth) pairs
+    r.close()
+
+
 def test_two_views_ragged_image(clusters):
     """Two views per call, an image that is not a multiple of the tile size
     and an ID buffer that does not divide it."""

@@ -170,6 +170,24 @@ def test_tile_lists_brute_force(cluster_frame):
         assert np.all((keys[s:e] >> np.uint64(32)) == t)
 
 
+def test_depth_ties_broken_by_gaussian_index():
+    """Four Gaussians at every mean give exact depth ties; every tile list
+    holds its Gaussians by depth, then by index (brute force per tile)."""
+    sc = synth.scene_ties(0, copies=4, per_cluster=256)
+    vm = render(sc, synth.orbit()[0], 320, 240, page_size=256)
+    pf = vm.get("pp_float").reshape(-1, 11)
+    pi = vm.get("pp_int").reshape(-1, 6)
+    keys, vals = vm.get("keys"), vm.get("vals")
+    ranges = vm.get("ranges").reshape(-1, 2)
+    depth_bits = pf[:, 2].view(np.uint32)
+    assert np.count_nonzero(keys[1:] == keys[:-1]) > 1000
+    for t in range(vm.TX * vm.TY):
+        tx, ty = t % vm.TX, t // vm.TX
+        cover = np.nonzero((pi[:, 0] == 0) & (pi[:, 1] <= tx) & (tx < pi[:, 3]) & (pi[:, 2] <= ty) & (ty < pi[:, 4]))[0]
+        s, e = ranges[t]
+        assert np.array_equal(vals[s:e], cover[np.lexsort((cover, depth_bits[cover]))])
+
+
 def needle_scene(seed=3, n=3000):
     """Anisotropic Gaussians (axis ratios up to 500), random orientations and
     opacities, in front of the identity camera: footprints from sub-pixel
