@@ -133,6 +133,37 @@ def test_depth_ties():
     r.close()
 
 
+def test_gaussians_covering_every_tile(clusters):
+    """Three Gaussians of 12 m scale at the centre of the orbit: each covers
+    all 1,200 tiles of a 640x480 image, so its run of pairs crosses several
+    emission blocks of 1,024 pairs, and each meets every pixel."""
+    sc0, _ = clusters
+    rng = np.random.default_rng(7)
+    extra = np.array([[0, 0, 0], [1, -1, 0.5], [-1, 1, -0.5]], np.float32)
+    k = len(extra)
+    sc = synth.Scene(np.concatenate([sc0.means, extra]),
+                     np.concatenate([sc0.scales, np.full((k, 3), 12.0, np.float32)]),
+                     np.concatenate([sc0.quats, np.tile(np.array([[1, 0, 0, 0]], np.float32), (k, 1))]),
+                     np.concatenate([sc0.opacity, np.full(k, 0.3, np.float32)]),
+                     np.concatenate([sc0.sh, rng.normal(0, 0.3, (k, 16, 3)).astype(np.float32)]))
+    osc = oracle.OracleScene(sc, 256, 1, 0.5, 2.0)
+    cams = synth.orbit(8, 25.0, 640, 480)
+    r = _renderer(sc, 256, 64, (640, 480), (160, 120), 0.5, full_scene=True)
+    ovm = oracle.OracleVM(osc, 64, (640, 480), (160, 120))
+    for f in range(3):
+        print(f"covering Gaussians frame {f}", flush=True)
+        _, out = r.frame([cams[f]])
+        ovm.frame([cams[f]])
+        compare_frame(r, ovm, out, 1, tag=f"covering {f}")
+        pi = ovm.get("pp_int").reshape(-1, 6)
+        tiles = (pi[:, 3] - pi[:, 1]) * (pi[:, 4] - pi[:, 2])
+        assert np.count_nonzero(tiles[pi[:, 0] == 0] == 1200) == k
+    r.render_full([cams[4]])
+    ovm.render_full([cams[4]])
+    compare_splat(r, ovm, 1, tag="covering full")
+    r.close()
+
+
 def test_two_views_ragged_image(clusters):
     """Two views per call, an image that is not a multiple of the tile size
     and an ID buffer that does not divide it."""
