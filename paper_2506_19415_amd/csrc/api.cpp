@@ -83,6 +83,11 @@ struct vm3dgs {
     uint64_t* d_status = nullptr; size_t status_words = 0;
     SortWork sw;
     uint32_t* d_total = nullptr; uint32_t* h_total = nullptr;
+    // device addresses of the pinned host buffers that readbacks write, and
+    // the readbacks queued since the last wait
+    void* hd_total = nullptr; void* hd_ctr = nullptr; void* hd_keys = nullptr; void* hd_lvl = nullptr;
+    void* hd_missing = nullptr;
+    ReadSegs rb;
     uint2* d_bstats = nullptr; uint2* h_bstats = nullptr;
     int frame = 0;
     bool multi = false;   // multi-kernel page table (several levels or a large table)
@@ -216,7 +221,31 @@ void ensure_status(vm3dgs* c) {
 // Wait, inside a frame, for the render stream to reach this point: a spin on
 // an event (the frame's readbacks are a few bytes and the host has nothing
 // else to do; a sleeping wait adds its wake-up time to every frame).
+// device address of pinned host memory
+void* host_dev(void* h) {
+    void* d = nullptr;
+    HIPCHK(hipHostGetDevicePointer(&d, h, 0));
+    return d;
+}
+
+// queue a readback of bytes at src into pinned host memory (dst: its device
+// address); queued readbacks run as one launch at the next flush
+void rb_add(vm3dgs* c, const void* src, void* dst, uint64_t bytes) {
+    if (bytes == 0) return;
+    if (c->rb.n >= ReadSegs::kMax || bytes > 0xffffffffull) throw std::length_error("readback segments exhausted");
+    c->rb.seg[c->rb.n++] = ReadSeg{src, dst, (uint32_t)bytes};
+}
+
+void rb_flush(vm3dgs* c) {
+    if (c->rb.n == 0) return;
+    launch_readback(c->sr, c->rb);
+    c->rb.n = 0;
+    HIPCHK(hipGetLastError());
+}
+
+// waits for the render stream (queued readbacks first)
 void spin_wait(vm3dgs* c) {
+    rb_flush(c);
     HIPCHK(hipEventRecord(c->ev_sync, c->sr));
     hipError_t e;
     while ((e = hipEventQuery(c->ev_sync)) == hipErrorNotReady) {
@@ -228,6 +257,7 @@ void spin_wait(vm3dgs* c) {
 void begin_work(vm3dgs* c) {
     launch_fill_u32(c->sr, c->d_zero, ZB_WORDS, 0u);
     c->sw.reset();
+    c->rb.n = 0;
 }
 
 
@@ -294,8 +324,8 @@ void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool,
         st->blend_evals = e;
         st->blend_alphas = al;
     }
-    HIPCHK(hipMemcpyAsync(c->h_total, c->d_total, sizeof(uint32_t), hipMemcpyDeviceToHost, c->sr));
-    HIPCHK(hipMemcpyAsync(c->h_total + 1, c->d_zero + ZB_ERR, sizeof(uint32_t), hipMemcpyDeviceToHost, c->sr));
+    rb_add(c, c->d_total, c->hd_total, sizeof(uint32_t));
+    rb_add(c, c->d_zero + ZB_ERR, (uint32_t*)c->hd_total + 1, sizeof(uint32_t));
     c->last_views = n_views; c->last_n_render = n_render;
     c->last_pbuf = pb; c->last_dbuf = db;
     if (st) st->render_gaussians = n_total;
@@ -556,6 +586,9 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         dalloc(&c->d_tile_order, (size_t)c->TX * c->TY * V);
         dalloc(&c->d_bstats, (size_t)c->TX * c->TY * V); halloc(&c->h_bstats, (size_t)c->TX * c->TY * V);
         dalloc(&c->d_total, 4); halloc(&c->h_total, 8);  // [0] pairs, [1] look-back error, [2..3] bytes, [4] copy error
+        c->hd_total = host_dev(c->h_total); c->hd_ctr = host_dev(c->h_ctr); c->hd_keys = host_dev(c->h_keys);
+        c->hd_missing = host_dev(c->h_missing);
+        if (c->h_lvl) c->hd_lvl = host_dev(c->h_lvl);
         c->cap_pairs = 0;
         ensure_pairs(c, o.pair_capacity ? o.pair_capacity : std::max<uint64_t>(R * 4, 1u << 22));
             ensure_status(c);
@@ -601,6 +634,7 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         HIPCHK(hipMemcpyAsync(c->d_cams, c->h_cams, sizeof(CamK) * n_views, hipMemcpyHostToDevice, c->sr));
         if (c->pf_on) push_poses(c, cams, n_views);
         c->sw.reset();
+        c->rb.n = 0;
         VisArgs va{};
         va.spheres = c->d_sph; va.n_pg = c->n_pg; va.cell_lo = c->d_clo; va.cell_hi = c->d_chi; va.nc = c->ps.nc();
         va.link_start = c->d_ls; va.link_dst = c->d_ld; va.use_links = (c->opt.flags & VM3DGS_FLAG_LINKS) ? 1 : 0;
@@ -662,7 +696,7 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         HIPCHK(hipGetLastError());
         HIPCHK(hipEventRecord(ev[2], c->sr));
         // the counters: how many copies, render entries and Gaussians this frame has
-        HIPCHK(hipMemcpyAsync(c->h_ctr, c->d_ctr, sizeof(uint32_t) * C_NCOUNTERS, hipMemcpyDeviceToHost, c->sr));
+        rb_add(c, c->d_ctr, c->hd_ctr, sizeof(uint32_t) * C_NCOUNTERS);
         spin_wait(c);
         const uint32_t* k = c->h_ctr;
         const uint32_t n_copy = k[C_NCOPY];
@@ -705,16 +739,11 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         c->pair_kind = 0;
         splat(c, c->d_rlist, k[C_NRL], c->d_pool, n_render, n_views, image, &st);
         // outputs of the frame: request order and missing list
-        if (c->last_n_req)
-            HIPCHK(hipMemcpyAsync(c->h_keys, c->d_keys + c->n_pg, sizeof(uint64_t) * c->last_n_req,
-                                  hipMemcpyDeviceToHost, c->sr));
-        if (c->last_n_req && c->L > 1)
-            HIPCHK(hipMemcpyAsync(c->h_lvl, c->d_lvl_out, c->last_n_req, hipMemcpyDeviceToHost, c->sr));
-        if (c->last_n_missing)
-            HIPCHK(hipMemcpyAsync(c->h_missing, c->d_missing, sizeof(int32_t) * 2 * c->last_n_missing,
-                                  hipMemcpyDeviceToHost, c->sr));
-        HIPCHK(hipMemcpyAsync(c->h_total + 2, c->d_zero + ZB_BYTES, 8, hipMemcpyDeviceToHost, c->sr));
-        HIPCHK(hipMemcpyAsync(c->h_total + 4, c->d_cp_err, 4, hipMemcpyDeviceToHost, c->sr));
+        rb_add(c, c->d_keys + c->n_pg, c->hd_keys, sizeof(uint64_t) * c->last_n_req);
+        if (c->L > 1) rb_add(c, c->d_lvl_out, c->hd_lvl, c->last_n_req);
+        rb_add(c, c->d_missing, c->hd_missing, sizeof(int32_t) * 2 * c->last_n_missing);
+        rb_add(c, c->d_zero + ZB_BYTES, (uint32_t*)c->hd_total + 2, 8);
+        rb_add(c, c->d_cp_err, (uint32_t*)c->hd_total + 4, 4);
         spin_wait(c);
         if (c->h_total[4]) throw HipError{hipErrorInvalidValue, "a page copy command left the store or the pool",
                                           __LINE__};
@@ -778,10 +807,12 @@ vm3dgs_status vm3dgs_render_full(vm3dgs* c, const vm3dgs_camera* cams, uint32_t 
         begin_work(c);
         c->pair_kind = 1;
         splat(c, c->d_rlist_full, (uint32_t)c->n_pg, c->d_full, (uint32_t)c->n_pg * (uint32_t)c->P, n_views, image, &st);
+        rb_flush(c);
         HIPCHK(hipStreamSynchronize(c->sr));
         if (!splat_pairs_ok(c, &st)) {
             splat(c, c->d_rlist_full, (uint32_t)c->n_pg, c->d_full, (uint32_t)c->n_pg * (uint32_t)c->P, n_views,
                   image, &st);
+            rb_flush(c);
             HIPCHK(hipStreamSynchronize(c->sr));
             if (!splat_pairs_ok(c, &st)) throw std::length_error("pair buffers could not hold the frame's pairs");
         }

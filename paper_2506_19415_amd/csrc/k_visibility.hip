@@ -279,6 +279,28 @@ __global__ void k_fill_multi(vm::FillSegs f) {
     }
 }
 
+// small device-to-host readbacks in one launch, instead of one copy command
+// each: 4-byte words where source, destination and size allow, else bytes;
+// the system-scope fence makes the writes visible to the host once the
+// stream has passed the kernel
+__global__ __launch_bounds__(256) void k_readback(vm::ReadSegs r) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int s = 0; s < r.n; ++s) {
+        const vm::ReadSeg g = r.seg[s];
+        if ((((uintptr_t)g.src | (uintptr_t)g.dst | (uintptr_t)g.bytes) & 3u) == 0) {
+            const uint32_t* a = (const uint32_t*)g.src;
+            uint32_t* b = (uint32_t*)g.dst;
+            for (uint32_t i = i0; i < g.bytes / 4; i += stride) b[i] = a[i];
+        } else {
+            const uint8_t* a = (const uint8_t*)g.src;
+            uint8_t* b = (uint8_t*)g.dst;
+            for (uint32_t i = i0; i < g.bytes; i += stride) b[i] = a[i];
+        }
+    }
+    __threadfence_system();
+}
+
 }  // namespace vmk
 
 namespace vm {
@@ -299,6 +321,12 @@ void launch_fill_multi(hipStream_t st, const FillSegs& f) {
     for (int s = 0; s < f.n; ++s) mx = std::max(mx, f.seg[s].n);
     if (mx) hipLaunchKernelGGL(k_fill_multi, dim3((unsigned)std::min<uint64_t>(nblk(mx, 256), 1024)), dim3(256), 0, st,
                                f);
+}
+
+void launch_readback(hipStream_t st, const ReadSegs& r) {
+    uint32_t mx = 0;
+    for (int s = 0; s < r.n; ++s) mx = std::max(mx, r.seg[s].bytes);
+    if (mx) hipLaunchKernelGGL(k_readback, dim3(std::min(nblk(mx / 4 + 1, 256), 64u)), dim3(256), 0, st, r);
 }
 
 void visibility_clears(const VisArgs& a, FillSegs& f) {

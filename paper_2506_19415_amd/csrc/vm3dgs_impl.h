@@ -175,6 +175,17 @@ struct FillSegs {
     int n = 0;
 };
 void launch_fill_multi(hipStream_t st, const FillSegs& f);
+// device-to-host readbacks at one point of a stream, in one launch: the GPU
+// writes each segment into mapped pinned host memory (at most kMax)
+struct ReadSeg {
+    const void* src; void* dst; uint32_t bytes;   // dst: device address of pinned host memory
+};
+struct ReadSegs {
+    static constexpr int kMax = 8;
+    ReadSeg seg[kMax];
+    int n = 0;
+};
+void launch_readback(hipStream_t st, const ReadSegs& r);
 void visibility_clears(const VisArgs& a, FillSegs& f);
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v);
 void launch_fill_u64(hipStream_t st, unsigned long long* p, uint64_t n, unsigned long long v);
