@@ -1,16 +1,23 @@
 // api.cpp -- the C ABI of include/vm3dgs.h: context, frame scheduler, copies.
 //
 // One frame (Sec. 4 of the paper):
-//   render stream: camera upload -> visibility kernels -> page table kernel
-//   host:          read back the counters and the copy list (the one place the
-//                  host waits on the device before splatting, like the paper's
-//                  fence before its page-table update, Sec. 5.1.3)
-//   copy stream:   hipMemcpyAsync of every missed page (contiguous runs
-//                  merged) from the pinned page-major store into its pool slot
-//   render stream: waits for the copies, then preprocess -> depth sort ->
-//                  scan of tile counts (pair total read back to size the
-//                  pair buffers) -> pair emission -> tile sort -> ranges ->
-//                  blend into the caller's image
+//   render stream: camera upload -> one launch of the frame's clears ->
+//                  visibility kernels -> page table kernel(s) -> readback of
+//                  the counters
+//   host:          waits for the counters (the one place the host waits on
+//                  the device before splatting, like the paper's fence
+//                  before its page-table update, Sec. 5.1.3); the copy list
+//                  stays on the device
+//   render stream: the GPU reads the missed pages from the pinned page-major
+//                  store into their pool slots (k_copy_pages), then
+//                  preprocess -> depth sort -> scan of tile counts -> pair
+//                  emission -> tile sort -> ranges -> blend into the
+//                  caller's image, with the pair count kept on the device
+//                  and grids bounded by the last frame's count
+//   copy stream:   prefetch copies, which the next frame waits for
+//   end:           one readback launch (pair count, request keys and levels,
+//                  missing list, flags); a frame with more pairs than its
+//                  bounds is splatted again with larger ones
 #include <hip/hip_runtime.h>
 #include <string.h>
 
