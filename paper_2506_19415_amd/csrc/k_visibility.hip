@@ -17,6 +17,10 @@
 //  k_links         a directly seen page pushes its depth to its linked pages
 //  k_requests      LOD level from the projected page radius, request keys
 //                  (class, depth, page)
+//
+// Also the frame's small utility launches: k_fill_multi (the clears at the
+// start of a frame, in one launch) and k_readback (the readbacks at a host
+// wait, written by the GPU into mapped pinned host memory, in one launch).
 #include <algorithm>
 #include <stdexcept>
 
