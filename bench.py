@@ -86,13 +86,13 @@ def psnr(a, b):
     return float("inf") if mse == 0.0 else 10.0 * math.log10(1.0 / mse)
 
 
-def cpu_baseline(sc, cams, budget_s=30.0):
+def cpu_baseline(sc, cams, P=1024, S=1465, budget_s=30.0):
     """The oracle (plain C, single thread) on a bounded sample: frames of the
     same path after one warm frame, until about budget_s seconds of frames."""
     import oracle
     t0 = time.time()
-    osc = oracle.OracleScene(sc, 1024, 1, TERRAIN_CELL_M, 2.0)
-    vm = oracle.OracleVM(osc, 1465, (1920, 1080), (240, 135))
+    osc = oracle.OracleScene(sc, P, 1, TERRAIN_CELL_M, 2.0)
+    vm = oracle.OracleVM(osc, S, (1920, 1080), (240, 135))
     build_s = time.time() - t0
     vm.frame([cams[0]])
     times = []
@@ -282,6 +282,10 @@ def main():
                          "LOD levels: fp32, half-precision pages, or half pages with eight views and the "
                          "learned prefetch")
     ap.add_argument("--city-n", type=int, default=50_000_000, help="Gaussians of the city workloads")
+    ap.add_argument("--page-size", type=int, default=1024,
+                    help="terrain6m: Gaussians per page (the page-size trend of the paper's Tab. 3)")
+    ap.add_argument("--pool-frac", type=float, default=1.0,
+                    help="terrain6m: pool size as a fraction of 1.5M Gaussians (the buffer-size trend of Tab. 4)")
     ap.add_argument("--train-frames", type=int, default=2000,
                     help="city50m_prefetch8: plain-pass frames of training data for the network")
     args = ap.parse_args()
@@ -312,7 +316,9 @@ def main():
     cams = synth.path_terrain(sc)
     log(f"scene {sc.n} Gaussians generated in {time.time() - t0:.1f} s")
     t0 = time.time()
-    r = pkg.Renderer(sc, 1024, 1465, img=(1920, 1080), idbuf=(240, 135), cell=TERRAIN_CELL_M, full_scene=True)
+    P = args.page_size
+    S = max(1, round(1465 * 1024 * args.pool_frac / P))
+    r = pkg.Renderer(sc, P, S, img=(1920, 1080), idbuf=(240, 135), cell=TERRAIN_CELL_M, full_scene=True)
     log(f"create {time.time() - t0:.1f} s")
     n_cam = len(cams)
     K, W = args.steps, args.warmup
@@ -399,7 +405,8 @@ def main():
     flops = statistics.mean([FLOP_EVAL * e + FLOP_ALPHA * a for e, a in zip(evals, alphas)])
     achieved = flops / (blend_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / ALU_PEAK_TFLOPS, "traffic": blend_traffic(), "kernel": "k_blend",
+                "frac": achieved / ALU_PEAK_TFLOPS,
+                "traffic": blend_traffic() if (P, S) == (1024, 1465) else None, "kernel": "k_blend",
                 "per_unit": f"{FLOP_EVAL} flop per pixel-Gaussian evaluation + {FLOP_ALPHA} per alpha evaluation",
                 "evals_per_launch": statistics.mean(evals), "alphas_per_launch": statistics.mean(alphas),
                 "launch_ms": blend_ms}
@@ -417,9 +424,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded terrain + buildings, 6M Gaussians)",
-        "config": {"workload": "terrain6m: 6M Gaussians, 1024/page, pool 1465 pages, 1920x1080, "
+        "config": {"workload": f"terrain6m: 6M Gaussians, {P}/page, pool {S} pages, 1920x1080, "
                                "ID buffer 240x135, 70 deg, 300-frame fly-through at 1.7 m",
-                   "page_size": 1024, "pool_pages": 1465, "image": [1920, 1080], "idbuf": [240, 135],
+                   "page_size": P, "pool_pages": S, "image": [1920, 1080], "idbuf": [240, 135],
                    "proxy_cell_m": TERRAIN_CELL_M},
         "fps_median_frame": 1000.0 / statistics.median(walls),
         "full_scene_fps": full_fps,
@@ -452,7 +459,7 @@ def main():
     del vm_imgs
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        res["cpu_baseline"] = cpu_baseline(sc, cams)
+        res["cpu_baseline"] = cpu_baseline(sc, cams, P, S)
     print(json.dumps(res), flush=True)
 
 
