@@ -86,13 +86,13 @@ def psnr(a, b):
     return float("inf") if mse == 0.0 else 10.0 * math.log10(1.0 / mse)
 
 
-def cpu_baseline(sc, cams, P=1024, S=1465, budget_s=30.0):
+def cpu_baseline(sc, cams, P=1024, S=1465, links=True, budget_s=30.0):
     """The oracle (plain C, single thread) on a bounded sample: frames of the
     same path after one warm frame, until about budget_s seconds of frames."""
     import oracle
     t0 = time.time()
     osc = oracle.OracleScene(sc, P, 1, TERRAIN_CELL_M, 2.0)
-    vm = oracle.OracleVM(osc, S, (1920, 1080), (240, 135))
+    vm = oracle.OracleVM(osc, S, (1920, 1080), (240, 135), use_links=links)
     build_s = time.time() - t0
     vm.frame([cams[0]])
     times = []
@@ -284,6 +284,8 @@ def main():
     ap.add_argument("--city-n", type=int, default=50_000_000, help="Gaussians of the city workloads")
     ap.add_argument("--page-size", type=int, default=1024,
                     help="terrain6m: Gaussians per page (the page-size trend of the paper's Tab. 3)")
+    ap.add_argument("--no-links", action="store_true",
+                    help="terrain6m: pages requested only where the ID buffer sees them (the links trend of Tab. 2)")
     ap.add_argument("--pool-frac", type=float, default=1.0,
                     help="terrain6m: pool size as a fraction of 1.5M Gaussians (the buffer-size trend of Tab. 4)")
     ap.add_argument("--train-frames", type=int, default=2000,
@@ -318,7 +320,9 @@ def main():
     t0 = time.time()
     P = args.page_size
     S = max(1, round(1465 * 1024 * args.pool_frac / P))
-    r = pkg.Renderer(sc, P, S, img=(1920, 1080), idbuf=(240, 135), cell=TERRAIN_CELL_M, full_scene=True)
+    r = pkg.Renderer(sc, P, S, img=(1920, 1080), idbuf=(240, 135), cell=TERRAIN_CELL_M, full_scene=True,
+                     links=not args.no_links)
+    links_flag = 0 if args.no_links else pkg.VM3DGS_FLAG_LINKS
     log(f"create {time.time() - t0:.1f} s")
     n_cam = len(cams)
     K, W = args.steps, args.warmup
@@ -344,7 +348,7 @@ def main():
     # the same cameras again with the blend's work counters on, keeping the
     # images for the PSNR: with no missing pages the render set, and so the
     # image and the blend's work, depend only on the camera
-    r.set_flags(pkg.VM3DGS_FLAG_LINKS | pkg.VM3DGS_FLAG_BLEND_STATS)
+    r.set_flags(links_flag | pkg.VM3DGS_FLAG_BLEND_STATS)
     vm_imgs = torch.empty((K, 1080, 1920, 3), dtype=torch.float32, device="cuda")
     evals, alphas = [], []
     missing_second = 0
@@ -354,7 +358,7 @@ def main():
         evals.append(out.stats.blend_evals)
         alphas.append(out.stats.blend_alphas)
         missing_second += out.stats.missing
-    r.set_flags(pkg.VM3DGS_FLAG_LINKS)
+    r.set_flags(links_flag)
     missing_timed = sum(s["missing"] for s in stats)
     if missing_timed or missing_second:
         log(f"warning: missing pages (timed {missing_timed}, second pass {missing_second}): the second pass's "
@@ -406,7 +410,8 @@ def main():
     achieved = flops / (blend_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / ALU_PEAK_TFLOPS,
-                "traffic": blend_traffic() if (P, S) == (1024, 1465) else None, "kernel": "k_blend",
+                "traffic": blend_traffic() if (P, S, args.no_links) == (1024, 1465, False) else None,
+                "kernel": "k_blend",
                 "per_unit": f"{FLOP_EVAL} flop per pixel-Gaussian evaluation + {FLOP_ALPHA} per alpha evaluation",
                 "evals_per_launch": statistics.mean(evals), "alphas_per_launch": statistics.mean(alphas),
                 "launch_ms": blend_ms}
@@ -425,8 +430,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded terrain + buildings, 6M Gaussians)",
         "config": {"workload": f"terrain6m: 6M Gaussians, {P}/page, pool {S} pages, 1920x1080, "
-                               "ID buffer 240x135, 70 deg, 300-frame fly-through at 1.7 m",
-                   "page_size": P, "pool_pages": S, "image": [1920, 1080], "idbuf": [240, 135],
+                               "ID buffer 240x135, 70 deg, 300-frame fly-through at 1.7 m"
+                               + ("" if not args.no_links else ", no links"),
+                   "page_size": P, "pool_pages": S, "links": not args.no_links, "image": [1920, 1080], "idbuf": [240, 135],
                    "proxy_cell_m": TERRAIN_CELL_M},
         "fps_median_frame": 1000.0 / statistics.median(walls),
         "full_scene_fps": full_fps,
@@ -459,7 +465,7 @@ def main():
     del vm_imgs
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        res["cpu_baseline"] = cpu_baseline(sc, cams, P, S)
+        res["cpu_baseline"] = cpu_baseline(sc, cams, P, S, not args.no_links)
     print(json.dumps(res), flush=True)
 
 
