@@ -284,6 +284,8 @@ def main():
     ap.add_argument("--city-n", type=int, default=50_000_000, help="Gaussians of the city workloads")
     ap.add_argument("--page-size", type=int, default=1024,
                     help="terrain6m: Gaussians per page (the page-size trend of the paper's Tab. 3)")
+    ap.add_argument("--lod-levels", type=int, default=1,
+                    help="terrain6m: LOD levels, with thresholds that follow memory use (Tab. 4 with LOD)")
     ap.add_argument("--no-links", action="store_true",
                     help="terrain6m: pages requested only where the ID buffer sees them (the links trend of Tab. 2)")
     ap.add_argument("--pool-frac", type=float, default=1.0,
@@ -320,9 +322,12 @@ def main():
     t0 = time.time()
     P = args.page_size
     S = max(1, round(1465 * 1024 * args.pool_frac / P))
+    L = args.lod_levels
     r = pkg.Renderer(sc, P, S, img=(1920, 1080), idbuf=(240, 135), cell=TERRAIN_CELL_M, full_scene=True,
-                     links=not args.no_links)
-    links_flag = 0 if args.no_links else pkg.VM3DGS_FLAG_LINKS
+                     links=not args.no_links, lod_levels=L)
+    links_flag = (0 if args.no_links else pkg.VM3DGS_FLAG_LINKS) | (pkg.VM3DGS_FLAG_ADAPTIVE_LOD if L > 1 else 0)
+    if L > 1:
+        r.set_flags(links_flag)
     log(f"create {time.time() - t0:.1f} s")
     n_cam = len(cams)
     K, W = args.steps, args.warmup
@@ -410,7 +415,7 @@ def main():
     achieved = flops / (blend_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / ALU_PEAK_TFLOPS,
-                "traffic": blend_traffic() if (P, S, args.no_links) == (1024, 1465, False) else None,
+                "traffic": blend_traffic() if (P, S, args.no_links, L) == (1024, 1465, False, 1) else None,
                 "kernel": "k_blend",
                 "per_unit": f"{FLOP_EVAL} flop per pixel-Gaussian evaluation + {FLOP_ALPHA} per alpha evaluation",
                 "evals_per_launch": statistics.mean(evals), "alphas_per_launch": statistics.mean(alphas),
@@ -431,8 +436,9 @@ def main():
         "data": "synthetic (seeded terrain + buildings, 6M Gaussians)",
         "config": {"workload": f"terrain6m: 6M Gaussians, {P}/page, pool {S} pages, 1920x1080, "
                                "ID buffer 240x135, 70 deg, 300-frame fly-through at 1.7 m"
-                               + ("" if not args.no_links else ", no links"),
-                   "page_size": P, "pool_pages": S, "links": not args.no_links, "image": [1920, 1080], "idbuf": [240, 135],
+                               + ("" if not args.no_links else ", no links")
+                               + ("" if L == 1 else f", {L} LOD levels, adaptive thresholds"),
+                   "page_size": P, "pool_pages": S, "links": not args.no_links, "lod_levels": L, "image": [1920, 1080], "idbuf": [240, 135],
                    "proxy_cell_m": TERRAIN_CELL_M},
         "fps_median_frame": 1000.0 / statistics.median(walls),
         "full_scene_fps": full_fps,
@@ -463,7 +469,7 @@ def main():
         del src, dst
     r.close()
     del vm_imgs
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and L == 1:
         log("cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(sc, cams, P, S, not args.no_links)
     print(json.dumps(res), flush=True)
