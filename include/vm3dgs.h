@@ -64,12 +64,14 @@ typedef struct {
  * term fails the 1/255 alpha test; the image is the same either way, with
  * fewer (tile, Gaussian) pairs. */
 #define VM3DGS_FLAG_SIGMA3_TILES 8u
-/* With several LOD levels, move the level-0 radius with memory use (Sec. 4.1):
- * up (coarser) when the frame's required physical pages exceed 95 % of the
- * pool or requests go missing, down towards lod_radius_px below 80 % while
- * coarse levels are in use; the step grows by 1.5 while the direction holds
- * and halves when it reverses (1/64 .. 1/2, starting at 1/8).  The radius a
- * frame used is in stats.lod_radius_px; the next frame uses the new one. */
+/* With several LOD levels, move the level-0 radius with memory use
+ * (Sec. 5.1.1): aim at 50-80 % of the pool required by the frame.  Above
+ * 80 %, or with requests left missing, the radius grows by 1 + step
+ * (coarser); under 50 % with coarse levels in use it shrinks by 1 + step
+ * (finer).  The step starts at 1/8 and changes by 1 % of itself after a
+ * move that repeats (x 1.01) or reverses (x 0.99) a move made at most 4
+ * frames earlier.  The radius a frame used is in stats.lod_radius_px; the
+ * next frame uses the new one. */
 #define VM3DGS_FLAG_ADAPTIVE_LOD 16u
 
 typedef struct {

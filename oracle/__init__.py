@@ -56,6 +56,11 @@ def lib():
         L.or_vm_get.restype = C.c_int64
         L.or_vm_get.argtypes = [C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64]
         L.or_merge_children.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
+        L.or_merge_children_d.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
+        L.or_lod_level.restype = C.c_int
+        L.or_lod_level.argtypes = [C.c_float, C.c_float, C.c_float, C.c_float, C.c_int]
+        L.or_lod_control_trace.argtypes = [C.c_int, C.c_int, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_void_p]
         for nm in ("or_vm_exp_n", "or_round_f16_n", "or_round_bf16_n"):
             getattr(L, nm).argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
         L.or_vm_pagetable.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
@@ -136,10 +141,38 @@ def round_bf16(x: float) -> float:
 
 
 def merge_children(rec: np.ndarray) -> np.ndarray:
+    """Stored (float32) parent record of the children rec [k][59]."""
     rec = np.ascontiguousarray(rec, dtype=np.float32)
     out = np.zeros(59, dtype=np.float32)
     lib().or_merge_children(rec.ctypes.data, rec.shape[0], out.ctypes.data)
     return out
+
+
+def merge_children_d(rec: np.ndarray) -> np.ndarray:
+    """Parent record of the children rec [k][59] in double, before rounding."""
+    rec = np.ascontiguousarray(rec, dtype=np.float32)
+    out = np.zeros(59, dtype=np.float64)
+    lib().or_merge_children_d(rec.ctypes.data, rec.shape[0], out.ctypes.data)
+    return out
+
+
+def lod_level(fy: float, radius: float, depth: float, tau: float, levels: int) -> int:
+    return int(lib().or_lod_level(float(fy), float(radius), float(depth), float(tau), int(levels)))
+
+
+def lod_control_trace(S: int, tau0: float, req_slots, n_missing, n_coarse):
+    """The memory-use controller over a sequence of frames from a fresh
+    state: (tau, step) after each frame, float32 arrays."""
+    rs = np.ascontiguousarray(req_slots, dtype=np.int32)
+    nm = np.ascontiguousarray(n_missing, dtype=np.int32)
+    nc = np.ascontiguousarray(n_coarse, dtype=np.int32)
+    n = rs.shape[0]
+    assert nm.shape[0] == n and nc.shape[0] == n
+    tau = np.zeros(n, np.float32)
+    step = np.zeros(n, np.float32)
+    lib().or_lod_control_trace(n, int(S), float(tau0), rs.ctypes.data, nm.ctypes.data, nc.ctypes.data,
+                               tau.ctypes.data, step.ctypes.data)
+    return tau, step
 
 
 _SCENE_DT = {"perm": np.int64, "attr0": np.float32, "attr1": np.float32, "attr2": np.float32,

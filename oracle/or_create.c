@@ -248,13 +248,19 @@ static void rot_to_quat(double R[3][3], double q[4])
 }
 
 /* Parent of k children (records c[0..k-1]) by opacity-weighted moment
- * matching: mu = sum w mu_i / W, Sigma = sum w (Sigma_i + d d^T) / W,
- * opacity = min(1, sum o_i), SH = sum w SH_i / W, w_i = o_i. */
-void or_merge_children(const float* c, int k, float* out)
+ * matching (the parent construction read for Sec. 3 "Level of Detail"):
+ * mu = sum w mu_i / W, Sigma = sum w (Sigma_i + d d^T) / W (the law of total
+ * covariance of the opacity-weighted mixture), opacity = min(1, sum o_i),
+ * SH = sum w SH_i / W, w_i = o_i.  Sigma is written back as scale = sqrt of
+ * its eigenvalues (descending) and the rotation of its eigenvectors as a
+ * unit quaternion with w >= 0.  The record is produced in double
+ * (or_merge_children_d) and stored rounded to float (or_merge_children).
+ * All-zero opacities give the all-zero padding parent. */
+void or_merge_children_d(const float* c, int k, double* out)
 {
     double W = 0.0, osum = 0.0;
     for (int i = 0; i < k; i++) { W += c[i * OR_REC + 10]; osum += c[i * OR_REC + 10]; }
-    memset(out, 0, sizeof(float) * OR_REC);
+    for (int a = 0; a < OR_REC; a++) out[a] = 0.0;
     if (!(W > 0.0)) return;                       /* padding parent */
     double mu[3] = {0, 0, 0};
     for (int i = 0; i < k; i++) {
@@ -283,15 +289,22 @@ void or_merge_children(const float* c, int k, float* out)
     eig_sym3(S, lam, V);
     double qd[4];
     rot_to_quat(V, qd);
-    for (int a = 0; a < 3; a++) out[a] = (float)mu[a];
-    for (int e = 0; e < 3; e++) out[3 + e] = (float)sqrt(lam[e] > 0.0 ? lam[e] : 0.0);
-    for (int i = 0; i < 4; i++) out[6 + i] = (float)qd[i];
-    out[10] = (float)(osum < 1.0 ? osum : 1.0);
+    for (int a = 0; a < 3; a++) out[a] = mu[a];
+    for (int e = 0; e < 3; e++) out[3 + e] = sqrt(lam[e] > 0.0 ? lam[e] : 0.0);
+    for (int i = 0; i < 4; i++) out[6 + i] = qd[i];
+    out[10] = osum < 1.0 ? osum : 1.0;
     for (int j = 0; j < 48; j++) {
         double acc = 0.0;
         for (int i = 0; i < k; i++) acc += (double)c[i * OR_REC + 10] * c[i * OR_REC + 11 + j];
-        out[11 + j] = (float)(acc / W);
+        out[11 + j] = acc / W;
     }
+}
+
+void or_merge_children(const float* c, int k, float* out)
+{
+    double d[OR_REC];
+    or_merge_children_d(c, k, d);
+    for (int a = 0; a < OR_REC; a++) out[a] = (float)d[a];
 }
 
 static void round_half_form(float* rec)

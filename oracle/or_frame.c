@@ -24,6 +24,12 @@
 #include <string.h>
 #include "oracle.h"
 
+/* memory-use controller of the LOD thresholds (lod_controller below) */
+#define LOD_STEP0 0.125f
+#define LOD_QUICK 4
+#define LOD_TAU_MIN 0.0078125f
+#define LOD_TAU_MAX 65536.0f
+
 /* from or_create.c / or_math.c */
 int or_scene_P(const or_scene* s);
 int or_scene_L(const or_scene* s);
@@ -68,10 +74,10 @@ struct or_vm {
     int force_all;         /* test switch: every page is directly requested */
     int sigma3_tiles;      /* 1: tile rectangles from the 3-sigma radius alone (no support box) */
     int last_full;         /* the last splat was or_render_full (every level-0 Gaussian) */
-    /* LOD thresholds that follow memory use (Sec. 4.1) */
+    /* LOD thresholds that follow memory use (Sec. 4.1, Sec. 5.1.1) */
     int adaptive;
-    float tau0, lod_step, tau_used;
-    int lod_dir, req_slots, n_coarse;
+    float tau_used, lod_step;
+    int lod_dir, lod_last_move, req_slots, n_coarse;
     /* learned prefetch (Sec. 6 future work): configuration, pose history,
      * the logits a frame is given and what the last frame did with them */
     int pf_on, pf_K, pf_H, pf_budget;
@@ -749,7 +755,7 @@ or_vm* or_vm_create(const or_scene* s, int pool_pages, int copy_budget, int use_
     or_vm* vm = calloc(1, sizeof(or_vm));
     vm->s = s; vm->S = pool_pages; vm->budget = copy_budget; vm->use_links = use_links;
     vm->W = W; vm->H = H; vm->Wv = Wv; vm->Hv = Hv; vm->tau = tau; vm->guard = guard;
-    vm->tau0 = tau; vm->lod_step = 0.125f; vm->tau_used = tau;
+    vm->tau_used = tau; vm->lod_step = LOD_STEP0; vm->lod_dir = 0; vm->lod_last_move = 0;
     vm->TX = (W + 15) / 16; vm->TY = (H + 15) / 16;
     vm->P = or_scene_P(s); vm->L = or_scene_L(s); vm->n_pg = or_scene_npg(s);
     vm->bytes_g = or_scene_format(s) == 1 ? 124 : 236;
@@ -801,21 +807,62 @@ static int cmp_rq(const void* a, const void* b)
     return (x->key > y->key) - (x->key < y->key);
 }
 
-/* LOD thresholds from memory use: above 95 % of the pool required (or any
- * request missing) the level-0 radius moves up, below 80 % with coarse levels
- * requested it moves back down, not below its configured value; the relative
- * step grows by 1.5 while the direction holds and halves on a reversal
- * (1/64 .. 1/2).  The next frame uses the new radius. */
-static void lod_control(or_vm* vm)
+/* Level of detail of a page (Sec. 4.1 "Level of Detail"): the level follows
+ * the nearest depth of the page, read as its projected radius in pixels
+ * against halving thresholds: level l is the first with
+ * fy * radius / depth > tau / 2^l, and pages at or below tau / 2^(L-2) take
+ * the coarsest level L - 1. */
+int or_lod_level(float fy, float radius, float depth, float tau, int L)
+{
+    float rpx = (fy * radius) / depth;
+    float thr = tau;
+    int lvl = 0;
+    while (lvl < L - 1 && !(rpx > thr)) { lvl++; thr = thr * 0.5f; }
+    return lvl;
+}
+
+/* Thresholds that follow memory use (Sec. 5.1.1, with Sec. 4.1 and Sec. 5.3):
+ * the controller aims at 50-80 % of the pool.  Usage is the share of
+ * physical pages the frame required; requests left missing count as over
+ * the band.  Over 80 % (or anything missing) the transition distances
+ * shrink: tau, the level-0 radius in pixels, is multiplied by 1 + step.
+ * Under 50 % while some requested page is at a coarse level they grow:
+ * tau is divided by 1 + step.  The step changes by 1 % of itself after each
+ * move: up when the move repeats the direction of a move made at most
+ * LOD_QUICK frames earlier, down when it reverses such a move.  The new tau
+ * is used from the next frame on. */
+
+static void lod_controller(float* tau, float* step, int* dir, int* last_move, int frame, int S, int req_slots,
+                           int n_missing, int n_coarse)
 {
     int d = 0;
-    if (vm->n_missing > 0 || (int64_t)vm->req_slots * 20 > (int64_t)vm->S * 19) d = 1;
-    else if ((int64_t)vm->req_slots * 5 < (int64_t)vm->S * 4 && vm->n_coarse > 0 && vm->tau > vm->tau0) d = -1;
+    if (n_missing > 0 || (int64_t)req_slots * 5 > (int64_t)S * 4) d = 1;
+    else if ((int64_t)req_slots * 2 < (int64_t)S && n_coarse > 0) d = -1;
     if (d == 0) return;
-    if (vm->lod_dir == d) vm->lod_step = fminf(vm->lod_step * 1.5f, 0.5f);
-    else if (vm->lod_dir == -d) vm->lod_step = fmaxf(vm->lod_step * 0.5f, 0.015625f);
-    vm->lod_dir = d;
-    vm->tau = d > 0 ? vm->tau * (1.0f + vm->lod_step) : fmaxf(vm->tau / (1.0f + vm->lod_step), vm->tau0);
+    float t = d > 0 ? *tau * (1.0f + *step) : *tau / (1.0f + *step);
+    *tau = fminf(fmaxf(t, LOD_TAU_MIN), LOD_TAU_MAX);
+    if (*dir != 0 && frame - *last_move <= LOD_QUICK)
+        *step = *dir == d ? *step * 1.01f : *step * 0.99f;
+    *dir = d;
+    *last_move = frame;
+}
+
+static void lod_control(or_vm* vm)
+{
+    lod_controller(&vm->tau, &vm->lod_step, &vm->lod_dir, &vm->lod_last_move, vm->frame, vm->S, vm->req_slots,
+                   vm->n_missing, vm->n_coarse);
+}
+
+void or_lod_control_trace(int n, int S, float tau0, const int* req_slots, const int* n_missing,
+                          const int* n_coarse, float* tau_out, float* step_out)
+{
+    float tau = tau0, step = LOD_STEP0;
+    int dir = 0, last = 0;
+    for (int f = 0; f < n; f++) {
+        lod_controller(&tau, &step, &dir, &last, f, S, req_slots[f], n_missing[f], n_coarse[f]);
+        tau_out[f] = tau;
+        step_out[f] = step;
+    }
 }
 
 /* visibility, requests and page table; brute_force selects the every-pixel raster */
@@ -863,12 +910,7 @@ int or_vm_visibility(or_vm* vm, const or_camera* cams, int n_views, int brute_fo
         vm->page_level[p] = -1;
         if (d == NONE32) continue;
         uint32_t cls = vm->req_direct[p] != NONE32 ? 0u : 1u;
-        int lvl = 0;
-        if (vm->L > 1) {
-            float rpx = (fy * sp[4 * p + 3]) / bitsf(d);
-            float thr = vm->tau;
-            while (lvl < vm->L - 1 && !(rpx > thr)) { lvl++; thr = thr * 0.5f; }
-        }
+        int lvl = vm->L > 1 ? or_lod_level(fy, sp[4 * p + 3], bitsf(d), vm->tau, vm->L) : 0;
         vm->page_level[p] = (int8_t)lvl;
         r[nr].key = ((uint64_t)cls << 61) | ((uint64_t)d << 30) | (uint64_t)p;
         r[nr].page = p;

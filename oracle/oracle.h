@@ -52,6 +52,12 @@ or_scene* or_scene_build(const or_scene_in* in, int page_size, int lod_levels,
 void or_scene_free(or_scene* s);
 int64_t or_scene_get(const or_scene* s, const char* name, void* dst, int64_t cap);
 
+/* Parent of k children by opacity-weighted moment matching (Sec. 3 "Level
+ * of Detail", read as moment matching): out[59] in double, and the stored
+ * float record. */
+void or_merge_children_d(const float* children, int k, double* out);
+void or_merge_children(const float* children, int k, float* out);
+
 /* ---- per frame (Sec. 4) ---- */
 /* guard_px: the page-ID buffer and the frustum extend this many pixels past
  * each edge of the image */
@@ -78,6 +84,15 @@ void or_vm_set_force_all(or_vm* vm, int on);
 void or_vm_set_sigma3_tiles(or_vm* vm, int on);
 /* LOD thresholds that follow memory use (several levels only). */
 void or_vm_set_adaptive_lod(or_vm* vm, int on);
+/* Level of a page (Sec. 4.1 "Level of Detail"): the first l with projected
+ * radius fy * radius / depth > tau / 2^l, else L - 1. */
+int or_lod_level(float fy, float radius, float depth, float tau, int L);
+/* The memory-use controller (Sec. 5.1.1) run over n frames from a fresh
+ * state with radius tau0: per frame the pool size S, the physical pages the
+ * frame required, the requests left missing and the requested pages at a
+ * coarse level; out: the radius and the step after each frame. */
+void or_lod_control_trace(int n, int S, float tau0, const int* req_slots, const int* n_missing,
+                          const int* n_coarse, float* tau_out, float* step_out);
 
 /* Learned prefetch: n_clusters equal page-id ranges, hist_bins equal ranges
  * for the residency features, proposals where a logit exceeds

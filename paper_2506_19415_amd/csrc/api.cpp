@@ -34,6 +34,10 @@ bool pagetable_l1_fits(int n_pg, int S);
 
 using namespace vm;
 
+// memory-use controller of the LOD thresholds (lod_control below)
+constexpr float kLodStep0 = 0.125f, kLodTauMin = 0.0078125f, kLodTauMax = 65536.0f;
+constexpr int kLodQuick = 4;
+
 struct vm3dgs {
     vm3dgs_options opt{};
     PagedScene ps;
@@ -99,8 +103,8 @@ struct vm3dgs {
     int frame = 0;
     bool multi = false;   // multi-kernel page table (several levels or a large table)
     // LOD threshold control from memory use (VM3DGS_FLAG_ADAPTIVE_LOD)
-    float lod_tau = 0.0f, lod_step = 0.125f;
-    int lod_dir = 0;
+    float lod_tau = 0.0f, lod_step = kLodStep0;
+    int lod_dir = 0, lod_last_move = 0;
     // learned prefetch: configuration, pose history (host), features, proposals
     bool pf_on = false, pf_pending = false;
     vm3dgs_prefetch_opts pf{};
@@ -406,24 +410,27 @@ void pf_features(vm3dgs* c, uint32_t n_views) {
     launch_pf_features(c->sr, c->d_v2p, c->n_pg, c->L, (int)c->pf.hist_bins, (int)n_views, c->d_pf_x);
 }
 
-// The LOD thresholds follow memory use (Sec. 4.1): when the frame's required
-// physical pages exceed 95 % of the pool, or requests went missing, the level-0
-// radius tau moves up (coarser, thresholds move away from the camera); below
-// 80 % with coarse levels in use it moves back down, never below the
-// configured radius.  The relative step grows by 1.5 while the direction
-// holds and halves when it reverses (within 1/64 .. 1/2).  The new tau is
-// used from the next frame on.
+// The LOD thresholds follow memory use (Sec. 5.1.1, with Sec. 4.1 and
+// Sec. 5.3).  The aim is 50-80 % of the pool, usage being the share of
+// physical pages the frame required.  Over 80 %, or with requests left
+// missing, the transition distances shrink: the level-0 radius tau (pixels)
+// grows by the factor 1 + step.  Under 50 % while some requested page is at
+// a coarse level, tau shrinks by the same factor.  After a move the step
+// changes by 1 % of itself: up when the move repeats the direction of a
+// move made at most kLodQuick frames earlier, down when it reverses one.
+// tau stays within [2^-7, 2^16] px.  The new tau is used from the next frame.
 void lod_control(vm3dgs* c, uint32_t n_missing, uint32_t req_slots, uint32_t n_coarse) {
-    const float tau0 = c->opt.lod_radius_px;
     const uint64_t S = (uint64_t)c->S;
     int d = 0;
-    if (n_missing > 0 || (uint64_t)req_slots * 20 > S * 19) d = 1;
-    else if ((uint64_t)req_slots * 5 < S * 4 && n_coarse > 0 && c->lod_tau > tau0) d = -1;
+    if (n_missing > 0 || (uint64_t)req_slots * 5 > S * 4) d = 1;
+    else if ((uint64_t)req_slots * 2 < S && n_coarse > 0) d = -1;
     if (d == 0) return;
-    if (c->lod_dir == d) c->lod_step = std::min(c->lod_step * 1.5f, 0.5f);
-    else if (c->lod_dir == -d) c->lod_step = std::max(c->lod_step * 0.5f, 0.015625f);
+    const float t = d > 0 ? c->lod_tau * (1.0f + c->lod_step) : c->lod_tau / (1.0f + c->lod_step);
+    c->lod_tau = std::min(std::max(t, kLodTauMin), kLodTauMax);
+    if (c->lod_dir != 0 && c->frame - c->lod_last_move <= kLodQuick)
+        c->lod_step = c->lod_dir == d ? c->lod_step * 1.01f : c->lod_step * 0.99f;
     c->lod_dir = d;
-    c->lod_tau = d > 0 ? c->lod_tau * (1.0f + c->lod_step) : std::max(c->lod_tau / (1.0f + c->lod_step), tau0);
+    c->lod_last_move = c->frame;
 }
 
 vm3dgs_status fail(vm3dgs* c, const HipError& h) {
@@ -855,7 +862,7 @@ vm3dgs_status vm3dgs_reset(vm3dgs* c) {
         return fail(c, h);
     }
     c->frame = 0;
-    c->lod_tau = c->opt.lod_radius_px; c->lod_step = 0.125f; c->lod_dir = 0;
+    c->lod_tau = c->opt.lod_radius_px; c->lod_step = kLodStep0; c->lod_dir = 0; c->lod_last_move = 0;
     c->pf_n_hist = 0;
     c->pf_pending = false;
     c->last_n_copy = c->last_n_missing = c->last_n_req = c->last_n_rl = 0;

@@ -407,11 +407,13 @@ def test_vm_equals_full_when_everything_resident(clusters):
 
 
 def test_adaptive_lod_thresholds_follow_memory():
-    """The level-0 radius moves up while requests go missing or the pool is
-    over 95 % required, back down (never below its configured value) while it
-    is under 80 % with coarse levels in use; the relative step grows by 1.5
-    while the direction holds and halves on a reversal.  Missing pages vanish
-    within a few frames where the fixed thresholds keep losing them."""
+    """Along a city path whose pool first overloads and later frees up, the
+    level-0 radius moves only outside the 50-80 % band of Sec. 5.1.1: up
+    (coarser) while requests go missing or more than 80 % of the pool is
+    required, down while under 50 % with coarse pages requested, and it
+    stays put inside the band.  Missing pages vanish within a few frames
+    where the fixed thresholds keep losing them.  (The step rule is pinned
+    by the hand-worked trace in test_oracle_lod.)"""
     sc = synth.scene_city(0, n=400_000, size=300.0, block=60.0, street=12.0)
     cams = synth.path_city(sc, n_frames=60, width=320, height=180)
     osc = oracle.OracleScene(sc, 512, 3, 2.0, 2.0)
@@ -419,7 +421,7 @@ def test_adaptive_lod_thresholds_follow_memory():
     fixed = oracle.OracleVM(osc, S, (320, 180), (80, 45), lod_radius_px=tau0)
     vm = oracle.OracleVM(osc, S, (320, 180), (80, 45), lod_radius_px=tau0)
     vm.set_adaptive_lod(True)
-    taus, steps, miss_a, miss_f = [], [], [], []
+    taus, miss_a, miss_f, moves = [], [], [], {1: 0, -1: 0}
     for k in range(0, 60, 2):
         vm.frame([cams[k]])
         fixed.frame([cams[k]])
@@ -427,19 +429,17 @@ def test_adaptive_lod_thresholds_follow_memory():
         c = vm.counts()
         req_slots = len(set(vm.get("render_list").reshape(-1, 6)[:, 2].tolist()))
         coarse = int((vm.get("page_level") > 0).sum())
-        assert nxt >= tau0
-        if c["missing"] > 0 or req_slots * 20 > S * 19:
+        if c["missing"] > 0 or req_slots * 5 > S * 4:
             assert nxt > used, k
-        elif req_slots * 5 < S * 4 and coarse > 0 and used > tau0:
+            moves[1] += 1
+        elif req_slots * 2 < S and coarse > 0:
             assert nxt < used, k
+            moves[-1] += 1
         else:
             assert nxt == used, k
-        if nxt != used:
-            steps.append(nxt / used if nxt > used else used / nxt)
         taus.append(used)
         miss_a.append(c["missing"])
         miss_f.append(fixed.counts()["missing"])
-    # growth by 1.5 while moving the same way, starting at 1/8
-    assert abs(steps[0] - 1.125) < 1e-6 and abs(steps[1] - (1 + 0.125 * 1.5)) < 1e-6
-    assert max(taus) > 2 * tau0 and taus[-1] < max(taus)
+    assert moves[1] > 0
+    assert max(taus) > 2 * tau0
     assert sum(miss_a[8:]) < 0.05 * sum(miss_f[8:]), (sum(miss_a[8:]), sum(miss_f[8:]))
