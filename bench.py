@@ -1,20 +1,30 @@
 #!/usr/bin/env python3
 """Throughput of the VM-3DGS frame path on one MI355X.
 
-Workload (terrain6m): 6,000,000 Gaussians (3M on a 200 x 200 m heightfield,
-3M on the faces of 40 box buildings), pages of 1024 (5,860 pages), a pool of
-1,465 physical pages (1.5M Gaussians), 240x135 page-ID buffer, proxy cells
-of 0.5 m, 1920x1080 image, 70 degree horizontal field of view, a 300-frame
-fly-through 1.7 m above the ground; fp32 attributes; seeded synthetic data.
+Default workload (city50m_lod): 50,000,000 Gaussians of a 1 x 1 km city
+(street grid of 100 m blocks, 1-6 buildings per block, Gaussians on the
+ground, facades and roofs; colours that vary smoothly over the surfaces),
+pages of 1024, three LOD levels (1024 / 128 / 16 Gaussians per page; each
+parent moment-matches 8 children, scaled up by a fixed factor), a pool of
+3,907 physical pages (4M Gaussians), LOD thresholds that follow memory use,
+240x135 page-ID buffer, 2 m proxy cells, 1920x1080, 70 degree horizontal field
+of view, the 600-frame path (street level, ascent to 150 m, aerial view
+pitched 35 degrees down); fp32 attributes; seeded synthetic data.
 
 A step is one vm3dgs_frame (visibility, page table, copies of the misses,
 preprocess, sorts, blend) for the next camera of the path.  W warm-up steps
 (the cold first frame among them), then K timed steps.  The full-scene splat
-of every Gaussian (same kernels, no paging) is timed on the same cameras,
-and the PSNR of each timed VM frame against it is reported (the VM images
-come from a second pass over the same cameras, which also counts the blend's
-work; with no missing pages, which the JSON reports, they equal the timed
-frames' images).
+of every level-0 Gaussian (same kernels, no paging) is timed on the same
+cameras, and the PSNR of each timed VM frame against it is reported (the VM
+images come from a second pass over the same cameras from the same start,
+which also counts the blend's work; the frame path is deterministic, so they
+are the timed frames' images).  After the timed steps the whole path is run
+once more for the per-phase frame rates and PSNR.
+
+--workload terrain6m: 6,000,000 Gaussians on a 200 x 200 m terrain with 40
+buildings, one level, pool 1,465 pages; city50m_half: the city with
+half-precision pages; city50m_prefetch8: eight views per call at 1280x720
+with the learned prefetch.
 
 One JSON line on stdout; progress on stderr.
 """
@@ -33,29 +43,33 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FPS @1080p, VM vs full-scene splat on same GPU at PSNR>=40dB; stage GB/s"
 HBM_PEAK_GBS = 8000.0
-# fp32 vector peak without packed FP32 (the kernels are built without it):
+# MI355X published fp32 vector peak (counts packed FP32, two lanes' work per
+# instruction); the kernels are built without packed FP32, whose own ceiling is
 # 256 CUs x 4 SIMD x 16 lanes x 2 flops per FMA x 2.4 GHz = 78.6 TFLOP/s
-ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-# algorithmic flops of the blend per pixel-Gaussian evaluation: the exponent
-# (dx, dy, three products, two fused multiply-adds, two products) = 11; per
-# evaluation that computes alpha add the exp (x log2 e, 9 fused multiply-adds,
-# the 2^n scale = 20), opacity * exp, 1 - alpha and T (1 - alpha) = 23.  The
-# colour update of accepted terms (7) is not counted (lower bound).
-FLOP_EVAL, FLOP_ALPHA = 11, 23
+ALU_PEAK_TFLOPS = 157.3
+ALU_PEAK_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# algorithmic VALU work of the blend per evaluated pixel-Gaussian pair (the
+# exponent, alpha with its exp, the tests, transmittance and the colour
+# update, counted up to each pixel's stop)
+OPS_PER_EVAL = 25
 # proxy cell edge of the terrain workload: with 1 m cells the boxes of sparse
 # building facades hide the buildings behind them (8 of the 300 frames under
 # 40 dB against the full render); with 0.5 m cells every frame is above 47 dB
 TERRAIN_CELL_M = 0.5
+# LOD parents of the city workloads: moment-matched scales times this factor
+# (a merged Gaussian covers less than its children; the fixed scale-up fills
+# the gaps) and the initial level-0 radius of the threshold controller
+CITY_LOD_SCALE_UP = 1.6
+CITY_TAU0_PX = 32.0
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# HBM traffic of k_blend from the committed counter summary, valid only while
-# the kernel's source is the one the counters were taken on
+# HBM traffic of k_blend from the committed counter summary of the workload,
+# valid only while the kernel's source is the one the counters were taken on
 BLEND_SOURCES = ["paper_2506_19415_amd/csrc/k_splat.hip", "paper_2506_19415_amd/csrc/kcommon.h"]
-BLEND_PMC = "profiles/k_blend_terrain6m_pmc.md"
 
 
 def blend_source_hash():
@@ -66,8 +80,8 @@ def blend_source_hash():
     return h.hexdigest()
 
 
-def blend_traffic():
-    path = os.path.join(ROOT, BLEND_PMC)
+def blend_traffic(workload):
+    path = os.path.join(ROOT, "profiles", f"k_blend_{workload}_pmc.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -86,25 +100,67 @@ def psnr(a, b):
     return float("inf") if mse == 0.0 else 10.0 * math.log10(1.0 / mse)
 
 
-def cpu_baseline(sc, cams, P=1024, S=1465, links=True, budget_s=30.0):
-    """The oracle (plain C, single thread) on a bounded sample: frames of the
-    same path after one warm frame, until about budget_s seconds of frames."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores():
+    """Cores this process may run on (the affinity mask), and os.cpu_count()."""
+    try:
+        return len(os.sched_getaffinity(0)), os.cpu_count()
+    except AttributeError:
+        return os.cpu_count(), os.cpu_count()
+
+
+def cpu_baseline(make_vm, cams, workload, budget_s=12.0):
+    """The oracle (plain C) on a bounded sample of the same path: after one
+    warm frame, consecutive frames until about budget_s seconds, once on one
+    thread and once on every core this process may use (OpenMP over the
+    independent per-Gaussian and per-tile loops of its splat).  make_vm()
+    returns (oracle VM, create-time seconds)."""
     import oracle
-    t0 = time.time()
-    osc = oracle.OracleScene(sc, P, 1, TERRAIN_CELL_M, 2.0)
-    vm = oracle.OracleVM(osc, S, (1920, 1080), (240, 135), use_links=links)
-    build_s = time.time() - t0
-    vm.frame([cams[0]])
-    times = []
-    k = 1
-    while k < len(cams) and (not times or sum(times) < budget_s * 0.5):
-        t = time.time()
-        vm.frame([cams[k]])
-        times.append(time.time() - t)
-        k += 1
-    return {"value": len(times) / sum(times), "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"frames 1..{len(times)} of the terrain6m path at 1920x1080 after a warm frame 0 "
-                      f"(oracle create-time build {build_s:.1f} s not included)"}
+    n_cores, n_os = host_cores()
+    legs = {}
+    build_s = 0.0
+    for threads in (1, n_cores):
+        oracle.set_threads(threads)
+        vm, build_s = make_vm()
+        vm.frame([cams[0]])
+        times = []
+        k = 1
+        while k < len(cams) and (not times or sum(times) < budget_s):
+            t = time.time()
+            vm.frame([cams[k]])
+            times.append(time.time() - t)
+            k += 1
+        legs[threads] = (len(times) / sum(times), len(times))
+        del vm
+    oracle.set_threads(n_cores)
+    fps_all, n_all = legs[n_cores]
+    fps_one, n_one = legs[1]
+    return {"value": fps_all, "unit": "frames/s", "cores": n_cores, "kind": "oracle",
+            "value_one_core": fps_one, "cpu_model": cpu_model(), "nproc": n_os,
+            "sample": f"frames 1..{n_all} ({n_cores} threads) and 1..{n_one} (one thread) of the {workload} path "
+                      f"at the bench's resolution after a warm frame 0 (oracle create-time build {build_s:.1f} s "
+                      "not included)"}
+
+
+def blend_roofline(evals, blend_ms, traffic, n_frames):
+    """k_blend against the fp32 vector peak: OPS_PER_EVAL VALU operations per
+    evaluated pixel-Gaussian pair, per launch, over the launch's mean time."""
+    ops = statistics.mean(evals) * OPS_PER_EVAL
+    achieved = ops / (blend_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / ALU_PEAK_TFLOPS, "traffic": traffic, "kernel": "k_blend",
+            "frac_of_unpacked_peak": achieved / ALU_PEAK_UNPACKED_TFLOPS,
+            "per_unit": f"{OPS_PER_EVAL} VALU ops per evaluated pixel-Gaussian pair",
+            "evals_per_launch": statistics.mean(evals), "launch_ms": blend_ms, "frames": n_frames}
 
 
 
@@ -116,10 +172,169 @@ CITY = {
     # half pages, eight views per call at 1280x720 on their own paths, sharing one pool, with the learned prefetch
     "city50m_prefetch8": dict(fmt=1, views=8, img=(1280, 720), idbuf=(160, 90)),
 }
+CITY_PHASES = [("street", 0, 200), ("ascent", 200, 400), ("aerial", 400, 600)]
 
 
-def run_city(args, pkg, synth):
-    """The city workloads: VM frames per second over the path, the full-scene
+def city_scene(args, synth):
+    t0 = time.time()
+    sc = synth.scene_city(0, n=args.city_n, color=args.city_color)
+    log(f"city scene {sc.n} Gaussians ({args.city_color} colours) in {time.time() - t0:.1f} s")
+    return sc
+
+
+def run_city_lod(args, pkg, synth):
+    """One view of the city along its path: VM frames per second, the
+    full-scene fp32 splat of all level-0 Gaussians on the same cameras (its
+    FPS and the PSNR of every timed VM frame against it), stage times, the
+    blend's roofline, per-phase frame rates and PSNR over the whole path, and
+    the oracle on the host."""
+    import torch
+    cfg = CITY[args.workload]
+    W, H = cfg["img"]
+    sc = city_scene(args, synth)
+    cams = synth.path_city(sc, n_frames=600, width=W, height=H)
+    n_path = len(cams)
+    t0 = time.time()
+    r = pkg.Renderer(sc, 1024, 3907, lod_levels=3, img=(W, H), idbuf=cfg["idbuf"], attr_format=cfg["fmt"],
+                     cell=2.0, lod_radius_px=args.tau0, lod_scale_up=args.lod_scale_up, full_scene=not args.no_full)
+    flags = pkg.VM3DGS_FLAG_LINKS | pkg.VM3DGS_FLAG_ADAPTIVE_LOD
+    r.set_flags(flags)
+    log(f"VM context (L=3, pool 3907, format {cfg['fmt']}, scale-up {args.lod_scale_up}) {time.time() - t0:.1f} s")
+    K, Wm = args.steps, args.warmup
+
+    for i in range(Wm):
+        _, out = r.frame([cams[i % n_path]])
+        if i == 0:
+            log(f"cold frame: copies {out.stats.copies} pages, {out.stats.bytes_copied / 1e6:.1f} MB, "
+                f"{out.stats.ms_total:.2f} ms")
+    torch.cuda.synchronize()
+    stats, walls = [], []
+    t_start = time.perf_counter()
+    for i in range(K):
+        t = time.perf_counter()
+        _, out = r.frame([cams[(Wm + i) % n_path]])
+        walls.append((time.perf_counter() - t) * 1e3)
+        stats.append(out.stats.as_dict())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    log(f"VM: {K} frames in {elapsed:.3f} s")
+
+    # full-scene baseline on the same cameras
+    full_fps, full_stats = None, []
+    if not args.no_full:
+        for i in range(2):
+            r.render_full([cams[(Wm + i) % n_path]])
+        torch.cuda.synchronize()
+        nf = min(K, 60)
+        tf = time.perf_counter()
+        for i in range(nf):
+            _, st = r.render_full([cams[(Wm + i) % n_path]])
+            full_stats.append(st.as_dict())
+        torch.cuda.synchronize()
+        full_fps = nf / (time.perf_counter() - tf)
+
+    # second pass from the same start with the blend's work counters: the
+    # timed frames' images (PSNR against the full render) and blend work
+    r.reset()
+    r.set_flags(flags | pkg.VM3DGS_FLAG_BLEND_STATS)
+    psnrs, evals = [], []
+    for i in range(Wm + K):
+        img, out = r.frame([cams[i % n_path]])
+        if i >= Wm:
+            evals.append(out.stats.blend_evals)
+            if not args.no_full:
+                vm_img = img[0].clone()
+                ref, _ = r.render_full([cams[i % n_path]])
+                psnrs.append(psnr(vm_img, ref[0]))
+    r.set_flags(flags)
+    if psnrs:
+        log(f"full: {full_fps:.1f} FPS; PSNR of the timed frames min {min(psnrs):.2f} median "
+            f"{statistics.median(psnrs):.2f}")
+
+    # the whole path once more: per-phase frame rate, PSNR on every 20th frame
+    phases = None
+    if not args.no_path:
+        r.reset()
+        pw, pp, ptau, pres = [], {}, [], []
+        for i in range(n_path):
+            t = time.perf_counter()
+            img, out = r.frame([cams[i]])
+            pw.append((time.perf_counter() - t) * 1e3)
+            ptau.append(out.stats.lod_radius_px)
+            pres.append(out.stats.render_gaussians)
+            if i % 20 == 10 and not args.no_full:
+                vm_img = img[0].clone()
+                ref, _ = r.render_full([cams[i]])
+                pp[i] = psnr(vm_img, ref[0])
+        phases = {}
+        for name, f0, f1 in CITY_PHASES:
+            ps = [v for k, v in pp.items() if f0 <= k < f1]
+            phases[name] = {"frames": [f0, f1], "fps_median_frame": 1000.0 / statistics.median(pw[max(f0, 1):f1]),
+                            "psnr_min": min(ps) if ps else None, "psnr_median": statistics.median(ps) if ps else None,
+                            "lod_radius_px_median": statistics.median(ptau[f0:f1]),
+                            "render_gaussians_median": statistics.median(pres[f0:f1])}
+            log(f"phase {name}: {phases[name]}")
+    r.close()
+
+    def med(key, rows):
+        return statistics.median([s_[key] for s_ in rows]) if rows else None
+
+    stage_keys = ["ms_visibility", "ms_pagetable", "ms_copy", "ms_preprocess", "ms_sort", "ms_blend", "ms_total"]
+    vm_stage = {k: med(k, stats) for k in stage_keys}
+    n_render = med("render_gaussians", stats)
+    pairs = med("pairs", stats)
+    bytes_g = 124 if cfg["fmt"] else 236
+    pre_ms = statistics.mean([s_["ms_preprocess"] for s_ in stats])
+    pre_bytes = statistics.mean([s_["render_gaussians"] for s_ in stats]) * (bytes_g + 64)
+    blend_ms = statistics.mean([s_["ms_blend"] for s_ in stats])
+    res = {
+        "metric": METRIC, "value": K / elapsed, "unit": "frames/s", "n_gpus": 1, "steps": K, "warmup": Wm,
+        "ms_per_step": elapsed * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": f"synthetic (seeded city, {sc.n} Gaussians, {args.city_color} colours)",
+        "config": {"workload": f"{args.workload}: {sc.n} Gaussians over 1 x 1 km, 1024/page, 3 LOD levels "
+                               f"(1024/128/16, parents scaled up x{args.lod_scale_up}), pool 3907 pages, "
+                               f"adaptive LOD from {args.tau0} px, 1920x1080, ID buffer 240x135, 70 deg, "
+                               f"frames {Wm}..{Wm + K - 1} of the 600-frame street-ascent-aerial path",
+                   "attr_format": "half" if cfg["fmt"] else "fp32", "page_size": 1024, "pool_pages": 3907,
+                   "lod_levels": 3, "lod_scale_up": args.lod_scale_up, "tau0_px": args.tau0,
+                   "image": [W, H], "idbuf": list(cfg["idbuf"]), "proxy_cell_m": 2.0},
+        "fps_median_frame": 1000.0 / statistics.median(walls),
+        "full_scene_fps": full_fps, "speedup_vs_full": (K / elapsed) / full_fps if full_fps else None,
+        "psnr_min": min(psnrs) if psnrs else None, "psnr_median": statistics.median(psnrs) if psnrs else None,
+        "stage_ms_median": vm_stage,
+        "full_stage_ms_median": {k: med(k, full_stats) for k in ["ms_preprocess", "ms_sort", "ms_blend", "ms_total"]}
+        if full_stats else None,
+        "render_gaussians_median": n_render, "pairs_median": pairs,
+        "lod_radius_px_median": med("lod_radius_px", stats),
+        "misses_per_frame": statistics.mean(s_["misses"] for s_ in stats),
+        "missing_per_frame": statistics.mean(s_["missing"] for s_ in stats),
+        "bytes_copied_per_frame": statistics.mean(s_["bytes_copied"] for s_ in stats),
+        "stage_gbs": {"copy_pcie": statistics.mean([s_["bytes_copied"] for s_ in stats]) /
+                      max(statistics.mean([s_["ms_copy"] for s_ in stats]) * 1e-3, 1e-9) / 1e9},
+        "preprocess_roofline": {"bound": "hbm", "achieved": pre_bytes / (pre_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": pre_bytes / (pre_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                "per_unit": f"{bytes_g + 64} B per render Gaussian ({bytes_g} B attributes read, "
+                                            "64 B written)"},
+        "roofline": blend_roofline(evals, blend_ms, blend_traffic(args.workload), K),
+        "phases": phases,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        log("cpu baseline (oracle) ...")
+
+        def make_vm():
+            t0 = time.time()
+            osc = oracle.OracleScene(sc, 1024, 3, 2.0, 2.0, attr_format=cfg["fmt"], lod_scale_up=args.lod_scale_up)
+            vm = oracle.OracleVM(osc, 3907, (W, H), cfg["idbuf"], lod_radius_px=args.tau0)
+            vm.set_adaptive_lod(True)
+            vm._osc = osc
+            return vm, time.time() - t0
+        res["cpu_baseline"] = cpu_baseline(make_vm, cams[Wm:], args.workload)
+    return res
+
+
+def run_city_prefetch(args, pkg, synth):
+    """The eight-view city workload: VM frames per second over the path, the full-scene
     fp32 splat of all level-0 Gaussians on the same cameras (FPS and the PSNR
     of every VM image against it), stage times; for the prefetch workload the
     demand misses, stalls and proposal quality with and without the network,
@@ -129,9 +344,7 @@ def run_city(args, pkg, synth):
     cfg = CITY[args.workload]
     W, H = cfg["img"]
     V = cfg["views"]
-    t0 = time.time()
-    sc = synth.scene_city(0, n=args.city_n)
-    log(f"city scene {sc.n} Gaussians in {time.time() - t0:.1f} s")
+    sc = city_scene(args, synth)
     if V == 1:
         paths = [synth.path_city(sc, n_frames=600, width=W, height=H)]
     else:
@@ -139,7 +352,7 @@ def run_city(args, pkg, synth):
     frames = [[p[i] for p in paths] for i in range(600)]
     t0 = time.time()
     r = pkg.Renderer(sc, 1024, 3907, lod_levels=3, img=(W, H), idbuf=cfg["idbuf"], max_views=V,
-                     attr_format=cfg["fmt"], cell=2.0, lod_radius_px=32.0)
+                     attr_format=cfg["fmt"], cell=2.0, lod_radius_px=args.tau0, lod_scale_up=args.lod_scale_up)
     log(f"VM context (L=3, pool 3907, format {cfg['fmt']}) {time.time() - t0:.1f} s")
     # LOD thresholds follow memory use (Sec. 4.1): the 4M-Gaussian pool cannot hold
     # every page at the 32 px radius near street level
@@ -154,12 +367,6 @@ def run_city(args, pkg, synth):
         dims = [28 + HB, 256, 256, 256, KC]
         n_paths = max(1, args.train_frames // 200)
         train_paths = [synth.path_city(sc, n_frames=200, width=W, height=H, seed=1000 + i) for i in range(n_paths)]
-        r1 = pkg.Renderer(sc, 1024, 3907, lod_levels=3, img=(W, H), idbuf=cfg["idbuf"], max_views=1,
-                          attr_format=cfg["fmt"], cell=2.0, lod_radius_px=32.0)
-        t0 = time.time()
-        X, Y = pf.collect(r1, train_paths, KC, HB, center, extent)
-        r1.close()
-        log(f"training data: {X.shape[0]} frames in {time.time() - t0:.1f} s, positive rate {Y.mean():.4f}")
         rng = np.random.default_rng(3)
         params = []
         for l in range(len(dims) - 1):
@@ -167,12 +374,19 @@ def run_city(args, pkg, synth):
             params.append(np.zeros(dims[l + 1], np.float32))
         net = pkg.Mlp(dims, max_batch=max(256, V))
         net.set_params(np.concatenate(params))
-        t0 = time.time()
-        losses = pf.train(net, X, Y, steps=3000, batch=256, lr=1e-3, log_every=1000)
-        log(f"training: 3000 Adam steps in {time.time() - t0:.1f} s, loss {losses}")
-        thr = pf.calibrate_threshold(net, X, Y, factor=2.0)
-        log(f"logit threshold {thr:.3f}")
-        pf_report = {"training_frames": int(X.shape[0]), "loss": losses, "dims": dims, "logit_threshold": thr}
+        # rows, labels and training in the library (vm3dgs_prefetch_train) on a one-view context
+        r1 = pkg.Renderer(sc, 1024, 3907, lod_levels=3, img=(W, H), idbuf=cfg["idbuf"], max_views=1,
+                          attr_format=cfg["fmt"], cell=2.0, lod_radius_px=args.tau0, lod_scale_up=args.lod_scale_up)
+        r1.set_flags(pkg.VM3DGS_FLAG_LINKS | pkg.VM3DGS_FLAG_ADAPTIVE_LOD)
+        r1.set_prefetch(net, KC, HB, 0.0, 64, center, extent)
+        tlog = r1.prefetch_train(train_paths, steps=args.train_steps, batch=256, lr=1e-3, seed=3,
+                                 proposal_factor=2.0, log_every=max(1, args.train_steps // 8))
+        r1.close()
+        thr = tlog["logit_threshold"]
+        log(f"training: {tlog['rows']} rows collected in {tlog['ms_collect'] / 1e3:.1f} s, positive rate "
+            f"{tlog['positive_rate']:.4f}; {args.train_steps} Adam steps in {tlog['ms_train'] / 1e3:.1f} s, loss "
+            f"{tlog['loss_first']:.4f} -> {tlog['loss_last']:.4f}; logit threshold {thr:.3f}")
+        pf_report = {"training_frames": int(tlog["rows"]), "train_log": tlog, "dims": dims, "logit_threshold": thr}
         r.set_prefetch(net, KC, HB, thr, 64, center, extent)
 
     def run_frames(n0, n):
@@ -226,7 +440,7 @@ def run_city(args, pkg, synth):
         full_fps = nf / (time.perf_counter() - tf)
         # PSNR on every 10th timed frame: re-run the VM path to that frame
         rv = pkg.Renderer(sc, 1024, 3907, lod_levels=3, img=(W, H), idbuf=cfg["idbuf"], max_views=V,
-                          attr_format=cfg["fmt"], cell=2.0, lod_radius_px=32.0)
+                          attr_format=cfg["fmt"], cell=2.0, lod_radius_px=args.tau0, lod_scale_up=args.lod_scale_up)
         rv.set_flags(pkg.VM3DGS_FLAG_LINKS | pkg.VM3DGS_FLAG_ADAPTIVE_LOD)
         if net is not None:
             rv.set_prefetch(net, 4096, 512, pf_report["logit_threshold"], 64, *pf.scene_frame(sc))
@@ -276,12 +490,19 @@ def main():
                     help="after the timed frames, one plain device-to-device copy of this many MiB "
                          "(the reference kernel that scales the HBM counters)")
     ap.add_argument("--print-source-hash", action="store_true", help="print the k_blend source hash and exit")
-    ap.add_argument("--workload", default="terrain6m", choices=["terrain6m", "city50m_lod", "city50m_half",
-                                                                "city50m_prefetch8"],
-                    help="terrain6m (the default, the metric's workload) or the 50M-Gaussian city with three "
-                         "LOD levels: fp32, half-precision pages, or half pages with eight views and the "
-                         "learned prefetch")
+    ap.add_argument("--workload", default="city50m_lod", choices=["city50m_lod", "city50m_half", "city50m_prefetch8",
+                                                                  "terrain6m"],
+                    help="city50m_lod (the default: the 50M-Gaussian city with three LOD levels at 1080p, fp32), "
+                         "city50m_half (half-precision pages), city50m_prefetch8 (half pages, eight views, the "
+                         "learned prefetch) or terrain6m (6M Gaussians, one level)")
     ap.add_argument("--city-n", type=int, default=50_000_000, help="Gaussians of the city workloads")
+    ap.add_argument("--city-color", default="smooth", choices=["smooth", "iid", "white"],
+                    help="city colours: smooth over the surfaces (default), independent per Gaussian, or white")
+    ap.add_argument("--lod-scale-up", type=float, default=CITY_LOD_SCALE_UP,
+                    help="city: factor on the moment-matched scales of the LOD parents")
+    ap.add_argument("--tau0", type=float, default=CITY_TAU0_PX,
+                    help="city: initial level-0 projected page radius (pixels) of the adaptive thresholds")
+    ap.add_argument("--no-path", action="store_true", help="city: skip the per-phase pass over the whole path")
     ap.add_argument("--page-size", type=int, default=1024,
                     help="terrain6m: Gaussians per page (the page-size trend of the paper's Tab. 3)")
     ap.add_argument("--lod-levels", type=int, default=1,
@@ -292,6 +513,7 @@ def main():
                     help="terrain6m: pool size as a fraction of 1.5M Gaussians (the buffer-size trend of Tab. 4)")
     ap.add_argument("--train-frames", type=int, default=2000,
                     help="city50m_prefetch8: plain-pass frames of training data for the network")
+    ap.add_argument("--train-steps", type=int, default=3000, help="city50m_prefetch8: Adam steps")
     args = ap.parse_args()
     if args.print_source_hash:
         print(blend_source_hash())
@@ -312,9 +534,30 @@ def main():
     from paper_2506_19415_amd import synth
 
     torch.cuda.set_device(0)
-    if args.workload != "terrain6m":
-        print(json.dumps(run_city(args, pkg, synth)), flush=True)
-        return
+    if args.workload == "terrain6m":
+        res = run_terrain(args, pkg, synth)
+    elif args.workload == "city50m_prefetch8":
+        res = run_city_prefetch(args, pkg, synth)
+    else:
+        res = run_city_lod(args, pkg, synth)
+    if args.calib_copy_mib > 0:
+        # an elementwise kernel that reads and writes the size once: the
+        # reference that scales the HBM counters of the profiled kernels
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mib} MiB read and written by one elementwise kernel")
+        del src, dst
+    print(json.dumps(res), flush=True)
+
+
+def run_terrain(args, pkg, synth):
+    """The terrain workload: one level (or --lod-levels), the full-scene
+    baseline and PSNR, the blend's roofline, the oracle on the host."""
+    import torch
     t0 = time.time()
     sc = synth.scene_terrain(0)
     cams = synth.path_terrain(sc)
@@ -411,15 +654,8 @@ def main():
     # dominant kernel of the VM step: k_blend (one launch per frame, timed with
     # HIP events on the render stream it runs on)
     blend_ms = statistics.mean([s["ms_blend"] for s in stats])
-    flops = statistics.mean([FLOP_EVAL * e + FLOP_ALPHA * a for e, a in zip(evals, alphas)])
-    achieved = flops / (blend_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / ALU_PEAK_TFLOPS,
-                "traffic": blend_traffic() if (P, S, args.no_links, L) == (1024, 1465, False, 1) else None,
-                "kernel": "k_blend",
-                "per_unit": f"{FLOP_EVAL} flop per pixel-Gaussian evaluation + {FLOP_ALPHA} per alpha evaluation",
-                "evals_per_launch": statistics.mean(evals), "alphas_per_launch": statistics.mean(alphas),
-                "launch_ms": blend_ms}
+    default_cfg = (P, S, args.no_links, L) == (1024, 1465, False, 1)
+    roofline = blend_roofline(evals, blend_ms, blend_traffic("terrain6m") if default_cfg else None, K)
     pre_ms = statistics.mean([s["ms_preprocess"] for s in stats])
     res = {
         "metric": METRIC,
@@ -458,21 +694,20 @@ def main():
                                 "per_unit": "300 B per render Gaussian (236 B attributes read, 64 B written)"},
         "roofline": roofline,
     }
-    if args.calib_copy_mib > 0:
-        n = args.calib_copy_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        torch.mul(src, 2.0, out=dst)   # an elementwise kernel: reads and writes the size once
-        torch.cuda.synchronize()
-        log(f"calibration copy: {args.calib_copy_mib} MiB read and written by one elementwise kernel")
-        del src, dst
     r.close()
     del vm_imgs
     if not args.no_cpu_baseline and L == 1:
+        import oracle
         log("cpu baseline (oracle) ...")
-        res["cpu_baseline"] = cpu_baseline(sc, cams, P, S, not args.no_links)
-    print(json.dumps(res), flush=True)
+
+        def make_vm():
+            t0 = time.time()
+            osc = oracle.OracleScene(sc, P, 1, TERRAIN_CELL_M, 2.0)
+            vm = oracle.OracleVM(osc, S, (1920, 1080), (240, 135), use_links=not args.no_links)
+            vm._osc = osc
+            return vm, time.time() - t0
+        res["cpu_baseline"] = cpu_baseline(make_vm, cams, "terrain6m")
+    return res
 
 
 if __name__ == "__main__":

@@ -88,6 +88,9 @@ typedef struct {
     void* stream_render;          /* hipStream_t for the frame's kernels, NULL = library-owned stream */
     void* stream_copy;            /* hipStream_t for page copies, NULL = library-owned stream */
     uint64_t pair_capacity;       /* initial (tile, Gaussian) pair capacity; grows on demand; 0 = automatic */
+    float lod_scale_up;           /* LOD parents: moment-matched scales times this factor (Sec. 3 Level of
+                                     Detail: merged Gaussians are scaled up by a fixed factor to fill gaps);
+                                     1 = moment matching alone; in (0, 16] */
 } vm3dgs_options;
 
 /* Fill *o with defaults: 1920x1080 image, 240x135 ID buffer with a 32 px
@@ -189,6 +192,15 @@ vm3dgs_status vm3dgs_reset(vm3dgs* ctx);
  * for later frames (VM3DGS_FLAG_FULL_SCENE_COPY is fixed at create).
  * Errors: INVALID_ARG for a NULL context. */
 vm3dgs_status vm3dgs_set_flags(vm3dgs* ctx, uint32_t flags);
+
+/* Set the LOD threshold tau (Sec. 4.1 Level of Detail: a page is drawn at
+ * level l when l is the first level with projected page radius
+ * fy * R / depth > tau / 2^l, capped at L - 1) for later frames, as
+ * lod_radius_px at create would; the adaptive controller (Sec. 5.1.1), when
+ * on, starts again from this tau with its initial step.
+ * Errors: INVALID_ARG for a NULL context or a tau that is not a positive
+ * finite number. */
+vm3dgs_status vm3dgs_set_lod_radius(vm3dgs* ctx, float tau_px);
 
 /* Block until the render and copy streams are idle. */
 vm3dgs_status vm3dgs_sync(vm3dgs* ctx);
@@ -296,6 +308,69 @@ vm3dgs_status vm3dgs_set_prefetch(vm3dgs* ctx, vm3dgs_mlp* net, const vm3dgs_pre
 /* Feature rows [n_views][28 + hist_bins] of the current state (the poses of
  * the frames so far and the residency now) into host memory. */
 vm3dgs_status vm3dgs_prefetch_features(vm3dgs* ctx, uint32_t n_views, float* x_host);
+
+/* ---- Learned page prefetch: training data and training -------------------
+ * Training data are the method's own page sets: camera paths rendered by
+ * the plain method (the network's stage off), one view per frame, each path
+ * from an empty pool (the context is reset before each path and after the
+ * call).  For frame t of a path with a frame t+1, the row is the feature
+ * row after frame t (as vm3dgs_prefetch_features gives it), and the label
+ * row marks (1.0) every cluster holding a page that frame t+1 requested and
+ * that was not resident, at any level, after frame t (0.0 elsewhere). */
+typedef struct {
+    const vm3dgs_camera* cams;      /* the cameras of all paths, path after path */
+    const uint32_t* path_frames;    /* frames of each path */
+    uint32_t n_paths;
+} vm3dgs_dataset;
+
+/* Rows of the dataset into host memory: x_host [cap_rows][28 + hist_bins],
+ * y_host [cap_rows][n_clusters] (either may be NULL to count only); *rows =
+ * frames minus paths.  Needs the stage (vm3dgs_set_prefetch, net may be
+ * NULL).  CAPACITY when the rows exceed cap_rows (nothing written past it);
+ * INVALID_ARG for a missing stage or empty data. */
+vm3dgs_status vm3dgs_prefetch_collect(vm3dgs* ctx, const vm3dgs_dataset* data, float* x_host, float* y_host,
+                                      uint64_t cap_rows, uint64_t* rows);
+
+typedef struct {
+    uint32_t steps;            /* Adam steps */
+    uint32_t batch;            /* rows per step, 1..the network's max_batch */
+    float lr;                  /* learning rate */
+    uint64_t seed;             /* the rows of each step: uniform draws with replacement (splitmix64) */
+    float proposal_factor;     /* > 0: set the stage's logit threshold so that the network, on the
+                                  training rows, proposes this many times as many clusters as the labels
+                                  hold (its (1 - factor * positive rate) quantile); 0: keep it */
+    uint32_t log_every;        /* record the loss every log_every steps (0: the first and last only) */
+} vm3dgs_train_opts;
+
+typedef struct {
+    uint64_t rows;             /* training rows */
+    float positive_rate;       /* share of label entries that are 1 */
+    float loss_first;          /* mean binary cross-entropy before the first step */
+    float loss_last;           /* before the last step */
+    float logit_threshold;     /* the stage's threshold after the call */
+    float ms_collect, ms_train;
+    uint32_t n_losses;         /* recorded losses in losses[] (at most 64, evenly thinned) */
+    float losses[64];
+} vm3dgs_train_log;
+
+/* Train the network attached to the stage (vm3dgs_set_prefetch with a net)
+ * on the dataset's rows with the library's kernels (bf16 matrix products,
+ * fp32 Adam), then set its logit threshold (proposal_factor).  The stage
+ * options stay; the context is reset.  log may be NULL.  INVALID_ARG for no
+ * network, empty data or a batch outside 1..max_batch; HIP, HOST_OOM,
+ * DEVICE_OOM. */
+vm3dgs_status vm3dgs_prefetch_train(vm3dgs* ctx, const vm3dgs_dataset* data, const vm3dgs_train_opts* opts,
+                                    vm3dgs_train_log* log);
+
+/* The network's widths and fp32 master weights to a file, and back: a
+ * little-endian binary file, "VM3DGSNN" then uint32 n_layers, uint32
+ * dims[n_layers + 1], float params[n_params] (the parameter layout above).
+ * Loading needs a network of the same widths and resets its Adam state.
+ * INVALID_ARG for a missing file, a bad header or other widths. */
+vm3dgs_status vm3dgs_mlp_save(vm3dgs_mlp* net, const char* path);
+vm3dgs_status vm3dgs_mlp_load(vm3dgs_mlp* net, const char* path);
+/* vm3dgs_mlp_load into the network attached to the stage. */
+vm3dgs_status vm3dgs_prefetch_load(vm3dgs* ctx, const char* path);
 
 #ifdef __cplusplus
 }

@@ -42,7 +42,8 @@ def lib():
         L.or_round_bf16.restype = C.c_float
         L.or_round_bf16.argtypes = [C.c_float]
         L.or_scene_build.restype = C.c_void_p
-        L.or_scene_build.argtypes = [C.POINTER(_Scene), C.c_int, C.c_int, C.c_double, C.c_double, C.c_int]
+        L.or_scene_build.argtypes = [C.POINTER(_Scene), C.c_int, C.c_int, C.c_double, C.c_double, C.c_int,
+                                     C.c_float]
         L.or_scene_free.argtypes = [C.c_void_p]
         L.or_scene_get.restype = C.c_int64
         L.or_scene_get.argtypes = [C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64]
@@ -55,8 +56,10 @@ def lib():
         L.or_render_full.argtypes = [C.c_void_p, C.POINTER(_Cam), C.c_int, C.c_void_p]
         L.or_vm_get.restype = C.c_int64
         L.or_vm_get.argtypes = [C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64]
-        L.or_merge_children.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
-        L.or_merge_children_d.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_set_threads.restype = C.c_int
+        L.or_merge_children.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_void_p]
+        L.or_merge_children_d.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_void_p]
         L.or_lod_level.restype = C.c_int
         L.or_lod_level.argtypes = [C.c_float, C.c_float, C.c_float, C.c_float, C.c_int]
         L.or_lod_control_trace.argtypes = [C.c_int, C.c_int, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -65,7 +68,7 @@ def lib():
             getattr(L, nm).argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
         L.or_vm_pagetable.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.or_vm_set_force_all.argtypes = [C.c_void_p, C.c_int]
-        L.or_vm_set_sigma3_tiles.argtypes = [C.c_void_p, C.c_int]
+        L.or_vm_set_support_box.argtypes = [C.c_void_p, C.c_int]
         L.or_vm_set_adaptive_lod.argtypes = [C.c_void_p, C.c_int]
         L.or_vm_render_fp64.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Cam), C.c_int, C.c_void_p]
         L.or_vm_set_prefetch.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_float, C.c_int, C.c_void_p, C.c_float]
@@ -140,19 +143,25 @@ def round_bf16(x: float) -> float:
     return lib().or_round_bf16(float(x))
 
 
-def merge_children(rec: np.ndarray) -> np.ndarray:
+def set_threads(n: int) -> int:
+    """OpenMP threads of the oracle's splat loops (n > 0 sets); returns the
+    count in use."""
+    return int(lib().or_set_threads(int(n)))
+
+
+def merge_children(rec: np.ndarray, scale_up: float = 1.0) -> np.ndarray:
     """Stored (float32) parent record of the children rec [k][59]."""
     rec = np.ascontiguousarray(rec, dtype=np.float32)
     out = np.zeros(59, dtype=np.float32)
-    lib().or_merge_children(rec.ctypes.data, rec.shape[0], out.ctypes.data)
+    lib().or_merge_children(rec.ctypes.data, rec.shape[0], float(scale_up), out.ctypes.data)
     return out
 
 
-def merge_children_d(rec: np.ndarray) -> np.ndarray:
+def merge_children_d(rec: np.ndarray, scale_up: float = 1.0) -> np.ndarray:
     """Parent record of the children rec [k][59] in double, before rounding."""
     rec = np.ascontiguousarray(rec, dtype=np.float32)
     out = np.zeros(59, dtype=np.float64)
-    lib().or_merge_children_d(rec.ctypes.data, rec.shape[0], out.ctypes.data)
+    lib().or_merge_children_d(rec.ctypes.data, rec.shape[0], float(scale_up), out.ctypes.data)
     return out
 
 
@@ -192,12 +201,12 @@ _VM_DT = {"lod": np.float32, "pf_keys": np.uint64, "pf_x": np.float32, "pf_count
 class OracleScene:
     """Create-time data built by the oracle (Morton pages, proxy, links, LOD)."""
 
-    def __init__(self, scene, page_size, lod_levels=1, cell_m=0.5, link_sigma=2.0, attr_format=0):
+    def __init__(self, scene, page_size, lod_levels=1, cell_m=0.5, link_sigma=2.0, attr_format=0, lod_scale_up=1.0):
         self._keep = [np.ascontiguousarray(a, dtype=np.float32) for a in
                       (scene.means, scene.scales, scene.quats, scene.opacity, scene.sh)]
         s = _Scene(scene.n, *[a.ctypes.data for a in self._keep])
         self.ptr = lib().or_scene_build(C.byref(s), int(page_size), int(lod_levels), float(cell_m),
-                                        float(link_sigma), int(attr_format))
+                                        float(link_sigma), int(attr_format), float(lod_scale_up))
         if not self.ptr:
             raise ValueError("oracle: invalid scene parameters")
         self.page_size = page_size
@@ -222,7 +231,7 @@ class OracleVM:
     """Per-frame oracle state: page table over ``pool_pages`` physical pages."""
 
     def __init__(self, oscene: OracleScene, pool_pages, img, idbuf, copy_budget=0, use_links=True,
-                 lod_radius_px=32.0, guard_px=32.0):
+                 lod_radius_px=32.0, guard_px=32.0, support_box=False):
         self.scene = oscene
         self.W, self.H = img
         self.Wv, self.Hv = idbuf
@@ -231,6 +240,8 @@ class OracleVM:
                                       self.W, self.H, self.Wv, self.Hv, float(lod_radius_px), float(guard_px))
         if not self.ptr:
             raise ValueError("oracle: invalid VM parameters")
+        if support_box:
+            self.set_support_box(True)
 
     def frame(self, cams, tile_mask=None):
         arr = cams_array(cams)
@@ -283,9 +294,12 @@ class OracleVM:
     def set_adaptive_lod(self, on=True):
         lib().or_vm_set_adaptive_lod(self.ptr, int(bool(on)))
 
-    def set_sigma3_tiles(self, on=True):
-        """Tile rectangles from the 3-sigma radius alone (support box off)."""
-        lib().or_vm_set_sigma3_tiles(self.ptr, int(bool(on)))
+    def set_support_box(self, on=True):
+        """Cut each 3-sigma tile rectangle to the Gaussian's support box (the
+        pixels where a term can pass the alpha test).  Off by default; the
+        image is the same either way, and with it on the pair list is that of
+        a renderer that makes this cut."""
+        lib().or_vm_set_support_box(self.ptr, int(bool(on)))
 
     def get(self, name):
         n = lib().or_vm_get(self.ptr, name.encode(), None, 0)

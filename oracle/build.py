@@ -1,7 +1,9 @@
 """Compile the CPU oracle into oracle/liboracle.so (test infrastructure only).
 
 Plain C99, -O2, no fast-math and no floating-point contraction, so every
-float operation is the IEEE operation written in the source.
+float operation is the IEEE operation written in the source.  OpenMP runs the
+independent per-Gaussian and per-tile loops of the splat on several threads
+(or_set_threads; the results do not depend on the count).
 """
 import os
 import subprocess
@@ -15,7 +17,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 def build(verbose=False):
     srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
     cmd = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-           "-fno-strict-aliasing", "-D_GNU_SOURCE", "-Wall", "-Wno-unused-function",
+           "-fno-strict-aliasing", "-D_GNU_SOURCE", "-fopenmp", "-Wall", "-Wno-unused-function",
            "-o", LIB + ".tmp"] + srcs + ["-lm"]
     if verbose:
         print(" ".join(cmd))

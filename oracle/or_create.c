@@ -253,10 +253,13 @@ static void rot_to_quat(double R[3][3], double q[4])
  * covariance of the opacity-weighted mixture), opacity = min(1, sum o_i),
  * SH = sum w SH_i / W, w_i = o_i.  Sigma is written back as scale = sqrt of
  * its eigenvalues (descending) and the rotation of its eigenvectors as a
- * unit quaternion with w >= 0.  The record is produced in double
- * (or_merge_children_d) and stored rounded to float (or_merge_children).
- * All-zero opacities give the all-zero padding parent. */
-void or_merge_children_d(const float* c, int k, double* out)
+ * unit quaternion with w >= 0.  The section then scales the merged Gaussian
+ * up by a fixed factor, because a merged Gaussian covers less than the
+ * children it replaces: the scales are multiplied by scale_up (so Sigma by
+ * scale_up^2).  The record is produced in double (or_merge_children_d) and
+ * stored rounded to float (or_merge_children).  All-zero opacities give the
+ * all-zero padding parent. */
+void or_merge_children_d(const float* c, int k, double scale_up, double* out)
 {
     double W = 0.0, osum = 0.0;
     for (int i = 0; i < k; i++) { W += c[i * OR_REC + 10]; osum += c[i * OR_REC + 10]; }
@@ -290,7 +293,7 @@ void or_merge_children_d(const float* c, int k, double* out)
     double qd[4];
     rot_to_quat(V, qd);
     for (int a = 0; a < 3; a++) out[a] = mu[a];
-    for (int e = 0; e < 3; e++) out[3 + e] = sqrt(lam[e] > 0.0 ? lam[e] : 0.0);
+    for (int e = 0; e < 3; e++) out[3 + e] = scale_up * sqrt(lam[e] > 0.0 ? lam[e] : 0.0);
     for (int i = 0; i < 4; i++) out[6 + i] = qd[i];
     out[10] = osum < 1.0 ? osum : 1.0;
     for (int j = 0; j < 48; j++) {
@@ -300,10 +303,10 @@ void or_merge_children_d(const float* c, int k, double* out)
     }
 }
 
-void or_merge_children(const float* c, int k, float* out)
+void or_merge_children(const float* c, int k, double scale_up, float* out)
 {
     double d[OR_REC];
-    or_merge_children_d(c, k, d);
+    or_merge_children_d(c, k, scale_up, d);
     for (int a = 0; a < OR_REC; a++) out[a] = (float)d[a];
 }
 
@@ -314,7 +317,8 @@ static void round_half_form(float* rec)
 }
 
 /* ------------------------------------------------------------------------ */
-or_scene* or_scene_build(const or_scene_in* in, int P, int L, double cell_m, double link_sigma, int attr_format)
+or_scene* or_scene_build(const or_scene_in* in, int P, int L, double cell_m, double link_sigma, int attr_format,
+                         float lod_scale_up)
 {
     if (!in || in->n <= 0 || P <= 0 || L < 1 || L > 3 || cell_m <= 0.0) return NULL;
     for (int l = 1; l < L; l++) if ((P >> (3 * l)) << (3 * l) != P || (P >> (3 * l)) == 0) return NULL;
@@ -382,7 +386,7 @@ or_scene* or_scene_build(const or_scene_in* in, int P, int L, double cell_m, dou
         int64_t cnt = (int64_t)s->n_pg * (P >> (3 * l));
         s->attr[l] = calloc((size_t)cnt * OR_REC, sizeof(float));
         for (int64_t i = 0; i < cnt; i++)
-            or_merge_children(s->attr[l - 1] + (8 * i) * OR_REC, 8, s->attr[l] + i * OR_REC);
+            or_merge_children(s->attr[l - 1] + (8 * i) * OR_REC, 8, lod_scale_up, s->attr[l] + i * OR_REC);
     }
 
     /* proxy boxes: occupied cells of the means */

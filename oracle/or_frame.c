@@ -19,6 +19,9 @@
  *     back alpha blending.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -59,7 +62,6 @@ typedef struct {
     float rgb[3];
     int rect[4];   /* x0 y0 x1 y1, tiles, exclusive upper */
     int tiles;
-    float hy;      /* half height of the support box in pixels (infinite: none) */
 } pp_t;
 
 typedef struct { int32_t page, level, slot, sub, count; int64_t base; } rl_t;
@@ -72,7 +74,7 @@ struct or_vm {
     int P, L, n_pg, bytes_g;
     int frame;
     int force_all;         /* test switch: every page is directly requested */
-    int sigma3_tiles;      /* 1: tile rectangles from the 3-sigma radius alone (no support box) */
+    int support_box;       /* 1: 3-sigma tile rectangles cut to the support box (default 0: plain 3-sigma) */
     int last_full;         /* the last splat was or_render_full (every level-0 Gaussian) */
     /* LOD thresholds that follow memory use (Sec. 4.1, Sec. 5.1.1) */
     int adaptive;
@@ -536,12 +538,41 @@ static void prefetch_stage(or_vm* vm, uint8_t* req_sub, uint8_t* slot_req)
 }
 
 /* ---- 6. splatting -------------------------------------------------------- */
-static void preprocess_one(const float* g, const or_camera* c, int W, int H, int TX, int TY, int sigma3_tiles,
+/* Support box of a projected Gaussian (an optional cut of its tile
+ * rectangle, off by default).  Blending accepts a term only where
+ * power >= -5.55, that is where the quadratic form Q = d^T Sigma'^-1 d is at
+ * most 11.1; over a column at horizontal offset dx the smallest Q is
+ * dx^2 / Sigma'_xx, so the accepted region lies within
+ * |dx| <= sqrt(11.1 Sigma'_xx) (and the same for rows).  The float
+ * evaluation of the power errs by less than 5e-7 kap Q with
+ * kap = (a + c)^2 / det >= cond(Sigma') + 2, so the threshold is divided by
+ * (1 - 5e-7 kap), and one pixel is added; a footprint with 5e-7 kap >= 1/2
+ * keeps its rectangle.  Tiles outside the box hold no accepted pixel of the
+ * Gaussian, so cutting the rectangle to it leaves the image unchanged (pinned
+ * by image identity and a float64 brute force of the accepted region); it
+ * only predicts which pairs a renderer that makes this cut emits. */
+static void support_box_cut(float a, float cc, float det, float u, float v, int TX, int TY,
+                            float* x0, float* x1, float* y0, float* y1)
+{
+    float kap = ((a + cc) * (a + cc)) / det;
+    float e = 5e-7f * kap;
+    if (!(e < 0.5f)) return;
+    float f = 1.0f / (1.0f - e);
+    float hx = sqrtf((11.11f * f) * a) + 1.0f;
+    float hy = sqrtf((11.11f * f) * cc) + 1.0f;
+    float bx0 = fminf(fmaxf(floorf((u - hx) / 16.0f), 0.0f), (float)TX);
+    float bx1 = fminf(fmaxf(floorf((u + hx) / 16.0f) + 1.0f, 0.0f), (float)TX);
+    float by0 = fminf(fmaxf(floorf((v - hy) / 16.0f), 0.0f), (float)TY);
+    float by1 = fminf(fmaxf(floorf((v + hy) / 16.0f) + 1.0f, 0.0f), (float)TY);
+    *x0 = fmaxf(*x0, bx0); *x1 = fminf(*x1, bx1);
+    *y0 = fmaxf(*y0, by0); *y1 = fminf(*y1, by1);
+}
+
+static void preprocess_one(const float* g, const or_camera* c, int W, int H, int TX, int TY, int support_box,
                            pp_t* o)
 {
     memset(o, 0, sizeof *o);
     o->culled = 1;
-    o->hy = INFINITY;
     float op = g[10];
     if (op == 0.0f) return;                       /* padding */
     float t[3];
@@ -599,32 +630,7 @@ static void preprocess_one(const float* g, const or_camera* c, int W, int H, int
     float x1 = fminf(fmaxf(floorf(((u + rad) + 15.0f) / 16.0f), 0.0f), (float)TX);
     float y0 = fminf(fmaxf(floorf((v - rad) / 16.0f), 0.0f), (float)TY);
     float y1 = fminf(fmaxf(floorf(((v + rad) + 15.0f) / 16.0f), 0.0f), (float)TY);
-    /* Support box.  Blending accepts a term only where power >= -5.55, that
-     * is where the quadratic form Q = d^T Sigma'^-1 d is at most 11.1; over a
-     * column at horizontal offset dx the smallest Q is dx^2 / Sigma'_xx, so
-     * the accepted region lies within |dx| <= sqrt(11.1 Sigma'_xx) (and the
-     * same for rows).  The float evaluation of the power errs by less than
-     * 5e-7 kap Q with kap = (a + c)^2 / det >= cond(Sigma') + 2, so the
-     * threshold is divided by (1 - 5e-7 kap), and one pixel is added; a
-     * footprint with 5e-7 kap >= 1/2 keeps the 3-sigma rectangle.  Tiles
-     * outside the box hold no accepted pixel of this Gaussian, so the image
-     * is that of the 3-sigma rectangles. */
-    float hy = INFINITY;
-    if (!sigma3_tiles) {
-        float kap = ((a + cc) * (a + cc)) / det;
-        float e = 5e-7f * kap;
-        if (e < 0.5f) {
-            float f = 1.0f / (1.0f - e);
-            float hx = sqrtf((11.11f * f) * a) + 1.0f;
-            hy = sqrtf((11.11f * f) * cc) + 1.0f;
-            float bx0 = fminf(fmaxf(floorf((u - hx) / 16.0f), 0.0f), (float)TX);
-            float bx1 = fminf(fmaxf(floorf((u + hx) / 16.0f) + 1.0f, 0.0f), (float)TX);
-            float by0 = fminf(fmaxf(floorf((v - hy) / 16.0f), 0.0f), (float)TY);
-            float by1 = fminf(fmaxf(floorf((v + hy) / 16.0f) + 1.0f, 0.0f), (float)TY);
-            x0 = fmaxf(x0, bx0); x1 = fminf(x1, bx1);
-            y0 = fmaxf(y0, by0); y1 = fminf(y1, by1);
-        }
-    }
+    if (support_box) support_box_cut(a, cc, det, u, v, TX, TY, &x0, &x1, &y0, &y1);
     int ix0 = (int)x0, ix1 = (int)x1, iy0 = (int)y0, iy1 = (int)y1;
     if (ix1 <= ix0 || iy1 <= iy0) return;
     /* colour from SH in the viewing direction */
@@ -637,7 +643,6 @@ static void preprocess_one(const float* g, const or_camera* c, int W, int H, int
     o->opacity = op;
     o->rect[0] = ix0; o->rect[1] = iy0; o->rect[2] = ix1; o->rect[3] = iy1;
     o->tiles = (ix1 - ix0) * (iy1 - iy0);
-    o->hy = hy;
     (void)W; (void)H;
 }
 
@@ -660,9 +665,12 @@ static void splat(or_vm* vm, const or_camera* cams, int n_views, const uint8_t* 
     int64_t nt = (int64_t)n_views * TX * TY;
     free(vm->pp);
     vm->pp = malloc(sizeof(pp_t) * (size_t)(n_views * n_render > 0 ? n_views * n_render : 1));
-    for (int v = 0; v < n_views; v++)
+    /* independent per Gaussian (and below per tile): OpenMP threads when built with them */
+    for (int v = 0; v < n_views; v++) {
+        #pragma omp parallel for schedule(static)
         for (int64_t r = 0; r < n_render; r++)
-            preprocess_one(gauss[r], &cams[v], W, H, TX, TY, vm->sigma3_tiles, &vm->pp[v * n_render + r]);
+            preprocess_one(gauss[r], &cams[v], W, H, TX, TY, vm->support_box, &vm->pp[v * n_render + r]);
+    }
     /* bucket per tile */
     int64_t* cnt = calloc((size_t)nt + 1, sizeof(int64_t));
     for (int v = 0; v < n_views; v++)
@@ -700,6 +708,7 @@ static void splat(or_vm* vm, const or_camera* cams, int n_views, const uint8_t* 
     vm->keys = malloc(sizeof(uint64_t) * (size_t)(np > 0 ? np : 1));
     vm->vals = malloc(sizeof(uint32_t) * (size_t)(np > 0 ? np : 1));
     vm->ranges = calloc((size_t)nt * 2, sizeof(uint32_t));
+    #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < nt; t++) {
         qsort(lists + cnt[t], (size_t)(cnt[t + 1] - cnt[t]), sizeof(dk), cmp_dk);
         for (int64_t k = cnt[t]; k < cnt[t + 1]; k++) {
@@ -714,36 +723,37 @@ static void splat(or_vm* vm, const or_camera* cams, int n_views, const uint8_t* 
     vm->image = calloc((size_t)n_views * W * H * 3, sizeof(float));
     vm->final_T = calloc((size_t)n_views * W * H, sizeof(float));
     vm->contrib = calloc((size_t)n_views * W * H, sizeof(int64_t));
-    for (int v = 0; v < n_views; v++)
-        for (int ty = 0; ty < TY; ty++)
-            for (int tx = 0; tx < TX; tx++) {
-                int64_t t = (int64_t)v * TX * TY + ty * TX + tx;
-                if (tile_mask && !tile_mask[t]) continue;
-                for (int py = ty * 16; py < ty * 16 + 16 && py < H; py++)
-                    for (int px = tx * 16; px < tx * 16 + 16 && px < W; px++) {
-                        float T = 1.0f, C[3] = {0.0f, 0.0f, 0.0f};
-                        int64_t nb = 0;
-                        for (int64_t k = cnt[t]; k < cnt[t + 1]; k++) {
-                            pp_t* o = &vm->pp[v * n_render + vm->vals[k]];
-                            float dx = o->u - (float)px, dy = o->v - (float)py;
-                            float q = fmaf(o->conic[0] * dx, dx, (o->conic[2] * dy) * dy);
-                            float power = fmaf(-0.5f, q, -((o->conic[1] * dx) * dy));
-                            if (power > 0.0f) continue;
-                            float alpha = fminf(0.99f, o->opacity * or_vm_exp(power));
-                            if (alpha < 1.0f / 255.0f) continue;
-                            float Tn = T * (1.0f - alpha);
-                            if (Tn < 0.0001f) break;
-                            float wgt = alpha * T;
-                            for (int ch = 0; ch < 3; ch++) C[ch] = fmaf(o->rgb[ch], wgt, C[ch]);
-                            T = Tn;
-                            nb++;
-                        }
-                        int64_t pix = ((int64_t)v * H + py) * W + px;
-                        for (int ch = 0; ch < 3; ch++) vm->image[pix * 3 + ch] = C[ch];
-                        vm->final_T[pix] = T;
-                        vm->contrib[pix] = nb;
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < nt; t++) {
+            int v = (int)(t / ((int64_t)TX * TY));
+            int ty = (int)((t % ((int64_t)TX * TY)) / TX);
+            int tx = (int)(t % TX);
+            if (tile_mask && !tile_mask[t]) continue;
+            for (int py = ty * 16; py < ty * 16 + 16 && py < H; py++)
+                for (int px = tx * 16; px < tx * 16 + 16 && px < W; px++) {
+                    float T = 1.0f, C[3] = {0.0f, 0.0f, 0.0f};
+                    int64_t nb = 0;
+                    for (int64_t k = cnt[t]; k < cnt[t + 1]; k++) {
+                        pp_t* o = &vm->pp[v * n_render + vm->vals[k]];
+                        float dx = o->u - (float)px, dy = o->v - (float)py;
+                        float q = fmaf(o->conic[0] * dx, dx, (o->conic[2] * dy) * dy);
+                        float power = fmaf(-0.5f, q, -((o->conic[1] * dx) * dy));
+                        if (power > 0.0f) continue;
+                        float alpha = fminf(0.99f, o->opacity * or_vm_exp(power));
+                        if (alpha < 1.0f / 255.0f) continue;
+                        float Tn = T * (1.0f - alpha);
+                        if (Tn < 0.0001f) break;
+                        float wgt = alpha * T;
+                        for (int ch = 0; ch < 3; ch++) C[ch] = fmaf(o->rgb[ch], wgt, C[ch]);
+                        T = Tn;
+                        nb++;
                     }
-            }
+                    int64_t pix = ((int64_t)v * H + py) * W + px;
+                    for (int ch = 0; ch < 3; ch++) vm->image[pix * 3 + ch] = C[ch];
+                    vm->final_T[pix] = T;
+                    vm->contrib[pix] = nb;
+                }
+        }
     free(lists); free(cnt);
 }
 
@@ -1000,7 +1010,20 @@ int or_vm_frame_prefetch(or_vm* vm, const or_camera* cams, int n_views, const fl
     return r;
 }
 
-void or_vm_set_sigma3_tiles(or_vm* vm, int on) { vm->sigma3_tiles = on; }
+void or_vm_set_support_box(or_vm* vm, int on) { vm->support_box = on; }
+
+/* threads of the per-Gaussian and per-tile loops (1 = single-threaded;
+ * returns the count in use, 1 when built without OpenMP) */
+int or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 void or_vm_set_adaptive_lod(or_vm* vm, int on) { vm->adaptive = on; }
 
@@ -1205,13 +1228,12 @@ int64_t or_vm_get(const or_vm* vm, const char* name, void* dst, int64_t cap)
             }
         return bytes;
     }
-    if (!strcmp(name, "pp_float")) {         /* [n][11] u v depth conic3 opacity rgb3 hy */
-        int64_t bytes = 44 * npp;
+    if (!strcmp(name, "pp_float")) {         /* [n][10] u v depth conic3 opacity rgb3 */
+        int64_t bytes = 40 * npp;
         if (dst && cap >= bytes)
             for (int64_t i = 0; i < npp; i++) {
                 const pp_t* o = &vm->pp[i];
-                float* f = (float*)dst + 11 * i;
-                f[10] = o->hy;
+                float* f = (float*)dst + 10 * i;
                 f[0] = o->u; f[1] = o->v; f[2] = o->depth;
                 f[3] = o->conic[0]; f[4] = o->conic[1]; f[5] = o->conic[2];
                 f[6] = o->opacity; f[7] = o->rgb[0]; f[8] = o->rgb[1]; f[9] = o->rgb[2];

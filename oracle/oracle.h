@@ -48,15 +48,16 @@ double or_sh_basis(int k, double x, double y, double z);
 
 /* ---- create time (Sec. 3) ---- */
 or_scene* or_scene_build(const or_scene_in* in, int page_size, int lod_levels,
-                         double cell_m, double link_sigma, int attr_format);
+                         double cell_m, double link_sigma, int attr_format, float lod_scale_up);
 void or_scene_free(or_scene* s);
 int64_t or_scene_get(const or_scene* s, const char* name, void* dst, int64_t cap);
 
 /* Parent of k children by opacity-weighted moment matching (Sec. 3 "Level
- * of Detail", read as moment matching): out[59] in double, and the stored
- * float record. */
-void or_merge_children_d(const float* children, int k, double* out);
-void or_merge_children(const float* children, int k, float* out);
+ * of Detail", read as moment matching), its scales then multiplied by
+ * scale_up (the section's fixed factor that fills gaps; 1 = moment matching
+ * alone): out[59] in double, and the stored float record. */
+void or_merge_children_d(const float* children, int k, double scale_up, double* out);
+void or_merge_children(const float* children, int k, double scale_up, float* out);
 
 /* ---- per frame (Sec. 4) ---- */
 /* guard_px: the page-ID buffer and the frustum extend this many pixels past
@@ -81,7 +82,9 @@ int or_vm_pagetable(or_vm* vm, int n, const int32_t* pages, const int8_t* levels
 /* Test switches: every page directly requested; tile rectangles from the
  * 3-sigma radius alone (the support box off). */
 void or_vm_set_force_all(or_vm* vm, int on);
-void or_vm_set_sigma3_tiles(or_vm* vm, int on);
+void or_vm_set_support_box(or_vm* vm, int on);
+/* OpenMP threads of the splat loops (n > 0 sets; returns the count in use) */
+int or_set_threads(int n);
 /* LOD thresholds that follow memory use (several levels only). */
 void or_vm_set_adaptive_lod(or_vm* vm, int on);
 /* Level of a page (Sec. 4.1 "Level of Detail"): the first l with projected

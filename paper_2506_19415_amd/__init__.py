@@ -41,7 +41,7 @@ class vm3dgs_options(C.Structure):
                 ("max_views", C.c_uint32), ("attr_format", C.c_uint32), ("copy_budget_pages", C.c_uint32),
                 ("idbuf_guard_px", C.c_float), ("proxy_cell_m", C.c_float), ("link_sigma", C.c_float),
                 ("lod_radius_px", C.c_float), ("flags", C.c_uint32), ("stream_render", C.c_void_p),
-                ("stream_copy", C.c_void_p), ("pair_capacity", C.c_uint64)]
+                ("stream_copy", C.c_void_p), ("pair_capacity", C.c_uint64), ("lod_scale_up", C.c_float)]
 
 
 class vm3dgs_camera(C.Structure):
@@ -65,6 +65,26 @@ class vm3dgs_stats(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class vm3dgs_dataset(C.Structure):
+    _fields_ = [("cams", C.c_void_p), ("path_frames", C.c_void_p), ("n_paths", C.c_uint32)]
+
+
+class vm3dgs_train_opts(C.Structure):
+    _fields_ = [("steps", C.c_uint32), ("batch", C.c_uint32), ("lr", C.c_float), ("seed", C.c_uint64),
+                ("proposal_factor", C.c_float), ("log_every", C.c_uint32)]
+
+
+class vm3dgs_train_log(C.Structure):
+    _fields_ = [("rows", C.c_uint64), ("positive_rate", C.c_float), ("loss_first", C.c_float),
+                ("loss_last", C.c_float), ("logit_threshold", C.c_float), ("ms_collect", C.c_float),
+                ("ms_train", C.c_float), ("n_losses", C.c_uint32), ("losses", C.c_float * 64)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "losses"}
+        d["losses"] = [float(self.losses[i]) for i in range(self.n_losses)]
+        return d
 
 
 class vm3dgs_frame_out(C.Structure):
@@ -97,6 +117,8 @@ def lib():
         L.vm3dgs_debug_get.restype = C.c_int64
         L.vm3dgs_set_flags.argtypes = [C.c_void_p, C.c_uint32]
         L.vm3dgs_set_flags.restype = C.c_int32
+        L.vm3dgs_set_lod_radius.argtypes = [C.c_void_p, C.c_float]
+        L.vm3dgs_set_lod_radius.restype = C.c_int32
         L.vm3dgs_sync.argtypes = [C.c_void_p]
         L.vm3dgs_sync.restype = C.c_int32
         L.vm3dgs_last_error.argtypes = [C.c_void_p]
@@ -133,6 +155,15 @@ def lib():
         L.vm3dgs_set_prefetch.restype = C.c_int32
         L.vm3dgs_prefetch_features.argtypes = [vp, u32, vp]
         L.vm3dgs_prefetch_features.restype = C.c_int32
+        L.vm3dgs_prefetch_collect.argtypes = [vp, C.POINTER(vm3dgs_dataset), vp, vp, C.c_uint64,
+                                              C.POINTER(C.c_uint64)]
+        L.vm3dgs_prefetch_collect.restype = C.c_int32
+        L.vm3dgs_prefetch_train.argtypes = [vp, C.POINTER(vm3dgs_dataset), C.POINTER(vm3dgs_train_opts),
+                                            C.POINTER(vm3dgs_train_log)]
+        L.vm3dgs_prefetch_train.restype = C.c_int32
+        for name in ("vm3dgs_mlp_save", "vm3dgs_mlp_load", "vm3dgs_prefetch_load"):
+            getattr(L, name).argtypes = [vp, C.c_char_p]
+            getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
 
@@ -228,6 +259,10 @@ def vm3dgs_set_flags(h, flags: int):
     _check(h, lib().vm3dgs_set_flags(h, int(flags)))
 
 
+def vm3dgs_set_lod_radius(h, tau_px: float):
+    _check(h, lib().vm3dgs_set_lod_radius(h, float(tau_px)))
+
+
 def vm3dgs_sync(h):
     _check(h, lib().vm3dgs_sync(h))
 
@@ -242,7 +277,7 @@ class Renderer:
 
     def __init__(self, scene, page_size, pool_pages, lod_levels=1, img=(1920, 1080), idbuf=(240, 135),
                  max_views=1, attr_format=0, cell=1.0, link_sigma=2.0, lod_radius_px=32.0, links=True,
-                 full_scene=False, copy_budget=0, pair_capacity=0, guard_px=32.0):
+                 full_scene=False, copy_budget=0, pair_capacity=0, guard_px=32.0, lod_scale_up=1.0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Renderer needs a HIP device")
@@ -256,6 +291,7 @@ class Renderer:
         o.proxy_cell_m, o.link_sigma, o.lod_radius_px = cell, link_sigma, lod_radius_px
         o.flags = (VM3DGS_FLAG_LINKS if links else 0) | (VM3DGS_FLAG_FULL_SCENE_COPY if full_scene else 0)
         o.pair_capacity = pair_capacity
+        o.lod_scale_up = lod_scale_up
         self.opts = o
         self.W, self.H = img
         self.h = vm3dgs_create(scene, page_size, pool_pages, lod_levels, o)
@@ -294,12 +330,50 @@ class Renderer:
         if rc != 0:
             raise Vm3dgsError(rc, lib().vm3dgs_last_error(self.h).decode())
         self.pf_net = net
+        self.pf_opts = o
         self.pf_width = 28 + int(hist_bins)
 
     def reset(self):
         rc = lib().vm3dgs_reset(self.h)
         if rc != 0:
             raise Vm3dgsError(rc, lib().vm3dgs_last_error(self.h).decode())
+
+    def _dataset(self, paths):
+        """A vm3dgs_dataset of camera paths (one view per frame); the arrays
+        it points to are returned with it and must outlive the call."""
+        cams = [c for p in paths for c in p]
+        arr = _cameras(cams)
+        frames = (C.c_uint32 * len(paths))(*[len(p) for p in paths])
+        return vm3dgs_dataset(C.cast(arr, C.c_void_p), C.cast(frames, C.c_void_p), len(paths)), (arr, frames)
+
+    def prefetch_collect(self, paths):
+        """vm3dgs_prefetch_collect: feature and label rows of the paths."""
+        ds, keep = self._dataset(paths)
+        rows = sum(max(len(p) - 1, 0) for p in paths)
+        o = self.pf_opts
+        X = np.zeros((rows, 28 + o.hist_bins), np.float32)
+        Y = np.zeros((rows, o.n_clusters), np.float32)
+        n = C.c_uint64()
+        rc = lib().vm3dgs_prefetch_collect(self.h, C.byref(ds), X.ctypes.data, Y.ctypes.data, rows, C.byref(n))
+        if rc != 0:
+            raise Vm3dgsError(rc, lib().vm3dgs_last_error(self.h).decode())
+        return X[:n.value], Y[:n.value]
+
+    def prefetch_train(self, paths, steps, batch=256, lr=1e-3, seed=0, proposal_factor=0.0, log_every=0):
+        """vm3dgs_prefetch_train on the attached network; returns the log."""
+        ds, keep = self._dataset(paths)
+        t = vm3dgs_train_opts(int(steps), int(batch), float(lr), int(seed), float(proposal_factor), int(log_every))
+        log_ = vm3dgs_train_log()
+        rc = lib().vm3dgs_prefetch_train(self.h, C.byref(ds), C.byref(t), C.byref(log_))
+        if rc != 0:
+            raise Vm3dgsError(rc, lib().vm3dgs_last_error(self.h).decode())
+        self.pf_opts.logit_threshold = log_.logit_threshold
+        return log_.as_dict()
+
+    def prefetch_load(self, path):
+        rc = lib().vm3dgs_prefetch_load(self.h, str(path).encode())
+        if rc != 0:
+            raise Vm3dgsError(rc, "vm3dgs_prefetch_load failed")
 
     def prefetch_features(self, n_views=1):
         x = np.zeros((n_views, self.pf_width), np.float32)
@@ -311,6 +385,9 @@ class Renderer:
     def set_flags(self, flags):
         vm3dgs_set_flags(self.h, flags)
         self.opts.flags = (self.opts.flags & VM3DGS_FLAG_FULL_SCENE_COPY) | (flags & ~VM3DGS_FLAG_FULL_SCENE_COPY)
+
+    def set_lod_radius(self, tau_px):
+        vm3dgs_set_lod_radius(self.h, tau_px)
 
     def get(self, name, dtype):
         return vm3dgs_debug_get(self.h, name, dtype)
@@ -394,6 +471,12 @@ class Mlp:
                                                 C.byref(loss) if want_loss else None))
         self.sync()
         return loss.value if want_loss else None
+
+    def save(self, path):
+        self._check(lib().vm3dgs_mlp_save(self.h, str(path).encode()))
+
+    def load(self, path):
+        self._check(lib().vm3dgs_mlp_load(self.h, str(path).encode()))
 
     def sync(self):
         self._check(lib().vm3dgs_mlp_sync(self.h))

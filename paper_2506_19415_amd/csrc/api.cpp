@@ -410,6 +410,19 @@ void pf_features(vm3dgs* c, uint32_t n_views) {
     launch_pf_features(c->sr, c->d_v2p, c->n_pg, c->L, (int)c->pf.hist_bins, (int)n_views, c->d_pf_x);
 }
 
+}  // namespace
+
+namespace vm {
+bool prefetch_stage_of(const vm3dgs* c, vm3dgs_mlp** net, vm3dgs_prefetch_opts* opts) {
+    if (!c || !c->pf_on) return false;
+    if (net) *net = c->pf_net;
+    if (opts) *opts = c->pf;
+    return true;
+}
+}  // namespace vm
+
+namespace {
+
 // The LOD thresholds follow memory use (Sec. 5.1.1, with Sec. 4.1 and
 // Sec. 5.3).  The aim is 50-80 % of the pool, usage being the share of
 // physical pages the frame required.  Over 80 %, or with requests left
@@ -462,6 +475,7 @@ void vm3dgs_options_default(vm3dgs_options* o) {
     o->attr_format = 0; o->copy_budget_pages = 0;
     o->proxy_cell_m = 1.0f; o->link_sigma = 2.0f; o->lod_radius_px = 32.0f; o->idbuf_guard_px = 32.0f;
     o->flags = VM3DGS_FLAG_LINKS;
+    o->lod_scale_up = 1.0f;
 }
 
 const char* vm3dgs_create_error(void) { return g_create_error.c_str(); }
@@ -488,6 +502,7 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
     if (!(o.proxy_cell_m > 0.0f) || !(o.link_sigma >= 0.0f) || !(o.lod_radius_px > 0.0f) ||
         !(o.idbuf_guard_px >= 0.0f && o.idbuf_guard_px <= 4096.0f))
         return inval("proxy_cell_m, link_sigma, lod_radius_px out of range");
+    if (!(o.lod_scale_up > 0.0f && o.lod_scale_up <= 16.0f)) return inval("lod_scale_up must be in (0, 16]");
     if (scene->n > (uint64_t)INT32_MAX * page_size) return inval("scene too large");
 
     vm3dgs* c = new (std::nothrow) vm3dgs();
@@ -495,7 +510,7 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
     c->opt = o;
     try {
         std::string e = build_paged_scene(*scene, (int)page_size, (int)lod_levels, (int)o.attr_format,
-                                          (double)o.proxy_cell_m, (double)o.link_sigma, c->ps);
+                                          (double)o.proxy_cell_m, (double)o.link_sigma, (double)o.lod_scale_up, c->ps);
         if (!e.empty()) { g_create_error = e; delete c; return VM3DGS_E_INVALID_ARG; }
     } catch (const std::bad_alloc&) {
         g_create_error = "host allocation failed";
@@ -928,6 +943,14 @@ vm3dgs_status vm3dgs_set_flags(vm3dgs* c, uint32_t flags) {
     return VM3DGS_OK;
 }
 
+vm3dgs_status vm3dgs_set_lod_radius(vm3dgs* c, float tau_px) {
+    if (!c) return VM3DGS_E_INVALID_ARG;
+    if (!(tau_px > 0.0f) || !std::isfinite(tau_px)) return bad(c, "tau_px must be a positive finite number");
+    c->opt.lod_radius_px = tau_px;
+    c->lod_tau = tau_px; c->lod_step = kLodStep0; c->lod_dir = 0; c->lod_last_move = c->frame;
+    return VM3DGS_OK;
+}
+
 vm3dgs_status vm3dgs_sync(vm3dgs* c) {
     if (!c) return VM3DGS_E_INVALID_ARG;
     if (c->poisoned) return VM3DGS_E_STATE;
@@ -968,8 +991,9 @@ vm3dgs_status vm3dgs_pages_build(const vm3dgs_scene* scene, uint32_t page_size, 
         g_create_error = "scene is NULL or empty";
         return VM3DGS_E_INVALID_ARG;
     }
-    if (page_size == 0 || lod_levels < 1 || lod_levels > 3 || o.attr_format > 1 || !(o.proxy_cell_m > 0.0f)) {
-        g_create_error = "page_size, lod_levels, attr_format or proxy_cell_m out of range";
+    if (page_size == 0 || lod_levels < 1 || lod_levels > 3 || o.attr_format > 1 || !(o.proxy_cell_m > 0.0f) ||
+        !(o.lod_scale_up > 0.0f && o.lod_scale_up <= 16.0f)) {
+        g_create_error = "page_size, lod_levels, attr_format, proxy_cell_m or lod_scale_up out of range";
         return VM3DGS_E_INVALID_ARG;
     }
     for (uint32_t l = 1; l < lod_levels; ++l)
@@ -981,7 +1005,7 @@ vm3dgs_status vm3dgs_pages_build(const vm3dgs_scene* scene, uint32_t page_size, 
     if (!p) return VM3DGS_E_HOST_OOM;
     try {
         std::string e = build_paged_scene(*scene, (int)page_size, (int)lod_levels, (int)o.attr_format,
-                                          (double)o.proxy_cell_m, (double)o.link_sigma, p->ps);
+                                          (double)o.proxy_cell_m, (double)o.link_sigma, (double)o.lod_scale_up, p->ps);
         if (!e.empty()) { g_create_error = e; delete p; return VM3DGS_E_INVALID_ARG; }
         p->store.resize((size_t)p->ps.store_bytes);
         encode_store(p->ps, p->store.data());

@@ -202,8 +202,9 @@ void quat_of(const double R[3][3], double q[4]) {
         for (int i = 0; i < 4; ++i) q[i] = -q[i];
 }
 
-// moment matching of k children into one parent (all-zero when no opacity)
-void merge(const float* ch, int k, float* out) {
+// moment matching of k children into one parent (all-zero when no opacity);
+// the parent's scales are then multiplied by scale_up
+void merge(const float* ch, int k, double scale_up, float* out) {
     double W = 0.0, osum = 0.0;
     for (int i = 0; i < k; ++i) { W += ch[i * REC + 10]; osum += ch[i * REC + 10]; }
     memset(out, 0, sizeof(float) * REC);
@@ -236,7 +237,7 @@ void merge(const float* ch, int k, float* out) {
     eigen_sym3(S, lam, V);
     quat_of(V, q);
     for (int a = 0; a < 3; ++a) out[a] = (float)mu[a];
-    for (int e = 0; e < 3; ++e) out[3 + e] = (float)sqrt(lam[e] > 0.0 ? lam[e] : 0.0);
+    for (int e = 0; e < 3; ++e) out[3 + e] = (float)(scale_up * sqrt(lam[e] > 0.0 ? lam[e] : 0.0));
     for (int i = 0; i < 4; ++i) out[6 + i] = (float)q[i];
     out[10] = (float)(osum < 1.0 ? osum : 1.0);
     for (int j = 0; j < 48; ++j) {
@@ -312,7 +313,7 @@ inline float bf16_to_f32(uint16_t b) {
 }  // namespace
 
 std::string build_paged_scene(const vm3dgs_scene& sc, int P, int L, int fmt, double cell_m, double link_sigma,
-                              PagedScene& ps) {
+                              double lod_scale_up, PagedScene& ps) {
     const int64_t n = (int64_t)sc.n;
     ps = PagedScene();
     ps.n_in = n; ps.P = P; ps.L = L; ps.fmt = fmt;
@@ -381,7 +382,7 @@ std::string build_paged_scene(const vm3dgs_scene& sc, int P, int L, int fmt, dou
         const float* src = ps.rec[l - 1].data();
         float* dst = ps.rec[l].data();
         parallel_for(cnt, [&](int64_t a, int64_t b) {
-            for (int64_t i = a; i < b; ++i) merge(src + (size_t)(8 * i) * REC, 8, dst + (size_t)i * REC);
+            for (int64_t i = a; i < b; ++i) merge(src + (size_t)(8 * i) * REC, 8, lod_scale_up, dst + (size_t)i * REC);
         });
     }
 

@@ -188,9 +188,26 @@ __global__ void k_w_to_bf16(const float* __restrict__ w, int64_t off, int n, uin
     if (i < n) wb[i] = to_bf16(w[off + i]);
 }
 
+// rows idx[i] of src [.][width] into dst [i][width] (training minibatches)
+__global__ void k_gather_rows(const float* __restrict__ src, const uint32_t* __restrict__ idx, uint32_t n,
+                              uint32_t width, float* __restrict__ dst) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (uint64_t)n * width) return;
+    const uint64_t r = i / width, c = i - r * width;
+    dst[i] = src[(uint64_t)idx[r] * width + c];
+}
+
 }  // namespace vmk
 
 namespace vm {
+
+void launch_gather_rows(hipStream_t st, const float* src, const uint32_t* idx, uint32_t n, uint32_t width,
+                        float* dst) {
+    const uint64_t total = (uint64_t)n * width;
+    if (total == 0) return;
+    hipLaunchKernelGGL(vmk::k_gather_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, src, idx, n, width,
+                       dst);
+}
 using namespace vmk;
 
 static unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }

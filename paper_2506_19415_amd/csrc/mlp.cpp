@@ -3,6 +3,7 @@
 // and the per-batch activations on the device; every step is a kernel of
 // k_mlp.hip on the network's stream.
 #include <hip/hip_runtime.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -73,6 +74,7 @@ const char* vm3dgs_mlp_create_error(void) { return g_mlp_create_error.c_str(); }
 namespace vm {
 const MlpDev* mlp_dev_of(const vm3dgs_mlp* net) { return &net->d; }
 int mlp_max_batch_of(const vm3dgs_mlp* net) { return net->max_batch; }
+hipStream_t mlp_stream_of(const vm3dgs_mlp* net) { return net->st; }
 }  // namespace vm
 
 extern "C" {
@@ -232,6 +234,44 @@ vm3dgs_status vm3dgs_mlp_train_step(vm3dgs_mlp* m, const float* x, const float* 
         return fail(m, f);
     }
     return VM3DGS_OK;
+}
+
+// "VM3DGSNN", uint32 n_layers, uint32 dims[n_layers + 1], float params[n_params]
+static const char kMlpMagic[8] = {'V', 'M', '3', 'D', 'G', 'S', 'N', 'N'};
+
+vm3dgs_status vm3dgs_mlp_save(vm3dgs_mlp* m, const char* path) {
+    if (!m || !path) return VM3DGS_E_INVALID_ARG;
+    std::vector<float> p((size_t)m->n_params);
+    const vm3dgs_status st = vm3dgs_mlp_get_state(m, p.data(), nullptr, nullptr, (uint64_t)m->n_params, nullptr);
+    if (st != VM3DGS_OK) return st;
+    FILE* f = fopen(path, "wb");
+    if (!f) { m->err = std::string("cannot open ") + path + " for writing"; return VM3DGS_E_INVALID_ARG; }
+    const uint32_t nl = (uint32_t)m->d.n_layers;
+    uint32_t dims[9];
+    for (int l = 0; l <= m->d.n_layers; ++l) dims[l] = (uint32_t)m->d.dims[l];
+    const bool ok = fwrite(kMlpMagic, 1, 8, f) == 8 && fwrite(&nl, 4, 1, f) == 1 &&
+                    fwrite(dims, 4, nl + 1, f) == nl + 1 && fwrite(p.data(), 4, p.size(), f) == p.size();
+    if (fclose(f) != 0 || !ok) { m->err = std::string("write to ") + path + " failed"; return VM3DGS_E_INVALID_ARG; }
+    return VM3DGS_OK;
+}
+
+vm3dgs_status vm3dgs_mlp_load(vm3dgs_mlp* m, const char* path) {
+    if (!m || !path) return VM3DGS_E_INVALID_ARG;
+    FILE* f = fopen(path, "rb");
+    if (!f) { m->err = std::string("cannot open ") + path; return VM3DGS_E_INVALID_ARG; }
+    char magic[8];
+    uint32_t nl = 0, dims[9];
+    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kMlpMagic, 8) == 0 && fread(&nl, 4, 1, f) == 1 &&
+              nl == (uint32_t)m->d.n_layers && fread(dims, 4, nl + 1, f) == nl + 1;
+    for (uint32_t l = 0; ok && l <= nl; ++l) ok = dims[l] == (uint32_t)m->d.dims[l];
+    std::vector<float> p;
+    if (ok) {
+        p.resize((size_t)m->n_params);
+        ok = fread(p.data(), 4, p.size(), f) == p.size() && fgetc(f) == EOF;
+    }
+    fclose(f);
+    if (!ok) { m->err = std::string(path) + " is not a network of these widths"; return VM3DGS_E_INVALID_ARG; }
+    return vm3dgs_mlp_set_params(m, p.data(), (uint64_t)p.size());
 }
 
 vm3dgs_status vm3dgs_mlp_sync(vm3dgs_mlp* m) {

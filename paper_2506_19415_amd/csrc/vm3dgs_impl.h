@@ -34,7 +34,7 @@ struct PagedScene {
 
 // Builds everything of Sec. 3 for the library; returns "" or an error text.
 std::string build_paged_scene(const vm3dgs_scene& sc, int page_size, int lod_levels, int fmt, double cell_m,
-                              double link_sigma, PagedScene& out);
+                              double link_sigma, double lod_scale_up, PagedScene& out);
 // Writes the page-major SoA store of every level into dst (store_bytes).
 void encode_store(const PagedScene& ps, uint8_t* dst);
 
@@ -234,6 +234,12 @@ void launch_pf_features(hipStream_t st, const int32_t* v2p, int n_pg, int L, int
 void launch_prefetch(hipStream_t st, const PfArgs& a, SortWork& sw);
 const MlpDev* mlp_dev_of(const vm3dgs_mlp* net);
 int mlp_max_batch_of(const vm3dgs_mlp* net);
+hipStream_t mlp_stream_of(const vm3dgs_mlp* net);
+// rows idx[i] of src [.][width] into dst [n][width] (k_mlp.hip)
+void launch_gather_rows(hipStream_t st, const float* src, const uint32_t* idx, uint32_t n, uint32_t width,
+                        float* dst);
+// the prefetch stage of a context: its network (or NULL) and options; false without a stage
+bool prefetch_stage_of(const vm3dgs* ctx, vm3dgs_mlp** net, vm3dgs_prefetch_opts* opts);
 
 // copies of the misses by the GPU from the pinned host store (one command per
 // 16 KB chunk and workgroup); bytes_done accumulates the bytes copied

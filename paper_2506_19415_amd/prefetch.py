@@ -1,19 +1,16 @@
-"""Training and evaluation of the learned page prefetch (host driver).
+"""Evaluation of the learned page prefetch (host driver).
 
 The paper names prefetching as future work (Sec. 6).  Here a network proposes
 lowest-priority page requests from the last four camera poses and the
 current residency; the visibility pass keeps deciding what is rendered.
+Training rows, labels and the training itself are the library's
+(vm3dgs_prefetch_collect, vm3dgs_prefetch_train); this module orders calls
+and measures:
 
-- ``collect``: plain frames (no prefetch) along camera paths; for each frame t
-  the feature row after its page table and the label row: the clusters that
-  hold a page requested at t+1 that was not resident after t.
-- ``train``: minibatch Adam on the GPU with the library's own kernels.
-- ``evaluate``: the same paths with and without the network: demand misses per
-  frame, the stall (the copy stage's milliseconds), and the proposals' recall
-  and precision against the next frame's requests.
-
-Every step runs in the library (frames, features, forward, backward, Adam);
-this module only orders the calls and keeps the arrays.
+- ``collect``: the library's feature and label rows of plain frames.
+- ``evaluate``: the same paths with and without the network: demand misses
+  per frame, the stall (the copy stage's milliseconds), and the proposals'
+  recall and precision against the next frame's requests.
 """
 import numpy as np
 
@@ -30,63 +27,12 @@ def _resident(r, n_pg, L):
     return (v2p >= 0).any(1)
 
 
-def _clusters(pages, n_pg, K):
-    return (np.asarray(pages, np.int64) * K) // n_pg
-
-
 def collect(r, paths, n_clusters, hist_bins, center, extent):
-    """Feature and label rows of every frame but the last of each path.
+    """Feature and label rows of every frame but the last of each path, from
+    the library (the stage is attached without a network first).
     r: a Renderer of one view; it is reset before each path."""
-    n_pg, L = int(r.get("info", np.int64)[0]), int(r.get("info", np.int64)[2])
     r.set_prefetch(None, n_clusters, hist_bins, 0.0, 0, center, extent)
-    X, Y = [], []
-    for cams in paths:
-        r.reset()
-        prev_x = prev_res = None
-        for cam in cams:
-            _, out = r.frame([cam])
-            req = np.ctypeslib.as_array(out.requests, (out.n_requests,)).copy() if out.n_requests else \
-                np.zeros(0, np.int32)
-            if prev_x is not None:
-                new = req[~prev_res[req]]
-                y = np.zeros(n_clusters, np.float32)
-                y[_clusters(new, n_pg, n_clusters)] = 1.0
-                X.append(prev_x)
-                Y.append(y)
-            prev_x = r.prefetch_features(1)[0]
-            prev_res = _resident(r, n_pg, L)
-    return np.stack(X), np.stack(Y)
-
-
-def train(net, X, Y, steps, batch=256, lr=1e-3, seed=0, log_every=0):
-    """Minibatch Adam steps on the GPU; returns the loss of each logged step."""
-    import torch
-    rng = np.random.default_rng(seed)
-    Xd = torch.tensor(X, device="cuda")
-    Yd = torch.tensor(Y, device="cuda")
-    losses = []
-    n = X.shape[0]
-    for it in range(steps):
-        idx = torch.tensor(rng.integers(0, n, batch), device="cuda")
-        want = log_every and (it % log_every == 0 or it == steps - 1)
-        loss = net.train_step(Xd[idx].contiguous(), Yd[idx].contiguous(), lr, want_loss=bool(want))
-        if want:
-            losses.append((it, loss))
-    net.sync()
-    return losses
-
-
-def calibrate_threshold(net, X, Y, factor=2.0, batch=256):
-    """The logit threshold at which the network proposes about `factor` times
-    as many clusters as the labels hold on the rows X (positives are rare,
-    so the plain 0.5 probability proposes almost nothing)."""
-    import torch
-    zs = []
-    for i in range(0, X.shape[0], batch):
-        zs.append(net.forward(torch.tensor(X[i:i + batch], device="cuda")).cpu().numpy())
-    z = np.concatenate(zs).ravel()
-    q = min(max(1.0 - factor * float(Y.mean()), 0.0), 1.0)
-    return float(np.quantile(z, q))
+    return r.prefetch_collect(paths)
 
 
 def evaluate(r, net, paths, n_clusters, hist_bins, threshold, budget, center, extent, skip=2):

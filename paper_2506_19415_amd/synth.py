@@ -390,10 +390,16 @@ def path_terrain(scene: Scene, n_frames: int = 300, width: int = 1920, height: i
 # City (LOD configuration), scalable so tests can run a small copy
 # --------------------------------------------------------------------------
 def scene_city(seed: int = 0, n: int = 50_000_000, size: float = 1000.0, block: float = 100.0,
-               street: float = 20.0) -> Scene:
+               street: float = 20.0, color: str = "iid") -> Scene:
     """Street grid of 100 m blocks with 20 m streets; 1-6 buildings per block
     with log-normal heights clipped to 10-150 m; Gaussians split over ground,
-    facades and roofs by area."""
+    facades and roofs by area.
+
+    color: "iid" draws every SH coefficient of every Gaussian independently
+    (N(0, 0.3^2), DC + 0.5), as the cluster and terrain scenes do; "smooth"
+    gives colours that vary smoothly over the surfaces (see _city_colours);
+    "white" makes every Gaussian white with no view dependence, so that an
+    image shows coverage (1 - final transmittance) alone."""
     rng = np.random.Generator(np.random.PCG64(seed))
     nb = int(round(size / block))
     half = size / 2
@@ -431,7 +437,8 @@ def scene_city(seed: int = 0, n: int = 50_000_000, size: float = 1000.0, block: 
                          0.7 * sp * np.exp(rng.normal(0, 0.2, n_ground)),
                          np.full(n_ground, 0.02)], 1)]
     parts_n = [np.tile(np.array([[0.0, 0.0, 1.0]]), (n_ground, 1))]
-    for (cx, cy, w, d, h), c in zip(boxes, per_box):
+    parts_o = [np.full(n_ground, -1, np.int32)]
+    for b, ((cx, cy, w, d, h), c) in enumerate(zip(boxes, per_box)):
         if c <= 0:
             continue
         areas = np.array([w * h, w * h, d * h, d * h, w * d])
@@ -450,14 +457,105 @@ def scene_city(seed: int = 0, n: int = 50_000_000, size: float = 1000.0, block: 
                                  0.7 * spb * np.exp(rng.normal(0, 0.2, c)),
                                  np.full(c, 0.02)], 1))
         parts_n.append(nn)
+        parts_o.append(np.full(c, b, np.int32))
     means = np.concatenate(parts_m, 0)
     scales = np.concatenate(parts_s, 0)
     quats = _frame_quats(np.concatenate(parts_n, 0), rng)
     nn_ = means.shape[0]
     opacity = _sigmoid(rng.normal(2.0, 1.0, size=nn_))
-    sh = _sh(rng, nn_)
+    if color == "iid":
+        sh = _sh(rng, nn_)
+    elif color == "smooth":
+        sh = _city_colours(rng, means, np.concatenate(parts_o, 0), boxes, size, block, street)
+    elif color == "white":
+        sh = np.zeros((nn_, 16, 3), np.float32)
+        sh[:, 0, :] = np.float32(0.5 / SH_C0)
+    else:
+        raise ValueError(f"unknown city colour model {color!r}")
     return _pack(means, scales, quats, opacity, sh, bounds=(means.min(0), means.max(0)),
-                 extra={"boxes": boxes, "size": size, "block": block, "street": street, "seed": seed})
+                 extra={"boxes": boxes, "size": size, "block": block, "street": street, "seed": seed,
+                        "color": color})
+
+
+# degree-0 real SH constant 1 / (2 sqrt(pi)): colour = SH_C0 * DC + 0.5 + higher degrees
+SH_C0 = 0.28209479177387814
+
+
+def _waves(rng, d, n_waves, wl_min, wl_max):
+    """n_waves plane waves in d dimensions: random unit directions,
+    wavelengths log-uniform in [wl_min, wl_max], random phases."""
+    k = rng.normal(size=(n_waves, d))
+    k /= np.linalg.norm(k, axis=1, keepdims=True)
+    wl = np.exp(rng.uniform(math.log(wl_min), math.log(wl_max), size=n_waves))
+    return k * (2 * math.pi / wl)[:, None], rng.uniform(0, 2 * math.pi, size=n_waves)
+
+
+def _field(pts, waves, sd):
+    """Sum of the plane waves at pts, scaled to standard deviation sd."""
+    k, ph = waves
+    v = np.zeros(pts.shape[0])
+    for i in range(len(ph)):
+        arg = np.full(pts.shape[0], ph[i])
+        for j in range(pts.shape[1]):
+            arg += pts[:, j] * k[i, j]
+        v += np.sin(arg)
+    return (v * (sd * math.sqrt(2.0 / len(ph)))).astype(np.float32)
+
+
+def _city_colours(rng, means, owner, boxes, size, block, street, chunk=1_000_000):
+    """Spatially smooth colours for the city, as a captured scene's colours
+    are correlated over its surfaces.  Albedo (rgb in [0, 1]):
+      ground   asphalt grey 0.30 on the streets, 0.50 on the blocks, each
+               channel plus a field of 6 plane waves (wavelengths 6-60 m,
+               standard deviation 0.06);
+      building a base colour per building, U[0.30, 0.75] per channel, plus a
+               3-D field of 6 plane waves (wavelengths 4-30 m, sd 0.05).
+    DC = (albedo - 0.5) / SH_C0 + N(0, 0.01^2) per Gaussian (fine grain).
+    Degrees 1-3: one set of 15 x 3 coefficients N(0, 0.04^2) for the ground
+    and one per building (shared view dependence, so a surface keeps one
+    sheen), plus N(0, 0.004^2) per Gaussian."""
+    n = means.shape[0]
+    nb = len(boxes)
+    base = rng.uniform(0.30, 0.75, size=(nb, 3)).astype(np.float32)
+    hi_ground = rng.normal(0.0, 0.04, size=(15, 3)).astype(np.float32)
+    hi_build = rng.normal(0.0, 0.04, size=(nb, 15, 3)).astype(np.float32)
+    g_waves = [_waves(rng, 2, 6, 6.0, 60.0) for _ in range(3)]
+    b_waves = [_waves(rng, 3, 6, 4.0, 30.0) for _ in range(3)]
+    noise_rng = np.random.Generator(np.random.PCG64(int(rng.integers(1 << 62))))
+    hi_all = np.concatenate([hi_build, hi_ground[None]], 0)   # owner -1 (ground) reads the last row
+    sh = _sh(noise_rng, n, std=1.0, dc_offset=0.0)
+    hi_flat = hi_all.reshape(nb + 1, 45)
+
+    def fill(s0):
+        s1 = min(n, s0 + chunk)
+        m = means[s0:s1]
+        own = owner[s0:s1]
+        alb = np.empty((s1 - s0, 3), np.float32)
+        g = own < 0
+        if g.any():
+            xy = m[g, :2]
+            # streets are centred on x = -size/2 + k * block (likewise y)
+            fx = np.mod(xy[:, 0] + 0.5 * size, block)
+            fy = np.mod(xy[:, 1] + 0.5 * size, block)
+            on_street = (np.minimum(fx, block - fx) < street / 2) | (np.minimum(fy, block - fy) < street / 2)
+            lvl = np.where(on_street, 0.30, 0.50).astype(np.float32)
+            for c in range(3):
+                alb[g, c] = lvl + _field(xy, g_waves[c], 0.06)
+        b = ~g
+        if b.any():
+            for c in range(3):
+                alb[b, c] = base[own[b], c] + _field(m[b], b_waves[c], 0.05)
+        np.clip(alb, 0.02, 0.98, out=alb)
+        blk = sh[s0:s1]
+        blk[:, 0, :] *= np.float32(0.01)
+        blk[:, 0, :] += (alb - np.float32(0.5)) / np.float32(SH_C0)
+        blk[:, 1:, :] *= np.float32(0.004)
+        blk[:, 1:, :] += np.take(hi_flat, own, axis=0, mode="wrap").reshape(s1 - s0, 15, 3)
+
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(fill, range(0, n, chunk)))
+    return sh
 
 
 def path_city(scene: Scene, n_frames: int = 600, width: int = 1920, height: int = 1080,

@@ -31,13 +31,16 @@ def test_struct_layout_matches_c_compiler(tmp_path):
     """The binding's structures have the sizes and field offsets the C compiler
     gives the header's structures."""
     import subprocess
-    fields = {"vm3dgs_options": ["img_w", "flags", "stream_render", "stream_copy", "pair_capacity"],
+    fields = {"vm3dgs_options": ["img_w", "flags", "stream_render", "stream_copy", "pair_capacity", "lod_scale_up"],
               "vm3dgs_camera": ["view", "cam_pos", "fx", "znear"],
               "vm3dgs_stats": ["candidates", "prefetched", "render_gaussians", "blend_alphas", "ms_visibility",
                                "ms_total"],
               "vm3dgs_scene": ["n", "sh"],
               "vm3dgs_frame_out": ["requests", "n_requests", "missing", "n_missing", "stats"],
-              "vm3dgs_prefetch_opts": ["n_clusters", "budget_pages", "logit_threshold", "center", "extent"]}
+              "vm3dgs_prefetch_opts": ["n_clusters", "budget_pages", "logit_threshold", "center", "extent"],
+              "vm3dgs_dataset": ["cams", "path_frames", "n_paths"],
+              "vm3dgs_train_opts": ["steps", "batch", "lr", "seed", "proposal_factor", "log_every"],
+              "vm3dgs_train_log": ["rows", "positive_rate", "loss_last", "ms_train", "n_losses", "losses"]}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "vm3dgs.h"', "int main(void) {"]
     for s, fs in fields.items():
         lines.append(f'printf("{s} %zu\\n", sizeof({s}));')

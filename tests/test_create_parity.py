@@ -9,17 +9,18 @@ import paper_2506_19415_amd as pkg
 from paper_2506_19415_amd import synth
 
 
-def _opts(cell, link_sigma=2.0, fmt=0):
+def _opts(cell, link_sigma=2.0, fmt=0, scale_up=1.0):
     o = pkg.vm3dgs_options_default()
     o.proxy_cell_m = cell
     o.link_sigma = link_sigma
     o.attr_format = fmt
+    o.lod_scale_up = scale_up
     return o
 
 
-def _both(sc, P, L, cell, fmt=0, link_sigma=2.0):
-    h = pkg.vm3dgs_pages_build(sc, P, L, _opts(cell, link_sigma, fmt))
-    osc = oracle.OracleScene(sc, P, L, cell, link_sigma, fmt)
+def _both(sc, P, L, cell, fmt=0, link_sigma=2.0, scale_up=1.0):
+    h = pkg.vm3dgs_pages_build(sc, P, L, _opts(cell, link_sigma, fmt, scale_up))
+    osc = oracle.OracleScene(sc, P, L, cell, link_sigma, fmt, lod_scale_up=scale_up)
     return h, osc
 
 
@@ -65,10 +66,10 @@ def test_terrain_paging_parity():
         pkg.vm3dgs_pages_destroy(h)
 
 
-@pytest.mark.parametrize("fmt", [0, 1])
-def test_lod_and_half_form_parity(fmt):
+@pytest.mark.parametrize("fmt,scale_up", [(0, 1.0), (1, 1.0), (0, 1.6)])
+def test_lod_and_half_form_parity(fmt, scale_up):
     sc = synth.scene_city(0, n=40000, size=120.0, block=40.0, street=8.0)
-    h, osc = _both(sc, 512, 3, 2.0, fmt=fmt)
+    h, osc = _both(sc, 512, 3, 2.0, fmt=fmt, scale_up=scale_up)
     try:
         _check_same(h, osc, 3)
     finally:

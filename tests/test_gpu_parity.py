@@ -17,6 +17,13 @@ pytestmark = pytest.mark.gpu
 NONE32 = np.uint32(0xffffffff)
 
 
+def _ovm(*a, **kw):
+    """The oracle VM with the support-box cut of the tile rectangles, which
+    the library makes (its pair list is then the library's; the image is
+    that of the plain 3-sigma rectangles either way)."""
+    return oracle.OracleVM(*a, support_box=True, **kw)
+
+
 def _renderer(sc, P, S, img, idbuf, cell, **kw):
     import paper_2506_19415_amd as pkg
     return pkg.Renderer(sc, P, S, img=img, idbuf=idbuf, cell=cell, **kw)
@@ -59,15 +66,19 @@ def compare_frame(r, ovm, out, n_views, check_image=True, tag=""):
 def compare_splat(r, ovm, n_views, check_image=True, tag=""):
     g = r.get
     pf, pi = g("pp_float", np.float32).reshape(-1, 11), g("pp_int", np.int32).reshape(-1, 6)
-    of, oi = ovm.get("pp_float").reshape(-1, 11), ovm.get("pp_int").reshape(-1, 6)
-    assert pf.shape == of.shape, tag
+    of, oi = ovm.get("pp_float").reshape(-1, 10), ovm.get("pp_int").reshape(-1, 6)
+    assert pf.shape[0] == of.shape[0], tag
     assert np.array_equal(pi[:, 0], oi[:, 0]), tag           # culled
     vis = oi[:, 0] == 0
     assert np.array_equal(pi[vis], oi[vis]), tag              # rect and tile counts
     assert np.array_equal(pf[vis, 2].view(np.uint32), of[vis, 2].view(np.uint32)), tag   # depth keys
     assert np.array_equal(pf[vis, :2], of[vis, :2]), tag      # pixel centre
     np.testing.assert_allclose(pf[vis, 3:10], of[vis, 3:10], rtol=1e-5, atol=1e-7, err_msg=tag)
-    assert np.array_equal(pf[vis, 10], of[vis, 10]), tag     # support-box half height
+    # the library's support-box half height (its blend skips the rows beyond
+    # it): every row where the conic's quadratic form can reach 11.1 is within
+    c64 = pf[vis, 3:6].astype(np.float64)
+    syy = c64[:, 0] / (c64[:, 0] * c64[:, 2] - c64[:, 1] ** 2)
+    assert np.all(pf[vis, 10].astype(np.float64) >= np.sqrt(11.1 * syy)), tag
     n_render = pf.shape[0] // n_views
     keys, vals = g("keys", np.uint32), g("vals", np.uint32)
     okeys, ovals = ovm.get("keys"), ovm.get("vals")
@@ -98,7 +109,7 @@ def test_clusters_all_frames(clusters):
     sc, osc = clusters
     cams = synth.orbit()
     r = _renderer(sc, 256, 64, (320, 240), (80, 60), 0.5, full_scene=True)
-    ovm = oracle.OracleVM(osc, 64, (320, 240), (80, 60))
+    ovm = _ovm(osc, 64, (320, 240), (80, 60))
     for k, cam in enumerate(cams):
         print(f"clusters frame {k}", flush=True)
         _, out = r.frame([cam])
@@ -119,7 +130,7 @@ def test_depth_ties():
     osc = oracle.OracleScene(sc, 256, 1, 0.5, 2.0)
     cams = synth.orbit()
     r = _renderer(sc, 256, 64, (320, 240), (80, 60), 0.5, full_scene=True)
-    ovm = oracle.OracleVM(osc, 64, (320, 240), (80, 60))
+    ovm = _ovm(osc, 64, (320, 240), (80, 60))
     for k in range(4):
         print(f"depth ties frame {k}", flush=True)
         _, out = r.frame([cams[k]])
@@ -149,7 +160,7 @@ def test_gaussians_covering_every_tile(clusters):
     osc = oracle.OracleScene(sc, 256, 1, 0.5, 2.0)
     cams = synth.orbit(8, 25.0, 640, 480)
     r = _renderer(sc, 256, 64, (640, 480), (160, 120), 0.5, full_scene=True)
-    ovm = oracle.OracleVM(osc, 64, (640, 480), (160, 120))
+    ovm = _ovm(osc, 64, (640, 480), (160, 120))
     for f in range(3):
         print(f"covering Gaussians frame {f}", flush=True)
         _, out = r.frame([cams[f]])
@@ -171,7 +182,7 @@ def test_two_views_ragged_image(clusters):
     W, H, Wv, Hv = 330, 250, 70, 50
     cams = [synth.orbit(8, 25.0, W, H)[i] for i in (1, 6)]
     r = _renderer(sc, 256, 96, (W, H), (Wv, Hv), 0.5, max_views=2)
-    ovm = oracle.OracleVM(osc, 96, (W, H), (Wv, Hv))
+    ovm = _ovm(osc, 96, (W, H), (Wv, Hv))
     for k in range(2):
         _, out = r.frame(cams)
         ovm.frame(cams)
@@ -183,7 +194,7 @@ def test_copy_budget_and_no_links(clusters):
     sc, osc = clusters
     cams = synth.orbit()
     r = _renderer(sc, 256, 64, (320, 240), (80, 60), 0.5, copy_budget=5, links=False)
-    ovm = oracle.OracleVM(osc, 64, (320, 240), (80, 60), copy_budget=5, use_links=False)
+    ovm = _ovm(osc, 64, (320, 240), (80, 60), copy_budget=5, use_links=False)
     for k in range(3):
         _, out = r.frame([cams[k]])
         ovm.frame([cams[k]])
@@ -200,7 +211,7 @@ def test_empty_and_inside_views(clusters):
     away = synth.look_at(centre + np.array([0.0, 0.0, 60.0]), [0.0, 0.0, 1.0], 320, 240, 60.0)
     inside = synth.look_at(centre, [1.0, 0.2, 0.1], 320, 240, 60.0)
     r = _renderer(sc, 256, 64, (320, 240), (80, 60), 0.5)
-    ovm = oracle.OracleVM(osc, 64, (320, 240), (80, 60))
+    ovm = _ovm(osc, 64, (320, 240), (80, 60))
     _, out = r.frame([away])
     ovm.frame([away])
     assert out.n_requests == 0 and out.stats.pairs == 0
@@ -220,7 +231,7 @@ def test_padding_page_and_tiny_pool():
     osc = oracle.OracleScene(sc, 256, 1, 0.5, 2.0)
     cams = synth.orbit(4, 20.0, 160, 128)
     r = _renderer(sc, 256, 1, (160, 128), (40, 32), 0.5)
-    ovm = oracle.OracleVM(osc, 1, (160, 128), (40, 32))
+    ovm = _ovm(osc, 1, (160, 128), (40, 32))
     for k, cam in enumerate(cams):
         _, out = r.frame([cam])
         ovm.frame([cam])
@@ -236,7 +247,7 @@ def test_half_form_clusters():
     osc = oracle.OracleScene(sc, 256, 1, 0.5, 2.0, attr_format=1)
     cams = synth.orbit()
     r = _renderer(sc, 256, 64, (320, 240), (80, 60), 0.5, attr_format=1)
-    ovm = oracle.OracleVM(osc, 64, (320, 240), (80, 60))
+    ovm = _ovm(osc, 64, (320, 240), (80, 60))
     for k in (0, 3, 5):
         _, out = r.frame([cams[k]])
         ovm.frame([cams[k]])
@@ -251,7 +262,7 @@ def test_eight_views_shared_pool(clusters):
     sc, osc = clusters
     cams = synth.orbit(8, 25.0, 160, 120)
     r = _renderer(sc, 256, 128, (160, 120), (40, 30), 0.5, max_views=8)
-    ovm = oracle.OracleVM(osc, 128, (160, 120), (40, 30))
+    ovm = _ovm(osc, 128, (160, 120), (40, 30))
     _, out = r.frame(cams)
     ovm.frame(cams)
     compare_frame(r, ovm, out, 8, tag="eight views")
@@ -271,7 +282,7 @@ def test_terrain6m_full_size_sampled():
     print("terrain6m generated", flush=True)
     r = pkg.Renderer(sc, 1024, 1465, img=(1920, 1080), idbuf=(240, 135), cell=0.5, full_scene=True, pair_capacity=1)
     osc = oracle.OracleScene(sc, 1024, 1, 0.5, 2.0)
-    ovm = oracle.OracleVM(osc, 1465, (1920, 1080), (240, 135))
+    ovm = _ovm(osc, 1465, (1920, 1080), (240, 135))
     TX, TY = 120, 68
     rng = np.random.default_rng(0)
     tiles = np.concatenate([rng.choice(TX * (TY - 1), 40, replace=False), TX * (TY - 1) + rng.choice(TX, 8, replace=False)])
@@ -291,7 +302,7 @@ def test_terrain6m_full_size_sampled():
         req = np.ctypeslib.as_array(out.requests, (out.n_requests,))
         assert np.array_equal(req, ovm.get("req_page")), k
         pf, pi = g("pp_float", np.float32).reshape(-1, 11), g("pp_int", np.int32).reshape(-1, 6)
-        of, oi = ovm.get("pp_float").reshape(-1, 11), ovm.get("pp_int").reshape(-1, 6)
+        of, oi = ovm.get("pp_float").reshape(-1, 10), ovm.get("pp_int").reshape(-1, 6)
         assert np.array_equal(pi[:, 0], oi[:, 0]), k
         vis = oi[:, 0] == 0
         assert np.array_equal(pi[vis], oi[vis]), k
@@ -330,7 +341,7 @@ def test_lod_city(city, L, tau, S, budget, fmt):
     osc = oracle.OracleScene(sc, 512, L, 2.0, 2.0, attr_format=fmt)
     r = _renderer(sc, 512, S, (480, 270), (120, 68), 2.0, lod_levels=L, lod_radius_px=tau,
                   copy_budget=budget, attr_format=fmt)
-    ovm = oracle.OracleVM(osc, S, (480, 270), (120, 68), copy_budget=budget, lod_radius_px=tau)
+    ovm = _ovm(osc, S, (480, 270), (120, 68), copy_budget=budget, lod_radius_px=tau)
     seen = np.zeros(L, np.int64)
     evictions = 0
     for k in range(0, 30, 2):
@@ -352,7 +363,7 @@ def test_large_one_level_table(clusters):
     osc = oracle.OracleScene(sc, 2, 1, 0.5, 2.0)
     cams = synth.orbit()
     r = _renderer(sc, 2, 6000, (320, 240), (80, 60), 0.5)
-    ovm = oracle.OracleVM(osc, 6000, (320, 240), (80, 60))
+    ovm = _ovm(osc, 6000, (320, 240), (80, 60))
     for k in range(4):
         print(f"large table frame {k}", flush=True)
         _, out = r.frame([cams[k]])
@@ -372,7 +383,7 @@ def test_one_level_table_at_its_limit(clusters, S):
     cams = synth.orbit()
     r = _renderer(sc, 4, S, (320, 240), (160, 120), 0.5)
     assert int(r.get("info", np.int64)[0]) == 8192
-    ovm = oracle.OracleVM(osc, S, (320, 240), (160, 120))
+    ovm = _ovm(osc, S, (320, 240), (160, 120))
     most = 0
     for k in range(4):
         print(f"table at its limit S={S} frame {k}", flush=True)
@@ -394,7 +405,7 @@ def test_adaptive_lod_thresholds(city):
     osc = oracle.OracleScene(sc, 512, 3, 2.0, 2.0)
     r = _renderer(sc, 512, 60, (320, 180), (80, 45), 2.0, lod_levels=3, lod_radius_px=64.0)
     r.set_flags(pkg.VM3DGS_FLAG_LINKS | pkg.VM3DGS_FLAG_ADAPTIVE_LOD)
-    ovm = oracle.OracleVM(osc, 60, (320, 180), (80, 45), lod_radius_px=64.0)
+    ovm = _ovm(osc, 60, (320, 180), (80, 45), lod_radius_px=64.0)
     ovm.set_adaptive_lod(True)
     taus = []
     for k in range(0, 60, 2):

@@ -146,6 +146,22 @@ def test_parent_sh_and_opacity():
     assert oracle.merge_children_d(kids)[10] == pytest.approx(8 * float(np.float32(0.02)), rel=1e-12)
 
 
+def test_parent_scale_up():
+    """The fixed scale-up of the merged Gaussian (Sec. 3 Level of Detail):
+    the parent's covariance is the mixture's times the factor squared; mean,
+    rotation, opacity and colour are those of plain moment matching."""
+    rng = np.random.default_rng(16)
+    for k in (1.25, 1.6, 2.0):
+        for _ in range(20):
+            kids = _random_children(rng)
+            p1 = oracle.merge_children_d(kids)
+            pk = oracle.merge_children_d(kids, scale_up=k)
+            mu, cov = _mixture_moments(kids)
+            assert np.abs(_cov_of(pk) - k * k * cov).max() <= 1e-9 * k * k * np.abs(cov).max()
+            assert np.array_equal(pk[0:3], p1[0:3]) and np.array_equal(pk[6:], p1[6:])
+            assert np.allclose(pk[3:6], k * p1[3:6], rtol=1e-15, atol=0)
+
+
 def test_parent_covariance_by_sampling():
     """Sample covariance of the opacity-weighted mixture (no formula of the
     moments involved) against the parent's covariance."""

@@ -31,10 +31,10 @@ def truth_sets(ovm):
     quadratic form is at most 2 ln 255 (opacity <= 1), i.e. within 3.33
     standard deviations along its major axis; each Gaussian is evaluated on
     that window, widened by one pixel, clipped to the image."""
-    pf = ovm.get("pp_float").reshape(-1, 11).astype(np.float64)
+    pf = ovm.get("pp_float").reshape(-1, 10).astype(np.float64)
     pi = ovm.get("pp_int").reshape(-1, 6)
     vis = np.nonzero(pi[:, 0] == 0)[0]
-    depth_bits = ovm.get("pp_float").reshape(-1, 11)[:, 2].view(np.uint32)
+    depth_bits = ovm.get("pp_float").reshape(-1, 10)[:, 2].view(np.uint32)
     order = vis[np.lexsort((vis, depth_bits[vis]))]
     T = np.ones((H, W))
     done = np.zeros((H, W), bool)

@@ -10,6 +10,7 @@
   (depth, index).
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -78,7 +79,7 @@ def test_ewa_conic_vs_finite_difference(mean, scale, quat):
     q /= np.linalg.norm(q)
     sc = one_gaussian_scene(mean, scale, q)
     vm = render(sc, cam, W, H)
-    f = vm.get("pp_float").reshape(-1, 11)[0]
+    f = vm.get("pp_float").reshape(-1, 10)[0]
     mu = np.array(mean, np.float64)
 
     def proj(p):
@@ -109,7 +110,7 @@ def test_sh_colour_matches_basis():
         sh = np.zeros((16, 3), np.float32)
         sh[k] = [0.9, -0.7, 0.3]
         vm = render(one_gaussian_scene(mean, [0.05] * 3, sh=sh[None]), cam, W, H)
-        rgb = vm.get("pp_float").reshape(-1, 11)[0, 7:10]
+        rgb = vm.get("pp_float").reshape(-1, 10)[0, 7:10]
         ref = np.maximum(oracle.sh_basis(k, *d) * sh[k].astype(np.float64) + 0.5, 0.0)
         assert np.allclose(rgb, ref, atol=2e-6), (k, rgb, ref)
 
@@ -142,7 +143,7 @@ def test_transmittance_invariants(cluster_frame):
     T = vm.get("final_T")
     img = vm.get("image").reshape(-1, 3)
     assert T.min() >= 1e-4 and T.max() <= 1.0
-    pf = vm.get("pp_float").reshape(-1, 11)
+    pf = vm.get("pp_float").reshape(-1, 10)
     pi = vm.get("pp_int").reshape(-1, 6)
     max_rgb = pf[pi[:, 0] == 0, 7:10].max()
     assert np.all(img.max(1) <= max_rgb * (1.0 - T) + 1e-5)
@@ -154,7 +155,7 @@ def test_transmittance_invariants(cluster_frame):
 def test_tile_lists_brute_force(cluster_frame):
     vm = cluster_frame
     TX, TY = vm.TX, vm.TY
-    pf = vm.get("pp_float").reshape(-1, 11)
+    pf = vm.get("pp_float").reshape(-1, 10)
     pi = vm.get("pp_int").reshape(-1, 6)
     keys = vm.get("keys")
     vals = vm.get("vals")
@@ -175,7 +176,7 @@ def test_depth_ties_broken_by_gaussian_index():
     holds its Gaussians by depth, then by index (brute force per tile)."""
     sc = synth.scene_ties(0, copies=4, per_cluster=256)
     vm = render(sc, synth.orbit()[0], 320, 240, page_size=256)
-    pf = vm.get("pp_float").reshape(-1, 11)
+    pf = vm.get("pp_float").reshape(-1, 10)
     pi = vm.get("pp_int").reshape(-1, 6)
     keys, vals = vm.get("keys"), vm.get("vals")
     ranges = vm.get("ranges").reshape(-1, 2)
@@ -205,13 +206,12 @@ def needle_scene(seed=3, n=3000):
 def _render_both(osc, cams, W, H):
     out = []
     for sigma3 in (True, False):
-        vm = oracle.OracleVM(osc, 4096, (W, H), (W // 4, H // 4))
-        vm.set_sigma3_tiles(sigma3)
+        vm = oracle.OracleVM(osc, 4096, (W, H), (W // 4, H // 4), support_box=not sigma3)
         res = []
         for cam in cams:
             vm.render_full([cam])
             res.append((vm.image()[0].copy(), vm.get("final_T").copy(), vm.get("contrib").copy(),
-                        vm.get("keys").size, vm.get("pp_float").reshape(-1, 11), vm.get("pp_int").reshape(-1, 6)))
+                        vm.get("keys").size, vm.get("pp_float").reshape(-1, 10), vm.get("pp_int").reshape(-1, 6)))
         out.append(res)
     return out
 
@@ -239,8 +239,8 @@ def test_support_box_keeps_the_image(which):
 def test_support_box_contains_the_accepted_region():
     """Brute force in float64: every pixel of the 3-sigma rectangle where the
     quadratic form of the conic is at most 11.1 (power >= -5.55) lies in a
-    tile of the cut rectangle and within hy rows of the centre; the cut
-    rectangle never leaves the 3-sigma one."""
+    tile of the cut rectangle; the cut rectangle never leaves the 3-sigma
+    one, and it is tighter for many Gaussians."""
     W, H = 192, 144
     osc = oracle.OracleScene(needle_scene(), 1, 1, 0.5, 2.0)
     (s3,), (bx,) = _render_both(osc, [identity_cam(W, H)], W, H)
@@ -260,15 +260,8 @@ def test_support_box_contains_the_accepted_region():
         assert pi3[g, 1] <= x0 and pi3[g, 2] <= y0 and x1 <= pi3[g, 3] and y1 <= pi3[g, 4]
         tx, ty = ii[acc] // 16, jj[acc] // 16
         assert np.all((tx >= x0) & (tx < x1) & (ty >= y0) & (ty < y1)), g
-        hy = float(pf[g, 10])
-        assert np.all(np.abs(jj[acc] - v) <= hy), g
-        if np.isfinite(hy):
-            n_tight += 1
-            # the half height is the closed form sqrt(11.11 f Sigma'_yy) + 1
-            det = a * c - b * b
-            syy = a / det
-            assert hy >= math.sqrt(11.1 * syy) and hy <= math.sqrt(11.2 * syy) * 1.05 + 1.0 + 1e-3, g
-    assert n_tight > 0.9 * vis.size
+        n_tight += int((x1 - x0) * (y1 - y0) < (pi3[g, 3] - pi3[g, 1]) * (pi3[g, 4] - pi3[g, 2]))
+    assert n_tight > 0.25 * vis.size
 
 
 def test_fp64_render_of_the_render_set(cluster_frame):
@@ -304,3 +297,19 @@ def test_fp64_render_lone_gaussian_closed_form():
     inside = (ii // 16 >= tx0) & (ii // 16 < tx1) & (jj // 16 >= ty0) & (jj // 16 < ty1)
     exp_img = np.where((inside & (alpha >= 1.0 / 255.0))[..., None], alpha[..., None] * rgb, 0.0)
     assert np.abs(img - exp_img).max() < 1e-13
+
+
+def test_threads_do_not_change_results():
+    """The splat's per-Gaussian and per-tile loops are independent: one
+    thread and several give the same pairs, image and transmittance."""
+    osc = oracle.OracleScene(synth.scene_clusters(0), 256, 1, 0.5, 2.0)
+    cam = synth.orbit()[2]
+    res = []
+    for n in (1, 4):
+        oracle.set_threads(n)
+        vm = oracle.OracleVM(osc, 64, (320, 240), (80, 60))
+        vm.frame([cam])
+        res.append((vm.get("keys").copy(), vm.get("vals").copy(), vm.image()[0].copy(), vm.get("final_T").copy()))
+    oracle.set_threads(os.cpu_count() or 1)
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
