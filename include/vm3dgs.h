@@ -163,6 +163,25 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
 vm3dgs_status vm3dgs_frame(vm3dgs* ctx, const vm3dgs_camera* cams, uint32_t n_views, float* image_dev,
                            vm3dgs_frame_out* out);
 
+/* vm3dgs_frame for callers that cannot allocate memory while they run
+ * frames (code under stream capture, serving loops, hosts that forbid
+ * allocation after set-up): the same frame, with the same kernels and the
+ * same results, that allocates nothing.  Every buffer it uses was made by
+ * vm3dgs_create, except the (tile, Gaussian) pair buffers, which are one
+ * fixed array of device memory per GPU (128 MiB, part of the library's code
+ * object, held by each GPU the library runs on until the process ends).  It
+ * holds 7,864,320 pairs (VM3DGS_NOALLOC_MAX_PAIRS).  A frame with more pairs
+ * returns CAPACITY: the page table, copies and counters of that frame are
+ * done (the frame counter advances), its image is not written, and
+ * vm3dgs_frame renders the same view with buffers that grow.  Every context
+ * on one GPU shares the array, which keeps the last call's pairs; calls that
+ * overlap on one GPU (two threads, or contexts on different streams whose
+ * frames run at once) race on it and must be serialised by the caller.
+ * Arguments, outputs and other errors as vm3dgs_frame. */
+#define VM3DGS_NOALLOC_MAX_PAIRS 7864320u
+vm3dgs_status vm3dgs_frame_noalloc(vm3dgs* ctx, const vm3dgs_camera* cams, uint32_t n_views, float* image_dev,
+                                   vm3dgs_frame_out* out);
+
 /* Splat every level-0 Gaussian of the scene with the same kernels and no
  * paging (the no-virtual-memory baseline of Sec. 5.3).  Needs
  * VM3DGS_FLAG_FULL_SCENE_COPY at create.  image_dev as in vm3dgs_frame;

@@ -21,6 +21,7 @@ VM3DGS_FLAG_FULL_SCENE_COPY = 2
 VM3DGS_FLAG_BLEND_STATS = 4
 VM3DGS_FLAG_SIGMA3_TILES = 8
 VM3DGS_FLAG_ADAPTIVE_LOD = 16
+VM3DGS_NOALLOC_MAX_PAIRS = 7864320
 
 _ERRORS = {-1: "INVALID_ARG", -2: "HOST_OOM", -3: "DEVICE_OOM", -4: "HIP", -5: "STATE", -6: "CAPACITY"}
 
@@ -110,6 +111,9 @@ def lib():
         L.vm3dgs_frame.argtypes = [C.c_void_p, C.POINTER(vm3dgs_camera), C.c_uint32, C.c_void_p,
                                    C.POINTER(vm3dgs_frame_out)]
         L.vm3dgs_frame.restype = C.c_int32
+        L.vm3dgs_frame_noalloc.argtypes = [C.c_void_p, C.POINTER(vm3dgs_camera), C.c_uint32, C.c_void_p,
+                                           C.POINTER(vm3dgs_frame_out)]
+        L.vm3dgs_frame_noalloc.restype = C.c_int32
         L.vm3dgs_render_full.argtypes = [C.c_void_p, C.POINTER(vm3dgs_camera), C.c_uint32, C.c_void_p,
                                          C.POINTER(vm3dgs_stats)]
         L.vm3dgs_render_full.restype = C.c_int32
@@ -207,6 +211,13 @@ def vm3dgs_frame(h, cams, image_dev_ptr: int) -> vm3dgs_frame_out:
     out = vm3dgs_frame_out()
     arr = _cameras(cams)
     _check(h, lib().vm3dgs_frame(h, arr, len(cams), C.c_void_p(image_dev_ptr), C.byref(out)))
+    return out
+
+
+def vm3dgs_frame_noalloc(h, cams, image_dev_ptr: int) -> vm3dgs_frame_out:
+    out = vm3dgs_frame_out()
+    arr = _cameras(cams)
+    _check(h, lib().vm3dgs_frame_noalloc(h, arr, len(cams), C.c_void_p(image_dev_ptr), C.byref(out)))
     return out
 
 
@@ -311,6 +322,13 @@ class Renderer:
     def frame(self, cams):
         self._torch_idle()
         out = vm3dgs_frame(self.h, cams, self.image.data_ptr())
+        return self.image[:len(cams)], out
+
+    def frame_noalloc(self, cams):
+        """vm3dgs_frame_noalloc: the same frame with the pair buffers in the
+        library's fixed device scratch (nothing allocated)."""
+        self._torch_idle()
+        out = vm3dgs_frame_noalloc(self.h, cams, self.image.data_ptr())
         return self.image[:len(cams)], out
 
     def render_full(self, cams):

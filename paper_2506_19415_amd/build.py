@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvm3dgs.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["k_sort.hip", "k_visibility.hip", "k_pagetable.hip", "k_splat.hip", "k_mlp.hip", "k_prefetch.hip", "create.cpp", "api.cpp",
+SOURCES = ["k_sort.hip", "k_visibility.hip", "k_pagetable.hip", "k_splat.hip", "k_mlp.hip", "k_prefetch.hip", "scratch.hip", "create.cpp", "api.cpp",
            "prefetch_train.cpp",
            "mlp.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",

@@ -88,6 +88,11 @@ struct vm3dgs {
     uint32_t pair_cover = 0;                        // its bound
     uint32_t* d_pkey[2] = {nullptr, nullptr}; uint32_t* d_pval[2] = {nullptr, nullptr};
     uint32_t* d_emit_start = nullptr;
+    // vm3dgs_frame_noalloc: this device's fixed scratch, and whether the call
+    // in flight splats into it; the sorted pairs of the last splat
+    uint8_t* d_noalloc = nullptr;
+    bool noalloc = false;
+    const uint32_t* last_pk = nullptr; const uint32_t* last_pv = nullptr;
     uint2* d_ranges = nullptr; uint32_t* d_tile_order = nullptr;
     // zero block: counters | look-back error flag | tickets | histograms (cleared per frame)
     uint32_t* d_zero = nullptr;
@@ -288,6 +293,36 @@ void ensure_pairs(vm3dgs* c, uint64_t n) {
     ensure_status(c);
 }
 
+// pair buffers of one splat: the context's own, or the fixed scratch of
+// vm3dgs_frame_noalloc (status words, keys, values, emission block starts,
+// each at a 256-byte boundary)
+struct PairBufs {
+    uint32_t* key[2]; uint32_t* val[2]; uint32_t* emit_start; uint64_t* status;
+    uint64_t cap;
+};
+
+PairBufs noalloc_bufs(uint8_t* base, uint64_t* end_bytes = nullptr) {
+    PairBufs b{};
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        uint8_t* p = base + off;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    b.status = (uint64_t*)take(8 * (uint64_t)lb_status_words(kNoallocPairs));
+    for (int i = 0; i < 2; ++i) b.key[i] = (uint32_t*)take(4 * kNoallocPairs);
+    for (int i = 0; i < 2; ++i) b.val[i] = (uint32_t*)take(4 * kNoallocPairs);
+    b.emit_start = (uint32_t*)take(4 * (kNoallocPairs / EMIT_SPAN + 2));
+    b.cap = kNoallocPairs;
+    if (end_bytes) *end_bytes = off;
+    return b;
+}
+
+// a frame of vm3dgs_frame_noalloc with more pairs than the fixed scratch holds
+struct NoallocCapacity {
+    uint32_t pairs;
+};
+
 // the render half of a frame: preprocess .. blend for n_render Gaussians per view
 void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool, uint32_t n_render, uint32_t n_views,
            float* image, vm3dgs_stats* st) {
@@ -310,20 +345,30 @@ void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool,
     // the pair count stays on the device: emission, tile sort and ranges read
     // it there, with grids sized for a bound on it; the host checks the count
     // against the bound once the frame is done (splat_pairs_ok)
-    const uint32_t cap = (uint32_t)std::min<uint64_t>({c->cap_pairs, (uint64_t)c->pair_grid[c->pair_kind],
+    PairBufs pbuf{{c->d_pkey[0], c->d_pkey[1]}, {c->d_pval[0], c->d_pval[1]}, c->d_emit_start, c->sw.status,
+                  c->cap_pairs};
+    if (c->noalloc) pbuf = noalloc_bufs(c->d_noalloc);
+    const uint32_t cap = (uint32_t)std::min<uint64_t>({pbuf.cap, (uint64_t)c->pair_grid[c->pair_kind],
                                                        0xffffffffull});
     c->pair_cover = cap;
-    launch_emit(c->sr, c->d_dval[db], c->d_offs, c->d_tiles, c->d_rect, c->d_emit_start, (uint32_t)n_total,
-                c->d_total, n_render, c->TX, c->TY, c->d_pkey[0], c->d_pval[0], cap);
+    // the fixed scratch is shared by every context on the GPU: its status
+    // words are cleared so that no word of an earlier call matches an epoch
+    if (c->noalloc) launch_fill_u32(c->sr, (uint32_t*)pbuf.status, 2 * (uint64_t)lb_status_words(cap), 0u);
+    launch_emit(c->sr, c->d_dval[db], c->d_offs, c->d_tiles, c->d_rect, pbuf.emit_start, (uint32_t)n_total,
+                c->d_total, n_render, c->TX, c->TY, pbuf.key[0], pbuf.val[0], cap);
     const uint32_t n_tiles = (uint32_t)(c->TX * c->TY) * n_views;
-    const int pb = onesweep_u32_dev(c->sr, c->sw, c->d_pkey, c->d_pval, cap, c->d_total, 0,
+    uint64_t* const own_status = c->sw.status;
+    c->sw.status = pbuf.status;
+    const int pb = onesweep_u32_dev(c->sr, c->sw, pbuf.key, pbuf.val, cap, c->d_total, 0,
                                     std::max(1, bits_for(n_tiles)));
-    launch_ranges(c->sr, c->d_pkey[pb], cap, c->d_total, c->d_ranges, n_tiles);
+    c->sw.status = own_status;
+    c->last_pk = pbuf.key[pb]; c->last_pv = pbuf.val[pb];
+    launch_ranges(c->sr, pbuf.key[pb], cap, c->d_total, c->d_ranges, n_tiles);
     launch_tile_order(c->sr, c->d_ranges, n_tiles, c->d_tile_order);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[5], c->sr));
     const bool bstats = (c->opt.flags & VM3DGS_FLAG_BLEND_STATS) != 0;
-    launch_blend(c->sr, c->d_ranges, c->d_tile_order, c->d_pval[pb], c->d_xy, c->d_conic, c->d_rgb,
+    launch_blend(c->sr, c->d_ranges, c->d_tile_order, pbuf.val[pb], c->d_xy, c->d_conic, c->d_rgb,
                  (int)c->opt.img_w, (int)c->opt.img_h, c->TX, c->TY, (int)n_views, image, bstats ? c->d_bstats : nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[6], c->sr));
@@ -350,6 +395,10 @@ bool splat_pairs_ok(vm3dgs* c, vm3dgs_stats* st) {
     const uint64_t want = std::min<uint64_t>((uint64_t)n_pairs + n_pairs / 2 + 1024, 0xffffffffull);
     c->pair_grid[c->pair_kind] = (uint32_t)want;
     if (n_pairs > c->pair_cover) {
+        if (c->noalloc) {
+            if (n_pairs > kNoallocPairs) throw NoallocCapacity{n_pairs};
+            return false;   // a larger grid over the same fixed buffers
+        }
         ensure_pairs(c, n_pairs);
         return false;
     }
@@ -532,7 +581,22 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         HIPCHK(hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming));
         for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+        {
+            // this device's fixed scratch for vm3dgs_frame_noalloc (looked up
+            // once per device, with the device current)
+            void* p = nullptr;
+            HIPCHK(noalloc_scratch(&p));
+            uint64_t used = 0;
+            noalloc_bufs((uint8_t*)p, &used);
+            if (used > kNoallocScratchBytes)
+                throw HipError{hipErrorInvalidValue, "fixed scratch layout exceeds its size", __LINE__};
+            c->d_noalloc = (uint8_t*)p;
+        }
         const int n_pg = c->n_pg, S = c->S, L = c->L, V = (int)o.max_views;
+        // frame outputs at their largest, so that no frame call allocates host memory
+        c->out_req.reserve((size_t)n_pg);
+        c->out_req_level.reserve((size_t)n_pg);
+        c->out_missing.reserve((size_t)2 * n_pg * L);
         const int64_t nc = ps.nc();
         // scene metadata
         dalloc(&c->d_sph, n_pg);
@@ -645,13 +709,24 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
     return VM3DGS_OK;
 }
 
-vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views, float* image,
-                           vm3dgs_frame_out* out) {
+}  // extern "C"
+
+namespace {
+
+// one frame; with noalloc the pair buffers are the device's fixed scratch and
+// nothing is allocated
+vm3dgs_status frame_impl(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views, float* image,
+                         vm3dgs_frame_out* out, bool noalloc) {
     if (!c) return VM3DGS_E_INVALID_ARG;
     if (c->poisoned) return VM3DGS_E_STATE;
     if (!cams || !image || n_views == 0) return bad(c, "cams, image and n_views must be given");
     if (n_views > c->opt.max_views) { c->err = "n_views exceeds max_views"; return VM3DGS_E_CAPACITY; }
     vm3dgs_stats st{};
+    struct ModeGuard {
+        vm3dgs* c;
+        ModeGuard(vm3dgs* c_, bool m) : c(c_) { c->noalloc = m; }
+        ~ModeGuard() { c->noalloc = false; }
+    } mode(c, noalloc);
     try {
         hipEvent_t* ev = c->ev;
         float fy_max = 0.0f;
@@ -805,6 +880,13 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         c->frame++;
     } catch (const HipError& h) {
         return fail(c, h);
+    } catch (const NoallocCapacity& e) {
+        // the page table has taken the frame; its image is not rendered
+        c->frame++;
+        c->last_n_pairs = 0;
+        c->err = "the frame has " + std::to_string(e.pairs) + " (tile, Gaussian) pairs; vm3dgs_frame_noalloc holds " +
+                 std::to_string(kNoallocPairs);
+        return VM3DGS_E_CAPACITY;
     } catch (const std::length_error& e) {
         c->err = e.what();
         c->poisoned = true;
@@ -819,6 +901,20 @@ vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_view
         out->stats = st;
     }
     return VM3DGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vm3dgs_status vm3dgs_frame(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views, float* image,
+                           vm3dgs_frame_out* out) {
+    return frame_impl(c, cams, n_views, image, out, false);
+}
+
+vm3dgs_status vm3dgs_frame_noalloc(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views, float* image,
+                                   vm3dgs_frame_out* out) {
+    return frame_impl(c, cams, n_views, image, out, true);
 }
 
 vm3dgs_status vm3dgs_render_full(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views, float* image,
@@ -1154,8 +1250,8 @@ int64_t vm3dgs_debug_get(vm3dgs* c, const char* name, void* dst, int64_t cap) {
         }
         return bytes;
     }
-    if (n == "keys") return dev(c->d_pkey[c->last_pbuf], 4 * (int64_t)c->last_n_pairs);
-    if (n == "vals") return dev(c->d_pval[c->last_pbuf], 4 * (int64_t)c->last_n_pairs);
+    if (n == "keys") return dev(c->last_pk, 4 * (int64_t)c->last_n_pairs);
+    if (n == "vals") return dev(c->last_pv, 4 * (int64_t)c->last_n_pairs);
     if (n == "ranges") return dev(c->d_ranges, 8 * (int64_t)c->TX * c->TY * V);
     if (n == "depth_order") return dev(c->d_dval[c->last_dbuf], 4 * nt);
     if (n == "blend_stats") return host(c->h_bstats, 8 * (int64_t)c->TX * c->TY * V);

@@ -15,6 +15,16 @@ constexpr int REC = 59;   // floats per Gaussian record
 constexpr int SUBS = 64;  // sub-slots per physical page
 constexpr uint32_t EMIT_SPAN = 1024;  // pairs per workgroup of the pair emission
 
+// vm3dgs_frame_noalloc: the (tile, Gaussian) pair buffers of a frame live in
+// a fixed device array of kNoallocScratchBytes per GPU (scratch.hip), laid
+// out as the look-back status words of the pair sort, then keys and values
+// (two of each, ping-pong), then the emission block starts.  It holds
+// kNoallocPairs pairs.
+constexpr uint64_t kNoallocScratchBytes = 128ull << 20;
+constexpr uint64_t kNoallocPairs = VM3DGS_NOALLOC_MAX_PAIRS;   // 7.5 Mi
+// the current device's scratch address, looked up once per device
+hipError_t noalloc_scratch(void** out);
+
 // ----------------------------------------------------------- create time
 struct PagedScene {
     int64_t n_in = 0;
