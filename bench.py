@@ -5,11 +5,15 @@ Default workload (city50m_lod): 50,000,000 Gaussians of a 1 x 1 km city
 (street grid of 100 m blocks, 1-6 buildings per block, Gaussians on the
 ground, facades and roofs; colours that vary smoothly over the surfaces),
 pages of 1024, three LOD levels (1024 / 128 / 16 Gaussians per page; each
-parent moment-matches 8 children, scaled up by a fixed factor), a pool of
+parent moment-matches 8 children), a pool of
 3,907 physical pages (4M Gaussians), LOD thresholds that follow memory use,
-240x135 page-ID buffer, 2 m proxy cells, 1920x1080, 70 degree horizontal field
+480x270 page-ID buffer, 2 m proxy cells, 1920x1080, 70 degree horizontal field
 of view, the 600-frame path (street level, ascent to 150 m, aerial view
-pitched 35 degrees down); fp32 attributes; seeded synthetic data.
+pitched 35 degrees down); fp32 attributes; seeded synthetic data.  The
+page-ID buffer is a quarter of the image in each direction (480x270): at
+240x135 the city's coarse ID pixels miss pages that the full render shows
+(all-level-0 frames of the path at 36.6-50 dB against the full render, at
+41.6-70 dB with 480x270, for 0.02 ms more visibility work).
 
 A step is one vm3dgs_frame (visibility, page table, copies of the misses,
 preprocess, sorts, blend) for the next camera of the path.  W warm-up steps
@@ -57,9 +61,10 @@ OPS_PER_EVAL = 25
 # 40 dB against the full render); with 0.5 m cells every frame is above 47 dB
 TERRAIN_CELL_M = 0.5
 # LOD parents of the city workloads: moment-matched scales times this factor
-# (a merged Gaussian covers less than its children; the fixed scale-up fills
-# the gaps) and the initial level-0 radius of the threshold controller
-CITY_LOD_SCALE_UP = 1.6
+# (1: moment matching alone; on the city path factors of 1.6 and 2 lowered the
+# PSNR of the LOD frames against the full render), and the initial level-0
+# radius of the threshold controller
+CITY_LOD_SCALE_UP = 1.0
 CITY_TAU0_PX = 32.0
 
 
@@ -166,11 +171,11 @@ def blend_roofline(evals, blend_ms, traffic, n_frames):
 
 CITY = {
     # three LOD levels (1024/128/16), the pool of 4M Gaussians, 1080p, the 600-frame street-ascent-aerial path
-    "city50m_lod": dict(fmt=0, views=1, img=(1920, 1080), idbuf=(240, 135)),
+    "city50m_lod": dict(fmt=0, views=1, img=(1920, 1080), idbuf=(480, 270)),
     # the same with half-precision pages (SH bf16; scale, rotation, opacity fp16; means fp32)
-    "city50m_half": dict(fmt=1, views=1, img=(1920, 1080), idbuf=(240, 135)),
+    "city50m_half": dict(fmt=1, views=1, img=(1920, 1080), idbuf=(480, 270)),
     # half pages, eight views per call at 1280x720 on their own paths, sharing one pool, with the learned prefetch
-    "city50m_prefetch8": dict(fmt=1, views=8, img=(1280, 720), idbuf=(160, 90)),
+    "city50m_prefetch8": dict(fmt=1, views=8, img=(1280, 720), idbuf=(320, 180)),
 }
 CITY_PHASES = [("street", 0, 200), ("ascent", 200, 400), ("aerial", 400, 600)]
 
@@ -293,7 +298,7 @@ def run_city_lod(args, pkg, synth):
         "dtype": "f32", "data": f"synthetic (seeded city, {sc.n} Gaussians, {args.city_color} colours)",
         "config": {"workload": f"{args.workload}: {sc.n} Gaussians over 1 x 1 km, 1024/page, 3 LOD levels "
                                f"(1024/128/16, parents scaled up x{args.lod_scale_up}), pool 3907 pages, "
-                               f"adaptive LOD from {args.tau0} px, 1920x1080, ID buffer 240x135, 70 deg, "
+                               f"adaptive LOD from {args.tau0} px, 1920x1080, ID buffer {cfg['idbuf'][0]}x{cfg['idbuf'][1]}, 70 deg, "
                                f"frames {Wm}..{Wm + K - 1} of the 600-frame street-ascent-aerial path",
                    "attr_format": "half" if cfg["fmt"] else "fp32", "page_size": 1024, "pool_pages": 3907,
                    "lod_levels": 3, "lod_scale_up": args.lod_scale_up, "tau0_px": args.tau0,

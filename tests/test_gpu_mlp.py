@@ -110,7 +110,6 @@ def test_training_is_reproducible():
     has written it."""
     import torch
     import paper_2506_19415_amd as pkg
-    from paper_2506_19415_amd import prefetch as pf
     dims = [92, 128, 128, 512]
     p0 = _params(dims, 7)
     rng = np.random.default_rng(8)
@@ -120,7 +119,12 @@ def test_training_is_reproducible():
     for _ in range(2):
         net = pkg.Mlp(dims, max_batch=256)
         net.set_params(p0)
-        pf.train(net, X, Y, steps=200, batch=256, lr=1e-3)
+        Xd, Yd = torch.tensor(X, device="cuda"), torch.tensor(Y, device="cuda")
+        pick = np.random.default_rng(0)
+        for _ in range(200):
+            idx = torch.tensor(pick.integers(0, X.shape[0], 256), device="cuda")
+            net.train_step(Xd[idx].contiguous(), Yd[idx].contiguous(), 1e-3, want_loss=False)
+        net.sync()
         out.append(net.get_state()[0])
         net.close()
     torch.cuda.synchronize()
