@@ -56,6 +56,7 @@ def lib():
         L.or_render_full.argtypes = [C.c_void_p, C.POINTER(_Cam), C.c_int, C.c_void_p]
         L.or_vm_get.restype = C.c_int64
         L.or_vm_get.argtypes = [C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64]
+        L.or_vm_set_async.argtypes = [C.c_void_p, C.c_int]
         L.or_set_threads.argtypes = [C.c_int]
         L.or_set_threads.restype = C.c_int
         L.or_merge_children.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_void_p]
@@ -314,7 +315,12 @@ class OracleVM:
     def counts(self):
         c = self.get("counts")
         return dict(zip(["requests", "hits", "misses", "evictions", "copies", "missing",
-                         "render_pages", "render_gaussians"], [int(x) for x in c]))
+                         "render_pages", "render_gaussians", "fallbacks"], [int(x) for x in c]))
+
+    def set_async(self, on=True):
+        """Streaming: the frame renders what was resident when it started and
+        its copies land for the next frame."""
+        lib().or_vm_set_async(self.ptr, int(bool(on)))
 
     def image(self, n_views=1):
         return self.get("image").reshape(n_views, self.H, self.W, 3)

@@ -76,6 +76,12 @@ struct or_vm {
     int force_all;         /* test switch: every page is directly requested */
     int support_box;       /* 1: 3-sigma tile rectangles cut to the support box (default 0: plain 3-sigma) */
     int last_full;         /* the last splat was or_render_full (every level-0 Gaussian) */
+    /* streaming (Sec. 4.3, Sec. 5.1.2): a frame's copies land for the next
+     * frame; it renders what was resident when it started, a page resident
+     * only at another level at that level (the switch is deferred) */
+    int async;
+    int8_t* rlevel;        /* [n_pg] level a requested page is rendered at, -1 none (streaming) */
+    int n_fallback;        /* requests rendered at another level (streaming) */
     /* LOD thresholds that follow memory use (Sec. 4.1, Sec. 5.1.1) */
     int adaptive;
     float tau_used, lod_step;
@@ -282,11 +288,19 @@ static void page_table(or_vm* vm)
     int32_t* miss = malloc(sizeof(int32_t) * 2 * (size_t)(vm->n_req > 0 ? vm->n_req : 1));
     int nm = 0;
     vm->hits = vm->misses = vm->evictions = 0;
-    /* stage 1: required entries, hits refresh last use, misses keep request order */
+    vm->n_fallback = 0;
+    /* stage 1: required entries, hits refresh last use, misses keep request
+     * order.  Streaming: a miss whose page is resident at another level is
+     * drawn at that level this frame (the resident level nearest to the
+     * requested one, the finer at equal distance): that entry is required
+     * too, and these misses (level transitions) are served after the others */
+    int32_t* later = malloc(sizeof(int32_t) * 2 * (size_t)(vm->n_req > 0 ? vm->n_req : 1));
+    int nl = 0;
     for (int i = 0; i < vm->n_req; i++) {
         int32_t p = vm->req_page[i];
         int l = vm->req_level[i];
         int32_t e = vm->v2p[p * L + l];
+        if (vm->async) vm->rlevel[p] = -1;
         if (e >= 0) {
             int s = e / SUBS, j = e % SUBS;
             req_sub[s * SUBS + j] = 1;
@@ -294,10 +308,31 @@ static void page_table(or_vm* vm)
             vm->sub_last_used[s * SUBS + j] = vm->frame;
             vm->last_used[s] = vm->frame;
             vm->hits++;
+            if (vm->async) vm->rlevel[p] = (int8_t)l;
+            continue;
+        }
+        int fl = -1;
+        if (vm->async)
+            for (int d = 1; d < L && fl < 0; d++) {
+                if (l - d >= 0 && vm->v2p[p * L + l - d] >= 0) fl = l - d;
+                else if (l + d < L && vm->v2p[p * L + l + d] >= 0) fl = l + d;
+            }
+        if (fl >= 0) {
+            int32_t f = vm->v2p[p * L + fl];
+            int s = f / SUBS, j = f % SUBS;
+            req_sub[s * SUBS + j] = 1;
+            slot_req[s] = 1;
+            vm->sub_last_used[s * SUBS + j] = vm->frame;
+            vm->last_used[s] = vm->frame;
+            vm->rlevel[p] = (int8_t)fl;
+            vm->n_fallback++;
+            later[2 * nl] = p; later[2 * nl + 1] = l; nl++;
         } else {
             miss[2 * nm] = p; miss[2 * nm + 1] = l; nm++;
         }
     }
+    for (int i = 0; i < nl; i++) { miss[2 * nm] = later[2 * i]; miss[2 * nm + 1] = later[2 * i + 1]; nm++; }
+    free(later);
     vm->misses = nm;
     /* stage 2 candidate lists, fixed at the start of the stage */
     ck* wl = malloc(sizeof(ck) * (size_t)S);
@@ -785,6 +820,8 @@ or_vm* or_vm_create(const or_scene* s, int pool_pages, int copy_budget, int use_
     vm->req_class = malloc((size_t)vm->n_pg);
     vm->req_depth = malloc(sizeof(uint32_t) * (size_t)vm->n_pg);
     vm->page_level = malloc((size_t)vm->n_pg);
+    vm->rlevel = malloc((size_t)vm->n_pg);
+    for (int p = 0; p < vm->n_pg; p++) vm->rlevel[p] = -1;
     vm->copy = malloc(sizeof(int64_t) * 3 * (size_t)vm->n_pg * vm->L);
     vm->copy_id = malloc(sizeof(int32_t) * 4 * (size_t)vm->n_pg * vm->L);
     vm->missing = malloc(sizeof(int32_t) * 2 * (size_t)vm->n_pg * vm->L);
@@ -800,6 +837,7 @@ void or_vm_free(or_vm* vm)
     free(vm->slot_level); free(vm->last_used); free(vm->sub_vpage); free(vm->sub_last_used); free(vm->v2p);
     free(vm->cand); free(vm->idbuf); free(vm->req_direct); free(vm->req_link);
     free(vm->req_page); free(vm->req_level); free(vm->req_class); free(vm->req_depth); free(vm->page_level);
+    free(vm->rlevel);
     free(vm->copy); free(vm->copy_id); free(vm->missing); free(vm->rl);
     free(vm->pp); free(vm->keys); free(vm->vals); free(vm->ranges); free(vm->image); free(vm->final_T);
     free(vm->contrib);
@@ -946,7 +984,8 @@ int or_vm_visibility(or_vm* vm, const or_camera* cams, int n_views, int brute_fo
     return 0;
 }
 
-/* render list: resident required pages in page order */
+/* render list: resident required pages in page order (streaming: at the
+ * level stage 1 found resident when the frame started) */
 static void build_render_list(or_vm* vm)
 {
     int n_pg = vm->n_pg;
@@ -954,6 +993,8 @@ static void build_render_list(or_vm* vm)
     vm->n_render = 0;
     for (int p = 0; p < n_pg; p++) {
         int l = vm->page_level[p];
+        if (l < 0) continue;
+        if (vm->async) l = vm->rlevel[p];
         if (l < 0) continue;
         int32_t e = vm->v2p[p * vm->L + l];
         if (e < 0) continue;
@@ -1011,6 +1052,8 @@ int or_vm_frame_prefetch(or_vm* vm, const or_camera* cams, int n_views, const fl
 }
 
 void or_vm_set_support_box(or_vm* vm, int on) { vm->support_box = on; }
+
+void or_vm_set_async(or_vm* vm, int on) { vm->async = on; }
 
 /* threads of the per-Gaussian and per-tile loops (1 = single-threaded;
  * returns the count in use, 1 when built without OpenMP) */
@@ -1215,7 +1258,8 @@ int64_t or_vm_get(const or_vm* vm, const char* name, void* dst, int64_t cap)
         return put(dst, cap, c, sizeof c);
     }
     if (!strcmp(name, "counts")) {
-        int64_t c[8] = {vm->n_req, vm->hits, vm->misses, vm->evictions, vm->n_copy, vm->n_missing, vm->n_rl, vm->n_render};
+        int64_t c[9] = {vm->n_req, vm->hits, vm->misses, vm->evictions, vm->n_copy, vm->n_missing, vm->n_rl, vm->n_render,
+                        vm->n_fallback};
         return put(dst, cap, c, sizeof c);
     }
     if (!strcmp(name, "render_list")) {

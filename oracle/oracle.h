@@ -83,6 +83,12 @@ int or_vm_pagetable(or_vm* vm, int n, const int32_t* pages, const int8_t* levels
  * 3-sigma radius alone (the support box off). */
 void or_vm_set_force_all(or_vm* vm, int on);
 void or_vm_set_support_box(or_vm* vm, int on);
+/* streaming (Sec. 4.3, Sec. 5.1.2): a frame renders what was resident when
+ * it started (a page resident only at another level at the nearest such
+ * level, the finer at equal distance; that entry is required too), its
+ * copies land for the next frame, and level transitions are served after
+ * the other misses */
+void or_vm_set_async(or_vm* vm, int on);
 /* OpenMP threads of the splat loops (n > 0 sets; returns the count in use) */
 int or_set_threads(int n);
 /* LOD thresholds that follow memory use (several levels only). */

@@ -443,3 +443,84 @@ def test_adaptive_lod_thresholds_follow_memory():
     assert moves[1] > 0
     assert max(taus) > 2 * tau0
     assert sum(miss_a[8:]) < 0.05 * sum(miss_f[8:]), (sum(miss_a[8:]), sum(miss_f[8:]))
+
+def _render_set(vm):
+    rl = vm.get("render_list").reshape(-1, 6)
+    return [[int(p), int(l)] for p, l in rl[:, :2]]
+
+
+def test_streaming_trace_golden():
+    """Streaming (copies land one frame later): the hand-worked traces of
+    tests/golden/stream_trace.json, one level and two levels (a level
+    transition drawn at the resident level and served after the other
+    misses); the same requests without streaming render what they copy."""
+    g = json.load(open(os.path.join(GOLD, "stream_trace.json")))
+    t = g["l1"]
+    osc = oracle.OracleScene(_tiny_scene(5, t["page_size"]), t["page_size"], 1, 1.0, 2.0)
+    for async_, key in ((True, "render"), (False, "render_sync")):
+        vm = oracle.OracleVM(osc, t["pool_pages"], (64, 64), (16, 16))
+        vm.set_async(async_)
+        for frame, exp in zip(t["frames"], t[key]):
+            vm.pagetable(frame)
+            assert [p for p, _ in _render_set(vm)] == exp
+    t = g["lod"]
+    P, L = t["page_size"], t["lod_levels"]
+    osc = oracle.OracleScene(_tiny_scene(6, P), P, L, 1.0, 2.0)
+
+    def check(vm, exp, tag):
+        assert _render_set(vm) == exp["render"], tag
+        assert vm.get("copy_id").reshape(-1, 4).tolist() == exp["copies"], tag
+        assert vm.get("missing").reshape(-1, 2).tolist() == exp["missing"], tag
+
+    vm = oracle.OracleVM(osc, t["pool_pages"], (64, 64), (16, 16))
+    vm.set_async(True)
+    for k, fr in enumerate(t["frames"]):
+        req = np.array(fr["req"])
+        vm.pagetable(req[:, 0], req[:, 1])
+        check(vm, fr, ("streaming", k))
+        assert vm.counts()["fallbacks"] == fr["fallbacks"]
+    vm = oracle.OracleVM(osc, t["pool_pages"], (64, 64), (16, 16))
+    for k in range(2):
+        req = np.array(t["frames"][k]["req"])
+        vm.pagetable(req[:, 0], req[:, 1])
+    check(vm, t["sync_frame2"], "without streaming")
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_streaming_invariants_random(seed):
+    """Random request streams over two levels with streaming: a frame renders
+    exactly the requested pages resident (at some level) when it started, at
+    the requested level if resident there, else at the nearest resident
+    level (the finer at equal distance); nothing it renders is evicted or
+    overwritten by its copies; and its misses without a resident level are
+    served before those with one."""
+    rng = np.random.default_rng(seed)
+    n_pages, P, L, S = 30, 8, 2, 5
+    osc = oracle.OracleScene(_tiny_scene(n_pages, P), P, L, 1.0, 2.0)
+    vm = oracle.OracleVM(osc, S, (64, 64), (16, 16))
+    vm.set_async(True)
+    for f in range(50):
+        k = int(rng.integers(1, 10))
+        pages = rng.choice(n_pages, size=k, replace=False)
+        levels = rng.integers(0, L, size=k).astype(np.int8)
+        before = vm.get("v2p").reshape(n_pages, L).copy()
+        vm.pagetable(pages, levels)
+        after = vm.get("v2p").reshape(n_pages, L)
+        want = []
+        for p, l in zip(pages, levels):
+            res = [q for q in range(L) if before[p, q] >= 0]
+            if not res:
+                continue
+            best = min(res, key=lambda q: (abs(q - int(l)), q))
+            want.append([int(p), best])
+        got = _render_set(vm)
+        assert got == sorted(want), (f, got, want)
+        rl = vm.get("render_list").reshape(-1, 6)
+        for p, l, s, j, _, _ in rl:
+            assert before[p, l] == s * 64 + j == after[p, l]
+        ci = vm.get("copy_id").reshape(-1, 4)
+        rendered = {(int(s), int(j)) for _, _, s, j, _, _ in rl}
+        assert not any((int(s), int(j)) in rendered for _, _, s, j in ci)
+        # service order: level transitions (a level resident) after plain misses
+        fb = [any(before[p, q] >= 0 for q in range(L)) for p, _, _, _ in ci]
+        assert fb == sorted(fb)
