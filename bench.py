@@ -66,6 +66,8 @@ TERRAIN_CELL_M = 0.5
 # radius of the threshold controller
 CITY_LOD_SCALE_UP = 1.0
 CITY_TAU0_PX = 32.0
+# streaming runs (--stream): the paper's staging buffer of 40 pages per frame
+STAGING_PAGES = 40
 
 
 def log(*a):
@@ -200,11 +202,13 @@ def run_city_lod(args, pkg, synth):
     cams = synth.path_city(sc, n_frames=600, width=W, height=H)
     n_path = len(cams)
     t0 = time.time()
-    r = pkg.Renderer(sc, 1024, 3907, lod_levels=3, img=(W, H), idbuf=cfg["idbuf"], attr_format=cfg["fmt"],
-                     cell=2.0, lod_radius_px=args.tau0, lod_scale_up=args.lod_scale_up, full_scene=not args.no_full)
-    flags = pkg.VM3DGS_FLAG_LINKS | pkg.VM3DGS_FLAG_ADAPTIVE_LOD
+    S = args.city_pool
+    r = pkg.Renderer(sc, 1024, S, lod_levels=3, img=(W, H), idbuf=cfg["idbuf"], attr_format=cfg["fmt"],
+                     cell=2.0, lod_radius_px=args.tau0, lod_scale_up=args.lod_scale_up, full_scene=not args.no_full,
+                     copy_budget=STAGING_PAGES if args.stream else 0)
+    flags = pkg.VM3DGS_FLAG_LINKS | pkg.VM3DGS_FLAG_ADAPTIVE_LOD | (pkg.VM3DGS_FLAG_ASYNC_MISSES if args.stream else 0)
     r.set_flags(flags)
-    log(f"VM context (L=3, pool 3907, format {cfg['fmt']}, scale-up {args.lod_scale_up}) {time.time() - t0:.1f} s")
+    log(f"VM context (L=3, pool {S}, format {cfg['fmt']}, scale-up {args.lod_scale_up}) {time.time() - t0:.1f} s")
     K, Wm = args.steps, args.warmup
 
     for i in range(Wm):
@@ -297,12 +301,13 @@ def run_city_lod(args, pkg, synth):
         "ms_per_step": elapsed * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": f"synthetic (seeded city, {sc.n} Gaussians, {args.city_color} colours)",
         "config": {"workload": f"{args.workload}: {sc.n} Gaussians over 1 x 1 km, 1024/page, 3 LOD levels "
-                               f"(1024/128/16, parents scaled up x{args.lod_scale_up}), pool 3907 pages, "
+                               f"(1024/128/16, parents scaled up x{args.lod_scale_up}), pool {S} pages, "
                                f"adaptive LOD from {args.tau0} px, 1920x1080, ID buffer {cfg['idbuf'][0]}x{cfg['idbuf'][1]}, 70 deg, "
-                               f"frames {Wm}..{Wm + K - 1} of the 600-frame street-ascent-aerial path",
-                   "attr_format": "half" if cfg["fmt"] else "fp32", "page_size": 1024, "pool_pages": 3907,
+                               f"frames {Wm}..{Wm + K - 1} of the 600-frame street-ascent-aerial path"
+                               + (f", streaming (staging {STAGING_PAGES} pages)" if args.stream else ""),
+                   "attr_format": "half" if cfg["fmt"] else "fp32", "page_size": 1024, "pool_pages": S,
                    "lod_levels": 3, "lod_scale_up": args.lod_scale_up, "tau0_px": args.tau0,
-                   "image": [W, H], "idbuf": list(cfg["idbuf"]), "proxy_cell_m": 2.0},
+                   "image": [W, H], "idbuf": list(cfg["idbuf"]), "proxy_cell_m": 2.0, "streaming": args.stream},
         "fps_median_frame": 1000.0 / statistics.median(walls),
         "full_scene_fps": full_fps, "speedup_vs_full": (K / elapsed) / full_fps if full_fps else None,
         "psnr_min": min(psnrs) if psnrs else None, "psnr_median": statistics.median(psnrs) if psnrs else None,
@@ -312,6 +317,7 @@ def run_city_lod(args, pkg, synth):
         "render_gaussians_median": n_render, "pairs_median": pairs,
         "lod_radius_px_median": med("lod_radius_px", stats),
         "misses_per_frame": statistics.mean(s_["misses"] for s_ in stats),
+        "fallbacks_per_frame": statistics.mean(s_["fallbacks"] for s_ in stats),
         "missing_per_frame": statistics.mean(s_["missing"] for s_ in stats),
         "bytes_copied_per_frame": statistics.mean(s_["bytes_copied"] for s_ in stats),
         "stage_gbs": {"copy_pcie": statistics.mean([s_["bytes_copied"] for s_ in stats]) /
@@ -330,8 +336,10 @@ def run_city_lod(args, pkg, synth):
         def make_vm():
             t0 = time.time()
             osc = oracle.OracleScene(sc, 1024, 3, 2.0, 2.0, attr_format=cfg["fmt"], lod_scale_up=args.lod_scale_up)
-            vm = oracle.OracleVM(osc, 3907, (W, H), cfg["idbuf"], lod_radius_px=args.tau0)
+            vm = oracle.OracleVM(osc, S, (W, H), cfg["idbuf"], lod_radius_px=args.tau0,
+                                 copy_budget=STAGING_PAGES if args.stream else 0)
             vm.set_adaptive_lod(True)
+            vm.set_async(args.stream)
             vm._osc = osc
             return vm, time.time() - t0
         res["cpu_baseline"] = cpu_baseline(make_vm, cams[Wm:], args.workload)
@@ -508,6 +516,10 @@ def main():
     ap.add_argument("--tau0", type=float, default=CITY_TAU0_PX,
                     help="city: initial level-0 projected page radius (pixels) of the adaptive thresholds")
     ap.add_argument("--no-path", action="store_true", help="city: skip the per-phase pass over the whole path")
+    ap.add_argument("--city-pool", type=int, default=3907,
+                    help="city50m_lod / city50m_half: physical pages of the pool (3907 = 4M Gaussians)")
+    ap.add_argument("--stream", action="store_true",
+                    help="city: streaming (frames do not wait for their page copies; staging budget of 40 pages)")
     ap.add_argument("--page-size", type=int, default=1024,
                     help="terrain6m: Gaussians per page (the page-size trend of the paper's Tab. 3)")
     ap.add_argument("--lod-levels", type=int, default=1,

@@ -73,6 +73,18 @@ typedef struct {
  * frames earlier.  The radius a frame used is in stats.lod_radius_px; the
  * next frame uses the new one. */
 #define VM3DGS_FLAG_ADAPTIVE_LOD 16u
+/* Streaming (Sec. 4.3, Sec. 5.1.2): a frame does not wait for its own page
+ * copies.  It renders the requested pages that were resident when it
+ * started: at the requested level, or, for a page resident only at other
+ * levels, at the nearest of them (the finer at equal distance; the level
+ * switch is deferred until the copy has landed, and that entry is required
+ * for the frame).  Its misses are served in request order (directly seen
+ * before linked, then depth), those with such a resident level after all
+ * the others; the copies run on the copy stream beside the frame's splat,
+ * and the next frame waits for them before it reads or writes the pool.
+ * copy_budget_pages is the per-frame staging budget (Sec. 5.1.2: 40 pages).
+ * stats.bytes_copied counts the bytes the frame issues. */
+#define VM3DGS_FLAG_ASYNC_MISSES 32u
 
 typedef struct {
     uint32_t img_w, img_h;        /* output image, pixels */
@@ -116,6 +128,7 @@ typedef struct {
     uint32_t render_pages;      /* resident requested pages splatted this frame */
     uint32_t pool_pages_used;   /* physical pages holding at least one virtual page */
     uint32_t prefetched;        /* pages copied by the prefetch stage (not awaited by this frame) */
+    uint32_t fallbacks;         /* streaming: requested pages drawn at another resident level */
     uint64_t render_gaussians;  /* Gaussians in the render set (incl. padding) x views */
     uint64_t visible_gaussians; /* of those, not culled by the projection */
     uint64_t pairs;             /* (tile, Gaussian) pairs sorted and blended */

@@ -21,6 +21,7 @@ VM3DGS_FLAG_FULL_SCENE_COPY = 2
 VM3DGS_FLAG_BLEND_STATS = 4
 VM3DGS_FLAG_SIGMA3_TILES = 8
 VM3DGS_FLAG_ADAPTIVE_LOD = 16
+VM3DGS_FLAG_ASYNC_MISSES = 32
 VM3DGS_NOALLOC_MAX_PAIRS = 7864320
 
 _ERRORS = {-1: "INVALID_ARG", -2: "HOST_OOM", -3: "DEVICE_OOM", -4: "HIP", -5: "STATE", -6: "CAPACITY"}
@@ -58,7 +59,7 @@ class vm3dgs_prefetch_opts(C.Structure):
 class vm3dgs_stats(C.Structure):
     _fields_ = [(n, C.c_uint32) for n in ("candidates", "requested", "direct", "linked", "hits", "misses",
                                            "evictions", "missing", "copies", "render_pages", "pool_pages_used",
-                                           "prefetched")] + \
+                                           "prefetched", "fallbacks")] + \
                [(n, C.c_uint64) for n in ("render_gaussians", "visible_gaussians", "pairs", "bytes_copied",
                                            "blend_evals", "blend_alphas")] + \
                [(n, C.c_float) for n in ("ms_visibility", "ms_pagetable", "ms_copy", "ms_preprocess", "ms_sort",

@@ -65,6 +65,10 @@ struct vm3dgs {
     int8_t* d_slot_level = nullptr; int32_t* d_last_used = nullptr; int32_t* d_sub_vpage = nullptr;
     int32_t* d_sub_lu = nullptr; int32_t* d_v2p = nullptr; uint8_t* d_req_sub = nullptr; uint8_t* d_slot_req = nullptr;
     uint32_t* d_miss = nullptr;
+    // copy commands, two lists used in turn by consecutive frames: the copies
+    // a frame leaves running on the copy stream read theirs while the next
+    // frame's page table writes the other
+    CopyCmd* d_copies_buf[2] = {nullptr, nullptr}; int cpb = 0;
     CopyCmd* d_copies = nullptr; CopyCmd* h_copies = nullptr; int32_t* d_copy_id = nullptr;
     int32_t* d_missing = nullptr; int32_t* h_missing = nullptr;
     uint64_t* h_keys = nullptr;
@@ -72,11 +76,16 @@ struct vm3dgs {
     uint64_t* d_lkeys_alt = nullptr; uint64_t* d_wkeys[2] = {nullptr, nullptr};
     uint64_t* d_ck[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
     uint32_t* d_lflag = nullptr; uint32_t* d_lpos = nullptr; int32_t* d_fresh = nullptr;
+    uint32_t* d_lflag2 = nullptr; uint32_t* d_lpos2 = nullptr; int8_t* d_rlevel = nullptr;   // streaming
+    // streaming (VM3DGS_FLAG_ASYNC_MISSES): the demand copies of the last frame,
+    // on the copy stream, which the next frame waits for before it touches the pool
+    hipEvent_t ev_async = nullptr;
+    bool async_pending = false;
     int8_t* d_lvl_out = nullptr; int8_t* h_lvl = nullptr;
     RenderEntry* d_rlist = nullptr; RenderEntry* d_rlist_full = nullptr;
     // splat
     uint64_t cap_render = 0;
-    float2* d_xy = nullptr; float4* d_conic = nullptr; float4* d_rgb = nullptr;
+    float4* d_xy = nullptr; float4* d_conic = nullptr; float4* d_rgb = nullptr;   // xy: centre, support half-widths
     uint32_t* d_depth = nullptr; uint2* d_rect = nullptr; uint32_t* d_tiles = nullptr;
     uint32_t* d_dkey[2] = {nullptr, nullptr}; uint32_t* d_dval[2] = {nullptr, nullptr};
     uint32_t* d_offs = nullptr;
@@ -197,11 +206,13 @@ void free_all(vm3dgs* c) {
     dfree(c->d_keys); c->d_ctr = nullptr; hfree(c->h_ctr);
     dfree(c->d_slot_level); dfree(c->d_last_used); dfree(c->d_sub_vpage); dfree(c->d_sub_lu); dfree(c->d_v2p);
     dfree(c->d_req_sub); dfree(c->d_slot_req); dfree(c->d_miss);
-    dfree(c->d_copies); hfree(c->h_copies); dfree(c->d_copy_id); dfree(c->d_missing); hfree(c->h_missing);
+    dfree(c->d_copies_buf[0]); dfree(c->d_copies_buf[1]); c->d_copies = nullptr; hfree(c->h_copies); dfree(c->d_copy_id); dfree(c->d_missing); hfree(c->h_missing);
     hfree(c->h_keys);
     dfree(c->d_lkeys_alt); dfree(c->d_wkeys[0]); dfree(c->d_wkeys[1]);
     for (auto& q : c->d_ck) { dfree(q[0]); dfree(q[1]); }
-    dfree(c->d_lflag); dfree(c->d_lpos); dfree(c->d_fresh); dfree(c->d_lvl_out); hfree(c->h_lvl);
+    dfree(c->d_lflag); dfree(c->d_lpos); dfree(c->d_fresh);
+    dfree(c->d_lflag2); dfree(c->d_lpos2); dfree(c->d_rlevel);
+    if (c->ev_async) hipEventDestroy(c->ev_async); dfree(c->d_lvl_out); hfree(c->h_lvl);
     dfree(c->d_rlist); dfree(c->d_rlist_full);
     dfree(c->d_xy); dfree(c->d_conic); dfree(c->d_rgb); dfree(c->d_depth); dfree(c->d_rect); dfree(c->d_tiles);
     for (int i = 0; i < 2; ++i) { dfree(c->d_dkey[i]); dfree(c->d_dval[i]); dfree(c->d_pkey[i]); dfree(c->d_pval[i]); }
@@ -580,6 +591,7 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         else { HIPCHK(hipStreamCreateWithFlags(&c->sc, hipStreamNonBlocking)); c->own_sc = true; }
         HIPCHK(hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c->ev_async, hipEventDisableTiming));
         for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
         {
             // this device's fixed scratch for vm3dgs_frame_noalloc (looked up
@@ -655,12 +667,15 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         HIPCHK(hipMemset(c->d_sub_vpage, 0xff, sizeof(int32_t) * S * SUBS));
         HIPCHK(hipMemset(c->d_sub_lu, 0xff, sizeof(int32_t) * S * SUBS));
         HIPCHK(hipMemset(c->d_v2p, 0xff, sizeof(int32_t) * n_pg * L));
-        dalloc(&c->d_copies, (size_t)n_pg * L); halloc(&c->h_copies, (size_t)n_pg * L);
+        dalloc(&c->d_copies_buf[0], (size_t)n_pg * L); dalloc(&c->d_copies_buf[1], (size_t)n_pg * L);
+        c->d_copies = c->d_copies_buf[0];
+        halloc(&c->h_copies, (size_t)n_pg * L);
         dalloc(&c->d_copy_id, (size_t)4 * n_pg * L);
         dalloc(&c->d_missing, (size_t)2 * n_pg * L); halloc(&c->h_missing, (size_t)2 * n_pg * L);
         dalloc(&c->d_rlist, n_pg);
         if (c->multi) {
             dalloc(&c->d_lkeys_alt, n_pg); dalloc(&c->d_lflag, n_pg); dalloc(&c->d_lpos, (size_t)n_pg + 1);
+            dalloc(&c->d_lflag2, n_pg); dalloc(&c->d_lpos2, (size_t)n_pg + 1); dalloc(&c->d_rlevel, n_pg);
             dalloc(&c->d_wkeys[0], S); dalloc(&c->d_wkeys[1], S);
             for (int l = 1; l < L; ++l) { dalloc(&c->d_ck[l][0], (size_t)S * SUBS); dalloc(&c->d_ck[l][1], (size_t)S * SUBS); }
             dalloc(&c->d_fresh, (size_t)3 * S);
@@ -737,6 +752,8 @@ vm3dgs_status frame_impl(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views,
         HIPCHK(hipEventRecord(ev[0], c->sr));
         HIPCHK(hipMemcpyAsync(c->d_cams, c->h_cams, sizeof(CamK) * n_views, hipMemcpyHostToDevice, c->sr));
         if (c->pf_on) push_poses(c, cams, n_views);
+        c->cpb ^= 1;
+        c->d_copies = c->d_copies_buf[c->cpb];
         c->sw.reset();
         c->rb.n = 0;
         VisArgs va{};
@@ -767,12 +784,14 @@ vm3dgs_status frame_impl(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views,
         pa.sub_last_used = c->d_sub_lu; pa.v2p = c->d_v2p; pa.req_sub = c->d_req_sub; pa.slot_req = c->d_slot_req;
         pa.miss = c->d_miss; pa.copies = c->d_copies; pa.copy_id = c->d_copy_id; pa.missing = c->d_missing;
         pa.counters = c->d_ctr; pa.level_base = c->d_level_base; pa.rl = c->d_rlist;
+        const bool streaming = (c->opt.flags & VM3DGS_FLAG_ASYNC_MISSES) != 0;
+        pa.streaming = streaming ? 1 : 0; pa.rlevel = c->d_rlevel;
         if (!c->multi) {
             launch_pagetable(c->sr, pa, 0);
         } else {
             LodWork lw{};
             lw.keys_alt = c->d_lkeys_alt; lw.keys_out = c->d_keys + c->n_pg; lw.level_out = c->d_lvl_out;
-            lw.flag = c->d_lflag; lw.pos = c->d_lpos; lw.wkeys[0] = c->d_wkeys[0]; lw.wkeys[1] = c->d_wkeys[1];
+            lw.flag = c->d_lflag; lw.pos = c->d_lpos; lw.flag2 = c->d_lflag2; lw.pos2 = c->d_lpos2; lw.wkeys[0] = c->d_wkeys[0]; lw.wkeys[1] = c->d_wkeys[1];
             for (int l = 0; l < 3; ++l) { lw.ck[l][0] = c->d_ck[l][0]; lw.ck[l][1] = c->d_ck[l][1]; }
             lw.fresh = c->d_fresh;
             launch_pagetable_lod(c->sr, pa, c->sw, lw);
@@ -808,15 +827,33 @@ vm3dgs_status frame_impl(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views,
         const uint32_t n_dem = n_copy - n_pf;
         const uint64_t max_cmd = (uint64_t)c->P * c->ps.bytes_g;
         const uint64_t pool_bytes = max_cmd * (uint64_t)c->S;
-        // prefetch copies of earlier frames (copy stream) finish before this frame
-        // writes or reads the pool
+        // copies of earlier frames on the copy stream (prefetches, streamed
+        // misses) finish before this frame writes or reads the pool
         if (c->pf_pending) {
             HIPCHK(hipStreamWaitEvent(c->sr, c->ev_pf, 0));
             c->pf_pending = false;
+    c->async_pending = false;
         }
-        // demand copies: read by the GPU from the pinned store, in order before the splat
-        launch_copy_pages(c->sr, c->d_copies, 0, n_dem, max_cmd, c->h_store_dev, (uint64_t)c->ps.store_bytes,
-                          c->d_pool, pool_bytes, (unsigned long long*)(c->d_zero + ZB_BYTES), c->d_cp_err);
+        if (c->async_pending) {
+            HIPCHK(hipStreamWaitEvent(c->sr, c->ev_async, 0));
+            c->async_pending = false;
+        }
+        if (!streaming) {
+            // demand copies: read by the GPU from the pinned store, in order before the splat
+            launch_copy_pages(c->sr, c->d_copies, 0, n_dem, max_cmd, c->h_store_dev, (uint64_t)c->ps.store_bytes,
+                              c->d_pool, pool_bytes, (unsigned long long*)(c->d_zero + ZB_BYTES), c->d_cp_err);
+        } else if (n_dem) {
+            // streaming (Sec. 4.3, Sec. 5.1.2): the frame renders what was resident
+            // when it started; its copies run on the copy stream beside the splat
+            // and the next frame waits for them before it touches the pool
+            launch_copy_bytes(c->sr, c->d_copies, 0, n_dem, (unsigned long long*)(c->d_zero + ZB_BYTES));
+            HIPCHK(hipEventRecord(c->ev_copy, c->sr));
+            HIPCHK(hipStreamWaitEvent(c->sc, c->ev_copy, 0));
+            launch_copy_pages(c->sc, c->d_copies, 0, n_dem, max_cmd, c->h_store_dev, (uint64_t)c->ps.store_bytes,
+                              c->d_pool, pool_bytes, c->d_pf_bytes, c->d_cp_err);
+            HIPCHK(hipEventRecord(c->ev_async, c->sc));
+            c->async_pending = true;
+        }
         HIPCHK(hipGetLastError());
         // prefetch copies: on the copy stream, after the page table; not awaited by this frame
         if (n_pf) {
@@ -834,6 +871,7 @@ vm3dgs_status frame_impl(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views,
         c->last_n_pfreq = (c->pf_on && c->pf_net) ? k[C_NPFREQ] : 0u;
         c->last_n_pf = n_pf;
         st.prefetched = n_pf;
+        st.fallbacks = k[C_FALLBACK];
         const uint32_t n_render = k[C_NRENDER];
         c->last_n_copy = n_copy; c->last_n_missing = k[C_NMISSING]; c->last_n_req = k[C_NREQ];
         c->last_n_rl = k[C_NRL];
@@ -1209,19 +1247,20 @@ int64_t vm3dgs_debug_get(vm3dgs* c, const char* name, void* dst, int64_t cap) {
     if (n == "render_list") return dev(c->d_rlist, 16 * (int64_t)c->last_n_rl);
     const int64_t nt = (int64_t)c->last_n_render * c->last_views;
     if (n == "pp_float") {
-        const int64_t bytes = 44 * nt;
+        const int64_t bytes = 48 * nt;
         if (dst && cap >= bytes) {
-            std::vector<float2> xy((size_t)nt);
+            std::vector<float4> xy((size_t)nt);
             std::vector<float4> co((size_t)nt), rgb((size_t)nt);
             std::vector<uint32_t> dep((size_t)nt);
             hipStreamSynchronize(c->sr);
-            hipMemcpy(xy.data(), c->d_xy, 8 * nt, hipMemcpyDeviceToHost);
+            hipMemcpy(xy.data(), c->d_xy, 16 * nt, hipMemcpyDeviceToHost);
             hipMemcpy(co.data(), c->d_conic, 16 * nt, hipMemcpyDeviceToHost);
             hipMemcpy(rgb.data(), c->d_rgb, 16 * nt, hipMemcpyDeviceToHost);
             hipMemcpy(dep.data(), c->d_depth, 4 * nt, hipMemcpyDeviceToHost);
             for (int64_t i = 0; i < nt; ++i) {
-                float* f = (float*)dst + 11 * i;
-                f[10] = rgb[(size_t)i].w;
+                float* f = (float*)dst + 12 * i;
+                f[10] = xy[(size_t)i].w;   // support half height
+                f[11] = xy[(size_t)i].z;   // support half width
                 float d;
                 memcpy(&d, &dep[(size_t)i], 4);
                 f[0] = xy[(size_t)i].x; f[1] = xy[(size_t)i].y; f[2] = d;

@@ -53,13 +53,41 @@ __device__ int pow2_at_least(int n) {
 
 struct PtL1 {
     uint64_t* keys_sorted;  // out: requests in service order
-    int n_pg, P, S, frame, budget, bytes_g;
+    int n_pg, P, S, frame, budget, bytes_g, streaming;
     const int8_t* page_level;
     int8_t* slot_level; int32_t* last_used; int32_t* sub_vpage; int32_t* sub_last_used; int32_t* v2p;
     uint8_t* slot_req; uint32_t* miss;
     CopyCmd* copies; int32_t* copy_id; int32_t* missing; uint32_t* counters;
     RenderEntry* rl;
 };
+
+// requested pages resident now, in page order; returns their number
+__device__ uint32_t l1_render_list(const PtL1& a, uint32_t* scan_sh) {
+    const int t = threadIdx.x;
+    uint32_t n_rl = 0;
+    for (int base = 0; base < a.n_pg; base += PT_NT) {
+        const int p = base + t;
+        bool r = false;
+        int32_t e = -1;
+        if (p < a.n_pg && a.page_level[p] >= 0) {
+            e = a.v2p[p];
+            r = e >= 0;
+        }
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<PT_NT>(r ? 1u : 0u, scan_sh, &tot);
+        if (r) {
+            RenderEntry q;
+            q.pool_off = (uint32_t)((e / vmk::SUBS) * a.P);
+            q.count = (uint32_t)a.P;
+            q.base = (n_rl + ex) * (uint32_t)a.P;
+            q.level = 0;
+            a.rl[n_rl + ex] = q;
+        }
+        n_rl += tot;
+        __syncthreads();
+    }
+    return n_rl;
+}
 
 __global__ __launch_bounds__(PT_NT) void k_pagetable_l1(const uint64_t* __restrict__ req_keys, PtL1 a) {
     __shared__ uint64_t s[PT_MAXK];
@@ -104,6 +132,10 @@ __global__ __launch_bounds__(PT_NT) void k_pagetable_l1(const uint64_t* __restri
         n_miss += tot;
     }
     __syncthreads();
+    // streaming: the frame renders the pages resident when it started (the
+    // placements below only take pages no request of this frame holds)
+    uint32_t n_rl = 0;
+    if (a.streaming) n_rl = l1_render_list(a, scan_sh);
     // ---- stage 2 candidates: physical pages not required, (last use, slot) ascending
     uint64_t* cand = s;
     uint32_t n_free = 0;
@@ -153,29 +185,9 @@ __global__ __launch_bounds__(PT_NT) void k_pagetable_l1(const uint64_t* __restri
     }
     __syncthreads();
     __threadfence_block();
-    // ---- render list: requested and resident pages in page order
-    uint32_t n_rl = 0;
-    for (int base = 0; base < a.n_pg; base += PT_NT) {
-        const int p = base + t;
-        bool r = false;
-        int32_t e = -1;
-        if (p < a.n_pg && a.page_level[p] >= 0) {
-            e = a.v2p[p];
-            r = e >= 0;
-        }
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<PT_NT>(r ? 1u : 0u, scan_sh, &tot);
-        if (r) {
-            RenderEntry q;
-            q.pool_off = (uint32_t)((e / vmk::SUBS) * a.P);
-            q.count = (uint32_t)a.P;
-            q.base = (n_rl + ex) * (uint32_t)a.P;
-            q.level = 0;
-            a.rl[n_rl + ex] = q;
-        }
-        n_rl += tot;
-        __syncthreads();
-    }
+    // ---- render list: requested and resident pages in page order (streaming:
+    // built above, before the placements)
+    if (!a.streaming) n_rl = l1_render_list(a, scan_sh);
     uint32_t used = 0;
     for (int sl = t; sl < a.S; sl += PT_NT) used += a.sub_vpage[sl * vmk::SUBS] >= 0 ? 1u : 0u;
     used = wave_sum(used);
@@ -206,42 +218,66 @@ __global__ void k_ptl_pad_keys(uint64_t* __restrict__ keys, int n_pg, const uint
     if (i < n_pg && (uint32_t)i >= counters[vm::C_NREQ]) keys[i] = ~0ull;
 }
 
+// Streaming: a miss whose page is resident at another level is drawn at the
+// resident level nearest to the requested one (the finer at equal distance),
+// that entry is required too, and it is flagged in flag2 (served after the
+// other misses); rlevel receives the level each request is drawn at.  Two
+// requests never name one page, so the marks of different threads are of
+// different entries (the byte and int stores of equal values to one physical
+// page's flags and last use are the same values).
 __global__ void k_ptl_hits(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ counters,
                            const int8_t* __restrict__ page_level, int n_pg, int L, const int32_t* __restrict__ v2p,
                            uint8_t* __restrict__ req_sub, uint8_t* __restrict__ slot_req,
                            int32_t* __restrict__ last_used, int32_t* __restrict__ sub_last_used, int frame,
                            uint32_t* __restrict__ miss_flag, uint64_t* __restrict__ keys_out,
-                           int8_t* __restrict__ level_out) {
+                           int8_t* __restrict__ level_out, int streaming, uint32_t* __restrict__ miss_flag2,
+                           int8_t* __restrict__ rlevel) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_pg) return;
     const uint32_t n = counters[vm::C_NREQ];
-    uint32_t flag = 0;
+    uint32_t flag = 0, flag2 = 0;
     if ((uint32_t)i < n) {
         const uint64_t key = keys[i];
         const int32_t pg = (int32_t)(key & 0x3fffffffull);
         const int l = page_level[pg];
         keys_out[i] = key;
         level_out[i] = (int8_t)l;
-        const int32_t e = v2p[pg * L + l];
+        int32_t e = v2p[pg * L + l];
+        int drawn = e >= 0 ? l : -1;
+        if (e < 0 && streaming) {
+            for (int d = 1; d < L && drawn < 0; ++d) {
+                if (l - d >= 0 && v2p[pg * L + l - d] >= 0) drawn = l - d;
+                else if (l + d < L && v2p[pg * L + l + d] >= 0) drawn = l + d;
+            }
+            if (drawn >= 0) e = v2p[pg * L + drawn];
+        }
         if (e >= 0) {
             req_sub[e] = 1;
             slot_req[e / vmk::SUBS] = 1;
             last_used[e / vmk::SUBS] = frame;
             sub_last_used[e] = frame;
-        } else {
-            flag = 1;
         }
+        if (drawn != l) {
+            flag = drawn < 0 ? 1u : 0u;
+            flag2 = drawn < 0 ? 0u : 1u;
+        }
+        if (streaming) rlevel[pg] = (int8_t)drawn;
     }
     miss_flag[i] = flag;
+    if (streaming) miss_flag2[i] = flag2;
 }
 
+// misses in service order: request order, and with streaming the misses
+// drawn at another level (flag2, positions pos2 after the first list's total)
 __global__ void k_ptl_miss_list(const uint64_t* __restrict__ keys, const int8_t* __restrict__ page_level, int n_pg,
                                 const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos,
+                                const uint32_t* __restrict__ flag2, const uint32_t* __restrict__ pos2,
                                 uint32_t* __restrict__ miss) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_pg || !flag[i]) return;
+    if (i >= n_pg) return;
     const uint32_t pg = (uint32_t)(keys[i] & 0x3fffffffull);
-    miss[pos[i]] = pg | ((uint32_t)page_level[pg] << 30);
+    if (flag[i]) miss[pos[i]] = pg | ((uint32_t)page_level[pg] << 30);
+    else if (flag2 && flag2[i]) miss[pos[n_pg] + pos2[i]] = pg | ((uint32_t)page_level[pg] << 30);
 }
 
 // candidate keys: whole free pages (last use + 1, slot) and, per level l >= 1,
@@ -412,12 +448,15 @@ __global__ __launch_bounds__(WAVE) void k_ptl_walk(PtWalk a) {
 }
 
 // render list with per-level counts, and the number of occupied physical pages
+// streaming: a requested page is drawn at rlevel (the level stage one found
+// resident when the frame started), otherwise at its requested level if resident
 __global__ __launch_bounds__(PT_NT) void k_ptl_render_list(const int8_t* __restrict__ page_level,
                                                            const int32_t* __restrict__ v2p, int n_pg, int L, int P,
                                                            int S, const int8_t* __restrict__ slot_level,
                                                            const int32_t* __restrict__ sub_vpage,
                                                            const uint8_t* __restrict__ slot_req,
-                                                           RenderEntry* __restrict__ rl, uint32_t* __restrict__ counters) {
+                                                           RenderEntry* __restrict__ rl, uint32_t* __restrict__ counters,
+                                                           const int8_t* __restrict__ rlevel) {
     __shared__ uint32_t scan_sh[PT_NT / WAVE];
     __shared__ int8_t s_lvl[RL_SEG];   // per page of the segment: level rendered, or -1
     __shared__ uint32_t s_used, s_reqd;
@@ -431,7 +470,8 @@ __global__ __launch_bounds__(PT_NT) void k_ptl_render_list(const int8_t* __restr
     for (int seg = 0; seg < n_pg; seg += RL_SEG) {
         const int n = min(RL_SEG, n_pg - seg);
         for (int i = t; i < n; i += PT_NT) {
-            const int l = page_level[seg + i];
+            int l = page_level[seg + i];
+            if (l >= 0 && rlevel) l = rlevel[seg + i];
             s_lvl[i] = (int8_t)((l >= 0 && v2p[(int64_t)(seg + i) * L + l] >= 0) ? l : -1);
         }
         __syncthreads();
@@ -485,8 +525,11 @@ __global__ __launch_bounds__(PT_NT) void k_ptl_render_list(const int8_t* __restr
     }
 }
 
-__global__ void k_ptl_count_misses(const uint32_t* __restrict__ total, uint32_t* __restrict__ counters) {
-    counters[vm::C_MISSES] = *total;
+__global__ void k_ptl_count_misses(const uint32_t* __restrict__ total, const uint32_t* __restrict__ total2,
+                                   uint32_t* __restrict__ counters) {
+    const uint32_t t2 = total2 ? *total2 : 0u;
+    counters[vm::C_MISSES] = *total + t2;
+    counters[vm::C_FALLBACK] = t2;
 }
 
 
@@ -538,6 +581,22 @@ __global__ __launch_bounds__(CP_NT) void k_copy_pages(const vm::CopyCmd* __restr
     }
 }
 
+// bytes of copy commands [first, first + n) into *out (one workgroup)
+__global__ __launch_bounds__(PT_NT) void k_copy_bytes(const vm::CopyCmd* __restrict__ cmds, uint32_t first, uint32_t n,
+                                                     unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long part[PT_NT / WAVE];
+    unsigned long long b = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += PT_NT) b += (unsigned long long)cmds[first + i].bytes;
+    for (int o = WAVE / 2; o > 0; o >>= 1) b += __shfl_down(b, o);
+    if (__lane_id() == 0) part[threadIdx.x / WAVE] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+        for (int w = 0; w < PT_NT / WAVE; ++w) s += part[w];
+        *out = s;
+    }
+}
+
 }  // namespace vmk
 
 namespace vm {
@@ -549,6 +608,7 @@ void launch_pagetable(hipStream_t st, const PtArgs& a, int) {
     PtL1 k;
     k.keys_sorted = const_cast<uint64_t*>(a.req_keys) + a.n_pg;  // second half of the key buffer
     k.n_pg = a.n_pg; k.P = a.P; k.S = a.S; k.frame = a.frame; k.budget = a.budget; k.bytes_g = a.bytes_g;
+    k.streaming = a.streaming;
     k.page_level = a.page_level;
     k.slot_level = a.slot_level; k.last_used = a.last_used; k.sub_vpage = a.sub_vpage;
     k.sub_last_used = a.sub_last_used; k.v2p = a.v2p; k.slot_req = a.slot_req; k.miss = a.miss;
@@ -579,11 +639,14 @@ void launch_pagetable_lod(hipStream_t st, const PtArgs& a, SortWork& sw, const L
     launch_fill_u32(st, (uint32_t*)a.slot_req, ((uint64_t)S + 3) / 4, 0u);
     hipLaunchKernelGGL(k_ptl_hits, dim3(nb_pg), dim3(256), 0, st, keys, (const uint32_t*)a.counters, a.page_level,
                        n_pg, L, (const int32_t*)a.v2p, a.req_sub, a.slot_req, a.last_used, a.sub_last_used, a.frame,
-                       w.flag, w.keys_out, w.level_out);
+                       w.flag, w.keys_out, w.level_out, a.streaming, w.flag2, a.rlevel);
     scan_lb(st, sw, w.flag, (uint64_t)n_pg, w.pos, w.pos + n_pg);
-    hipLaunchKernelGGL(k_ptl_count_misses, dim3(1), dim3(1), 0, st, (const uint32_t*)(w.pos + n_pg), a.counters);
+    if (a.streaming) scan_lb(st, sw, w.flag2, (uint64_t)n_pg, w.pos2, w.pos2 + n_pg);
+    hipLaunchKernelGGL(k_ptl_count_misses, dim3(1), dim3(1), 0, st, (const uint32_t*)(w.pos + n_pg),
+                       a.streaming ? (const uint32_t*)(w.pos2 + n_pg) : nullptr, a.counters);
     hipLaunchKernelGGL(k_ptl_miss_list, dim3(nb_pg), dim3(256), 0, st, keys, a.page_level, n_pg,
-                       (const uint32_t*)w.flag, (const uint32_t*)w.pos, a.miss);
+                       (const uint32_t*)w.flag, (const uint32_t*)w.pos,
+                       a.streaming ? (const uint32_t*)w.flag2 : nullptr, (const uint32_t*)w.pos2, a.miss);
     const int idx_bits = bits_for_u((uint64_t)S * SUBS);
     // one bit above the largest eligible key, so that the all-ones keys of
     // ineligible entries sort strictly after every eligible one
@@ -617,12 +680,17 @@ void launch_pagetable_lod(hipStream_t st, const PtArgs& a, SortWork& sw, const L
     hipLaunchKernelGGL(k_ptl_walk, dim3(1), dim3(WAVE), 0, st, pw);
     hipLaunchKernelGGL(k_ptl_render_list, dim3(1), dim3(PT_NT), 0, st, (const int8_t*)a.page_level,
                        (const int32_t*)a.v2p, n_pg, L, a.P, S, (const int8_t*)a.slot_level,
-                       (const int32_t*)a.sub_vpage, (const uint8_t*)a.slot_req, a.rl, a.counters);
+                       (const int32_t*)a.sub_vpage, (const uint8_t*)a.slot_req, a.rl, a.counters,
+                       a.streaming ? (const int8_t*)a.rlevel : nullptr);
 }
 
 }  // namespace vm
 
 namespace vm {
+
+void launch_copy_bytes(hipStream_t st, const CopyCmd* cmds, uint32_t first, uint32_t count, unsigned long long* out) {
+    hipLaunchKernelGGL(vmk::k_copy_bytes, dim3(1), dim3(vmk::PT_NT), 0, st, cmds, first, count, out);
+}
 
 void launch_copy_pages(hipStream_t st, const CopyCmd* cmds, uint32_t first, uint32_t count, uint64_t max_cmd_bytes,
                        const uint8_t* host, uint64_t host_bytes, uint8_t* pool, uint64_t pool_bytes,

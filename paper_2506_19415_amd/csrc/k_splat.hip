@@ -64,7 +64,7 @@ struct PreArgs {
     int W, H, TX, TY;
     uint32_t n_render; uint64_t n_total;
     int sigma3_tiles;
-    float2* xy; float4* conic; float4* rgb; uint32_t* depth; uint2* rect; uint32_t* tiles;
+    float4* xy; float4* conic; float4* rgb; uint32_t* depth; uint2* rect; uint32_t* tiles;
     uint32_t* dkey; uint32_t* dval;
 };
 
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
     ok = ok && (t.z > c.znear);
     float u = 0.f, vv = 0.f, ca = 0.f, cb = 0.f, cc2 = 0.f;
     int ix0 = 0, iy0 = 0, ix1 = 0, iy1 = 0;
-    float hy = __builtin_inff();
+    float hx = __builtin_inff(), hy = __builtin_inff();
     float col[3] = {0.f, 0.f, 0.f};
     if (ok) {
         const float w = g.q[0], x = g.q[1], y = g.q[2], z = g.q[3];
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
                 const float e = 5e-7f * kap;
                 if (e < 0.5f) {
                     const float fm = 1.0f / (1.0f - e);
-                    const float hx = sqrtf((11.11f * fm) * A) + 1.0f;
+                    hx = sqrtf((11.11f * fm) * A) + 1.0f;
                     hy = sqrtf((11.11f * fm) * Cc) + 1.0f;
                     const float bx0 = fminf(fmaxf(floorf((u - hx) / 16.0f), 0.0f), (float)a.TX);
                     const float bx1 = fminf(fmaxf(floorf((u + hx) / 16.0f) + 1.0f, 0.0f), (float)a.TX);
@@ -205,9 +205,9 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
             }
         }
     }
-    a.xy[f] = make_float2(u, vv);
+    a.xy[f] = make_float4(u, vv, ok ? hx : __builtin_inff(), ok ? hy : __builtin_inff());
     a.conic[f] = make_float4(ca, cb, cc2, ok ? g.o : 0.0f);
-    a.rgb[f] = make_float4(col[0], col[1], col[2], ok ? hy : __builtin_inff());
+    a.rgb[f] = make_float4(col[0], col[1], col[2], 0.0f);
     a.depth[f] = ok ? __float_as_uint(t.z) : NONE32;
     a.rect[f] = ok ? make_uint2((uint32_t)ix0 | ((uint32_t)iy0 << 16), (uint32_t)ix1 | ((uint32_t)iy1 << 16))
                    : make_uint2(0u, 0u);
@@ -328,16 +328,21 @@ __global__ void k_ranges(const uint32_t* __restrict__ key, uint32_t cap, const u
 // barriers), so a wave whose strip holds most of the tile's work (a horizon
 // band, say) is not held back at every batch by the others: each wave walks
 // the tile's depth-ordered pairs in chunks of 64, one pair per lane, with the
-// gathers of the next chunk in flight while it blends the current one.  The
-// lanes whose Gaussian's support rows meet the strip form a mask; the wave
-// takes the set bits in order, four at a time, and broadcasts each Gaussian
-// from its lane through scalar registers (v_readlane).  The exponents of four
-// Gaussians are evaluated together, then the four are blended in order (the
-// pixel state after one decides whether the next one is taken); the lanes
-// evaluate with the pixel's "live" flag as a predicate, and the wave stops
-// when no lane is live.  STATS counts, per tile, the pixel-Gaussian
-// evaluations and those that reached the alpha computation (the algorithmic
-// work).
+// gathers of the next chunk in flight while it blends the current one.
+// Each lane first tests its Gaussian's support box (outside it no term passes
+// the alpha test) against the strip's pixels that still blend: the box's
+// columns and rows give a 64-bit mask of the strip's pixels (bit = lane), and
+// the lanes whose mask meets the wave's live mask form the chunk's work list.
+// A Gaussian that only covers pixels already stopped (an opaque band under a
+// sky that never stops, say) is so skipped by one test per 64 Gaussians.  The
+// wave takes the listed Gaussians in order, four at a time, and broadcasts
+// each from its lane through scalar registers (v_readlane).  The exponents of
+// four Gaussians are evaluated together, then the four are blended in order
+// (the pixel state after one decides whether the next one is taken); the
+// lanes evaluate with the pixel's "live" flag as a predicate, and the wave
+// stops when no lane is live.  STATS counts, per tile, the algorithmic work:
+// per pixel the list entries the front-to-back loop visits (up to and
+// including the one at which it stops), and the alpha evaluations.
 constexpr int BL_NT = TILE * TILE;
 
 __device__ __forceinline__ float uniform_f(float x) {
@@ -349,9 +354,24 @@ __device__ __forceinline__ float lane_f(float x, int i) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), i));
 }
 
+// pixels of a 16 x 4 strip (bit = row * 16 + column) whose centre lies in
+// the box |px - u| <= hx, |py - v| <= hy; (sx, sy) is the strip's first
+// pixel.  The support half-widths carry a pixel of margin, more than the
+// rounding of these differences.
+__device__ __forceinline__ uint64_t strip_box_mask(float u, float v, float hx, float hy, float sx, float sy) {
+    const float c0 = fmaxf(ceilf((u - hx) - sx), 0.0f), c1 = fminf(floorf((u + hx) - sx), 15.0f);
+    const float r0 = fmaxf(ceilf((v - hy) - sy), 0.0f), r1 = fminf(floorf((v + hy) - sy), 3.0f);
+    if (!(c0 <= c1) || !(r0 <= r1)) return 0ull;
+    const int ic0 = (int)c0, ic1 = (int)c1, ir0 = (int)r0, ir1 = (int)r1;
+    const uint64_t cols = (uint64_t)(((2u << ic1) - 1u) & ~((1u << ic0) - 1u));
+    // one bit per row in [ir0, ir1] at the row's first column
+    const uint64_t rows = (0x0001000100010001ull >> (16 * (3 - ir1))) & (~0ull << (16 * ir0));
+    return rows * cols;
+}
+
 template <bool STATS>
 __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ ranges, const uint32_t* __restrict__ order,
-                                                 const uint32_t* __restrict__ pval, const float2* __restrict__ xy,
+                                                 const uint32_t* __restrict__ pval, const float4* __restrict__ xy,
                                                  const float4* __restrict__ conic, const float4* __restrict__ rgb,
                                                  int W, int H, int TX, int TY, float* __restrict__ image,
                                                  uint2* __restrict__ stats) {
@@ -367,18 +387,19 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
     const uint2 rg = ranges[tile];
     const float fpx = (float)px, fpy = (float)py;
     const int lane = (int)__lane_id();
-    // centre row of this wave's strip, in a scalar register
-    const float strip_c = uniform_f((float)(ty * TILE + (int)(threadIdx.x / WAVE) * (WAVE / TILE)) + 1.5f);
+    // first pixel of this wave's strip, in scalar registers
+    const float strip_x = uniform_f((float)(tx * TILE));
+    const float strip_y = uniform_f((float)(ty * TILE + (int)(threadIdx.x / WAVE) * (WAVE / TILE)));
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    uint32_t n_eval = 0, n_alpha = 0;
+    uint32_t n_visit = inside ? rg.y - rg.x : 0u, n_alpha = 0;   // list entries the pixel's loop visits
     bool live = inside;   // this pixel still blends
     uint64_t live_m = __builtin_amdgcn_ballot_w64(live);   // the wave's live pixels
     bool wave_live = live_m != 0;
-    // chunk registers: this chunk's Gaussian (centre; conic and opacity;
-    // colour and support half height), the next chunk's, and the pair value
-    // of the one after
-    float2 n_p = make_float2(0.f, 0.f);
-    float4 n_co = make_float4(0.f, 0.f, 0.f, 0.f), n_cl = n_co;
+    // chunk registers: this chunk's Gaussian (centre and support half-widths;
+    // conic and opacity; colour), the next chunk's, and the pair value of the
+    // one after
+    float4 n_p = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 n_co = n_p, n_cl = n_p;
     if (rg.x + lane < rg.y) {
         const uint32_t f = pval[rg.x + lane];
         n_p = xy[f];
@@ -387,7 +408,7 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
     }
     uint32_t n_f = rg.x + WAVE + lane < rg.y ? pval[rg.x + WAVE + lane] : 0u;
     for (uint32_t base = rg.x; base < rg.y && wave_live; base += WAVE) {
-        const float2 gp = n_p;
+        const float4 gp = n_p;
         const float4 gb = n_co, gc = n_cl;
         const bool valid = base + lane < rg.y;
         if (base + WAVE + lane < rg.y) {
@@ -396,9 +417,10 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
             n_cl = rgb[n_f];
         }
         n_f = base + 2 * WAVE + lane < rg.y ? pval[base + 2 * WAVE + lane] : 0u;
-        // the chunk's Gaussians whose support rows meet this strip (the
-        // others are rejected by every pixel of the strip)
-        uint64_t mask = __builtin_amdgcn_ballot_w64(valid && fabsf(gp.y - strip_c) <= gc.w + 1.5f);
+        // the chunk's Gaussians whose support box meets a live pixel of the
+        // strip (every pixel rejects the others)
+        const uint64_t box = valid ? strip_box_mask(gp.x, gp.y, gp.z, gp.w, strip_x, strip_y) : 0ull;
+        uint64_t mask = __builtin_amdgcn_ballot_w64((box & live_m) != 0ull);
         while (mask != 0 && wave_live) {
             int ii[4];
             bool ok[4];
@@ -423,15 +445,10 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
                 mk[u] = __builtin_amdgcn_ballot_w64(pw[u] <= 0.0f) & __builtin_amdgcn_ballot_w64(pw[u] >= -5.55f) &
                         (ok[u] ? ~0ull : 0ull);
             }
-            if (((mk[0] | mk[1] | mk[2] | mk[3]) & live_m) == 0) {
-                // no live pixel of the strip is in range of any of the four
-                if (STATS) n_eval += live ? (uint32_t)(ok[0] + ok[1] + ok[2] + ok[3]) : 0u;
-                continue;
-            }
+            if (((mk[0] | mk[1] | mk[2] | mk[3]) & live_m) == 0) continue;   // no live pixel in range of any
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const float power = pw[u];
-                if (STATS) n_eval += (live && ok[u]) ? 1u : 0u;
                 if ((mk[u] & live_m) != 0) {
                     const bool in = live && power <= 0.0f && power >= -5.55f;
                     if (STATS) n_alpha += in ? 1u : 0u;
@@ -450,6 +467,7 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
                     C1 = add ? n1 : C1;
                     C2 = add ? n2 : C2;
                     T = add ? Tn : T;
+                    if (STATS && stop) n_visit = base + (uint32_t)ii[u] + 1u - rg.x;
                     live = live && !stop;
                     live_m = __builtin_amdgcn_ballot_w64(live);
                 }
@@ -462,7 +480,7 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
         o[0] = C0; o[1] = C1; o[2] = C2;
     }
     if (STATS) {
-        const uint32_t e = wave_sum(n_eval), al = wave_sum(n_alpha);
+        const uint32_t e = wave_sum(n_visit), al = wave_sum(n_alpha);
         if (lane == 0) { s_st[0][threadIdx.x / WAVE] = e; s_st[1][threadIdx.x / WAVE] = al; }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -513,7 +531,7 @@ void launch_tile_order(hipStream_t st, const uint2* ranges, uint32_t n_tiles, ui
     if (n_tiles) hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(TO_NT), 0, st, ranges, n_tiles, order);
 }
 
-void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* order, const uint32_t* pval, const float2* xy,
+void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* order, const uint32_t* pval, const float4* xy,
                   const float4* conic, const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image,
                   uint2* stats) {
     const uint32_t n_tiles = (uint32_t)(TX * TY * n_views);

@@ -101,6 +101,7 @@ enum Ctr {
     C_REQSLOTS,   // physical pages required after the demand stages
     C_NCOARSE,    // requests at a level above 0
     C_PTERR,      // page-table bound check (never set when the host checks hold)
+    C_FALLBACK,   // streaming: requests drawn at another resident level
     C_NCOUNTERS = 24
 };
 
@@ -138,6 +139,10 @@ struct PtArgs {
     CopyCmd* copies; int32_t* copy_id; int32_t* missing; uint32_t* counters;
     const int64_t* level_base;  // device [3]
     RenderEntry* rl;
+    // streaming: the frame renders what was resident when it started (a page
+    // resident only at another level at the nearest one); rlevel [n_pg] is
+    // the level each requested page is drawn at (several levels only)
+    int streaming; int8_t* rlevel;
 };
 void launch_pagetable(hipStream_t st, const PtArgs& a, int n_req_host_bound);
 
@@ -148,6 +153,8 @@ struct LodWork {
     int8_t* level_out;      // [n_pg] their levels (read back)
     uint32_t* flag;         // [n_pg]
     uint32_t* pos;          // [n_pg + 1]
+    uint32_t* flag2;        // [n_pg] streaming: misses with a resident level (served last)
+    uint32_t* pos2;         // [n_pg + 1]
     uint64_t* wkeys[2];     // [S] x 2
     uint64_t* ck[3][2];     // per level 1, 2: [S*64] x 2
     int32_t* fresh;         // [3][S]
@@ -161,7 +168,7 @@ struct SplatArgs {
     int W, H, TX, TY;
     uint32_t n_render;  // per view
     int sigma3_tiles;   // 1: 3-sigma tile rectangles only (no support box)
-    float2* xy; float4* conic; float4* rgb; uint32_t* depth; uint2* rect; uint32_t* tiles;
+    float4* xy; float4* conic; float4* rgb; uint32_t* depth; uint2* rect; uint32_t* tiles;
     uint32_t* dkey; uint32_t* dval;
 };
 void launch_preprocess(hipStream_t st, const SplatArgs& a);
@@ -172,7 +179,7 @@ void launch_emit(hipStream_t st, const uint32_t* order, const uint32_t* offsets,
 void launch_ranges(hipStream_t st, const uint32_t* pkey, uint32_t cap, const uint32_t* n_pairs_dev, uint2* ranges,
                    uint32_t n_tiles);
 void launch_tile_order(hipStream_t st, const uint2* ranges, uint32_t n_tiles, uint32_t* order);
-void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* order, const uint32_t* pval, const float2* xy,
+void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* order, const uint32_t* pval, const float4* xy,
                   const float4* conic, const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image,
                   uint2* stats);
 // fills done together in one launch (at most kMax)
@@ -251,6 +258,8 @@ void launch_gather_rows(hipStream_t st, const float* src, const uint32_t* idx, u
 // the prefetch stage of a context: its network (or NULL) and options; false without a stage
 bool prefetch_stage_of(const vm3dgs* ctx, vm3dgs_mlp** net, vm3dgs_prefetch_opts* opts);
 
+// total bytes of copy commands [first, first + count) into *out
+void launch_copy_bytes(hipStream_t st, const CopyCmd* cmds, uint32_t first, uint32_t count, unsigned long long* out);
 // copies of the misses by the GPU from the pinned host store (one command per
 // 16 KB chunk and workgroup); bytes_done accumulates the bytes copied
 void launch_copy_pages(hipStream_t st, const CopyCmd* cmds, uint32_t first, uint32_t count, uint64_t max_cmd_bytes,

@@ -33,7 +33,7 @@ def test_struct_layout_matches_c_compiler(tmp_path):
     import subprocess
     fields = {"vm3dgs_options": ["img_w", "flags", "stream_render", "stream_copy", "pair_capacity", "lod_scale_up"],
               "vm3dgs_camera": ["view", "cam_pos", "fx", "znear"],
-              "vm3dgs_stats": ["candidates", "prefetched", "render_gaussians", "blend_alphas", "ms_visibility",
+              "vm3dgs_stats": ["candidates", "prefetched", "fallbacks", "render_gaussians", "blend_alphas", "ms_visibility",
                                "ms_total"],
               "vm3dgs_scene": ["n", "sh"],
               "vm3dgs_frame_out": ["requests", "n_requests", "missing", "n_missing", "stats"],

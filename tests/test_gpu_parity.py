@@ -65,7 +65,7 @@ def compare_frame(r, ovm, out, n_views, check_image=True, tag=""):
 
 def compare_splat(r, ovm, n_views, check_image=True, tag=""):
     g = r.get
-    pf, pi = g("pp_float", np.float32).reshape(-1, 11), g("pp_int", np.int32).reshape(-1, 6)
+    pf, pi = g("pp_float", np.float32).reshape(-1, 12), g("pp_int", np.int32).reshape(-1, 6)
     of, oi = ovm.get("pp_float").reshape(-1, 10), ovm.get("pp_int").reshape(-1, 6)
     assert pf.shape[0] == of.shape[0], tag
     assert np.array_equal(pi[:, 0], oi[:, 0]), tag           # culled
@@ -74,11 +74,14 @@ def compare_splat(r, ovm, n_views, check_image=True, tag=""):
     assert np.array_equal(pf[vis, 2].view(np.uint32), of[vis, 2].view(np.uint32)), tag   # depth keys
     assert np.array_equal(pf[vis, :2], of[vis, :2]), tag      # pixel centre
     np.testing.assert_allclose(pf[vis, 3:10], of[vis, 3:10], rtol=1e-5, atol=1e-7, err_msg=tag)
-    # the library's support-box half height (its blend skips the rows beyond
-    # it): every row where the conic's quadratic form can reach 11.1 is within
+    # the library's support-box half height and width (its blend skips the
+    # pixels beyond them): every row and column where the conic's quadratic
+    # form can reach 11.1 is within them
     c64 = pf[vis, 3:6].astype(np.float64)
-    syy = c64[:, 0] / (c64[:, 0] * c64[:, 2] - c64[:, 1] ** 2)
+    det = c64[:, 0] * c64[:, 2] - c64[:, 1] ** 2
+    syy, sxx = c64[:, 0] / det, c64[:, 2] / det
     assert np.all(pf[vis, 10].astype(np.float64) >= np.sqrt(11.1 * syy)), tag
+    assert np.all(pf[vis, 11].astype(np.float64) >= np.sqrt(11.1 * sxx)), tag
     n_render = pf.shape[0] // n_views
     keys, vals = g("keys", np.uint32), g("vals", np.uint32)
     okeys, ovals = ovm.get("keys"), ovm.get("vals")
@@ -301,7 +304,7 @@ def test_terrain6m_full_size_sampled():
             assert np.array_equal(g(name, dt), ovm.get(name)), (k, name)
         req = np.ctypeslib.as_array(out.requests, (out.n_requests,))
         assert np.array_equal(req, ovm.get("req_page")), k
-        pf, pi = g("pp_float", np.float32).reshape(-1, 11), g("pp_int", np.int32).reshape(-1, 6)
+        pf, pi = g("pp_float", np.float32).reshape(-1, 12), g("pp_int", np.int32).reshape(-1, 6)
         of, oi = ovm.get("pp_float").reshape(-1, 10), ovm.get("pp_int").reshape(-1, 6)
         assert np.array_equal(pi[:, 0], oi[:, 0]), k
         vis = oi[:, 0] == 0
@@ -416,4 +419,56 @@ def test_adaptive_lod_thresholds(city):
         taus.append(out.stats.lod_radius_px)
         compare_frame(r, ovm, out, 1, tag=f"adaptive lod {k}")
     assert max(taus) > 128.0
+    r.close()
+
+
+# ---------------------------------------------------------------- streaming
+def test_streaming_one_level(clusters):
+    """Streaming (VM3DGS_FLAG_ASYNC_MISSES): frames render what was resident
+    when they started and their copies land for the next frame, with a
+    staging budget of 10 pages, a pool of 40 and no links (evictions); every
+    intermediate, the render set and the image against the oracle's model of
+    the same rule."""
+    import paper_2506_19415_amd as pkg
+    sc, osc = clusters
+    cams = synth.orbit()
+    r = _renderer(sc, 256, 40, (320, 240), (80, 60), 0.5, copy_budget=10, links=False)
+    r.set_flags(pkg.VM3DGS_FLAG_ASYNC_MISSES)
+    ovm = _ovm(osc, 40, (320, 240), (80, 60), copy_budget=10, use_links=False)
+    ovm.set_async(True)
+    rendered = evicted = 0
+    for k in list(range(8)) + [0, 1]:
+        print(f"streaming one level frame {k}", flush=True)
+        _, out = r.frame([cams[k]])
+        ovm.frame([cams[k]])
+        compare_frame(r, ovm, out, 1, tag=f"streaming {k}")
+        assert out.stats.render_pages <= out.stats.hits
+        rendered += out.stats.render_pages
+        evicted += out.stats.evictions
+    assert rendered > 0 and evicted > 0
+    r.close()
+
+
+@pytest.mark.parametrize("S,budget", [(64, 0), (48, 20)])
+def test_streaming_lod_city(city, S, budget):
+    """Streaming with three LOD levels on the street-to-aerial city path:
+    pages resident only at another level are drawn there (fallbacks) and
+    their transitions are served after the other misses; page-table state,
+    render set and image against the oracle, and the fallback count."""
+    import paper_2506_19415_amd as pkg
+    sc, cams = city
+    osc = oracle.OracleScene(sc, 512, 3, 2.0, 2.0)
+    r = _renderer(sc, 512, S, (480, 270), (120, 68), 2.0, lod_levels=3, lod_radius_px=128.0, copy_budget=budget)
+    r.set_flags(pkg.VM3DGS_FLAG_LINKS | pkg.VM3DGS_FLAG_ASYNC_MISSES)
+    ovm = _ovm(osc, S, (480, 270), (120, 68), copy_budget=budget, lod_radius_px=128.0)
+    ovm.set_async(True)
+    fallbacks = 0
+    for k in range(0, 30, 2):
+        print(f"streaming lod S={S} frame {k}", flush=True)
+        _, out = r.frame([cams[k]])
+        ovm.frame([cams[k]])
+        compare_frame(r, ovm, out, 1, tag=f"streaming lod {k}")
+        assert out.stats.fallbacks == ovm.counts()["fallbacks"], k
+        fallbacks += out.stats.fallbacks
+    assert fallbacks > 0
     r.close()
