@@ -125,19 +125,21 @@ def host_cores():
         return os.cpu_count(), os.cpu_count()
 
 
-def cpu_baseline(make_vm, cams, workload, budget_s=12.0):
+def cpu_baseline(make_scene, make_vm, cams, workload, budget_s=12.0):
     """The oracle (plain C) on a bounded sample of the same path: after one
     warm frame, consecutive frames until about budget_s seconds, once on one
     thread and once on every core this process may use (OpenMP over the
-    independent per-Gaussian and per-tile loops of its splat).  make_vm()
-    returns (oracle VM, create-time seconds)."""
+    independent per-Gaussian and per-tile loops of its splat).  make_scene()
+    builds the oracle's create-time data once, make_vm(scene) a fresh VM."""
     import oracle
     n_cores, n_os = host_cores()
     legs = {}
-    build_s = 0.0
+    t0 = time.time()
+    osc = make_scene()
+    build_s = time.time() - t0
     for threads in (1, n_cores):
         oracle.set_threads(threads)
-        vm, build_s = make_vm()
+        vm = make_vm(osc)
         vm.frame([cams[0]])
         times = []
         k = 1
@@ -333,16 +335,15 @@ def run_city_lod(args, pkg, synth):
         import oracle
         log("cpu baseline (oracle) ...")
 
-        def make_vm():
-            t0 = time.time()
-            osc = oracle.OracleScene(sc, 1024, 3, 2.0, 2.0, attr_format=cfg["fmt"], lod_scale_up=args.lod_scale_up)
+        def make_vm(osc):
             vm = oracle.OracleVM(osc, S, (W, H), cfg["idbuf"], lod_radius_px=args.tau0,
                                  copy_budget=STAGING_PAGES if args.stream else 0)
             vm.set_adaptive_lod(True)
             vm.set_async(args.stream)
-            vm._osc = osc
-            return vm, time.time() - t0
-        res["cpu_baseline"] = cpu_baseline(make_vm, cams[Wm:], args.workload)
+            return vm
+        res["cpu_baseline"] = cpu_baseline(
+            lambda: oracle.OracleScene(sc, 1024, 3, 2.0, 2.0, attr_format=cfg["fmt"], lod_scale_up=args.lod_scale_up),
+            make_vm, cams[Wm:], args.workload)
     return res
 
 
@@ -717,13 +718,10 @@ def run_terrain(args, pkg, synth):
         import oracle
         log("cpu baseline (oracle) ...")
 
-        def make_vm():
-            t0 = time.time()
-            osc = oracle.OracleScene(sc, P, 1, TERRAIN_CELL_M, 2.0)
-            vm = oracle.OracleVM(osc, S, (1920, 1080), (240, 135), use_links=not args.no_links)
-            vm._osc = osc
-            return vm, time.time() - t0
-        res["cpu_baseline"] = cpu_baseline(make_vm, cams, "terrain6m")
+        res["cpu_baseline"] = cpu_baseline(
+            lambda: oracle.OracleScene(sc, P, 1, TERRAIN_CELL_M, 2.0),
+            lambda osc: oracle.OracleVM(osc, S, (1920, 1080), (240, 135), use_links=not args.no_links),
+            cams, "terrain6m")
     return res
 
 
