@@ -14,7 +14,7 @@
 //                of their pair counts, so that the longest tiles start first
 //                and the short ones fill in behind them.
 //  k_blend       one 256-thread workgroup per 16x16 tile, one pixel per
-//                thread, one 16 x 4 strip per wave; each wave walks the
+//                thread, one 4 x 16 strip per wave; each wave walks the
 //                tile's pairs on its own (registers, no LDS, no barriers);
 //                per pixel front-to-back blending until transmittance would
 //                fall below 1e-4; the wave stops when all its pixels are done.
@@ -323,9 +323,9 @@ __global__ void k_ranges(const uint32_t* __restrict__ key, uint32_t cap, const u
     if (i == n - 1 || key[i + 1] != t) ranges[t].y = i + 1;
 }
 
-// One 256-thread workgroup per 16x16 tile, one pixel per thread, one 16 x 4
-// strip per wave.  The four waves of a tile work independently (no LDS, no
-// barriers), so a wave whose strip holds most of the tile's work (a horizon
+// One 256-thread workgroup per 16x16 tile, one pixel per thread, one 4 x 16
+// strip (4 columns, 16 rows) per wave.  The four waves of a tile work
+// independently (no LDS, no barriers), so a wave whose strip holds most of the tile's work (a horizon
 // band, say) is not held back at every batch by the others: each wave walks
 // the tile's depth-ordered pairs in chunks of 64, one pair per lane, with the
 // gathers of the next chunk in flight while it blends the current one.
@@ -354,18 +354,25 @@ __device__ __forceinline__ float lane_f(float x, int i) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), i));
 }
 
-// pixels of a 16 x 4 strip (bit = row * 16 + column) whose centre lies in
-// the box |px - u| <= hx, |py - v| <= hy; (sx, sy) is the strip's first
-// pixel.  The support half-widths carry a pixel of margin, more than the
-// rounding of these differences.
+// A wave's strip: BL_SW columns by BL_SH rows of the tile (BL_SW * BL_SH =
+// 64), lane = row * BL_SW + column.  Strips side by side: a horizontal band
+// (a horizon, ground seen at a grazing angle) spreads over all four waves.
+constexpr int BL_SW = 4, BL_SH = WAVE / BL_SW;
+static_assert(BL_SW == 4 && BL_SH == 16, "strip_box_mask replicates a 4-bit column mask over 16 rows");
+
+// pixels of a strip (bit = lane) whose centre lies in the box
+// |px - u| <= hx, |py - v| <= hy; (sx, sy) is the strip's first pixel.  The
+// support half-widths carry a pixel of margin, more than the rounding of
+// these differences.
 __device__ __forceinline__ uint64_t strip_box_mask(float u, float v, float hx, float hy, float sx, float sy) {
-    const float c0 = fmaxf(ceilf((u - hx) - sx), 0.0f), c1 = fminf(floorf((u + hx) - sx), 15.0f);
-    const float r0 = fmaxf(ceilf((v - hy) - sy), 0.0f), r1 = fminf(floorf((v + hy) - sy), 3.0f);
+    const float c0 = fmaxf(ceilf((u - hx) - sx), 0.0f), c1 = fminf(floorf((u + hx) - sx), (float)(BL_SW - 1));
+    const float r0 = fmaxf(ceilf((v - hy) - sy), 0.0f), r1 = fminf(floorf((v + hy) - sy), (float)(BL_SH - 1));
     if (!(c0 <= c1) || !(r0 <= r1)) return 0ull;
     const int ic0 = (int)c0, ic1 = (int)c1, ir0 = (int)r0, ir1 = (int)r1;
     const uint64_t cols = (uint64_t)(((2u << ic1) - 1u) & ~((1u << ic0) - 1u));
     // one bit per row in [ir0, ir1] at the row's first column
-    const uint64_t rows = (0x0001000100010001ull >> (16 * (3 - ir1))) & (~0ull << (16 * ir0));
+    constexpr uint64_t first_cols = 0x1111111111111111ull;   // bit row * BL_SW, every row
+    const uint64_t rows = (first_cols >> (BL_SW * (BL_SH - 1 - ir1))) & (~0ull << (BL_SW * ir0));
     return rows * cols;
 }
 
@@ -381,15 +388,16 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
     const uint32_t view = tile / per_view;
     const uint32_t t = tile - view * per_view;
     const int tx = (int)(t % (uint32_t)TX), ty = (int)(t / (uint32_t)TX);
-    const int px = tx * TILE + (int)(threadIdx.x % TILE);
-    const int py = ty * TILE + (int)(threadIdx.x / TILE);
+    const int wave = (int)(threadIdx.x / WAVE);
+    const int px = tx * TILE + wave * BL_SW + (int)(threadIdx.x % WAVE) % BL_SW;
+    const int py = ty * TILE + (int)(threadIdx.x % WAVE) / BL_SW;
     const bool inside = px < W && py < H;
     const uint2 rg = ranges[tile];
     const float fpx = (float)px, fpy = (float)py;
     const int lane = (int)__lane_id();
     // first pixel of this wave's strip, in scalar registers
-    const float strip_x = uniform_f((float)(tx * TILE));
-    const float strip_y = uniform_f((float)(ty * TILE + (int)(threadIdx.x / WAVE) * (WAVE / TILE)));
+    const float strip_x = uniform_f((float)(tx * TILE + wave * BL_SW));
+    const float strip_y = uniform_f((float)(ty * TILE));
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     uint32_t n_visit = inside ? rg.y - rg.x : 0u, n_alpha = 0;   // list entries the pixel's loop visits
     bool live = inside;   // this pixel still blends
