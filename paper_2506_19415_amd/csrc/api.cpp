@@ -691,7 +691,7 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         dalloc(&c->d_rect, R); dalloc(&c->d_tiles, R); dalloc(&c->d_offs, R + 1);
         for (int i = 0; i < 2; ++i) { dalloc(&c->d_dkey[i], R); dalloc(&c->d_dval[i], R); }
         dalloc(&c->d_ranges, (size_t)c->TX * c->TY * V);
-        dalloc(&c->d_tile_order, (size_t)c->TX * c->TY * V);
+        dalloc(&c->d_tile_order, (size_t)c->TX * c->TY * V + 1);   // + the count of long tiles
         dalloc(&c->d_bstats, (size_t)c->TX * c->TY * V); halloc(&c->h_bstats, (size_t)c->TX * c->TY * V);
         dalloc(&c->d_total, 4); halloc(&c->h_total, 8);  // [0] pairs, [1] look-back error, [2..3] bytes, [4] copy error
         c->hd_total = host_dev(c->h_total); c->hd_ctr = host_dev(c->h_ctr); c->hd_keys = host_dev(c->h_keys);

@@ -14,10 +14,12 @@
 //                of their pair counts, so that the longest tiles start first
 //                and the short ones fill in behind them.
 //  k_blend       one 256-thread workgroup per 16x16 tile, one pixel per
-//                thread, one 4 x 16 strip per wave; each wave walks the
-//                tile's pairs on its own (registers, no LDS, no barriers);
-//                per pixel front-to-back blending until transmittance would
-//                fall below 1e-4; the wave stops when all its pixels are done.
+//                thread, one 4 x 16 strip per wave (a long tile: four
+//                workgroups, one 1 x 16 column per wave); each wave walks
+//                the tile's pairs on its own (registers, no LDS, no
+//                barriers); per pixel front-to-back blending until
+//                transmittance would fall below 1e-4; the wave stops when
+//                all its pixels are done.
 #include "kcommon.h"
 #include "vm3dgs_impl.h"
 
@@ -288,6 +290,10 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
 
 constexpr int TO_NT = 1024;
 
+// classes at or above this one hold the long tiles (1024 pairs or more)
+constexpr int BL_LONG_CLASS = 11;
+
+// order[n_tiles] receives the number of long tiles (a prefix of the order)
 __global__ __launch_bounds__(TO_NT) void k_tile_order(const uint2* __restrict__ ranges, uint32_t n_tiles,
                                                       uint32_t* __restrict__ order) {
     __shared__ uint32_t cnt[33];
@@ -304,6 +310,7 @@ __global__ __launch_bounds__(TO_NT) void k_tile_order(const uint2* __restrict__ 
             const uint32_t k = cnt[c];
             cnt[c] = acc;
             acc += k;
+            if (c == BL_LONG_CLASS) order[n_tiles] = acc;
         }
     }
     __syncthreads();
@@ -325,8 +332,12 @@ __global__ void k_ranges(const uint32_t* __restrict__ key, uint32_t cap, const u
 
 // One 256-thread workgroup per 16x16 tile, one pixel per thread, one 4 x 16
 // strip (4 columns, 16 rows) per wave.  The four waves of a tile work
-// independently (no LDS, no barriers), so a wave whose strip holds most of the tile's work (a horizon
-// band, say) is not held back at every batch by the others: each wave walks
+// independently (no LDS, no barriers), so a wave whose strip holds most of
+// the tile's work (a horizon band, say) is not held back at every batch by
+// the others.  A long tile (1024 pairs or more, the first ones of the blend
+// order) goes to four workgroups of four waves, one pixel column per wave
+// (lanes 0..15 the column's rows): sixteen waves on its pairs instead of
+// four, the long tiles no longer the tail of the launch.  Each wave walks
 // the tile's depth-ordered pairs in chunks of 64, one pair per lane, with the
 // gathers of the next chunk in flight while it blends the current one.
 // Each lane first tests its Gaussian's support box (outside it no term passes
@@ -354,49 +365,79 @@ __device__ __forceinline__ float lane_f(float x, int i) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), i));
 }
 
-// A wave's strip: BL_SW columns by BL_SH rows of the tile (BL_SW * BL_SH =
-// 64), lane = row * BL_SW + column.  Strips side by side: a horizontal band
-// (a horizon, ground seen at a grazing angle) spreads over all four waves.
-constexpr int BL_SW = 4, BL_SH = WAVE / BL_SW;
-static_assert(BL_SW == 4 && BL_SH == 16, "strip_box_mask replicates a 4-bit column mask over 16 rows");
+// Long tiles given four workgroups each, at most (the others of a larger
+// count keep one).  The launch carries BL_LONG_CAP * 4 workgroups for them;
+// those without a long tile exit at once.
+constexpr uint32_t BL_LONG_CAP = 1024;
+static_assert(BL_LONG_CAP % 8 == 0, "long workgroups come in groups of 32, four per XCD slot");
 
-// pixels of a strip (bit = lane) whose centre lies in the box
-// |px - u| <= hx, |py - v| <= hy; (sx, sy) is the strip's first pixel.  The
-// support half-widths carry a pixel of margin, more than the rounding of
-// these differences.
+// A wave's strip: SW columns by 16 rows of the tile, lane = row * SW +
+// column (SW = 1: lanes 16..63 idle).  Pixels of the strip (bit = lane)
+// whose centre lies in the box |px - u| <= hx, |py - v| <= hy; (sx, sy) is
+// the strip's first pixel.  The support half-widths carry a pixel of margin,
+// more than the rounding of these differences.
+template <int SW>
 __device__ __forceinline__ uint64_t strip_box_mask(float u, float v, float hx, float hy, float sx, float sy) {
-    const float c0 = fmaxf(ceilf((u - hx) - sx), 0.0f), c1 = fminf(floorf((u + hx) - sx), (float)(BL_SW - 1));
-    const float r0 = fmaxf(ceilf((v - hy) - sy), 0.0f), r1 = fminf(floorf((v + hy) - sy), (float)(BL_SH - 1));
+    static_assert(SW == 1 || SW == 4, "strips of 1 or 4 columns");
+    const float c0 = fmaxf(ceilf((u - hx) - sx), 0.0f), c1 = fminf(floorf((u + hx) - sx), (float)(SW - 1));
+    const float r0 = fmaxf(ceilf((v - hy) - sy), 0.0f), r1 = fminf(floorf((v + hy) - sy), 15.0f);
     if (!(c0 <= c1) || !(r0 <= r1)) return 0ull;
     const int ic0 = (int)c0, ic1 = (int)c1, ir0 = (int)r0, ir1 = (int)r1;
     const uint64_t cols = (uint64_t)(((2u << ic1) - 1u) & ~((1u << ic0) - 1u));
     // one bit per row in [ir0, ir1] at the row's first column
-    constexpr uint64_t first_cols = 0x1111111111111111ull;   // bit row * BL_SW, every row
-    const uint64_t rows = (first_cols >> (BL_SW * (BL_SH - 1 - ir1))) & (~0ull << (BL_SW * ir0));
+    constexpr uint64_t first_cols = SW == 4 ? 0x1111111111111111ull : 0xffffull;   // bit row * SW, rows 0..15
+    const uint64_t rows = (first_cols >> (SW * (15 - ir1))) & (~0ull << (SW * ir0));
     return rows * cols;
+}
+
+// Number of workgroups k_blend is launched with for n_tiles tiles.
+__host__ __device__ inline uint32_t blend_long_slots(uint32_t n_tiles) {
+    return ((n_tiles < BL_LONG_CAP ? n_tiles : BL_LONG_CAP) + 7u) & ~7u;
 }
 
 template <bool STATS>
 __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ ranges, const uint32_t* __restrict__ order,
                                                  const uint32_t* __restrict__ pval, const float4* __restrict__ xy,
                                                  const float4* __restrict__ conic, const float4* __restrict__ rgb,
-                                                 int W, int H, int TX, int TY, float* __restrict__ image,
-                                                 uint2* __restrict__ stats) {
+                                                 int W, int H, int TX, int TY, int n_views,
+                                                 float* __restrict__ image, uint2* __restrict__ stats) {
     __shared__ uint32_t s_st[2][BL_NT / WAVE];
-    const uint32_t tile = order[blockIdx.x];
+    // Workgroups [0, 4 * slots) serve the long tiles, the rest the others in
+    // order.  Workgroup ids go round-robin over the eight XCDs, so a long
+    // tile's four workgroups are taken 8 ids apart (one XCD, one L2 for the
+    // tile's Gaussians).
+    const uint32_t n_tiles = (uint32_t)(TX * TY) * (uint32_t)n_views;
+    const uint32_t slots = blend_long_slots(n_tiles);
+    const uint32_t n_long = min(order[n_tiles], slots);
+    const uint32_t b = blockIdx.x;
+    uint32_t idx, group = 0;
+    bool long_tile = false;
+    if (b < 4 * slots) {
+        const uint32_t s = b >> 3;
+        idx = (s >> 2) * 8 + (b & 7);
+        group = s & 3;
+        if (idx >= n_long) return;
+        long_tile = true;
+    } else {
+        idx = b - 4 * slots + n_long;
+        if (idx >= n_tiles) return;
+    }
+    const uint32_t tile = order[idx];
     const uint32_t per_view = (uint32_t)(TX * TY);
     const uint32_t view = tile / per_view;
     const uint32_t t = tile - view * per_view;
     const int tx = (int)(t % (uint32_t)TX), ty = (int)(t / (uint32_t)TX);
     const int wave = (int)(threadIdx.x / WAVE);
-    const int px = tx * TILE + wave * BL_SW + (int)(threadIdx.x % WAVE) % BL_SW;
-    const int py = ty * TILE + (int)(threadIdx.x % WAVE) / BL_SW;
-    const bool inside = px < W && py < H;
+    const int lane = (int)__lane_id();
+    // short: a 4 x 16 strip per wave; long: column group * 4 + wave
+    const int sx = long_tile ? tx * TILE + (int)group * 4 + wave : tx * TILE + wave * 4;
+    const int px = long_tile ? sx : sx + lane % 4;
+    const int py = long_tile ? ty * TILE + lane : ty * TILE + lane / 4;
+    const bool inside = (!long_tile || lane < TILE) && px < W && py < H;
     const uint2 rg = ranges[tile];
     const float fpx = (float)px, fpy = (float)py;
-    const int lane = (int)__lane_id();
     // first pixel of this wave's strip, in scalar registers
-    const float strip_x = uniform_f((float)(tx * TILE + wave * BL_SW));
+    const float strip_x = uniform_f((float)sx);
     const float strip_y = uniform_f((float)(ty * TILE));
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     uint32_t n_visit = inside ? rg.y - rg.x : 0u, n_alpha = 0;   // list entries the pixel's loop visits
@@ -427,7 +468,9 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
         n_f = base + 2 * WAVE + lane < rg.y ? pval[base + 2 * WAVE + lane] : 0u;
         // the chunk's Gaussians whose support box meets a live pixel of the
         // strip (every pixel rejects the others)
-        const uint64_t box = valid ? strip_box_mask(gp.x, gp.y, gp.z, gp.w, strip_x, strip_y) : 0ull;
+        const uint64_t box = !valid ? 0ull
+                             : long_tile ? strip_box_mask<1>(gp.x, gp.y, gp.z, gp.w, strip_x, strip_y)
+                                         : strip_box_mask<4>(gp.x, gp.y, gp.z, gp.w, strip_x, strip_y);
         uint64_t mask = __builtin_amdgcn_ballot_w64((box & live_m) != 0ull);
         while (mask != 0 && wave_live) {
             int ii[4];
@@ -491,10 +534,11 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
         const uint32_t e = wave_sum(n_visit), al = wave_sum(n_alpha);
         if (lane == 0) { s_st[0][threadIdx.x / WAVE] = e; s_st[1][threadIdx.x / WAVE] = al; }
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == 0) {   // stats cleared before the launch: a long tile's four add up
             uint32_t se = 0, sa = 0;
             for (int i = 0; i < BL_NT / WAVE; ++i) { se += s_st[0][i]; sa += s_st[1][i]; }
-            stats[tile] = make_uint2(se, sa);
+            atomicAdd(&stats[tile].x, se);
+            atomicAdd(&stats[tile].y, sa);
         }
     }
 }
@@ -543,12 +587,16 @@ void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* order, co
                   const float4* conic, const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image,
                   uint2* stats) {
     const uint32_t n_tiles = (uint32_t)(TX * TY * n_views);
-    if (stats)
-        hipLaunchKernelGGL(k_blend<true>, dim3(n_tiles), dim3(BL_NT), 0, st, ranges, order, pval, xy, conic, rgb, W, H,
-                           TX, TY, image, stats);
-    else
-        hipLaunchKernelGGL(k_blend<false>, dim3(n_tiles), dim3(BL_NT), 0, st, ranges, order, pval, xy, conic, rgb, W,
-                           H, TX, TY, image, stats);
+    if (!n_tiles) return;
+    const uint32_t n_blocks = n_tiles + 4 * blend_long_slots(n_tiles);
+    if (stats) {
+        launch_fill_u32(st, (uint32_t*)stats, 2 * (uint64_t)n_tiles, 0u);
+        hipLaunchKernelGGL(k_blend<true>, dim3(n_blocks), dim3(BL_NT), 0, st, ranges, order, pval, xy, conic, rgb, W,
+                           H, TX, TY, n_views, image, stats);
+    } else {
+        hipLaunchKernelGGL(k_blend<false>, dim3(n_blocks), dim3(BL_NT), 0, st, ranges, order, pval, xy, conic, rgb, W,
+                           H, TX, TY, n_views, image, stats);
+    }
 }
 
 }  // namespace vm

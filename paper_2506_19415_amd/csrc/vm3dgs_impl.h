@@ -178,6 +178,7 @@ void launch_emit(hipStream_t st, const uint32_t* order, const uint32_t* offsets,
                  int TX, int TY, uint32_t* pkey, uint32_t* pval, uint32_t cap);
 void launch_ranges(hipStream_t st, const uint32_t* pkey, uint32_t cap, const uint32_t* n_pairs_dev, uint2* ranges,
                    uint32_t n_tiles);
+// order: n_tiles + 1 words (the blend order, then the number of long tiles)
 void launch_tile_order(hipStream_t st, const uint2* ranges, uint32_t n_tiles, uint32_t* order);
 void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* order, const uint32_t* pval, const float4* xy,
                   const float4* conic, const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image,
