@@ -196,7 +196,8 @@ _VM_DT = {"lod": np.float32, "pf_keys": np.uint64, "pf_x": np.float32, "pf_count
           "sub_last_used": np.int32, "v2p": np.int32, "copies": np.int64, "copy_id": np.int32,
           "missing": np.int32, "counts": np.int64, "render_list": np.int32, "pp_float": np.float32,
           "pp_int": np.int32, "n_pairs": np.int64, "keys": np.uint64, "vals": np.uint32,
-          "ranges": np.uint32, "image": np.float32, "final_T": np.float32, "contrib": np.int64}
+          "ranges": np.uint32, "image": np.float32, "final_T": np.float32, "contrib": np.int64,
+          "visits": np.int64}
 
 
 class OracleScene:

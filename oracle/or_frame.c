@@ -121,6 +121,7 @@ struct or_vm {
     float* image;          /* [views][H][W][3] */
     float* final_T;        /* [views][H][W] */
     int64_t* contrib;      /* [views][H][W] Gaussians blended per pixel */
+    int64_t* visits;       /* [views][H][W] list entries the pixel's loop visits (up to and including the stop) */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -754,10 +755,11 @@ static void splat(or_vm* vm, const or_camera* cams, int n_views, const uint8_t* 
         vm->ranges[2 * t + 1] = (uint32_t)cnt[t + 1];
     }
     /* blend */
-    free(vm->image); free(vm->final_T); free(vm->contrib);
+    free(vm->image); free(vm->final_T); free(vm->contrib); free(vm->visits);
     vm->image = calloc((size_t)n_views * W * H * 3, sizeof(float));
     vm->final_T = calloc((size_t)n_views * W * H, sizeof(float));
     vm->contrib = calloc((size_t)n_views * W * H, sizeof(int64_t));
+    vm->visits = calloc((size_t)n_views * W * H, sizeof(int64_t));
     #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t t = 0; t < nt; t++) {
             int v = (int)(t / ((int64_t)TX * TY));
@@ -767,7 +769,7 @@ static void splat(or_vm* vm, const or_camera* cams, int n_views, const uint8_t* 
             for (int py = ty * 16; py < ty * 16 + 16 && py < H; py++)
                 for (int px = tx * 16; px < tx * 16 + 16 && px < W; px++) {
                     float T = 1.0f, C[3] = {0.0f, 0.0f, 0.0f};
-                    int64_t nb = 0;
+                    int64_t nb = 0, nvis = cnt[t + 1] - cnt[t];
                     for (int64_t k = cnt[t]; k < cnt[t + 1]; k++) {
                         pp_t* o = &vm->pp[v * n_render + vm->vals[k]];
                         float dx = o->u - (float)px, dy = o->v - (float)py;
@@ -777,7 +779,7 @@ static void splat(or_vm* vm, const or_camera* cams, int n_views, const uint8_t* 
                         float alpha = fminf(0.99f, o->opacity * or_vm_exp(power));
                         if (alpha < 1.0f / 255.0f) continue;
                         float Tn = T * (1.0f - alpha);
-                        if (Tn < 0.0001f) break;
+                        if (Tn < 0.0001f) { nvis = k - cnt[t] + 1; break; }
                         float wgt = alpha * T;
                         for (int ch = 0; ch < 3; ch++) C[ch] = fmaf(o->rgb[ch], wgt, C[ch]);
                         T = Tn;
@@ -787,6 +789,7 @@ static void splat(or_vm* vm, const or_camera* cams, int n_views, const uint8_t* 
                     for (int ch = 0; ch < 3; ch++) vm->image[pix * 3 + ch] = C[ch];
                     vm->final_T[pix] = T;
                     vm->contrib[pix] = nb;
+                    vm->visits[pix] = nvis;
                 }
         }
     free(lists); free(cnt);
@@ -840,7 +843,7 @@ void or_vm_free(or_vm* vm)
     free(vm->rlevel);
     free(vm->copy); free(vm->copy_id); free(vm->missing); free(vm->rl);
     free(vm->pp); free(vm->keys); free(vm->vals); free(vm->ranges); free(vm->image); free(vm->final_T);
-    free(vm->contrib);
+    free(vm->contrib); free(vm->visits);
     free(vm->pf_keys); free(vm->pf_x);
     free(vm);
 }
@@ -1301,5 +1304,6 @@ int64_t or_vm_get(const or_vm* vm, const char* name, void* dst, int64_t cap)
     if (!strcmp(name, "image")) return put(dst, cap, vm->image, 12 * nv * vm->W * vm->H);
     if (!strcmp(name, "final_T")) return put(dst, cap, vm->final_T, 4 * nv * vm->W * vm->H);
     if (!strcmp(name, "contrib")) return put(dst, cap, vm->contrib, 8 * nv * vm->W * vm->H);
+    if (!strcmp(name, "visits")) return put(dst, cap, vm->visits, 8 * nv * vm->W * vm->H);
     return -1;
 }

@@ -313,3 +313,48 @@ def test_threads_do_not_change_results():
     oracle.set_threads(os.cpu_count() or 1)
     for a, b in zip(*res):
         assert np.array_equal(a, b)
+
+
+def test_visit_counts_hand_worked():
+    """Six Gaussians of opacity 0.95 on the optical axis (depths 2..7 m): at
+    the pixel under their centres every term has alpha 0.95, so the
+    transmittance goes 0.05, 0.0025, 1.25e-4 and the fourth term would take
+    it to 6.25e-6 < 1e-4: the loop stops there, having visited four list
+    entries and blended three.  A pixel of the same tile 15 px away is
+    outside every footprint: it visits the whole list and blends nothing.
+    The neighbour pixel (one column off) blends all six and never stops."""
+    W = H = 33
+    n = 6
+    sc = synth.Scene(np.array([[0.0, 0.0, 2.0 + k] for k in range(n)], np.float32),
+                     np.full((n, 3), 0.002, np.float32), np.tile(np.array([[1, 0, 0, 0]], np.float32), (n, 1)),
+                     np.full(n, 0.95, np.float32), np.zeros((n, 16, 3), np.float32))
+    vm = render(sc, identity_cam(W, H), W, H)
+    visits = vm.get("visits").reshape(H, W)
+    contrib = vm.get("contrib").reshape(H, W)
+    ranges = vm.get("ranges").reshape(-1, 2)
+    TX = vm.TX
+    t = 1 * TX + 1                      # tile of pixel (16, 16)
+    assert ranges[t, 1] - ranges[t, 0] == n
+    assert (visits[16, 16], contrib[16, 16]) == (4, 3)
+    assert abs(float(vm.get("final_T").reshape(H, W)[16, 16]) - 0.05 ** 3) < 1e-9
+    assert (visits[31, 31], contrib[31, 31]) == (n, 0)
+    assert (visits[16, 17], contrib[16, 17]) == (n, n)
+
+
+def test_visit_counts_invariants(cluster_frame):
+    """Per pixel: blended <= visited <= the tile's list length; a pixel that
+    visited fewer entries than its list holds stopped at the last one it
+    visited, which it did not blend, and with alpha <= 0.99 a stop needs a
+    transmittance below 1e-4 / 0.01."""
+    vm = cluster_frame
+    TX = vm.TX
+    W, H = vm.W, vm.H
+    visits = vm.get("visits").reshape(H, W)
+    contrib = vm.get("contrib").reshape(H, W)
+    ranges = vm.get("ranges").reshape(-1, 2).astype(np.int64)
+    n_list = (ranges[:, 1] - ranges[:, 0])[(np.arange(H)[:, None] // 16) * TX + np.arange(W)[None, :] // 16]
+    assert np.all(contrib <= visits) and np.all(visits <= n_list)
+    stopped = visits < n_list
+    assert np.all(contrib[stopped] + 1 <= visits[stopped])
+    assert np.all(vm.get("final_T").reshape(H, W)[stopped] < 0.01)
+    assert stopped.any() and (~stopped).any()
