@@ -582,8 +582,10 @@ static void prefetch_stage(or_vm* vm, uint8_t* req_sub, uint8_t* slot_req)
  * |dx| <= sqrt(11.1 Sigma'_xx) (and the same for rows).  The float
  * evaluation of the power errs by less than 5e-7 kap Q with
  * kap = (a + c)^2 / det >= cond(Sigma') + 2, so the threshold is divided by
- * (1 - 5e-7 kap), and one pixel is added; a footprint with 5e-7 kap >= 1/2
- * keeps its rectangle.  Tiles outside the box hold no accepted pixel of the
+ * (1 - 5e-7 kap).  The box edges u -+ h and the pixel and tile offsets taken
+ * from them are float values, each rounding off by at most 2^-24 (|u| + h):
+ * 1/64 pixel plus 1e-6 (|u| + h) is added to cover them.  A footprint with
+ * 5e-7 kap >= 1/2 keeps its rectangle.  Tiles outside the box hold no accepted pixel of the
  * Gaussian, so cutting the rectangle to it leaves the image unchanged (pinned
  * by image identity and a float64 brute force of the accepted region); it
  * only predicts which pairs a renderer that makes this cut emits. */
@@ -594,8 +596,9 @@ static void support_box_cut(float a, float cc, float det, float u, float v, int 
     float e = 5e-7f * kap;
     if (!(e < 0.5f)) return;
     float f = 1.0f / (1.0f - e);
-    float hx = sqrtf((11.11f * f) * a) + 1.0f;
-    float hy = sqrtf((11.11f * f) * cc) + 1.0f;
+    float rx = sqrtf((11.11f * f) * a), ry = sqrtf((11.11f * f) * cc);
+    float hx = rx + (0.015625f + 1e-6f * (fabsf(u) + rx));
+    float hy = ry + (0.015625f + 1e-6f * (fabsf(v) + ry));
     float bx0 = fminf(fmaxf(floorf((u - hx) / 16.0f), 0.0f), (float)TX);
     float bx1 = fminf(fmaxf(floorf((u + hx) / 16.0f) + 1.0f, 0.0f), (float)TX);
     float by0 = fminf(fmaxf(floorf((v - hy) / 16.0f), 0.0f), (float)TY);

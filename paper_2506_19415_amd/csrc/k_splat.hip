@@ -160,8 +160,11 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
                 const float e = 5e-7f * kap;
                 if (e < 0.5f) {
                     const float fm = 1.0f / (1.0f - e);
-                    hx = sqrtf((11.11f * fm) * A) + 1.0f;
-                    hy = sqrtf((11.11f * fm) * Cc) + 1.0f;
+                    // plus a margin over the float rounding of the box
+                    // edges and of the offsets taken from them
+                    const float rx = sqrtf((11.11f * fm) * A), ry = sqrtf((11.11f * fm) * Cc);
+                    hx = rx + (0.015625f + 1e-6f * (fabsf(u) + rx));
+                    hy = ry + (0.015625f + 1e-6f * (fabsf(vv) + ry));
                     const float bx0 = fminf(fmaxf(floorf((u - hx) / 16.0f), 0.0f), (float)a.TX);
                     const float bx1 = fminf(fmaxf(floorf((u + hx) / 16.0f) + 1.0f, 0.0f), (float)a.TX);
                     const float by0 = fminf(fmaxf(floorf((vv - hy) / 16.0f), 0.0f), (float)a.TY);
