@@ -13,13 +13,14 @@
 //  k_tile_order  blend order of the tiles: by decreasing power-of-two class
 //                of their pair counts, so that the longest tiles start first
 //                and the short ones fill in behind them.
-//  k_blend       one 256-thread workgroup per 16x16 tile, one pixel per
-//                thread, one 4 x 16 strip per wave (a long tile: four
-//                workgroups, one 1 x 16 column per wave); each wave walks
-//                the tile's pairs on its own (registers, no LDS, no
-//                barriers); per pixel front-to-back blending until
-//                transmittance would fall below 1e-4; the wave stops when
-//                all its pixels are done.
+//  k_blend       per pixel front-to-back blending until the transmittance
+//                would fall below 1e-4.  Short tiles: one 256-thread
+//                workgroup, a 4 x 16 strip per wave, each wave walking the
+//                pairs on its own (registers, no barriers).  Long tiles:
+//                four workgroups (16 x 4 bands), chunks of 256 pairs,
+//                Gaussian-parallel selection of the terms that pass the
+//                alpha test into per-pixel bit masks (LDS), then
+//                pixel-parallel compositing of the selected terms in order.
 #include "kcommon.h"
 #include "vm3dgs_impl.h"
 
@@ -293,10 +294,10 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
 
 constexpr int TO_NT = 1024;
 
-// classes at or above this one hold the long tiles (1024 pairs or more)
+// The blend's long tiles: tile-order classes from this one up (counts of
+// 2^10 or more).  order[n_tiles] receives their number (a prefix of the
+// order).
 constexpr int BL_LONG_CLASS = 11;
-
-// order[n_tiles] receives the number of long tiles (a prefix of the order)
 __global__ __launch_bounds__(TO_NT) void k_tile_order(const uint2* __restrict__ ranges, uint32_t n_tiles,
                                                       uint32_t* __restrict__ order) {
     __shared__ uint32_t cnt[33];
@@ -333,31 +334,58 @@ __global__ void k_ranges(const uint32_t* __restrict__ key, uint32_t cap, const u
     if (i == n - 1 || key[i + 1] != t) ranges[t].y = i + 1;
 }
 
-// One 256-thread workgroup per 16x16 tile, one pixel per thread, one 4 x 16
-// strip (4 columns, 16 rows) per wave.  The four waves of a tile work
-// independently (no LDS, no barriers), so a wave whose strip holds most of
-// the tile's work (a horizon band, say) is not held back at every batch by
-// the others.  A long tile (1024 pairs or more, the first ones of the blend
-// order) goes to four workgroups of four waves, one pixel column per wave
-// (lanes 0..15 the column's rows): sixteen waves on its pairs instead of
-// four, the long tiles no longer the tail of the launch.  Each wave walks
-// the tile's depth-ordered pairs in chunks of 64, one pair per lane, with the
-// gathers of the next chunk in flight while it blends the current one.
-// Each lane first tests its Gaussian's support box (outside it no term passes
-// the alpha test) against the strip's pixels that still blend: the box's
-// columns and rows give a 64-bit mask of the strip's pixels (bit = lane), and
-// the lanes whose mask meets the wave's live mask form the chunk's work list.
-// A Gaussian that only covers pixels already stopped (an opaque band under a
-// sky that never stops, say) is so skipped by one test per 64 Gaussians.  The
-// wave takes the listed Gaussians in order, four at a time, and broadcasts
-// each from its lane through scalar registers (v_readlane).  The exponents of
-// four Gaussians are evaluated together, then the four are blended in order
-// (the pixel state after one decides whether the next one is taken); the
-// lanes evaluate with the pixel's "live" flag as a predicate, and the wave
-// stops when no lane is live.  STATS counts, per tile, the algorithmic work:
-// per pixel the list entries the front-to-back loop visits (up to and
-// including the one at which it stops), and the alpha evaluations.
+// k_blend: 256-thread workgroups, depth-ordered pairs in chunks, per pixel
+// front-to-back blending until the transmittance would fall below 1e-4.
+// Two ways of walking a tile's pairs, chosen per tile:
+//
+// Strip walk (tiles of fewer than BL_LONG pairs; one workgroup, one pixel
+// per thread).  A 4 x 16 strip (4 columns, 16 rows) per wave, and the four
+// waves of the tile work independently (registers only, no barriers), so a
+// wave whose strip holds most of the work (a horizon band, say) is not held
+// back by the others.  Each wave reads the pairs in chunks of 64, one per
+// lane, with the gathers of the next chunk in flight; each lane tests its
+// Gaussian's support box (outside it no term passes the alpha test) against
+// the strip's pixels that still blend, and the lanes whose box meets one
+// form the chunk's work list.  The wave takes the listed Gaussians in
+// order, four at a time, broadcasting each from its lane through scalar
+// registers (v_readlane): the exponents of the four are evaluated together,
+// then the four are blended in order, every lane with its pixel's "live"
+// flag as a predicate.  The wave stops when no lane is live.
+//
+// Band walk (tiles of BL_LONG pairs or more: the far end of a street, a
+// horizon, where thousands of Gaussians of a few pixels each meet in one
+// tile).  Broadcasting those to a strip of pixels wastes most lanes (each
+// covers a handful), so the tile goes to four workgroups, one 16 x 4 band
+// each (on one XCD, so the tile's Gaussians are read through one L2), and a
+// workgroup takes the pairs in chunks of 256, one per thread, in two phases:
+//  1. selection, Gaussian-parallel: each thread evaluates its Gaussian over
+//     the live pixels of its support box within the band (boxes of more
+//     than BL_SEL_BOX pixels are evaluated by their whole wave, one pixel
+//     per lane), and where a term passes the alpha test sets the Gaussian's
+//     bit in the pixel's 256-bit mask in LDS;
+//  2. compositing, pixel-parallel (wave w: row w of the band, lanes 0..15):
+//     each pixel walks its mask bits in depth order, evaluating those terms
+//     again (the same float operations on the same values, hence the same
+//     decisions) and blending them; the chunk's Gaussians are read from LDS.
+// Both walks evaluate a term with the same float operations, so either
+// yields the same image.
+//
+// STATS counts, per tile, the algorithmic work: per pixel the list entries
+// the front-to-back loop visits (up to and including the one at which it
+// stops), and the alpha evaluations (terms in the power range at pixels
+// still blending; the band walk counts those live when the chunk starts).
 constexpr int BL_NT = TILE * TILE;
+constexpr uint32_t BL_LONG = 1024;   // tiles with this many pairs take the band walk
+constexpr int BL_BANDS = 4;          // workgroups (16 x 4 bands) per long tile
+constexpr int BL_BAND_PX = TILE * TILE / BL_BANDS;
+constexpr int BL_CH = BL_NT;         // pairs per band-walk chunk, one per thread
+constexpr int BL_WORDS = BL_CH / 32;
+constexpr int BL_SEL_BOX = 16;       // larger boxes are evaluated by the whole wave
+// Long tiles given a band walk, at most (the others of a larger count take
+// the strip walk).  The launch carries room for this many.
+constexpr uint32_t BL_LONG_CAP = 2048;
+static_assert(BL_LONG == (1u << (BL_LONG_CLASS - 1)), "the long tiles are whole tile-order classes");
+static_assert(BL_BANDS == 4 && BL_BAND_PX == WAVE && BL_NT / WAVE == BL_BANDS, "band layout: one band row per wave");
 
 __device__ __forceinline__ float uniform_f(float x) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
@@ -367,89 +395,92 @@ __device__ __forceinline__ float uniform_f(float x) {
 __device__ __forceinline__ float lane_f(float x, int i) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), i));
 }
+__device__ __forceinline__ int lane_i(int x, int i) { return __builtin_amdgcn_readlane(x, i); }
 
-// Long tiles given four workgroups each, at most (the others of a larger
-// count keep one).  The launch carries BL_LONG_CAP * 4 workgroups for them;
-// those without a long tile exit at once.
-constexpr uint32_t BL_LONG_CAP = 1024;
-static_assert(BL_LONG_CAP % 8 == 0, "long workgroups come in groups of 32, four per XCD slot");
+// The exponent of a Gaussian at a pixel (its centre (u, v), conic
+// (ca, cb, cc)), as every walk evaluates it; a term can pass the alpha test
+// only for power in [-5.55, 0] (exp(-5.55) < 1/255, opacity <= 1).
+__device__ __forceinline__ float blend_power(float u, float v, float ca, float cb, float cc, float fpx, float fpy) {
+    const float dx = u - fpx, dy = v - fpy;
+    const float q = fmaf(ca * dx, dx, (cc * dy) * dy);
+    return fmaf(-0.5f, q, -((cb * dx) * dy));
+}
+__device__ __forceinline__ bool power_in_range(float power) { return power <= 0.0f && power >= -5.55f; }
+__device__ __forceinline__ float blend_alpha(float power, float op) {
+    return fminf(0.99f, op * vm_exp_core(__builtin_amdgcn_fmed3f(power, -6.0f, 0.0f)));
+}
 
-// A wave's strip: SW columns by 16 rows of the tile, lane = row * SW +
-// column (SW = 1: lanes 16..63 idle).  Pixels of the strip (bit = lane)
-// whose centre lies in the box |px - u| <= hx, |py - v| <= hy; (sx, sy) is
-// the strip's first pixel.  The support half-widths carry a pixel of margin,
-// more than the rounding of these differences.
-template <int SW>
+// Pixels of a 4 x 16 strip (bit = lane = row * 4 + column) whose centre lies
+// in the box |px - u| <= hx, |py - v| <= hy; (sx, sy) is the strip's first
+// pixel.  The support half-widths carry a margin above the rounding of
+// these differences.
 __device__ __forceinline__ uint64_t strip_box_mask(float u, float v, float hx, float hy, float sx, float sy) {
-    static_assert(SW == 1 || SW == 4, "strips of 1 or 4 columns");
-    const float c0 = fmaxf(ceilf((u - hx) - sx), 0.0f), c1 = fminf(floorf((u + hx) - sx), (float)(SW - 1));
+    const float c0 = fmaxf(ceilf((u - hx) - sx), 0.0f), c1 = fminf(floorf((u + hx) - sx), 3.0f);
     const float r0 = fmaxf(ceilf((v - hy) - sy), 0.0f), r1 = fminf(floorf((v + hy) - sy), 15.0f);
     if (!(c0 <= c1) || !(r0 <= r1)) return 0ull;
     const int ic0 = (int)c0, ic1 = (int)c1, ir0 = (int)r0, ir1 = (int)r1;
     const uint64_t cols = (uint64_t)(((2u << ic1) - 1u) & ~((1u << ic0) - 1u));
     // one bit per row in [ir0, ir1] at the row's first column
-    constexpr uint64_t first_cols = SW == 4 ? 0x1111111111111111ull : 0xffffull;   // bit row * SW, rows 0..15
-    const uint64_t rows = (first_cols >> (SW * (15 - ir1))) & (~0ull << (SW * ir0));
+    constexpr uint64_t first_cols = 0x1111111111111111ull;   // bit row * 4, rows 0..15
+    const uint64_t rows = (first_cols >> (4 * (15 - ir1))) & (~0ull << (4 * ir0));
     return rows * cols;
 }
 
-// Number of workgroups k_blend is launched with for n_tiles tiles.
-__host__ __device__ inline uint32_t blend_long_slots(uint32_t n_tiles) {
-    return ((n_tiles < BL_LONG_CAP ? n_tiles : BL_LONG_CAP) + 7u) & ~7u;
+// LDS of the band walk: the chunk's Gaussians (centre and support
+// half-widths; conic and opacity; colour), the per-pixel masks of the
+// chunk's selected Gaussians, word-major (consecutive pixels read
+// consecutive words: no bank conflicts), and the band's live pixels, 16 bits
+// per row.
+struct BlendLds {
+    float4 g[3][BL_CH];
+    uint32_t mask[BL_WORDS][BL_BAND_PX];
+    uint32_t live[BL_BANDS];
+    uint32_t st[2][BL_NT / WAVE];
+};
+
+// per-pixel blend state
+struct PixelBlend {
+    float T, C0, C1, C2;
+    bool live;
+    uint32_t n_visit;
+};
+
+// one term of a pixel's front-to-back loop; returns whether the pixel stops
+__device__ __forceinline__ bool blend_term(PixelBlend& px, float alpha, bool in, float r, float g, float b) {
+    const bool take = in && alpha >= 1.0f / 255.0f;
+    const float Tn = px.T * (1.0f - alpha);
+    const bool stop = take && Tn < 0.0001f;
+    const bool add = take && !stop;
+    const float wgt = alpha * px.T;
+    const float n0 = fmaf(r, wgt, px.C0), n1 = fmaf(g, wgt, px.C1), n2 = fmaf(b, wgt, px.C2);
+    px.C0 = add ? n0 : px.C0;
+    px.C1 = add ? n1 : px.C1;
+    px.C2 = add ? n2 : px.C2;
+    px.T = add ? Tn : px.T;
+    return stop;
 }
 
 template <bool STATS>
-__global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ ranges, const uint32_t* __restrict__ order,
-                                                 const uint32_t* __restrict__ pval, const float4* __restrict__ xy,
-                                                 const float4* __restrict__ conic, const float4* __restrict__ rgb,
-                                                 int W, int H, int TX, int TY, int n_views,
-                                                 float* __restrict__ image, uint2* __restrict__ stats) {
-    __shared__ uint32_t s_st[2][BL_NT / WAVE];
-    // Workgroups [0, 4 * slots) serve the long tiles, the rest the others in
-    // order.  Workgroup ids go round-robin over the eight XCDs, so a long
-    // tile's four workgroups are taken 8 ids apart (one XCD, one L2 for the
-    // tile's Gaussians).
-    const uint32_t n_tiles = (uint32_t)(TX * TY) * (uint32_t)n_views;
-    const uint32_t slots = blend_long_slots(n_tiles);
-    const uint32_t n_long = min(order[n_tiles], slots);
-    const uint32_t b = blockIdx.x;
-    uint32_t idx, group = 0;
-    bool long_tile = false;
-    if (b < 4 * slots) {
-        const uint32_t s = b >> 3;
-        idx = (s >> 2) * 8 + (b & 7);
-        group = s & 3;
-        if (idx >= n_long) return;
-        long_tile = true;
-    } else {
-        idx = b - 4 * slots + n_long;
-        if (idx >= n_tiles) return;
-    }
-    const uint32_t tile = order[idx];
-    const uint32_t per_view = (uint32_t)(TX * TY);
-    const uint32_t view = tile / per_view;
-    const uint32_t t = tile - view * per_view;
-    const int tx = (int)(t % (uint32_t)TX), ty = (int)(t / (uint32_t)TX);
+__device__ __forceinline__ void strip_walk(uint2 rg, const uint32_t* __restrict__ pval, const float4* __restrict__ xy,
+                                           const float4* __restrict__ conic, const float4* __restrict__ rgb, int tx,
+                                           int ty, int W, int H, PixelBlend& pb, uint32_t& n_alpha, int& px_out,
+                                           int& py_out) {
     const int wave = (int)(threadIdx.x / WAVE);
     const int lane = (int)__lane_id();
-    // short: a 4 x 16 strip per wave; long: column group * 4 + wave
-    const int sx = long_tile ? tx * TILE + (int)group * 4 + wave : tx * TILE + wave * 4;
-    const int px = long_tile ? sx : sx + lane % 4;
-    const int py = long_tile ? ty * TILE + lane : ty * TILE + lane / 4;
-    const bool inside = (!long_tile || lane < TILE) && px < W && py < H;
-    const uint2 rg = ranges[tile];
+    const int px = tx * TILE + wave * 4 + lane % 4;
+    const int py = ty * TILE + lane / 4;
+    px_out = px; py_out = py;
+    const bool inside = px < W && py < H;
     const float fpx = (float)px, fpy = (float)py;
     // first pixel of this wave's strip, in scalar registers
-    const float strip_x = uniform_f((float)sx);
+    const float strip_x = uniform_f((float)(tx * TILE + wave * 4));
     const float strip_y = uniform_f((float)(ty * TILE));
-    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    uint32_t n_visit = inside ? rg.y - rg.x : 0u, n_alpha = 0;   // list entries the pixel's loop visits
-    bool live = inside;   // this pixel still blends
-    uint64_t live_m = __builtin_amdgcn_ballot_w64(live);   // the wave's live pixels
+    pb.live = inside;
+    pb.n_visit = inside ? rg.y - rg.x : 0u;
+    uint64_t live_m = __builtin_amdgcn_ballot_w64(pb.live);   // the wave's live pixels
     bool wave_live = live_m != 0;
-    // chunk registers: this chunk's Gaussian (centre and support half-widths;
-    // conic and opacity; colour), the next chunk's, and the pair value of the
-    // one after
+    // chunk registers: this chunk's Gaussian, the next chunk's, and the pair
+    // value of the one after
     float4 n_p = make_float4(0.f, 0.f, 0.f, 0.f);
     float4 n_co = n_p, n_cl = n_p;
     if (rg.x + lane < rg.y) {
@@ -471,9 +502,7 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
         n_f = base + 2 * WAVE + lane < rg.y ? pval[base + 2 * WAVE + lane] : 0u;
         // the chunk's Gaussians whose support box meets a live pixel of the
         // strip (every pixel rejects the others)
-        const uint64_t box = !valid ? 0ull
-                             : long_tile ? strip_box_mask<1>(gp.x, gp.y, gp.z, gp.w, strip_x, strip_y)
-                                         : strip_box_mask<4>(gp.x, gp.y, gp.z, gp.w, strip_x, strip_y);
+        const uint64_t box = valid ? strip_box_mask(gp.x, gp.y, gp.z, gp.w, strip_x, strip_y) : 0ull;
         uint64_t mask = __builtin_amdgcn_ballot_w64((box & live_m) != 0ull);
         while (mask != 0 && wave_live) {
             int ii[4];
@@ -484,62 +513,219 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
                 ii[u] = ok[u] ? (int)__builtin_ctzll(mask) : 0;
                 mask = ok[u] ? (mask & (mask - 1)) : mask;
             }
-            // exponents and in-range masks of the four (exp(-5.55) < 1/255 and
-            // opacity <= 1: outside [-5.55, 0] a term fails the alpha test);
-            // one ballot per compare, no lane booleans
+            // exponents and in-range masks of the four; one ballot per
+            // compare, no lane booleans
             float pw[4];
             uint64_t mk[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const float gu = lane_f(gp.x, ii[u]), gv = lane_f(gp.y, ii[u]);
-                const float ca = lane_f(gb.x, ii[u]), cb = lane_f(gb.y, ii[u]), cc = lane_f(gb.z, ii[u]);
-                const float dx = gu - fpx, dy = gv - fpy;
-                const float q = fmaf(ca * dx, dx, (cc * dy) * dy);
-                pw[u] = fmaf(-0.5f, q, -((cb * dx) * dy));
+                pw[u] = blend_power(lane_f(gp.x, ii[u]), lane_f(gp.y, ii[u]), lane_f(gb.x, ii[u]),
+                                    lane_f(gb.y, ii[u]), lane_f(gb.z, ii[u]), fpx, fpy);
                 mk[u] = __builtin_amdgcn_ballot_w64(pw[u] <= 0.0f) & __builtin_amdgcn_ballot_w64(pw[u] >= -5.55f) &
                         (ok[u] ? ~0ull : 0ull);
             }
             if (((mk[0] | mk[1] | mk[2] | mk[3]) & live_m) == 0) continue;   // no live pixel in range of any
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const float power = pw[u];
                 if ((mk[u] & live_m) != 0) {
-                    const bool in = live && power <= 0.0f && power >= -5.55f;
+                    const bool in = pb.live && power_in_range(pw[u]);
                     if (STATS) n_alpha += in ? 1u : 0u;
                     // every lane computes; the pixel's state changes only where "in"
-                    const float op = lane_f(gb.w, ii[u]);
-                    const float alpha = fminf(0.99f, op * vm_exp_core(__builtin_amdgcn_fmed3f(power, -6.0f, 0.0f)));
-                    const bool take = in && alpha >= 1.0f / 255.0f;
-                    const float Tn = T * (1.0f - alpha);
-                    const bool stop = take && Tn < 0.0001f;
-                    const bool add = take && !stop;
-                    const float wgt = alpha * T;
-                    const float n0 = fmaf(lane_f(gc.x, ii[u]), wgt, C0);
-                    const float n1 = fmaf(lane_f(gc.y, ii[u]), wgt, C1);
-                    const float n2 = fmaf(lane_f(gc.z, ii[u]), wgt, C2);
-                    C0 = add ? n0 : C0;
-                    C1 = add ? n1 : C1;
-                    C2 = add ? n2 : C2;
-                    T = add ? Tn : T;
-                    if (STATS && stop) n_visit = base + (uint32_t)ii[u] + 1u - rg.x;
-                    live = live && !stop;
-                    live_m = __builtin_amdgcn_ballot_w64(live);
+                    const float alpha = blend_alpha(pw[u], lane_f(gb.w, ii[u]));
+                    const bool stop = blend_term(pb, alpha, in, lane_f(gc.x, ii[u]), lane_f(gc.y, ii[u]),
+                                                 lane_f(gc.z, ii[u]));
+                    if (STATS && stop) pb.n_visit = base + (uint32_t)ii[u] + 1u - rg.x;
+                    pb.live = pb.live && !stop;
+                    live_m = __builtin_amdgcn_ballot_w64(pb.live);
                 }
             }
             wave_live = live_m != 0;   // the wave stops when every pixel is done
         }
     }
-    if (inside) {
+}
+
+// phase 1 for one Gaussian and one band pixel (q = row * 16 + column, at
+// image position (fx, fy))
+__device__ __forceinline__ void select_term(BlendLds& L, uint32_t bit, int word, int q, float fx, float fy, float u,
+                                            float v, float ca, float cb, float cc, float op, uint32_t& n_alpha) {
+    const float power = blend_power(u, v, ca, cb, cc, fx, fy);
+    if (power_in_range(power)) {
+        ++n_alpha;
+        if (blend_alpha(power, op) >= 1.0f / 255.0f) atomicOr(&L.mask[word][q], bit);
+    }
+}
+
+template <bool STATS>
+__device__ __forceinline__ void band_walk(BlendLds& L, uint2 rg, const uint32_t* __restrict__ pval,
+                                          const float4* __restrict__ xy, const float4* __restrict__ conic,
+                                          const float4* __restrict__ rgb, int tx, int ty, int band, int W, int H,
+                                          PixelBlend& pb, uint32_t& n_alpha, int& px_out, int& py_out) {
+    const int t = (int)threadIdx.x, wave = t / WAVE, lane = (int)__lane_id();
+    // the band: columns tx * 16 + [0, 16), rows by0 + [0, 4); this thread's
+    // compositing pixel: row `wave`, column `lane` (lanes 0..15)
+    const int by0 = ty * TILE + band * (TILE / BL_BANDS);
+    const bool owner = lane < TILE;
+    const int q = wave * TILE + (lane & (TILE - 1));   // band pixel of the owner
+    const int px = tx * TILE + (lane & (TILE - 1)), py = by0 + wave;
+    px_out = owner ? px : W;   // non-owners write no pixel
+    py_out = py;
+    const float fpx = (float)px, fpy = (float)py;
+    const float tx0 = (float)(tx * TILE), ty0 = (float)by0;
+    pb.live = owner && px < W && py < H;
+    pb.n_visit = pb.live ? rg.y - rg.x : 0u;
+    if (owner) {
+#pragma unroll
+        for (int w = 0; w < BL_WORDS; ++w) L.mask[w][q] = 0u;
+    }
+    uint32_t lm = (uint32_t)__builtin_amdgcn_ballot_w64(pb.live) & 0xffffu;
+    if (lane == 0) L.live[wave] = lm;
+    // registers: this chunk's Gaussian, the next chunk's, the pair value of the one after
+    float4 n_p = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 n_co = n_p, n_cl = n_p;
+    if (rg.x + t < rg.y) {
+        const uint32_t f = pval[rg.x + t];
+        n_p = xy[f];
+        n_co = conic[f];
+        n_cl = rgb[f];
+    }
+    uint32_t n_f = rg.x + BL_CH + t < rg.y ? pval[rg.x + BL_CH + t] : 0u;
+    __syncthreads();
+    for (uint32_t base = rg.x; base < rg.y; base += BL_CH) {
+        // the band's live pixels, bit row * 16 + column (uniform)
+        const uint64_t live = (uint64_t)L.live[0] | ((uint64_t)L.live[1] << 16) | ((uint64_t)L.live[2] << 32) |
+                              ((uint64_t)L.live[3] << 48);
+        if (live == 0) break;
+        const float4 gp = n_p, gb = n_co, gc = n_cl;
+        const bool valid = base + t < rg.y;
+        if (base + BL_CH + t < rg.y) {
+            n_p = xy[n_f];
+            n_co = conic[n_f];
+            n_cl = rgb[n_f];
+        }
+        n_f = base + 2 * BL_CH + t < rg.y ? pval[base + 2 * BL_CH + t] : 0u;
+        L.g[0][t] = gp; L.g[1][t] = gb; L.g[2][t] = gc;
+        // 1. selection: this thread's Gaussian over the live pixels of its box in the band
+        const float c0 = fmaxf(ceilf((gp.x - gp.z) - tx0), 0.0f), c1 = fminf(floorf((gp.x + gp.z) - tx0), 15.0f);
+        const float r0 = fmaxf(ceilf((gp.y - gp.w) - ty0), 0.0f), r1 = fminf(floorf((gp.y + gp.w) - ty0), 3.0f);
+        const bool has = valid && c0 <= c1 && r0 <= r1;
+        const int ic0 = has ? (int)c0 : 0, ic1 = has ? (int)c1 : -1;
+        const int ir0 = has ? (int)r0 : 0, ir1 = has ? (int)r1 : -1;
+        const bool small = (ic1 - ic0 + 1) * (ir1 - ir0 + 1) <= BL_SEL_BOX;
+        const uint32_t bit = 1u << (t & 31);
+        const int word = t >> 5;
+        if (small) {
+            for (int y = ir0; y <= ir1; ++y) {
+                const uint32_t row = (uint32_t)(live >> (y * TILE));
+                for (int x = ic0; x <= ic1; ++x)
+                    if ((row >> x) & 1u)
+                        select_term(L, bit, word, y * TILE + x, tx0 + (float)x, ty0 + (float)y, gp.x, gp.y, gb.x,
+                                    gb.y, gb.z, gb.w, n_alpha);
+            }
+        }
+        // the others: one at a time, a band pixel per lane
+        uint64_t big = __builtin_amdgcn_ballot_w64(!small);
+        const int bx = lane & (TILE - 1), byy = lane / TILE;
+        const bool lane_live = (live >> lane) & 1ull;
+        while (big != 0) {
+            const int j = (int)__builtin_ctzll(big);
+            big &= big - 1;
+            const int x0 = lane_i(ic0, j), x1 = lane_i(ic1, j), y0 = lane_i(ir0, j), y1 = lane_i(ir1, j);
+            if (lane_live && bx >= x0 && bx <= x1 && byy >= y0 && byy <= y1) {
+                const int jt = wave * WAVE + j;
+                select_term(L, 1u << (jt & 31), jt >> 5, lane, tx0 + (float)bx, ty0 + (float)byy, lane_f(gp.x, j),
+                            lane_f(gp.y, j), lane_f(gb.x, j), lane_f(gb.y, j), lane_f(gb.z, j), lane_f(gb.w, j),
+                            n_alpha);
+            }
+        }
+        __syncthreads();
+        // 2. compositing: this thread's pixel over its selected Gaussians in order
+        if (pb.live) {
+            for (int w = 0; w < BL_WORDS && pb.live; ++w) {
+                uint32_t m = L.mask[w][q];
+                while (m != 0u) {
+                    const int g = w * 32 + (int)__builtin_ctz(m);
+                    m &= m - 1u;
+                    const float4 P = L.g[0][g], Q = L.g[1][g], R = L.g[2][g];
+                    const float power = blend_power(P.x, P.y, Q.x, Q.y, Q.z, fpx, fpy);
+                    const float alpha = blend_alpha(power, Q.w);
+                    if (blend_term(pb, alpha, power_in_range(power), R.x, R.y, R.z)) {
+                        if (STATS) pb.n_visit = base + (uint32_t)g + 1u - rg.x;
+                        pb.live = false;
+                        break;
+                    }
+                }
+            }
+        }
+        if (owner) {
+#pragma unroll
+            for (int w = 0; w < BL_WORDS; ++w) L.mask[w][q] = 0u;
+        }
+        lm = (uint32_t)__builtin_amdgcn_ballot_w64(pb.live) & 0xffffu;
+        if (lane == 0) L.live[wave] = lm;
+        __syncthreads();
+    }
+}
+
+// Workgroups for n_tiles tiles: four per long tile (at most BL_LONG_CAP of
+// them, rounded up to a multiple of 8, plus up to 28 left over by that
+// rounding), one per other tile.
+__host__ __device__ inline uint32_t blend_long_slots(uint32_t n_tiles) {
+    return ((n_tiles < BL_LONG_CAP ? n_tiles : BL_LONG_CAP) + 7u) & ~7u;
+}
+__host__ __device__ inline uint32_t blend_workgroups(uint32_t n_tiles) {
+    return n_tiles + (BL_BANDS - 1) * blend_long_slots(n_tiles) + 4 * 7;
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ ranges, const uint32_t* __restrict__ order,
+                                                 const uint32_t* __restrict__ pval, const float4* __restrict__ xy,
+                                                 const float4* __restrict__ conic, const float4* __restrict__ rgb,
+                                                 int W, int H, int TX, int TY, int n_views,
+                                                 float* __restrict__ image, uint2* __restrict__ stats) {
+    __shared__ BlendLds L;
+    // Workgroups [0, 4 * n8) serve the n_long long tiles (the first ones of
+    // the order; n8 = n_long rounded up to a multiple of 8), the rest the
+    // other tiles in order.  Workgroup ids go round-robin over the eight
+    // XCDs, so a long tile's four workgroups are taken 8 ids apart (one XCD).
+    const uint32_t n_tiles = (uint32_t)(TX * TY) * (uint32_t)n_views;
+    const uint32_t n_long = min(order[n_tiles], blend_long_slots(n_tiles));
+    const uint32_t n8 = (n_long + 7u) & ~7u;
+    const uint32_t b = blockIdx.x;
+    uint32_t idx;
+    int band = -1;
+    if (b < 4 * n8) {
+        const uint32_t s = b >> 3;
+        idx = (s >> 2) * 8 + (b & 7);
+        band = (int)(s & 3);
+        if (idx >= n_long) return;
+    } else {
+        idx = n_long + (b - 4 * n8);
+        if (idx >= n_tiles) return;
+    }
+    const uint32_t tile = order[idx];
+    const uint32_t per_view = (uint32_t)(TX * TY);
+    const uint32_t view = tile / per_view;
+    const uint32_t t = tile - view * per_view;
+    const int tx = (int)(t % (uint32_t)TX), ty = (int)(t / (uint32_t)TX);
+    const uint2 rg = ranges[tile];
+    PixelBlend pb{1.0f, 0.0f, 0.0f, 0.0f, false, 0u};
+    uint32_t n_alpha = 0;
+    int px, py;
+    if (band >= 0)   // uniform over the workgroup
+        band_walk<STATS>(L, rg, pval, xy, conic, rgb, tx, ty, band, W, H, pb, n_alpha, px, py);
+    else
+        strip_walk<STATS>(rg, pval, xy, conic, rgb, tx, ty, W, H, pb, n_alpha, px, py);
+    if (px < W && py < H) {
         float* o = image + (((size_t)view * H + py) * W + px) * 3;
-        o[0] = C0; o[1] = C1; o[2] = C2;
+        o[0] = pb.C0; o[1] = pb.C1; o[2] = pb.C2;
     }
     if (STATS) {
-        const uint32_t e = wave_sum(n_visit), al = wave_sum(n_alpha);
-        if (lane == 0) { s_st[0][threadIdx.x / WAVE] = e; s_st[1][threadIdx.x / WAVE] = al; }
+        const uint32_t e = wave_sum(pb.n_visit), al = wave_sum(n_alpha);
+        if (__lane_id() == 0) { L.st[0][threadIdx.x / WAVE] = e; L.st[1][threadIdx.x / WAVE] = al; }
         __syncthreads();
         if (threadIdx.x == 0) {   // stats cleared before the launch: a long tile's four add up
             uint32_t se = 0, sa = 0;
-            for (int i = 0; i < BL_NT / WAVE; ++i) { se += s_st[0][i]; sa += s_st[1][i]; }
+            for (int i = 0; i < BL_NT / WAVE; ++i) { se += L.st[0][i]; sa += L.st[1][i]; }
             atomicAdd(&stats[tile].x, se);
             atomicAdd(&stats[tile].y, sa);
         }
@@ -591,7 +777,7 @@ void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* order, co
                   uint2* stats) {
     const uint32_t n_tiles = (uint32_t)(TX * TY * n_views);
     if (!n_tiles) return;
-    const uint32_t n_blocks = n_tiles + 4 * blend_long_slots(n_tiles);
+    const uint32_t n_blocks = blend_workgroups(n_tiles);
     if (stats) {
         launch_fill_u32(st, (uint32_t*)stats, 2 * (uint64_t)n_tiles, 0u);
         hipLaunchKernelGGL(k_blend<true>, dim3(n_blocks), dim3(BL_NT), 0, st, ranges, order, pval, xy, conic, rgb, W,

@@ -272,6 +272,69 @@ def test_eight_views_shared_pool(clusters):
     r.close()
 
 
+def _dense_scene(seed=0, n=40000):
+    """A ball of Gaussians (normal, 1 m deviation) seen from 25 m: tiles of
+    up to 15,000 pairs.  80 % sub-pixel to a few pixels, 17 % up to ~10 px,
+    3 % large and faint; most pixels of the dense tiles stop on the
+    transmittance threshold, the outer ones never do."""
+    rng = np.random.default_rng(seed)
+    means = rng.normal(0.0, 1.0, (n, 3)).clip(-3, 3)
+    kind = rng.uniform(size=n)
+    s = np.where(kind < 0.8, np.exp(rng.uniform(np.log(0.004), np.log(0.04), n)),
+                 np.where(kind < 0.97, np.exp(rng.uniform(np.log(0.04), np.log(0.3), n)),
+                          np.exp(rng.uniform(np.log(0.3), np.log(1.5), n))))
+    scales = s[:, None] * np.exp(rng.uniform(-0.7, 0.7, (n, 3)))
+    q = rng.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    op = np.where(kind < 0.97, rng.uniform(0.05, 1.0, n), rng.uniform(0.02, 0.3, n))
+    return synth.Scene(means.astype(np.float32), scales.astype(np.float32), q.astype(np.float32),
+                       op.astype(np.float32), rng.normal(0.0, 0.4, (n, 16, 3)).astype(np.float32))
+
+
+def _tile_sums(a, W, H, TX, TY):
+    """Per-tile sums of a per-pixel [H][W] array (16x16 tiles, ragged edges)."""
+    pad = np.zeros((TY * 16, TX * 16), np.int64)
+    pad[:H, :W] = a
+    return pad.reshape(TY, 16, TX, 16).sum(axis=(1, 3)).reshape(-1)
+
+
+def test_dense_tiles():
+    """Tiles of 1,024 pairs or more take the band walk (four workgroups per
+    tile), the others the strip walk: two views (the ball at the centre, and at the
+    ragged bottom-right corner of a 312x232 image), every intermediate and
+    the image against the oracle, and the blend's per-tile work counter
+    (list entries visited per pixel, up to the stop) equal to the oracle's
+    per-pixel visits summed over each tile."""
+    import paper_2506_19415_amd as pkg
+    sc = _dense_scene()
+    osc = oracle.OracleScene(sc, 256, 1, 0.5, 2.0)
+    W, H = 312, 232
+    c0 = synth.orbit(8, 25.0, W, H)[0]
+    eye = np.array([25.0, 0.0, 0.0])
+    c1 = synth.look_at(eye, np.array([-1.0, -0.52, 0.38]), W, H, 60.0)
+    cams = [c0, c1]
+    r = _renderer(sc, 256, 256, (W, H), (78, 58), 0.5, max_views=2, full_scene=True)
+    ovm = _ovm(osc, 256, (W, H), (78, 58))
+    r.set_flags(pkg.VM3DGS_FLAG_LINKS | pkg.VM3DGS_FLAG_BLEND_STATS)
+    for k in range(2):
+        print(f"dense tiles frame {k}", flush=True)
+        _, out = r.frame(cams)
+        ovm.frame(cams)
+        compare_frame(r, ovm, out, 2, tag=f"dense {k}")
+    TX, TY = (W + 15) // 16, (H + 15) // 16
+    rg = ovm.get("ranges").reshape(-1, 2).astype(np.int64)
+    n_pairs = rg[:, 1] - rg[:, 0]
+    assert np.count_nonzero(n_pairs >= 1024) >= 16 and n_pairs.max() > 8 * 1024
+    # the long tiles at the corner view are cut by the image edge
+    corner = n_pairs[TX * TY:].reshape(TY, TX)
+    assert corner[-1, :].max() >= 1024 and corner[:, -1].max() >= 1024
+    visits = ovm.get("visits").reshape(2, H, W)
+    want = np.concatenate([_tile_sums(visits[v], W, H, TX, TY) for v in range(2)])
+    got = r.get("blend_stats", np.uint32).reshape(-1, 2)[: 2 * TX * TY, 0].astype(np.int64)
+    assert np.array_equal(got, want)
+    r.close()
+
+
 @pytest.mark.slow
 def test_terrain6m_full_size_sampled():
     """The bench workload at full size in the bench's launch configuration:
