@@ -544,6 +544,29 @@ __device__ __forceinline__ void strip_walk(uint2 rg, const uint32_t* __restrict_
     }
 }
 
+// value of sub-lane j of this lane's quad (DPP quad_perm [j, j, j, j])
+__device__ __forceinline__ int quad_bcast_i(int x, int j) {
+    switch (j) {
+    case 0: return __builtin_amdgcn_update_dpp(0, x, 0x00, 0xf, 0xf, false);
+    case 1: return __builtin_amdgcn_update_dpp(0, x, 0x55, 0xf, 0xf, false);
+    case 2: return __builtin_amdgcn_update_dpp(0, x, 0xaa, 0xf, 0xf, false);
+    default: return __builtin_amdgcn_update_dpp(0, x, 0xff, 0xf, 0xf, false);
+    }
+}
+__device__ __forceinline__ float quad_bcast(float x, int j) {
+    return __builtin_bit_cast(float, quad_bcast_i(__builtin_bit_cast(int, x), j));
+}
+
+// 16 bits, one per quad of a wave-wide mask in which the lanes of a quad agree
+__device__ __forceinline__ uint32_t quad_live16(uint64_t m) {
+    uint64_t x = m & 0x1111111111111111ull;   // lane 4c -> bit 4c
+    x = (x | (x >> 3)) & 0x0303030303030303ull;
+    x = (x | (x >> 6)) & 0x000f000f000f000full;
+    x = (x | (x >> 12)) & 0x000000ff000000ffull;
+    x = (x | (x >> 24)) & 0xffffull;
+    return (uint32_t)x;
+}
+
 // phase 1 for one Gaussian and one band pixel (q = row * 16 + column, at
 // image position (fx, fy))
 __device__ __forceinline__ void select_term(BlendLds& L, uint32_t bit, int word, int q, float fx, float fy, float u,
@@ -561,23 +584,23 @@ __device__ __forceinline__ void band_walk(BlendLds& L, uint2 rg, const uint32_t*
                                           const float4* __restrict__ rgb, int tx, int ty, int band, int W, int H,
                                           PixelBlend& pb, uint32_t& n_alpha, int& px_out, int& py_out) {
     const int t = (int)threadIdx.x, wave = t / WAVE, lane = (int)__lane_id();
-    // the band: columns tx * 16 + [0, 16), rows by0 + [0, 4); this thread's
-    // compositing pixel: row `wave`, column `lane` (lanes 0..15)
+    // the band: columns tx * 16 + [0, 16), rows by0 + [0, 4).  Compositing:
+    // wave w takes row w, a quad of lanes per pixel (column lane / 4); the
+    // quad's lanes hold the same pixel state and sub-lane k = lane % 4
+    // evaluates every fourth selected term
     const int by0 = ty * TILE + band * (TILE / BL_BANDS);
-    const bool owner = lane < TILE;
-    const int q = wave * TILE + (lane & (TILE - 1));   // band pixel of the owner
-    const int px = tx * TILE + (lane & (TILE - 1)), py = by0 + wave;
-    px_out = owner ? px : W;   // non-owners write no pixel
+    const int col = lane >> 2, sub = lane & 3;
+    const int q = wave * TILE + col;   // band pixel of the quad
+    const int px = tx * TILE + col, py = by0 + wave;
+    px_out = sub == 0 ? px : W;   // one lane of the quad writes the pixel
     py_out = py;
     const float fpx = (float)px, fpy = (float)py;
     const float tx0 = (float)(tx * TILE), ty0 = (float)by0;
-    pb.live = owner && px < W && py < H;
-    pb.n_visit = pb.live ? rg.y - rg.x : 0u;
-    if (owner) {
+    pb.live = px < W && py < H;
+    pb.n_visit = pb.live && sub == 0 ? rg.y - rg.x : 0u;
 #pragma unroll
-        for (int w = 0; w < BL_WORDS; ++w) L.mask[w][q] = 0u;
-    }
-    uint32_t lm = (uint32_t)__builtin_amdgcn_ballot_w64(pb.live) & 0xffffu;
+    for (int w = 0; w < BL_WORDS / 4; ++w) L.mask[sub * (BL_WORDS / 4) + w][q] = 0u;
+    uint32_t lm = quad_live16(__builtin_amdgcn_ballot_w64(pb.live));
     if (lane == 0) L.live[wave] = lm;
     // registers: this chunk's Gaussian, the next chunk's, the pair value of the one after
     float4 n_p = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -638,29 +661,45 @@ __device__ __forceinline__ void band_walk(BlendLds& L, uint2 rg, const uint32_t*
             }
         }
         __syncthreads();
-        // 2. compositing: this thread's pixel over its selected Gaussians in order
-        if (pb.live) {
+        // 2. compositing: the quad's pixel over its selected Gaussians in
+        // order, four at a time: sub-lane k evaluates the k-th (exponent and
+        // alpha, the costly part), then the quad blends the four in order,
+        // each lane taking them from the others (DPP quad broadcasts)
+        if (pb.live) {   // uniform over the quad
             for (int w = 0; w < BL_WORDS && pb.live; ++w) {
                 uint32_t m = L.mask[w][q];
-                while (m != 0u) {
-                    const int g = w * 32 + (int)__builtin_ctz(m);
-                    m &= m - 1u;
-                    const float4 P = L.g[0][g], Q = L.g[1][g], R = L.g[2][g];
-                    const float power = blend_power(P.x, P.y, Q.x, Q.y, Q.z, fpx, fpy);
-                    const float alpha = blend_alpha(power, Q.w);
-                    if (blend_term(pb, alpha, power_in_range(power), R.x, R.y, R.z)) {
-                        if (STATS) pb.n_visit = base + (uint32_t)g + 1u - rg.x;
-                        pb.live = false;
-                        break;
+                while (m != 0u && pb.live) {
+                    uint32_t mk = m;   // without its first `sub` bits
+                    for (int i = 0; i < sub; ++i) mk &= mk - 1u;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) m &= m - 1u;
+                    // this lane's term: alpha, or -1 where none or out of range
+                    float a = -1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+                    const int g = mk != 0u ? w * 32 + (int)__builtin_ctz(mk) : 0;
+                    if (mk != 0u) {
+                        const float4 P = L.g[0][g], Q = L.g[1][g], R = L.g[2][g];
+                        const float power = blend_power(P.x, P.y, Q.x, Q.y, Q.z, fpx, fpy);
+                        if (power_in_range(power)) a = blend_alpha(power, Q.w);
+                        cr = R.x; cg = R.y; cb = R.z;
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        // every lane of the quad takes part in each broadcast
+                        // (a DPP read from an inactive lane gives 0)
+                        const float aj = quad_bcast(a, j);
+                        const int gj = STATS ? quad_bcast_i(g, j) : 0;
+                        if (blend_term(pb, aj, aj >= 0.0f, quad_bcast(cr, j), quad_bcast(cg, j), quad_bcast(cb, j))) {
+                            if (STATS && sub == 0) pb.n_visit = base + (uint32_t)gj + 1u - rg.x;
+                            pb.live = false;
+                            break;
+                        }
                     }
                 }
             }
         }
-        if (owner) {
 #pragma unroll
-            for (int w = 0; w < BL_WORDS; ++w) L.mask[w][q] = 0u;
-        }
-        lm = (uint32_t)__builtin_amdgcn_ballot_w64(pb.live) & 0xffffu;
+        for (int w = 0; w < BL_WORDS / 4; ++w) L.mask[sub * (BL_WORDS / 4) + w][q] = 0u;
+        lm = quad_live16(__builtin_amdgcn_ballot_w64(pb.live));
         if (lane == 0) L.live[wave] = lm;
         __syncthreads();
     }
