@@ -113,6 +113,7 @@ struct or_vm {
     int8_t* page_level;    /* [n_pg] requested level, -1 none */
     int n_copy; int64_t* copy; int32_t* copy_id;   /* [n][3] bytes triples, [n][4] page level slot sub */
     int n_missing; int32_t* missing;               /* [n][2] page level */
+    int n_missing_cap;                             /* of them, those left for want of a free pool entry */
     int hits, misses, evictions;
     int n_rl; rl_t* rl; int64_t n_render;
     pp_t* pp;              /* [views][n_render] */
@@ -361,7 +362,7 @@ static void page_table(or_vm* vm)
     int32_t* fresh_list[3] = {NULL, NULL, NULL};
     int fresh_n[3] = {0, 0, 0}, fresh_h[3] = {0, 0, 0};
     for (int l = 0; l < 3; l++) { fresh[l][0] = -1; fresh[l][1] = 0; fresh_list[l] = malloc(sizeof(int32_t) * (size_t)(S + 1)); }
-    vm->n_copy = 0; vm->n_missing = 0;
+    vm->n_copy = 0; vm->n_missing = 0; vm->n_missing_cap = 0;
     for (int i = 0; i < nm; i++) {
         int32_t p = miss[2 * i];
         int l = miss[2 * i + 1];
@@ -405,6 +406,7 @@ static void page_table(or_vm* vm)
         }
         if (ts < 0) {
             vm->missing[2 * vm->n_missing] = p; vm->missing[2 * vm->n_missing + 1] = l; vm->n_missing++;
+            vm->n_missing_cap++;
             continue;
         }
         assign(vm, p, l, ts, tj, req_sub, slot_req);
@@ -877,8 +879,10 @@ int or_lod_level(float fy, float radius, float depth, float tau, int L)
 
 /* Thresholds that follow memory use (Sec. 5.1.1, with Sec. 4.1 and Sec. 5.3):
  * the controller aims at 50-80 % of the pool.  Usage is the share of
- * physical pages the frame required; requests left missing count as over
- * the band.  Over 80 % (or anything missing) the transition distances
+ * physical pages the frame required; requests left missing for want of a
+ * free pool entry count as over the band (those the copy budget defers do
+ * not: they say nothing about memory use).  Over 80 % (or anything missing
+ * for want of space) the transition distances
  * shrink: tau, the level-0 radius in pixels, is multiplied by 1 + step.
  * Under 50 % while some requested page is at a coarse level they grow:
  * tau is divided by 1 + step.  The step changes by 1 % of itself after each
@@ -904,7 +908,7 @@ static void lod_controller(float* tau, float* step, int* dir, int* last_move, in
 static void lod_control(or_vm* vm)
 {
     lod_controller(&vm->tau, &vm->lod_step, &vm->lod_dir, &vm->lod_last_move, vm->frame, vm->S, vm->req_slots,
-                   vm->n_missing, vm->n_coarse);
+                   vm->n_missing_cap, vm->n_coarse);
 }
 
 void or_lod_control_trace(int n, int S, float tau0, const int* req_slots, const int* n_missing,

@@ -323,3 +323,28 @@ def test_lod_controller_limits():
     assert np.all(tau == 32.0) and np.all(step == 0.125)
     tau, step = oracle.lod_control_trace(10, 32.0, [6] * n, [0] * n, [3] * n)
     assert np.all(tau == 32.0) and np.all(step == 0.125)
+
+
+def test_lod_controller_ignores_budget_deferrals():
+    """Pages the copy budget defers are no sign of memory use: with a pool
+    that holds the whole scene and a budget of two pages per frame, the cold
+    frames leave requests missing, yet the thresholds only move finer (usage
+    under 50 % with coarse requests), as they do without the budget.
+    Counting those deferrals as over the band would push tau up every frame."""
+    sc = synth.scene_clusters(0)
+    osc = oracle.OracleScene(sc, 256, 3, 0.5, 2.0)
+    cams = synth.orbit()
+    taus = {}
+    for budget in (0, 2):
+        vm = oracle.OracleVM(osc, 256, (320, 240), (80, 60), copy_budget=budget, lod_radius_px=32.0)
+        vm.set_adaptive_lod(True)
+        seq, missing = [], 0
+        for k in range(4):
+            vm.frame([cams[k % len(cams)]])
+            seq.append(float(vm.get("lod")[0]))
+            missing += vm.counts()["missing"]
+        taus[budget] = seq
+        if budget:
+            assert missing > 0
+    for budget in (0, 2):
+        assert taus[budget][0] <= 32.0 and np.all(np.diff(taus[budget]) <= 0), (budget, taus[budget])
