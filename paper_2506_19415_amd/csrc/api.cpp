@@ -486,16 +486,18 @@ namespace {
 // The LOD thresholds follow memory use (Sec. 5.1.1, with Sec. 4.1 and
 // Sec. 5.3).  The aim is 50-80 % of the pool, usage being the share of
 // physical pages the frame required.  Over 80 %, or with requests left
-// missing, the transition distances shrink: the level-0 radius tau (pixels)
+// missing for want of a free pool entry (not those the copy budget defers,
+// which say nothing about memory use), the transition distances shrink: the
+// level-0 radius tau (pixels)
 // grows by the factor 1 + step.  Under 50 % while some requested page is at
 // a coarse level, tau shrinks by the same factor.  After a move the step
 // changes by 1 % of itself: up when the move repeats the direction of a
 // move made at most kLodQuick frames earlier, down when it reverses one.
 // tau stays within [2^-7, 2^16] px.  The new tau is used from the next frame.
-void lod_control(vm3dgs* c, uint32_t n_missing, uint32_t req_slots, uint32_t n_coarse) {
+void lod_control(vm3dgs* c, uint32_t n_missing_cap, uint32_t req_slots, uint32_t n_coarse) {
     const uint64_t S = (uint64_t)c->S;
     int d = 0;
-    if (n_missing > 0 || (uint64_t)req_slots * 5 > S * 4) d = 1;
+    if (n_missing_cap > 0 || (uint64_t)req_slots * 5 > S * 4) d = 1;
     else if ((uint64_t)req_slots * 2 < S && n_coarse > 0) d = -1;
     if (d == 0) return;
     const float t = d > 0 ? c->lod_tau * (1.0f + c->lod_step) : c->lod_tau / (1.0f + c->lod_step);
@@ -867,7 +869,7 @@ vm3dgs_status frame_impl(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views,
         }
         st.lod_radius_px = c->lod_tau;
         if ((c->opt.flags & VM3DGS_FLAG_ADAPTIVE_LOD) && c->L > 1)
-            lod_control(c, k[C_NMISSING], k[C_REQSLOTS], k[C_NCOARSE]);
+            lod_control(c, k[C_NMISSCAP], k[C_REQSLOTS], k[C_NCOARSE]);
         c->last_n_pfreq = (c->pf_on && c->pf_net) ? k[C_NPFREQ] : 0u;
         c->last_n_pf = n_pf;
         st.prefetched = n_pf;

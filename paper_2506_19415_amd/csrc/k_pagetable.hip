@@ -213,11 +213,6 @@ __global__ __launch_bounds__(PT_NT) void k_pagetable_l1(const uint64_t* __restri
 
 // stage 1 over the sorted requests: hits, miss flags (request order kept)
 // unused key slots past the compacted requests sort last
-__global__ void k_ptl_pad_keys(uint64_t* __restrict__ keys, int n_pg, const uint32_t* __restrict__ counters) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n_pg && (uint32_t)i >= counters[vm::C_NREQ]) keys[i] = ~0ull;
-}
-
 // Streaming: a miss whose page is resident at another level is drawn at the
 // resident level nearest to the requested one (the finer at equal distance),
 // that entry is required too, and it is flagged in flag2 (served after the
@@ -280,9 +275,10 @@ __global__ void k_ptl_miss_list(const uint64_t* __restrict__ keys, const int8_t*
     else if (flag2 && flag2[i]) miss[pos[n_pg] + pos2[i]] = pg | ((uint32_t)page_level[pg] << 30);
 }
 
-// candidate keys: whole free pages (last use + 1, slot) and, per level l >= 1,
-// the non-required sub-slots of level-l pages (0 for empty else last use + 1,
-// slot * 64 + sub); ineligible entries are all-ones and sort last
+// candidate keys: whole free pages (last use + 1, slot; all-ones for required
+// pages, which sort last) and, per level l >= 1, the non-required sub-slots
+// of level-l pages (0 for empty else last use + 1, slot * 64 + sub), listed
+// in counters[C_NCAND1 / C_NCAND2] entries
 __global__ void k_ptl_cand_keys(int S, int L, int idx_bits, const int8_t* __restrict__ slot_level,
                                 const int32_t* __restrict__ last_used, const int32_t* __restrict__ sub_vpage,
                                 const int32_t* __restrict__ sub_last_used, const uint8_t* __restrict__ req_sub,
@@ -302,13 +298,18 @@ __global__ void k_ptl_cand_keys(int S, int L, int idx_bits, const int8_t* __rest
         ok1 = l == 1;
         ok2 = l == 2;
     }
-    if (L > 1) ck1[i] = ok1 ? key : ~0ull;
-    if (L > 2) ck2[i] = ok2 ? key : ~0ull;
+    // appended, wave by wave, to the level's list (its sort restores the order)
     const uint64_t b1 = __ballot(ok1), b2 = __ballot(ok2);
+    uint32_t base1 = 0, base2 = 0;
     if (__lane_id() == 0) {
-        if (b1) atomicAdd(&counters[vm::C_NCAND1], (uint32_t)__popcll(b1));
-        if (b2) atomicAdd(&counters[vm::C_NCAND2], (uint32_t)__popcll(b2));
+        if (b1) base1 = atomicAdd(&counters[vm::C_NCAND1], (uint32_t)__popcll(b1));
+        if (b2) base2 = atomicAdd(&counters[vm::C_NCAND2], (uint32_t)__popcll(b2));
     }
+    base1 = (uint32_t)__shfl((int)base1, 0, WAVE);
+    base2 = (uint32_t)__shfl((int)base2, 0, WAVE);
+    const uint64_t lt = lanemask_lt();
+    if (ok1) ck1[base1 + (uint32_t)__popcll(b1 & lt)] = key;
+    if (ok2) ck2[base2 + (uint32_t)__popcll(b2 & lt)] = key;
 }
 
 struct PtWalk {
@@ -335,7 +336,7 @@ __global__ __launch_bounds__(WAVE) void k_ptl_walk(PtWalk a) {
     const uint32_t n_s = (uint32_t)a.S;
     const uint32_t ncl[3] = {0u, a.counters[vm::C_NCAND1], a.counters[vm::C_NCAND2]};
     uint32_t pw = 0, pc[3] = {0, 0, 0}, fn[3] = {0, 0, 0}, fh[3] = {0, 0, 0};
-    uint32_t n_copy = 0, n_missing = 0, evict = 0;
+    uint32_t n_copy = 0, n_missing = 0, n_missing_cap = 0, evict = 0;
     for (uint32_t i = 0; i < n_miss; ++i) {
         const uint32_t m = a.miss[i];
         const int32_t p = (int32_t)(m & 0x3fffffffu);
@@ -414,8 +415,9 @@ __global__ __launch_bounds__(WAVE) void k_ptl_walk(PtWalk a) {
                 if (l > 0) ++fn[l];
             }
         }
-        if (ts < 0) {
+        if (ts < 0) {   // no free pool entry
             a.missing[2 * n_missing] = p; a.missing[2 * n_missing + 1] = l; ++n_missing;
+            ++n_missing_cap;
             continue;
         }
         const int e = ts * vmk::SUBS + tj;
@@ -444,6 +446,7 @@ __global__ __launch_bounds__(WAVE) void k_ptl_walk(PtWalk a) {
         a.counters[vm::C_EVICT] = evict;
         a.counters[vm::C_NCOPY] = n_copy;
         a.counters[vm::C_NMISSING] = n_missing;
+        a.counters[vm::C_NMISSCAP] = n_missing_cap;
     }
 }
 
@@ -629,11 +632,11 @@ static int bits_for_u(uint64_t n) {
 void launch_pagetable_lod(hipStream_t st, const PtArgs& a, SortWork& sw, const LodWork& w) {
     const int n_pg = a.n_pg, S = a.S, L = a.L;
     const unsigned nb_pg = (unsigned)((n_pg + 255) / 256);
-    // requests in service order: all n_pg key slots (unused ones are all-ones)
+    // requests in service order: the counters[C_NREQ] keys the visibility
+    // stage wrote (the sort's grid covers n_pg, its kernels read the count)
     uint64_t* rk[2] = {const_cast<uint64_t*>(a.req_keys), w.keys_alt};
     uint32_t* nov[2] = {nullptr, nullptr};
-    hipLaunchKernelGGL(k_ptl_pad_keys, dim3(nb_pg), dim3(256), 0, st, rk[0], n_pg, (const uint32_t*)a.counters);
-    const int kb = onesweep_u64(st, sw, rk, nov, (uint32_t)n_pg, 0, 64);
+    const int kb = onesweep_u64_dev(st, sw, rk, nov, (uint32_t)n_pg, a.counters + vm::C_NREQ, 0, 64);
     const uint64_t* keys = rk[kb];
     launch_fill_u32(st, (uint32_t*)a.req_sub, ((uint64_t)S * SUBS + 3) / 4, 0u);
     launch_fill_u32(st, (uint32_t*)a.slot_req, ((uint64_t)S + 3) / 4, 0u);
@@ -665,7 +668,9 @@ void launch_pagetable_lod(hipStream_t st, const PtArgs& a, SortWork& sw, const L
         pw.ck[l] = nullptr;
         if (l < L) {
             uint64_t* ck[2] = {w.ck[l][0], w.ck[l][1]};
-            const int cb = onesweep_u64(st, sw, ck, nov, (uint32_t)S * SUBS, 0, std::max(8, end_bit));
+            const int cb = onesweep_u64_dev(st, sw, ck, nov, (uint32_t)S * SUBS,
+                                            a.counters + (l == 1 ? vm::C_NCAND1 : vm::C_NCAND2), 0,
+                                            std::max(8, end_bit));
             pw.ck[l] = ck[cb];
         }
     }

@@ -318,6 +318,11 @@ int onesweep_u64(hipStream_t st, SortWork& w, uint64_t* keys[2], uint32_t* vals[
     return onesweep_impl<uint64_t>(st, w, keys, vals, n, nullptr, begin_bit, end_bit);
 }
 
+int onesweep_u64_dev(hipStream_t st, SortWork& w, uint64_t* keys[2], uint32_t* vals[2], uint32_t n_bound,
+                     const uint32_t* n_dev, int begin_bit, int end_bit) {
+    return onesweep_impl<uint64_t>(st, w, keys, vals, n_bound, n_dev, begin_bit, end_bit);
+}
+
 void scan_lb(hipStream_t st, SortWork& w, const uint32_t* in, uint64_t n, uint32_t* out, uint32_t* total) {
     const uint32_t nb = std::max(1u, div_up(n, SC_TILE));
     hipLaunchKernelGGL(k_scan_lb<InPlain>, dim3(nb), dim3(SC_NT), 0, st, InPlain{in}, n, out, total, w.status,

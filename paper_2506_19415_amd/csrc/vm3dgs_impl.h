@@ -83,6 +83,8 @@ int onesweep_u32_dev(hipStream_t st, SortWork& w, uint32_t* keys[2], uint32_t* v
                      const uint32_t* n_dev, int begin_bit, int end_bit);
 int onesweep_u64(hipStream_t st, SortWork& w, uint64_t* keys[2], uint32_t* vals[2], uint32_t n, int begin_bit,
                  int end_bit);
+int onesweep_u64_dev(hipStream_t st, SortWork& w, uint64_t* keys[2], uint32_t* vals[2], uint32_t n_bound,
+                     const uint32_t* n_dev, int begin_bit, int end_bit);
 void scan_lb(hipStream_t st, SortWork& w, const uint32_t* in, uint64_t n, uint32_t* out, uint32_t* total);
 void scan_lb_gather(hipStream_t st, SortWork& w, const uint32_t* a, const uint32_t* idx, uint64_t n, uint32_t* out,
                     uint32_t* total);
@@ -102,6 +104,7 @@ enum Ctr {
     C_NCOARSE,    // requests at a level above 0
     C_PTERR,      // page-table bound check (never set when the host checks hold)
     C_FALLBACK,   // streaming: requests drawn at another resident level
+    C_NMISSCAP,   // LOD table: requests left missing for want of a free pool entry
     C_NCOUNTERS = 24
 };
 
