@@ -43,7 +43,9 @@ def lib():
         L.or_round_bf16.argtypes = [C.c_float]
         L.or_scene_build.restype = C.c_void_p
         L.or_scene_build.argtypes = [C.POINTER(_Scene), C.c_int, C.c_int, C.c_double, C.c_double, C.c_int,
-                                     C.c_float]
+                                     C.c_float, C.c_int]
+        L.or_kmeans_page.restype = C.c_int
+        L.or_kmeans_page.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_void_p, C.c_void_p]
         L.or_scene_free.argtypes = [C.c_void_p]
         L.or_scene_get.restype = C.c_int64
         L.or_scene_get.argtypes = [C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64]
@@ -144,6 +146,17 @@ def round_bf16(x: float) -> float:
     return lib().or_round_bf16(float(x))
 
 
+def kmeans_page(records, k, scale_up=1.0):
+    """The k parents of one page's level from its records ([n][59] float32)
+    by the k-means builder; returns (parents [k][59], cluster of each record
+    (-1 for padding), Lloyd iterations run)."""
+    r = np.ascontiguousarray(records, dtype=np.float32)
+    out = np.zeros((k, 59), np.float32)
+    assign = np.zeros(len(r), np.int32)
+    it = lib().or_kmeans_page(r.ctypes.data, len(r), int(k), float(scale_up), out.ctypes.data, assign.ctypes.data)
+    return out, assign, int(it)
+
+
 def set_threads(n: int) -> int:
     """OpenMP threads of the oracle's splat loops (n > 0 sets); returns the
     count in use."""
@@ -203,12 +216,14 @@ _VM_DT = {"lod": np.float32, "pf_keys": np.uint64, "pf_x": np.float32, "pf_count
 class OracleScene:
     """Create-time data built by the oracle (Morton pages, proxy, links, LOD)."""
 
-    def __init__(self, scene, page_size, lod_levels=1, cell_m=0.5, link_sigma=2.0, attr_format=0, lod_scale_up=1.0):
+    def __init__(self, scene, page_size, lod_levels=1, cell_m=0.5, link_sigma=2.0, attr_format=0, lod_scale_up=1.0,
+                 lod_builder=0):
         self._keep = [np.ascontiguousarray(a, dtype=np.float32) for a in
                       (scene.means, scene.scales, scene.quats, scene.opacity, scene.sh)]
         s = _Scene(scene.n, *[a.ctypes.data for a in self._keep])
         self.ptr = lib().or_scene_build(C.byref(s), int(page_size), int(lod_levels), float(cell_m),
-                                        float(link_sigma), int(attr_format), float(lod_scale_up))
+                                        float(link_sigma), int(attr_format), float(lod_scale_up),
+                                        int(lod_builder))
         if not self.ptr:
             raise ValueError("oracle: invalid scene parameters")
         self.page_size = page_size

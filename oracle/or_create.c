@@ -310,6 +310,138 @@ void or_merge_children(const float* c, int k, double scale_up, float* out)
     for (int a = 0; a < OR_REC; a++) out[a] = (float)d[a];
 }
 
+/* ---- k-means parents (Sec. 3 "Level of Detail", the paper's builder) -----
+ * The section clusters the Gaussians of a page by their attributes with
+ * k-means, attributes scaled so that position dominates, and merges each
+ * cluster by the arithmetic mean of position, rotation, opacity and SH, the
+ * merged scale raised by a fixed factor.  Readings taken here:
+ *  - members: the records of the level below with opacity > 0, in their
+ *    (Morton) order; k = the level's Gaussians per page;
+ *  - features (double): position minus the members' mean, divided by their
+ *    RMS distance from it (1 when 0); and, times KM_W = 1/4, the quaternion
+ *    in its w >= 0 form, the base colour (C0 times the DC coefficients) and
+ *    the opacity;
+ *  - seeds: the members at positions floor((2i + 1) m / (2k)), i < k; with
+ *    m <= k members every member is a cluster of its own;
+ *  - Lloyd iterations: each member to its nearest centroid (squared
+ *    Euclidean distance, ties to the lower cluster), centroids to the mean
+ *    of their members (an empty cluster keeps its centroid), until no
+ *    assignment changes, at most KM_ITERS;
+ *  - merge: the means of position, opacity and SH; the mean of the
+ *    quaternions, each signed to agree with the cluster's first member,
+ *    normalised ((1, 0, 0, 0) if it vanishes) and put in w >= 0 form; the
+ *    mean of the scales times scale_up.  An empty cluster gives an all-zero
+ *    (padding) parent. */
+#define KM_ITERS 16
+#define KM_DIM 11
+static const double KM_W = 0.25;
+static const double KM_C0 = 0.28209479177387814;   /* 1 / (2 sqrt(pi)) */
+
+static double km_dist(const double* f, const double* c)
+{
+    double d = 0.0;
+    for (int a = 0; a < KM_DIM; a++) { double e = f[a] - c[a]; d += e * e; }
+    return d;
+}
+
+int or_kmeans_page(const float* c, int n, int k, double scale_up, float* out, int32_t* assign)
+{
+    memset(out, 0, sizeof(float) * OR_REC * (size_t)k);
+    if (assign) for (int j = 0; j < n; j++) assign[j] = -1;
+    int32_t* idx = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int m = 0;
+    for (int j = 0; j < n; j++) if (c[j * OR_REC + 10] > 0.0f) idx[m++] = j;
+    int32_t* as = malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int iters = 0;
+    if (m <= k) {
+        for (int j = 0; j < m; j++) as[j] = j;
+    } else {
+        double c0[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j < m; j++) for (int a = 0; a < 3; a++) c0[a] += c[idx[j] * OR_REC + a];
+        for (int a = 0; a < 3; a++) c0[a] /= m;
+        double ss = 0.0;
+        for (int j = 0; j < m; j++)
+            for (int a = 0; a < 3; a++) { double d = c[idx[j] * OR_REC + a] - c0[a]; ss += d * d; }
+        double rms = sqrt(ss / m);
+        double inv = rms > 0.0 ? 1.0 / rms : 1.0;
+        double* F = malloc(sizeof(double) * KM_DIM * (size_t)m);
+        for (int j = 0; j < m; j++) {
+            const float* g = c + idx[j] * OR_REC;
+            double* f = F + (size_t)j * KM_DIM;
+            double sg = g[6] < 0.0f ? -1.0 : 1.0;
+            for (int a = 0; a < 3; a++) f[a] = ((double)g[a] - c0[a]) * inv;
+            for (int a = 0; a < 4; a++) f[3 + a] = KM_W * (sg * (double)g[6 + a]);
+            for (int a = 0; a < 3; a++) f[7 + a] = KM_W * (KM_C0 * (double)g[11 + a]);
+            f[10] = KM_W * (double)g[10];
+        }
+        double* C = malloc(sizeof(double) * KM_DIM * (size_t)k);
+        double* S = malloc(sizeof(double) * KM_DIM * (size_t)k);
+        int64_t* cnt = malloc(sizeof(int64_t) * (size_t)k);
+        for (int i = 0; i < k; i++) {
+            int sd = (int)(((int64_t)(2 * i + 1) * m) / (2 * (int64_t)k));
+            memcpy(C + (size_t)i * KM_DIM, F + (size_t)sd * KM_DIM, sizeof(double) * KM_DIM);
+        }
+        for (int j = 0; j < m; j++) as[j] = -1;
+        for (int it = 0; it < KM_ITERS; it++) {
+            int changed = 0;
+            for (int j = 0; j < m; j++) {
+                const double* f = F + (size_t)j * KM_DIM;
+                int best = 0;
+                double bd = km_dist(f, C);
+                for (int i = 1; i < k; i++) {
+                    double d = km_dist(f, C + (size_t)i * KM_DIM);
+                    if (d < bd) { bd = d; best = i; }
+                }
+                if (as[j] != best) { as[j] = best; changed = 1; }
+            }
+            iters = it + 1;
+            if (!changed) break;
+            memset(S, 0, sizeof(double) * KM_DIM * (size_t)k);
+            memset(cnt, 0, sizeof(int64_t) * (size_t)k);
+            for (int j = 0; j < m; j++) {
+                cnt[as[j]]++;
+                for (int a = 0; a < KM_DIM; a++) S[(size_t)as[j] * KM_DIM + a] += F[(size_t)j * KM_DIM + a];
+            }
+            for (int i = 0; i < k; i++)
+                if (cnt[i] > 0)
+                    for (int a = 0; a < KM_DIM; a++) C[(size_t)i * KM_DIM + a] = S[(size_t)i * KM_DIM + a] / cnt[i];
+        }
+        free(F); free(C); free(S); free(cnt);
+    }
+    /* merge every cluster (members in their order) */
+    for (int i = 0; i < k; i++) {
+        double acc[OR_REC];
+        for (int a = 0; a < OR_REC; a++) acc[a] = 0.0;
+        int cn = 0, first = -1;
+        for (int j = 0; j < m; j++) {
+            if (as[j] != i) continue;
+            const float* g = c + idx[j] * OR_REC;
+            if (first < 0) first = idx[j];
+            const float* q0 = c + first * OR_REC + 6;
+            double dot = (double)g[6] * q0[0] + (double)g[7] * q0[1] + (double)g[8] * q0[2] + (double)g[9] * q0[3];
+            double sg = dot < 0.0 ? -1.0 : 1.0;
+            for (int a = 0; a < 6; a++) acc[a] += g[a];
+            for (int a = 6; a < 10; a++) acc[a] += sg * (double)g[a];
+            for (int a = 10; a < OR_REC; a++) acc[a] += g[a];
+            cn++;
+        }
+        if (cn == 0) continue;
+        float* o = out + (size_t)i * OR_REC;
+        for (int a = 0; a < 3; a++) o[a] = (float)(acc[a] / cn);
+        for (int a = 3; a < 6; a++) o[a] = (float)(scale_up * (acc[a] / cn));
+        double qn = sqrt(((acc[6] * acc[6] + acc[7] * acc[7]) + acc[8] * acc[8]) + acc[9] * acc[9]);
+        double q[4] = {1.0, 0.0, 0.0, 0.0};
+        if (qn > 0.0) for (int a = 0; a < 4; a++) q[a] = acc[6 + a] / qn;
+        if (q[0] < 0.0) for (int a = 0; a < 4; a++) q[a] = -q[a];
+        for (int a = 0; a < 4; a++) o[6 + a] = (float)q[a];
+        for (int a = 10; a < OR_REC; a++) o[a] = (float)(acc[a] / cn);
+    }
+    if (assign) for (int j = 0; j < m; j++) assign[idx[j]] = as[j];
+    free(as);
+    free(idx);
+    return iters;
+}
+
 static void round_half_form(float* rec)
 {
     for (int a = 3; a < 11; a++) rec[a] = or_round_f16(rec[a]);
@@ -318,9 +450,10 @@ static void round_half_form(float* rec)
 
 /* ------------------------------------------------------------------------ */
 or_scene* or_scene_build(const or_scene_in* in, int P, int L, double cell_m, double link_sigma, int attr_format,
-                         float lod_scale_up)
+                         float lod_scale_up, int lod_builder)
 {
-    if (!in || in->n <= 0 || P <= 0 || L < 1 || L > 3 || cell_m <= 0.0) return NULL;
+    if (!in || in->n <= 0 || P <= 0 || L < 1 || L > 3 || cell_m <= 0.0 || lod_builder < 0 || lod_builder > 1)
+        return NULL;
     for (int l = 1; l < L; l++) if ((P >> (3 * l)) << (3 * l) != P || (P >> (3 * l)) == 0) return NULL;
     or_scene* s = calloc(1, sizeof(or_scene));
     int64_t n = in->n;
@@ -385,8 +518,15 @@ or_scene* or_scene_build(const or_scene_in* in, int P, int L, double cell_m, dou
     for (int l = 1; l < L; l++) {
         int64_t cnt = (int64_t)s->n_pg * (P >> (3 * l));
         s->attr[l] = calloc((size_t)cnt * OR_REC, sizeof(float));
-        for (int64_t i = 0; i < cnt; i++)
-            or_merge_children(s->attr[l - 1] + (8 * i) * OR_REC, 8, lod_scale_up, s->attr[l] + i * OR_REC);
+        if (lod_builder == 1) {
+            int pl = P >> (3 * l), pb = P >> (3 * (l - 1));
+            for (int p = 0; p < s->n_pg; p++)
+                or_kmeans_page(s->attr[l - 1] + (int64_t)p * pb * OR_REC, pb, pl, lod_scale_up,
+                               s->attr[l] + (int64_t)p * pl * OR_REC, NULL);
+        } else {
+            for (int64_t i = 0; i < cnt; i++)
+                or_merge_children(s->attr[l - 1] + (8 * i) * OR_REC, 8, lod_scale_up, s->attr[l] + i * OR_REC);
+        }
     }
 
     /* proxy boxes: occupied cells of the means */

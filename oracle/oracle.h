@@ -47,8 +47,10 @@ float or_vm_exp(float x);
 double or_sh_basis(int k, double x, double y, double z);
 
 /* ---- create time (Sec. 3) ---- */
+/* lod_builder: 0 = parents of 8 consecutive children by moment matching,
+ * 1 = the section's k-means clustering within the page (or_kmeans_page) */
 or_scene* or_scene_build(const or_scene_in* in, int page_size, int lod_levels,
-                         double cell_m, double link_sigma, int attr_format, float lod_scale_up);
+                         double cell_m, double link_sigma, int attr_format, float lod_scale_up, int lod_builder);
 void or_scene_free(or_scene* s);
 int64_t or_scene_get(const or_scene* s, const char* name, void* dst, int64_t cap);
 
@@ -58,6 +60,12 @@ int64_t or_scene_get(const or_scene* s, const char* name, void* dst, int64_t cap
  * alone): out[59] in double, and the stored float record. */
 void or_merge_children_d(const float* children, int k, double scale_up, double* out);
 void or_merge_children(const float* children, int k, double scale_up, float* out);
+
+/* The k parents of one page's level from its n records c (Sec. 3 "Level of
+ * Detail": k-means on scaled attributes, arithmetic means, a fixed scale-up).
+ * out: k records; assign (nullable): the cluster of each record, -1 for
+ * padding.  Returns the Lloyd iterations run (KM_ITERS = 16 at most). */
+int or_kmeans_page(const float* c, int n, int k, double scale_up, float* out, int32_t* assign);
 
 /* ---- per frame (Sec. 4) ---- */
 /* guard_px: the page-ID buffer and the frustum extend this many pixels past

@@ -348,3 +348,118 @@ def test_lod_controller_ignores_budget_deferrals():
             assert missing > 0
     for budget in (0, 2):
         assert taus[budget][0] <= 32.0 and np.all(np.diff(taus[budget]) <= 0), (budget, taus[budget])
+
+
+# ---- the k-means builder (Sec. 3 "Level of Detail") ------------------------
+def _records(rng, n, spread=1.0):
+    r = np.zeros((n, 59), np.float32)
+    r[:, 0:3] = rng.normal(0.0, spread, (n, 3))
+    r[:, 3:6] = rng.uniform(0.01, 0.1, (n, 3))
+    q = rng.normal(size=(n, 4))
+    r[:, 6:10] = q / np.linalg.norm(q, axis=1, keepdims=True)
+    r[:, 10] = rng.uniform(0.05, 1.0, n)
+    r[:, 11:] = rng.normal(0.0, 0.3, (n, 48))
+    return r
+
+
+def _cluster_mean(r, members, scale_up):
+    """Arithmetic means of a cluster, written from the section's merge rule."""
+    g = r[members].astype(np.float64)
+    q0 = g[0, 6:10]
+    sg = np.where(g[:, 6:10] @ q0 < 0.0, -1.0, 1.0)
+    q = (g[:, 6:10] * sg[:, None]).mean(0)
+    q /= np.linalg.norm(q)
+    q *= -1.0 if q[0] < 0 else 1.0
+    out = np.zeros(59)
+    out[0:3] = g[:, 0:3].mean(0)
+    out[3:6] = scale_up * g[:, 3:6].mean(0)
+    out[6:10] = q
+    out[10:] = g[:, 10:].mean(0)
+    return out
+
+
+def test_kmeans_identical_children():
+    """Sixty-four identical records: one cluster holds them all (every
+    distance ties, and ties go to the lower cluster), its parent is the
+    record with its scales times the factor; the other parents are padding."""
+    rng = np.random.default_rng(1)
+    r = np.repeat(_records(rng, 1), 64, axis=0)
+    p, a, _ = oracle.kmeans_page(r, 8, 1.5)
+    assert np.all(a == 0)
+    want = r[0].astype(np.float64).copy()
+    want[3:6] *= 1.5
+    want[6:10] *= -1.0 if want[6] < 0 else 1.0   # parents in w >= 0 form
+    np.testing.assert_allclose(p[0], want, rtol=1e-6, atol=1e-7)
+    assert np.all(p[1:] == 0.0)
+
+
+def test_kmeans_separated_groups():
+    """Eight tight groups of eight, far apart and listed group by group (as a
+    Morton order lists them): the seeds fall one per group, the clusters are
+    the groups, and each parent is its group's arithmetic mean (position,
+    opacity, SH; sign-aligned normalised quaternion; scale times the factor)."""
+    rng = np.random.default_rng(2)
+    r = _records(rng, 64, spread=0.05)
+    for gi in range(8):
+        r[8 * gi:8 * gi + 8, 0] += 10.0 * gi
+    p, a, it = oracle.kmeans_page(r, 8, 2.0)
+    assert np.array_equal(a, np.repeat(np.arange(8), 8)) and it <= 2
+    for gi in range(8):
+        np.testing.assert_allclose(p[gi], _cluster_mean(r, np.arange(8 * gi, 8 * gi + 8), 2.0), rtol=2e-6, atol=2e-7)
+
+
+def test_kmeans_lloyd_fixed_point():
+    """A random page of 512 records (12 of them padding) into 64 clusters:
+    after convergence every member sits in the cluster whose centroid (the
+    mean of its members' features, computed here from the feature definition)
+    is nearest, ties to the lower index, and every parent is its cluster's
+    arithmetic mean; padding records belong to no cluster."""
+    rng = np.random.default_rng(3)
+    r = _records(rng, 512, spread=3.0)
+    r[500:] = 0.0
+    p, a, it = oracle.kmeans_page(r, 64, 1.0)
+    assert it < 16
+    assert np.all(a[500:] == -1) and np.all(a[:500] >= 0)
+    g = r[:500].astype(np.float64)
+    c0 = g[:, 0:3].mean(0)
+    rms = np.sqrt(((g[:, 0:3] - c0) ** 2).sum() / 500)
+    sg = np.where(g[:, 6] < 0, -1.0, 1.0)
+    F = np.concatenate([(g[:, 0:3] - c0) / rms, 0.25 * sg[:, None] * g[:, 6:10],
+                        0.25 * 0.28209479177387814 * g[:, 11:14], 0.25 * g[:, 10:11]], axis=1)
+    used = np.unique(a[:500])
+    C = np.stack([F[a[:500] == i].mean(0) for i in used])
+    d = ((F[:, None, :] - C[None, :, :]) ** 2).sum(-1)
+    nearest = used[np.argmin(d, axis=1)]
+    assert np.array_equal(nearest, a[:500])
+    for i in range(64):
+        m = np.nonzero(a == i)[0]
+        if m.size:
+            np.testing.assert_allclose(p[i], _cluster_mean(r, m, 1.0), rtol=2e-6, atol=2e-7)
+        else:
+            assert np.all(p[i] == 0.0)
+
+
+def test_kmeans_few_members():
+    """No more members than clusters: every member is a parent of its own
+    (scales times the factor), the rest padding."""
+    rng = np.random.default_rng(4)
+    r = _records(rng, 16)
+    r[5:] = 0.0
+    p, a, _ = oracle.kmeans_page(r, 8, 1.25)
+    assert np.array_equal(a[:5], np.arange(5)) and np.all(a[5:] == -1)
+    for i in range(5):
+        np.testing.assert_allclose(p[i], _cluster_mean(r, [i], 1.25), rtol=2e-6, atol=2e-7)
+    assert np.all(p[5:] == 0.0)
+
+
+def test_kmeans_scene_levels():
+    """The scene builder's k-means levels: level l of page p is the k-means
+    of page p's level l-1 into P/8^l parents."""
+    sc = synth.scene_clusters(0, n_clusters=2, per_cluster=1024)
+    osc = oracle.OracleScene(sc, 256, 3, 0.5, 2.0, lod_scale_up=1.5, lod_builder=1)
+    a0, a1, a2 = (osc.get(f"attr{l}").reshape(-1, 59) for l in range(3))
+    for pg in (0, 3, 7):
+        p1, _, _ = oracle.kmeans_page(a0[pg * 256:(pg + 1) * 256], 32, 1.5)
+        assert np.array_equal(p1.view(np.uint32), a1[pg * 32:(pg + 1) * 32].view(np.uint32))
+        p2, _, _ = oracle.kmeans_page(a1[pg * 32:(pg + 1) * 32], 4, 1.5)
+        assert np.array_equal(p2.view(np.uint32), a2[pg * 4:(pg + 1) * 4].view(np.uint32))
