@@ -100,9 +100,13 @@ typedef struct {
     void* stream_render;          /* hipStream_t for the frame's kernels, NULL = library-owned stream */
     void* stream_copy;            /* hipStream_t for page copies, NULL = library-owned stream */
     uint64_t pair_capacity;       /* initial (tile, Gaussian) pair capacity; grows on demand; 0 = automatic */
-    float lod_scale_up;           /* LOD parents: moment-matched scales times this factor (Sec. 3 Level of
-                                     Detail: merged Gaussians are scaled up by a fixed factor to fill gaps);
-                                     1 = moment matching alone; in (0, 16] */
+    float lod_scale_up;           /* LOD parents: merged scales times this factor (Sec. 3 Level of Detail:
+                                     merged Gaussians are scaled up by a fixed factor to fill gaps); in (0, 16] */
+    uint32_t lod_builder;         /* LOD parents (Sec. 3 Level of Detail): 0 = opacity-weighted moment matching
+                                     of 8 consecutive Morton children (default); 1 = the section's k-means
+                                     clustering of each page on scaled attributes (position first), parents
+                                     the clusters' arithmetic means, scales the mean times lod_scale_up.
+                                     Other values: VM3DGS_E_INVALID_ARG */
 } vm3dgs_options;
 
 /* Fill *o with defaults: 1920x1080 image, 240x135 ID buffer with a 32 px

@@ -43,7 +43,8 @@ class vm3dgs_options(C.Structure):
                 ("max_views", C.c_uint32), ("attr_format", C.c_uint32), ("copy_budget_pages", C.c_uint32),
                 ("idbuf_guard_px", C.c_float), ("proxy_cell_m", C.c_float), ("link_sigma", C.c_float),
                 ("lod_radius_px", C.c_float), ("flags", C.c_uint32), ("stream_render", C.c_void_p),
-                ("stream_copy", C.c_void_p), ("pair_capacity", C.c_uint64), ("lod_scale_up", C.c_float)]
+                ("stream_copy", C.c_void_p), ("pair_capacity", C.c_uint64), ("lod_scale_up", C.c_float),
+                ("lod_builder", C.c_uint32)]
 
 
 class vm3dgs_camera(C.Structure):
@@ -289,7 +290,8 @@ class Renderer:
 
     def __init__(self, scene, page_size, pool_pages, lod_levels=1, img=(1920, 1080), idbuf=(240, 135),
                  max_views=1, attr_format=0, cell=1.0, link_sigma=2.0, lod_radius_px=32.0, links=True,
-                 full_scene=False, copy_budget=0, pair_capacity=0, guard_px=32.0, lod_scale_up=1.0):
+                 full_scene=False, copy_budget=0, pair_capacity=0, guard_px=32.0, lod_scale_up=1.0,
+                 lod_builder=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Renderer needs a HIP device")
@@ -304,6 +306,7 @@ class Renderer:
         o.flags = (VM3DGS_FLAG_LINKS if links else 0) | (VM3DGS_FLAG_FULL_SCENE_COPY if full_scene else 0)
         o.pair_capacity = pair_capacity
         o.lod_scale_up = lod_scale_up
+        o.lod_builder = lod_builder
         self.opts = o
         self.W, self.H = img
         self.h = vm3dgs_create(scene, page_size, pool_pages, lod_levels, o)

@@ -538,6 +538,7 @@ void vm3dgs_options_default(vm3dgs_options* o) {
     o->proxy_cell_m = 1.0f; o->link_sigma = 2.0f; o->lod_radius_px = 32.0f; o->idbuf_guard_px = 32.0f;
     o->flags = VM3DGS_FLAG_LINKS;
     o->lod_scale_up = 1.0f;
+    o->lod_builder = 0;
 }
 
 const char* vm3dgs_create_error(void) { return g_create_error.c_str(); }
@@ -565,6 +566,7 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         !(o.idbuf_guard_px >= 0.0f && o.idbuf_guard_px <= 4096.0f))
         return inval("proxy_cell_m, link_sigma, lod_radius_px out of range");
     if (!(o.lod_scale_up > 0.0f && o.lod_scale_up <= 16.0f)) return inval("lod_scale_up must be in (0, 16]");
+    if (o.lod_builder > 1) return inval("lod_builder must be 0 or 1");
     if (scene->n > (uint64_t)INT32_MAX * page_size) return inval("scene too large");
 
     vm3dgs* c = new (std::nothrow) vm3dgs();
@@ -572,7 +574,8 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
     c->opt = o;
     try {
         std::string e = build_paged_scene(*scene, (int)page_size, (int)lod_levels, (int)o.attr_format,
-                                          (double)o.proxy_cell_m, (double)o.link_sigma, (double)o.lod_scale_up, c->ps);
+                                          (double)o.proxy_cell_m, (double)o.link_sigma, (double)o.lod_scale_up,
+                                          (int)o.lod_builder, c->ps);
         if (!e.empty()) { g_create_error = e; delete c; return VM3DGS_E_INVALID_ARG; }
     } catch (const std::bad_alloc&) {
         g_create_error = "host allocation failed";
@@ -1128,8 +1131,8 @@ vm3dgs_status vm3dgs_pages_build(const vm3dgs_scene* scene, uint32_t page_size, 
         return VM3DGS_E_INVALID_ARG;
     }
     if (page_size == 0 || lod_levels < 1 || lod_levels > 3 || o.attr_format > 1 || !(o.proxy_cell_m > 0.0f) ||
-        !(o.lod_scale_up > 0.0f && o.lod_scale_up <= 16.0f)) {
-        g_create_error = "page_size, lod_levels, attr_format, proxy_cell_m or lod_scale_up out of range";
+        !(o.lod_scale_up > 0.0f && o.lod_scale_up <= 16.0f) || o.lod_builder > 1) {
+        g_create_error = "page_size, lod_levels, attr_format, proxy_cell_m, lod_scale_up or lod_builder out of range";
         return VM3DGS_E_INVALID_ARG;
     }
     for (uint32_t l = 1; l < lod_levels; ++l)
@@ -1141,7 +1144,8 @@ vm3dgs_status vm3dgs_pages_build(const vm3dgs_scene* scene, uint32_t page_size, 
     if (!p) return VM3DGS_E_HOST_OOM;
     try {
         std::string e = build_paged_scene(*scene, (int)page_size, (int)lod_levels, (int)o.attr_format,
-                                          (double)o.proxy_cell_m, (double)o.link_sigma, (double)o.lod_scale_up, p->ps);
+                                          (double)o.proxy_cell_m, (double)o.link_sigma, (double)o.lod_scale_up,
+                                          (int)o.lod_builder, p->ps);
         if (!e.empty()) { g_create_error = e; delete p; return VM3DGS_E_INVALID_ARG; }
         p->store.resize((size_t)p->ps.store_bytes);
         encode_store(p->ps, p->store.data());

@@ -31,11 +31,11 @@ namespace vm {
 namespace {
 
 template <class F>
-void parallel_for(int64_t n, F f) {
+void parallel_for(int64_t n, F f, int64_t serial_below = 65536) {
     unsigned nt = std::thread::hardware_concurrency();
     if (nt == 0) nt = 1;
     if (nt > 16) nt = 16;
-    if (n < 65536 || nt == 1) {
+    if (n < serial_below || nt == 1) {
         f((int64_t)0, n);
         return;
     }
@@ -247,6 +247,130 @@ void merge(const float* ch, int k, double scale_up, float* out) {
     }
 }
 
+// k-means parents of one page's level (Sec. 3 Level of Detail): the n
+// records c of the level below go into k clusters, found by Lloyd's
+// algorithm on scaled attributes, and each cluster becomes one parent.
+//  - members: records with opacity > 0, in order; m <= k: one cluster each;
+//  - features (double): position minus the members' mean over their RMS
+//    distance from it (1 when 0); times 1/4 each: the quaternion in w >= 0
+//    form, the base colour C0 * DC, the opacity;
+//  - seeds: members floor((2i + 1) m / (2k)); at most 16 iterations of
+//    nearest centroid (squared distance, ties to the lower cluster) and
+//    centroid = mean of its members (empty clusters keep theirs), stopping
+//    when no member moves;
+//  - parent: means of position, opacity and SH; the quaternions' mean, each
+//    signed to agree with the cluster's first member, normalised
+//    ((1, 0, 0, 0) if it vanishes), w >= 0; the scales' mean times scale_up.
+//    An empty cluster gives an all-zero parent.
+constexpr int KM_ITERS = 16, KM_DIM = 11;
+constexpr double KM_W = 0.25, KM_C0 = 0.28209479177387814;
+
+void kmeans_page(const float* c, int n, int k, double scale_up, float* out) {
+    std::fill(out, out + (size_t)k * REC, 0.0f);
+    std::vector<int> mem;
+    mem.reserve((size_t)n);
+    for (int j = 0; j < n; ++j)
+        if (c[(size_t)j * REC + 10] > 0.0f) mem.push_back(j);
+    const int m = (int)mem.size();
+    std::vector<int> cl((size_t)m, -1);
+    if (m <= k) {
+        for (int j = 0; j < m; ++j) cl[(size_t)j] = j;
+    } else {
+        double mean[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j < m; ++j)
+            for (int a = 0; a < 3; ++a) mean[a] += c[(size_t)mem[(size_t)j] * REC + a];
+        for (int a = 0; a < 3; ++a) mean[a] /= m;
+        double ss = 0.0;
+        for (int j = 0; j < m; ++j)
+            for (int a = 0; a < 3; ++a) {
+                const double d = c[(size_t)mem[(size_t)j] * REC + a] - mean[a];
+                ss += d * d;
+            }
+        const double rms = sqrt(ss / m);
+        const double inv = rms > 0.0 ? 1.0 / rms : 1.0;
+        std::vector<double> F((size_t)m * KM_DIM), C((size_t)k * KM_DIM), S((size_t)k * KM_DIM);
+        std::vector<int64_t> cnt((size_t)k);
+        for (int j = 0; j < m; ++j) {
+            const float* g = c + (size_t)mem[(size_t)j] * REC;
+            double* f = &F[(size_t)j * KM_DIM];
+            const double sg = g[6] < 0.0f ? -1.0 : 1.0;
+            for (int a = 0; a < 3; ++a) f[a] = ((double)g[a] - mean[a]) * inv;
+            for (int a = 0; a < 4; ++a) f[3 + a] = KM_W * (sg * (double)g[6 + a]);
+            for (int a = 0; a < 3; ++a) f[7 + a] = KM_W * (KM_C0 * (double)g[11 + a]);
+            f[10] = KM_W * (double)g[10];
+        }
+        for (int i = 0; i < k; ++i) {
+            const int seed = (int)(((int64_t)(2 * i + 1) * m) / (2 * (int64_t)k));
+            std::copy(&F[(size_t)seed * KM_DIM], &F[(size_t)seed * KM_DIM] + KM_DIM, &C[(size_t)i * KM_DIM]);
+        }
+        auto dist = [&](const double* f, const double* ctr) {
+            double d = 0.0;
+            for (int a = 0; a < KM_DIM; ++a) {
+                const double e = f[a] - ctr[a];
+                d += e * e;
+            }
+            return d;
+        };
+        for (int it = 0; it < KM_ITERS; ++it) {
+            bool moved = false;
+            for (int j = 0; j < m; ++j) {
+                const double* f = &F[(size_t)j * KM_DIM];
+                int best = 0;
+                double bd = dist(f, &C[0]);
+                for (int i = 1; i < k; ++i) {
+                    const double d = dist(f, &C[(size_t)i * KM_DIM]);
+                    if (d < bd) { bd = d; best = i; }
+                }
+                if (cl[(size_t)j] != best) { cl[(size_t)j] = best; moved = true; }
+            }
+            if (!moved) break;
+            std::fill(S.begin(), S.end(), 0.0);
+            std::fill(cnt.begin(), cnt.end(), 0);
+            for (int j = 0; j < m; ++j) {
+                const int i = cl[(size_t)j];
+                ++cnt[(size_t)i];
+                for (int a = 0; a < KM_DIM; ++a) S[(size_t)i * KM_DIM + a] += F[(size_t)j * KM_DIM + a];
+            }
+            for (int i = 0; i < k; ++i)
+                if (cnt[(size_t)i] > 0)
+                    for (int a = 0; a < KM_DIM; ++a)
+                        C[(size_t)i * KM_DIM + a] = S[(size_t)i * KM_DIM + a] / cnt[(size_t)i];
+        }
+    }
+    // members of each cluster in order; accumulate in double
+    std::vector<double> acc((size_t)k * REC, 0.0);
+    std::vector<int> n_in((size_t)k, 0), first((size_t)k, -1);
+    for (int j = 0; j < m; ++j) {
+        const int i = cl[(size_t)j];
+        const float* g = c + (size_t)mem[(size_t)j] * REC;
+        if (first[(size_t)i] < 0) first[(size_t)i] = mem[(size_t)j];
+        const float* q0 = c + (size_t)first[(size_t)i] * REC + 6;
+        const double dot = (double)g[6] * q0[0] + (double)g[7] * q0[1] + (double)g[8] * q0[2] + (double)g[9] * q0[3];
+        const double sg = dot < 0.0 ? -1.0 : 1.0;
+        double* A = &acc[(size_t)i * REC];
+        for (int a = 0; a < 6; ++a) A[a] += g[a];
+        for (int a = 6; a < 10; ++a) A[a] += sg * (double)g[a];
+        for (int a = 10; a < REC; ++a) A[a] += g[a];
+        ++n_in[(size_t)i];
+    }
+    for (int i = 0; i < k; ++i) {
+        const int cn = n_in[(size_t)i];
+        if (cn == 0) continue;
+        const double* A = &acc[(size_t)i * REC];
+        float* o = out + (size_t)i * REC;
+        for (int a = 0; a < 3; ++a) o[a] = (float)(A[a] / cn);
+        for (int a = 3; a < 6; ++a) o[a] = (float)(scale_up * (A[a] / cn));
+        const double qn = sqrt(((A[6] * A[6] + A[7] * A[7]) + A[8] * A[8]) + A[9] * A[9]);
+        double q[4] = {1.0, 0.0, 0.0, 0.0};
+        if (qn > 0.0)
+            for (int a = 0; a < 4; ++a) q[a] = A[6 + a] / qn;
+        if (q[0] < 0.0)
+            for (int a = 0; a < 4; ++a) q[a] = -q[a];
+        for (int a = 0; a < 4; ++a) o[6 + a] = (float)q[a];
+        for (int a = 10; a < REC; ++a) o[a] = (float)(A[a] / cn);
+    }
+}
+
 // IEEE round to nearest even, bit-level: float -> binary16 / bfloat16
 inline uint16_t f32_to_f16(float f) {
     uint32_t x;
@@ -313,7 +437,7 @@ inline float bf16_to_f32(uint16_t b) {
 }  // namespace
 
 std::string build_paged_scene(const vm3dgs_scene& sc, int P, int L, int fmt, double cell_m, double link_sigma,
-                              double lod_scale_up, PagedScene& ps) {
+                              double lod_scale_up, int lod_builder, PagedScene& ps) {
     const int64_t n = (int64_t)sc.n;
     ps = PagedScene();
     ps.n_in = n; ps.P = P; ps.L = L; ps.fmt = fmt;
@@ -381,9 +505,21 @@ std::string build_paged_scene(const vm3dgs_scene& sc, int P, int L, int fmt, dou
         ps.rec[l].assign((size_t)cnt * REC, 0.0f);
         const float* src = ps.rec[l - 1].data();
         float* dst = ps.rec[l].data();
-        parallel_for(cnt, [&](int64_t a, int64_t b) {
-            for (int64_t i = a; i < b; ++i) merge(src + (size_t)(8 * i) * REC, 8, lod_scale_up, dst + (size_t)i * REC);
-        });
+        if (lod_builder == 1) {
+            const int pl = ps.P_l(l), pb = ps.P_l(l - 1);
+            parallel_for(
+                ps.n_pg,
+                [&](int64_t a, int64_t b) {
+                    for (int64_t p = a; p < b; ++p)
+                        kmeans_page(src + (size_t)(p * pb) * REC, pb, pl, lod_scale_up, dst + (size_t)(p * pl) * REC);
+                },
+                64);
+        } else {
+            parallel_for(cnt, [&](int64_t a, int64_t b) {
+                for (int64_t i = a; i < b; ++i)
+                    merge(src + (size_t)(8 * i) * REC, 8, lod_scale_up, dst + (size_t)i * REC);
+            });
+        }
     }
 
     // proxy: occupied cells of the means

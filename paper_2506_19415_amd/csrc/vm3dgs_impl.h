@@ -44,7 +44,7 @@ struct PagedScene {
 
 // Builds everything of Sec. 3 for the library; returns "" or an error text.
 std::string build_paged_scene(const vm3dgs_scene& sc, int page_size, int lod_levels, int fmt, double cell_m,
-                              double link_sigma, double lod_scale_up, PagedScene& out);
+                              double link_sigma, double lod_scale_up, int lod_builder, PagedScene& out);
 // Writes the page-major SoA store of every level into dst (store_bytes).
 void encode_store(const PagedScene& ps, uint8_t* dst);
 

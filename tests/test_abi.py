@@ -31,7 +31,7 @@ def test_struct_layout_matches_c_compiler(tmp_path):
     """The binding's structures have the sizes and field offsets the C compiler
     gives the header's structures."""
     import subprocess
-    fields = {"vm3dgs_options": ["img_w", "flags", "stream_render", "stream_copy", "pair_capacity", "lod_scale_up"],
+    fields = {"vm3dgs_options": ["img_w", "flags", "stream_render", "stream_copy", "pair_capacity", "lod_scale_up", "lod_builder"],
               "vm3dgs_camera": ["view", "cam_pos", "fx", "znear"],
               "vm3dgs_stats": ["candidates", "prefetched", "fallbacks", "render_gaussians", "blend_alphas", "ms_visibility",
                                "ms_total"],

@@ -9,18 +9,19 @@ import paper_2506_19415_amd as pkg
 from paper_2506_19415_amd import synth
 
 
-def _opts(cell, link_sigma=2.0, fmt=0, scale_up=1.0):
+def _opts(cell, link_sigma=2.0, fmt=0, scale_up=1.0, builder=0):
     o = pkg.vm3dgs_options_default()
     o.proxy_cell_m = cell
     o.link_sigma = link_sigma
     o.attr_format = fmt
     o.lod_scale_up = scale_up
+    o.lod_builder = builder
     return o
 
 
-def _both(sc, P, L, cell, fmt=0, link_sigma=2.0, scale_up=1.0):
-    h = pkg.vm3dgs_pages_build(sc, P, L, _opts(cell, link_sigma, fmt, scale_up))
-    osc = oracle.OracleScene(sc, P, L, cell, link_sigma, fmt, lod_scale_up=scale_up)
+def _both(sc, P, L, cell, fmt=0, link_sigma=2.0, scale_up=1.0, builder=0):
+    h = pkg.vm3dgs_pages_build(sc, P, L, _opts(cell, link_sigma, fmt, scale_up, builder))
+    osc = oracle.OracleScene(sc, P, L, cell, link_sigma, fmt, lod_scale_up=scale_up, lod_builder=builder)
     return h, osc
 
 
@@ -66,10 +67,12 @@ def test_terrain_paging_parity():
         pkg.vm3dgs_pages_destroy(h)
 
 
-@pytest.mark.parametrize("fmt,scale_up", [(0, 1.0), (1, 1.0), (0, 1.6)])
-def test_lod_and_half_form_parity(fmt, scale_up):
+@pytest.mark.parametrize("fmt,scale_up,builder", [(0, 1.0, 0), (1, 1.0, 0), (0, 1.6, 0), (0, 1.0, 1), (1, 2.0, 1)])
+def test_lod_and_half_form_parity(fmt, scale_up, builder):
+    """Both LOD builders (moment matching; the k-means of Sec. 3), both
+    storage forms."""
     sc = synth.scene_city(0, n=40000, size=120.0, block=40.0, street=8.0)
-    h, osc = _both(sc, 512, 3, 2.0, fmt=fmt, scale_up=scale_up)
+    h, osc = _both(sc, 512, 3, 2.0, fmt=fmt, scale_up=scale_up, builder=builder)
     try:
         _check_same(h, osc, 3)
     finally:
@@ -131,3 +134,9 @@ def test_store_layout_decodes_to_records(fmt):
             assert np.array_equal(dec[0][:, 11:], oracle.round_bf16_n(full[:, 11:]))
     finally:
         pkg.vm3dgs_pages_destroy(h)
+
+
+def test_unknown_lod_builder_rejected():
+    sc = synth.scene_clusters(0, n_clusters=1, per_cluster=512)
+    with pytest.raises(Exception):
+        pkg.vm3dgs_pages_build(sc, 256, 2, _opts(0.5, builder=2))
