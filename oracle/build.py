@@ -2,8 +2,9 @@
 
 Plain C99, -O2, no fast-math and no floating-point contraction, so every
 float operation is the IEEE operation written in the source.  OpenMP runs the
-independent per-Gaussian and per-tile loops of the splat on several threads
-(or_set_threads; the results do not depend on the count).
+independent per-Gaussian and per-tile loops of the splat and the per-page
+k-means of the LOD levels on several threads (or_set_threads; the results do
+not depend on the count).
 """
 import os
 import subprocess

@@ -520,6 +520,8 @@ or_scene* or_scene_build(const or_scene_in* in, int P, int L, double cell_m, dou
         s->attr[l] = calloc((size_t)cnt * OR_REC, sizeof(float));
         if (lod_builder == 1) {
             int pl = P >> (3 * l), pb = P >> (3 * (l - 1));
+            /* pages are independent: OpenMP over them changes no record */
+            #pragma omp parallel for schedule(dynamic, 16)
             for (int p = 0; p < s->n_pg; p++)
                 or_kmeans_page(s->attr[l - 1] + (int64_t)p * pb * OR_REC, pb, pl, lod_scale_up,
                                s->attr[l] + (int64_t)p * pl * OR_REC, NULL);

@@ -463,3 +463,19 @@ def test_kmeans_scene_levels():
         assert np.array_equal(p1.view(np.uint32), a1[pg * 32:(pg + 1) * 32].view(np.uint32))
         p2, _, _ = oracle.kmeans_page(a1[pg * 32:(pg + 1) * 32], 4, 1.5)
         assert np.array_equal(p2.view(np.uint32), a2[pg * 4:(pg + 1) * 4].view(np.uint32))
+
+
+def test_kmeans_levels_independent_of_threads():
+    """The k-means levels are built page by page on several threads; the
+    records do not depend on their number."""
+    sc = synth.scene_clusters(1, n_clusters=3, per_cluster=1024)
+    old = oracle.set_threads(0)
+    try:
+        got = []
+        for nt in (1, 4):
+            oracle.set_threads(nt)
+            osc = oracle.OracleScene(sc, 256, 3, 0.5, 2.0, lod_scale_up=2.5, lod_builder=1)
+            got.append([osc.get(f"attr{l}").view(np.uint32).copy() for l in (1, 2)])
+        assert all(np.array_equal(a, b) for a, b in zip(*got))
+    finally:
+        oracle.set_threads(old)
