@@ -68,6 +68,8 @@ CITY_LOD_SCALE_UP = 1.0
 CITY_TAU0_PX = 32.0
 # streaming runs (--stream): the paper's staging buffer of 40 pages per frame
 STAGING_PAGES = 40
+# LOD parent builders (vm3dgs_options.lod_builder)
+LOD_BUILDERS = {"moment": 0, "kmeans": 1}
 
 
 def log(*a):
@@ -207,10 +209,11 @@ def run_city_lod(args, pkg, synth):
     S = args.city_pool
     r = pkg.Renderer(sc, 1024, S, lod_levels=3, img=(W, H), idbuf=cfg["idbuf"], attr_format=cfg["fmt"],
                      cell=2.0, lod_radius_px=args.tau0, lod_scale_up=args.lod_scale_up, full_scene=not args.no_full,
-                     copy_budget=STAGING_PAGES if args.stream else 0)
+                     copy_budget=STAGING_PAGES if args.stream else 0, lod_builder=LOD_BUILDERS[args.lod_builder])
     flags = pkg.VM3DGS_FLAG_LINKS | pkg.VM3DGS_FLAG_ADAPTIVE_LOD | (pkg.VM3DGS_FLAG_ASYNC_MISSES if args.stream else 0)
     r.set_flags(flags)
-    log(f"VM context (L=3, pool {S}, format {cfg['fmt']}, scale-up {args.lod_scale_up}) {time.time() - t0:.1f} s")
+    log(f"VM context (L=3, pool {S}, format {cfg['fmt']}, {args.lod_builder} parents, scale-up {args.lod_scale_up}) "
+        f"{time.time() - t0:.1f} s")
     K, Wm = args.steps, args.warmup
 
     for i in range(Wm):
@@ -303,12 +306,13 @@ def run_city_lod(args, pkg, synth):
         "ms_per_step": elapsed * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": f"synthetic (seeded city, {sc.n} Gaussians, {args.city_color} colours)",
         "config": {"workload": f"{args.workload}: {sc.n} Gaussians over 1 x 1 km, 1024/page, 3 LOD levels "
-                               f"(1024/128/16, parents scaled up x{args.lod_scale_up}), pool {S} pages, "
+                               f"(1024/128/16, {args.lod_builder} parents scaled up x{args.lod_scale_up}), pool {S} pages, "
                                f"adaptive LOD from {args.tau0} px, 1920x1080, ID buffer {cfg['idbuf'][0]}x{cfg['idbuf'][1]}, 70 deg, "
                                f"frames {Wm}..{Wm + K - 1} of the 600-frame street-ascent-aerial path"
                                + (f", streaming (staging {STAGING_PAGES} pages)" if args.stream else ""),
                    "attr_format": "half" if cfg["fmt"] else "fp32", "page_size": 1024, "pool_pages": S,
-                   "lod_levels": 3, "lod_scale_up": args.lod_scale_up, "tau0_px": args.tau0,
+                   "lod_levels": 3, "lod_builder": args.lod_builder, "lod_scale_up": args.lod_scale_up,
+                   "tau0_px": args.tau0,
                    "image": [W, H], "idbuf": list(cfg["idbuf"]), "proxy_cell_m": 2.0, "streaming": args.stream},
         "fps_median_frame": 1000.0 / statistics.median(walls),
         "full_scene_fps": full_fps, "speedup_vs_full": (K / elapsed) / full_fps if full_fps else None,
@@ -342,7 +346,8 @@ def run_city_lod(args, pkg, synth):
             vm.set_async(args.stream)
             return vm
         res["cpu_baseline"] = cpu_baseline(
-            lambda: oracle.OracleScene(sc, 1024, 3, 2.0, 2.0, attr_format=cfg["fmt"], lod_scale_up=args.lod_scale_up),
+            lambda: oracle.OracleScene(sc, 1024, 3, 2.0, 2.0, attr_format=cfg["fmt"], lod_scale_up=args.lod_scale_up,
+                                       lod_builder=LOD_BUILDERS[args.lod_builder]),
             make_vm, cams[Wm:], args.workload)
     return res
 
@@ -514,6 +519,10 @@ def main():
                     help="city colours: smooth over the surfaces (default), independent per Gaussian, or white")
     ap.add_argument("--lod-scale-up", type=float, default=CITY_LOD_SCALE_UP,
                     help="city: factor on the moment-matched scales of the LOD parents")
+    ap.add_argument("--lod-builder", default="moment", choices=sorted(LOD_BUILDERS),
+                    help="city: LOD parents by moment matching of 8 Morton children (default) or by the k-means "
+                         "clustering of Sec. 3 (the oracle's build of it takes minutes at 50M: use with "
+                         "--no-cpu-baseline)")
     ap.add_argument("--tau0", type=float, default=CITY_TAU0_PX,
                     help="city: initial level-0 projected page radius (pixels) of the adaptive thresholds")
     ap.add_argument("--no-path", action="store_true", help="city: skip the per-phase pass over the whole path")

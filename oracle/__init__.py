@@ -159,7 +159,7 @@ def kmeans_page(records, k, scale_up=1.0):
 
 def set_threads(n: int) -> int:
     """OpenMP threads of the oracle's splat loops and k-means LOD levels (n > 0
-    count in use."""
+    sets); returns the count in use."""
     return int(lib().or_set_threads(int(n)))
 
 
