@@ -4,8 +4,9 @@
 Default workload (city50m_lod): 50,000,000 Gaussians of a 1 x 1 km city
 (street grid of 100 m blocks, 1-6 buildings per block, Gaussians on the
 ground, facades and roofs; colours that vary smoothly over the surfaces),
-pages of 1024, three LOD levels (1024 / 128 / 16 Gaussians per page; each
-parent moment-matches 8 children), a pool of
+pages of 1024, three LOD levels (1024 / 128 / 16 Gaussians per page; the
+parents of a page are the k-means clusters of its Gaussians, Sec. 3, their
+scales raised by a factor of 2.5), a pool of
 3,907 physical pages (4M Gaussians), LOD thresholds that follow memory use,
 480x270 page-ID buffer, 2 m proxy cells, 1920x1080, 70 degree horizontal field
 of view, the 600-frame path (street level, ascent to 150 m, aerial view
@@ -60,11 +61,13 @@ OPS_PER_EVAL = 25
 # building facades hide the buildings behind them (8 of the 300 frames under
 # 40 dB against the full render); with 0.5 m cells every frame is above 47 dB
 TERRAIN_CELL_M = 0.5
-# LOD parents of the city workloads: moment-matched scales times this factor
-# (1: moment matching alone; on the city path factors of 1.6 and 2 lowered the
-# PSNR of the LOD frames against the full render), and the initial level-0
-# radius of the threshold controller
-CITY_LOD_SCALE_UP = 1.0
+# LOD parents of the city workloads: the k-means builder of Sec. 3 with its
+# merged scales raised by 2.5 (on the city path the k-means parents with 2.5
+# keep the ascent and aerial frames 5 dB closer to the full render than
+# moment-matched parents, whose best factor is 1; 2 and 3 do worse than 2.5),
+# and the initial level-0 radius of the threshold controller
+CITY_LOD_BUILDER = "kmeans"
+CITY_LOD_SCALE_UP = {"kmeans": 2.5, "moment": 1.0}
 CITY_TAU0_PX = 32.0
 # streaming runs (--stream): the paper's staging buffer of 40 pages per frame
 STAGING_PAGES = 40
@@ -371,7 +374,8 @@ def run_city_prefetch(args, pkg, synth):
     frames = [[p[i] for p in paths] for i in range(600)]
     t0 = time.time()
     r = pkg.Renderer(sc, 1024, 3907, lod_levels=3, img=(W, H), idbuf=cfg["idbuf"], max_views=V,
-                     attr_format=cfg["fmt"], cell=2.0, lod_radius_px=args.tau0, lod_scale_up=args.lod_scale_up)
+                     attr_format=cfg["fmt"], cell=2.0, lod_radius_px=args.tau0, lod_scale_up=args.lod_scale_up,
+                     lod_builder=LOD_BUILDERS[args.lod_builder])
     log(f"VM context (L=3, pool 3907, format {cfg['fmt']}) {time.time() - t0:.1f} s")
     # LOD thresholds follow memory use (Sec. 4.1): the 4M-Gaussian pool cannot hold
     # every page at the 32 px radius near street level
@@ -395,7 +399,8 @@ def run_city_prefetch(args, pkg, synth):
         net.set_params(np.concatenate(params))
         # rows, labels and training in the library (vm3dgs_prefetch_train) on a one-view context
         r1 = pkg.Renderer(sc, 1024, 3907, lod_levels=3, img=(W, H), idbuf=cfg["idbuf"], max_views=1,
-                          attr_format=cfg["fmt"], cell=2.0, lod_radius_px=args.tau0, lod_scale_up=args.lod_scale_up)
+                          attr_format=cfg["fmt"], cell=2.0, lod_radius_px=args.tau0, lod_scale_up=args.lod_scale_up,
+                          lod_builder=LOD_BUILDERS[args.lod_builder])
         r1.set_flags(pkg.VM3DGS_FLAG_LINKS | pkg.VM3DGS_FLAG_ADAPTIVE_LOD)
         r1.set_prefetch(net, KC, HB, 0.0, 64, center, extent)
         tlog = r1.prefetch_train(train_paths, steps=args.train_steps, batch=256, lr=1e-3, seed=3,
@@ -459,7 +464,8 @@ def run_city_prefetch(args, pkg, synth):
         full_fps = nf / (time.perf_counter() - tf)
         # PSNR on every 10th timed frame: re-run the VM path to that frame
         rv = pkg.Renderer(sc, 1024, 3907, lod_levels=3, img=(W, H), idbuf=cfg["idbuf"], max_views=V,
-                          attr_format=cfg["fmt"], cell=2.0, lod_radius_px=args.tau0, lod_scale_up=args.lod_scale_up)
+                          attr_format=cfg["fmt"], cell=2.0, lod_radius_px=args.tau0, lod_scale_up=args.lod_scale_up,
+                          lod_builder=LOD_BUILDERS[args.lod_builder])
         rv.set_flags(pkg.VM3DGS_FLAG_LINKS | pkg.VM3DGS_FLAG_ADAPTIVE_LOD)
         if net is not None:
             rv.set_prefetch(net, 4096, 512, pf_report["logit_threshold"], 64, *pf.scene_frame(sc))
@@ -482,7 +488,8 @@ def run_city_prefetch(args, pkg, synth):
         "metric": METRIC, "value": K / elapsed, "unit": "frames/s", "n_gpus": 1, "steps": K, "warmup": Wm,
         "ms_per_step": elapsed * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": f"synthetic (seeded city, {sc.n} Gaussians)",
-        "config": {"workload": f"{args.workload}: {sc.n} Gaussians, 1024/page, 3 LOD levels, pool 3907 pages, "
+        "config": {"workload": f"{args.workload}: {sc.n} Gaussians, 1024/page, 3 LOD levels ({args.lod_builder} parents "
+                               f"scaled up x{args.lod_scale_up}), pool 3907 pages, "
                                f"{V} view(s) at {W}x{H}, 600-frame street-ascent-aerial path",
                    "attr_format": "half" if cfg["fmt"] else "fp32", "views": V},
         "fps_median_frame": 1000.0 / statistics.median(walls),
@@ -517,12 +524,12 @@ def main():
     ap.add_argument("--city-n", type=int, default=50_000_000, help="Gaussians of the city workloads")
     ap.add_argument("--city-color", default="smooth", choices=["smooth", "iid", "white"],
                     help="city colours: smooth over the surfaces (default), independent per Gaussian, or white")
-    ap.add_argument("--lod-scale-up", type=float, default=CITY_LOD_SCALE_UP,
-                    help="city: factor on the moment-matched scales of the LOD parents")
-    ap.add_argument("--lod-builder", default="moment", choices=sorted(LOD_BUILDERS),
-                    help="city: LOD parents by moment matching of 8 Morton children (default) or by the k-means "
-                         "clustering of Sec. 3 (the oracle's build of it takes minutes at 50M: use with "
-                         "--no-cpu-baseline)")
+    ap.add_argument("--lod-scale-up", type=float, default=None,
+                    help="city: factor on the merged scales of the LOD parents (default 2.5 for k-means, "
+                         "1 for moment matching)")
+    ap.add_argument("--lod-builder", default=CITY_LOD_BUILDER, choices=sorted(LOD_BUILDERS),
+                    help="city: LOD parents by the k-means clustering of Sec. 3 (default) or by moment matching "
+                         "of 8 Morton children")
     ap.add_argument("--tau0", type=float, default=CITY_TAU0_PX,
                     help="city: initial level-0 projected page radius (pixels) of the adaptive thresholds")
     ap.add_argument("--no-path", action="store_true", help="city: skip the per-phase pass over the whole path")
@@ -542,6 +549,8 @@ def main():
                     help="city50m_prefetch8: plain-pass frames of training data for the network")
     ap.add_argument("--train-steps", type=int, default=3000, help="city50m_prefetch8: Adam steps")
     args = ap.parse_args()
+    if args.lod_scale_up is None:
+        args.lod_scale_up = CITY_LOD_SCALE_UP[args.lod_builder]
     if args.print_source_hash:
         print(blend_source_hash())
         return
