@@ -398,16 +398,18 @@ def city():
     return sc, synth.path_city(sc, n_frames=30, width=480, height=270)
 
 
-@pytest.mark.parametrize("L,tau,S,budget,fmt", [(3, 128.0, 64, 0, 0), (3, 256.0, 48, 20, 1), (2, 128.0, 80, 0, 0)])
-def test_lod_city(city, L, tau, S, budget, fmt):
+@pytest.mark.parametrize("L,tau,S,budget,fmt,builder", [(3, 128.0, 64, 0, 0, 0), (3, 256.0, 48, 20, 1, 0),
+                                                         (2, 128.0, 80, 0, 0, 0), (3, 128.0, 64, 0, 0, 1)])
+def test_lod_city(city, L, tau, S, budget, fmt, builder):
     """Three (or two) LOD levels on a street-to-aerial city path: sub-slot
     reuse, pages converted between levels, evictions of whole physical pages,
-    missing pages under pool pressure and a copy budget; every intermediate
-    and the image against the oracle."""
+    missing pages under pool pressure and a copy budget; moment-matched and
+    k-means parents; every intermediate and the image against the oracle."""
     sc, cams = city
-    osc = oracle.OracleScene(sc, 512, L, 2.0, 2.0, attr_format=fmt)
+    osc = oracle.OracleScene(sc, 512, L, 2.0, 2.0, attr_format=fmt, lod_scale_up=2.5 if builder else 1.0,
+                             lod_builder=builder)
     r = _renderer(sc, 512, S, (480, 270), (120, 68), 2.0, lod_levels=L, lod_radius_px=tau,
-                  copy_budget=budget, attr_format=fmt)
+                  copy_budget=budget, attr_format=fmt, lod_scale_up=2.5 if builder else 1.0, lod_builder=builder)
     ovm = _ovm(osc, S, (480, 270), (120, 68), copy_budget=budget, lod_radius_px=tau)
     seen = np.zeros(L, np.int64)
     evictions = 0
