@@ -295,9 +295,9 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
 constexpr int TO_NT = 1024;
 
 // The blend's long tiles: tile-order classes from this one up (counts of
-// 2^10 or more).  order[n_tiles] receives their number (a prefix of the
+// 2^12 or more).  order[n_tiles] receives their number (a prefix of the
 // order).
-constexpr int BL_LONG_CLASS = 11;
+constexpr int BL_LONG_CLASS = 13;
 __global__ __launch_bounds__(TO_NT) void k_tile_order(const uint2* __restrict__ ranges, uint32_t n_tiles,
                                                       uint32_t* __restrict__ order) {
     __shared__ uint32_t cnt[33];
@@ -375,7 +375,7 @@ __global__ void k_ranges(const uint32_t* __restrict__ key, uint32_t cap, const u
 // stops), and the alpha evaluations (terms in the power range at pixels
 // still blending; the band walk counts those live when the chunk starts).
 constexpr int BL_NT = TILE * TILE;
-constexpr uint32_t BL_LONG = 1024;   // tiles with this many pairs take the band walk
+constexpr uint32_t BL_LONG = 4096;   // tiles with this many pairs take the band walk
 constexpr int BL_BANDS = 4;          // workgroups (16 x 4 bands) per long tile
 constexpr int BL_BAND_PX = TILE * TILE / BL_BANDS;
 constexpr int BL_CH = BL_NT;         // pairs per band-walk chunk, one per thread
