@@ -391,6 +391,81 @@ def test_terrain6m_full_size_sampled():
     r.close()
 
 
+@pytest.mark.slow
+def test_city50m_full_size_sampled():
+    """The default bench workload at full size, in its launch configuration:
+    the 50M-Gaussian city with three levels of k-means parents (scales x2.5),
+    a pool of 3,907 pages, adaptive thresholds, a 480x270 ID buffer at 1080p.
+    Frames 0 and 1 of the street, then 450 and 451 of the aerial phase (a jump
+    that evicts, converts pages between levels and copies hundreds of pages):
+    visibility, request order and levels, the whole page table, the copy list
+    and the preprocess compared in full; the pair lists, pixels and blend
+    visit counts of 40 random tiles and of the frame's four longest tiles
+    (the band walk)."""
+    import paper_2506_19415_amd as pkg
+    sc = synth.scene_city(0, n=50_000_000, color="smooth")
+    cams = synth.path_city(sc, n_frames=600, width=1920, height=1080)
+    print("city50m generated", flush=True)
+    r = _renderer(sc, 1024, 3907, (1920, 1080), (480, 270), 2.0, lod_levels=3, lod_radius_px=32.0, lod_scale_up=2.5,
+                  lod_builder=1)
+    r.set_flags(pkg.VM3DGS_FLAG_LINKS | pkg.VM3DGS_FLAG_ADAPTIVE_LOD | pkg.VM3DGS_FLAG_BLEND_STATS)
+    print("city50m library context", flush=True)
+    osc = oracle.OracleScene(sc, 1024, 3, 2.0, 2.0, lod_scale_up=2.5, lod_builder=1)
+    ovm = _ovm(osc, 3907, (1920, 1080), (480, 270), lod_radius_px=32.0)
+    ovm.set_adaptive_lod(True)
+    print("city50m oracle context", flush=True)
+    TX, TY = 120, 68
+    rng = np.random.default_rng(1)
+    for k in (0, 1, 450, 451):
+        _, out = r.frame([cams[k]])
+        g = r.get
+        ranges = g("ranges", np.uint32).reshape(-1, 2)[: TX * TY].astype(np.int64)
+        n_pairs = np.where(ranges[:, 1] > ranges[:, 0], ranges[:, 1] - ranges[:, 0], 0)
+        tiles = np.unique(np.concatenate([rng.choice(TX * TY, 40, replace=False), np.argsort(-n_pairs)[:4]]))
+        mask = np.zeros(TX * TY, np.uint8)
+        mask[tiles] = 1
+        ovm.frame([cams[k]], tile_mask=mask)
+        print(f"city50m frame {k}: {out.n_requests} requests, {out.stats.copies} copies, "
+              f"{out.stats.pairs} pairs, longest tile {n_pairs.max()}", flush=True)
+        for name, dt in [("cand", np.uint8), ("idbuf", np.uint64), ("req_direct", np.uint32), ("req_link", np.uint32),
+                         ("page_level", np.int8), ("slot_level", np.int8), ("last_used", np.int32),
+                         ("sub_vpage", np.int32), ("sub_last_used", np.int32), ("v2p", np.int32),
+                         ("copies", np.int64), ("copy_id", np.int32)]:
+            assert np.array_equal(g(name, dt), ovm.get(name)), (k, name)
+        req = np.ctypeslib.as_array(out.requests, (out.n_requests,))
+        assert np.array_equal(req, ovm.get("req_page")), k
+        lvl = np.ctypeslib.as_array(out.request_level, (out.n_requests,))
+        assert np.array_equal(lvl, ovm.get("req_level")), k
+        rl = g("render_list", np.uint32).reshape(-1, 4)
+        orl = ovm.get("render_list").reshape(-1, 6)
+        assert rl.shape[0] == orl.shape[0], k
+        assert np.array_equal(rl[:, 0], orl[:, 2] * 1024 + orl[:, 3] * orl[:, 4]), k
+        assert np.array_equal(rl[:, 1], orl[:, 4]) and np.array_equal(rl[:, 2], orl[:, 5]), k
+        pf, pi = g("pp_float", np.float32).reshape(-1, 12), g("pp_int", np.int32).reshape(-1, 6)
+        of, oi = ovm.get("pp_float").reshape(-1, 10), ovm.get("pp_int").reshape(-1, 6)
+        assert np.array_equal(pi[:, 0], oi[:, 0]), k
+        vis = oi[:, 0] == 0
+        assert np.array_equal(pi[vis], oi[vis]), k
+        assert np.array_equal(pf[vis, :3].view(np.uint32), of[vis, :3].view(np.uint32)), k
+        keys, vals = g("keys", np.uint32), g("vals", np.uint32)
+        okeys, ovals = ovm.get("keys"), ovm.get("vals")
+        orng = ovm.get("ranges").reshape(-1, 2)
+        img = r.image[0].cpu().numpy()
+        ref = ovm.image(1)[0]
+        visits = _tile_sums(ovm.get("visits").reshape(1080, 1920), 1920, 1080, TX, TY)
+        bst = g("blend_stats", np.uint32).reshape(-1, 2)[: TX * TY, 0].astype(np.int64)
+        for t in tiles:
+            s, e = ranges[t]
+            os_, oe = orng[t]
+            assert np.array_equal(vals[s:e], ovals[os_:oe]), (k, t)
+            assert np.all(keys[s:e] == t)
+            ty, tx = divmod(int(t), TX)
+            blk = (slice(ty * 16, min(ty * 16 + 16, 1080)), slice(tx * 16, tx * 16 + 16))
+            assert np.abs(img[blk] - ref[blk]).max() <= 1e-3, (k, t)
+            assert bst[t] == visits[t], (k, t, int(n_pairs[t]))
+    r.close()
+
+
 # ---------------------------------------------------------------- LOD levels
 @pytest.fixture(scope="module")
 def city():
