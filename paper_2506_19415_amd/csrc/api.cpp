@@ -270,14 +270,25 @@ void rb_flush(vm3dgs* c) {
     HIPCHK(hipGetLastError());
 }
 
-// waits for the render stream (queued readbacks first)
-void spin_wait(vm3dgs* c) {
+// the queued readbacks, then ev_sync on the render stream after them
+void mark_wait(vm3dgs* c) {
     rb_flush(c);
     HIPCHK(hipEventRecord(c->ev_sync, c->sr));
+}
+
+// the host waits for ev_sync by spinning: a sleeping wait adds its wake-up
+// time to every frame
+void spin_on_mark(vm3dgs* c) {
     hipError_t e;
     while ((e = hipEventQuery(c->ev_sync)) == hipErrorNotReady) {
     }
     if (e != hipSuccess) throw HipError{e, "hipEventQuery", __LINE__};
+}
+
+// waits for the render stream (queued readbacks first)
+void spin_wait(vm3dgs* c) {
+    mark_wait(c);
+    spin_on_mark(c);
 }
 
 // start of a frame's device work: clear counters, tickets and histograms
@@ -334,12 +345,8 @@ struct NoallocCapacity {
     uint32_t pairs;
 };
 
-// the render half of a frame: preprocess .. blend for n_render Gaussians per view
-void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool, uint32_t n_render, uint32_t n_views,
-           float* image, vm3dgs_stats* st) {
-    const uint64_t n_total = (uint64_t)n_render * n_views;
-    hipEvent_t* ev = c->ev;
-    HIPCHK(hipEventRecord(ev[3], c->sr));
+SplatArgs splat_args(const vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool, uint32_t n_render,
+                     uint32_t n_views) {
     SplatArgs a{};
     a.rl = rl; a.n_rl = (int)n_rl; a.pool = pool; a.P = c->P; a.fmt = c->ps.fmt;
     a.cams = c->d_cams; a.n_views = (int)n_views; a.W = (int)c->opt.img_w; a.H = (int)c->opt.img_h;
@@ -347,9 +354,25 @@ void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool,
     a.sigma3_tiles = (c->opt.flags & VM3DGS_FLAG_SIGMA3_TILES) ? 1 : 0;
     a.xy = c->d_xy; a.conic = c->d_conic; a.rgb = c->d_rgb; a.depth = c->d_depth; a.rect = c->d_rect;
     a.tiles = c->d_tiles; a.dkey = c->d_dkey[0]; a.dval = c->d_dval[0];
-    launch_preprocess(c->sr, a);
+    return a;
+}
+
+void splat_sorted(vm3dgs* c, uint32_t n_render, uint32_t n_views, float* image, vm3dgs_stats* st);
+
+// the render half of a frame: preprocess .. blend for n_render Gaussians per view
+void splat(vm3dgs* c, const RenderEntry* rl, uint32_t n_rl, const uint8_t* pool, uint32_t n_render, uint32_t n_views,
+           float* image, vm3dgs_stats* st) {
+    HIPCHK(hipEventRecord(c->ev[3], c->sr));
+    launch_preprocess(c->sr, splat_args(c, rl, n_rl, pool, n_render, n_views));
     HIPCHK(hipGetLastError());
-    HIPCHK(hipEventRecord(ev[4], c->sr));
+    HIPCHK(hipEventRecord(c->ev[4], c->sr));
+    splat_sorted(c, n_render, n_views, image, st);
+}
+
+// splat after the preprocess: depth sort .. blend
+void splat_sorted(vm3dgs* c, uint32_t n_render, uint32_t n_views, float* image, vm3dgs_stats* st) {
+    const uint64_t n_total = (uint64_t)n_render * n_views;
+    hipEvent_t* ev = c->ev;
     // depth order of the render set (culled entries carry all-ones keys and sort last)
     const int db = onesweep_u32(c->sr, c->sw, c->d_dkey, c->d_dval, (uint32_t)n_total, 0, 32);
     scan_lb_gather(c->sr, c->sw, c->d_tiles, c->d_dval[db], n_total, c->d_offs, c->d_total);
@@ -823,21 +846,23 @@ vm3dgs_status frame_impl(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views,
         }
         HIPCHK(hipGetLastError());
         HIPCHK(hipEventRecord(ev[2], c->sr));
-        // the counters: how many copies, render entries and Gaussians this frame has
+        // the counters: how many copies, render entries and Gaussians this
+        // frame has; the host reads them while the GPU runs the copies and the
+        // preprocess, which take these counts from the device
         rb_add(c, c->d_ctr, c->hd_ctr, sizeof(uint32_t) * C_NCOUNTERS);
-        spin_wait(c);
-        const uint32_t* k = c->h_ctr;
-        const uint32_t n_copy = k[C_NCOPY];
-        const uint32_t n_pf = (c->pf_on && c->pf_net) ? k[C_NPF] : 0u;
-        const uint32_t n_dem = n_copy - n_pf;
+        mark_wait(c);
+        const bool pf_stage = c->pf_on && c->pf_net;
         const uint64_t max_cmd = (uint64_t)c->P * c->ps.bytes_g;
         const uint64_t pool_bytes = max_cmd * (uint64_t)c->S;
+        const uint32_t max_copies = (uint32_t)c->n_pg * (uint32_t)c->L;
+        CopyRangeDev demand{c->d_ctr + C_NCOPY, pf_stage ? c->d_ctr + C_NPF : nullptr, 0};
         // copies of earlier frames on the copy stream (prefetches, streamed
-        // misses) finish before this frame writes or reads the pool
+        // misses) finish before this frame writes or reads the pool; a frame
+        // records ev_pf after its ev_async, so waiting for ev_pf covers both
         if (c->pf_pending) {
             HIPCHK(hipStreamWaitEvent(c->sr, c->ev_pf, 0));
             c->pf_pending = false;
-    c->async_pending = false;
+            c->async_pending = false;
         }
         if (c->async_pending) {
             HIPCHK(hipStreamWaitEvent(c->sr, c->ev_async, 0));
@@ -845,31 +870,44 @@ vm3dgs_status frame_impl(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views,
         }
         if (!streaming) {
             // demand copies: read by the GPU from the pinned store, in order before the splat
-            launch_copy_pages(c->sr, c->d_copies, 0, n_dem, max_cmd, c->h_store_dev, (uint64_t)c->ps.store_bytes,
-                              c->d_pool, pool_bytes, (unsigned long long*)(c->d_zero + ZB_BYTES), c->d_cp_err);
-        } else if (n_dem) {
+            launch_copy_pages_dev(c->sr, c->d_copies, demand, max_copies, max_cmd, c->h_store_dev,
+                                  (uint64_t)c->ps.store_bytes, c->d_pool, pool_bytes,
+                                  (unsigned long long*)(c->d_zero + ZB_BYTES), c->d_cp_err);
+        } else {
             // streaming (Sec. 4.3, Sec. 5.1.2): the frame renders what was resident
             // when it started; its copies run on the copy stream beside the splat
             // and the next frame waits for them before it touches the pool
-            launch_copy_bytes(c->sr, c->d_copies, 0, n_dem, (unsigned long long*)(c->d_zero + ZB_BYTES));
+            launch_copy_bytes_dev(c->sr, c->d_copies, demand, max_copies, (unsigned long long*)(c->d_zero + ZB_BYTES));
             HIPCHK(hipEventRecord(c->ev_copy, c->sr));
             HIPCHK(hipStreamWaitEvent(c->sc, c->ev_copy, 0));
-            launch_copy_pages(c->sc, c->d_copies, 0, n_dem, max_cmd, c->h_store_dev, (uint64_t)c->ps.store_bytes,
-                              c->d_pool, pool_bytes, c->d_pf_bytes, c->d_cp_err);
+            launch_copy_pages_dev(c->sc, c->d_copies, demand, max_copies, max_cmd, c->h_store_dev,
+                                  (uint64_t)c->ps.store_bytes, c->d_pool, pool_bytes, c->d_pf_bytes, c->d_cp_err);
             HIPCHK(hipEventRecord(c->ev_async, c->sc));
             c->async_pending = true;
         }
         HIPCHK(hipGetLastError());
         // prefetch copies: on the copy stream, after the page table; not awaited by this frame
-        if (n_pf) {
+        if (pf_stage) {
             HIPCHK(hipEventRecord(c->ev_copy, c->sr));
             HIPCHK(hipStreamWaitEvent(c->sc, c->ev_copy, 0));
-            launch_copy_pages(c->sc, c->d_copies, n_dem, n_pf, max_cmd, c->h_store_dev,
-                              (uint64_t)c->ps.store_bytes, c->d_pool, pool_bytes, c->d_pf_bytes, c->d_cp_err);
+            launch_copy_pages_dev(c->sc, c->d_copies, CopyRangeDev{demand.n_copy, demand.n_pf, 1}, max_copies,
+                                  max_cmd, c->h_store_dev, (uint64_t)c->ps.store_bytes, c->d_pool, pool_bytes,
+                                  c->d_pf_bytes, c->d_cp_err);
             HIPCHK(hipGetLastError());
             HIPCHK(hipEventRecord(c->ev_pf, c->sc));
             c->pf_pending = true;
         }
+        // the preprocess of the render set, sized on the device
+        HIPCHK(hipEventRecord(ev[3], c->sr));
+        launch_preprocess_dev(c->sr, splat_args(c, c->d_rlist, 0, c->d_pool, 0, n_views), c->d_ctr + C_NRENDER,
+                              c->d_ctr + C_NRL, c->cap_render);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipEventRecord(ev[4], c->sr));
+        spin_on_mark(c);
+        const uint32_t* k = c->h_ctr;
+        const uint32_t n_copy = k[C_NCOPY];
+        const uint32_t n_pf = pf_stage ? k[C_NPF] : 0u;
+        const uint32_t n_dem = n_copy - n_pf;
         st.lod_radius_px = c->lod_tau;
         if ((c->opt.flags & VM3DGS_FLAG_ADAPTIVE_LOD) && c->L > 1)
             lod_control(c, k[C_NMISSCAP], k[C_REQSLOTS], k[C_NCOARSE]);
@@ -884,7 +922,7 @@ vm3dgs_status frame_impl(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views,
         st.hits = k[C_HITS]; st.misses = k[C_MISSES]; st.evictions = k[C_EVICT]; st.missing = k[C_NMISSING];
         st.copies = n_dem; st.render_pages = k[C_NRL]; st.pool_pages_used = k[C_POOLUSED];
         c->pair_kind = 0;
-        splat(c, c->d_rlist, k[C_NRL], c->d_pool, n_render, n_views, image, &st);
+        splat_sorted(c, n_render, n_views, image, &st);
         // outputs of the frame: request order and missing list
         rb_add(c, c->d_keys + c->n_pg, c->hd_keys, sizeof(uint64_t) * c->last_n_req);
         if (c->L > 1) rb_add(c, c->d_lvl_out, c->hd_lvl, c->last_n_req);

@@ -537,22 +537,20 @@ __global__ void k_ptl_count_misses(const uint32_t* __restrict__ total, const uin
 
 
 // ------------------------------------------------------------------ page copies
-// Miss streaming by the GPU itself: each workgroup reads one 16 KB chunk of a
-// copy command from the pinned host store (over PCIe, with many loads in
-// flight) and writes it into the pool; the commands stay on the device.
+// Miss streaming by the GPU itself: workgroups take 16 KB chunks of the copy
+// commands in turn, read each from the pinned host store (over PCIe, with many
+// loads in flight) and write it into the pool; the commands and their count
+// stay on the device, so the copies are queued before the host knows it.
 // Offsets and sizes are multiples of 4 bytes (Gaussian records are 236 or 124
 // bytes); 16-byte accesses where the command allows.  A command that would
 // leave the store or the pool is skipped and flagged.
 constexpr int CP_NT = 256;
 constexpr uint32_t CP_CHUNK = 16384;
 
-__global__ __launch_bounds__(CP_NT) void k_copy_pages(const vm::CopyCmd* __restrict__ cmds, uint32_t first,
-                                                      uint32_t chunks_per_cmd, const uint8_t* __restrict__ host,
-                                                      uint64_t host_bytes, uint8_t* __restrict__ pool,
-                                                      uint64_t pool_bytes, unsigned long long* __restrict__ bytes_done,
-                                                      uint32_t* __restrict__ err) {
-    const uint32_t c = first + blockIdx.x / chunks_per_cmd;
-    const uint32_t ch = blockIdx.x % chunks_per_cmd;
+__device__ __forceinline__ void copy_chunk(const vm::CopyCmd* __restrict__ cmds, uint32_t c, uint32_t ch,
+                                           const uint8_t* __restrict__ host, uint64_t host_bytes,
+                                           uint8_t* __restrict__ pool, uint64_t pool_bytes,
+                                           unsigned long long* __restrict__ bytes_done, uint32_t* __restrict__ err) {
     const vm::CopyCmd cmd = cmds[c];
     const uint64_t h0 = (uint64_t)cmd.host_off, p0 = (uint64_t)cmd.pool_off, nb = (uint64_t)cmd.bytes;
     if (cmd.host_off < 0 || cmd.pool_off < 0 || cmd.bytes < 0 || h0 + nb > host_bytes || p0 + nb > pool_bytes) {
@@ -584,10 +582,39 @@ __global__ __launch_bounds__(CP_NT) void k_copy_pages(const vm::CopyCmd* __restr
     }
 }
 
-// bytes of copy commands [first, first + n) into *out (one workgroup)
-__global__ __launch_bounds__(PT_NT) void k_copy_bytes(const vm::CopyCmd* __restrict__ cmds, uint32_t first, uint32_t n,
-                                                     unsigned long long* __restrict__ out) {
+// the commands of a range read on the device (demand: the first n_copy - n_pf,
+// prefetch: the last n_pf), at most max_count of them; workgroups stride over
+// the chunks
+__device__ __forceinline__ void dev_range(const vm::CopyRangeDev& r, uint32_t max_count, uint32_t& first,
+                                          uint32_t& count) {
+    const uint32_t nc = *r.n_copy, np = r.n_pf ? *r.n_pf : 0u;
+    first = r.prefetch ? nc - np : 0u;
+    count = r.prefetch ? np : nc - np;
+    if (first > max_count) first = max_count;
+    if (count > max_count - first) count = max_count - first;
+}
+
+__global__ __launch_bounds__(CP_NT) void k_copy_pages(const vm::CopyCmd* __restrict__ cmds, vm::CopyRangeDev r,
+                                                          uint32_t max_count, uint32_t chunks_per_cmd,
+                                                          const uint8_t* __restrict__ host, uint64_t host_bytes,
+                                                          uint8_t* __restrict__ pool, uint64_t pool_bytes,
+                                                          unsigned long long* __restrict__ bytes_done,
+                                                          uint32_t* __restrict__ err) {
+    uint32_t first, count;
+    dev_range(r, max_count, first, count);
+    const uint64_t items = (uint64_t)count * chunks_per_cmd;
+    for (uint64_t it = blockIdx.x; it < items; it += gridDim.x)
+        copy_chunk(cmds, first + (uint32_t)(it / chunks_per_cmd), (uint32_t)(it % chunks_per_cmd), host, host_bytes,
+                   pool, pool_bytes, bytes_done, err);
+}
+
+// bytes of the copy commands of a range (read on the device, at most
+// max_count commands) into *out (one workgroup)
+__global__ __launch_bounds__(PT_NT) void k_copy_bytes(const vm::CopyCmd* __restrict__ cmds, vm::CopyRangeDev r,
+                                                     uint32_t max_count, unsigned long long* __restrict__ out) {
     __shared__ unsigned long long part[PT_NT / WAVE];
+    uint32_t first, n;
+    dev_range(r, max_count, first, n);
     unsigned long long b = 0;
     for (uint32_t i = threadIdx.x; i < n; i += PT_NT) b += (unsigned long long)cmds[first + i].bytes;
     for (int o = WAVE / 2; o > 0; o >>= 1) b += __shfl_down(b, o);
@@ -693,16 +720,19 @@ void launch_pagetable_lod(hipStream_t st, const PtArgs& a, SortWork& sw, const L
 
 namespace vm {
 
-void launch_copy_bytes(hipStream_t st, const CopyCmd* cmds, uint32_t first, uint32_t count, unsigned long long* out) {
-    hipLaunchKernelGGL(vmk::k_copy_bytes, dim3(1), dim3(vmk::PT_NT), 0, st, cmds, first, count, out);
+void launch_copy_bytes_dev(hipStream_t st, const CopyCmd* cmds, CopyRangeDev r, uint32_t max_count,
+                           unsigned long long* out) {
+    hipLaunchKernelGGL(vmk::k_copy_bytes, dim3(1), dim3(vmk::PT_NT), 0, st, cmds, r, max_count, out);
 }
 
-void launch_copy_pages(hipStream_t st, const CopyCmd* cmds, uint32_t first, uint32_t count, uint64_t max_cmd_bytes,
-                       const uint8_t* host, uint64_t host_bytes, uint8_t* pool, uint64_t pool_bytes,
-                       unsigned long long* bytes_done, uint32_t* err) {
-    if (count == 0) return;
+void launch_copy_pages_dev(hipStream_t st, const CopyCmd* cmds, CopyRangeDev r, uint32_t max_count,
+                           uint64_t max_cmd_bytes, const uint8_t* host, uint64_t host_bytes, uint8_t* pool,
+                           uint64_t pool_bytes, unsigned long long* bytes_done, uint32_t* err) {
+    if (max_count == 0) return;
     const uint32_t per = (uint32_t)((max_cmd_bytes + vmk::CP_CHUNK - 1) / vmk::CP_CHUNK);
-    hipLaunchKernelGGL(vmk::k_copy_pages, dim3(count * per), dim3(vmk::CP_NT), 0, st, cmds, first, per, host,
+    // 8 workgroups per compute unit, striding over the chunks
+    const uint32_t nb = (uint32_t)std::min<uint64_t>((uint64_t)max_count * per, 2048);
+    hipLaunchKernelGGL(vmk::k_copy_pages, dim3(nb), dim3(vmk::CP_NT), 0, st, cmds, r, max_count, per, host,
                        host_bytes, pool, pool_bytes, bytes_done, err);
 }
 

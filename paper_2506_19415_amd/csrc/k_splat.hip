@@ -66,14 +66,34 @@ struct PreArgs {
     const CamK* cams;
     int W, H, TX, TY;
     uint32_t n_render; uint64_t n_total;
+    // counts on the device (launched before the host has read them):
+    // n_render and n_rl from these words, n_total bounded by max_total, and
+    // the grid strides over the entries
+    const uint32_t* n_render_dev; const uint32_t* n_rl_dev; int n_views; uint64_t max_total;
     int sigma3_tiles;
     float4* xy; float4* conic; float4* rgb; uint32_t* depth; uint2* rect; uint32_t* tiles;
     uint32_t* dkey; uint32_t* dval;
 };
 
+__device__ __forceinline__ void preprocess_one(const PreArgs& a, uint64_t f);
+
 __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
+    if (a.n_render_dev) {
+        a.n_render = *a.n_render_dev;
+        a.n_rl = (int)*a.n_rl_dev;
+        a.n_total = (uint64_t)a.n_render * (uint32_t)a.n_views;
+        if (a.n_total > a.max_total) a.n_total = a.max_total;
+        if (a.n_rl == 0) return;
+        for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f < a.n_total;
+             f += (uint64_t)gridDim.x * blockDim.x)
+            preprocess_one(a, f);
+        return;
+    }
     const uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= a.n_total) return;
+    if (f < a.n_total) preprocess_one(a, f);
+}
+
+__device__ __forceinline__ void preprocess_one(const PreArgs& a, uint64_t f) {
     const uint32_t v = (uint32_t)(f / a.n_render);
     const uint32_t gi = (uint32_t)(f - (uint64_t)v * a.n_render);
     // render entry holding gi: last entry with base <= gi
@@ -544,13 +564,14 @@ __device__ __forceinline__ void strip_walk(uint2 rg, const uint32_t* __restrict_
     }
 }
 
-// value of sub-lane j of this lane's quad (DPP quad_perm [j, j, j, j])
+// value of sub-lane j of this lane's quad (DPP quad_perm [j, j, j, j]; 0
+// from an inactive lane)
 __device__ __forceinline__ int quad_bcast_i(int x, int j) {
     switch (j) {
-    case 0: return __builtin_amdgcn_update_dpp(0, x, 0x00, 0xf, 0xf, false);
-    case 1: return __builtin_amdgcn_update_dpp(0, x, 0x55, 0xf, 0xf, false);
-    case 2: return __builtin_amdgcn_update_dpp(0, x, 0xaa, 0xf, 0xf, false);
-    default: return __builtin_amdgcn_update_dpp(0, x, 0xff, 0xf, 0xf, false);
+    case 0: return __builtin_amdgcn_mov_dpp(x, 0x00, 0xf, 0xf, true);
+    case 1: return __builtin_amdgcn_mov_dpp(x, 0x55, 0xf, 0xf, true);
+    case 2: return __builtin_amdgcn_mov_dpp(x, 0xaa, 0xf, 0xf, true);
+    default: return __builtin_amdgcn_mov_dpp(x, 0xff, 0xf, 0xf, true);
     }
 }
 __device__ __forceinline__ float quad_bcast(float x, int j) {
@@ -664,36 +685,47 @@ __device__ __forceinline__ void band_walk(BlendLds& L, uint2 rg, const uint32_t*
         // 2. compositing: the quad's pixel over its selected Gaussians in
         // order, four at a time: sub-lane k evaluates the k-th (exponent and
         // alpha, the costly part), then the quad blends the four in order,
-        // each lane taking them from the others (DPP quad broadcasts)
+        // each lane taking their alphas from the others (DPP quad
+        // broadcasts) and keeping one colour channel (sub-lane k: channel k,
+        // none for k = 3), without branches: a term after the stop is not taken
         if (pb.live) {   // uniform over the quad
+            const float* const gcol = &L.g[2][0].x;
             for (int w = 0; w < BL_WORDS && pb.live; ++w) {
                 uint32_t m = L.mask[w][q];
                 while (m != 0u && pb.live) {
                     uint32_t mk = m;   // without its first `sub` bits
-                    for (int i = 0; i < sub; ++i) mk &= mk - 1u;
+                    mk = sub >= 1 ? mk & (mk - 1u) : mk;
+                    mk = sub >= 2 ? mk & (mk - 1u) : mk;
+                    mk = sub >= 3 ? mk & (mk - 1u) : mk;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) m &= m - 1u;
                     // this lane's term: alpha, or -1 where none or out of range
-                    float a = -1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+                    float a = -1.0f;
                     const int g = mk != 0u ? w * 32 + (int)__builtin_ctz(mk) : 0;
                     if (mk != 0u) {
-                        const float4 P = L.g[0][g], Q = L.g[1][g], R = L.g[2][g];
+                        const float4 P = L.g[0][g], Q = L.g[1][g];
                         const float power = blend_power(P.x, P.y, Q.x, Q.y, Q.z, fpx, fpy);
                         if (power_in_range(power)) a = blend_alpha(power, Q.w);
-                        cr = R.x; cg = R.y; cb = R.z;
                     }
+                    bool alive = true;
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         // every lane of the quad takes part in each broadcast
                         // (a DPP read from an inactive lane gives 0)
                         const float aj = quad_bcast(a, j);
-                        const int gj = STATS ? quad_bcast_i(g, j) : 0;
-                        if (blend_term(pb, aj, aj >= 0.0f, quad_bcast(cr, j), quad_bcast(cg, j), quad_bcast(cb, j))) {
-                            if (STATS && sub == 0) pb.n_visit = base + (uint32_t)gj + 1u - rg.x;
-                            pb.live = false;
-                            break;
-                        }
+                        const int gj = quad_bcast_i(g, j);
+                        const float cj = gcol[4 * gj + sub];
+                        const bool take = alive && aj >= 1.0f / 255.0f;
+                        const float Tn = pb.T * (1.0f - aj);
+                        const bool stop = take && Tn < 0.0001f;
+                        const bool add = take && !stop;
+                        const float nc = fmaf(cj, aj * pb.T, pb.C0);
+                        pb.C0 = add ? nc : pb.C0;
+                        pb.T = add ? Tn : pb.T;
+                        if (STATS && stop && sub == 0) pb.n_visit = base + (uint32_t)gj + 1u - rg.x;
+                        alive = alive && !stop;
                     }
+                    pb.live = alive;
                 }
             }
         }
@@ -703,6 +735,9 @@ __device__ __forceinline__ void band_walk(BlendLds& L, uint2 rg, const uint32_t*
         if (lane == 0) L.live[wave] = lm;
         __syncthreads();
     }
+    // the pixel's colour from the quad's three channel lanes
+    const float c0 = quad_bcast(pb.C0, 0), c1 = quad_bcast(pb.C0, 1), c2 = quad_bcast(pb.C0, 2);
+    pb.C0 = c0; pb.C1 = c1; pb.C2 = c2;
 }
 
 // Workgroups for n_tiles tiles: four per long tile (at most BL_LONG_CAP of
@@ -786,8 +821,25 @@ void launch_preprocess(hipStream_t st, const SplatArgs& s) {
     a.sigma3_tiles = s.sigma3_tiles;
     a.xy = s.xy; a.conic = s.conic; a.rgb = s.rgb; a.depth = s.depth; a.rect = s.rect; a.tiles = s.tiles;
     a.dkey = s.dkey; a.dval = s.dval;
+    a.n_render_dev = nullptr; a.n_rl_dev = nullptr; a.n_views = s.n_views; a.max_total = a.n_total;
     if (a.n_total == 0 || s.n_rl == 0) return;
     hipLaunchKernelGGL(k_preprocess, dim3(nblk(a.n_total, 256)), dim3(256), 0, st, a);
+}
+
+void launch_preprocess_dev(hipStream_t st, const SplatArgs& s, const uint32_t* n_render_dev, const uint32_t* n_rl_dev,
+                           uint64_t max_total) {
+    PreArgs a;
+    a.rl = s.rl; a.n_rl = 0; a.pool = s.pool; a.fmt = s.fmt; a.bytes_g = s.fmt == 1 ? 124 : 236;
+    a.cams = s.cams; a.W = s.W; a.H = s.H; a.TX = s.TX; a.TY = s.TY;
+    a.n_render = 0; a.n_total = 0;
+    a.sigma3_tiles = s.sigma3_tiles;
+    a.xy = s.xy; a.conic = s.conic; a.rgb = s.rgb; a.depth = s.depth; a.rect = s.rect; a.tiles = s.tiles;
+    a.dkey = s.dkey; a.dval = s.dval;
+    a.n_render_dev = n_render_dev; a.n_rl_dev = n_rl_dev; a.n_views = s.n_views; a.max_total = max_total;
+    if (max_total == 0) return;
+    // 8 workgroups of 4 waves per compute unit, striding
+    const unsigned nb = (unsigned)std::min<uint64_t>(nblk(max_total, 256), 2048);
+    hipLaunchKernelGGL(k_preprocess, dim3(nb), dim3(256), 0, st, a);
 }
 
 void launch_emit(hipStream_t st, const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles,

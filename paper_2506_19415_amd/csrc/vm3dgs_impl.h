@@ -175,6 +175,11 @@ struct SplatArgs {
     uint32_t* dkey; uint32_t* dval;
 };
 void launch_preprocess(hipStream_t st, const SplatArgs& a);
+// the same with the render set's size read on the device (*n_render_dev
+// Gaussians per view in *n_rl_dev entries, at most max_total in all): it is
+// queued before the host has read the page table's counters
+void launch_preprocess_dev(hipStream_t st, const SplatArgs& a, const uint32_t* n_render_dev, const uint32_t* n_rl_dev,
+                           uint64_t max_total);
 // pairs counted on the device (*n_pairs_dev); the grids cover the capacity cap
 void launch_emit(hipStream_t st, const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles,
                  const uint2* rect, uint32_t* starts, uint32_t n_total, const uint32_t* n_pairs_dev, uint32_t n_render,
@@ -262,12 +267,22 @@ void launch_gather_rows(hipStream_t st, const float* src, const uint32_t* idx, u
 // the prefetch stage of a context: its network (or NULL) and options; false without a stage
 bool prefetch_stage_of(const vm3dgs* ctx, vm3dgs_mlp** net, vm3dgs_prefetch_opts* opts);
 
-// total bytes of copy commands [first, first + count) into *out
-void launch_copy_bytes(hipStream_t st, const CopyCmd* cmds, uint32_t first, uint32_t count, unsigned long long* out);
-// copies of the misses by the GPU from the pinned host store (one command per
-// 16 KB chunk and workgroup); bytes_done accumulates the bytes copied
-void launch_copy_pages(hipStream_t st, const CopyCmd* cmds, uint32_t first, uint32_t count, uint64_t max_cmd_bytes,
-                       const uint8_t* host, uint64_t host_bytes, uint8_t* pool, uint64_t pool_bytes,
-                       unsigned long long* bytes_done, uint32_t* err);
+// a range of copy commands whose bounds the kernel reads on the device: of
+// *n_copy commands the last *n_pf (none when n_pf is null) are prefetches;
+// prefetch 0 takes the others (the demand copies), 1 the prefetches
+struct CopyRangeDev {
+    const uint32_t* n_copy = nullptr;
+    const uint32_t* n_pf = nullptr;
+    int prefetch = 0;
+};
+// total bytes of the commands of such a range (at most max_count) into *out
+void launch_copy_bytes_dev(hipStream_t st, const CopyCmd* cmds, CopyRangeDev r, uint32_t max_count,
+                           unsigned long long* out);
+// copies of the misses of such a range by the GPU from the pinned host store
+// (16 KB chunks, workgroups striding over them); bytes_done accumulates the
+// bytes copied, err is set by a command outside the store or the pool
+void launch_copy_pages_dev(hipStream_t st, const CopyCmd* cmds, CopyRangeDev r, uint32_t max_count,
+                           uint64_t max_cmd_bytes, const uint8_t* host, uint64_t host_bytes, uint8_t* pool,
+                           uint64_t pool_bytes, unsigned long long* bytes_done, uint32_t* err);
 
 }  // namespace vm
