@@ -44,6 +44,8 @@ struct vm3dgs {
     int S = 0, L = 1, P = 0, n_pg = 0, TX = 0, TY = 0;
     hipStream_t sr = nullptr, sc = nullptr;
     bool own_sr = false, own_sc = false;
+    hipStream_t sb = nullptr;   // the blend's second stream, forked from sr and joined back
+    hipEvent_t ev_bfork = nullptr, ev_bjoin = nullptr;
     hipEvent_t ev_copy = nullptr;
     hipEvent_t ev_sync = nullptr;   // host waits inside a frame spin on this event
     hipEvent_t ev[8] = {};
@@ -132,6 +134,7 @@ struct vm3dgs {
     uint32_t last_n_pfreq = 0, last_n_pf = 0;
     // last frame, for vm3dgs_debug_get and the frame output
     uint32_t last_views = 0, last_n_render = 0, last_n_pairs = 0, last_n_copy = 0, last_n_missing = 0;
+    uint32_t last_n_xlong = 0xffffffffu;   // longest tiles of the last splat (none yet: room for all)
     uint32_t last_n_req = 0, last_n_rl = 0;
     int last_pbuf = 0, last_dbuf = 0;
     std::vector<int32_t> out_req, out_missing;
@@ -228,6 +231,9 @@ void free_all(vm3dgs* c) {
         if (e) hipEventDestroy(e);
     if (c->own_sr && c->sr) hipStreamDestroy(c->sr);
     if (c->own_sc && c->sc) hipStreamDestroy(c->sc);
+    if (c->sb) hipStreamDestroy(c->sb);
+    if (c->ev_bfork) hipEventDestroy(c->ev_bfork);
+    if (c->ev_bjoin) hipEventDestroy(c->ev_bjoin);
 }
 
 constexpr int ZB_CTR = 0, ZB_ERR = C_NCOUNTERS, ZB_BYTES = ZB_ERR + 2, ZB_TICKETS = ZB_ERR + 16,
@@ -402,9 +408,33 @@ void splat_sorted(vm3dgs* c, uint32_t n_render, uint32_t n_views, float* image, 
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[5], c->sr));
     const bool bstats = (c->opt.flags & VM3DGS_FLAG_BLEND_STATS) != 0;
-    launch_blend(c->sr, c->d_ranges, c->d_tile_order, pbuf.val[pb], c->d_xy, c->d_conic, c->d_rgb,
-                 (int)c->opt.img_w, (int)c->opt.img_h, c->TX, c->TY, (int)n_views, image, bstats ? c->d_bstats : nullptr);
-    HIPCHK(hipGetLastError());
+    {
+        uint2* const bs = bstats ? c->d_bstats : nullptr;
+        const int W = (int)c->opt.img_w, H = (int)c->opt.img_h;
+        if (bs) launch_fill_u32(c->sr, (uint32_t*)bs, 2 * (uint64_t)n_tiles, 0u);
+        // the longest tiles' alpha band walk on the render stream, the other
+        // tiles beside it on the blend stream, joined back; room for half
+        // as many longest tiles again as the last frame had (their count is
+        // known on the device only; any beyond take the other launch), and
+        // one launch alone after a frame without them
+        const uint32_t h = c->last_n_xlong;
+        const uint32_t x_cap = h == 0 ? 0u : blend_x_cap(n_tiles, h > 0x3fffffffu ? h : h + h / 2 + 8);
+        if (x_cap) {
+            HIPCHK(hipEventRecord(c->ev_bfork, c->sr));
+            HIPCHK(hipStreamWaitEvent(c->sb, c->ev_bfork, 0));
+            launch_blend_x(c->sr, c->d_ranges, c->d_tile_order, pbuf.val[pb], c->d_xy, c->d_conic, c->d_rgb, W, H,
+                           c->TX, c->TY, (int)n_views, x_cap, image, bs);
+            launch_blend(c->sb, c->d_ranges, c->d_tile_order, pbuf.val[pb], c->d_xy, c->d_conic, c->d_rgb, W, H,
+                         c->TX, c->TY, (int)n_views, x_cap, image, bs);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipEventRecord(c->ev_bjoin, c->sb));
+            HIPCHK(hipStreamWaitEvent(c->sr, c->ev_bjoin, 0));
+        } else {
+            launch_blend(c->sr, c->d_ranges, c->d_tile_order, pbuf.val[pb], c->d_xy, c->d_conic, c->d_rgb, W, H,
+                         c->TX, c->TY, (int)n_views, 0u, image, bs);
+            HIPCHK(hipGetLastError());
+        }
+    }
     HIPCHK(hipEventRecord(ev[6], c->sr));
     if (bstats && st) {
         HIPCHK(hipMemcpyAsync(c->h_bstats, c->d_bstats, sizeof(uint2) * n_tiles, hipMemcpyDeviceToHost, c->sr));
@@ -416,6 +446,7 @@ void splat_sorted(vm3dgs* c, uint32_t n_render, uint32_t n_views, float* image, 
     }
     rb_add(c, c->d_total, c->hd_total, sizeof(uint32_t));
     rb_add(c, c->d_zero + ZB_ERR, (uint32_t*)c->hd_total + 1, sizeof(uint32_t));
+    rb_add(c, c->d_tile_order + n_tiles + 1, (uint32_t*)c->hd_total + 5, sizeof(uint32_t));
     c->last_views = n_views; c->last_n_render = n_render;
     c->last_pbuf = pb; c->last_dbuf = db;
     if (st) st->render_gaussians = n_total;
@@ -426,6 +457,7 @@ void splat_sorted(vm3dgs* c, uint32_t n_render, uint32_t n_views, float* image, 
 bool splat_pairs_ok(vm3dgs* c, vm3dgs_stats* st) {
     if (c->h_total[1]) throw HipError{hipErrorUnknown, "single-pass scan look-back did not complete", __LINE__};
     const uint32_t n_pairs = c->h_total[0];
+    c->last_n_xlong = c->h_total[5];
     const uint64_t want = std::min<uint64_t>((uint64_t)n_pairs + n_pairs / 2 + 1024, 0xffffffffull);
     c->pair_grid[c->pair_kind] = (uint32_t)want;
     if (n_pairs > c->pair_cover) {
@@ -617,6 +649,9 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         else { HIPCHK(hipStreamCreateWithFlags(&c->sr, hipStreamNonBlocking)); c->own_sr = true; }
         if (o.stream_copy) c->sc = (hipStream_t)o.stream_copy;
         else { HIPCHK(hipStreamCreateWithFlags(&c->sc, hipStreamNonBlocking)); c->own_sc = true; }
+        HIPCHK(hipStreamCreateWithFlags(&c->sb, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&c->ev_bfork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c->ev_bjoin, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&c->ev_async, hipEventDisableTiming));
@@ -719,9 +754,9 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
         dalloc(&c->d_rect, R); dalloc(&c->d_tiles, R); dalloc(&c->d_offs, R + 1);
         for (int i = 0; i < 2; ++i) { dalloc(&c->d_dkey[i], R); dalloc(&c->d_dval[i], R); }
         dalloc(&c->d_ranges, (size_t)c->TX * c->TY * V);
-        dalloc(&c->d_tile_order, (size_t)c->TX * c->TY * V + 1);   // + the count of long tiles
+        dalloc(&c->d_tile_order, (size_t)c->TX * c->TY * V + 2);   // + the counts of long and longest tiles
         dalloc(&c->d_bstats, (size_t)c->TX * c->TY * V); halloc(&c->h_bstats, (size_t)c->TX * c->TY * V);
-        dalloc(&c->d_total, 4); halloc(&c->h_total, 8);  // [0] pairs, [1] look-back error, [2..3] bytes, [4] copy error
+        dalloc(&c->d_total, 4); halloc(&c->h_total, 8);  // [0] pairs, [1] look-back error, [2..3] bytes, [4] copy error, [5] longest tiles
         c->hd_total = host_dev(c->h_total); c->hd_ctr = host_dev(c->h_ctr); c->hd_keys = host_dev(c->h_keys);
         c->hd_missing = host_dev(c->h_missing);
         if (c->h_lvl) c->hd_lvl = host_dev(c->h_lvl);

@@ -21,6 +21,8 @@
 //                Gaussian-parallel selection of the terms that pass the
 //                alpha test into per-pixel bit masks (LDS), then
 //                pixel-parallel compositing of the selected terms in order.
+#include <type_traits>
+
 #include "kcommon.h"
 #include "vm3dgs_impl.h"
 
@@ -316,8 +318,10 @@ constexpr int TO_NT = 1024;
 
 // The blend's long tiles: tile-order classes from this one up (counts of
 // 2^12 or more).  order[n_tiles] receives their number (a prefix of the
-// order).
+// order), order[n_tiles + 1] that of the tiles from BL_XLONG_CLASS up
+// (counts of 2^14 or more, the alpha band walk's).
 constexpr int BL_LONG_CLASS = 13;
+constexpr int BL_XLONG_CLASS = 15;
 __global__ __launch_bounds__(TO_NT) void k_tile_order(const uint2* __restrict__ ranges, uint32_t n_tiles,
                                                       uint32_t* __restrict__ order) {
     __shared__ uint32_t cnt[33];
@@ -335,6 +339,7 @@ __global__ __launch_bounds__(TO_NT) void k_tile_order(const uint2* __restrict__ 
             cnt[c] = acc;
             acc += k;
             if (c == BL_LONG_CLASS) order[n_tiles] = acc;
+            if (c == BL_XLONG_CLASS) order[n_tiles + 1] = acc;
         }
     }
     __syncthreads();
@@ -401,10 +406,13 @@ constexpr int BL_BAND_PX = TILE * TILE / BL_BANDS;
 constexpr int BL_CH = BL_NT;         // pairs per band-walk chunk, one per thread
 constexpr int BL_WORDS = BL_CH / 32;
 constexpr int BL_SEL_BOX = 16;       // larger boxes are evaluated by the whole wave
+constexpr int BL_APAD = BL_BAND_PX + 1;   // alpha row stride: a term's pixels, one word of padding
 // Long tiles given a band walk, at most (the others of a larger count take
-// the strip walk).  The launch carries room for this many.
+// the strip walk).
 constexpr uint32_t BL_LONG_CAP = 2048;
+constexpr uint32_t BL_XLONG = 16384;   // tiles with this many pairs take the alpha band walk
 static_assert(BL_LONG == (1u << (BL_LONG_CLASS - 1)), "the long tiles are whole tile-order classes");
+static_assert(BL_XLONG == (1u << (BL_XLONG_CLASS - 1)) && BL_XLONG >= BL_LONG, "the longest tiles too");
 static_assert(BL_BANDS == 4 && BL_BAND_PX == WAVE && BL_NT / WAVE == BL_BANDS, "band layout: one band row per wave");
 
 __device__ __forceinline__ float uniform_f(float x) {
@@ -458,6 +466,20 @@ struct BlendLds {
     uint32_t st[2][BL_NT / WAVE];
 };
 
+
+// LDS of the alpha band walk (the longest tiles): the alphas that the selection finds (term t,
+// band pixel q at t * BL_APAD + q: the lanes of a wave, on consecutive
+// terms, write distinct banks), the chunk's colours, the per-pixel masks of
+// the chunk's selected Gaussians, word-major (consecutive pixels read
+// consecutive words: no bank conflicts), and the band's live pixels, 16 bits
+// per row.
+struct AlphaLds {
+    float alpha[BL_CH * BL_APAD];
+    float4 col[BL_CH];
+    uint32_t mask[BL_WORDS][BL_BAND_PX];
+    uint32_t live[BL_BANDS];
+    uint32_t st[2][BL_NT / WAVE];
+};
 // per-pixel blend state
 struct PixelBlend {
     float T, C0, C1, C2;
@@ -596,6 +618,22 @@ __device__ __forceinline__ void select_term(BlendLds& L, uint32_t bit, int word,
     if (power_in_range(power)) {
         ++n_alpha;
         if (blend_alpha(power, op) >= 1.0f / 255.0f) atomicOr(&L.mask[word][q], bit);
+    }
+}
+
+// phase 1 for chunk term jt and band pixel q (= row * 16 + column, at image
+// position (fx, fy)): a term that passes the alpha test is selected and
+// its alpha kept
+__device__ __forceinline__ void select_alpha_term(AlphaLds& L, int jt, int q, float fx, float fy, float u, float v, float ca,
+                                            float cb, float cc, float op, uint32_t& n_alpha) {
+    const float power = blend_power(u, v, ca, cb, cc, fx, fy);
+    if (power_in_range(power)) {
+        ++n_alpha;
+        const float a = blend_alpha(power, op);
+        if (a >= 1.0f / 255.0f) {
+            atomicOr(&L.mask[jt >> 5][q], 1u << (jt & 31));
+            L.alpha[jt * BL_APAD + q] = a;
+        }
     }
 }
 
@@ -740,6 +778,134 @@ __device__ __forceinline__ void band_walk(BlendLds& L, uint2 rg, const uint32_t*
     pb.C0 = c0; pb.C1 = c1; pb.C2 = c2;
 }
 
+template <bool STATS>
+__device__ __forceinline__ void band_walk_alpha(AlphaLds& L, uint2 rg, const uint32_t* __restrict__ pval,
+                                          const float4* __restrict__ xy, const float4* __restrict__ conic,
+                                          const float4* __restrict__ rgb, int tx, int ty, int band, int W, int H,
+                                          PixelBlend& pb, uint32_t& n_alpha, int& px_out, int& py_out) {
+    const int t = (int)threadIdx.x, wave = t / WAVE, lane = (int)__lane_id();
+    // the band: columns tx * 16 + [0, 16), rows by0 + [0, 4).  Compositing:
+    // wave w takes row w, a quad of lanes per pixel (column lane / 4); the
+    // quad's lanes hold the same transmittance, sub-lane k = lane % 4 the
+    // pixel's colour channel k (none for k = 3)
+    const int by0 = ty * TILE + band * (TILE / BL_BANDS);
+    const int col = lane >> 2, sub = lane & 3;
+    const int q = wave * TILE + col;   // band pixel of the quad
+    const int px = tx * TILE + col, py = by0 + wave;
+    px_out = sub == 0 ? px : W;   // one lane of the quad writes the pixel
+    py_out = py;
+    const float fpx = (float)px, fpy = (float)py;
+    const float tx0 = (float)(tx * TILE), ty0 = (float)by0;
+    pb.live = px < W && py < H;
+    pb.n_visit = pb.live && sub == 0 ? rg.y - rg.x : 0u;
+#pragma unroll
+    for (int w = 0; w < BL_WORDS / 4; ++w) L.mask[sub * (BL_WORDS / 4) + w][q] = 0u;
+    uint32_t lm = quad_live16(__builtin_amdgcn_ballot_w64(pb.live));
+    if (lane == 0) L.live[wave] = lm;
+    // registers: this chunk's Gaussian, the next chunk's, the pair value of the one after
+    float4 n_p = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 n_co = n_p, n_cl = n_p;
+    if (rg.x + t < rg.y) {
+        const uint32_t f = pval[rg.x + t];
+        n_p = xy[f];
+        n_co = conic[f];
+        n_cl = rgb[f];
+    }
+    uint32_t n_f = rg.x + BL_CH + t < rg.y ? pval[rg.x + BL_CH + t] : 0u;
+    __syncthreads();
+    for (uint32_t base = rg.x; base < rg.y; base += BL_CH) {
+        // the band's live pixels, bit row * 16 + column (uniform)
+        const uint64_t live = (uint64_t)L.live[0] | ((uint64_t)L.live[1] << 16) | ((uint64_t)L.live[2] << 32) |
+                              ((uint64_t)L.live[3] << 48);
+        if (live == 0) break;
+        const float4 gp = n_p, gb = n_co, gc = n_cl;
+        const bool valid = base + t < rg.y;
+        if (base + BL_CH + t < rg.y) {
+            n_p = xy[n_f];
+            n_co = conic[n_f];
+            n_cl = rgb[n_f];
+        }
+        n_f = base + 2 * BL_CH + t < rg.y ? pval[base + 2 * BL_CH + t] : 0u;
+        L.col[t] = gc;
+        // 1. selection: this thread's Gaussian over the live pixels of its box in the band
+        const float c0 = fmaxf(ceilf((gp.x - gp.z) - tx0), 0.0f), c1 = fminf(floorf((gp.x + gp.z) - tx0), 15.0f);
+        const float r0 = fmaxf(ceilf((gp.y - gp.w) - ty0), 0.0f), r1 = fminf(floorf((gp.y + gp.w) - ty0), 3.0f);
+        const bool has = valid && c0 <= c1 && r0 <= r1;
+        const int ic0 = has ? (int)c0 : 0, ic1 = has ? (int)c1 : -1;
+        const int ir0 = has ? (int)r0 : 0, ir1 = has ? (int)r1 : -1;
+        const bool small = (ic1 - ic0 + 1) * (ir1 - ir0 + 1) <= BL_SEL_BOX;
+        if (small) {
+            for (int y = ir0; y <= ir1; ++y) {
+                const uint32_t row = (uint32_t)(live >> (y * TILE));
+                for (int x = ic0; x <= ic1; ++x)
+                    if ((row >> x) & 1u)
+                        select_alpha_term(L, t, y * TILE + x, tx0 + (float)x, ty0 + (float)y, gp.x, gp.y, gb.x, gb.y,
+                                    gb.z, gb.w, n_alpha);
+            }
+        }
+        // the others: one at a time, a band pixel per lane
+        uint64_t big = __builtin_amdgcn_ballot_w64(!small);
+        const int bx = lane & (TILE - 1), byy = lane / TILE;
+        const bool lane_live = (live >> lane) & 1ull;
+        while (big != 0) {
+            const int j = (int)__builtin_ctzll(big);
+            big &= big - 1;
+            const int x0 = lane_i(ic0, j), x1 = lane_i(ic1, j), y0 = lane_i(ir0, j), y1 = lane_i(ir1, j);
+            if (lane_live && bx >= x0 && bx <= x1 && byy >= y0 && byy <= y1) {
+                select_alpha_term(L, wave * WAVE + j, lane, tx0 + (float)bx, ty0 + (float)byy, lane_f(gp.x, j),
+                            lane_f(gp.y, j), lane_f(gb.x, j), lane_f(gb.y, j), lane_f(gb.z, j), lane_f(gb.w, j),
+                            n_alpha);
+            }
+        }
+        __syncthreads();
+        // 2. compositing: the quad's pixel over its selected Gaussians in
+        // order, four at a time, with the alphas that the selection kept;
+        // without branches: a term after the stop is not taken
+        if (pb.live) {   // uniform over the quad
+            const float* const gcol = &L.col[0].x + sub;   // term j's channel at gcol[4 * j]
+            const float* const arow = &L.alpha[q];         // term j's alpha at arow[j * BL_APAD]
+            for (int w = 0; w < BL_WORDS && pb.live; ++w) {
+                uint32_t m = L.mask[w][q];
+                while (m != 0u && pb.live) {
+                    uint32_t jj[4];
+                    float a[4], cj[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const bool ok = m != 0u;
+                        jj[u] = ok ? (uint32_t)(w * 32) + (uint32_t)__builtin_ctz(m) : 0u;
+                        m &= m - 1u;
+                        const float av = arow[jj[u] * BL_APAD];
+                        a[u] = ok ? av : -1.0f;
+                        cj[u] = gcol[4 * jj[u]];
+                    }
+                    bool alive = true;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const bool take = alive && a[u] >= 1.0f / 255.0f;
+                        const float Tn = pb.T * (1.0f - a[u]);
+                        const bool stop = take && Tn < 0.0001f;
+                        const bool add = take && !stop;
+                        const float nc = fmaf(cj[u], a[u] * pb.T, pb.C0);
+                        pb.C0 = add ? nc : pb.C0;
+                        pb.T = add ? Tn : pb.T;
+                        if (STATS && stop && sub == 0) pb.n_visit = base + jj[u] + 1u - rg.x;
+                        alive = alive && !stop;
+                    }
+                    pb.live = alive;
+                }
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < BL_WORDS / 4; ++w) L.mask[sub * (BL_WORDS / 4) + w][q] = 0u;
+        lm = quad_live16(__builtin_amdgcn_ballot_w64(pb.live));
+        if (lane == 0) L.live[wave] = lm;
+        __syncthreads();
+    }
+    // the pixel's colour from the quad's three channel lanes
+    const float c0 = quad_bcast(pb.C0, 0), c1 = quad_bcast(pb.C0, 1), c2 = quad_bcast(pb.C0, 2);
+    pb.C0 = c0; pb.C1 = c1; pb.C2 = c2;
+}
+
 // Workgroups for n_tiles tiles: four per long tile (at most BL_LONG_CAP of
 // them, rounded up to a multiple of 8, plus up to 28 left over by that
 // rounding), one per other tile.
@@ -750,30 +916,66 @@ __host__ __device__ inline uint32_t blend_workgroups(uint32_t n_tiles) {
     return n_tiles + (BL_BANDS - 1) * blend_long_slots(n_tiles) + 4 * 7;
 }
 
+// The long tiles (order[n_tiles] of them, at most BL_LONG_CAP) and, among
+// them first, those with BL_XLONG pairs or more that the alpha band walk
+// takes (order[n_tiles + 1] of them, at most x_cap).
+struct BlendSplit {
+    uint32_t n_long, n_x;
+};
+__device__ __forceinline__ BlendSplit blend_split(const uint32_t* __restrict__ order, uint32_t n_tiles,
+                                                  uint32_t x_cap) {
+    const uint32_t n_long = min(order[n_tiles], blend_long_slots(n_tiles));
+    return BlendSplit{n_long, min(min(order[n_tiles + 1], x_cap), n_long)};
+}
+
+// Writes the pixel and adds the workgroup's work counters to its tile's.
+template <bool STATS>
+__device__ __forceinline__ void blend_finish(uint32_t (&st)[2][BL_NT / WAVE], const PixelBlend& pb, uint32_t n_alpha,
+                                             int px, int py, int W, int H, uint32_t view, uint32_t tile,
+                                             float* __restrict__ image, uint2* __restrict__ stats) {
+    if (px < W && py < H) {
+        float* o = image + (((size_t)view * H + py) * W + px) * 3;
+        o[0] = pb.C0; o[1] = pb.C1; o[2] = pb.C2;
+    }
+    if (STATS) {
+        const uint32_t e = wave_sum(pb.n_visit), al = wave_sum(n_alpha);
+        if (__lane_id() == 0) { st[0][threadIdx.x / WAVE] = e; st[1][threadIdx.x / WAVE] = al; }
+        __syncthreads();
+        if (threadIdx.x == 0) {   // stats cleared before the launch: a long tile's four add up
+            uint32_t se = 0, sa = 0;
+            for (int i = 0; i < BL_NT / WAVE; ++i) { se += st[0][i]; sa += st[1][i]; }
+            atomicAdd(&stats[tile].x, se);
+            atomicAdd(&stats[tile].y, sa);
+        }
+    }
+}
+
+// The tiles of `order` but the first n_x: band walk over the long ones,
+// strip walk over the others.
 template <bool STATS>
 __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ ranges, const uint32_t* __restrict__ order,
                                                  const uint32_t* __restrict__ pval, const float4* __restrict__ xy,
                                                  const float4* __restrict__ conic, const float4* __restrict__ rgb,
-                                                 int W, int H, int TX, int TY, int n_views,
+                                                 int W, int H, int TX, int TY, int n_views, uint32_t x_cap,
                                                  float* __restrict__ image, uint2* __restrict__ stats) {
     __shared__ BlendLds L;
-    // Workgroups [0, 4 * n8) serve the n_long long tiles (the first ones of
-    // the order; n8 = n_long rounded up to a multiple of 8), the rest the
-    // other tiles in order.  Workgroup ids go round-robin over the eight
-    // XCDs, so a long tile's four workgroups are taken 8 ids apart (one XCD).
+    // Workgroups [0, 4 * n8) serve the long tiles from n_x on (n8: their
+    // number rounded up to a multiple of 8), the rest the other tiles in
+    // order.  Workgroup ids go round-robin over the eight XCDs, so a long
+    // tile's four workgroups are taken 8 ids apart (one XCD).
     const uint32_t n_tiles = (uint32_t)(TX * TY) * (uint32_t)n_views;
-    const uint32_t n_long = min(order[n_tiles], blend_long_slots(n_tiles));
-    const uint32_t n8 = (n_long + 7u) & ~7u;
+    const BlendSplit sp = blend_split(order, n_tiles, x_cap);
+    const uint32_t n8 = (sp.n_long - sp.n_x + 7u) & ~7u;
     const uint32_t b = blockIdx.x;
     uint32_t idx;
     int band = -1;
     if (b < 4 * n8) {
         const uint32_t s = b >> 3;
-        idx = (s >> 2) * 8 + (b & 7);
+        idx = sp.n_x + (s >> 2) * 8 + (b & 7);
         band = (int)(s & 3);
-        if (idx >= n_long) return;
+        if (idx >= sp.n_long) return;
     } else {
-        idx = n_long + (b - 4 * n8);
+        idx = sp.n_long + (b - 4 * n8);
         if (idx >= n_tiles) return;
     }
     const uint32_t tile = order[idx];
@@ -789,21 +991,37 @@ __global__ __launch_bounds__(BL_NT) void k_blend(const uint2* __restrict__ range
         band_walk<STATS>(L, rg, pval, xy, conic, rgb, tx, ty, band, W, H, pb, n_alpha, px, py);
     else
         strip_walk<STATS>(rg, pval, xy, conic, rgb, tx, ty, W, H, pb, n_alpha, px, py);
-    if (px < W && py < H) {
-        float* o = image + (((size_t)view * H + py) * W + px) * 3;
-        o[0] = pb.C0; o[1] = pb.C1; o[2] = pb.C2;
-    }
-    if (STATS) {
-        const uint32_t e = wave_sum(pb.n_visit), al = wave_sum(n_alpha);
-        if (__lane_id() == 0) { L.st[0][threadIdx.x / WAVE] = e; L.st[1][threadIdx.x / WAVE] = al; }
-        __syncthreads();
-        if (threadIdx.x == 0) {   // stats cleared before the launch: a long tile's four add up
-            uint32_t se = 0, sa = 0;
-            for (int i = 0; i < BL_NT / WAVE; ++i) { se += L.st[0][i]; sa += L.st[1][i]; }
-            atomicAdd(&stats[tile].x, se);
-            atomicAdd(&stats[tile].y, sa);
-        }
-    }
+    blend_finish<STATS>(L.st, pb, n_alpha, px, py, W, H, view, tile, image, stats);
+}
+
+// The first n_x tiles of `order`: the alpha band walk, four workgroups per
+// tile (a launch of 4 * x_cap workgroups, x_cap a multiple of 8), beside
+// k_blend on another stream.
+template <bool STATS>
+__global__ __launch_bounds__(BL_NT) void k_blend_x(const uint2* __restrict__ ranges,
+                                                   const uint32_t* __restrict__ order,
+                                                   const uint32_t* __restrict__ pval, const float4* __restrict__ xy,
+                                                   const float4* __restrict__ conic, const float4* __restrict__ rgb,
+                                                   int W, int H, int TX, int TY, int n_views, uint32_t x_cap,
+                                                   float* __restrict__ image, uint2* __restrict__ stats) {
+    __shared__ AlphaLds L;
+    const uint32_t n_tiles = (uint32_t)(TX * TY) * (uint32_t)n_views;
+    const BlendSplit sp = blend_split(order, n_tiles, x_cap);
+    const uint32_t b = blockIdx.x, s = b >> 3;
+    const uint32_t idx = (s >> 2) * 8 + (b & 7);
+    const int band = (int)(s & 3);
+    if (idx >= sp.n_x) return;
+    const uint32_t tile = order[idx];
+    const uint32_t per_view = (uint32_t)(TX * TY);
+    const uint32_t view = tile / per_view;
+    const uint32_t t = tile - view * per_view;
+    const int tx = (int)(t % (uint32_t)TX), ty = (int)(t / (uint32_t)TX);
+    const uint2 rg = ranges[tile];
+    PixelBlend pb{1.0f, 0.0f, 0.0f, 0.0f, false, 0u};
+    uint32_t n_alpha = 0;
+    int px, py;
+    band_walk_alpha<STATS>(L, rg, pval, xy, conic, rgb, tx, ty, band, W, H, pb, n_alpha, px, py);
+    blend_finish<STATS>(L.st, pb, n_alpha, px, py, W, H, view, tile, image, stats);
 }
 
 }  // namespace vmk
@@ -863,20 +1081,37 @@ void launch_tile_order(hipStream_t st, const uint2* ranges, uint32_t n_tiles, ui
     if (n_tiles) hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(TO_NT), 0, st, ranges, n_tiles, order);
 }
 
+uint32_t blend_x_cap(uint32_t n_tiles, uint32_t want) {
+    const uint32_t c = std::min({want, n_tiles, BL_LONG_CAP});
+    return (c + 7u) & ~7u;
+}
+
 void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* order, const uint32_t* pval, const float4* xy,
-                  const float4* conic, const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image,
-                  uint2* stats) {
+                  const float4* conic, const float4* rgb, int W, int H, int TX, int TY, int n_views, uint32_t x_cap,
+                  float* image, uint2* stats) {
     const uint32_t n_tiles = (uint32_t)(TX * TY * n_views);
     if (!n_tiles) return;
     const uint32_t n_blocks = blend_workgroups(n_tiles);
-    if (stats) {
-        launch_fill_u32(st, (uint32_t*)stats, 2 * (uint64_t)n_tiles, 0u);
+    if (stats)
         hipLaunchKernelGGL(k_blend<true>, dim3(n_blocks), dim3(BL_NT), 0, st, ranges, order, pval, xy, conic, rgb, W,
-                           H, TX, TY, n_views, image, stats);
-    } else {
+                           H, TX, TY, n_views, x_cap, image, stats);
+    else
         hipLaunchKernelGGL(k_blend<false>, dim3(n_blocks), dim3(BL_NT), 0, st, ranges, order, pval, xy, conic, rgb, W,
-                           H, TX, TY, n_views, image, stats);
-    }
+                           H, TX, TY, n_views, x_cap, image, stats);
+}
+
+void launch_blend_x(hipStream_t st, const uint2* ranges, const uint32_t* order, const uint32_t* pval,
+                    const float4* xy, const float4* conic, const float4* rgb, int W, int H, int TX, int TY,
+                    int n_views, uint32_t x_cap, float* image, uint2* stats) {
+    const uint32_t n_tiles = (uint32_t)(TX * TY * n_views);
+    if (!n_tiles || !x_cap) return;
+    const uint32_t n_blocks = BL_BANDS * x_cap;
+    if (stats)
+        hipLaunchKernelGGL(k_blend_x<true>, dim3(n_blocks), dim3(BL_NT), 0, st, ranges, order, pval, xy, conic, rgb,
+                           W, H, TX, TY, n_views, x_cap, image, stats);
+    else
+        hipLaunchKernelGGL(k_blend_x<false>, dim3(n_blocks), dim3(BL_NT), 0, st, ranges, order, pval, xy, conic, rgb,
+                           W, H, TX, TY, n_views, x_cap, image, stats);
 }
 
 }  // namespace vm

@@ -186,11 +186,24 @@ void launch_emit(hipStream_t st, const uint32_t* order, const uint32_t* offsets,
                  int TX, int TY, uint32_t* pkey, uint32_t* pval, uint32_t cap);
 void launch_ranges(hipStream_t st, const uint32_t* pkey, uint32_t cap, const uint32_t* n_pairs_dev, uint2* ranges,
                    uint32_t n_tiles);
-// order: n_tiles + 1 words (the blend order, then the number of long tiles)
+// order: n_tiles + 2 words (the blend order, then the number of long tiles
+// and of the longest ones)
 void launch_tile_order(hipStream_t st, const uint2* ranges, uint32_t n_tiles, uint32_t* order);
+// the blend of the tiles in order, in two launches that may run side by
+// side and must be given the same x_cap: launch_blend_x takes the first
+// tiles, those with 16384 pairs or more (at most x_cap of them; alpha band
+// walk, four workgroups each), launch_blend the others (band walk for those
+// with 4096 pairs or more, strip walk for the rest).  stats (or null): per
+// tile, the visited list entries and the alpha evaluations, added to
+// (cleared by the caller)
 void launch_blend(hipStream_t st, const uint2* ranges, const uint32_t* order, const uint32_t* pval, const float4* xy,
-                  const float4* conic, const float4* rgb, int W, int H, int TX, int TY, int n_views, float* image,
-                  uint2* stats);
+                  const float4* conic, const float4* rgb, int W, int H, int TX, int TY, int n_views, uint32_t x_cap,
+                  float* image, uint2* stats);
+void launch_blend_x(hipStream_t st, const uint2* ranges, const uint32_t* order, const uint32_t* pval,
+                    const float4* xy, const float4* conic, const float4* rgb, int W, int H, int TX, int TY,
+                    int n_views, uint32_t x_cap, float* image, uint2* stats);
+// room for want such tiles of n_tiles (a multiple of 8, at most the walk's limit)
+uint32_t blend_x_cap(uint32_t n_tiles, uint32_t want);
 // fills done together in one launch (at most kMax)
 struct FillSeg {
     void* p; uint64_t n; uint64_t v; int wide;   // wide: 8-byte words, else 4-byte
