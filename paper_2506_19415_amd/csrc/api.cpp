@@ -136,6 +136,8 @@ struct vm3dgs {
     uint32_t last_views = 0, last_n_render = 0, last_n_pairs = 0, last_n_copy = 0, last_n_missing = 0;
     uint32_t last_n_xlong = 0xffffffffu;   // longest tiles of the last splat (none yet: room for all)
     uint32_t last_n_req = 0, last_n_rl = 0;
+    // the last frame's request and level-1/2 candidate counts (all ones: none yet)
+    uint32_t hint_req = ~0u, hint_cand[3] = {~0u, ~0u, ~0u};
     int last_pbuf = 0, last_dbuf = 0;
     std::vector<int32_t> out_req, out_missing;
     std::vector<int8_t> out_req_level;
@@ -849,6 +851,8 @@ vm3dgs_status frame_impl(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views,
         pa.counters = c->d_ctr; pa.level_base = c->d_level_base; pa.rl = c->d_rlist;
         const bool streaming = (c->opt.flags & VM3DGS_FLAG_ASYNC_MISSES) != 0;
         pa.streaming = streaming ? 1 : 0; pa.rlevel = c->d_rlevel;
+        pa.hint_req = c->hint_req;
+        for (int l = 0; l < 3; ++l) pa.hint_cand[l] = c->hint_cand[l];
         if (!c->multi) {
             launch_pagetable(c->sr, pa, 0);
         } else {
@@ -952,6 +956,7 @@ vm3dgs_status frame_impl(vm3dgs* c, const vm3dgs_camera* cams, uint32_t n_views,
         st.fallbacks = k[C_FALLBACK];
         const uint32_t n_render = k[C_NRENDER];
         c->last_n_copy = n_copy; c->last_n_missing = k[C_NMISSING]; c->last_n_req = k[C_NREQ];
+        c->hint_req = k[C_NREQ]; c->hint_cand[1] = k[C_NCAND1]; c->hint_cand[2] = k[C_NCAND2];
         c->last_n_rl = k[C_NRL];
         st.candidates = k[C_CAND]; st.requested = k[C_NREQ]; st.direct = k[C_DIRECT]; st.linked = k[C_LINKED];
         st.hits = k[C_HITS]; st.misses = k[C_MISSES]; st.evictions = k[C_EVICT]; st.missing = k[C_NMISSING];
@@ -1094,6 +1099,9 @@ vm3dgs_status vm3dgs_reset(vm3dgs* c) {
     c->pf_pending = false;
     c->last_n_copy = c->last_n_missing = c->last_n_req = c->last_n_rl = 0;
     c->last_n_pfreq = c->last_n_pf = 0;
+    c->hint_req = ~0u;
+    for (auto& h : c->hint_cand) h = ~0u;
+    c->last_n_xlong = ~0u;
     return VM3DGS_OK;
 }
 

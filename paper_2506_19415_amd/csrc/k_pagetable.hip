@@ -663,7 +663,9 @@ void launch_pagetable_lod(hipStream_t st, const PtArgs& a, SortWork& sw, const L
     // stage wrote (the sort's grid covers n_pg, its kernels read the count)
     uint64_t* rk[2] = {const_cast<uint64_t*>(a.req_keys), w.keys_alt};
     uint32_t* nov[2] = {nullptr, nullptr};
-    const int kb = onesweep_u64_dev(st, sw, rk, nov, (uint32_t)n_pg, a.counters + vm::C_NREQ, 0, 64);
+    const int kb = a.hint_req <= kSortSmallMax
+                       ? sort_small_u64(st, rk, (uint32_t)n_pg, a.counters + vm::C_NREQ, 0, 64)
+                       : onesweep_u64_dev(st, sw, rk, nov, (uint32_t)n_pg, a.counters + vm::C_NREQ, 0, 64);
     const uint64_t* keys = rk[kb];
     launch_fill_u32(st, (uint32_t*)a.req_sub, ((uint64_t)S * SUBS + 3) / 4, 0u);
     launch_fill_u32(st, (uint32_t*)a.slot_req, ((uint64_t)S + 3) / 4, 0u);
@@ -686,7 +688,10 @@ void launch_pagetable_lod(hipStream_t st, const PtArgs& a, SortWork& sw, const L
                        (const int32_t*)a.sub_vpage, (const int32_t*)a.sub_last_used, (const uint8_t*)a.req_sub,
                        (const uint8_t*)a.slot_req, w.wkeys[0], w.ck[1][0], w.ck[2][0], a.counters);
     uint64_t* wk[2] = {w.wkeys[0], w.wkeys[1]};
-    const int wb = onesweep_u64(st, sw, wk, nov, (uint32_t)S, 0, std::max(8, end_bit));
+    // the pool's slots (S keys): one workgroup for up to two of its tiles
+    const int wb = (uint32_t)S <= 2 * kSortSmallMax
+                       ? sort_small_u64(st, wk, (uint32_t)S, nullptr, 0, std::max(8, end_bit))
+                       : onesweep_u64(st, sw, wk, nov, (uint32_t)S, 0, std::max(8, end_bit));
     PtWalk pw;
     pw.wkeys = wk[wb];
     pw.ck[0] = nullptr;
@@ -695,9 +700,11 @@ void launch_pagetable_lod(hipStream_t st, const PtArgs& a, SortWork& sw, const L
         pw.ck[l] = nullptr;
         if (l < L) {
             uint64_t* ck[2] = {w.ck[l][0], w.ck[l][1]};
-            const int cb = onesweep_u64_dev(st, sw, ck, nov, (uint32_t)S * SUBS,
-                                            a.counters + (l == 1 ? vm::C_NCAND1 : vm::C_NCAND2), 0,
-                                            std::max(8, end_bit));
+            const uint32_t* n_cand = a.counters + (l == 1 ? vm::C_NCAND1 : vm::C_NCAND2);
+            const int cb = a.hint_cand[l] <= kSortSmallMax
+                               ? sort_small_u64(st, ck, (uint32_t)S * SUBS, n_cand, 0, std::max(8, end_bit))
+                               : onesweep_u64_dev(st, sw, ck, nov, (uint32_t)S * SUBS, n_cand, 0,
+                                                  std::max(8, end_bit));
             pw.ck[l] = ck[cb];
         }
     }

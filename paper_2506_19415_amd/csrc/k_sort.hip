@@ -249,6 +249,91 @@ __global__ __launch_bounds__(NT) void k_os_pass(const K* __restrict__ kin, const
     }
 }
 
+// ------------------------------------------------------------------ one workgroup
+// A stable LSD radix sort of up to a few thousand keys by one workgroup, all
+// passes in one launch: per pass, tiles of SS_TILE keys in order, each ranked
+// like a onesweep tile (ballot digit matching per wave, a scan over digits)
+// and written to its digit's running position; several tiles take a digit
+// histogram of all keys first.  Keys ping-pong between the two buffers in
+// global memory (L2-resident at these sizes) as the onesweep passes do.
+constexpr int SS_NT = 1024, SS_ITEMS = 8, SS_TILE = SS_NT * SS_ITEMS;
+
+template <typename K>
+__global__ __launch_bounds__(SS_NT) void k_sort_small(K* __restrict__ k0, K* __restrict__ k1, uint32_t n_arg,
+                                                      const uint32_t* __restrict__ n_dev, int begin_bit,
+                                                      int passes) {
+    constexpr int NW = SS_NT / WAVE, SPAN = SS_TILE / NW;
+    __shared__ uint32_t wc[NW][256];
+    __shared__ uint32_t gpos[256];
+    __shared__ uint32_t scan_sh[NW];
+    const uint32_t n = n_dev ? min(*n_dev, n_arg) : n_arg;
+    const uint32_t n_tiles = (n + SS_TILE - 1) / SS_TILE;
+    const int w = threadIdx.x / WAVE;
+    const uint64_t lt = lanemask_lt();
+    for (int p = 0; p < passes; ++p) {
+        const K* __restrict__ src = (p & 1) ? k1 : k0;
+        K* __restrict__ dst = (p & 1) ? k0 : k1;
+        const int shift = begin_bit + 8 * p;
+        if (n_tiles > 1) {
+            // digit starts over all keys
+            for (int i = threadIdx.x; i < 256; i += SS_NT) wc[0][i] = 0;
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < n; i += SS_NT) atomicAdd(&wc[0][digit_of(src[i], shift)], 1u);
+            __syncthreads();
+            const int d = threadIdx.x;
+            uint32_t all;
+            const uint32_t start = block_excl_scan<SS_NT>(d < 256 ? wc[0][d] : 0u, scan_sh, &all);
+            if (d < 256) gpos[d] = start;
+            __syncthreads();
+        }
+        for (uint32_t t = 0; t < n_tiles; ++t) {
+            for (int i = threadIdx.x; i < NW * 256; i += SS_NT) (&wc[0][0])[i] = 0;
+            __syncthreads();
+            const uint32_t base = t * SS_TILE + w * SPAN;
+            K key[SS_ITEMS];
+            uint32_t rank[SS_ITEMS];
+#pragma unroll
+            for (int r = 0; r < SS_ITEMS; ++r) {
+                const uint32_t idx = base + r * WAVE + __lane_id();
+                key[r] = idx < n ? src[idx] : (K)0;
+            }
+#pragma unroll
+            for (int r = 0; r < SS_ITEMS; ++r) {
+                const bool valid = base + r * WAVE + __lane_id() < n;
+                const uint32_t d = digit_of(key[r], shift);
+                const uint64_t peers = match_digit8(d, valid);
+                const uint32_t old = valid ? wc[w][d] : 0u;
+                rank[r] = old + (uint32_t)__popcll(peers & lt);
+                if (valid && (peers & lt) == 0) wc[w][d] = old + (uint32_t)__popcll(peers);
+            }
+            __syncthreads();
+            {
+                // per digit: the tile's count and start, the waves' starts
+                // within it, then its destination offset (one tile: its start)
+                const int d = threadIdx.x;
+                const bool dig = d < 256;
+                uint32_t c[NW], tot = 0;
+#pragma unroll
+                for (int i = 0; i < NW; ++i) { c[i] = dig ? wc[i][d] : 0u; tot += c[i]; }
+                uint32_t all;
+                const uint32_t start = block_excl_scan<SS_NT>(tot, scan_sh, &all);
+                if (dig) {
+                    const uint32_t g = n_tiles > 1 ? gpos[d] : start;
+                    uint32_t run = g;
+#pragma unroll
+                    for (int i = 0; i < NW; ++i) { wc[i][d] = run; run += c[i]; }
+                    if (n_tiles > 1) gpos[d] = run;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < SS_ITEMS; ++r)
+                if (base + r * WAVE + __lane_id() < n) dst[wc[w][digit_of(key[r], shift)] + rank[r]] = key[r];
+            __syncthreads();
+        }
+    }
+}
+
 }  // namespace vmk
 
 // ------------------------------------------------------------------ host
@@ -321,6 +406,15 @@ int onesweep_u64(hipStream_t st, SortWork& w, uint64_t* keys[2], uint32_t* vals[
 int onesweep_u64_dev(hipStream_t st, SortWork& w, uint64_t* keys[2], uint32_t* vals[2], uint32_t n_bound,
                      const uint32_t* n_dev, int begin_bit, int end_bit) {
     return onesweep_impl<uint64_t>(st, w, keys, vals, n_bound, n_dev, begin_bit, end_bit);
+}
+
+int sort_small_u64(hipStream_t st, uint64_t* keys[2], uint32_t n_bound, const uint32_t* n_dev, int begin_bit,
+                   int end_bit) {
+    const int passes = (end_bit - begin_bit + 7) / 8;
+    if (n_bound == 0 || passes == 0) return 0;
+    hipLaunchKernelGGL(k_sort_small<uint64_t>, dim3(1), dim3(SS_NT), 0, st, keys[0], keys[1], n_bound, n_dev,
+                       begin_bit, passes);
+    return passes & 1;
 }
 
 void scan_lb(hipStream_t st, SortWork& w, const uint32_t* in, uint64_t n, uint32_t* out, uint32_t* total) {

@@ -85,6 +85,13 @@ int onesweep_u64(hipStream_t st, SortWork& w, uint64_t* keys[2], uint32_t* vals[
                  int end_bit);
 int onesweep_u64_dev(hipStream_t st, SortWork& w, uint64_t* keys[2], uint32_t* vals[2], uint32_t n_bound,
                      const uint32_t* n_dev, int begin_bit, int end_bit);
+// the same sort of keys only (the result in keys[returned index], as above)
+// by one workgroup in one launch: for counts up to a few thousand, where the
+// onesweep passes are bound by their launches
+int sort_small_u64(hipStream_t st, uint64_t* keys[2], uint32_t n_bound, const uint32_t* n_dev, int begin_bit,
+                   int end_bit);
+// counts up to which sort_small_u64 beats the onesweep passes
+constexpr uint32_t kSortSmallMax = 8192;
 void scan_lb(hipStream_t st, SortWork& w, const uint32_t* in, uint64_t n, uint32_t* out, uint32_t* total);
 void scan_lb_gather(hipStream_t st, SortWork& w, const uint32_t* a, const uint32_t* idx, uint64_t n, uint32_t* out,
                     uint32_t* total);
@@ -146,6 +153,10 @@ struct PtArgs {
     // resident only at another level at the nearest one); rlevel [n_pg] is
     // the level each requested page is drawn at (several levels only)
     int streaming; int8_t* rlevel;
+    // the last frame's request and level-1/2 candidate counts (all ones:
+    // none yet); the LOD table sorts such lists by one workgroup when the
+    // last frame's fitted
+    uint32_t hint_req = ~0u, hint_cand[3] = {~0u, ~0u, ~0u};
 };
 void launch_pagetable(hipStream_t st, const PtArgs& a, int n_req_host_bound);
 

@@ -500,19 +500,24 @@ def test_lod_city(city, L, tau, S, budget, fmt, builder):
     r.close()
 
 
-def test_large_one_level_table(clusters):
+@pytest.mark.parametrize("S", [6000, 12000])
+def test_large_one_level_table(clusters, S):
     """One level with more pages than the single-workgroup page table holds
-    (16,384 pages of 2): the multi-kernel page table, bit-exact as well."""
+    (16,384 pages of 2): the multi-kernel page table, bit-exact as well.  Its
+    sorts of the requests and of the pool's slots run in one workgroup from
+    the second frame (requests) or throughout (slots); 12,000 slots make that
+    sort take two tiles."""
     sc, _ = clusters
     osc = oracle.OracleScene(sc, 2, 1, 0.5, 2.0)
     cams = synth.orbit()
-    r = _renderer(sc, 2, 6000, (320, 240), (80, 60), 0.5)
-    ovm = _ovm(osc, 6000, (320, 240), (80, 60))
+    r = _renderer(sc, 2, S, (320, 240), (80, 60), 0.5)
+    ovm = _ovm(osc, S, (320, 240), (80, 60))
     for k in range(4):
-        print(f"large table frame {k}", flush=True)
+        print(f"large table S={S} frame {k}", flush=True)
         _, out = r.frame([cams[k]])
         ovm.frame([cams[k]])
-        compare_frame(r, ovm, out, 1, tag=f"large table {k}")
+        compare_frame(r, ovm, out, 1, tag=f"large table S={S} {k}")
+        print(f"  requests {out.n_requests}", flush=True)
     r.close()
 
 
