@@ -250,12 +250,17 @@ __global__ __launch_bounds__(NT) void k_os_pass(const K* __restrict__ kin, const
 }
 
 // ------------------------------------------------------------------ one workgroup
-// A stable LSD radix sort of up to a few thousand keys by one workgroup, all
-// passes in one launch: per pass, tiles of SS_TILE keys in order, each ranked
-// like a onesweep tile (ballot digit matching per wave, a scan over digits)
-// and written to its digit's running position; several tiles take a digit
-// histogram of all keys first.  Keys ping-pong between the two buffers in
-// global memory (L2-resident at these sizes) as the onesweep passes do.
+// Keys only, up to a few thousand, by one workgroup in one launch.  Up to
+// SS_TILE keys: a bitonic sort in LDS (the count padded to a power of two
+// with all-ones keys), comparing the keys' bits in [begin_bit, end_bit); it
+// is not stable, so it gives the stable sort's result when keys that agree
+// on those bits are equal (as the page table's are: each holds its page,
+// slot or sub-slot index, or is all ones).  More keys: a stable LSD radix
+// sort, per pass tiles of SS_TILE keys in order, each ranked like a
+// onesweep tile (ballot digit matching per wave, a scan over digits) and
+// written to its digit's running position after a digit histogram of all
+// keys, ping-ponging between the two buffers in global memory as the
+// onesweep passes do.  Either way the result is in buffer passes % 2.
 constexpr int SS_NT = 1024, SS_ITEMS = 8, SS_TILE = SS_NT * SS_ITEMS;
 
 template <typename K>
@@ -266,7 +271,30 @@ __global__ __launch_bounds__(SS_NT) void k_sort_small(K* __restrict__ k0, K* __r
     __shared__ uint32_t wc[NW][256];
     __shared__ uint32_t gpos[256];
     __shared__ uint32_t scan_sh[NW];
+    __shared__ K sk[SS_TILE];
     const uint32_t n = n_dev ? min(*n_dev, n_arg) : n_arg;
+    if (n <= (uint32_t)SS_TILE) {
+        const int nbits = 8 * passes;
+        const K mask = (nbits >= (int)(8 * sizeof(K)) ? ~(K)0 : (((K)1 << nbits) - 1)) << begin_bit;
+        uint32_t N = 1;
+        while (N < n) N <<= 1;
+        for (uint32_t i = threadIdx.x; i < N; i += SS_NT) sk[i] = i < n ? k0[i] : ~(K)0;
+        __syncthreads();
+        for (uint32_t k = 2; k <= N; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                for (uint32_t t = threadIdx.x; t < N / 2; t += SS_NT) {
+                    const uint32_t i = 2 * t - (t & (j - 1));   // t with a 0 bit inserted at j
+                    const K a = sk[i], b = sk[i + j];
+                    const bool up = (i & k) == 0;
+                    if (((a & mask) > (b & mask)) == up) { sk[i] = b; sk[i + j] = a; }
+                }
+                __syncthreads();
+            }
+        }
+        K* __restrict__ out = (passes & 1) ? k1 : k0;
+        for (uint32_t i = threadIdx.x; i < n; i += SS_NT) out[i] = sk[i];
+        return;
+    }
     const uint32_t n_tiles = (n + SS_TILE - 1) / SS_TILE;
     const int w = threadIdx.x / WAVE;
     const uint64_t lt = lanemask_lt();
@@ -274,18 +302,18 @@ __global__ __launch_bounds__(SS_NT) void k_sort_small(K* __restrict__ k0, K* __r
         const K* __restrict__ src = (p & 1) ? k1 : k0;
         K* __restrict__ dst = (p & 1) ? k0 : k1;
         const int shift = begin_bit + 8 * p;
-        if (n_tiles > 1) {
-            // digit starts over all keys
-            for (int i = threadIdx.x; i < 256; i += SS_NT) wc[0][i] = 0;
-            __syncthreads();
-            for (uint32_t i = threadIdx.x; i < n; i += SS_NT) atomicAdd(&wc[0][digit_of(src[i], shift)], 1u);
-            __syncthreads();
+        // digit starts over all keys
+        for (int i = threadIdx.x; i < 256; i += SS_NT) wc[0][i] = 0;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < n; i += SS_NT) atomicAdd(&wc[0][digit_of(src[i], shift)], 1u);
+        __syncthreads();
+        {
             const int d = threadIdx.x;
             uint32_t all;
             const uint32_t start = block_excl_scan<SS_NT>(d < 256 ? wc[0][d] : 0u, scan_sh, &all);
             if (d < 256) gpos[d] = start;
-            __syncthreads();
         }
+        __syncthreads();
         for (uint32_t t = 0; t < n_tiles; ++t) {
             for (int i = threadIdx.x; i < NW * 256; i += SS_NT) (&wc[0][0])[i] = 0;
             __syncthreads();
@@ -308,21 +336,13 @@ __global__ __launch_bounds__(SS_NT) void k_sort_small(K* __restrict__ k0, K* __r
             }
             __syncthreads();
             {
-                // per digit: the tile's count and start, the waves' starts
-                // within it, then its destination offset (one tile: its start)
+                // per digit: the waves' starts from the digit's running position
                 const int d = threadIdx.x;
-                const bool dig = d < 256;
-                uint32_t c[NW], tot = 0;
+                if (d < 256) {
+                    uint32_t run = gpos[d];
 #pragma unroll
-                for (int i = 0; i < NW; ++i) { c[i] = dig ? wc[i][d] : 0u; tot += c[i]; }
-                uint32_t all;
-                const uint32_t start = block_excl_scan<SS_NT>(tot, scan_sh, &all);
-                if (dig) {
-                    const uint32_t g = n_tiles > 1 ? gpos[d] : start;
-                    uint32_t run = g;
-#pragma unroll
-                    for (int i = 0; i < NW; ++i) { wc[i][d] = run; run += c[i]; }
-                    if (n_tiles > 1) gpos[d] = run;
+                    for (int i = 0; i < NW; ++i) { const uint32_t c = wc[i][d]; wc[i][d] = run; run += c; }
+                    gpos[d] = run;
                 }
             }
             __syncthreads();

@@ -85,9 +85,11 @@ int onesweep_u64(hipStream_t st, SortWork& w, uint64_t* keys[2], uint32_t* vals[
                  int end_bit);
 int onesweep_u64_dev(hipStream_t st, SortWork& w, uint64_t* keys[2], uint32_t* vals[2], uint32_t n_bound,
                      const uint32_t* n_dev, int begin_bit, int end_bit);
-// the same sort of keys only (the result in keys[returned index], as above)
-// by one workgroup in one launch: for counts up to a few thousand, where the
-// onesweep passes are bound by their launches
+// keys only by one workgroup in one launch (the result in keys[returned
+// index], as above), for counts up to a few thousand, where the onesweep
+// passes are bound by their launches; its result is the stable sort's when
+// keys that agree on the sorted bits are equal (up to 8192 keys it sorts
+// without keeping their order)
 int sort_small_u64(hipStream_t st, uint64_t* keys[2], uint32_t n_bound, const uint32_t* n_dev, int begin_bit,
                    int end_bit);
 // counts up to which sort_small_u64 beats the onesweep passes
