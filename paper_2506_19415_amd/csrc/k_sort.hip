@@ -280,6 +280,10 @@ __global__ __launch_bounds__(SS_NT) void k_sort_small(K* __restrict__ k0, K* __r
         while (N < n) N <<= 1;
         for (uint32_t i = threadIdx.x; i < N; i += SS_NT) sk[i] = i < n ? k0[i] : ~(K)0;
         __syncthreads();
+        // a stage with j < 64 keeps each wave within its own blocks of 128
+        // keys (its lanes' pairs t hold i in [128 (t / 64), 128 (t / 64 + 1))),
+        // and a wave's LDS accesses take effect in order: it needs no
+        // workgroup barrier, only one that keeps the compiler's order
         for (uint32_t k = 2; k <= N; k <<= 1) {
             for (uint32_t j = k >> 1; j > 0; j >>= 1) {
                 for (uint32_t t = threadIdx.x; t < N / 2; t += SS_NT) {
@@ -288,8 +292,10 @@ __global__ __launch_bounds__(SS_NT) void k_sort_small(K* __restrict__ k0, K* __r
                     const bool up = (i & k) == 0;
                     if (((a & mask) > (b & mask)) == up) { sk[i] = b; sk[i + j] = a; }
                 }
-                __syncthreads();
+                if (j >= (uint32_t)WAVE) __syncthreads();
+                else __builtin_amdgcn_wave_barrier();
             }
+            __syncthreads();
         }
         K* __restrict__ out = (passes & 1) ? k1 : k0;
         for (uint32_t i = threadIdx.x; i < n; i += SS_NT) out[i] = sk[i];
