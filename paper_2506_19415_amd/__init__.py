@@ -181,7 +181,16 @@ def vm3dgs_options_default() -> vm3dgs_options:
     return o
 
 
+def pack_cameras(cams):
+    """The cameras as the C array vm3dgs_frame takes; the frame calls accept
+    such an array in place of a list (a caller that renders the same cameras
+    again, or times its frames, packs them once)."""
+    return _cameras(cams)
+
+
 def _cameras(cams):
+    if isinstance(cams, C.Array) and cams._type_ is vm3dgs_camera:
+        return cams
     arr = (vm3dgs_camera * len(cams))()
     for i, c in enumerate(cams):
         v = np.ascontiguousarray(c.view, dtype=np.float32).reshape(16)
