@@ -168,10 +168,11 @@ vm3dgs_status vm3dgs_create(const vm3dgs_scene* scene, uint32_t page_size, uint3
  * the misses (read by the GPU from the pinned store, on the render stream
  * before the preprocess; prefetch copies on the copy stream), splatting of
  * the resident pages.  image_dev: device, caller-owned,
- * [n_views][img_h][img_w][3] float32, written on the render stream and
- * complete when that stream reaches the end of this call's work (the call
- * returns after that); work of other streams that reads or writes it must be
- * complete before the call.  The frame
+ * [n_views][img_h][img_w][3] float32, written on the render stream (and on
+ * a stream of the library's own that the blend forks from the render stream
+ * and joins back to it) and complete when the render stream reaches the end
+ * of this call's work (the call returns after that); work of other streams
+ * that reads or writes it must be complete before the call.  The frame
  * counter advances on every call.  out may be NULL.  The (tile, Gaussian)
  * pairs of one call are counted in 32 bits (at most 2^32 - 1); the pair
  * buffers grow as needed (a call that outgrows them splats again).
